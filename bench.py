@@ -1,0 +1,153 @@
+"""Benchmark of the MCLG hot path on one MI355X.
+
+One step = one fused stream + Monte Carlo collide pass over every site of the
+workload (D1Q3, L = 2^24, rho = 50, u0 = 0.1, C = 10, lambda = 1, Poisson
+initial state, seed 2).  Prints one JSON line with site updates per second,
+the HBM roofline of the fused kernel, and the oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--extra]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_SITE_UPDATE = 12     # 3 x uint16 read + 3 x uint16 written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_L16M.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1706_01094_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s: float = 15.0) -> dict:
+    """The oracle (single-threaded C) on a bounded sample of the workload:
+    the first 2^20 sites' worth of lattice (its own periodic lattice of that
+    length, same rho, u0, seed), stepped until ~budget_s of CPU time."""
+    import oracle as O
+    import synth
+    w = synth.PLAIN_LARGE
+    L = 1 << 20
+    sim = O.OracleSim([L], w["seed"], C=10, n_max=255)
+    sim.init_poisson(0, w["rho"], w["u0"])
+    sim.step(1)  # builds the table blocks this density visits
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        sim.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    sim.close()
+    return {"value": steps * L / dt, "unit": "site updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle on a periodic L=2^20 lattice of the same workload "
+                      f"(rho=50, u0=0.1, C=10), {steps} steps timed after 1 warm-up step"}
+
+
+def run_plain(args, torch, M):
+    import synth
+    w = synth.PLAIN_LARGE
+    L = w["L"]
+    lat = M.Lattice(L, w["seed"], C=10, lam=(1, 1), n_max=255, rho=w["rho"], u0=w["u0"])
+    if args.schedule:
+        g, t = (int(v) for v in args.schedule.split(","))
+        lat.set_schedule(g, t)
+    stream = lat.stream
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    if args.graph:
+        chunk = 100
+        done = 0
+        while done + chunk <= args.steps:
+            lat.step_graph(chunk)
+            done += chunk
+        lat.step(args.steps - done)
+    else:
+        lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    rc = lat.check()
+    if rc != 0:
+        raise SystemExit(f"device error {rc}")
+    lat.close()
+    return L, gpu_ms, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10_000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--schedule", default="", help="groups,threads")
+    ap.add_argument("--graph", action="store_true", help="launch steps from captured HIP graphs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the lattice and replica work of this build "
+              "runs on a single MI355X (sharding across GPUs is described in DESIGN.md).",
+              file=sys.stderr)
+        raise SystemExit(2)
+    import torch
+    from paper_1706_01094_amd import mclg as M
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+
+    L, gpu_ms, wall = run_plain(args, torch, M)
+    ms_per_step = gpu_ms / args.steps
+    value = L * args.steps / (gpu_ms / 1e3)
+    achieved = BYTES_PER_SITE_UPDATE * L / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "site updates/s (stream+MC collide, D1Q3), % HBM peak; batched vs plain",
+        "value": value,
+        "unit": "site updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "d1q3_L16M_rho50_u0.1", "L": L, "rho": 50.0, "u0": 0.1, "C": 10,
+                   "lambda": 1, "n_max": 255, "seed": 2, "launch": "graph" if args.graph else "plain",
+                   "schedule": args.schedule or "default"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * mclg.h -- C ABI of the MI355X Monte Carlo Lattice Gas library (libmclg.so).
+ *
+ * The method is the integer lattice gas of Blommel & Wagner, "Integer Lattice
+ * Gas with Monte Carlo collision operator recovers the entropic lattice
+ * Boltzmann method with Poisson distributed fluctuations" (arXiv:1706.01094):
+ * integer occupation numbers n_i(x,t) on a periodic D1Q3 lattice (velocities
+ * -1, 0, +1, Eq. (D1Q3vel)) evolve by n_i(x+v_i, t+1) = n_i(x,t) + Xi_i
+ * (Sec. "The Monte Carlo Lattice Gas algorithm"), where Xi is the result of C
+ * random binary sub-collisions per site (Eq. (select), Eq. (omega)) with the
+ * D1Q3 transition probabilities of Sec. "A D1Q3 implementation".  Mass N and
+ * momentum J are conserved exactly at every site.
+ *
+ * Stated rules (the paper leaves them open; results are bit-exact functions
+ * of them):
+ *   - a sub-collision picks an ordered pair of distinct particles uniformly;
+ *   - n(x,t) is the pre-collision state; one step collides every site, then
+ *     streams; step t draws its random numbers with counter t;
+ *   - the C sub-collisions of a site are sampled in one draw from their exact
+ *     joint law (integer matrix power on the site's (N, |J|) fiber), quantised
+ *     to uint32 thresholds floor(2^32 * cumulative probability); the outcome
+ *     is the number of thresholds <= r for one Philox4x32-10 word r;
+ *   - sites with N > n_max use the literal sub-collision loop instead;
+ *   - Philox4x32-10 key = (seed low, seed high); counter =
+ *     (site word, t, replica id, purpose | block << 2); collisions use word
+ *     x & 3 of counter (x >> 2, t, replica, 0); Poisson initial counts use
+ *     words 0, 1, 2 of counter (x, 0, replica, 1); the literal loop consumes
+ *     blocks j = 0, 1, ... of counter (x, t, replica, 2 | j << 2) in order.
+ *
+ * Conventions for every entry point:
+ *   - every call returns an int: MCLG_OK (0) or a negative MCLG_E_* code; no
+ *     exception crosses the ABI;
+ *   - device memory is owned by the caller (e.g. torch tensors) and must stay
+ *     alive until mclg_destroy; the library never allocates device memory;
+ *   - host arrays passed in are copied before the call returns;
+ *   - device work is enqueued on the caller's stream in stream order; calls
+ *     that return host data synchronise that stream;
+ *   - a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MCLG_H
+#define MCLG_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCLG_ABI_VERSION 1u
+
+enum {
+  MCLG_OK = 0,
+  MCLG_E_INVAL = -1,       /* bad argument, size, or buffer too small */
+  MCLG_E_RANGE = -2,       /* a site exceeded N = 65535 (or n_max with C = inf) */
+  MCLG_E_HIP = -3,         /* HIP runtime error; see mclg_last_hip_error */
+  MCLG_E_NOMEM = -4,       /* host allocation failed */
+  MCLG_E_UNSUPPORTED = -5, /* lattice or mode not implemented (D2Q9) */
+  MCLG_E_FULL = -6         /* server: no slot or arena space for the job */
+};
+
+enum { MCLG_D1Q3 = 1, MCLG_D2Q9 = 2 };
+#define MCLG_C_EQUILIBRIUM (-1) /* C -> infinity: redraw from the fiber equilibrium */
+
+enum {
+  MCLG_FLAG_NO_STREAM = 1u /* collisions only, no streaming (Fig. 5 variant, shear-wave init) */
+};
+
+enum { MCLG_INIT_COUNTS = 1, MCLG_INIT_POISSON = 2 };
+
+#define MCLG_MAX_MODES 8
+
+typedef struct mclg_ctx mclg_ctx;
+
+/* Simulation of n_replicas independent periodic lattices.  Replica r has
+ * L[r] sites and RNG identity replica_id[r] (default r). */
+typedef struct {
+  uint32_t abi_version;        /* MCLG_ABI_VERSION */
+  uint32_t lattice;            /* MCLG_D1Q3 */
+  uint32_t n_replicas;         /* >= 1 */
+  uint32_t flags;              /* MCLG_FLAG_* */
+  const uint64_t *L;           /* host [n_replicas]; 1 <= L < 2^31 */
+  const uint64_t *replica_id;  /* host [n_replicas], each < 2^32, or NULL */
+  uint64_t seed;               /* Philox key */
+  int32_t C;                   /* sub-collisions per step, >= 0, or MCLG_C_EQUILIBRIUM */
+  uint32_t lambda_num;         /* acceptance lambda = num / den in (0, 1] */
+  uint32_t lambda_den;
+  uint32_t n_max;              /* tables cover N <= n_max (<= 1023); default 255 */
+  void *stream;                /* hipStream_t; NULL = null stream */
+  void *state;                 /* device, caller-owned, >= state_bytes of mclg_sizes */
+  uint64_t state_bytes;
+  void *workspace;             /* device, caller-owned, >= workspace_bytes of mclg_sizes */
+  uint64_t workspace_bytes;
+} mclg_config;
+
+typedef struct {
+  uint32_t kind;               /* MCLG_INIT_COUNTS or MCLG_INIT_POISSON */
+  const uint16_t *counts;      /* COUNTS: device [sum_r 3 L[r]] uint16, replica r's
+                                  block is [3][L[r]] (n_-1, n_0, n_+1 rows) in
+                                  logical site order; replicas packed densely */
+  const double *rho;           /* POISSON: host [n_replicas], mean density >= 0 */
+  const double *u0;            /* POISSON: host [n_replicas], velocity in [-1, 1] */
+} mclg_init_spec;
+
+/* Exact integer sums over the sites of one replica (modulo 2^64). */
+typedef struct {
+  int64_t t;           /* steps taken */
+  int64_t sites;       /* L */
+  int64_t sum_n[3];    /* sum_x n_i(x), i = -1, 0, +1 */
+  int64_t sum_n2[3];   /* sum_x n_i(x)^2 */
+  int64_t sum_nn[3];   /* sum n_-1 n_0, sum n_0 n_+1, sum n_-1 n_+1 */
+  int64_t sum_N;       /* sum N(x) */
+  int64_t sum_J;       /* sum J(x) = n_+1 - n_-1 */
+  int64_t sum_N2;      /* sum N(x)^2 */
+  int64_t n0_odd;      /* sites with odd n_0 (conserved per site) */
+  int64_t max_N;       /* max_x N(x) */
+  int64_t fourier[MCLG_MAX_MODES][2]; /* sum N(x) tw[2m][x], sum N(x) tw[2m+1][x] */
+} mclg_moments_t;
+
+/* Bytes of device state and workspace needed by a configuration (state,
+ * workspace and stream fields are ignored).  The state holds, per replica,
+ * three uint16 arrays padded to 128 elements, in an internal in-place
+ * shifted layout (use mclg_get_counts for logical order). */
+int mclg_sizes(const mclg_config *cfg, uint64_t *state_bytes, uint64_t *workspace_bytes);
+
+/* Validate cfg, build (or reuse) the exact collision tables on the host,
+ * upload them into the workspace, write the initial state (t = 0) and
+ * synchronise the stream.  On success *out owns a host context. */
+int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out);
+
+/* Enqueue n_steps steps of every replica (one batched launch per step). */
+int mclg_step(mclg_ctx *ctx, uint64_t n_steps);
+
+/* Enqueue n_steps steps of one replica only (one launch per step): the plain
+ * per-lattice schedule.  Replicas may then differ in t. */
+int mclg_step_replica(mclg_ctx *ctx, uint32_t replica, uint64_t n_steps);
+
+/* Capture n_steps batched steps in a HIP graph (once per distinct n_steps)
+ * and launch it; same results as mclg_step. */
+int mclg_step_graph(mclg_ctx *ctx, uint64_t n_steps);
+
+/* Exact moments of every replica into host_out[n_replicas]; synchronises.
+ * twiddle: device int32, NULL when n_modes = 0; replica r's block is
+ * [2 n_modes][L[r]], blocks packed densely in replica order. */
+int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
+                 mclg_moments_t *host_out);
+
+/* Logical counts of one replica into host_out[3][L]; synchronises. */
+int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
+
+/* Sticky error state of the device (MCLG_E_RANGE if any site overflowed);
+ * synchronises. */
+int mclg_check(mclg_ctx *ctx);
+
+/* Select the launch schedule: sites per thread (1, 2, 4 or 8 groups of four
+ * sites) and threads per block (64..1024, multiple of 64).  Any choice gives
+ * identical bits. */
+int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t threads_per_block);
+
+int mclg_destroy(mclg_ctx *ctx);
+const char *mclg_strerror(int code);
+int mclg_last_hip_error(const mclg_ctx *ctx);
+
+/* ---- Host-only inspection (no GPU needed) ---- */
+
+/* Quantised row of the collision law: for the fiber (N, absJ) and incoming
+ * rest count n0, writes the full-fiber thresholds (m - 1 values as uint64,
+ * value 2^32 meaning "never") to thr, m = (N - absJ)/2 + 1 to *m_out. */
+int mclg_table_row(int32_t C, uint32_t lambda_num, uint32_t lambda_den, uint32_t N,
+                   uint32_t absJ, uint32_t n0, uint64_t *thr, uint32_t cap, uint32_t *m_out);
+
+/* Poisson(mu) thresholds of the initial-state rule: outcomes k_lo..k_lo+cnt-1,
+ * cnt - 1 thresholds (uint64) to thr. */
+int mclg_poisson_thresholds(double mu, uint32_t *k_lo, uint32_t *cnt, uint64_t *thr,
+                            uint32_t cap);
+
+/* ---- Serving: continuous batching of simulation jobs ---- */
+
+typedef struct mclg_server mclg_server;
+
+typedef struct {
+  uint32_t abi_version;
+  uint32_t max_slots;          /* concurrent jobs */
+  uint64_t seed;
+  int32_t C;
+  uint32_t lambda_num, lambda_den, n_max;
+  void *stream;
+  void *arena;                 /* device, caller-owned: job states */
+  uint64_t arena_bytes;        /* admission budget */
+  void *workspace;             /* device, caller-owned, >= mclg_server_sizes */
+  uint64_t workspace_bytes;
+} mclg_server_config;
+
+typedef struct {
+  uint64_t job_id;             /* RNG replica identity (< 2^32) and handle */
+  uint64_t L;                  /* sites */
+  uint64_t steps;              /* steps to run */
+  double rho, u0;              /* Poisson initial state */
+} mclg_job;
+
+typedef struct {
+  uint64_t job_id;
+  mclg_moments_t moments;      /* final exact moments (t = steps) */
+} mclg_job_result;
+
+int mclg_server_sizes(const mclg_server_config *cfg, uint64_t *workspace_bytes);
+int mclg_server_create(const mclg_server_config *cfg, mclg_server **out);
+/* Queue a job (host only).  MCLG_E_INVAL if it can never fit the arena. */
+int mclg_server_submit(mclg_server *srv, const mclg_job *job);
+/* Admit queued jobs while slots and arena space allow (first-fit, FIFO
+ * order), then enqueue k batched steps of every resident job; jobs that
+ * reach their step count are retired (moments computed, space freed). */
+int mclg_server_tick(mclg_server *srv, uint32_t k);
+/* Copy up to cap finished results to out; *n_out = number copied. */
+int mclg_server_poll(mclg_server *srv, mclg_job_result *out, uint32_t cap, uint32_t *n_out);
+/* Jobs queued, resident, and arena bytes in use. */
+int mclg_server_stats(const mclg_server *srv, uint64_t *queued, uint64_t *resident,
+                      uint64_t *arena_used);
+int mclg_server_destroy(mclg_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

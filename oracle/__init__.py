@@ -57,6 +57,7 @@ def lib() -> ct.CDLL:
         L.mco_get_counts.argtypes = [ct.c_void_p, u32, P(ct.c_uint16)]
         L.mco_get_t.argtypes = [ct.c_void_p, u32]
         L.mco_get_t.restype = i64
+        L.mco_set_site_offset.argtypes = [ct.c_void_p, u32, u64, i64]
         L.mco_moments.argtypes = [ct.c_void_p, u32, P(ct.c_int32), u32, P(Moments)]
         L.mco_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         L.mco_philox4x32_10.restype = None
@@ -191,6 +192,11 @@ class OracleSim:
         out = np.zeros((3, int(self.L[rep])), dtype=np.uint16)
         _check(lib().mco_get_counts(self._h, rep, _ptr(out, ct.c_uint16)), "get_counts")
         return out
+
+    def set_site_offset(self, rep: int, xoff: int, t: int = 0):
+        rc = lib().mco_set_site_offset(self._h, rep, xoff, t)
+        if rc != 0:
+            raise OracleError(f"set_site_offset rc={rc}")
 
     def t(self, rep: int = 0) -> int:
         return int(lib().mco_get_t(self._h, rep))

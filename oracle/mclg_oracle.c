@@ -511,6 +511,7 @@ struct mco_sim {
   collide_params cp;
   uint64_t *L;
   uint64_t *rid;
+  uint64_t *xoff;  /* RNG site index = x + xoff (window of a larger lattice) */
   int64_t *t;
   uint16_t **cur, **nxt; /* per replica [3][L] logical order */
   int range_error;
@@ -531,10 +532,11 @@ int mco_create(uint32_t n_rep, const uint64_t *L, const uint64_t *replica_id, ui
   s->cp.C = C; s->cp.p = lam_p; s->cp.q = lam_q; s->cp.nmax = n_max; s->cp.seed = seed;
   s->L = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
   s->rid = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
+  s->xoff = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
   s->t = (int64_t *)calloc(n_rep, sizeof(int64_t));
   s->cur = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
   s->nxt = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
-  int bad = !s->L || !s->rid || !s->t || !s->cur || !s->nxt ||
+  int bad = !s->L || !s->rid || !s->xoff || !s->t || !s->cur || !s->nxt ||
             cache_init(&s->cp.tc, C, lam_p, lam_q, n_max);
   for (uint32_t r = 0; !bad && r < n_rep; ++r) {
     s->L[r] = L[r];
@@ -554,7 +556,7 @@ void mco_destroy(mco_sim *s) {
     if (s->cur) free(s->cur[r]);
     if (s->nxt) free(s->nxt[r]);
   }
-  free(s->cur); free(s->nxt); free(s->L); free(s->rid); free(s->t);
+  free(s->cur); free(s->nxt); free(s->L); free(s->rid); free(s->xoff); free(s->t);
   cache_free(&s->cp.tc);
   free(s);
 }
@@ -580,7 +582,8 @@ int mco_init_poisson(mco_sim *s, uint32_t rep, double rho, double u0) {
     if (rc) { free(thr); return rc; }
     for (uint64_t x = 0; x < L; ++x) {
       uint32_t words[4];
-      rng_block(s->cp.seed, (uint32_t)x, 0, (uint32_t)s->rid[rep], PURPOSE_INIT, 0, words);
+      rng_block(s->cp.seed, (uint32_t)(x + s->xoff[rep]), 0, (uint32_t)s->rid[rep], PURPOSE_INIT, 0,
+                words);
       uint32_t r = words[i];
       uint32_t idx = 0;
       for (uint32_t k = 0; k + 1 < cnt; ++k) idx += (thr[k] <= r);
@@ -605,7 +608,8 @@ int mco_step_replica(mco_sim *s, uint32_t rep, uint64_t n) {
     const uint32_t t = (uint32_t)s->t[rep];
     for (uint64_t x = 0; x < L; ++x) {
       uint64_t a = in[x], b = in[L + x], c = in[2 * L + x];
-      int rc = collide_site(&s->cp, (uint32_t)s->rid[rep], t, (uint32_t)x, &a, &b, &c, 0);
+      int rc = collide_site(&s->cp, (uint32_t)s->rid[rep], t, (uint32_t)(x + s->xoff[rep]),
+                            &a, &b, &c, 0);
       if (rc == MCO_E_RANGE) status = MCO_E_RANGE;
       else if (rc) return rc;
       if (stream) {
@@ -641,6 +645,13 @@ int mco_step(mco_sim *s, uint64_t n) {
 int mco_get_counts(const mco_sim *s, uint32_t rep, uint16_t *out) {
   if (!s || rep >= s->n_rep || !out) return MCO_E_INVAL;
   memcpy(out, s->cur[rep], 3 * s->L[rep] * sizeof(uint16_t));
+  return MCO_OK;
+}
+
+int mco_set_site_offset(mco_sim *s, uint32_t rep, uint64_t xoff, int64_t t) {
+  if (!s || rep >= s->n_rep || xoff + s->L[rep] >= (1ull << 32) || t < 0) return MCO_E_INVAL;
+  s->xoff[rep] = xoff;
+  s->t[rep] = t;
   return MCO_OK;
 }
 

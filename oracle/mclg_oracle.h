@@ -60,6 +60,10 @@ int mco_step_replica(mco_sim *s, uint32_t rep, uint64_t n);
 int mco_step(mco_sim *s, uint64_t n);
 int mco_get_counts(const mco_sim *s, uint32_t rep, uint16_t *out);
 int64_t mco_get_t(const mco_sim *s, uint32_t rep);
+/* Treat replica rep as the window [xoff, xoff + L) of a larger lattice for the
+ * RNG (site index x + xoff) and set its step counter to t.  The window's own
+ * periodic wrap is wrong near its ends; callers keep a halo of t sites. */
+int mco_set_site_offset(mco_sim *s, uint32_t rep, uint64_t xoff, int64_t t);
 /* twiddle: [2*n_modes][L] int32 rows (cos_1, sin_1, cos_2, sin_2, ...) or NULL */
 int mco_moments(const mco_sim *s, uint32_t rep, const int32_t *twiddle,
                 uint32_t n_modes, mco_moments_t *out);

@@ -1,0 +1,454 @@
+// C ABI of the MCLG library: configuration, layout, context and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/mclg.h"
+#include "device.h"
+#include "tables.h"
+
+using namespace mclg;
+
+namespace {
+
+constexpr uint32_t kPadElems = 128;     // array stride granularity (256 B)
+constexpr uint32_t kMinTileSites = 256; // smallest schedule tile
+constexpr uint32_t kPoisCap = 1024;     // thresholds per initial Poisson law
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  uint64_t state_bytes = 0;
+  std::vector<uint64_t> off, stride, dense;
+  uint64_t total_sites = 0, max_tiles = 0;
+  // workspace byte offsets
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_rowbase,
+      o_rowdesc, o_thr, ws_bytes;
+};
+
+bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, Layout &lay) {
+  lay.off.resize(n);
+  lay.stride.resize(n);
+  lay.dense.resize(n);
+  uint64_t elems = 0, dense = 0, tiles = 0;
+  for (uint32_t r = 0; r < n; ++r) {
+    lay.stride[r] = align_up(L[r], kPadElems);
+    lay.off[r] = elems;
+    lay.dense[r] = dense;
+    elems += 3 * lay.stride[r];
+    dense += L[r];
+    tiles += (L[r] + kMinTileSites - 1) / kMinTileSites;
+  }
+  lay.state_bytes = elems * sizeof(uint16_t);
+  lay.total_sites = dense;
+  lay.max_tiles = tiles;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  lay.o_ctrl = take(256);
+  lay.o_slots = take(sizeof(SlotDev) * n);
+  lay.o_tslot = take(sizeof(uint32_t) * n);
+  lay.o_tiles = take(sizeof(TileDev) * tiles);
+  lay.o_list = take(sizeof(uint32_t) * n);
+  lay.o_mom = take(sizeof(MomDev) * n);
+  lay.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
+  lay.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
+  lay.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
+  lay.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
+  lay.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
+  lay.ws_bytes = o;
+  return true;
+}
+
+int validate(const mclg_config *cfg) {
+  if (!cfg || cfg->abi_version != MCLG_ABI_VERSION) return MCLG_E_INVAL;
+  if (cfg->lattice == MCLG_D2Q9) return MCLG_E_UNSUPPORTED;
+  if (cfg->lattice != MCLG_D1Q3) return MCLG_E_INVAL;
+  if (cfg->n_replicas == 0 || !cfg->L) return MCLG_E_INVAL;
+  if (cfg->flags & ~(uint32_t)MCLG_FLAG_NO_STREAM) return MCLG_E_INVAL;
+  for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
+    if (cfg->L[r] == 0 || cfg->L[r] >= (1ull << 31)) return MCLG_E_INVAL;
+    if (cfg->replica_id && cfg->replica_id[r] >= (1ull << 32)) return MCLG_E_INVAL;
+  }
+  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max)) return MCLG_E_INVAL;
+  return MCLG_OK;
+}
+
+}  // namespace
+
+struct mclg_ctx {
+  uint32_t n = 0, flags = 0;
+  uint64_t seed = 0;
+  int32_t C = 0;
+  uint32_t lam_p = 1, lam_q = 1, n_max = 0;
+  std::vector<uint64_t> L, rid;
+  hipStream_t stream = nullptr;
+  uint16_t *state = nullptr;
+  uint8_t *ws = nullptr;
+  Layout lay;
+  std::shared_ptr<const CollisionTables> tab;
+  std::vector<int64_t> t;
+  Schedule sch;
+  std::vector<TileDev> tiles;
+  std::vector<uint32_t> tile_begin, tile_end;
+  int last_hip = 0;
+  std::map<uint64_t, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+
+  uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
+  uint32_t *ticket() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl) + 1; }
+  SlotDev *slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
+  uint32_t *tslot() { return reinterpret_cast<uint32_t *>(ws + lay.o_tslot); }
+  TileDev *tiles_dev() { return reinterpret_cast<TileDev *>(ws + lay.o_tiles); }
+  MomDev *mom() { return reinterpret_cast<MomDev *>(ws + lay.o_mom); }
+  TableDev table() {
+    TableDev d;
+    d.rowbase = reinterpret_cast<const uint32_t *>(ws + lay.o_rowbase);
+    d.rowdesc = reinterpret_cast<const uint2 *>(ws + lay.o_rowdesc);
+    d.thr = reinterpret_cast<const uint32_t *>(ws + lay.o_thr);
+    return d;
+  }
+  StepParams params() const {
+    StepParams p;
+    p.seed = seed;
+    p.C = C;
+    p.lam_p = lam_p;
+    p.lam_q = lam_q;
+    p.n_max = n_max;
+    p.no_stream = (flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u;
+    p.tile_sites = sch.tile_sites();
+    return p;
+  }
+  int hip(hipError_t e) {
+    if (e == hipSuccess) return MCLG_OK;
+    last_hip = (int)e;
+    return MCLG_E_HIP;
+  }
+  void build_tiles() {
+    tiles.clear();
+    tile_begin.assign(n, 0);
+    tile_end.assign(n, 0);
+    const uint32_t ts = sch.tile_sites();
+    for (uint32_t r = 0; r < n; ++r) {
+      tile_begin[r] = (uint32_t)tiles.size();
+      for (uint64_t x0 = 0; x0 < L[r]; x0 += ts) tiles.push_back(TileDev{r, (uint32_t)x0});
+      tile_end[r] = (uint32_t)tiles.size();
+    }
+  }
+  void drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : graph_defs) (void)hipGraphDestroy(g);
+    graphs.clear();
+    graph_defs.clear();
+  }
+};
+
+extern "C" {
+
+int mclg_sizes(const mclg_config *cfg, uint64_t *state_bytes, uint64_t *workspace_bytes) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  if (!tab) return MCLG_E_INVAL;
+  Layout lay;
+  compute_layout(cfg->n_replicas, cfg->L, tab.get(), lay);
+  if (state_bytes) *state_bytes = lay.state_bytes;
+  if (workspace_bytes) *workspace_bytes = lay.ws_bytes;
+  return MCLG_OK;
+}
+
+int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out) {
+  if (!out || !init) return MCLG_E_INVAL;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!cfg->state || !cfg->workspace) return MCLG_E_INVAL;
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  if (!tab) return MCLG_E_INVAL;
+  std::unique_ptr<mclg_ctx> c(new (std::nothrow) mclg_ctx());
+  if (!c) return MCLG_E_NOMEM;
+  c->n = cfg->n_replicas;
+  c->flags = cfg->flags;
+  c->seed = cfg->seed;
+  c->C = cfg->C;
+  c->lam_p = cfg->lambda_num;
+  c->lam_q = cfg->lambda_den;
+  c->n_max = cfg->n_max;
+  c->L.assign(cfg->L, cfg->L + c->n);
+  c->rid.resize(c->n);
+  for (uint32_t r = 0; r < c->n; ++r) c->rid[r] = cfg->replica_id ? cfg->replica_id[r] : r;
+  c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  c->state = reinterpret_cast<uint16_t *>(cfg->state);
+  c->ws = reinterpret_cast<uint8_t *>(cfg->workspace);
+  c->tab = tab;
+  compute_layout(c->n, cfg->L, tab.get(), c->lay);
+  if (cfg->state_bytes < c->lay.state_bytes || cfg->workspace_bytes < c->lay.ws_bytes)
+    return MCLG_E_INVAL;
+  c->t.assign(c->n, 0);
+  c->build_tiles();
+
+  const Layout &lay = c->lay;
+  hipStream_t s = c->stream;
+  std::vector<SlotDev> slots(c->n);
+  std::vector<uint32_t> list(c->n);
+  for (uint32_t r = 0; r < c->n; ++r) {
+    slots[r].off = lay.off[r];
+    slots[r].dense = lay.dense[r];
+    slots[r].L = (uint32_t)c->L[r];
+    slots[r].stride = (uint32_t)lay.stride[r];
+    slots[r].rid = (uint32_t)c->rid[r];
+    slots[r].pad = 0;
+    list[r] = r;
+  }
+  std::vector<uint32_t> ctrl(64, 0), tz(c->n, 0);
+  // Poisson laws (host) for the initial state
+  std::vector<PoisDesc> pdesc(3 * c->n);
+  std::vector<uint32_t> pool;
+  if (init->kind == MCLG_INIT_POISSON) {
+    if (!init->rho || !init->u0) return MCLG_E_INVAL;
+    pool.assign((size_t)kPoisCap * 3 * c->n, 0);
+    for (uint32_t r = 0; r < c->n; ++r) {
+      if (!(init->rho[r] >= 0.0) || !(init->u0[r] >= -1.0 && init->u0[r] <= 1.0))
+        return MCLG_E_INVAL;
+      double mu[3];
+      feq(init->rho[r], init->u0[r], mu);
+      for (int i = 0; i < 3; ++i) {
+        uint32_t k_lo = 0;
+        std::vector<uint64_t> full;
+        if (!poisson_full(mu[i], k_lo, full)) return MCLG_E_INVAL;
+        CompactLaw cl = compact(k_lo, full);
+        if (cl.thr.size() > kPoisCap) return MCLG_E_INVAL;
+        PoisDesc &d = pdesc[3 * r + i];
+        d.off = (uint32_t)((3 * r + i) * kPoisCap);
+        d.k_first = cl.k_first;
+        d.nthr = (uint32_t)cl.thr.size();
+        d.pad = 0;
+        std::copy(cl.thr.begin(), cl.thr.end(), pool.begin() + d.off);
+      }
+    }
+  } else if (init->kind != MCLG_INIT_COUNTS || !init->counts) {
+    return MCLG_E_INVAL;
+  }
+  auto up = [&](uint64_t off, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (!e) e = up(lay.o_ctrl, ctrl.data(), 256);
+  if (!e) e = up(lay.o_slots, slots.data(), sizeof(SlotDev) * c->n);
+  if (!e) e = up(lay.o_tslot, tz.data(), sizeof(uint32_t) * c->n);
+  if (!e) e = up(lay.o_tiles, c->tiles.data(), sizeof(TileDev) * c->tiles.size());
+  if (!e) e = up(lay.o_list, list.data(), sizeof(uint32_t) * c->n);
+  if (!e) e = up(lay.o_rowbase, tab->rowbase.data(), sizeof(uint32_t) * tab->rowbase.size());
+  if (!e) e = up(lay.o_rowdesc, tab->rowdesc.data(), sizeof(uint32_t) * tab->rowdesc.size());
+  if (!e) e = up(lay.o_thr, tab->thr.data(), sizeof(uint32_t) * tab->thr.size());
+  const uint32_t ts = c->sch.tile_sites();
+  if (init->kind == MCLG_INIT_POISSON) {
+    if (!e) e = up(lay.o_pdesc, pdesc.data(), sizeof(PoisDesc) * pdesc.size());
+    if (!e) e = up(lay.o_pool, pool.data(), sizeof(uint32_t) * pool.size());
+    if (!e)
+      e = launch_init_poisson(s, c->state, c->slots(), c->tslot(), c->tiles_dev(),
+                              (uint32_t)c->tiles.size(), ts,
+                              reinterpret_cast<const PoisDesc *>(c->ws + lay.o_pdesc),
+                              reinterpret_cast<const uint32_t *>(c->ws + lay.o_pool), c->seed,
+                              c->err());
+  } else {
+    if (!e)
+      e = launch_init_counts(s, c->state, c->slots(), c->tiles_dev(), (uint32_t)c->tiles.size(),
+                             ts, init->counts);
+  }
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return c->hip(e);
+  uint32_t err = 0;
+  e = hipMemcpy(&err, c->err(), sizeof(err), hipMemcpyDeviceToHost);
+  if (e) return c->hip(e);
+  *out = c.release();
+  return err ? MCLG_E_RANGE : MCLG_OK;
+}
+
+static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
+                      uint32_t n_slots) {
+  hipError_t e = launch_step(c->sch, c->stream, c->state, c->slots(), c->tslot(),
+                             c->tiles_dev() + tile_lo, tile_hi - tile_lo, nullptr, slot_first,
+                             n_slots, c->ticket(), c->err(), c->table(), c->params());
+  return c->hip(e);
+}
+
+int mclg_step(mclg_ctx *c, uint64_t n_steps) {
+  if (!c) return MCLG_E_INVAL;
+  for (uint64_t i = 0; i < n_steps; ++i) {
+    int rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n);
+    if (rc) return rc;
+    for (auto &t : c->t) ++t;
+  }
+  return MCLG_OK;
+}
+
+int mclg_step_replica(mclg_ctx *c, uint32_t r, uint64_t n_steps) {
+  if (!c || r >= c->n) return MCLG_E_INVAL;
+  for (uint64_t i = 0; i < n_steps; ++i) {
+    int rc = step_range(c, c->tile_begin[r], c->tile_end[r], r, 1);
+    if (rc) return rc;
+    ++c->t[r];
+  }
+  return MCLG_OK;
+}
+
+int mclg_step_graph(mclg_ctx *c, uint64_t n_steps) {
+  if (!c || !c->stream || n_steps == 0) return MCLG_E_INVAL;
+  auto it = c->graphs.find(n_steps);
+  if (it == c->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e) return c->hip(e);
+    int rc = MCLG_OK;
+    for (uint64_t i = 0; i < n_steps && !rc; ++i)
+      rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n);
+    e = hipStreamEndCapture(c->stream, &g);
+    if (rc) return rc;
+    if (e) return c->hip(e);
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e) { (void)hipGraphDestroy(g); return c->hip(e); }
+    c->graph_defs.push_back(g);
+    it = c->graphs.emplace(n_steps, ge).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second, c->stream);
+  if (e) return c->hip(e);
+  for (auto &t : c->t) t += (int64_t)n_steps;
+  return MCLG_OK;
+}
+
+static int read_err(mclg_ctx *c) {
+  uint32_t err = 0;
+  hipError_t e = hipMemcpyAsync(&err, c->err(), sizeof(err), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) return c->hip(e);
+  return err ? MCLG_E_RANGE : MCLG_OK;
+}
+
+int mclg_check(mclg_ctx *c) {
+  if (!c) return MCLG_E_INVAL;
+  return read_err(c);
+}
+
+int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_moments_t *out) {
+  if (!c || !out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle)) return MCLG_E_INVAL;
+  hipStream_t s = c->stream;
+  hipError_t e = launch_zero(s, reinterpret_cast<unsigned long long *>(c->mom()),
+                             (uint64_t)c->n * (sizeof(MomDev) / 8));
+  if (!e)
+    e = launch_moments(s, c->state, c->slots(), c->tslot(), c->tiles_dev(),
+                       (uint32_t)c->tiles.size(), c->sch.tile_sites(),
+                       (c->flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u, twiddle, n_modes, c->mom());
+  std::vector<MomDev> h(c->n);
+  if (!e) e = hipMemcpyAsync(h.data(), c->mom(), sizeof(MomDev) * c->n, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return c->hip(e);
+  for (uint32_t r = 0; r < c->n; ++r) {
+    mclg_moments_t &o = out[r];
+    std::memset(&o, 0, sizeof(o));
+    const unsigned long long *v = h[r].v;
+    o.t = c->t[r];
+    o.sites = (int64_t)c->L[r];
+    for (int i = 0; i < 3; ++i) {
+      o.sum_n[i] = (int64_t)v[i];
+      o.sum_n2[i] = (int64_t)v[3 + i];
+      o.sum_nn[i] = (int64_t)v[6 + i];
+    }
+    o.sum_N = (int64_t)v[9];
+    o.sum_J = (int64_t)v[10];
+    o.sum_N2 = (int64_t)v[11];
+    o.n0_odd = (int64_t)v[12];
+    o.max_N = (int64_t)v[13];
+    for (uint32_t m = 0; m < n_modes; ++m) {
+      o.fourier[m][0] = (int64_t)v[14 + 2 * m];
+      o.fourier[m][1] = (int64_t)v[15 + 2 * m];
+    }
+  }
+  return read_err(c);
+}
+
+int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
+  if (!c || !out || r >= c->n) return MCLG_E_INVAL;
+  const uint64_t L = c->L[r], stride = c->lay.stride[r];
+  std::vector<uint16_t> raw(3 * stride);
+  hipError_t e = hipMemcpyAsync(raw.data(), c->state + c->lay.off[r], 3 * stride * 2,
+                                hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) return c->hip(e);
+  const uint64_t tm = (c->flags & MCLG_FLAG_NO_STREAM) ? 0 : (uint64_t)c->t[r] % L;
+  for (uint64_t x = 0; x < L; ++x) {
+    out[x] = raw[(x + tm) % L];
+    out[L + x] = raw[stride + x];
+    out[2 * L + x] = raw[2 * stride + (x + L - tm) % L];
+  }
+  return read_err(c);
+}
+
+int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads) {
+  if (!c) return MCLG_E_INVAL;
+  if (!(groups == 1 || groups == 2 || groups == 4 || groups == 8)) return MCLG_E_INVAL;
+  if (threads < 64 || threads > 1024 || threads % 64) return MCLG_E_INVAL;
+  c->sch.groups = groups;
+  c->sch.threads = threads;
+  c->build_tiles();
+  c->drop_graphs();
+  hipError_t e = hipMemcpyAsync(c->tiles_dev(), c->tiles.data(), sizeof(TileDev) * c->tiles.size(),
+                                hipMemcpyHostToDevice, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  return c->hip(e);
+}
+
+int mclg_destroy(mclg_ctx *c) {
+  if (!c) return MCLG_E_INVAL;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->drop_graphs();
+  delete c;
+  return MCLG_OK;
+}
+
+const char *mclg_strerror(int code) {
+  switch (code) {
+    case MCLG_OK: return "ok";
+    case MCLG_E_INVAL: return "invalid argument";
+    case MCLG_E_RANGE: return "site occupation out of range";
+    case MCLG_E_HIP: return "HIP runtime error";
+    case MCLG_E_NOMEM: return "host out of memory";
+    case MCLG_E_UNSUPPORTED: return "unsupported lattice or mode";
+    case MCLG_E_FULL: return "server full";
+    default: return "unknown error";
+  }
+}
+
+int mclg_last_hip_error(const mclg_ctx *c) { return c ? c->last_hip : 0; }
+
+int mclg_table_row(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t absJ, uint32_t n0,
+                   uint64_t *thr, uint32_t cap, uint32_t *m_out) {
+  if (!thr || !m_out) return MCLG_E_INVAL;
+  std::vector<uint64_t> full;
+  if (!collision_row_full(C, p, q, N, absJ, n0, full)) return MCLG_E_INVAL;
+  if (full.size() > cap) return MCLG_E_INVAL;
+  std::copy(full.begin(), full.end(), thr);
+  *m_out = (uint32_t)full.size() + 1;
+  return MCLG_OK;
+}
+
+int mclg_poisson_thresholds(double mu, uint32_t *k_lo, uint32_t *cnt, uint64_t *thr,
+                            uint32_t cap) {
+  if (!k_lo || !cnt || !thr) return MCLG_E_INVAL;
+  std::vector<uint64_t> full;
+  if (!poisson_full(mu, *k_lo, full)) return MCLG_E_INVAL;
+  if (full.size() > cap) return MCLG_E_INVAL;
+  std::copy(full.begin(), full.end(), thr);
+  *cnt = (uint32_t)full.size() + 1;
+  return MCLG_OK;
+}
+
+}  // extern "C"

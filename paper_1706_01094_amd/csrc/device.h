@@ -1,0 +1,89 @@
+// Device-side data structures and launchers of the MCLG library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mclg {
+
+// One simulated lattice ("slot").  Its state is three uint16 arrays of
+// `stride` elements starting at element `off` of the state buffer:
+// n_-1, n_0, n_+1.  In-place shifted layout: logical n_+1(x, t) is stored at
+// physical (x - t) mod L, n_-1(x, t) at (x + t) mod L, n_0(x) at x, so that
+// streaming costs nothing and every element is read and written by exactly
+// one site per step.  With MCLG_FLAG_NO_STREAM the layout is unshifted.
+struct SlotDev {
+  uint64_t off;      // element offset of the n_-1 array in the state buffer
+  uint64_t dense;    // packed site offset (init counts, twiddles)
+  uint32_t L;        // sites
+  uint32_t stride;   // elements per array (L rounded up to 128)
+  uint32_t rid;      // RNG replica identity
+  uint32_t pad;
+};
+
+struct TileDev {
+  uint32_t slot;     // slot index
+  uint32_t x0;       // first site (multiple of 4)
+};
+
+struct StepParams {
+  uint64_t seed;
+  int32_t C;
+  uint32_t lam_p, lam_q;
+  uint32_t n_max;
+  uint32_t no_stream;
+  uint32_t tile_sites;
+};
+
+struct TableDev {
+  const uint32_t *rowbase;
+  const uint2 *rowdesc;
+  const uint32_t *thr;
+};
+
+// Exact per-slot sums, all modulo 2^64.
+struct MomDev {
+  unsigned long long v[32];
+  // 0..2 sum n, 3..5 sum n^2, 6..8 sum nn, 9 sum N, 10 sum J, 11 sum N^2,
+  // 12 n0 odd, 13 max N, 14..29 fourier (m, cos/sin)
+};
+
+struct PoisDesc {
+  uint32_t off;      // offset in the threshold pool
+  uint32_t k_first;
+  uint32_t nthr;     // q - 1
+  uint32_t pad;
+};
+
+// Launch configuration of the fused stream+collide kernel.
+struct Schedule {
+  uint32_t groups = 2;    // groups of 4 sites per thread
+  uint32_t threads = 256; // threads per block
+  uint32_t tile_sites() const { return groups * threads * 4; }
+};
+
+hipError_t launch_step(const Schedule &sch, hipStream_t s, uint16_t *state, const SlotDev *slots,
+                       uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
+                       const uint32_t *slot_list, uint32_t slot_first, uint32_t n_slots,
+                       uint32_t *ticket, uint32_t *err, TableDev tab, StepParams p);
+
+hipError_t launch_init_poisson(hipStream_t s, uint16_t *state, const SlotDev *slots,
+                               const uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
+                               uint32_t tile_sites, const PoisDesc *desc, const uint32_t *pool,
+                               uint64_t seed, uint32_t *err);
+
+hipError_t launch_init_counts(hipStream_t s, uint16_t *state, const SlotDev *slots,
+                              const TileDev *tiles, uint32_t n_tiles, uint32_t tile_sites,
+                              const uint16_t *counts);
+
+hipError_t launch_zero(hipStream_t s, unsigned long long *p, uint64_t n);
+
+hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *slots,
+                          const uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
+                          uint32_t tile_sites, uint32_t no_stream, const int32_t *twiddle,
+                          uint32_t n_modes, MomDev *out);
+
+hipError_t launch_set_t(hipStream_t s, uint32_t *tslot, const uint32_t *slot_list, uint32_t n,
+                        uint32_t value);
+
+}  // namespace mclg

@@ -1,0 +1,413 @@
+// Continuous-batching server of MCLG simulation jobs.
+//
+// Jobs are queued on the host, admitted first-fit into a caller-owned device
+// arena (their state stays resident until they finish), and advanced together
+// by the batched stream+collide kernel: every launch covers the tiles of all
+// resident jobs, each job at its own step t (per-slot step counters on the
+// device).  A job's result depends only on (seed, job id, L, steps, rho, u0)
+// and the collision parameters, never on what else is resident.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/mclg.h"
+#include "device.h"
+#include "tables.h"
+
+using namespace mclg;
+
+namespace {
+
+constexpr uint32_t kPad = 128;
+constexpr uint32_t kPoisCap = 1024;
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+struct SrvLayout {
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_rowbase,
+      o_rowdesc, o_thr, bytes, max_tiles;
+};
+
+SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
+                     uint32_t tile_sites) {
+  SrvLayout l;
+  uint64_t o = 0;
+  auto take = [&](uint64_t b) {
+    uint64_t at = o;
+    o = align_up(o + b, 256);
+    return at;
+  };
+  const uint64_t n = cfg->max_slots;
+  // every resident site occupies 6 arena bytes; each slot adds one partial tile
+  l.max_tiles = cfg->arena_bytes / (6ull * tile_sites) + n + 1;
+  l.o_ctrl = take(256);
+  l.o_slots = take(sizeof(SlotDev) * n);
+  l.o_tslot = take(sizeof(uint32_t) * n);
+  l.o_tiles = take(sizeof(TileDev) * l.max_tiles);
+  l.o_list = take(sizeof(uint32_t) * n);
+  l.o_mom = take(sizeof(MomDev) * n);
+  l.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
+  l.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
+  l.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
+  l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
+  l.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
+  l.bytes = o;
+  return l;
+}
+
+struct Resident {
+  mclg_job job;
+  uint64_t arena_off;   // bytes
+  uint64_t bytes;
+  uint64_t t = 0;
+  bool active = false;
+};
+
+}  // namespace
+
+struct mclg_server {
+  mclg_server_config cfg;
+  std::shared_ptr<const CollisionTables> tab;
+  SrvLayout lay;
+  Schedule sch;
+  uint8_t *ws = nullptr;
+  uint16_t *arena = nullptr;
+  hipStream_t s = nullptr;
+  std::deque<mclg_job> queue;
+  std::vector<Resident> slot;
+  std::map<uint64_t, uint64_t> free_spans;  // offset -> bytes
+  uint64_t arena_used = 0;
+  std::vector<mclg_job_result> done;
+  // host mirrors of device tables (kept alive across async uploads)
+  std::vector<SlotDev> h_slots;
+  std::vector<TileDev> h_tiles;
+  std::vector<uint32_t> h_list;
+  std::vector<PoisDesc> h_pdesc;
+  std::vector<uint32_t> h_pool;
+  uint32_t n_tiles = 0, n_active = 0;
+  int last_hip = 0;
+
+  uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
+  uint32_t *ticket() { return err() + 1; }
+  SlotDev *d_slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
+  uint32_t *d_tslot() { return reinterpret_cast<uint32_t *>(ws + lay.o_tslot); }
+  TileDev *d_tiles() { return reinterpret_cast<TileDev *>(ws + lay.o_tiles); }
+  uint32_t *d_list() { return reinterpret_cast<uint32_t *>(ws + lay.o_list); }
+  MomDev *d_mom() { return reinterpret_cast<MomDev *>(ws + lay.o_mom); }
+  TableDev table() {
+    TableDev d;
+    d.rowbase = reinterpret_cast<const uint32_t *>(ws + lay.o_rowbase);
+    d.rowdesc = reinterpret_cast<const uint2 *>(ws + lay.o_rowdesc);
+    d.thr = reinterpret_cast<const uint32_t *>(ws + lay.o_thr);
+    return d;
+  }
+  int hip(hipError_t e) {
+    if (e == hipSuccess) return MCLG_OK;
+    last_hip = (int)e;
+    return MCLG_E_HIP;
+  }
+  hipError_t up(void *dst, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  }
+
+  bool alloc(uint64_t bytes, uint64_t &off) {
+    for (auto it = free_spans.begin(); it != free_spans.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        uint64_t rest = it->second - bytes;
+        free_spans.erase(it);
+        if (rest) free_spans[off + bytes] = rest;
+        arena_used += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    arena_used -= bytes;
+    auto it = free_spans.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_spans.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_spans.erase(nx);
+    }
+    if (it != free_spans.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_spans.erase(it);
+      }
+    }
+  }
+  static uint64_t job_bytes(uint64_t L) { return 3 * align_up(L, kPad) * sizeof(uint16_t); }
+
+  StepParams params() const {
+    StepParams p;
+    p.seed = cfg.seed;
+    p.C = cfg.C;
+    p.lam_p = cfg.lambda_num;
+    p.lam_q = cfg.lambda_den;
+    p.n_max = cfg.n_max;
+    p.no_stream = 0;
+    p.tile_sites = sch.tile_sites();
+    return p;
+  }
+
+  // Rebuild the tile and slot lists of the resident jobs and upload them.
+  hipError_t rebuild_lists() {
+    h_tiles.clear();
+    h_list.clear();
+    const uint32_t ts = sch.tile_sites();
+    for (uint32_t i = 0; i < slot.size(); ++i) {
+      if (!slot[i].active) continue;
+      h_list.push_back(i);
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) h_tiles.push_back(TileDev{i, (uint32_t)x0});
+    }
+    if (h_tiles.size() > lay.max_tiles) return hipErrorInvalidValue;
+    n_tiles = (uint32_t)h_tiles.size();
+    n_active = (uint32_t)h_list.size();
+    hipError_t e = up(d_tiles(), h_tiles.data(), sizeof(TileDev) * h_tiles.size());
+    if (!e) e = up(d_list(), h_list.data(), sizeof(uint32_t) * h_list.size());
+    return e;
+  }
+
+  // Admit queued jobs (FIFO, stop at the first that does not fit).
+  int admit() {
+    std::vector<uint32_t> fresh;
+    while (!queue.empty()) {
+      const mclg_job &j = queue.front();
+      uint32_t free_slot = UINT32_MAX;
+      for (uint32_t i = 0; i < slot.size(); ++i)
+        if (!slot[i].active) { free_slot = i; break; }
+      if (free_slot == UINT32_MAX) break;
+      uint64_t bytes = job_bytes(j.L), off = 0;
+      if (!alloc(bytes, off)) break;
+      Resident &r = slot[free_slot];
+      r.job = j;
+      r.arena_off = off;
+      r.bytes = bytes;
+      r.t = 0;
+      r.active = true;
+      SlotDev &sd = h_slots[free_slot];
+      sd.off = off / sizeof(uint16_t);
+      sd.dense = 0;
+      sd.L = (uint32_t)j.L;
+      sd.stride = (uint32_t)align_up(j.L, kPad);
+      sd.rid = (uint32_t)j.job_id;
+      sd.pad = 0;
+      double mu[3];
+      feq(j.rho, j.u0, mu);
+      for (int i = 0; i < 3; ++i) {
+        uint32_t k_lo = 0;
+        std::vector<uint64_t> full;
+        poisson_full(mu[i], k_lo, full);
+        CompactLaw cl = compact(k_lo, full);
+        PoisDesc &d = h_pdesc[3 * free_slot + i];
+        d.off = (3 * free_slot + i) * kPoisCap;
+        d.k_first = cl.k_first;
+        d.nthr = (uint32_t)cl.thr.size();
+        std::copy(cl.thr.begin(), cl.thr.end(), h_pool.begin() + d.off);
+      }
+      fresh.push_back(free_slot);
+      queue.pop_front();
+    }
+    if (fresh.empty()) return MCLG_OK;
+    // Upload the changed host mirrors; then initialise the new jobs only.
+    std::vector<TileDev> init_tiles;
+    const uint32_t ts = sch.tile_sites();
+    for (uint32_t i : fresh)
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) init_tiles.push_back(TileDev{i, (uint32_t)x0});
+    if (init_tiles.size() > lay.max_tiles) return MCLG_E_INVAL;
+    hipError_t e = up(d_slots(), h_slots.data(), sizeof(SlotDev) * h_slots.size());
+    if (!e) e = up(ws + lay.o_pdesc, h_pdesc.data(), sizeof(PoisDesc) * h_pdesc.size());
+    if (!e) e = up(ws + lay.o_pool, h_pool.data(), sizeof(uint32_t) * h_pool.size());
+    // fresh slot ids and their tiles go through the list/tile areas, which
+    // are rebuilt right after
+    if (!e) e = up(d_list(), fresh.data(), sizeof(uint32_t) * fresh.size());
+    if (!e) e = up(d_tiles(), init_tiles.data(), sizeof(TileDev) * init_tiles.size());
+    if (!e) e = launch_set_t(s, d_tslot(), d_list(), (uint32_t)fresh.size(), 0u);
+    if (!e)
+      e = launch_init_poisson(s, arena, d_slots(), d_tslot(), d_tiles(), (uint32_t)init_tiles.size(),
+                              ts, reinterpret_cast<const PoisDesc *>(ws + lay.o_pdesc),
+                              reinterpret_cast<const uint32_t *>(ws + lay.o_pool), cfg.seed, err());
+    if (!e) e = hipStreamSynchronize(s);
+    if (!e) e = rebuild_lists();
+    if (!e) e = hipStreamSynchronize(s);
+    return hip(e);
+  }
+
+  // Moments of finished jobs, then free their slots.
+  int retire() {
+    std::vector<uint32_t> fin;
+    for (uint32_t i = 0; i < slot.size(); ++i)
+      if (slot[i].active && slot[i].t >= slot[i].job.steps) fin.push_back(i);
+    if (fin.empty()) return MCLG_OK;
+    std::vector<TileDev> tl;
+    const uint32_t ts = sch.tile_sites();
+    for (uint32_t i : fin)
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) tl.push_back(TileDev{i, (uint32_t)x0});
+    if (tl.size() > lay.max_tiles) return MCLG_E_INVAL;
+    hipError_t e = up(d_tiles(), tl.data(), sizeof(TileDev) * tl.size());
+    if (!e) e = launch_zero(s, reinterpret_cast<unsigned long long *>(d_mom()),
+                            (uint64_t)slot.size() * (sizeof(MomDev) / 8));
+    if (!e)
+      e = launch_moments(s, arena, d_slots(), d_tslot(), d_tiles(), (uint32_t)tl.size(), ts, 0u,
+                         nullptr, 0u, d_mom());
+    std::vector<MomDev> h(slot.size());
+    if (!e) e = hipMemcpyAsync(h.data(), d_mom(), sizeof(MomDev) * h.size(), hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return hip(e);
+    for (uint32_t i : fin) {
+      mclg_job_result res;
+      std::memset(&res, 0, sizeof(res));
+      res.job_id = slot[i].job.job_id;
+      mclg_moments_t &o = res.moments;
+      const unsigned long long *v = h[i].v;
+      o.t = (int64_t)slot[i].t;
+      o.sites = (int64_t)slot[i].job.L;
+      for (int k = 0; k < 3; ++k) {
+        o.sum_n[k] = (int64_t)v[k];
+        o.sum_n2[k] = (int64_t)v[3 + k];
+        o.sum_nn[k] = (int64_t)v[6 + k];
+      }
+      o.sum_N = (int64_t)v[9];
+      o.sum_J = (int64_t)v[10];
+      o.sum_N2 = (int64_t)v[11];
+      o.n0_odd = (int64_t)v[12];
+      o.max_N = (int64_t)v[13];
+      done.push_back(res);
+      slot[i].active = false;
+      release(slot[i].arena_off, slot[i].bytes);
+    }
+    e = rebuild_lists();
+    if (!e) e = hipStreamSynchronize(s);
+    return hip(e);
+  }
+};
+
+extern "C" {
+
+int mclg_server_sizes(const mclg_server_config *cfg, uint64_t *workspace_bytes) {
+  if (!cfg || cfg->abi_version != MCLG_ABI_VERSION || cfg->max_slots == 0 || !workspace_bytes)
+    return MCLG_E_INVAL;
+  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max)) return MCLG_E_INVAL;
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  if (!tab) return MCLG_E_INVAL;
+  Schedule sch;
+  *workspace_bytes = srv_layout(cfg, tab.get(), sch.tile_sites()).bytes;
+  return MCLG_OK;
+}
+
+int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
+  uint64_t need = 0;
+  int rc = mclg_server_sizes(cfg, &need);
+  if (rc) return rc;
+  if (!out || !cfg->arena || !cfg->workspace || cfg->workspace_bytes < need) return MCLG_E_INVAL;
+  std::unique_ptr<mclg_server> sv(new (std::nothrow) mclg_server());
+  if (!sv) return MCLG_E_NOMEM;
+  sv->cfg = *cfg;
+  sv->tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  sv->lay = srv_layout(cfg, sv->tab.get(), sv->sch.tile_sites());
+  sv->ws = reinterpret_cast<uint8_t *>(cfg->workspace);
+  sv->arena = reinterpret_cast<uint16_t *>(cfg->arena);
+  sv->s = reinterpret_cast<hipStream_t>(cfg->stream);
+  sv->slot.resize(cfg->max_slots);
+  sv->h_slots.assign(cfg->max_slots, SlotDev{});
+  sv->h_pdesc.assign(3ull * cfg->max_slots, PoisDesc{});
+  sv->h_pool.assign((size_t)kPoisCap * 3 * cfg->max_slots, 0);
+  uint64_t usable = cfg->arena_bytes / 256 * 256;
+  if (usable) sv->free_spans[0] = usable;
+  std::vector<uint32_t> ctrl(64, 0), tz(cfg->max_slots, 0);
+  const CollisionTables &t = *sv->tab;
+  hipError_t e = sv->up(sv->ws + sv->lay.o_ctrl, ctrl.data(), 256);
+  if (!e) e = sv->up(sv->d_tslot(), tz.data(), 4 * tz.size());
+  if (!e) e = sv->up(sv->ws + sv->lay.o_rowbase, t.rowbase.data(), 4 * t.rowbase.size());
+  if (!e) e = sv->up(sv->ws + sv->lay.o_rowdesc, t.rowdesc.data(), 4 * t.rowdesc.size());
+  if (!e) e = sv->up(sv->ws + sv->lay.o_thr, t.thr.data(), 4 * t.thr.size());
+  if (!e) e = hipStreamSynchronize(sv->s);
+  if (e) return sv->hip(e);
+  *out = sv.release();
+  return MCLG_OK;
+}
+
+int mclg_server_submit(mclg_server *sv, const mclg_job *job) {
+  if (!sv || !job || job->L == 0 || job->L >= (1ull << 31) || job->job_id >= (1ull << 32))
+    return MCLG_E_INVAL;
+  if (!(job->rho >= 0.0) || !(job->u0 >= -1.0 && job->u0 <= 1.0)) return MCLG_E_INVAL;
+  if (mclg_server::job_bytes(job->L) > sv->cfg.arena_bytes / 256 * 256) return MCLG_E_INVAL;
+  double mu[3];
+  feq(job->rho, job->u0, mu);
+  for (double m : mu) {
+    uint32_t k_lo = 0;
+    std::vector<uint64_t> full;
+    if (!poisson_full(m, k_lo, full) || compact(k_lo, full).thr.size() > kPoisCap) return MCLG_E_INVAL;
+  }
+  sv->queue.push_back(*job);
+  return MCLG_OK;
+}
+
+int mclg_server_tick(mclg_server *sv, uint32_t k) {
+  if (!sv) return MCLG_E_INVAL;
+  int rc = sv->admit();
+  if (rc) return rc;
+  uint32_t left = k;
+  while (left > 0) {
+    if (sv->n_active == 0) {
+      rc = sv->admit();
+      if (rc) return rc;
+      if (sv->n_active == 0) break;
+    }
+    uint64_t chunk = left;
+    for (auto &r : sv->slot)
+      if (r.active) chunk = std::min<uint64_t>(chunk, r.job.steps - r.t);
+    for (uint64_t i = 0; i < chunk; ++i) {
+      hipError_t e = launch_step(sv->sch, sv->s, sv->arena, sv->d_slots(), sv->d_tslot(),
+                                 sv->d_tiles(), sv->n_tiles, sv->d_list(), 0, sv->n_active,
+                                 sv->ticket(), sv->err(), sv->table(), sv->params());
+      if (e) return sv->hip(e);
+    }
+    for (auto &r : sv->slot)
+      if (r.active) r.t += chunk;
+    left -= (uint32_t)chunk;
+    rc = sv->retire();
+    if (rc) return rc;
+    rc = sv->admit();
+    if (rc) return rc;
+  }
+  return MCLG_OK;
+}
+
+int mclg_server_poll(mclg_server *sv, mclg_job_result *out, uint32_t cap, uint32_t *n_out) {
+  if (!sv || !n_out || (cap && !out)) return MCLG_E_INVAL;
+  uint32_t n = (uint32_t)std::min<size_t>(cap, sv->done.size());
+  std::copy(sv->done.begin(), sv->done.begin() + n, out);
+  sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+  *n_out = n;
+  uint32_t err = 0;
+  hipError_t e = hipMemcpy(&err, sv->err(), sizeof(err), hipMemcpyDeviceToHost);
+  if (e) return sv->hip(e);
+  return err ? MCLG_E_RANGE : MCLG_OK;
+}
+
+int mclg_server_stats(const mclg_server *sv, uint64_t *queued, uint64_t *resident,
+                      uint64_t *arena_used) {
+  if (!sv) return MCLG_E_INVAL;
+  if (queued) *queued = sv->queue.size();
+  if (resident) *resident = sv->n_active;
+  if (arena_used) *arena_used = sv->arena_used;
+  return MCLG_OK;
+}
+
+int mclg_server_destroy(mclg_server *sv) {
+  if (!sv) return MCLG_E_INVAL;
+  if (sv->s) (void)hipStreamSynchronize(sv->s);
+  delete sv;
+  return MCLG_OK;
+}
+
+}  // extern "C"

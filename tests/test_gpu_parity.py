@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit for bit.
+
+The state is integer counts, so the bar is exact equality of every count
+after every compared step.  Inputs are seeded (synth/); the oracle computes
+its own initial state from the same rule or takes the same synthetic counts.
+Full-size runs are checked on light-cone windows the oracle recomputes
+independently, and by exact conservation.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_1706_01094_amd.mclg import E_RANGE, Lattice, MclgError
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(L, seed, C=10, lam=(1, 1), n_max=255, rho=10.0, u0=0.0, counts=None, flags=0,
+         replica_id=None):
+    say("case", dict(L=L, seed=seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags))
+    g = Lattice(L, seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, counts=counts, flags=flags,
+                replica_id=replica_id)
+    o = O.OracleSim(L, seed, C=C, lam=lam, n_max=n_max, flags=flags, replica_id=replica_id)
+    Ls = np.atleast_1d(L)
+    rhos = np.broadcast_to(np.asarray(rho, dtype=float), (len(Ls),))
+    u0s = np.broadcast_to(np.asarray(u0, dtype=float), (len(Ls),))
+    off = 0
+    for r in range(len(Ls)):
+        if counts is None:
+            o.init_poisson(r, float(rhos[r]), float(u0s[r]))
+        else:
+            n = int(Ls[r])
+            o.init_counts(r, np.asarray(counts).reshape(-1)[3 * off: 3 * (off + n)].reshape(3, n))
+            off += n
+    return g, o
+
+
+def same(g, o, r=0, allow_range=False):
+    a = g.counts(r, allow_range=allow_range)
+    b = o.counts(r)
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"replica {r} t={o.t(r)}: {len(bad)} counts differ, first {bad[:5].tolist()}")
+
+
+def test_plain_small_every_step():
+    """L = 256, rho = 10, u = 0, seed 1, C = 10, lambda = 1: 1000 steps, the
+    full state compared after every step."""
+    w = synth.PLAIN_SMALL
+    g, o = pair(w["L"], w["seed"], rho=w["rho"], u0=w["u0"])
+    same(g, o)
+    for _ in range(w["steps"]):
+        g.step(1)
+        o.step(1)
+        same(g, o)
+    m = g.moments()[0]
+    mo = o.moments(0)
+    for k in ("t", "sum_n", "sum_n2", "sum_nn", "sum_N", "sum_J", "sum_N2", "n0_odd", "max_N"):
+        assert m[k] == mo[k], k
+
+
+@pytest.mark.parametrize("groups,threads", [(1, 64), (2, 256), (4, 128), (8, 1024), (2, 512)])
+def test_ragged_tiles_and_schedules(groups, threads):
+    """Several tiles plus a ragged tail, at u != 0; every schedule gives the
+    oracle's bits."""
+    L = 3 * 2048 + 37
+    g, o = pair(L, 7, rho=30.0, u0=0.15)
+    g.set_schedule(groups, threads)
+    for _ in range(12):
+        g.step(5)
+        o.step(5)
+        same(g, o)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7, 129])
+def test_tiny_lattices(L):
+    counts = synth.random_counts(L, seed=L)
+    g, o = pair(L, 3, counts=counts)
+    for _ in range(20):
+        g.step(1)
+        o.step(1)
+        same(g, o)
+
+
+def test_direct_path_above_n_max():
+    """Sites with N > n_max take the paper's literal sub-collision loop."""
+    g, o = pair(3000, 11, n_max=24, rho=30.0, u0=-0.05)
+    m = g.moments()[0]
+    assert m["max_N"] > 24
+    for _ in range(10):
+        g.step(3)
+        o.step(3)
+        same(g, o)
+
+
+@pytest.mark.parametrize("C,lam", [(0, (1, 1)), (1, (1, 1)), (3, (1, 2)), (10, (3, 4)), (-1, (1, 1))])
+def test_collision_parameters(C, lam):
+    g, o = pair(2500, 13, C=C, lam=lam, rho=20.0, u0=0.1)
+    for _ in range(8):
+        g.step(4)
+        o.step(4)
+        same(g, o)
+
+
+def test_no_stream_flag():
+    g, o = pair(2000, 17, rho=40.0, flags=1)
+    for _ in range(10):
+        g.step(2)
+        o.step(2)
+        same(g, o)
+
+
+def test_moments_with_fourier_modes():
+    import torch
+    L = 5000
+    g, o = pair(L, 19, rho=25.0, u0=0.05)
+    tw = synth.twiddles(L, 3)
+    twd = torch.as_tensor(tw).to("cuda:0")
+    for _ in range(3):
+        g.step(7)
+        o.step(7)
+        m = g.moments(twd, 3)[0]
+        mo = o.moments(0, tw)
+        assert m["fourier"][:3] == mo["fourier"][:3]
+        for k in ("t", "sum_n", "sum_n2", "sum_nn", "sum_N", "sum_J", "sum_N2", "n0_odd", "max_N"):
+            assert m[k] == mo[k], k
+
+
+def test_overflow_is_flagged_and_site_kept():
+    """A site with N > 65535 is not collided and raises the sticky range
+    error on both sides."""
+    L = 64
+    counts = synth.random_counts(L, seed=5)
+    counts[:, 10] = 30000
+    g, o = pair(L, 23, counts=counts)
+    g.step(1)
+    rc = o.step(1)
+    assert rc == -2
+    assert g.check() == E_RANGE
+    same(g, o, allow_range=True)
+    with pytest.raises(MclgError):
+        g.counts(0)
+
+
+def test_batched_replicas_step_replica_and_graph():
+    """Uneven replicas in one launch, single-replica launches and a captured
+    HIP graph all reproduce the oracle; graph replays are checked one by one
+    with eager work in between."""
+    L = [100, 2048, 3000, 777, 5, 4096]
+    rid = [10, 11, 12, 13, 14, 99]
+    rho = [5.0, 10.0, 50.0, 80.0, 20.0, 33.0]
+    u0 = [0.0, 0.1, -0.2, 0.05, 0.0, 0.15]
+    g, o = pair(L, 29, rho=rho, u0=u0, replica_id=rid)
+    for r in range(len(L)):
+        same(g, o, r)
+    g.step(10)
+    o.step(10)
+    for r in range(len(L)):
+        same(g, o, r)
+    g.step_replica(2, 5)
+    o.step(5, rep=2)
+    g.step(3)
+    o.step(3)
+    for r in range(len(L)):
+        same(g, o, r)
+    for _ in range(3):
+        g.step_graph(4)
+        o.step(4)
+        for r in range(len(L)):
+            same(g, o, r)
+        g.step(1)
+        o.step(1)
+    for r in range(len(L)):
+        same(g, o, r)
+
+
+def _window_check(g, L, seed, rho, u0, T, x0s, W=1500, counts=None):
+    for x0 in x0s:
+        lo = x0 - T
+        n = W + 2 * T
+        o = O.OracleSim([n], seed, C=10)
+        o.set_site_offset(0, lo, 0)
+        if counts is None:
+            o.init_poisson(0, rho, u0)
+        else:
+            o.init_counts(0, counts[:, lo:lo + n])
+        o.step(T)
+        want = o.counts(0)[:, T:T + W]
+        got = g.counts(0)[:, x0:x0 + W]
+        assert np.array_equal(got, want), f"window at {x0}"
+
+
+def test_full_size_plain_large_windows():
+    """L = 2^24, rho = 50, u0 = 0.1 in the benchmark's launch schedule: exact
+    conservation over the whole lattice and the oracle's light-cone windows."""
+    w = synth.PLAIN_LARGE
+    L = w["L"]
+    say("full-size", L)
+    g = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    m0 = g.moments()[0]
+    T = 16
+    g.step(T)
+    m1 = g.moments()[0]
+    assert m1["sum_N"] == m0["sum_N"] and m1["sum_J"] == m0["sum_J"]
+    assert m1["n0_odd"] == m0["n0_odd"]
+    rng = np.random.default_rng(0)
+    x0s = [T, L // 2, L - 1500 - T] + [int(v) for v in rng.integers(T, L - 1500 - T, size=3)]
+    _window_check(g, L, w["seed"], w["rho"], w["u0"], T, x0s)
+
+
+def test_full_size_density_wave():
+    """L = 2^22 density wave from synthetic counts: whole-lattice state and
+    the int64 Fourier amplitude equal the oracle after 6 steps."""
+    import torch
+    w = synth.DENSITY_WAVE
+    L = w["L"]
+    counts = synth.density_wave_counts()
+    say("density wave", L)
+    g = Lattice(L, w["seed"], counts=counts)
+    o = O.OracleSim([L], w["seed"], C=10)
+    o.init_counts(0, counts)
+    tw = synth.twiddles(L, 1)
+    twd = torch.as_tensor(tw).to("cuda:0")
+    for _ in range(2):
+        g.step(3)
+        o.step(3)
+        same(g, o)
+        assert g.moments(twd, 1)[0]["fourier"][0] == o.moments(0, tw)["fourier"][0]
+
+
+def test_full_size_batched_sampled_replicas():
+    """All 1024 replicas of the batched workload in one launch per step;
+    a sample of replicas recomputed whole by the oracle."""
+    man = synth.replica_manifest()
+    say("batched", len(man["L"]), int(man["L"].sum()))
+    g = Lattice(man["L"], synth.BATCHED["seed"], rho=man["rho"], u0=man["u0"],
+                replica_id=man["replica_id"])
+    T = 6
+    g.step(T)
+    for r in [0, 1, 511, 777, 1023]:
+        o = O.OracleSim([int(man["L"][r])], synth.BATCHED["seed"], C=10,
+                        replica_id=[int(man["replica_id"][r])])
+        o.init_poisson(0, float(man["rho"][r]), float(man["u0"][r]))
+        o.step(T)
+        assert np.array_equal(g.counts(r), o.counts(0)), r

@@ -109,10 +109,12 @@ __device__ __forceinline__ void collide(uint32_t &a, uint32_t &b, uint32_t &c, u
   const uint32_t absJ = (uint32_t)(J < 0 ? -J : J);
   uint32_t bn;
   if (N <= p.n_max) {
+    // fiber states ascend in n0 = par + 2k
+    const uint32_t par = (N - absJ) & 1u;
     const uint32_t base = tab.rowbase[(N * (N + 1u) >> 1) + absJ];
-    const uint2 d = tab.rowdesc[base + ((N - absJ - b) >> 1)];
+    const uint2 d = tab.rowdesc[base + ((b - par) >> 1)];
     const uint32_t idx = count_le(tab.thr + d.x, (d.y >> 16) - 1u, r);
-    bn = ((N - absJ) & 1u) + 2u * ((d.y & 0xffffu) + idx);
+    bn = par + 2u * ((d.y & 0xffffu) + idx);
   } else if (p.C < 0) {
     atomicOr(err, kErrEqRange);
     return;

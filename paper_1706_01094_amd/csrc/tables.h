@@ -13,7 +13,8 @@ namespace mclg {
 
 // Device image of the collision tables (copied verbatim to the workspace).
 //   rowbase[N (N + 1) / 2 + |J|] = index of the fiber's first row
-//   rowdesc[rowbase + (N - |J| - n0) / 2] = {thr offset, k_first | q << 16}
+//   rowdesc[rowbase + (n0 - par) / 2] = {thr offset, k_first | q << 16},
+//     par = (N - |J|) mod 2 (fiber states ascend in n0 = par + 2k)
 //   thr[offset .. offset + q - 2] ascending uint32 thresholds
 // Sampling: n0' = ((N - |J|) & 1) + 2 (k_first + #{i : thr[offset + i] <= r}).
 struct CollisionTables {

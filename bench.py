@@ -72,9 +72,11 @@ def run_plain(args, torch, M):
     L = w["L"]
     lat = M.Lattice(L, w["seed"], C=10, lam=(1, 1), n_max=255, rho=w["rho"], u0=w["u0"])
     if args.schedule:
-        g, t = (int(v) for v in args.schedule.split(","))
-        lat.set_schedule(g, t)
+        g, t, b = (int(v) for v in args.schedule.split(","))
+        lat.set_schedule(g, t, b)
     stream = lat.stream
+    cov, lds_bytes = lat.lds_coverage()
+    run_plain.lds = {"expected_lds_fraction": round(cov, 5), "lds_bytes": lds_bytes}
     lat.step(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -106,7 +108,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10_000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--schedule", default="", help="groups,threads")
+    ap.add_argument("--schedule", default="", help="groups,threads,lds_bytes")
     ap.add_argument("--graph", action="store_true", help="launch steps from captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     args = ap.parse_args()
@@ -140,7 +142,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "d1q3_L16M_rho50_u0.1", "L": L, "rho": 50.0, "u0": 0.1, "C": 10,
                    "lambda": 1, "n_max": 255, "seed": 2, "launch": "graph" if args.graph else "plain",
-                   "schedule": args.schedule or "default"},
+                   "schedule": args.schedule or "default", **getattr(run_plain, "lds", {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }

@@ -150,10 +150,17 @@ int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
  * synchronises. */
 int mclg_check(mclg_ctx *ctx);
 
-/* Select the launch schedule: sites per thread (1, 2, 4 or 8 groups of four
- * sites) and threads per block (64..1024, multiple of 64).  Any choice gives
- * identical bits. */
-int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t threads_per_block);
+/* Select the launch schedule: chunks of eight sites per lane per tile (1, 2
+ * or 4), threads per block (64..1024, multiple of 64) and the
+ * bytes of LDS each block devotes to its replica's collision image (0..131072;
+ * the image caches the most visited table rows, misses read the exact rows in
+ * global memory).  Any choice gives identical bits; synchronises the stream. */
+int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t threads_per_block,
+                      uint32_t lds_budget_bytes);
+
+/* Expected fraction of site updates whose draw is decided from LDS (from the
+ * product-Poisson law the images were built for) and the LDS bytes per block. */
+int mclg_lds_coverage(const mclg_ctx *ctx, double *expected_fraction, uint32_t *lds_bytes);
 
 int mclg_destroy(mclg_ctx *ctx);
 const char *mclg_strerror(int code);

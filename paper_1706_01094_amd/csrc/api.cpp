@@ -2,8 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <memory>
 #include <new>
 #include <vector>
@@ -19,6 +21,7 @@ namespace {
 constexpr uint32_t kPadElems = 128;     // array stride granularity (256 B)
 constexpr uint32_t kMinTileSites = 256; // smallest schedule tile
 constexpr uint32_t kPoisCap = 1024;     // thresholds per initial Poisson law
+constexpr uint32_t kMaxImage = 128 * 1024; // largest LDS collision image
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -27,8 +30,8 @@ struct Layout {
   std::vector<uint64_t> off, stride, dense;
   uint64_t total_sites = 0, max_tiles = 0;
   // workspace byte offsets
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_rowbase,
-      o_rowdesc, o_thr, ws_bytes;
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_ipool,
+      o_rowbase, o_rowdesc, o_thr, ws_bytes;
 };
 
 bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, Layout &lay) {
@@ -61,6 +64,8 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
   lay.o_mom = take(sizeof(MomDev) * n);
   lay.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   lay.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
+  lay.o_idesc = take(sizeof(ImageDesc) * n);
+  lay.o_ipool = take((uint64_t)kMaxImage * n);
   lay.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   lay.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
   lay.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
@@ -102,6 +107,12 @@ struct mclg_ctx {
   int last_hip = 0;
   std::map<uint64_t, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
+  // LDS collision images (a cache in front of the exact global rows)
+  std::vector<double> est_rho, est_u;   // density and velocity each image targets
+  std::vector<ImageDesc> img_desc;
+  std::vector<uint8_t> img_pool;
+  uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
+  double coverage = 0.0;                // expected LDS hit fraction (site-weighted)
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
   uint32_t *ticket() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl) + 1; }
@@ -142,6 +153,89 @@ struct mclg_ctx {
       for (uint64_t x0 = 0; x0 < L[r]; x0 += ts) tiles.push_back(TileDev{r, (uint32_t)x0});
       tile_end[r] = (uint32_t)tiles.size();
     }
+  }
+  ImageDesc *img_desc_dev() { return reinterpret_cast<ImageDesc *>(ws + lay.o_idesc); }
+  StepLaunch launch_args(uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
+                         uint32_t n_slots) {
+    StepLaunch a;
+    a.state = state;
+    a.slots = slots();
+    a.tslot = tslot();
+    a.tiles = tiles_dev() + tile_lo;
+    a.n_tiles = tile_hi - tile_lo;
+    a.slot_list = nullptr;
+    a.slot_first = slot_first;
+    a.n_slots = n_slots;
+    a.ticket = ticket();
+    a.err = err();
+    a.tab = table();
+    a.p = params();
+    a.images = img_desc_dev();
+    a.image_pool = ws + lay.o_ipool;
+    a.lds_bytes = lds_bytes;
+    a.max_blocks = max_blocks;
+    return a;
+  }
+  // (Re)build the images for the current budget, upload them, and size the
+  // persistent grid from the runtime's occupancy for that LDS footprint.
+  hipError_t prepare_images() {
+    const uint32_t queues = (sch.threads / 64u) * kQueueBytesPerWave;
+    const uint32_t room = lds_limit > queues ? lds_limit - queues : 0u;
+    const uint32_t budget = std::min(sch.lds_budget, std::min(kMaxImage, room)) / 16u * 16u;
+    std::map<std::pair<double, double>, uint32_t> uniq;
+    std::vector<uint32_t> which(n);
+    std::vector<std::pair<double, double>> keys;
+    for (uint32_t r = 0; r < n; ++r) {
+      auto k = std::make_pair(est_rho[r], est_u[r]);
+      auto it = uniq.find(k);
+      if (it == uniq.end()) { it = uniq.emplace(k, (uint32_t)keys.size()).first; keys.push_back(k); }
+      which[r] = it->second;
+    }
+    std::vector<LdsImage> ims(keys.size());
+    std::atomic<size_t> next(0);
+    auto work = [&]() {
+      for (size_t i; (i = next.fetch_add(1)) < keys.size();)
+        ims[i] = budget >= 64 ? build_image(*tab, keys[i].first, keys[i].second, budget) : LdsImage();
+    };
+    std::vector<std::thread> th;
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (unsigned i = 0; i < nt; ++i) th.emplace_back(work);
+    for (auto &x : th) x.join();
+    img_pool.clear();
+    img_desc.assign(n, ImageDesc{});
+    std::vector<uint64_t> at(ims.size());
+    lds_bytes = 16;
+    for (size_t i = 0; i < ims.size(); ++i) {
+      at[i] = img_pool.size();
+      auto b = ims[i].blob();
+      img_pool.insert(img_pool.end(), b.begin(), b.end());
+      img_pool.resize((img_pool.size() + 15) / 16 * 16, 0);
+      lds_bytes = std::max<uint32_t>(lds_bytes, (uint32_t)(b.size() + 15) / 16 * 16);
+    }
+    double cov = 0.0, sites = 0.0;
+    for (uint32_t r = 0; r < n; ++r) {
+      const LdsImage &im = ims[which[r]];
+      ImageDesc &d = img_desc[r];
+      d.off = at[which[r]];
+      d.bytes = (uint32_t)(im.dir.size() ? im.blob().size() : 0);
+      d.dir_bytes = im.dir_bytes();
+      d.dim_a = im.dim_a;
+      d.dim_c = im.dim_c;
+      d.b_lo = im.b_lo;
+      d.nb = im.nb;
+      cov += im.coverage * (double)L[r];
+      sites += (double)L[r];
+    }
+    coverage = sites > 0 ? cov / sites : 0.0;
+    if (img_pool.size() > (uint64_t)kMaxImage * n) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (!img_pool.empty())
+      e = hipMemcpyAsync(ws + lay.o_ipool, img_pool.data(), img_pool.size(), hipMemcpyHostToDevice, stream);
+    if (!e) e = hipMemcpyAsync(img_desc_dev(), img_desc.data(), sizeof(ImageDesc) * n,
+                               hipMemcpyHostToDevice, stream);
+    if (!e) e = hipStreamSynchronize(stream);
+    if (!e) e = step_occupancy(sch, lds_bytes, n_cu, max_blocks);
+    return e;
   }
   void drop_graphs() {
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -265,6 +359,30 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   }
   if (!e) e = hipStreamSynchronize(s);
   if (e) return c->hip(e);
+  // device limits for the LDS images
+  int dev = 0, v = 0;
+  e = hipGetDevice(&dev);
+  if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (!e) c->lds_limit = (uint32_t)std::max(0, v - 1024);
+  if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+  if (!e) c->n_cu = (uint32_t)std::max(1, v);
+  if (e) return c->hip(e);
+  // what density and velocity each replica's image should target
+  c->est_rho.assign(c->n, 0.0);
+  c->est_u.assign(c->n, 0.0);
+  if (init->kind == MCLG_INIT_POISSON) {
+    for (uint32_t r = 0; r < c->n; ++r) { c->est_rho[r] = init->rho[r]; c->est_u[r] = init->u0[r]; }
+  } else {
+    std::vector<mclg_moments_t> m(c->n);
+    int rc2 = mclg_moments(c.get(), nullptr, 0, m.data());
+    if (rc2 && rc2 != MCLG_E_RANGE) return rc2;
+    for (uint32_t r = 0; r < c->n; ++r) {
+      c->est_rho[r] = (double)m[r].sum_N / (double)c->L[r];
+      c->est_u[r] = m[r].sum_N ? (double)m[r].sum_J / (double)m[r].sum_N : 0.0;
+    }
+  }
+  e = c->prepare_images();
+  if (e) return c->hip(e);
   uint32_t err = 0;
   e = hipMemcpy(&err, c->err(), sizeof(err), hipMemcpyDeviceToHost);
   if (e) return c->hip(e);
@@ -274,9 +392,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
 
 static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
                       uint32_t n_slots) {
-  hipError_t e = launch_step(c->sch, c->stream, c->state, c->slots(), c->tslot(),
-                             c->tiles_dev() + tile_lo, tile_hi - tile_lo, nullptr, slot_first,
-                             n_slots, c->ticket(), c->err(), c->table(), c->params());
+  hipError_t e = launch_step(c->sch, c->stream, c->launch_args(tile_lo, tile_hi, slot_first, n_slots));
   return c->hip(e);
 }
 
@@ -392,18 +508,28 @@ int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
   return read_err(c);
 }
 
-int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads) {
+int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t lds_budget) {
   if (!c) return MCLG_E_INVAL;
-  if (!(groups == 1 || groups == 2 || groups == 4 || groups == 8)) return MCLG_E_INVAL;
+  if (!(groups == 1 || groups == 2 || groups == 4)) return MCLG_E_INVAL;
   if (threads < 64 || threads > 1024 || threads % 64) return MCLG_E_INVAL;
+  if (lds_budget > kMaxImage) return MCLG_E_INVAL;
   c->sch.groups = groups;
   c->sch.threads = threads;
+  c->sch.lds_budget = lds_budget;
   c->build_tiles();
   c->drop_graphs();
   hipError_t e = hipMemcpyAsync(c->tiles_dev(), c->tiles.data(), sizeof(TileDev) * c->tiles.size(),
                                 hipMemcpyHostToDevice, c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
+  if (!e) e = c->prepare_images();
   return c->hip(e);
+}
+
+int mclg_lds_coverage(const mclg_ctx *c, double *expected_fraction, uint32_t *lds_bytes) {
+  if (!c || !expected_fraction || !lds_bytes) return MCLG_E_INVAL;
+  *expected_fraction = c->coverage;
+  *lds_bytes = c->lds_bytes;
+  return MCLG_OK;
 }
 
 int mclg_destroy(mclg_ctx *c) {

@@ -48,6 +48,14 @@ struct MomDev {
   // 12 n0 odd, 13 max N, 14..29 fourier (m, cos/sin)
 };
 
+// Where a slot's LDS image lives in the image pool (see LdsImage).
+struct ImageDesc {
+  uint64_t off;        // byte offset in the image pool (16-byte aligned)
+  uint32_t bytes;      // 0 = no image
+  uint32_t dir_bytes;
+  uint32_t dim_a, dim_c, b_lo, nb;
+};
+
 struct PoisDesc {
   uint32_t off;      // offset in the threshold pool
   uint32_t k_first;
@@ -57,15 +65,40 @@ struct PoisDesc {
 
 // Launch configuration of the fused stream+collide kernel.
 struct Schedule {
-  uint32_t groups = 2;    // groups of 4 sites per thread
-  uint32_t threads = 256; // threads per block
-  uint32_t tile_sites() const { return groups * threads * 4; }
+  uint32_t groups = 1;       // chunks of 8 sites per lane per tile
+  uint32_t threads = 1024;   // threads per block
+  uint32_t lds_budget = 112 * 1024;  // bytes of collision image per block
+  uint32_t tile_sites() const { return groups * threads * 8; }
 };
 
-hipError_t launch_step(const Schedule &sch, hipStream_t s, uint16_t *state, const SlotDev *slots,
-                       uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
-                       const uint32_t *slot_list, uint32_t slot_first, uint32_t n_slots,
-                       uint32_t *ticket, uint32_t *err, TableDev tab, StepParams p);
+struct StepLaunch {
+  uint16_t *state;
+  const SlotDev *slots;
+  uint32_t *tslot;
+  const TileDev *tiles;
+  uint32_t n_tiles;
+  const uint32_t *slot_list;  // slots advanced by this launch, or null for a range
+  uint32_t slot_first, n_slots;
+  uint32_t *ticket, *err;
+  TableDev tab;
+  StepParams p;
+  const ImageDesc *images;    // per slot
+  const uint8_t *image_pool;
+  uint32_t lds_bytes;         // LDS per block for the image (largest image, 16-byte multiple);
+                              // the per-wave miss queues follow it
+  uint32_t max_blocks;        // persistent grid size
+};
+
+hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
+
+// Bytes of LDS per wave for its queue of undecided draws.
+constexpr uint32_t kQueueBytesPerWave = 128 * 16;
+
+// Persistent grid size: resident blocks per CU for this LDS footprint x CUs.
+hipError_t step_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,
+                          uint32_t &max_blocks);
+// Dynamic LDS of one block: image (rounded to 16 bytes) + miss queues.
+uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes);
 
 hipError_t launch_init_poisson(hipStream_t s, uint16_t *state, const SlotDev *slots,
                                const uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,

@@ -11,6 +11,8 @@
 // dense contraction, so no MFMA.
 #include "device.h"
 
+#include <algorithm>
+
 namespace mclg {
 namespace {
 
@@ -26,9 +28,11 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
       k.x += 0x9E3779B9u;
       k.y += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    // one 32x32 -> 64-bit multiply per product (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y,
+                   (uint32_t)p0);
   }
   return c;
 }
@@ -76,7 +80,7 @@ struct WordStream {
 
 // The paper's C sub-collisions one by one (Eq. (select), Eq. (omega)); used
 // for sites with N > n_max.  Returns the new rest count.
-__device__ __noinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint32_t c,
+__device__ __forceinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint32_t c,
                                                 const StepParams &p, uint32_t x, uint32_t t,
                                                 uint32_t rid) {
   WordStream ws;
@@ -98,87 +102,402 @@ __device__ __noinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint32_t
   return b;
 }
 
-// One site: returns the post-collision (a, b, c) in place.
-__device__ __forceinline__ void collide(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t r,
-                                        const StepParams &p, const TableDev &tab, uint32_t x,
-                                        uint32_t t, uint32_t rid, uint32_t *err) {
-  const uint32_t N = a + b + c;
-  if (N > 65535u) { atomicOr(err, kErrOverflow); return; }
-  if (N < 2u || p.C == 0) return;
-  const int32_t J = (int32_t)c - (int32_t)a;
-  const uint32_t absJ = (uint32_t)(J < 0 ? -J : J);
-  uint32_t bn;
-  if (N <= p.n_max) {
-    // fiber states ascend in n0 = par + 2k
-    const uint32_t par = (N - absJ) & 1u;
-    const uint32_t base = tab.rowbase[(N * (N + 1u) >> 1) + absJ];
-    const uint2 d = tab.rowdesc[base + ((b - par) >> 1)];
-    const uint32_t idx = count_le(tab.thr + d.x, (d.y >> 16) - 1u, r);
-    bn = par + 2u * ((d.y & 0xffffu) + idx);
-  } else if (p.C < 0) {
-    atomicOr(err, kErrEqRange);
-    return;
-  } else {
-    bn = collide_direct(a, b, c, p, x, t, rid);
-  }
-  a = (uint32_t)(((int32_t)N - (int32_t)bn - J) >> 1);
-  c = (uint32_t)(((int32_t)N - (int32_t)bn + J) >> 1);
-  b = bn;
+// Exact row of the global tables: the number of thresholds <= r.
+__device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
+                                                   uint32_t b, uint32_t par, uint32_t r) {
+  const uint32_t base = tab.rowbase[(N * (N + 1u) >> 1) + absJ];
+  const uint2 d = tab.rowdesc[base + ((b - par) >> 1)];  // fiber states ascend in n0
+  return (d.y & 0xffffu) + count_le(tab.thr + d.x, (d.y >> 16) - 1u, r);
 }
 
-// Fused stream + collide over one tile of tile_sites sites per block.
-// G groups of four consecutive sites per thread; one Philox call per group.
-template <int G>
-__global__ void __launch_bounds__(1024) k_step(
-    uint16_t *__restrict__ state, const SlotDev *__restrict__ slots, uint32_t *tslot,
-    const TileDev *__restrict__ tiles, const uint32_t *__restrict__ slot_list,
-    uint32_t slot_first, uint32_t n_slots, uint32_t *ticket, uint32_t *err, TableDev tab,
-    StepParams p) {
-  const TileDev tile = tiles[blockIdx.x];
-  const SlotDev sl = slots[tile.slot];
-  const uint32_t t = tslot[tile.slot];
-  const uint32_t L = sl.L;
-  const uint32_t tm = p.no_stream ? 0u : t % L;
-  uint16_t *const nm = state + sl.off;
-  uint16_t *const n0 = nm + sl.stride;
-  uint16_t *const np = n0 + sl.stride;
-  const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
+// The slot's collision image in LDS: directory of (min(a,c), max(a,c)) pairs,
+// then 16-byte records (k_s, top 16 bits of 7 thresholds).  Decides the
+// outcome exactly whenever the top 16 bits of r fall strictly inside the
+// record's window and differ from every stored value; returns false
+// otherwise.
+struct LdsView {
+  const uint16_t *dir;
+  const uint4 *rec;
+  uint32_t dim_a, dim_c, b_lo, nb;
+};
+
+__device__ __forceinline__ bool lds_outcome(const LdsView &v, uint32_t a, uint32_t b, uint32_t c,
+                                            uint32_t r, uint32_t &idx) {
+  const uint32_t lo = min(a, c), hi = max(a, c), bi = b - v.b_lo;
+  if (lo >= v.dim_a || hi >= v.dim_c || bi >= v.nb) return false;
+  const uint32_t pidx = v.dir[lo * v.dim_c + hi];
+  if (pidx == 0xFFFFu) return false;
+  const uint4 q = v.rec[pidx * v.nb + bi];
+  const uint32_t rh = r >> 16;
+  const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
+                 t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
+  const bool inside = (rh > t1) & (rh < t7);
+  const bool tie = (rh == t2) | (rh == t3) | (rh == t4) | (rh == t5) | (rh == t6);
+  idx = (q.x & 0xffffu) + (uint32_t)(t2 < rh) + (uint32_t)(t3 < rh) + (uint32_t)(t4 < rh) +
+        (uint32_t)(t5 < rh) + (uint32_t)(t6 < rh);
+  return inside & !tie;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t get16(const uint32_t (&w)[4], int e) {
+  return (e & 1) ? (w[e >> 1] >> 16) : (w[e >> 1] & 0xffffu);
+}
+__device__ __forceinline__ void set16(uint32_t (&w)[4], int e, uint32_t v) {
+  if (e & 1) w[e >> 1] = (w[e >> 1] & 0xffffu) | (v << 16);
+  else w[e >> 1] = (w[e >> 1] & 0xffff0000u) | (v & 0xffffu);
+}
+// out = elements [s, s + 8) of the sixteen uint16 of (lo ++ hi); s is
+// wave-uniform, 0 <= s <= 8.
+__device__ __forceinline__ void extract8(const uint32_t (&lo)[4], const uint32_t (&hi)[4],
+                                         uint32_t s, uint32_t (&out)[4]) {
+  const uint32_t w[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  const uint32_t sh = (s & 1u) * 2u;
+  switch (s >> 1) {
+#define MCLG_EXTRACT_CASE(K)                                                      \
+  case K:                                                                         \
+    for (int j = 0; j < 4; ++j)                                                   \
+      out[j] = (K + j + 1 < 8) ? __builtin_amdgcn_alignbyte(w[(K + j + 1) & 7], w[K + j], sh) \
+                               : w[K + j];                                        \
+    break;
+    MCLG_EXTRACT_CASE(0)
+    MCLG_EXTRACT_CASE(1)
+    MCLG_EXTRACT_CASE(2)
+    MCLG_EXTRACT_CASE(3)
+#undef MCLG_EXTRACT_CASE
+    default:
+      for (int j = 0; j < 4; ++j) out[j] = hi[j];
+  }
+}
+__device__ __forceinline__ void shfl_down4(const uint32_t (&v)[4], uint32_t (&o)[4]) {
+  for (int j = 0; j < 4; ++j) o[j] = __shfl_down(v[j], 1u);
+}
+__device__ __forceinline__ void shfl_up4(const uint32_t (&v)[4], uint32_t (&o)[4]) {
+  for (int j = 0; j < 4; ++j) o[j] = __shfl_up(v[j], 1u);
+}
+__device__ __forceinline__ void load4(const uint16_t *p, uint32_t (&v)[4]) {
+  const uint4 q = *reinterpret_cast<const uint4 *>(p);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void store4(uint16_t *p, const uint32_t (&v)[4]) {
+  *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Eight consecutive elements [s, s + 8) of an array whose window of 512
+// elements starting at s does not wrap: lane-aligned 16-byte loads, the next
+// lane's vector by a shuffle (the last lane reads the vector after the
+// window), and a byte-align by the wave-uniform misalignment s & 7.
+__device__ __forceinline__ void load_window(const uint16_t *arr, uint32_t s, uint32_t lane,
+                                            uint32_t (&out)[4]) {
+  const uint32_t bmis = s & 7u, A = s - bmis;
+  uint32_t v[4], nx[4];
+  load4(arr + A + 8u * lane, v);
+  if (bmis == 0u) {
+    for (int j = 0; j < 4; ++j) out[j] = v[j];
+    return;
+  }
+  uint32_t ext[4];
+  load4(arr + A + 512u, ext);
+  shfl_down4(v, nx);
+  if (lane == 63u)
+    for (int j = 0; j < 4; ++j) nx[j] = ext[j];
+  extract8(v, nx, bmis, out);
+}
+// Inverse of load_window: lanes 1..63 store their aligned vector; lane 0
+// and lane 63 store only the elements of the two boundary vectors this
+// window owns (the rest belongs to the neighbouring windows).
+__device__ __forceinline__ void store_window(uint16_t *arr, uint32_t s, uint32_t lane,
+                                             const uint32_t (&o)[4]) {
+  const uint32_t bmis = s & 7u, A = s - bmis;
+  if (bmis == 0u) {
+    store4(arr + A + 8u * lane, o);
+    return;
+  }
+  uint32_t prev[4], al[4];
+  shfl_up4(o, prev);
+  extract8(prev, o, 8u - bmis, al);
+  if (lane != 0u) {
+    store4(arr + A + 8u * lane, al);
+  } else {
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const uint32_t xg = tile.x0 + (g * blockDim.x + threadIdx.x) * 4u;
-    if (xg >= L) continue;
-    const uint4 w = philox10(make_uint4(xg >> 2, t, sl.rid, 0u), key);
+    for (int e = 0; e < 8; ++e)
+      if ((uint32_t)e < 8u - bmis) arr[s + e] = (uint16_t)get16(o, e);
+  }
+  if (lane == 63u) {
 #pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-      const uint32_t x = xg + k;
-      if (x >= L) break;
-      uint32_t pm = x + tm;
-      pm -= (pm >= L) ? L : 0u;
-      const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-      uint32_t a = nm[pm], b = n0[x], c = np[pp];
-      collide(a, b, c, word_of(w, k), p, tab, x, t, sl.rid, err);
-      nm[pm] = (uint16_t)a;
-      n0[x] = (uint16_t)b;
-      np[pp] = (uint16_t)c;
+    for (int e = 0; e < 8; ++e)
+      if ((uint32_t)e < bmis) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)bmis + e);
+  }
+}
+
+// Element k of a site triple gets rest count bn; n_-1 and n_+1 follow from
+// the conserved N and J (Eq. (collcons)).
+__device__ __forceinline__ void apply_outcome(uint32_t (&va)[4], uint32_t (&vb)[4],
+                                              uint32_t (&vc)[4], int k, uint32_t bn) {
+  const int32_t ea = (int32_t)get16(va, k), eb = (int32_t)get16(vb, k),
+                ec = (int32_t)get16(vc, k);
+  const int32_t N = ea + eb + ec, J = ec - ea;
+  set16(va, k, (uint32_t)((N - (int32_t)bn - J) >> 1));
+  set16(vb, k, bn);
+  set16(vc, k, (uint32_t)((N - (int32_t)bn + J) >> 1));
+}
+
+// Per-wave queue of draws the LDS image could not decide (or sites with
+// N > n_max); drained by all lanes at once.
+constexpr uint32_t kQueue = kQueueBytesPerWave / 16;
+
+// Exact outcome for a queued site: global row, or the literal loop.
+__device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepParams &p,
+                                                const TableDev &tab, uint32_t t, uint32_t rid,
+                                                uint32_t *err) {
+  const uint32_t x = e.x, a = e.y & 0xffffu, b = e.y >> 16, c = e.z, r = e.w;
+  const uint32_t N = a + b + c;
+  if (N <= p.n_max) {
+    const uint32_t absJ = (uint32_t)abs((int32_t)c - (int32_t)a);
+    const uint32_t par = (N - absJ) & 1u;
+    return par + 2u * global_outcome(tab, N, absJ, b, par, r);
+  }
+  if (p.C < 0) {
+    atomicOr(err, kErrEqRange);
+    return b;
+  }
+  return collide_direct(a, b, c, p, x, t, rid);
+}
+
+// Per-chunk state of one lane while its eight sites are decided.
+struct ChunkCtx {
+  uint32_t x8;     // first of the lane's eight sites
+  uint4 w0, w1;    // Philox words of sites x8 .. x8 + 7
+  uint32_t L;
+  uint32_t qn;     // the wave's queue fill (wave-uniform)
+};
+
+// Where a slot's three arrays are and how they are shifted at step t.
+struct SlotView {
+  uint16_t *nm, *n0, *np;
+  uint32_t L, tm, t, rid;
+};
+
+// Site K of the lane: decide from the LDS image, or queue it (all lanes
+// place their queued sites by ballot order).
+template <int K>
+__device__ __forceinline__ void decide_site(ChunkCtx &cx, uint32_t (&va)[4], uint32_t (&vb)[4],
+                                            uint32_t (&vc)[4], const LdsView &lv, uint4 *queue,
+                                            const StepParams &p, const TableDev &tab, uint32_t t,
+                                            uint32_t rid, uint32_t *err) {
+  const uint4 &w = K < 4 ? cx.w0 : cx.w1;
+  const uint32_t r = (K & 3) == 0 ? w.x : (K & 3) == 1 ? w.y : (K & 3) == 2 ? w.z : w.w;
+  const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
+  const uint32_t N = ea + eb + ec;
+  bool miss = false;
+  if (cx.x8 + K < cx.L) {
+    if (N > 65535u) {
+      atomicOr(err, kErrOverflow);
+    } else if (N >= 2u && p.C != 0) {
+      uint32_t idx;
+      if (N <= p.n_max && lds_outcome(lv, ea, eb, ec, r, idx)) {
+        const uint32_t absJ = (uint32_t)abs((int32_t)ec - (int32_t)ea);
+        apply_outcome(va, vb, vc, K, ((N - absJ) & 1u) + 2u * idx);
+      } else {
+        miss = true;
+      }
     }
   }
+  const uint64_t bal = __ballot(miss);
+  if (bal) {
+    const uint32_t cnt = (uint32_t)__popcll(bal);
+    const uint4 e = make_uint4(cx.x8 + K, ea | (eb << 16), ec, r);
+    if (cx.qn + cnt <= kQueue) {
+      // queued: the state keeps the pre-collision counts until the drain
+      // writes the final ones
+      if (miss) queue[cx.qn + lanes_below(bal)] = e;
+      cx.qn += cnt;
+    } else if (miss) {  // queue full: this lane resolves the site itself
+      apply_outcome(va, vb, vc, K, resolve_queued(e, p, tab, t, rid, err));
+    }
+  }
+}
+
+// Resolve every queued draw of the wave (all lanes in parallel) and store
+// the site's three final counts.  The wave first waits until all of its
+// earlier memory operations have completed -- among them the stores that
+// wrote the pre-collision counts of these sites -- so the final counts land
+// after them.
+__device__ __forceinline__ void drain_queue(uint4 *queue, uint32_t qn, uint32_t lane,
+                                            const SlotView &v, const StepParams &p,
+                                            const TableDev &tab, uint32_t *err) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (uint32_t i = lane; i < qn; i += 64u) {
+    const uint4 e = queue[i];
+    const uint32_t x = e.x, ea = e.y & 0xffffu, eb = e.y >> 16, ec = e.z;
+    const uint32_t bn = resolve_queued(e, p, tab, v.t, v.rid, err);
+    const int32_t N = (int32_t)(ea + eb + ec), J = (int32_t)ec - (int32_t)ea;
+    uint32_t pm = x + v.tm;
+    pm -= (pm >= v.L) ? v.L : 0u;
+    const uint32_t pp = x >= v.tm ? x - v.tm : x + v.L - v.tm;
+    v.nm[pm] = (uint16_t)((N - (int32_t)bn - J) >> 1);
+    v.n0[x] = (uint16_t)bn;
+    v.np[pp] = (uint16_t)((N - (int32_t)bn + J) >> 1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Fused stream + collide.  Persistent blocks: block i takes a contiguous run
+// of tiles (so consecutive tiles mostly share a slot) and loads the slot's
+// collision image into LDS whenever the slot changes.  A tile holds
+// G chunks of 512 sites per wave; each lane owns 8 consecutive sites of a
+// chunk (two Philox calls).  All state of a tile is loaded before any of it
+// is stored: every physical element belongs to exactly one site per step.
+template <int G>
+__global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
+  extern __shared__ uint4 lds[];
+  const StepParams &p = a.p;
+  const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  uint4 *const queue = lds + a.lds_bytes / 16u + wave * kQueue;
+  const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
+  const uint32_t tb = blockIdx.x * per;
+  const uint32_t te = min(a.n_tiles, tb + per);
+  uint32_t cur = 0xFFFFFFFFu;
+  uint32_t qn = 0;  // queued draws of this wave (wave-uniform), all of slot `cur`
+  SlotView sv;
+  sv.nm = sv.n0 = sv.np = nullptr;
+  sv.L = 1; sv.tm = sv.t = sv.rid = 0;
+  LdsView lv;
+  lv.dir = reinterpret_cast<const uint16_t *>(lds);
+  lv.rec = lds;
+  lv.dim_a = lv.dim_c = lv.nb = lv.b_lo = 0;
+  for (uint32_t ti = tb; ti < te; ++ti) {
+    const TileDev tile = a.tiles[ti];
+    if (tile.slot != cur) {
+      if (qn) drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
+      qn = 0;
+      cur = tile.slot;
+      const ImageDesc im = a.images[cur];
+      __syncthreads();  // previous image no longer in use
+      const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
+      for (uint32_t i = threadIdx.x; i < im.bytes / 16u; i += blockDim.x) lds[i] = src[i];
+      __syncthreads();
+      lv.dim_a = im.bytes ? im.dim_a : 0u;
+      lv.dim_c = im.dim_c;
+      lv.b_lo = im.b_lo;
+      lv.nb = im.nb;
+      lv.rec = lds + im.dir_bytes / 16u;
+      const SlotDev sl = a.slots[cur];
+      sv.t = a.tslot[cur];
+      sv.L = sl.L;
+      sv.tm = p.no_stream ? 0u : sv.t % sl.L;
+      sv.rid = sl.rid;
+      sv.nm = a.state + sl.off;
+      sv.n0 = sv.nm + sl.stride;
+      sv.np = sv.n0 + sl.stride;
+    } else if (qn > kQueue - 64u) {
+      drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
+      qn = 0;
+    }
+    const uint32_t L = sv.L, tm = sv.tm, t = sv.t;
+    uint16_t *const nm = sv.nm;
+    uint16_t *const n0 = sv.n0;
+    uint16_t *const np = sv.np;
+
+    // ---- load ----
+    uint32_t va[G][4], vb[G][4], vc[G][4];
+    uint32_t xs[G], sm[G], sp[G];
+    bool fast[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      xs[g] = tile.x0 + ((uint32_t)g * nwaves + wave) * 512u;
+      sm[g] = xs[g] + tm;
+      sm[g] -= (sm[g] >= L) ? L : 0u;
+      sp[g] = xs[g] >= tm ? xs[g] - tm : xs[g] + L - tm;
+      fast[g] = (xs[g] + 512u <= L) & (sm[g] + 512u <= L) & (sp[g] + 512u <= L);
+      if (fast[g]) {
+        load_window(nm, sm[g], lane, va[g]);
+        load4(n0 + xs[g] + 8u * lane, vb[g]);
+        load_window(np, sp[g], lane, vc[g]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t x = xs[g] + 8u * lane + k;
+          uint32_t ea = 0, eb = 0, ec = 0;
+          if (x < L) {
+            uint32_t pm = x + tm;
+            pm -= (pm >= L) ? L : 0u;
+            const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+            ea = nm[pm]; eb = n0[x]; ec = np[pp];
+          }
+          set16(va[g], k, ea); set16(vb[g], k, eb); set16(vc[g], k, ec);
+        }
+      }
+    }
+
+    // ---- collide: LDS image first, the rest into the wave's queue ----
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      ChunkCtx cx;
+      cx.x8 = xs[g] + 8u * lane;
+      cx.w0 = philox10(make_uint4(cx.x8 >> 2, t, sv.rid, 0u), key);
+      cx.w1 = philox10(make_uint4((cx.x8 >> 2) + 1u, t, sv.rid, 0u), key);
+      cx.L = L;
+      cx.qn = qn;
+      decide_site<0>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<1>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<2>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<3>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<4>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<5>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<6>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<7>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      qn = cx.qn;
+    }
+
+    // ---- store ----
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (fast[g]) {
+        store_window(nm, sm[g], lane, va[g]);
+        store4(n0 + xs[g] + 8u * lane, vb[g]);
+        store_window(np, sp[g], lane, vc[g]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t x = xs[g] + 8u * lane + k;
+          if (x < L) {
+            uint32_t pm = x + tm;
+            pm -= (pm >= L) ? L : 0u;
+            const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+            nm[pm] = (uint16_t)get16(va[g], k);
+            n0[x] = (uint16_t)get16(vb[g], k);
+            np[pp] = (uint16_t)get16(vc[g], k);
+          }
+        }
+      }
+    }
+  }
+  if (qn) drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
   // The last block of the launch advances t of every slot in the launch.
-  // Every block has read t before it takes its ticket, so nothing reads the
-  // new value during this launch.
+  // Every block has consumed its loads of t before it takes its ticket (the
+  // values shaped its work), so nothing reads the new value during this
+  // launch; the next launch sees it through the kernel boundary.
   __shared__ uint32_t last;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1u;
-  }
+  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1u;
   __syncthreads();
   if (last) {
-    __threadfence();
-    for (uint32_t i = threadIdx.x; i < n_slots; i += blockDim.x) {
-      const uint32_t s = slot_list ? slot_list[i] : slot_first + i;
-      tslot[s] += 1u;
+    for (uint32_t i = threadIdx.x; i < a.n_slots; i += blockDim.x) {
+      const uint32_t s = a.slot_list ? a.slot_list[i] : a.slot_first + i;
+      a.tslot[s] += 1u;
     }
-    if (threadIdx.x == 0) atomicExch(ticket, 0u);
+    if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
   }
 }
 
@@ -300,17 +619,43 @@ __global__ void __launch_bounds__(256) k_moments(
 
 }  // namespace
 
-hipError_t launch_step(const Schedule &sch, hipStream_t s, uint16_t *state, const SlotDev *slots,
-                       uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
-                       const uint32_t *slot_list, uint32_t slot_first, uint32_t n_slots,
-                       uint32_t *ticket, uint32_t *err, TableDev tab, StepParams p) {
-  if (n_tiles == 0) return hipSuccess;
-  dim3 grid(n_tiles), block(sch.threads);
+template <int G>
+static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<G>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step<G>, (int)threads, lds);
+}
+
+uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
+  return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kQueueBytesPerWave;
+}
+
+hipError_t step_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,
+                          uint32_t &max_blocks) {
+  int b = 0;
+  hipError_t e;
+  const uint32_t lds = step_lds_bytes(sch, lds_bytes);
   switch (sch.groups) {
-    case 1: k_step<1><<<grid, block, 0, s>>>(state, slots, tslot, tiles, slot_list, slot_first, n_slots, ticket, err, tab, p); break;
-    case 2: k_step<2><<<grid, block, 0, s>>>(state, slots, tslot, tiles, slot_list, slot_first, n_slots, ticket, err, tab, p); break;
-    case 4: k_step<4><<<grid, block, 0, s>>>(state, slots, tslot, tiles, slot_list, slot_first, n_slots, ticket, err, tab, p); break;
-    case 8: k_step<8><<<grid, block, 0, s>>>(state, slots, tslot, tiles, slot_list, slot_first, n_slots, ticket, err, tab, p); break;
+    case 1: e = occupancy_of<1>(sch.threads, lds, b); break;
+    case 2: e = occupancy_of<2>(sch.threads, lds, b); break;
+    case 4: e = occupancy_of<4>(sch.threads, lds, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e) return e;
+  if (b < 1) return hipErrorInvalidConfiguration;
+  max_blocks = (uint32_t)b * n_cu;
+  return hipSuccess;
+}
+
+hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) {
+  if (a.n_tiles == 0) return hipSuccess;
+  dim3 grid(std::max<uint32_t>(1, std::min(a.n_tiles, a.max_blocks))), block(sch.threads);
+  const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
+  switch (sch.groups) {
+    case 1: k_step<1><<<grid, block, lds, s>>>(a); break;
+    case 2: k_step<2><<<grid, block, lds, s>>>(a); break;
+    case 4: k_step<4><<<grid, block, lds, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -26,11 +26,12 @@ namespace {
 
 constexpr uint32_t kPad = 128;
 constexpr uint32_t kPoisCap = 1024;
+constexpr uint32_t kImage = 96 * 1024;  // LDS collision image budget per job
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_rowbase,
-      o_rowdesc, o_thr, bytes, max_tiles;
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_ipool,
+      o_rowbase, o_rowdesc, o_thr, bytes, max_tiles;
 };
 
 SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
@@ -53,6 +54,8 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_mom = take(sizeof(MomDev) * n);
   l.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   l.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
+  l.o_idesc = take(sizeof(ImageDesc) * n);
+  l.o_ipool = take((uint64_t)kImage * n);
   l.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
   l.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
@@ -89,7 +92,9 @@ struct mclg_server {
   std::vector<uint32_t> h_list;
   std::vector<PoisDesc> h_pdesc;
   std::vector<uint32_t> h_pool;
+  std::vector<ImageDesc> h_idesc;
   uint32_t n_tiles = 0, n_active = 0;
+  uint32_t lds_bytes = 16, max_blocks = 1, image_budget = kImage, n_cu = 1;
   int last_hip = 0;
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
@@ -146,6 +151,27 @@ struct mclg_server {
   }
   static uint64_t job_bytes(uint64_t L) { return 3 * align_up(L, kPad) * sizeof(uint16_t); }
 
+  ImageDesc *d_idesc() { return reinterpret_cast<ImageDesc *>(ws + lay.o_idesc); }
+  StepLaunch launch_args() {
+    StepLaunch a;
+    a.state = arena;
+    a.slots = d_slots();
+    a.tslot = d_tslot();
+    a.tiles = d_tiles();
+    a.n_tiles = n_tiles;
+    a.slot_list = d_list();
+    a.slot_first = 0;
+    a.n_slots = n_active;
+    a.ticket = ticket();
+    a.err = err();
+    a.tab = table();
+    a.p = params();
+    a.images = d_idesc();
+    a.image_pool = ws + lay.o_ipool;
+    a.lds_bytes = lds_bytes;
+    a.max_blocks = max_blocks;
+    return a;
+  }
   StepParams params() const {
     StepParams p;
     p.seed = cfg.seed;
@@ -213,6 +239,23 @@ struct mclg_server {
         d.nthr = (uint32_t)cl.thr.size();
         std::copy(cl.thr.begin(), cl.thr.end(), h_pool.begin() + d.off);
       }
+      // collision image for this job's density and velocity
+      LdsImage im = image_budget >= 64 ? build_image(*tab, j.rho, j.u0, image_budget) : LdsImage();
+      auto blob = im.blob();
+      ImageDesc &idd = h_idesc[free_slot];
+      idd.off = (uint64_t)free_slot * kImage;
+      idd.bytes = im.dir.empty() ? 0u : (uint32_t)blob.size();
+      idd.dir_bytes = im.dir_bytes();
+      idd.dim_a = im.dim_a;
+      idd.dim_c = im.dim_c;
+      idd.b_lo = im.b_lo;
+      idd.nb = im.nb;
+      if (idd.bytes) {
+        hipError_t e = hipMemcpyAsync(ws + lay.o_ipool + idd.off, blob.data(), blob.size(),
+                                      hipMemcpyHostToDevice, s);
+        if (!e) e = hipStreamSynchronize(s);  // blob is a local buffer
+        if (e) return hip(e);
+      }
       fresh.push_back(free_slot);
       queue.pop_front();
     }
@@ -224,6 +267,7 @@ struct mclg_server {
       for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) init_tiles.push_back(TileDev{i, (uint32_t)x0});
     if (init_tiles.size() > lay.max_tiles) return MCLG_E_INVAL;
     hipError_t e = up(d_slots(), h_slots.data(), sizeof(SlotDev) * h_slots.size());
+    if (!e) e = up(d_idesc(), h_idesc.data(), sizeof(ImageDesc) * h_idesc.size());
     if (!e) e = up(ws + lay.o_pdesc, h_pdesc.data(), sizeof(PoisDesc) * h_pdesc.size());
     if (!e) e = up(ws + lay.o_pool, h_pool.data(), sizeof(uint32_t) * h_pool.size());
     // fresh slot ids and their tiles go through the list/tile areas, which
@@ -320,6 +364,19 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
   sv->h_slots.assign(cfg->max_slots, SlotDev{});
   sv->h_pdesc.assign(3ull * cfg->max_slots, PoisDesc{});
   sv->h_pool.assign((size_t)kPoisCap * 3 * cfg->max_slots, 0);
+  sv->h_idesc.assign(cfg->max_slots, ImageDesc{});
+  {
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const uint32_t queues = (sv->sch.threads / 64u) * kQueueBytesPerWave;
+    if (!e) sv->image_budget = std::min<uint32_t>(kImage, (uint32_t)std::max(0, v - 1024 - (int)queues)) / 16u * 16u;
+    if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    if (!e) sv->n_cu = (uint32_t)std::max(1, v);
+    sv->lds_bytes = std::max<uint32_t>(16, sv->image_budget);
+    if (!e) e = step_occupancy(sv->sch, sv->lds_bytes, sv->n_cu, sv->max_blocks);
+    if (e) return sv->hip(e);
+  }
   uint64_t usable = cfg->arena_bytes / 256 * 256;
   if (usable) sv->free_spans[0] = usable;
   std::vector<uint32_t> ctrl(64, 0), tz(cfg->max_slots, 0);
@@ -366,9 +423,7 @@ int mclg_server_tick(mclg_server *sv, uint32_t k) {
     for (auto &r : sv->slot)
       if (r.active) chunk = std::min<uint64_t>(chunk, r.job.steps - r.t);
     for (uint64_t i = 0; i < chunk; ++i) {
-      hipError_t e = launch_step(sv->sch, sv->s, sv->arena, sv->d_slots(), sv->d_tslot(),
-                                 sv->d_tiles(), sv->n_tiles, sv->d_list(), 0, sv->n_active,
-                                 sv->ticket(), sv->err(), sv->table(), sv->params());
+      hipError_t e = launch_step(sv->sch, sv->s, sv->launch_args());
       if (e) return sv->hip(e);
     }
     for (auto &r : sv->slot)

@@ -43,6 +43,33 @@ void feq(double rho, double u, double out[3]);
 // Poisson(mu) thresholds of the initial-state rule (full list, uint64).
 bool poisson_full(double mu, uint32_t &k_lo, std::vector<uint64_t> &thr);
 
+// LDS image of the hottest collision rows of one workload (a performance
+// cache: every site it cannot decide goes to the exact global tables, so the
+// results never depend on it).
+//
+// A row is addressed by (a', b, c') = (min(n_-1, n_+1), n_0, max(n_-1, n_+1)),
+// which fixes N, |J| and n0.  `dir[a' * dim_c + c']` is the index p of an
+// (a', c') pair or 0xFFFF; the record of (p, b) is records[p * nb + b - b_lo],
+// eight uint16: k_s, then the top 16 bits of the full-fiber thresholds
+// thr_{k_s - 1} .. thr_{k_s + 5} (thr_{-1} = 0, thr_{>= m - 1} = 2^32, clamped
+// to 0xFFFF).  With rh = r >> 16 the draw is decided in LDS when
+// T1 < rh < T7 and no inner T equals rh; then the outcome index is
+// k_s + #{inner T < rh}.  Otherwise (or when the row is absent) the exact
+// global row decides.
+struct LdsImage {
+  uint32_t dim_a = 0, dim_c = 0, b_lo = 0, nb = 0;
+  std::vector<uint16_t> dir;      // dim_a * dim_c
+  std::vector<uint16_t> records;  // 8 per record
+  double coverage = 0.0;          // expected fraction of site updates decided in LDS
+  // serialised: dir padded to 16 bytes, then the records
+  std::vector<uint8_t> blob() const;
+  uint32_t dir_bytes() const { return (uint32_t)((dim_a * dim_c * 2 + 15) / 16 * 16); }
+};
+
+// Build the image for a lattice near the product-Poisson law at
+// f^eq(rho, u) within `budget` bytes.
+LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t budget);
+
 // Compacted form used on the device: n = k_first + #{thr[i] <= r}.
 struct CompactLaw {
   uint32_t k_first = 0;

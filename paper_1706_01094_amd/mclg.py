@@ -83,7 +83,8 @@ _SIGS = {
     "mclg_moments": [vp, vp, u32, P(mclg_moments_t)],
     "mclg_get_counts": [vp, u32, P(ct.c_uint16)],
     "mclg_check": [vp],
-    "mclg_set_schedule": [vp, u32, u32],
+    "mclg_set_schedule": [vp, u32, u32, u32],
+    "mclg_lds_coverage": [vp, P(dbl), P(u32)],
     "mclg_destroy": [vp],
     "mclg_strerror": [ct.c_int],
     "mclg_last_hip_error": [vp],
@@ -184,8 +185,14 @@ def mclg_step_graph(ctx: int, n: int):
     _check(lib().mclg_step_graph(ctx, n), "mclg_step_graph")
 
 
-def mclg_set_schedule(ctx: int, groups: int, threads: int):
-    _check(lib().mclg_set_schedule(ctx, groups, threads), "mclg_set_schedule")
+def mclg_set_schedule(ctx: int, groups: int, threads: int, lds_budget: int = 96 * 1024):
+    _check(lib().mclg_set_schedule(ctx, groups, threads, lds_budget), "mclg_set_schedule")
+
+
+def mclg_lds_coverage(ctx: int):
+    f, b = dbl(0), u32(0)
+    _check(lib().mclg_lds_coverage(ctx, ct.byref(f), ct.byref(b)), "mclg_lds_coverage")
+    return f.value, b.value
 
 
 def mclg_check(ctx: int) -> int:
@@ -276,8 +283,11 @@ class Lattice:
     def step_graph(self, n: int):
         mclg_step_graph(self.ctx, n)
 
-    def set_schedule(self, groups: int, threads: int):
-        mclg_set_schedule(self.ctx, groups, threads)
+    def set_schedule(self, groups: int, threads: int, lds_budget: int = 96 * 1024):
+        mclg_set_schedule(self.ctx, groups, threads, lds_budget)
+
+    def lds_coverage(self):
+        return mclg_lds_coverage(self.ctx)
 
     def check(self) -> int:
         return mclg_check(self.ctx)

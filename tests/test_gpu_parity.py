@@ -67,13 +67,16 @@ def test_plain_small_every_step():
         assert m[k] == mo[k], k
 
 
-@pytest.mark.parametrize("groups,threads", [(1, 64), (2, 256), (4, 128), (8, 1024), (2, 512)])
-def test_ragged_tiles_and_schedules(groups, threads):
-    """Several tiles plus a ragged tail, at u != 0; every schedule gives the
-    oracle's bits."""
+@pytest.mark.parametrize("groups,threads,lds", [(1, 64, 96 << 10), (2, 256, 0), (4, 128, 4096),
+                                                (4, 1024, 112 << 10), (2, 512, 32 << 10),
+                                                (1, 1024, 96 << 10), (2, 64, 128 << 10)])
+def test_ragged_tiles_and_schedules(groups, threads, lds):
+    """Several tiles plus a ragged tail, at u != 0; every schedule and LDS
+    image size (0 = every draw from the global rows) gives the oracle's bits."""
     L = 3 * 2048 + 37
     g, o = pair(L, 7, rho=30.0, u0=0.15)
-    g.set_schedule(groups, threads)
+    g.set_schedule(groups, threads, lds)
+    say("lds coverage", g.lds_coverage())
     for _ in range(12):
         g.step(5)
         o.step(5)

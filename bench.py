@@ -103,6 +103,160 @@ def run_plain(args, torch, M):
     return L, gpu_ms, wall
 
 
+def _events(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return e0, e1
+
+
+def run_batched(args, torch, M):
+    """1024 independent replicas of uneven L and density: plain per-replica
+    launches vs one batched launch per step vs captured HIP graphs."""
+    import synth
+    from paper_1706_01094_amd import autotune
+    man = synth.replica_manifest()
+    sites = int(man["L"].sum())
+    lat = M.Lattice(man["L"], synth.BATCHED["seed"], rho=man["rho"], u0=man["u0"],
+                    replica_id=man["replica_id"])
+    tuned = autotune.tune(man["L"], man["rho"], man["u0"], replica_id=man["replica_id"],
+                          steps=10, use_cache=False)
+    lat.set_schedule(*tuned["schedule"])
+    out = {"workload": "d1q3_1024_replicas", "replicas": len(man["L"]), "sites": sites,
+           "schedule": list(tuned["schedule"]),
+           "autotune_trials": [[*t["schedule"], round(t.get("seconds_per_step", -1) * 1e6, 1)]
+                               for t in tuned["trials"]]}
+    lat.step(args.batched_warmup)
+    torch.cuda.synchronize()
+    for mode in ("batched", "graph"):
+        e0, e1 = _events(torch, lat.stream)
+        e0.record(lat.stream)
+        if mode == "batched":
+            lat.step(args.batched_steps)
+        else:
+            chunk = 100
+            for _ in range(args.batched_steps // chunk):
+                lat.step_graph(chunk)
+            lat.step(args.batched_steps % chunk)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[mode] = {"steps": args.batched_steps, "ms": ms,
+                     "site_updates_per_s": sites * args.batched_steps / (ms / 1e3)}
+    # plain: one launch per replica per step
+    n = len(man["L"])
+    e0, e1 = _events(torch, lat.stream)
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    for _ in range(args.plain_steps):
+        for r in range(n):
+            lat.step_replica(r, 1)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    out["plain_per_replica"] = {"steps": args.plain_steps, "launches": args.plain_steps * n,
+                                "ms": ms, "wall_s": wall,
+                                "site_updates_per_s": sites * args.plain_steps / (ms / 1e3)}
+    out["batched_vs_plain"] = out["batched"]["site_updates_per_s"] / \
+        out["plain_per_replica"]["site_updates_per_s"]
+    out["graph_vs_plain"] = out["graph"]["site_updates_per_s"] / \
+        out["plain_per_replica"]["site_updates_per_s"]
+    if lat.check() != 0:
+        raise SystemExit("device error in the batched run")
+    m = lat.moments()
+    out["t"] = int(m[0]["t"])
+    lat.close()
+    return out
+
+
+def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, time_limit):
+    """Real-time driver: jobs are submitted when their arrival time has
+    passed; the server advances all resident jobs k steps per tick."""
+    srv = M.Server(arena_bytes, max_slots, seed)
+    t0 = time.perf_counter()
+    nxt = 0
+    done = {}
+    work = 0
+    while len(done) < len(jobs):
+        now = time.perf_counter() - t0
+        if now > time_limit:
+            break
+        while nxt < len(jobs) and jobs[nxt]["arrival"] <= now:
+            j = jobs[nxt]
+            srv.submit(j["job_id"], j["L"], j["steps"], j["rho"], j["u0"])
+            nxt += 1
+        q, r, _ = srv.stats()
+        if q == 0 and r == 0:
+            if nxt < len(jobs):
+                time.sleep(max(0.0, min(0.01, jobs[nxt]["arrival"] - now)))
+            continue
+        srv.tick(k)
+        tnow = time.perf_counter() - t0
+        for jid, m in srv.poll():
+            done[jid] = tnow
+    q, r, used = srv.stats()
+    srv.close()
+    lat = sorted(done[j["job_id"]] - j["arrival"] for j in jobs if j["job_id"] in done)
+    work = sum(j["L"] * j["steps"] for j in jobs if j["job_id"] in done)
+    span = max(done.values()) - jobs[0]["arrival"] if done else 0.0
+    pct = (lambda f: lat[min(len(lat) - 1, int(f * len(lat)))] if lat else None)
+    return {"jobs": len(jobs), "completed": len(done), "queued_at_end": q, "resident_at_end": r,
+            "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99),
+            "site_updates_per_s": work / span if span > 0 else 0.0,
+            "span_s": span, "site_updates": work}
+
+
+def run_served(args, torch, M, capacity):
+    """Poisson arrivals (200 jobs/s) of jobs with L log-uniform in
+    [2^12, 2^24], steps U{100..5000}, rho U{5..100}; 200 GB arena."""
+    import synth
+    cfg = synth.SERVED
+    out = {"workload": "d1q3_served_200_per_s", "arena_bytes": cfg["budget"]}
+    jobs = synth.job_trace(args.serve_window)
+    offered = sum(j["L"] * j["steps"] for j in jobs) / args.serve_window
+    out["trace"] = {"window_s": args.serve_window, "jobs": len(jobs),
+                    "offered_site_updates_per_s": offered}
+    out["overloaded"] = _serve(M, torch, jobs, cfg["budget"], 8192, cfg["seed"], 50,
+                               args.serve_limit)
+    # sustainable rate: 0.8 x measured batched capacity
+    mean_work = offered / cfg["rate"]
+    rate = 0.8 * capacity / mean_work
+    jobs2 = synth.job_trace(args.serve_window * 2, rate=rate, seed=cfg["seed"] + 1)
+    out["sustainable"] = {"rate_jobs_per_s": rate, "jobs": len(jobs2),
+                          **_serve(M, torch, jobs2, cfg["budget"], 8192, cfg["seed"], 50,
+                                   args.serve_limit)}
+    return out
+
+
+def run_wave(args, torch, M):
+    """Decaying density wave, L = 2^22, 5000 steps, int64 Fourier projection
+    (Eq. (A)) every 10 steps."""
+    import numpy as np
+    import synth
+    w = synth.DENSITY_WAVE
+    L = w["L"]
+    counts = synth.density_wave_counts()
+    tw = synth.twiddles(L, 1)
+    lat = M.Lattice(L, w["seed"], counts=counts)
+    twd = torch.as_tensor(tw).to(lat.device)
+    den = float(np.sum(tw[1].astype(np.float64) ** 2))
+    amp = []
+    e0, e1 = _events(torch, lat.stream)
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    for _ in range(w["steps"] // w["log_every"]):
+        lat.step(w["log_every"])
+        m = lat.moments(twd, 1)[0]
+        amp.append(m["fourier"][0][1] / den)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.close()
+    return {"workload": "d1q3_L4M_wave_rho40", "steps": w["steps"], "logs": len(amp),
+            "wall_s": wall, "site_updates_per_s_incl_logging": L * w["steps"] / wall,
+            "amplitude_first": amp[0], "amplitude_last": amp[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,7 +265,25 @@ def main():
     ap.add_argument("--schedule", default="", help="groups,threads,lds_bytes")
     ap.add_argument("--graph", action="store_true", help="launch steps from captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the plain headline (skip batched, served, density wave)")
+    ap.add_argument("--batched-steps", type=int, default=2000)
+    ap.add_argument("--batched-warmup", type=int, default=20)
+    ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--serve-window", type=float, default=2.0)
+    ap.add_argument("--serve-limit", type=float, default=60.0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run 8 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 8}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the lattice and replica work of this build "
               "runs on a single MI355X (sharding across GPUs is described in DESIGN.md).",
@@ -146,6 +318,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
+    if not args.no_extra:
+        extra = {}
+        extra["batched"] = run_batched(args, torch, M)
+        extra["density_wave"] = run_wave(args, torch, M)
+        torch.cuda.empty_cache()
+        extra["served"] = run_served(args, torch, M, extra["batched"]["batched"]["site_updates_per_s"])
+        out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -284,30 +284,43 @@ struct SlotView {
 };
 
 // Site K of the lane: decide from the LDS image, or queue it (all lanes
-// place their queued sites by ballot order).
+// place their queued sites by ballot order).  Branch-free apart from the
+// queue: indices are clamped into the image and the outcome is selected.
+// With b' drawn, n_-1 and n_+1 follow from the conserved N and J
+// (Eq. (collcons)): a' = a + (b - b')/2, c' = c + (b - b')/2.
 template <int K>
-__device__ __forceinline__ void decide_site(ChunkCtx &cx, uint32_t (&va)[4], uint32_t (&vb)[4],
-                                            uint32_t (&vc)[4], const LdsView &lv, uint4 *queue,
+__device__ __forceinline__ void decide_site(ChunkCtx &cx, bool full, uint32_t (&va)[4],
+                                            uint32_t (&vb)[4], uint32_t (&vc)[4],
+                                            const LdsView &lv, uint4 *queue,
                                             const StepParams &p, const TableDev &tab, uint32_t t,
                                             uint32_t rid, uint32_t *err) {
   const uint4 &w = K < 4 ? cx.w0 : cx.w1;
   const uint32_t r = (K & 3) == 0 ? w.x : (K & 3) == 1 ? w.y : (K & 3) == 2 ? w.z : w.w;
   const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
   const uint32_t N = ea + eb + ec;
-  bool miss = false;
-  if (cx.x8 + K < cx.L) {
-    if (N > 65535u) {
-      atomicOr(err, kErrOverflow);
-    } else if (N >= 2u && p.C != 0) {
-      uint32_t idx;
-      if (N <= p.n_max && lds_outcome(lv, ea, eb, ec, r, idx)) {
-        const uint32_t absJ = (uint32_t)abs((int32_t)ec - (int32_t)ea);
-        apply_outcome(va, vb, vc, K, ((N - absJ) & 1u) + 2u * idx);
-      } else {
-        miss = true;
-      }
-    }
-  }
+  const bool live = full | (cx.x8 + K < cx.L);
+  if (live & (N > 65535u)) atomicOr(err, kErrOverflow);
+  const bool collide = live & (N >= 2u) & (N <= 65535u) & (p.C != 0);
+  // LDS image lookup with clamped indices
+  const uint32_t lo = min(ea, ec), hi = max(ea, ec), bi = eb - lv.b_lo;
+  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb) & (N <= p.n_max);
+  const uint32_t pidx = lv.dir[inbox ? __umul24(lo, lv.dim_c) + hi : 0u];
+  const bool have = inbox & (pidx != 0xFFFFu);
+  const uint4 q = lv.rec[have ? __umul24(pidx, lv.nb) + bi : 0u];
+  const uint32_t rh = r >> 16;
+  const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
+                 t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
+  const bool hit = have & (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) &
+                   (rh != t5) & (rh != t6);
+  const uint32_t idx = (q.x & 0xffffu) + (uint32_t)(t2 < rh) + (uint32_t)(t3 < rh) +
+                       (uint32_t)(t4 < rh) + (uint32_t)(t5 < rh) + (uint32_t)(t6 < rh);
+  const uint32_t par = eb & 1u;  // N - |J| = b + 2 min(a, c): the fiber's parity is b's
+  const uint32_t bn = par + 2u * idx;
+  const int32_t d = (collide & hit) ? ((int32_t)eb - (int32_t)bn) >> 1 : 0;
+  set16(va, K, (uint32_t)((int32_t)ea + d));
+  set16(vb, K, (uint32_t)((int32_t)eb - 2 * d));
+  set16(vc, K, (uint32_t)((int32_t)ec + d));
+  const bool miss = collide & !hit;
   const uint64_t bal = __ballot(miss);
   if (bal) {
     const uint32_t cnt = (uint32_t)__popcll(bal);
@@ -449,14 +462,14 @@ __global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
       cx.w1 = philox10(make_uint4((cx.x8 >> 2) + 1u, t, sv.rid, 0u), key);
       cx.L = L;
       cx.qn = qn;
-      decide_site<0>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<1>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<2>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<3>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<4>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<5>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<6>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<7>(cx, va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<0>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<1>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<2>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<3>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<4>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<5>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<6>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
+      decide_site<7>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
       qn = cx.qn;
     }
 

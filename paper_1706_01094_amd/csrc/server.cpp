@@ -266,10 +266,14 @@ struct mclg_server {
     for (uint32_t i : fresh)
       for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) init_tiles.push_back(TileDev{i, (uint32_t)x0});
     if (init_tiles.size() > lay.max_tiles) return MCLG_E_INVAL;
-    hipError_t e = up(d_slots(), h_slots.data(), sizeof(SlotDev) * h_slots.size());
-    if (!e) e = up(d_idesc(), h_idesc.data(), sizeof(ImageDesc) * h_idesc.size());
-    if (!e) e = up(ws + lay.o_pdesc, h_pdesc.data(), sizeof(PoisDesc) * h_pdesc.size());
-    if (!e) e = up(ws + lay.o_pool, h_pool.data(), sizeof(uint32_t) * h_pool.size());
+    hipError_t e = hipSuccess;
+    for (uint32_t i : fresh) {  // only the admitted slots' entries change
+      if (!e) e = up(d_slots() + i, &h_slots[i], sizeof(SlotDev));
+      if (!e) e = up(d_idesc() + i, &h_idesc[i], sizeof(ImageDesc));
+      if (!e) e = up(ws + lay.o_pdesc + sizeof(PoisDesc) * 3 * i, &h_pdesc[3 * i], sizeof(PoisDesc) * 3);
+      if (!e) e = up(ws + lay.o_pool + sizeof(uint32_t) * kPoisCap * 3 * i,
+                     &h_pool[(size_t)kPoisCap * 3 * i], sizeof(uint32_t) * kPoisCap * 3);
+    }
     // fresh slot ids and their tiles go through the list/tile areas, which
     // are rebuilt right after
     if (!e) e = up(d_list(), fresh.data(), sizeof(uint32_t) * fresh.size());

@@ -54,7 +54,8 @@ enum {
   MCLG_E_HIP = -3,         /* HIP runtime error; see mclg_last_hip_error */
   MCLG_E_NOMEM = -4,       /* host allocation failed */
   MCLG_E_UNSUPPORTED = -5, /* lattice or mode not implemented (D2Q9) */
-  MCLG_E_FULL = -6         /* server: no slot or arena space for the job */
+  MCLG_E_FULL = -6,        /* server: no slot or arena space for the job */
+  MCLG_E_INTERNAL = -7     /* a device-side consistency check failed (a library bug) */
 };
 
 enum { MCLG_D1Q3 = 1, MCLG_D2Q9 = 2 };
@@ -150,8 +151,8 @@ int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
  * synchronises. */
 int mclg_check(mclg_ctx *ctx);
 
-/* Select the launch schedule: chunks of eight sites per lane per tile (1, 2
- * or 4), threads per block (64..1024, multiple of 64) and the
+/* Select the launch schedule: chunks of eight sites per lane per tile (must
+ * be 1), threads per block (64..1024, multiple of 64) and the
  * bytes of LDS each block devotes to its replica's collision image (0..131072;
  * the image caches the most visited table rows, misses read the exact rows in
  * global memory).  Any choice gives identical bits; synchronises the stream. */

@@ -19,7 +19,7 @@ using namespace mclg;
 namespace {
 
 constexpr uint32_t kPadElems = 128;     // array stride granularity (256 B)
-constexpr uint32_t kMinTileSites = 256; // smallest schedule tile
+constexpr uint32_t kMinTileSites = 512; // chunk of the step kernel
 constexpr uint32_t kPoisCap = 1024;     // thresholds per initial Poisson law
 constexpr uint32_t kMaxImage = 128 * 1024; // largest LDS collision image
 
@@ -30,7 +30,7 @@ struct Layout {
   std::vector<uint64_t> off, stride, dense;
   uint64_t total_sites = 0, max_tiles = 0;
   // workspace byte offsets
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_ipool,
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, ws_bytes;
 };
 
@@ -65,6 +65,7 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
   lay.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   lay.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
   lay.o_idesc = take(sizeof(ImageDesc) * n);
+  lay.o_over = take(kOverflowBytes);
   lay.o_ipool = take((uint64_t)kMaxImage * n);
   lay.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   lay.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
@@ -150,7 +151,8 @@ struct mclg_ctx {
     const uint32_t ts = sch.tile_sites();
     for (uint32_t r = 0; r < n; ++r) {
       tile_begin[r] = (uint32_t)tiles.size();
-      for (uint64_t x0 = 0; x0 < L[r]; x0 += ts) tiles.push_back(TileDev{r, (uint32_t)x0});
+      const uint32_t next = tile_begin[r] + (uint32_t)((L[r] + ts - 1) / ts);
+      for (uint64_t x0 = 0; x0 < L[r]; x0 += ts) tiles.push_back(TileDev{r, (uint32_t)x0, next, 0});
       tile_end[r] = (uint32_t)tiles.size();
     }
   }
@@ -172,6 +174,7 @@ struct mclg_ctx {
     a.p = params();
     a.images = img_desc_dev();
     a.image_pool = ws + lay.o_ipool;
+    a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);
     a.lds_bytes = lds_bytes;
     a.max_blocks = max_blocks;
     return a;
@@ -367,6 +370,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
   if (!e) c->n_cu = (uint32_t)std::max(1, v);
   if (e) return c->hip(e);
+  if (c->n_cu > 256) return MCLG_E_UNSUPPORTED;  // overflow region sized for 256 CUs
   // what density and velocity each replica's image should target
   c->est_rho.assign(c->n, 0.0);
   c->est_u.assign(c->n, 0.0);
@@ -387,7 +391,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   e = hipMemcpy(&err, c->err(), sizeof(err), hipMemcpyDeviceToHost);
   if (e) return c->hip(e);
   *out = c.release();
-  return err ? MCLG_E_RANGE : MCLG_OK;
+  return (err & 4u) ? MCLG_E_INTERNAL : err ? MCLG_E_RANGE : MCLG_OK;
 }
 
 static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
@@ -446,7 +450,7 @@ static int read_err(mclg_ctx *c) {
   hipError_t e = hipMemcpyAsync(&err, c->err(), sizeof(err), hipMemcpyDeviceToHost, c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
   if (e) return c->hip(e);
-  return err ? MCLG_E_RANGE : MCLG_OK;
+  return (err & 4u) ? MCLG_E_INTERNAL : err ? MCLG_E_RANGE : MCLG_OK;
 }
 
 int mclg_check(mclg_ctx *c) {
@@ -510,7 +514,7 @@ int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
 
 int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t lds_budget) {
   if (!c) return MCLG_E_INVAL;
-  if (!(groups == 1 || groups == 2 || groups == 4)) return MCLG_E_INVAL;
+  if (groups != 1) return MCLG_E_INVAL;
   if (threads < 64 || threads > 1024 || threads % 64) return MCLG_E_INVAL;
   if (lds_budget > kMaxImage) return MCLG_E_INVAL;
   c->sch.groups = groups;
@@ -549,6 +553,7 @@ const char *mclg_strerror(int code) {
     case MCLG_E_NOMEM: return "host out of memory";
     case MCLG_E_UNSUPPORTED: return "unsupported lattice or mode";
     case MCLG_E_FULL: return "server full";
+    case MCLG_E_INTERNAL: return "internal consistency check failed";
     default: return "unknown error";
   }
 }

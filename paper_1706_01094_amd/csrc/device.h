@@ -21,9 +21,12 @@ struct SlotDev {
   uint32_t pad;
 };
 
+// A chunk of 512 sites of one slot (the last chunk of a slot may be short).
 struct TileDev {
   uint32_t slot;     // slot index
-  uint32_t x0;       // first site (multiple of 4)
+  uint32_t x0;       // first site (multiple of 512)
+  uint32_t next;     // index of the first chunk after this slot's run of chunks
+  uint32_t pad;
 };
 
 struct StepParams {
@@ -65,10 +68,10 @@ struct PoisDesc {
 
 // Launch configuration of the fused stream+collide kernel.
 struct Schedule {
-  uint32_t groups = 1;       // chunks of 8 sites per lane per tile
+  uint32_t groups = 1;       // chunks of 8 sites per lane (must be 1)
   uint32_t threads = 1024;   // threads per block
   uint32_t lds_budget = 112 * 1024;  // bytes of collision image per block
-  uint32_t tile_sites() const { return groups * threads * 8; }
+  uint32_t tile_sites() const { return 512; }  // one chunk: 64 lanes x 8 sites
 };
 
 struct StepLaunch {
@@ -84,6 +87,7 @@ struct StepLaunch {
   StepParams p;
   const ImageDesc *images;    // per slot
   const uint8_t *image_pool;
+  uint4 *overflow;            // kOverflowPerWave entries per resident wave
   uint32_t lds_bytes;         // LDS per block for the image (largest image, 16-byte multiple);
                               // the per-wave miss queues follow it
   uint32_t max_blocks;        // persistent grid size
@@ -93,6 +97,12 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 
 // Bytes of LDS per wave for its queue of undecided draws.
 constexpr uint32_t kQueueBytesPerWave = 128 * 16;
+// Entries of the global overflow area per wave (one chunk's worth of sites),
+// and the number of waves the overflow region is sized for (all waves that
+// can be resident on a 256-CU device).
+constexpr uint32_t kOverflowPerWave = 512;
+constexpr uint32_t kOverflowWaves = 256 * 32;
+constexpr uint64_t kOverflowBytes = (uint64_t)kOverflowPerWave * kOverflowWaves * 16;
 
 // Persistent grid size: resident blocks per CU for this LDS footprint x CUs.
 hipError_t step_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,

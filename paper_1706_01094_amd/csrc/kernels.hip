@@ -18,6 +18,7 @@ namespace {
 
 constexpr uint32_t kErrOverflow = 1u;   // a site with N > 65535
 constexpr uint32_t kErrEqRange = 2u;    // C = infinity and N > n_max
+constexpr uint32_t kErrInternal = 4u;   // queue capacity exceeded (a bug)
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53,
 // 0xCD9E8D57, Weyl increments 0x9E3779B9, 0xBB67AE85.
@@ -111,32 +112,14 @@ __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t
 }
 
 // The slot's collision image in LDS: directory of (min(a,c), max(a,c)) pairs,
-// then 16-byte records (k_s, top 16 bits of 7 thresholds).  Decides the
-// outcome exactly whenever the top 16 bits of r fall strictly inside the
-// record's window and differ from every stored value; returns false
-// otherwise.
+// then 16-byte records (k_s, top 16 bits of 7 thresholds).  A record decides
+// the outcome exactly whenever the top 16 bits of r fall strictly inside its
+// window and differ from every stored value.
 struct LdsView {
   const uint16_t *dir;
   const uint4 *rec;
   uint32_t dim_a, dim_c, b_lo, nb;
 };
-
-__device__ __forceinline__ bool lds_outcome(const LdsView &v, uint32_t a, uint32_t b, uint32_t c,
-                                            uint32_t r, uint32_t &idx) {
-  const uint32_t lo = min(a, c), hi = max(a, c), bi = b - v.b_lo;
-  if (lo >= v.dim_a || hi >= v.dim_c || bi >= v.nb) return false;
-  const uint32_t pidx = v.dir[lo * v.dim_c + hi];
-  if (pidx == 0xFFFFu) return false;
-  const uint4 q = v.rec[pidx * v.nb + bi];
-  const uint32_t rh = r >> 16;
-  const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
-                 t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
-  const bool inside = (rh > t1) & (rh < t7);
-  const bool tie = (rh == t2) | (rh == t3) | (rh == t4) | (rh == t5) | (rh == t6);
-  idx = (q.x & 0xffffu) + (uint32_t)(t2 < rh) + (uint32_t)(t3 < rh) + (uint32_t)(t4 < rh) +
-        (uint32_t)(t5 < rh) + (uint32_t)(t6 < rh);
-  return inside & !tie;
-}
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers
@@ -188,70 +171,14 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Eight consecutive elements [s, s + 8) of an array whose window of 512
-// elements starting at s does not wrap: lane-aligned 16-byte loads, the next
-// lane's vector by a shuffle (the last lane reads the vector after the
-// window), and a byte-align by the wave-uniform misalignment s & 7.
-__device__ __forceinline__ void load_window(const uint16_t *arr, uint32_t s, uint32_t lane,
-                                            uint32_t (&out)[4]) {
-  const uint32_t bmis = s & 7u, A = s - bmis;
-  uint32_t v[4], nx[4];
-  load4(arr + A + 8u * lane, v);
-  if (bmis == 0u) {
-    for (int j = 0; j < 4; ++j) out[j] = v[j];
-    return;
-  }
-  uint32_t ext[4];
-  load4(arr + A + 512u, ext);
-  shfl_down4(v, nx);
-  if (lane == 63u)
-    for (int j = 0; j < 4; ++j) nx[j] = ext[j];
-  extract8(v, nx, bmis, out);
-}
-// Inverse of load_window: lanes 1..63 store their aligned vector; lane 0
-// and lane 63 store only the elements of the two boundary vectors this
-// window owns (the rest belongs to the neighbouring windows).
-__device__ __forceinline__ void store_window(uint16_t *arr, uint32_t s, uint32_t lane,
-                                             const uint32_t (&o)[4]) {
-  const uint32_t bmis = s & 7u, A = s - bmis;
-  if (bmis == 0u) {
-    store4(arr + A + 8u * lane, o);
-    return;
-  }
-  uint32_t prev[4], al[4];
-  shfl_up4(o, prev);
-  extract8(prev, o, 8u - bmis, al);
-  if (lane != 0u) {
-    store4(arr + A + 8u * lane, al);
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < 8u - bmis) arr[s + e] = (uint16_t)get16(o, e);
-  }
-  if (lane == 63u) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < bmis) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)bmis + e);
-  }
-}
-
-// Element k of a site triple gets rest count bn; n_-1 and n_+1 follow from
-// the conserved N and J (Eq. (collcons)).
-__device__ __forceinline__ void apply_outcome(uint32_t (&va)[4], uint32_t (&vb)[4],
-                                              uint32_t (&vc)[4], int k, uint32_t bn) {
-  const int32_t ea = (int32_t)get16(va, k), eb = (int32_t)get16(vb, k),
-                ec = (int32_t)get16(vc, k);
-  const int32_t N = ea + eb + ec, J = ec - ea;
-  set16(va, k, (uint32_t)((N - (int32_t)bn - J) >> 1));
-  set16(vb, k, bn);
-  set16(vc, k, (uint32_t)((N - (int32_t)bn + J) >> 1));
-}
-
 // Per-wave queue of draws the LDS image could not decide (or sites with
 // N > n_max); drained by all lanes at once.
 constexpr uint32_t kQueue = kQueueBytesPerWave / 16;
+constexpr uint32_t kOverflow = kOverflowPerWave;
 
-// Exact outcome for a queued site: global row, or the literal loop.
+// Exact outcome for a queued site: global row, or the literal loop.  It is
+// only reached from the drain, outside the unrolled per-site code, so the
+// hot loop stays small enough for the instruction cache.
 __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepParams &p,
                                                 const TableDev &tab, uint32_t t, uint32_t rid,
                                                 uint32_t *err) {
@@ -274,7 +201,9 @@ struct ChunkCtx {
   uint32_t x8;     // first of the lane's eight sites
   uint4 w0, w1;    // Philox words of sites x8 .. x8 + 7
   uint32_t L;
-  uint32_t qn;     // the wave's queue fill (wave-uniform)
+  uint32_t qn;     // the wave's LDS queue fill (wave-uniform)
+  uint32_t on;     // the wave's overflow fill in global memory (wave-uniform)
+  uint4 *over;     // the wave's overflow area (kOverflow entries)
 };
 
 // Where a slot's three arrays are and how they are shifted at step t.
@@ -283,57 +212,99 @@ struct SlotView {
   uint32_t L, tm, t, rid;
 };
 
-// Site K of the lane: decide from the LDS image, or queue it (all lanes
-// place their queued sites by ballot order).  Branch-free apart from the
-// queue: indices are clamped into the image and the outcome is selected.
-// With b' drawn, n_-1 and n_+1 follow from the conserved N and J
-// (Eq. (collcons)): a' = a + (b - b')/2, c' = c + (b - b')/2.
+// Site K of the lane, in three phases so that the LDS reads of several
+// sites are in flight together: (1) the directory read, (2) the record
+// read, (3) the decision.  Branch-free apart from the queue: indices are
+// clamped into the image and the outcome is selected.  With b' drawn,
+// n_-1 and n_+1 follow from the conserved N and J (Eq. (collcons)):
+// a' = a + (b - b')/2, c' = c + (b - b')/2.
+struct SiteLook {
+  uint32_t ea, eb, ec, N, bi, pidx;
+  bool inbox, live;
+  uint4 q;
+};
+
 template <int K>
-__device__ __forceinline__ void decide_site(ChunkCtx &cx, bool full, uint32_t (&va)[4],
-                                            uint32_t (&vb)[4], uint32_t (&vc)[4],
-                                            const LdsView &lv, uint4 *queue,
-                                            const StepParams &p, const TableDev &tab, uint32_t t,
-                                            uint32_t rid, uint32_t *err) {
+__device__ __forceinline__ void site_dir(SiteLook &s, const ChunkCtx &cx, bool full,
+                                         const uint32_t (&va)[4], const uint32_t (&vb)[4],
+                                         const uint32_t (&vc)[4], const LdsView &lv,
+                                         const StepParams &p) {
+  s.ea = get16(va, K);
+  s.eb = get16(vb, K);
+  s.ec = get16(vc, K);
+  s.N = s.ea + s.eb + s.ec;
+  s.live = full | (cx.x8 + K < cx.L);
+  const uint32_t lo = min(s.ea, s.ec), hi = max(s.ea, s.ec);
+  s.bi = s.eb - lv.b_lo;
+  s.inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (s.bi < lv.nb) & (s.N <= p.n_max);
+  s.pidx = lv.dir[s.inbox ? __umul24(lo, lv.dim_c) + hi : 0u];
+}
+
+__device__ __forceinline__ void site_rec(SiteLook &s, const LdsView &lv) {
+  s.inbox &= s.pidx != 0xFFFFu;
+  s.q = lv.rec[s.inbox ? __umul24(s.pidx, lv.nb) + s.bi : 0u];
+}
+
+template <int K>
+__device__ __forceinline__ void site_finish(const SiteLook &s, ChunkCtx &cx, uint32_t (&va)[4],
+                                            uint32_t (&vb)[4], uint32_t (&vc)[4], uint4 *queue,
+                                            const StepParams &p, uint32_t *err) {
   const uint4 &w = K < 4 ? cx.w0 : cx.w1;
   const uint32_t r = (K & 3) == 0 ? w.x : (K & 3) == 1 ? w.y : (K & 3) == 2 ? w.z : w.w;
-  const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
-  const uint32_t N = ea + eb + ec;
-  const bool live = full | (cx.x8 + K < cx.L);
-  if (live & (N > 65535u)) atomicOr(err, kErrOverflow);
-  const bool collide = live & (N >= 2u) & (N <= 65535u) & (p.C != 0);
-  // LDS image lookup with clamped indices
-  const uint32_t lo = min(ea, ec), hi = max(ea, ec), bi = eb - lv.b_lo;
-  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb) & (N <= p.n_max);
-  const uint32_t pidx = lv.dir[inbox ? __umul24(lo, lv.dim_c) + hi : 0u];
-  const bool have = inbox & (pidx != 0xFFFFu);
-  const uint4 q = lv.rec[have ? __umul24(pidx, lv.nb) + bi : 0u];
+  if (s.live & (s.N > 65535u)) atomicOr(err, kErrOverflow);
+  const bool collide = s.live & (s.N >= 2u) & (s.N <= 65535u) & (p.C != 0);
+  const uint4 q = s.q;
   const uint32_t rh = r >> 16;
   const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
                  t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
-  const bool hit = have & (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) &
+  const bool hit = s.inbox & (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) &
                    (rh != t5) & (rh != t6);
   const uint32_t idx = (q.x & 0xffffu) + (uint32_t)(t2 < rh) + (uint32_t)(t3 < rh) +
                        (uint32_t)(t4 < rh) + (uint32_t)(t5 < rh) + (uint32_t)(t6 < rh);
-  const uint32_t par = eb & 1u;  // N - |J| = b + 2 min(a, c): the fiber's parity is b's
+  const uint32_t par = s.eb & 1u;  // N - |J| = b + 2 min(a, c): the fiber's parity is b's
   const uint32_t bn = par + 2u * idx;
-  const int32_t d = (collide & hit) ? ((int32_t)eb - (int32_t)bn) >> 1 : 0;
-  set16(va, K, (uint32_t)((int32_t)ea + d));
-  set16(vb, K, (uint32_t)((int32_t)eb - 2 * d));
-  set16(vc, K, (uint32_t)((int32_t)ec + d));
+  const int32_t d = (collide & hit) ? ((int32_t)s.eb - (int32_t)bn) >> 1 : 0;
+  set16(va, K, (uint32_t)((int32_t)s.ea + d));
+  set16(vb, K, (uint32_t)((int32_t)s.eb - 2 * d));
+  set16(vc, K, (uint32_t)((int32_t)s.ec + d));
   const bool miss = collide & !hit;
   const uint64_t bal = __ballot(miss);
   if (bal) {
     const uint32_t cnt = (uint32_t)__popcll(bal);
-    const uint4 e = make_uint4(cx.x8 + K, ea | (eb << 16), ec, r);
+    const uint4 e = make_uint4(cx.x8 + K, s.ea | (s.eb << 16), s.ec, r);
+    // queued: the state keeps the pre-collision counts until the drain
+    // writes the final ones; a full LDS queue spills to global memory
     if (cx.qn + cnt <= kQueue) {
-      // queued: the state keeps the pre-collision counts until the drain
-      // writes the final ones
       if (miss) queue[cx.qn + lanes_below(bal)] = e;
       cx.qn += cnt;
-    } else if (miss) {  // queue full: this lane resolves the site itself
-      apply_outcome(va, vb, vc, K, resolve_queued(e, p, tab, t, rid, err));
+    } else if (cx.on + cnt <= kOverflow) {
+      if (miss) cx.over[cx.on + lanes_below(bal)] = e;
+      cx.on += cnt;
+    } else if (miss) {
+      atomicOr(err, kErrInternal);  // unreachable by the drain rule
     }
   }
+}
+
+// Four sites K0..K0+3 of the lane: directory reads, record reads, decisions.
+template <int K0>
+__device__ __forceinline__ void decide_four(ChunkCtx &cx, bool full, uint32_t (&va)[4],
+                                            uint32_t (&vb)[4], uint32_t (&vc)[4],
+                                            const LdsView &lv, uint4 *queue,
+                                            const StepParams &p, uint32_t *err) {
+  SiteLook s0, s1, s2, s3;
+  site_dir<K0 + 0>(s0, cx, full, va, vb, vc, lv, p);
+  site_dir<K0 + 1>(s1, cx, full, va, vb, vc, lv, p);
+  site_dir<K0 + 2>(s2, cx, full, va, vb, vc, lv, p);
+  site_dir<K0 + 3>(s3, cx, full, va, vb, vc, lv, p);
+  site_rec(s0, lv);
+  site_rec(s1, lv);
+  site_rec(s2, lv);
+  site_rec(s3, lv);
+  site_finish<K0 + 0>(s0, cx, va, vb, vc, queue, p, err);
+  site_finish<K0 + 1>(s1, cx, va, vb, vc, queue, p, err);
+  site_finish<K0 + 2>(s2, cx, va, vb, vc, queue, p, err);
+  site_finish<K0 + 3>(s3, cx, va, vb, vc, queue, p, err);
 }
 
 // Resolve every queued draw of the wave (all lanes in parallel) and store
@@ -341,15 +312,15 @@ __device__ __forceinline__ void decide_site(ChunkCtx &cx, bool full, uint32_t (&
 // earlier memory operations have completed -- among them the stores that
 // wrote the pre-collision counts of these sites -- so the final counts land
 // after them.
-__device__ __forceinline__ void drain_queue(uint4 *queue, uint32_t qn, uint32_t lane,
-                                            const SlotView &v, const StepParams &p,
-                                            const TableDev &tab, uint32_t *err) {
+__device__ __forceinline__ void drain_queue(const uint4 *queue, uint32_t qn, const uint4 *over,
+                                        uint32_t on, uint32_t lane, const SlotView &v,
+                                        const StepParams &p, const TableDev &tab, uint32_t *err) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  for (uint32_t i = lane; i < qn; i += 64u) {
-    const uint4 e = queue[i];
+  for (uint32_t i = lane; i < qn + on; i += 64u) {
+    const uint4 e = i < qn ? queue[i] : over[i - qn];
     const uint32_t x = e.x, ea = e.y & 0xffffu, eb = e.y >> 16, ec = e.z;
     const uint32_t bn = resolve_queued(e, p, tab, v.t, v.rid, err);
     const int32_t N = (int32_t)(ea + eb + ec), J = (int32_t)ec - (int32_t)ea;
@@ -364,24 +335,124 @@ __device__ __forceinline__ void drain_queue(uint4 *queue, uint32_t qn, uint32_t 
   __builtin_amdgcn_wave_barrier();
 }
 
+// ---------------------------------------------------------------------------
+// Streaming over a wave's run of consecutive chunks
+// ---------------------------------------------------------------------------
+// Where chunk xs .. xs + 511 of a slot lies at step t: the three physical
+// windows (n_-1 at (x + t) mod L, n_0 at x, n_+1 at (x - t) mod L) and
+// whether none of them wraps around the end of the lattice (fast path).
+struct Win {
+  uint32_t xs, sm, sp;
+  uint32_t fast;  // 0 or 1
+};
+__device__ __forceinline__ Win locate(uint32_t xs, const SlotView &v) {
+  Win w;
+  w.xs = xs;
+  w.sm = xs + v.tm;
+  w.sm -= (w.sm >= v.L) ? v.L : 0u;
+  w.sp = xs >= v.tm ? xs - v.tm : xs + v.L - v.tm;
+  w.fast = (uint32_t)((xs + 512u <= v.L) & (w.sm + 512u <= v.L) & (w.sp + 512u <= v.L));
+  return w;
+}
+// The lane-aligned vectors of a fast chunk (element 8 * lane of the aligned
+// base of each window).
+struct Raw {
+  uint32_t m[4], z[4], p[4];
+};
+__device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint32_t lane,
+                                          Raw &r) {
+  load4(v.nm + (w.sm & ~7u) + 8u * lane, r.m);
+  load4(v.n0 + w.xs + 8u * lane, r.z);
+  load4(v.np + (w.sp & ~7u) + 8u * lane, r.p);
+}
+// Realign one misaligned window: lane i needs elements [b, b + 8) of its
+// vector followed by lane i+1's; lane 63 takes the vector after the window
+// (`ext`, wave-uniform).
+__device__ __forceinline__ void realign(const uint32_t (&raw)[4], const uint32_t (&ext)[4],
+                                        uint32_t b, uint32_t lane, uint32_t (&out)[4]) {
+  if (b == 0u) {
+    for (int j = 0; j < 4; ++j) out[j] = raw[j];
+    return;
+  }
+  uint32_t nx[4];
+  shfl_down4(raw, nx);
+  if (lane == 63u)
+    for (int j = 0; j < 4; ++j) nx[j] = ext[j];
+  extract8(raw, nx, b, out);
+}
+// Store one misaligned window back to its aligned vectors.  Lanes 1..63
+// write whole vectors.  Lane 0's vector starts with the previous chunk's last
+// b elements: merged from `carry_in` when the previous chunk deferred them,
+// else lane 0 writes only its own elements.  The b elements after the window
+// belong to lane 63: with `defer` they are left for the next chunk's lane 0
+// (returned through `carry_out`), else lane 63 writes them.
+__device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t lane,
+                                            const uint32_t (&o)[4], bool have_carry,
+                                            const uint32_t (&carry_in)[4], bool defer,
+                                            uint32_t (&carry_out)[4]) {
+  const uint32_t b = s & 7u, A = s - b;
+  if (b == 0u) {
+    store4(arr + A + 8u * lane, o);
+    return;
+  }
+  uint32_t prev[4], al[4];
+  shfl_up4(o, prev);
+  if (lane == 0u && have_carry)
+    for (int j = 0; j < 4; ++j) prev[j] = carry_in[j];
+  extract8(prev, o, 8u - b, al);
+  if (lane != 0u || have_carry) {
+    store4(arr + A + 8u * lane, al);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if ((uint32_t)e < 8u - b) arr[s + e] = (uint16_t)get16(o, e);
+  }
+  if (defer) {
+    for (int j = 0; j < 4; ++j) carry_out[j] = __builtin_amdgcn_readlane(o[j], 63);
+  } else if (lane == 63u) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)b + e);
+  }
+}
+// Write deferred boundary elements (elements 8 - b .. 7 of `carry`) to the
+// vector after the window at s.
+__device__ __forceinline__ void flush_carry(uint16_t *arr, uint32_t s, uint32_t lane,
+                                            const uint32_t (&carry)[4]) {
+  const uint32_t b = s & 7u, A = s - b;
+  if (lane == 0u) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(carry, 8 - (int)b + e);
+  }
+}
+
 // Fused stream + collide.  Persistent blocks: block i takes a contiguous run
-// of tiles (so consecutive tiles mostly share a slot) and loads the slot's
-// collision image into LDS whenever the slot changes.  A tile holds
-// G chunks of 512 sites per wave; each lane owns 8 consecutive sites of a
-// chunk (two Philox calls).  All state of a tile is loaded before any of it
-// is stored: every physical element belongs to exactly one site per step.
-template <int G>
-__global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
+// of chunks; a run of one slot's chunks (a segment) is split among the
+// block's waves into contiguous runs, and each wave streams through its run
+// with one chunk of lookahead: the next chunk's vectors are requested before
+// the current one is decided, the vector after a misaligned window is the
+// next chunk's first lane vector, and the boundary vector between two
+// chunks is written whole by the second.  The slot's collision image is
+// loaded into LDS at each segment.  Each lane owns 8 consecutive sites of a
+// chunk (two Philox calls).  Every physical element belongs to exactly one
+// site per step, so the in-place update has no races.
+template <int MAXT>
+__global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   extern __shared__ uint4 lds[];
   const StepParams &p = a.p;
   const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const uint32_t lane = threadIdx.x & 63u, nwaves = blockDim.x >> 6;
+  // wave-uniform, which the compiler cannot infer from threadIdx.x
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint4 *const queue = lds + a.lds_bytes / 16u + wave * kQueue;
+  uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
+  uint32_t on = 0;  // overflow fill (wave-uniform)
+  uint32_t qn = 0;  // LDS queue fill (wave-uniform), all of slot `cur`
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
-  const uint32_t tb = blockIdx.x * per;
-  const uint32_t te = min(a.n_tiles, tb + per);
+  const uint32_t cb = blockIdx.x * per;
+  const uint32_t ce = min(a.n_tiles, cb + per);
   uint32_t cur = 0xFFFFFFFFu;
-  uint32_t qn = 0;  // queued draws of this wave (wave-uniform), all of slot `cur`
   SlotView sv;
   sv.nm = sv.n0 = sv.np = nullptr;
   sv.L = 1; sv.tm = sv.t = sv.rid = 0;
@@ -389,16 +460,20 @@ __global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
   lv.dir = reinterpret_cast<const uint16_t *>(lds);
   lv.rec = lds;
   lv.dim_a = lv.dim_c = lv.nb = lv.b_lo = 0;
-  for (uint32_t ti = tb; ti < te; ++ti) {
-    const TileDev tile = a.tiles[ti];
-    if (tile.slot != cur) {
-      if (qn) drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
-      qn = 0;
-      cur = tile.slot;
+
+  for (uint32_t i = cb; i < ce;) {
+    const TileDev t0 = a.tiles[i];
+    const uint32_t se = min(ce, t0.next);
+    if (t0.slot != cur) {
+      if (qn + on) {  // queued draws belong to the previous slot
+        drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
+        qn = on = 0;
+      }
+      cur = t0.slot;
       const ImageDesc im = a.images[cur];
       __syncthreads();  // previous image no longer in use
       const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
-      for (uint32_t i = threadIdx.x; i < im.bytes / 16u; i += blockDim.x) lds[i] = src[i];
+      for (uint32_t k = threadIdx.x; k < im.bytes / 16u; k += blockDim.x) lds[k] = src[k];
       __syncthreads();
       lv.dim_a = im.bytes ? im.dim_a : 0u;
       lv.dim_c = im.dim_c;
@@ -413,90 +488,121 @@ __global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
       sv.nm = a.state + sl.off;
       sv.n0 = sv.nm + sl.stride;
       sv.np = sv.n0 + sl.stride;
-    } else if (qn > kQueue - 64u) {
-      drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
-      qn = 0;
     }
+    // this wave's run of the segment's chunks
+    const uint32_t n = se - i;
+    const uint32_t k0 = i + (wave * n) / nwaves, k1 = i + ((wave + 1) * n) / nwaves;
     const uint32_t L = sv.L, tm = sv.tm, t = sv.t;
     uint16_t *const nm = sv.nm;
     uint16_t *const n0 = sv.n0;
     uint16_t *const np = sv.np;
-
-    // ---- load ----
-    uint32_t va[G][4], vb[G][4], vc[G][4];
-    uint32_t xs[G], sm[G], sp[G];
-    bool fast[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      xs[g] = tile.x0 + ((uint32_t)g * nwaves + wave) * 512u;
-      sm[g] = xs[g] + tm;
-      sm[g] -= (sm[g] >= L) ? L : 0u;
-      sp[g] = xs[g] >= tm ? xs[g] - tm : xs[g] + L - tm;
-      fast[g] = (xs[g] + 512u <= L) & (sm[g] + 512u <= L) & (sp[g] + 512u <= L);
-      if (fast[g]) {
-        load_window(nm, sm[g], lane, va[g]);
-        load4(n0 + xs[g] + 8u * lane, vb[g]);
-        load_window(np, sp[g], lane, vc[g]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t x = xs[g] + 8u * lane + k;
-          uint32_t ea = 0, eb = 0, ec = 0;
-          if (x < L) {
-            uint32_t pm = x + tm;
-            pm -= (pm >= L) ? L : 0u;
-            const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-            ea = nm[pm]; eb = n0[x]; ec = np[pp];
-          }
-          set16(va[g], k, ea); set16(vb[g], k, eb); set16(vc[g], k, ec);
+    if (k0 < k1) {
+      Win cw = locate(t0.x0 + (k0 - i) * 512u, sv);
+      Raw cr;
+      if (cw.fast) issue_raw(cw, sv, lane, cr);
+      bool carry = false;
+      uint32_t cm[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
+      for (uint32_t k = k0; k < k1; ++k) {
+        Win nw = cw;
+        Raw nr;
+        bool next_fast = false;
+        if (k + 1 < k1) {
+          nw = locate(cw.xs + 512u, sv);
+          if (nw.fast) issue_raw(nw, sv, lane, nr);
+          // contiguous in all three arrays: neither shifted window wraps to 0
+          next_fast = ((nw.fast & cw.fast) != 0u) & (nw.sm == cw.sm + 512u) &
+                      (nw.sp == cw.sp + 512u);
         }
-      }
-    }
-
-    // ---- collide: LDS image first, the rest into the wave's queue ----
+        // ---- the chunk's three windows ----
+        uint32_t va[4], vb[4], vc[4];
+        if (cw.fast) {
+          const uint32_t bm = cw.sm & 7u, bp = cw.sp & 7u;
+          uint32_t em[4], ep[4];
+          if (next_fast) {
+            for (int j = 0; j < 4; ++j) em[j] = __builtin_amdgcn_readlane(nr.m[j], 0);
+            for (int j = 0; j < 4; ++j) ep[j] = __builtin_amdgcn_readlane(nr.p[j], 0);
+          } else {
+            if (bm) load4(nm + (cw.sm & ~7u) + 512u, em);
+            if (bp) load4(np + (cw.sp & ~7u) + 512u, ep);
+          }
+          realign(cr.m, em, bm, lane, va);
+          for (int j = 0; j < 4; ++j) vb[j] = cr.z[j];
+          realign(cr.p, ep, bp, lane, vc);
+        } else {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      ChunkCtx cx;
-      cx.x8 = xs[g] + 8u * lane;
-      cx.w0 = philox10(make_uint4(cx.x8 >> 2, t, sv.rid, 0u), key);
-      cx.w1 = philox10(make_uint4((cx.x8 >> 2) + 1u, t, sv.rid, 0u), key);
-      cx.L = L;
-      cx.qn = qn;
-      decide_site<0>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<1>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<2>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<3>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<4>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<5>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<6>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      decide_site<7>(cx, fast[g], va[g], vb[g], vc[g], lv, queue, p, a.tab, t, sv.rid, a.err);
-      qn = cx.qn;
-    }
-
-    // ---- store ----
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (fast[g]) {
-        store_window(nm, sm[g], lane, va[g]);
-        store4(n0 + xs[g] + 8u * lane, vb[g]);
-        store_window(np, sp[g], lane, vc[g]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t x = xs[g] + 8u * lane + k;
-          if (x < L) {
-            uint32_t pm = x + tm;
-            pm -= (pm >= L) ? L : 0u;
-            const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-            nm[pm] = (uint16_t)get16(va[g], k);
-            n0[x] = (uint16_t)get16(vb[g], k);
-            np[pp] = (uint16_t)get16(vc[g], k);
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t x = cw.xs + 8u * lane + e;
+            uint32_t ea = 0, eb = 0, ec = 0;
+            if (x < L) {
+              uint32_t pm = x + tm;
+              pm -= (pm >= L) ? L : 0u;
+              const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+              ea = nm[pm]; eb = n0[x]; ec = np[pp];
+            }
+            set16(va, e, ea); set16(vb, e, eb); set16(vc, e, ec);
           }
         }
+
+        // ---- collide: LDS image first, the rest into the wave's queue ----
+        {
+          ChunkCtx cx;
+          cx.x8 = cw.xs + 8u * lane;
+          cx.w0 = philox10(make_uint4(cx.x8 >> 2, t, sv.rid, 0u), key);
+          cx.w1 = philox10(make_uint4((cx.x8 >> 2) + 1u, t, sv.rid, 0u), key);
+          cx.L = L;
+          cx.qn = qn;
+          cx.on = on;
+          cx.over = over;
+          decide_four<0>(cx, cw.fast, va, vb, vc, lv, queue, p, a.err);
+          decide_four<4>(cx, cw.fast, va, vb, vc, lv, queue, p, a.err);
+          qn = cx.qn;
+          on = cx.on;
+        }
+
+        // ---- store ----
+        if (cw.fast) {
+          uint32_t ncm[4], ncp[4];
+          store_merge(nm, cw.sm, lane, va, carry, cm, next_fast, ncm);
+          store4(n0 + cw.xs + 8u * lane, vb);
+          store_merge(np, cw.sp, lane, vc, carry, cp, next_fast, ncp);
+          carry = next_fast;
+          if (carry)
+            for (int j = 0; j < 4; ++j) { cm[j] = ncm[j]; cp[j] = ncp[j]; }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t x = cw.xs + 8u * lane + e;
+            if (x < L) {
+              uint32_t pm = x + tm;
+              pm -= (pm >= L) ? L : 0u;
+              const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+              nm[pm] = (uint16_t)get16(va, e);
+              n0[x] = (uint16_t)get16(vb, e);
+              np[pp] = (uint16_t)get16(vc, e);
+            }
+          }
+          carry = false;
+        }
+        // Drain a nearly full queue (at most kQueue - 64 entries stay queued,
+        // so the next chunk's 64 x 8 draws always fit the LDS queue plus the
+        // overflow area).  Deferred boundary elements are written first: the
+        // drain's final counts must land after every placeholder.
+        if (qn + on > kQueue - 64u) {
+          if (carry) {
+            flush_carry(nm, cw.sm, lane, cm);
+            flush_carry(np, cw.sp, lane, cp);
+            carry = false;
+          }
+          drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
+          qn = on = 0;
+        }
+        cw = nw;
+        cr = nr;
       }
     }
+    i = se;
   }
-  if (qn) drain_queue(queue, qn, lane, sv, p, a.tab, a.err);
+  if (qn + on) drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
   // The last block of the launch advances t of every slot in the launch.
   // Every block has consumed its loads of t before it takes its ticket (the
   // values shaped its work), so nothing reads the new value during this
@@ -506,8 +612,8 @@ __global__ void __launch_bounds__(1024) k_step(StepLaunch a) {
   if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1u;
   __syncthreads();
   if (last) {
-    for (uint32_t i = threadIdx.x; i < a.n_slots; i += blockDim.x) {
-      const uint32_t s = a.slot_list ? a.slot_list[i] : a.slot_first + i;
+    for (uint32_t k = threadIdx.x; k < a.n_slots; k += blockDim.x) {
+      const uint32_t s = a.slot_list ? a.slot_list[k] : a.slot_first + k;
       a.tslot[s] += 1u;
     }
     if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
@@ -632,29 +738,26 @@ __global__ void __launch_bounds__(256) k_moments(
 
 }  // namespace
 
-template <int G>
+template <int MAXT>
 static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<G>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<MAXT>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step<G>, (int)threads, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step<MAXT>, (int)threads, lds);
 }
 
 uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
   return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kQueueBytesPerWave;
 }
 
+// Blocks of up to 512 threads may use up to 256 VGPRs per lane.
 hipError_t step_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,
                           uint32_t &max_blocks) {
   int b = 0;
-  hipError_t e;
+  if (sch.groups != 1) return hipErrorInvalidValue;
   const uint32_t lds = step_lds_bytes(sch, lds_bytes);
-  switch (sch.groups) {
-    case 1: e = occupancy_of<1>(sch.threads, lds, b); break;
-    case 2: e = occupancy_of<2>(sch.threads, lds, b); break;
-    case 4: e = occupancy_of<4>(sch.threads, lds, b); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipError_t e = sch.threads <= 512 ? occupancy_of<512>(sch.threads, lds, b)
+                                    : occupancy_of<1024>(sch.threads, lds, b);
   if (e) return e;
   if (b < 1) return hipErrorInvalidConfiguration;
   max_blocks = (uint32_t)b * n_cu;
@@ -665,12 +768,9 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) 
   if (a.n_tiles == 0) return hipSuccess;
   dim3 grid(std::max<uint32_t>(1, std::min(a.n_tiles, a.max_blocks))), block(sch.threads);
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
-  switch (sch.groups) {
-    case 1: k_step<1><<<grid, block, lds, s>>>(a); break;
-    case 2: k_step<2><<<grid, block, lds, s>>>(a); break;
-    case 4: k_step<4><<<grid, block, lds, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (sch.groups != 1) return hipErrorInvalidValue;
+  if (sch.threads <= 512) k_step<512><<<grid, block, lds, s>>>(a);
+  else k_step<1024><<<grid, block, lds, s>>>(a);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ constexpr uint32_t kImage = 96 * 1024;  // LDS collision image budget per job
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_ipool,
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, bytes, max_tiles;
 };
 
@@ -55,6 +55,7 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   l.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
   l.o_idesc = take(sizeof(ImageDesc) * n);
+  l.o_over = take(kOverflowBytes);
   l.o_ipool = take((uint64_t)kImage * n);
   l.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
@@ -168,6 +169,7 @@ struct mclg_server {
     a.p = params();
     a.images = d_idesc();
     a.image_pool = ws + lay.o_ipool;
+    a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);
     a.lds_bytes = lds_bytes;
     a.max_blocks = max_blocks;
     return a;
@@ -192,7 +194,8 @@ struct mclg_server {
     for (uint32_t i = 0; i < slot.size(); ++i) {
       if (!slot[i].active) continue;
       h_list.push_back(i);
-      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) h_tiles.push_back(TileDev{i, (uint32_t)x0});
+      const uint32_t next = (uint32_t)(h_tiles.size() + (slot[i].job.L + ts - 1) / ts);
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) h_tiles.push_back(TileDev{i, (uint32_t)x0, next, 0});
     }
     if (h_tiles.size() > lay.max_tiles) return hipErrorInvalidValue;
     n_tiles = (uint32_t)h_tiles.size();
@@ -264,7 +267,7 @@ struct mclg_server {
     std::vector<TileDev> init_tiles;
     const uint32_t ts = sch.tile_sites();
     for (uint32_t i : fresh)
-      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) init_tiles.push_back(TileDev{i, (uint32_t)x0});
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) init_tiles.push_back(TileDev{i, (uint32_t)x0, 0, 0});
     if (init_tiles.size() > lay.max_tiles) return MCLG_E_INVAL;
     hipError_t e = hipSuccess;
     for (uint32_t i : fresh) {  // only the admitted slots' entries change
@@ -298,7 +301,7 @@ struct mclg_server {
     std::vector<TileDev> tl;
     const uint32_t ts = sch.tile_sites();
     for (uint32_t i : fin)
-      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) tl.push_back(TileDev{i, (uint32_t)x0});
+      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) tl.push_back(TileDev{i, (uint32_t)x0, 0, 0});
     if (tl.size() > lay.max_tiles) return MCLG_E_INVAL;
     hipError_t e = up(d_tiles(), tl.data(), sizeof(TileDev) * tl.size());
     if (!e) e = launch_zero(s, reinterpret_cast<unsigned long long *>(d_mom()),
@@ -377,6 +380,7 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
     if (!e) sv->image_budget = std::min<uint32_t>(kImage, (uint32_t)std::max(0, v - 1024 - (int)queues)) / 16u * 16u;
     if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
     if (!e) sv->n_cu = (uint32_t)std::max(1, v);
+    if (!e && sv->n_cu > 256) return MCLG_E_UNSUPPORTED;  // overflow region sized for 256 CUs
     sv->lds_bytes = std::max<uint32_t>(16, sv->image_budget);
     if (!e) e = step_occupancy(sv->sch, sv->lds_bytes, sv->n_cu, sv->max_blocks);
     if (e) return sv->hip(e);
@@ -450,7 +454,7 @@ int mclg_server_poll(mclg_server *sv, mclg_job_result *out, uint32_t cap, uint32
   uint32_t err = 0;
   hipError_t e = hipMemcpy(&err, sv->err(), sizeof(err), hipMemcpyDeviceToHost);
   if (e) return sv->hip(e);
-  return err ? MCLG_E_RANGE : MCLG_OK;
+  return (err & 4u) ? MCLG_E_INTERNAL : err ? MCLG_E_RANGE : MCLG_OK;
 }
 
 int mclg_server_stats(const mclg_server *sv, uint64_t *queued, uint64_t *resident,

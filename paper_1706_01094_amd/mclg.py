@@ -23,7 +23,7 @@ C_EQUILIBRIUM = -1
 FLAG_NO_STREAM = 1
 INIT_COUNTS, INIT_POISSON = 1, 2
 MAX_MODES = 8
-OK, E_INVAL, E_RANGE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_FULL = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVAL, E_RANGE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_FULL, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 u32, u64, i32, i64, dbl, vp = ct.c_uint32, ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_double, ct.c_void_p
 P = ct.POINTER

@@ -182,7 +182,7 @@ struct mclg_ctx {
   // (Re)build the images for the current budget, upload them, and size the
   // persistent grid from the runtime's occupancy for that LDS footprint.
   hipError_t prepare_images() {
-    const uint32_t queues = (sch.threads / 64u) * kQueueBytesPerWave;
+    const uint32_t queues = (sch.threads / 64u) * kWaveLdsBytes;
     const uint32_t room = lds_limit > queues ? lds_limit - queues : 0u;
     const uint32_t budget = std::min(sch.lds_budget, std::min(kMaxImage, room)) / 16u * 16u;
     std::map<std::pair<double, double>, uint32_t> uniq;
@@ -198,7 +198,7 @@ struct mclg_ctx {
     std::atomic<size_t> next(0);
     auto work = [&]() {
       for (size_t i; (i = next.fetch_add(1)) < keys.size();)
-        ims[i] = budget >= 64 ? build_image(*tab, keys[i].first, keys[i].second, budget) : LdsImage();
+        ims[i] = build_image(*tab, keys[i].first, keys[i].second, budget);
     };
     std::vector<std::thread> th;
     unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -220,7 +220,7 @@ struct mclg_ctx {
       const LdsImage &im = ims[which[r]];
       ImageDesc &d = img_desc[r];
       d.off = at[which[r]];
-      d.bytes = (uint32_t)(im.dir.size() ? im.blob().size() : 0);
+      d.bytes = (uint32_t)im.blob().size();
       d.dir_bytes = im.dir_bytes();
       d.dim_a = im.dim_a;
       d.dim_c = im.dim_c;

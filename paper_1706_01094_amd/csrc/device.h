@@ -54,7 +54,7 @@ struct MomDev {
 // Where a slot's LDS image lives in the image pool (see LdsImage).
 struct ImageDesc {
   uint64_t off;        // byte offset in the image pool (16-byte aligned)
-  uint32_t bytes;      // 0 = no image
+  uint32_t bytes;      // every slot has one (at least the two special slots)
   uint32_t dir_bytes;
   uint32_t dim_a, dim_c, b_lo, nb;
 };
@@ -95,10 +95,11 @@ struct StepLaunch {
 
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 
-// Bytes of LDS per wave for its queue of undecided draws.
-constexpr uint32_t kQueueBytesPerWave = 128 * 16;
-// Entries of the global overflow area per wave (one chunk's worth of sites),
-// and the number of waves the overflow region is sized for (all waves that
+constexpr uint32_t kQueue = 128;  // LDS queue entries (16 bytes) per wave
+// per-wave LDS after the image: the queue, then two carried boundary vectors
+constexpr uint32_t kWaveLdsBytes = kQueue * 16 + 2 * 16;
+// Entries of the global overflow area per wave (one chunk's worth of sites;
+// the queue continues there when its LDS part is full), and the number of waves the overflow region is sized for (all waves that
 // can be resident on a 256-CU device).
 constexpr uint32_t kOverflowPerWave = 512;
 constexpr uint32_t kOverflowWaves = 256 * 32;

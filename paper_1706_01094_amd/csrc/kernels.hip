@@ -28,6 +28,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
     if (i) {
       k.x += 0x9E3779B9u;
       k.y += 0xBB67AE85u;
+      // recomputed at every use (scalar adds) rather than held in registers
+      asm volatile("" : "+s"(k.x), "+s"(k.y));
     }
     // one 32x32 -> 64-bit multiply per product (v_mad_u64_u32)
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
@@ -119,7 +121,9 @@ struct LdsView {
   const uint16_t *dir;
   const uint4 *rec;
   uint32_t dim_a, dim_c, b_lo, nb;
+  uint32_t never;  // directory slot of the "never" records; the "skip" slot follows
 };
+constexpr uint32_t kSkipRecordX = 0xFFFF8000u;  // first word of the skip record
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers
@@ -173,7 +177,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 
 // Per-wave queue of draws the LDS image could not decide (or sites with
 // N > n_max); drained by all lanes at once.
-constexpr uint32_t kQueue = kQueueBytesPerWave / 16;
 constexpr uint32_t kOverflow = kOverflowPerWave;
 
 // Exact outcome for a queued site: global row, or the literal loop.  It is
@@ -196,115 +199,150 @@ __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepPara
   return collide_direct(a, b, c, p, x, t, rid);
 }
 
-// Per-chunk state of one lane while its eight sites are decided.
-struct ChunkCtx {
-  uint32_t x8;     // first of the lane's eight sites
-  uint4 w0, w1;    // Philox words of sites x8 .. x8 + 7
-  uint32_t L;
-  uint32_t qn;     // the wave's LDS queue fill (wave-uniform)
-  uint32_t on;     // the wave's overflow fill in global memory (wave-uniform)
-  uint4 *over;     // the wave's overflow area (kOverflow entries)
-};
-
 // Where a slot's three arrays are and how they are shifted at step t.
 struct SlotView {
   uint16_t *nm, *n0, *np;
   uint32_t L, tm, t, rid;
 };
 
-// Site K of the lane, in three phases so that the LDS reads of several
-// sites are in flight together: (1) the directory read, (2) the record
-// read, (3) the decision.  Branch-free apart from the queue: indices are
-// clamped into the image and the outcome is selected.  With b' drawn,
-// n_-1 and n_+1 follow from the conserved N and J (Eq. (collcons)):
-// a' = a + (b - b')/2, c' = c + (b - b')/2.
+// Two 16-bit lanes of a 32-bit register.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_add16(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
+}
+
+// Decision of one site from the LDS image, in three phases so that the LDS
+// reads of several sites are in flight together: (1) directory read, (2)
+// record read, (3) decision.  There is no branch per site and nothing but
+// the record is carried from one phase to the next: a site that does not
+// collide reads the skip slot, a site outside the image (or of an absent
+// pair) reads a never record, and neither record decides a draw.  A record
+// holds (b >> 1) - k_s and the top 16 bits of seven consecutive thresholds
+// t1..t7 of the site's fiber row; with the top half rh of the draw strictly
+// between t1 and t7 and equal to none of t2..t6 the drawn state index is
+// k_s + #{t2..t6 < rh}, and the move of Eq. (collcons) is
+// d = (b - b') / 2 = (b >> 1) - k_s - #{t2..t6 < rh}  (b' has b's parity).
 struct SiteLook {
-  uint32_t ea, eb, ec, N, bi, pidx;
-  bool inbox, live;
+  uint32_t pidx, bix;
   uint4 q;
 };
 
 template <int K>
-__device__ __forceinline__ void site_dir(SiteLook &s, const ChunkCtx &cx, bool full,
+__device__ __forceinline__ void site_dir(SiteLook &s, uint32_t x8, uint32_t L, bool full,
                                          const uint32_t (&va)[4], const uint32_t (&vb)[4],
                                          const uint32_t (&vc)[4], const LdsView &lv,
-                                         const StepParams &p) {
-  s.ea = get16(va, K);
-  s.eb = get16(vb, K);
-  s.ec = get16(vc, K);
-  s.N = s.ea + s.eb + s.ec;
-  s.live = full | (cx.x8 + K < cx.L);
-  const uint32_t lo = min(s.ea, s.ec), hi = max(s.ea, s.ec);
-  s.bi = s.eb - lv.b_lo;
-  s.inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (s.bi < lv.nb) & (s.N <= p.n_max);
-  s.pidx = lv.dir[s.inbox ? __umul24(lo, lv.dim_c) + hi : 0u];
+                                         const StepParams &p, bool &range_err) {
+  const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
+  const uint32_t N = ea + eb + ec;
+  const bool live = full | (x8 + K < L);
+  range_err |= live & (N > 65535u);
+  const bool collide = live & (N >= 2u) & (N <= 65535u) & (p.C != 0);
+  const uint32_t lo = min(ea, ec), hi = max(ea, ec), bi = eb - lv.b_lo;
+  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb);
+  const uint32_t slot = inbox ? __umul24(lo, lv.dim_c) + hi : lv.never;
+  s.bix = (collide & inbox) ? bi : 0u;
+  s.pidx = lv.dir[collide ? slot : lv.never + 1u];
 }
 
 __device__ __forceinline__ void site_rec(SiteLook &s, const LdsView &lv) {
-  s.inbox &= s.pidx != 0xFFFFu;
-  s.q = lv.rec[s.inbox ? __umul24(s.pidx, lv.nb) + s.bi : 0u];
+  s.q = lv.rec[__umul24(s.pidx, lv.nb) + s.bix];
 }
 
+// Returns d (0 unless decided here); sets bit K of `miss` for a collision
+// the image did not decide.
 template <int K>
-__device__ __forceinline__ void site_finish(const SiteLook &s, ChunkCtx &cx, uint32_t (&va)[4],
-                                            uint32_t (&vb)[4], uint32_t (&vc)[4], uint4 *queue,
-                                            const StepParams &p, uint32_t *err) {
-  const uint4 &w = K < 4 ? cx.w0 : cx.w1;
-  const uint32_t r = (K & 3) == 0 ? w.x : (K & 3) == 1 ? w.y : (K & 3) == 2 ? w.z : w.w;
-  if (s.live & (s.N > 65535u)) atomicOr(err, kErrOverflow);
-  const bool collide = s.live & (s.N >= 2u) & (s.N <= 65535u) & (p.C != 0);
+__device__ __forceinline__ int32_t site_finish(const SiteLook &s, uint32_t r, uint32_t &miss) {
   const uint4 q = s.q;
   const uint32_t rh = r >> 16;
   const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
                  t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
-  const bool hit = s.inbox & (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) &
-                   (rh != t5) & (rh != t6);
-  const uint32_t idx = (q.x & 0xffffu) + (uint32_t)(t2 < rh) + (uint32_t)(t3 < rh) +
-                       (uint32_t)(t4 < rh) + (uint32_t)(t5 < rh) + (uint32_t)(t6 < rh);
-  const uint32_t par = s.eb & 1u;  // N - |J| = b + 2 min(a, c): the fiber's parity is b's
-  const uint32_t bn = par + 2u * idx;
-  const int32_t d = (collide & hit) ? ((int32_t)s.eb - (int32_t)bn) >> 1 : 0;
-  set16(va, K, (uint32_t)((int32_t)s.ea + d));
-  set16(vb, K, (uint32_t)((int32_t)s.eb - 2 * d));
-  set16(vc, K, (uint32_t)((int32_t)s.ec + d));
-  const bool miss = collide & !hit;
-  const uint64_t bal = __ballot(miss);
-  if (bal) {
-    const uint32_t cnt = (uint32_t)__popcll(bal);
-    const uint4 e = make_uint4(cx.x8 + K, s.ea | (s.eb << 16), s.ec, r);
-    // queued: the state keeps the pre-collision counts until the drain
-    // writes the final ones; a full LDS queue spills to global memory
-    if (cx.qn + cnt <= kQueue) {
-      if (miss) queue[cx.qn + lanes_below(bal)] = e;
-      cx.qn += cnt;
-    } else if (cx.on + cnt <= kOverflow) {
-      if (miss) cx.over[cx.on + lanes_below(bal)] = e;
-      cx.on += cnt;
-    } else if (miss) {
-      atomicOr(err, kErrInternal);  // unreachable by the drain rule
-    }
-  }
+  const bool hit = (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) & (rh != t5) &
+                   (rh != t6);
+  const int32_t d = (int32_t)(int16_t)(q.x & 0xffffu) - (int32_t)(t2 < rh) - (int32_t)(t3 < rh) -
+                    (int32_t)(t4 < rh) - (int32_t)(t5 < rh) - (int32_t)(t6 < rh);
+  miss |= (!hit & (q.x != kSkipRecordX)) ? (1u << K) : 0u;
+  return hit ? d : 0;
 }
 
-// Four sites K0..K0+3 of the lane: directory reads, record reads, decisions.
+// Sites 2j and 2j + 1 move by d0 and d1: n_-1 and n_+1 gain d, n_0 loses 2d
+// (16-bit lanes; every result is a count in [0, 65535]).
+template <int J>
+__device__ __forceinline__ void apply_pair(uint32_t (&va)[4], uint32_t (&vb)[4],
+                                           uint32_t (&vc)[4], int32_t d0, int32_t d1) {
+  const uint32_t dp = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
+  va[J] = pk_add16(va[J], dp);
+  vc[J] = pk_add16(vc[J], dp);
+  vb[J] = pk_sub16(vb[J], pk_add16(dp, dp));
+}
+
+// Sites K0..K0+3 of the lane (K0 = 0 or 4): directory reads, record reads,
+// decisions, updates.
 template <int K0>
-__device__ __forceinline__ void decide_four(ChunkCtx &cx, bool full, uint32_t (&va)[4],
-                                            uint32_t (&vb)[4], uint32_t (&vc)[4],
-                                            const LdsView &lv, uint4 *queue,
-                                            const StepParams &p, uint32_t *err) {
+__device__ __forceinline__ void decide_four(uint32_t x8, uint32_t L, bool full, const uint4 &w,
+                                            uint32_t (&va)[4], uint32_t (&vb)[4],
+                                            uint32_t (&vc)[4], const LdsView &lv,
+                                            const StepParams &p, uint32_t &miss,
+                                            bool &range_err) {
   SiteLook s0, s1, s2, s3;
-  site_dir<K0 + 0>(s0, cx, full, va, vb, vc, lv, p);
-  site_dir<K0 + 1>(s1, cx, full, va, vb, vc, lv, p);
-  site_dir<K0 + 2>(s2, cx, full, va, vb, vc, lv, p);
-  site_dir<K0 + 3>(s3, cx, full, va, vb, vc, lv, p);
+  site_dir<K0 + 0>(s0, x8, L, full, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 1>(s1, x8, L, full, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 2>(s2, x8, L, full, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 3>(s3, x8, L, full, va, vb, vc, lv, p, range_err);
   site_rec(s0, lv);
   site_rec(s1, lv);
   site_rec(s2, lv);
   site_rec(s3, lv);
-  site_finish<K0 + 0>(s0, cx, va, vb, vc, queue, p, err);
-  site_finish<K0 + 1>(s1, cx, va, vb, vc, queue, p, err);
-  site_finish<K0 + 2>(s2, cx, va, vb, vc, queue, p, err);
-  site_finish<K0 + 3>(s3, cx, va, vb, vc, queue, p, err);
+  const int32_t d0 = site_finish<K0 + 0>(s0, w.x, miss);
+  const int32_t d1 = site_finish<K0 + 1>(s1, w.y, miss);
+  apply_pair<K0 / 2>(va, vb, vc, d0, d1);
+  const int32_t d2 = site_finish<K0 + 2>(s2, w.z, miss);
+  const int32_t d3 = site_finish<K0 + 3>(s3, w.w, miss);
+  apply_pair<K0 / 2 + 1>(va, vb, vc, d2, d3);
+}
+
+// The wave's queue of undecided draws: a virtual array of kQueue entries in
+// LDS followed by kOverflow entries in global memory, filled to F
+// (wave-uniform).  An entry is (x, a | b << 16, c, r) with the site's
+// pre-collision counts, which the state keeps until the drain.
+constexpr uint32_t kDrainAt = kQueue - 32;  // drain once F exceeds this
+static_assert(kDrainAt + 512 <= kQueue + kOverflow, "a chunk's draws must fit the queue");
+
+template <int K>
+__device__ __forceinline__ void push_one(uint4 *queue, uint4 *over, uint32_t miss, uint32_t &pos,
+                                         uint32_t x8, const uint32_t (&va)[4],
+                                         const uint32_t (&vb)[4], const uint32_t (&vc)[4],
+                                         uint32_t r, bool lds_only) {
+  if (miss & (1u << K)) {
+    const uint4 e = make_uint4(x8 + K, get16(va, K) | (get16(vb, K) << 16), get16(vc, K), r);
+    if (lds_only || pos < kQueue) queue[pos] = e;
+    else over[pos - kQueue] = e;
+    ++pos;
+  }
+}
+
+// Append every missed draw of the chunk (lane-major, then by site) to the
+// queue.  The lane's offset is the exclusive prefix sum of the per-lane miss
+// counts, assembled from ballots of the four bits of each count.
+__device__ __forceinline__ void push_misses(uint4 *queue, uint4 *over, uint32_t &F, uint32_t miss,
+                                            uint32_t x8, const uint32_t (&va)[4],
+                                            const uint32_t (&vb)[4], const uint32_t (&vc)[4],
+                                            const uint4 &w0, const uint4 &w1) {
+  const uint32_t m = (uint32_t)__builtin_popcount(miss);
+  const uint64_t b0 = __ballot(m & 1u), b1 = __ballot(m & 2u), b2 = __ballot(m & 4u),
+                 b3 = __ballot(m & 8u);
+  const uint32_t total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) +
+                         4u * (uint32_t)__popcll(b2) + 8u * (uint32_t)__popcll(b3);
+  uint32_t pos = F + lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2) +
+                 8u * lanes_below(b3);
+  const bool lds_only = F + total <= kQueue;
+#define MCLG_PUSH(K, R) push_one<K>(queue, over, miss, pos, x8, va, vb, vc, R, lds_only)
+  MCLG_PUSH(0, w0.x); MCLG_PUSH(1, w0.y); MCLG_PUSH(2, w0.z); MCLG_PUSH(3, w0.w);
+  MCLG_PUSH(4, w1.x); MCLG_PUSH(5, w1.y); MCLG_PUSH(6, w1.z); MCLG_PUSH(7, w1.w);
+#undef MCLG_PUSH
+  F += total;
 }
 
 // Resolve every queued draw of the wave (all lanes in parallel) and store
@@ -312,15 +350,16 @@ __device__ __forceinline__ void decide_four(ChunkCtx &cx, bool full, uint32_t (&
 // earlier memory operations have completed -- among them the stores that
 // wrote the pre-collision counts of these sites -- so the final counts land
 // after them.
-__device__ __forceinline__ void drain_queue(const uint4 *queue, uint32_t qn, const uint4 *over,
-                                        uint32_t on, uint32_t lane, const SlotView &v,
-                                        const StepParams &p, const TableDev &tab, uint32_t *err) {
+__device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *over, uint32_t F,
+                                            uint32_t lane, const SlotView &v,
+                                            const StepParams &p, const TableDev &tab,
+                                            uint32_t *err) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_s_waitcnt(0);  // vmcnt = expcnt = lgkmcnt = 0
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  for (uint32_t i = lane; i < qn + on; i += 64u) {
-    const uint4 e = i < qn ? queue[i] : over[i - qn];
+  for (uint32_t i = lane; i < F; i += 64u) {
+    const uint4 e = i < kQueue ? queue[i] : over[i - kQueue];
     const uint32_t x = e.x, ea = e.y & 0xffffu, eb = e.y >> 16, ec = e.z;
     const uint32_t bn = resolve_queued(e, p, tab, v.t, v.rid, err);
     const int32_t N = (int32_t)(ea + eb + ec), J = (int32_t)ec - (int32_t)ea;
@@ -382,14 +421,15 @@ __device__ __forceinline__ void realign(const uint32_t (&raw)[4], const uint32_t
 }
 // Store one misaligned window back to its aligned vectors.  Lanes 1..63
 // write whole vectors.  Lane 0's vector starts with the previous chunk's last
-// b elements: merged from `carry_in` when the previous chunk deferred them,
-// else lane 0 writes only its own elements.  The b elements after the window
-// belong to lane 63: with `defer` they are left for the next chunk's lane 0
-// (returned through `carry_out`), else lane 63 writes them.
+// b elements: merged from the wave's carry slot `cs` (LDS) when the previous
+// chunk deferred them, else lane 0 writes only its own elements.  The b
+// elements after the window belong to lane 63: with `defer` its vector goes
+// to the carry slot for the next chunk's lane 0, else lane 63 writes them.
+// LDS operations of a wave complete in order, so the slot is read before it
+// is rewritten.
 __device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t lane,
                                             const uint32_t (&o)[4], bool have_carry,
-                                            const uint32_t (&carry_in)[4], bool defer,
-                                            uint32_t (&carry_out)[4]) {
+                                            bool defer, uint4 *cs) {
   const uint32_t b = s & 7u, A = s - b;
   if (b == 0u) {
     store4(arr + A + 8u * lane, o);
@@ -397,8 +437,10 @@ __device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t 
   }
   uint32_t prev[4], al[4];
   shfl_up4(o, prev);
-  if (lane == 0u && have_carry)
-    for (int j = 0; j < 4; ++j) prev[j] = carry_in[j];
+  if (lane == 0u && have_carry) {
+    const uint4 c = *cs;
+    prev[0] = c.x; prev[1] = c.y; prev[2] = c.z; prev[3] = c.w;
+  }
   extract8(prev, o, 8u - b, al);
   if (lane != 0u || have_carry) {
     store4(arr + A + 8u * lane, al);
@@ -407,23 +449,28 @@ __device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t 
     for (int e = 0; e < 8; ++e)
       if ((uint32_t)e < 8u - b) arr[s + e] = (uint16_t)get16(o, e);
   }
-  if (defer) {
-    for (int j = 0; j < 4; ++j) carry_out[j] = __builtin_amdgcn_readlane(o[j], 63);
-  } else if (lane == 63u) {
+  if (lane == 63u) {
+    if (defer) {
+      *cs = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)b + e);
+      for (int e = 0; e < 8; ++e)
+        if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)b + e);
+    }
   }
 }
-// Write deferred boundary elements (elements 8 - b .. 7 of `carry`) to the
-// vector after the window at s.
+// Write the deferred boundary elements of the chunk before the window at s
+// (elements 8 - b .. 7 of the carried vector) to their places, the first b
+// elements of the aligned vector that holds s.
 __device__ __forceinline__ void flush_carry(uint16_t *arr, uint32_t s, uint32_t lane,
-                                            const uint32_t (&carry)[4]) {
+                                            const uint4 *cs) {
   const uint32_t b = s & 7u, A = s - b;
-  if (lane == 0u) {
+  if (lane == 0u && b != 0u) {
+    const uint4 c4 = *cs;
+    const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(carry, 8 - (int)b + e);
+      if ((uint32_t)e < b) arr[A + e] = (uint16_t)get16(c, 8 - (int)b + e);
   }
 }
 
@@ -436,7 +483,9 @@ __device__ __forceinline__ void flush_carry(uint16_t *arr, uint32_t s, uint32_t 
 // chunks is written whole by the second.  The slot's collision image is
 // loaded into LDS at each segment.  Each lane owns 8 consecutive sites of a
 // chunk (two Philox calls).  Every physical element belongs to exactly one
-// site per step, so the in-place update has no races.
+// site per step, so the in-place update has no races.  Undecided draws wait
+// in the wave's queue, which is drained between chunks (outside the hot
+// loop) once it nears capacity, and at the end of the slot's segment.
 template <int MAXT>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   extern __shared__ uint4 lds[];
@@ -445,10 +494,11 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   const uint32_t lane = threadIdx.x & 63u, nwaves = blockDim.x >> 6;
   // wave-uniform, which the compiler cannot infer from threadIdx.x
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint4 *const queue = lds + a.lds_bytes / 16u + wave * kQueue;
+  uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
+  uint4 *const carry_m = queue + kQueue;  // deferred boundary vectors of n_-1, n_+1
+  uint4 *const carry_p = carry_m + 1;
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
-  uint32_t on = 0;  // overflow fill (wave-uniform)
-  uint32_t qn = 0;  // LDS queue fill (wave-uniform), all of slot `cur`
+  uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
   const uint32_t cb = blockIdx.x * per;
   const uint32_t ce = min(a.n_tiles, cb + per);
@@ -459,26 +509,30 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   LdsView lv;
   lv.dir = reinterpret_cast<const uint16_t *>(lds);
   lv.rec = lds;
-  lv.dim_a = lv.dim_c = lv.nb = lv.b_lo = 0;
+  lv.dim_a = lv.dim_c = lv.nb = lv.b_lo = lv.never = 0;
 
-  for (uint32_t i = cb; i < ce;) {
-    const TileDev t0 = a.tiles[i];
+  for (uint32_t i = cb;;) {
+    TileDev t0;
+    t0.slot = cur;
+    if (i < ce) t0 = a.tiles[i];
+    if (F && (i >= ce || t0.slot != cur)) {  // queued draws belong to slot `cur`
+      drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
+      F = 0;
+    }
+    if (i >= ce) break;
     const uint32_t se = min(ce, t0.next);
     if (t0.slot != cur) {
-      if (qn + on) {  // queued draws belong to the previous slot
-        drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
-        qn = on = 0;
-      }
       cur = t0.slot;
       const ImageDesc im = a.images[cur];
       __syncthreads();  // previous image no longer in use
       const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
       for (uint32_t k = threadIdx.x; k < im.bytes / 16u; k += blockDim.x) lds[k] = src[k];
       __syncthreads();
-      lv.dim_a = im.bytes ? im.dim_a : 0u;
+      lv.dim_a = im.dim_a;
       lv.dim_c = im.dim_c;
       lv.b_lo = im.b_lo;
       lv.nb = im.nb;
+      lv.never = im.dim_a * im.dim_c;
       lv.rec = lds + im.dir_bytes / 16u;
       const SlotDev sl = a.slots[cur];
       sv.t = a.tslot[cur];
@@ -491,18 +545,18 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     }
     // this wave's run of the segment's chunks
     const uint32_t n = se - i;
-    const uint32_t k0 = i + (wave * n) / nwaves, k1 = i + ((wave + 1) * n) / nwaves;
+    const uint32_t k1 = i + ((wave + 1) * n) / nwaves;
+    uint32_t k = i + (wave * n) / nwaves;
     const uint32_t L = sv.L, tm = sv.tm, t = sv.t;
     uint16_t *const nm = sv.nm;
     uint16_t *const n0 = sv.n0;
     uint16_t *const np = sv.np;
-    if (k0 < k1) {
-      Win cw = locate(t0.x0 + (k0 - i) * 512u, sv);
-      Raw cr;
-      if (cw.fast) issue_raw(cw, sv, lane, cr);
-      bool carry = false;
-      uint32_t cm[4] = {0, 0, 0, 0}, cp[4] = {0, 0, 0, 0};
-      for (uint32_t k = k0; k < k1; ++k) {
+    Win cw = locate(t0.x0 + (k - i) * 512u, sv);
+    Raw cr;
+    if (k < k1 && cw.fast) issue_raw(cw, sv, lane, cr);
+    bool carry = false;
+    while (k < k1) {
+      do {
         Win nw = cw;
         Raw nr;
         bool next_fast = false;
@@ -545,29 +599,24 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
 
         // ---- collide: LDS image first, the rest into the wave's queue ----
         {
-          ChunkCtx cx;
-          cx.x8 = cw.xs + 8u * lane;
-          cx.w0 = philox10(make_uint4(cx.x8 >> 2, t, sv.rid, 0u), key);
-          cx.w1 = philox10(make_uint4((cx.x8 >> 2) + 1u, t, sv.rid, 0u), key);
-          cx.L = L;
-          cx.qn = qn;
-          cx.on = on;
-          cx.over = over;
-          decide_four<0>(cx, cw.fast, va, vb, vc, lv, queue, p, a.err);
-          decide_four<4>(cx, cw.fast, va, vb, vc, lv, queue, p, a.err);
-          qn = cx.qn;
-          on = cx.on;
+          const uint32_t x8 = cw.xs + 8u * lane;
+          const uint4 w0 = philox10(make_uint4(x8 >> 2, t, sv.rid, 0u), key);
+          const uint4 w1 = philox10(make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u), key);
+          const bool full = cw.fast != 0u;
+          uint32_t miss = 0;
+          bool range_err = false;
+          decide_four<0>(x8, L, full, w0, va, vb, vc, lv, p, miss, range_err);
+          decide_four<4>(x8, L, full, w1, va, vb, vc, lv, p, miss, range_err);
+          if (range_err) atomicOr(a.err, kErrOverflow);
+          if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
         }
 
         // ---- store ----
         if (cw.fast) {
-          uint32_t ncm[4], ncp[4];
-          store_merge(nm, cw.sm, lane, va, carry, cm, next_fast, ncm);
+          store_merge(nm, cw.sm, lane, va, carry, next_fast, carry_m);
           store4(n0 + cw.xs + 8u * lane, vb);
-          store_merge(np, cw.sp, lane, vc, carry, cp, next_fast, ncp);
+          store_merge(np, cw.sp, lane, vc, carry, next_fast, carry_p);
           carry = next_fast;
-          if (carry)
-            for (int j = 0; j < 4; ++j) { cm[j] = ncm[j]; cp[j] = ncp[j]; }
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -583,26 +632,26 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
           }
           carry = false;
         }
-        // Drain a nearly full queue (at most kQueue - 64 entries stay queued,
-        // so the next chunk's 64 x 8 draws always fit the LDS queue plus the
-        // overflow area).  Deferred boundary elements are written first: the
-        // drain's final counts must land after every placeholder.
-        if (qn + on > kQueue - 64u) {
-          if (carry) {
-            flush_carry(nm, cw.sm, lane, cm);
-            flush_carry(np, cw.sp, lane, cp);
-            carry = false;
-          }
-          drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
-          qn = on = 0;
-        }
         cw = nw;
         cr = nr;
+        ++k;
+      } while (k < k1 && F <= kDrainAt);
+      // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
+      // fit.  Deferred boundary elements are written before a drain: the
+      // drain's final counts must land after every placeholder.  (The run's
+      // last chunk defers nothing.)
+      if (k < k1) {
+        if (carry) {
+          flush_carry(nm, cw.sm, lane, carry_m);
+          flush_carry(np, cw.sp, lane, carry_p);
+          carry = false;
+        }
+        drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
+        F = 0;
       }
     }
     i = se;
   }
-  if (qn + on) drain_queue(queue, qn, over, on, lane, sv, p, a.tab, a.err);
   // The last block of the launch advances t of every slot in the launch.
   // Every block has consumed its loads of t before it takes its ticket (the
   // values shaped its work), so nothing reads the new value during this
@@ -747,7 +796,7 @@ static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
 }
 
 uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
-  return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kQueueBytesPerWave;
+  return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kWaveLdsBytes;
 }
 
 // Blocks of up to 512 threads may use up to 256 VGPRs per lane.

@@ -243,11 +243,11 @@ struct mclg_server {
         std::copy(cl.thr.begin(), cl.thr.end(), h_pool.begin() + d.off);
       }
       // collision image for this job's density and velocity
-      LdsImage im = image_budget >= 64 ? build_image(*tab, j.rho, j.u0, image_budget) : LdsImage();
+      LdsImage im = build_image(*tab, j.rho, j.u0, image_budget);
       auto blob = im.blob();
       ImageDesc &idd = h_idesc[free_slot];
       idd.off = (uint64_t)free_slot * kImage;
-      idd.bytes = im.dir.empty() ? 0u : (uint32_t)blob.size();
+      idd.bytes = (uint32_t)blob.size();
       idd.dir_bytes = im.dir_bytes();
       idd.dim_a = im.dim_a;
       idd.dim_c = im.dim_c;
@@ -376,12 +376,12 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
     int dev = 0, v = 0;
     hipError_t e = hipGetDevice(&dev);
     if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    const uint32_t queues = (sv->sch.threads / 64u) * kQueueBytesPerWave;
+    const uint32_t queues = (sv->sch.threads / 64u) * kWaveLdsBytes;
     if (!e) sv->image_budget = std::min<uint32_t>(kImage, (uint32_t)std::max(0, v - 1024 - (int)queues)) / 16u * 16u;
     if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
     if (!e) sv->n_cu = (uint32_t)std::max(1, v);
     if (!e && sv->n_cu > 256) return MCLG_E_UNSUPPORTED;  // overflow region sized for 256 CUs
-    sv->lds_bytes = std::max<uint32_t>(16, sv->image_budget);
+    sv->lds_bytes = std::max<uint32_t>(64, sv->image_budget);  // the smallest image is 48 bytes
     if (!e) e = step_occupancy(sv->sch, sv->lds_bytes, sv->n_cu, sv->max_blocks);
     if (e) return sv->hip(e);
   }

@@ -434,74 +434,88 @@ inline uint16_t top16(uint64_t v) { return (uint16_t)std::min<uint64_t>(v >> 16,
 
 LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t budget) {
   LdsImage im;
-  if (tab.C == 0 || budget < 64) return im;
-  double f[3];
-  feq(rho, std::max(-1.0, std::min(1.0, u)), f);
-  const uint32_t kmax = std::min<uint32_t>(tab.n_max, 1023);
-  auto pa = pois_pmf(f[0], kmax), pb = pois_pmf(f[1], kmax), pc = pois_pmf(f[2], kmax);
-  // (a', c') pair masses
+  // the two special directory slots and the records they need: a "never"
+  // slot (nb records, also the target of absent pairs) and one "skip" record
+  auto image_bytes = [](uint32_t da, uint32_t dc, uint32_t np, uint32_t nb) {
+    return (uint64_t)((da * dc + 2) * 2 + 15) / 16 * 16 + ((uint64_t)(np + 1) * nb + 1) * 16;
+  };
+  uint32_t dim_a = 0, dim_c = 0, best_lo = 0, best_nb = 1, best_np = 0;
+  std::vector<double> pb;
   struct Pair { uint32_t a, c; double p; };
   std::vector<Pair> pairs;
-  for (uint32_t a = 0; a <= kmax; ++a)
-    for (uint32_t c = a; c <= kmax; ++c) {
-      double p = pa[a] * pc[c] + (a != c ? pa[c] * pc[a] : 0.0);
-      if (p > 1e-12) pairs.push_back({a, c, p});
+  if (tab.C != 0 && budget >= 256) {
+    double f[3];
+    feq(rho, std::max(-1.0, std::min(1.0, u)), f);
+    const uint32_t kmax = std::min<uint32_t>(tab.n_max, 1023);
+    auto pa = pois_pmf(f[0], kmax), pc = pois_pmf(f[2], kmax);
+    pb = pois_pmf(f[1], kmax);
+    // (a', c') pair masses
+    for (uint32_t a = 0; a <= kmax; ++a)
+      for (uint32_t c = a; c <= kmax; ++c) {
+        double p = pa[a] * pc[c] + (a != c ? pa[c] * pc[a] : 0.0);
+        if (p > 1e-12) pairs.push_back({a, c, p});
+      }
+    std::sort(pairs.begin(), pairs.end(), [](const Pair &x, const Pair &y) { return x.p > y.p; });
+    std::vector<double> pair_cum(pairs.size() + 1, 0.0);
+    for (size_t i = 0; i < pairs.size(); ++i) pair_cum[i + 1] = pair_cum[i] + pairs[i].p;
+    // b ranges: grow a central interval around the mode, keep the best split
+    uint32_t mode = (uint32_t)std::floor(f[1]);
+    if (mode > kmax) mode = kmax;
+    double best = -1.0;
+    uint32_t lo = mode, hi = mode;
+    double pbr = pb[mode];
+    for (;;) {
+      const uint32_t nb = hi - lo + 1;
+      // directory size is bounded by the pairs' extent; reserve it generously
+      const long room = (long)budget - 2048 - 16 * (long)(nb + 1);
+      const uint32_t np =
+          room > 0 ? (uint32_t)std::min<size_t>(pairs.size(), room / (16 * nb)) : 0;
+      if (np == 0) break;
+      const double cov = pbr * pair_cum[np];
+      if (cov > best) { best = cov; best_lo = lo; best_nb = nb; best_np = np; }
+      if (lo == 0 && hi == kmax) break;
+      const bool left = lo > 0 && (hi == kmax || pb[lo - 1] >= pb[hi + 1]);
+      if (left) { --lo; pbr += pb[lo]; } else { ++hi; pbr += pb[hi]; }
     }
-  std::sort(pairs.begin(), pairs.end(), [](const Pair &x, const Pair &y) { return x.p > y.p; });
-  std::vector<double> pair_cum(pairs.size() + 1, 0.0);
-  for (size_t i = 0; i < pairs.size(); ++i) pair_cum[i + 1] = pair_cum[i] + pairs[i].p;
-  // b ranges: grow a central interval around the mode, keep the best split
-  uint32_t mode = (uint32_t)std::floor(f[1]);
-  if (mode > kmax) mode = kmax;
-  double best = -1.0;
-  uint32_t best_lo = 0, best_nb = 0, best_np = 0;
-  uint32_t lo = mode, hi = mode;
-  double pbr = pb[mode];
-  for (;;) {
-    uint32_t nb = hi - lo + 1;
-    // directory size is bounded by the pairs' extent; reserve it generously
-    long room = (long)budget - 2048;
-    uint32_t np = room > 0 ? (uint32_t)std::min<size_t>(pairs.size(), room / (16 * nb)) : 0;
-    if (np == 0) break;
-    double cov = pbr * pair_cum[np];
-    if (cov > best) { best = cov; best_lo = lo; best_nb = nb; best_np = np; }
-    if (lo == 0 && hi == kmax) break;
-    bool left = lo > 0 && (hi == kmax || pb[lo - 1] >= pb[hi + 1]);
-    if (left) { --lo; pbr += pb[lo]; } else { ++hi; pbr += pb[hi]; }
-  }
-  if (best_np == 0) return im;
-  uint32_t dim_a = 0, dim_c = 0;
-  for (uint32_t i = 0; i < best_np; ++i) {
-    dim_a = std::max(dim_a, pairs[i].a + 1);
-    dim_c = std::max(dim_c, pairs[i].c + 1);
-  }
-  // shrink the pair count until directory + records fit the budget
-  while (best_np > 0 && (uint64_t)((dim_a * dim_c * 2 + 15) / 16 * 16) +
-                                (uint64_t)best_np * best_nb * 16 > budget) {
-    --best_np;
-    dim_a = dim_c = 0;
-    for (uint32_t i = 0; i < best_np; ++i) {
-      dim_a = std::max(dim_a, pairs[i].a + 1);
-      dim_c = std::max(dim_c, pairs[i].c + 1);
+    if (best_np == 0) best_nb = 1;
+    auto extent = [&](uint32_t np) {
+      dim_a = dim_c = 0;
+      for (uint32_t i = 0; i < np; ++i) {
+        dim_a = std::max(dim_a, pairs[i].a + 1);
+        dim_c = std::max(dim_c, pairs[i].c + 1);
+      }
+    };
+    extent(best_np);
+    // shrink the pair count until directory + records fit the budget
+    while (best_np > 0 && image_bytes(dim_a, dim_c, best_np, best_nb) > budget) extent(--best_np);
+    if (best_np == 0 || best_np + 1 >= 0xFFFF) {
+      best_np = 0;
+      best_nb = 1;
+      best_lo = 0;
+      dim_a = dim_c = 0;
     }
   }
-  if (best_np == 0 || best_np >= 0xFFFF) return im;
+  const uint32_t np = best_np, nb = best_nb;
   im.dim_a = dim_a;
   im.dim_c = dim_c;
   im.b_lo = best_lo;
-  im.nb = best_nb;
-  im.dir.assign((size_t)dim_a * dim_c, 0xFFFF);
-  im.records.assign((size_t)best_np * best_nb * 8, 0);
+  im.nb = nb;
+  im.dir.assign((size_t)dim_a * dim_c + 2, (uint16_t)np);  // absent pairs: never
+  im.dir[(size_t)dim_a * dim_c + 1] = (uint16_t)(np + 1);   // skip
+  im.records.assign(((size_t)(np + 1) * nb + 1) * 8, 0);
+  for (size_t k = 0; k < (size_t)nb; ++k) im.records[((size_t)np * nb + k) * 8 + 1] = 0xFFFF;
+  im.records[(size_t)(np + 1) * nb * 8 + 0] = 0x8000;
+  im.records[(size_t)(np + 1) * nb * 8 + 1] = 0xFFFF;
   double covered = 0.0;
-  for (uint32_t pi = 0; pi < best_np; ++pi) {
+  for (uint32_t pi = 0; pi < np; ++pi) {
     const Pair &pr = pairs[pi];
     im.dir[(size_t)pr.a * dim_c + pr.c] = (uint16_t)pi;
-    for (uint32_t bi = 0; bi < best_nb; ++bi) {
+    for (uint32_t bi = 0; bi < nb; ++bi) {
       const uint32_t b = best_lo + bi;
-      uint16_t *rec = &im.records[((size_t)pi * best_nb + bi) * 8];
+      uint16_t *rec = &im.records[((size_t)pi * nb + bi) * 8];
       const uint32_t N = pr.a + b + pr.c, absJ = pr.c - pr.a;
       if (N < 2 || N > tab.n_max) {  // never decided here
-        rec[0] = 0; rec[1] = 0xFFFF; rec[7] = 0;
+        rec[0] = 0; rec[1] = 0xFFFF;
         continue;
       }
       const uint32_t par = (N - absJ) & 1u;
@@ -514,12 +528,13 @@ LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t 
       // window start with the most mass
       long best_ks = 0;
       uint64_t best_w = 0;
-      long ks_hi = m > 6 ? (long)m - 6 : 0;
+      const long ks_hi = m > 6 ? (long)m - 6 : 0;
       for (long ks = 0; ks <= ks_hi; ++ks) {
-        uint64_t w = full_thr(thr, kf, q, ks + 5) - full_thr(thr, kf, q, ks - 1);
+        const uint64_t w = full_thr(thr, kf, q, ks + 5) - full_thr(thr, kf, q, ks - 1);
         if (ks == 0 || w > best_w) { best_w = w; best_ks = ks; }
       }
-      rec[0] = (uint16_t)best_ks;
+      // the kernel's move for the window's first state: (b >> 1) - k_s
+      rec[0] = (uint16_t)(int16_t)((long)(b >> 1) - best_ks);
       for (int j = 0; j < 7; ++j) rec[1 + j] = top16(full_thr(thr, kf, q, best_ks - 1 + j));
       covered += pr.p * pb[b] * (double)best_w / 4294967296.0;
     }

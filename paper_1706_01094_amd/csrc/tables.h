@@ -48,22 +48,29 @@ bool poisson_full(double mu, uint32_t &k_lo, std::vector<uint64_t> &thr);
 // results never depend on it).
 //
 // A row is addressed by (a', b, c') = (min(n_-1, n_+1), n_0, max(n_-1, n_+1)),
-// which fixes N, |J| and n0.  `dir[a' * dim_c + c']` is the index p of an
-// (a', c') pair or 0xFFFF; the record of (p, b) is records[p * nb + b - b_lo],
-// eight uint16: k_s, then the top 16 bits of the full-fiber thresholds
-// thr_{k_s - 1} .. thr_{k_s + 5} (thr_{-1} = 0, thr_{>= m - 1} = 2^32, clamped
-// to 0xFFFF).  With rh = r >> 16 the draw is decided in LDS when
-// T1 < rh < T7 and no inner T equals rh; then the outcome index is
-// k_s + #{inner T < rh}.  Otherwise (or when the row is absent) the exact
-// global row decides.
+// which fixes N, |J| and n0.  With np pairs in the image, `dir` holds
+// dim_a * dim_c + 2 entries: dir[a' * dim_c + c'] is the index p of an
+// (a', c') pair, or np for an absent pair; the two extra entries are the
+// "never" slot (np) and the "skip" slot (np + 1).  The record of (p, b) is
+// records[p * nb + b - b_lo]: eight uint16, (b >> 1) - k_s as int16, then the
+// top 16 bits of the full-fiber thresholds thr_{k_s - 1} .. thr_{k_s + 5}
+// (thr_{-1} = 0, thr_{>= m - 1} = 2^32, clamped to 0xFFFF).  With
+// rh = r >> 16 the draw is decided in LDS when T1 < rh < T7 and no inner T
+// equals rh; then the outcome index is k_s + #{inner T < rh}, i.e. the
+// site's n0 moves by -2 ((b >> 1) - k_s - #{inner T < rh}).  Records of the
+// never slot (and of rows the tables do not hold) have T1 = 0xFFFF and
+// decide nothing: the exact global row decides.  The one skip record,
+// records[(np + 1) * nb], is (0x8000, 0xFFFF, 0, ...) and marks a site that
+// does not collide.  Without room for any pair the image is just the
+// directory's two slots and these records (np = 0, nb = 1).
 struct LdsImage {
   uint32_t dim_a = 0, dim_c = 0, b_lo = 0, nb = 0;
-  std::vector<uint16_t> dir;      // dim_a * dim_c
+  std::vector<uint16_t> dir;      // dim_a * dim_c + 2
   std::vector<uint16_t> records;  // 8 per record
   double coverage = 0.0;          // expected fraction of site updates decided in LDS
   // serialised: dir padded to 16 bytes, then the records
   std::vector<uint8_t> blob() const;
-  uint32_t dir_bytes() const { return (uint32_t)((dim_a * dim_c * 2 + 15) / 16 * 16); }
+  uint32_t dir_bytes() const { return (uint32_t)(((dim_a * dim_c + 2) * 2 + 15) / 16 * 16); }
 };
 
 // Build the image for a lattice near the product-Poisson law at

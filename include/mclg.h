@@ -159,6 +159,12 @@ int mclg_check(mclg_ctx *ctx);
 int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t threads_per_block,
                       uint32_t lds_budget_bytes);
 
+/* Upper bound on the persistent grid of the step kernel (0 = as many blocks
+ * as fit on the device, the default).  A smaller grid gives each wave longer
+ * runs of chunks (and leaves CUs to other work); any value gives identical
+ * bits.  Drops captured graphs; synchronises the stream. */
+int mclg_set_grid_limit(mclg_ctx *ctx, uint32_t max_blocks);
+
 /* Expected fraction of site updates whose draw is decided from LDS (from the
  * product-Poisson law the images were built for) and the LDS bytes per block. */
 int mclg_lds_coverage(const mclg_ctx *ctx, double *expected_fraction, uint32_t *lds_bytes);

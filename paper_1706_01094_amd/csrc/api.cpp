@@ -113,6 +113,7 @@ struct mclg_ctx {
   std::vector<ImageDesc> img_desc;
   std::vector<uint8_t> img_pool;
   uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
+  uint32_t grid_limit = 0;  // 0: occupancy-derived grid
   double coverage = 0.0;                // expected LDS hit fraction (site-weighted)
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
@@ -176,7 +177,7 @@ struct mclg_ctx {
     a.image_pool = ws + lay.o_ipool;
     a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);
     a.lds_bytes = lds_bytes;
-    a.max_blocks = max_blocks;
+    a.max_blocks = grid_limit ? std::min(max_blocks, grid_limit) : max_blocks;
     return a;
   }
   // (Re)build the images for the current budget, upload them, and size the
@@ -526,6 +527,14 @@ int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t l
                                 hipMemcpyHostToDevice, c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
   if (!e) e = c->prepare_images();
+  return c->hip(e);
+}
+
+int mclg_set_grid_limit(mclg_ctx *c, uint32_t max_blocks) {
+  if (!c) return MCLG_E_INVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  c->grid_limit = max_blocks;
+  c->drop_graphs();
   return c->hip(e);
 }
 

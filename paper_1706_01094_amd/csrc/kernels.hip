@@ -39,6 +39,24 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
   }
   return c;
 }
+// Two Philox4x32-10 calls with the same key, interleaved round by round
+// (one key schedule, two independent multiply chains).
+__device__ __forceinline__ void philox10_x2(uint4 &c0, uint4 &c1, uint2 k) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    if (i) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+      asm volatile("" : "+s"(k.x), "+s"(k.y));
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0.x, q0 = (uint64_t)0xD2511F53u * c1.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c0.z, q1 = (uint64_t)0xCD9E8D57u * c1.z;
+    c0 = make_uint4((uint32_t)(p1 >> 32) ^ c0.y ^ k.x, (uint32_t)p1,
+                    (uint32_t)(p0 >> 32) ^ c0.w ^ k.y, (uint32_t)p0);
+    c1 = make_uint4((uint32_t)(q1 >> 32) ^ c1.y ^ k.x, (uint32_t)q1,
+                    (uint32_t)(q0 >> 32) ^ c1.w ^ k.y, (uint32_t)q0);
+  }
+}
 
 __device__ __forceinline__ uint32_t word_of(const uint4 &w, uint32_t i) {
   return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
@@ -105,12 +123,47 @@ __device__ __forceinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint3
   return b;
 }
 
+// Index of the first row of fiber (N, |J|) in the global tables, in closed
+// form: fibers are stored by N, then |J|, and fiber (N, j) holds
+// floor((N - j) / 2) + 1 rows, so with S(M) = M + 1 + floor(M^2 / 4) rows in
+// the fibers (M, 0..M) and T(K) = sum_{M <= K} floor(M^2 / 4), the base is
+// N (N + 1) / 2 + T(N - 1) + S(N) - S(N - j).  (Saves a dependent load.)
+__device__ __forceinline__ uint32_t fiber_base(uint32_t N, uint32_t absJ) {
+  auto S = [](uint32_t M) { return M + 1u + ((M * M) >> 2); };
+  uint32_t T = 0;
+  if (N >= 1u) {
+    const uint32_t K = N - 1u, i = K >> 1;
+    T = (K & 1u) ? i * (i + 1u) * (4u * i + 5u) / 6u : i * (i + 1u) * (4u * i - 1u) / 6u;
+  }
+  return ((N * (N + 1u)) >> 1) + T + S(N) - S(N - absJ);
+}
+
+// Number of entries <= r of an ascending array of n values: probe seven
+// evenly spaced pivots at once, then count the one bucket left (all its
+// loads at once) -- two rounds of independent loads for n <= 64.
+__device__ __forceinline__ uint32_t count_le_wide(const uint32_t *__restrict__ t, uint32_t n,
+                                                  uint32_t r) {
+  uint32_t lo = 0;
+  while (n > 8u) {
+    const uint32_t s = (n + 7u) >> 3;  // bucket width; pivots t[lo + j s - 1]
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t j = 1; j < 8; ++j)
+      c += (j * s <= n && t[lo + j * s - 1u] <= r) ? 1u : 0u;
+    lo += c * s;
+    n = min(s, n - c * s);
+  }
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < 8; ++j) c += (j < n && t[lo + j] <= r) ? 1u : 0u;
+  return lo + c;
+}
+
 // Exact row of the global tables: the number of thresholds <= r.
 __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
                                                    uint32_t b, uint32_t par, uint32_t r) {
-  const uint32_t base = tab.rowbase[(N * (N + 1u) >> 1) + absJ];
-  const uint2 d = tab.rowdesc[base + ((b - par) >> 1)];  // fiber states ascend in n0
-  return (d.y & 0xffffu) + count_le(tab.thr + d.x, (d.y >> 16) - 1u, r);
+  const uint2 d = tab.rowdesc[fiber_base(N, absJ) + ((b - par) >> 1)];  // states ascend in n0
+  return (d.y & 0xffffu) + count_le_wide(tab.thr + d.x, (d.y >> 16) - 1u, r);
 }
 
 // The slot's collision image in LDS: directory of (min(a,c), max(a,c)) pairs,
@@ -170,6 +223,36 @@ __device__ __forceinline__ void load4(const uint16_t *p, uint32_t (&v)[4]) {
 __device__ __forceinline__ void store4(uint16_t *p, const uint32_t (&v)[4]) {
   *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
 }
+// A slot's three arrays through one buffer resource: byte address =
+// voff (per lane) + soff (wave-uniform, a scalar register).  Offsets stay
+// 32-bit, and the per-lane part of a chunk's vector accesses is the same
+// 16 * lane for every window.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+__device__ __forceinline__ void bload4(Rsrc r, uint32_t voff, uint32_t soff, uint32_t (&v)[4]) {
+  const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+}
+__device__ __forceinline__ void bstore4(Rsrc r, uint32_t voff, uint32_t soff,
+                                        const uint32_t (&v)[4]) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 q = {v[0], v[1], v[2], v[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ uint32_t bload2(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, (int)soff, 0);
+}
+// Orders this wave's LDS accesses on either side: a vector one lane writes
+// and another lane reads passes through LDS, and a compiler reasoning per
+// thread may otherwise swap a read and a write made under exclusive lane
+// conditions.  No instruction is emitted.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -201,8 +284,14 @@ __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepPara
 
 // Where a slot's three arrays are and how they are shifted at step t.
 struct SlotView {
-  uint16_t *nm, *n0, *np;
+  uint32_t lo, hi;  // address of the slot's n_-1 array; n_0 and n_+1 follow
+  uint32_t ab;      // bytes per array
   uint32_t L, tm, t, rid;
+  // the buffer resource, rebuilt at each use from wave-uniform scalars
+  __device__ __forceinline__ Rsrc rs() const {
+    return __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), 0, (int)(3u * ab), kRsrcWord3);
+  }
 };
 
 // Two 16-bit lanes of a 32-bit register.
@@ -231,15 +320,14 @@ struct SiteLook {
 };
 
 template <int K>
-__device__ __forceinline__ void site_dir(SiteLook &s, uint32_t x8, uint32_t L, bool full,
+__device__ __forceinline__ void site_dir(SiteLook &s,
                                          const uint32_t (&va)[4], const uint32_t (&vb)[4],
                                          const uint32_t (&vc)[4], const LdsView &lv,
                                          const StepParams &p, bool &range_err) {
   const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
   const uint32_t N = ea + eb + ec;
-  const bool live = full | (x8 + K < L);
-  range_err |= live & (N > 65535u);
-  const bool collide = live & (N >= 2u) & (N <= 65535u) & (p.C != 0);
+  range_err |= N > 65535u;
+  const bool collide = (N >= 2u) & (N <= 65535u) & (p.C != 0);
   const uint32_t lo = min(ea, ec), hi = max(ea, ec), bi = eb - lv.b_lo;
   const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb);
   const uint32_t slot = inbox ? __umul24(lo, lv.dim_c) + hi : lv.never;
@@ -281,16 +369,16 @@ __device__ __forceinline__ void apply_pair(uint32_t (&va)[4], uint32_t (&vb)[4],
 // Sites K0..K0+3 of the lane (K0 = 0 or 4): directory reads, record reads,
 // decisions, updates.
 template <int K0>
-__device__ __forceinline__ void decide_four(uint32_t x8, uint32_t L, bool full, const uint4 &w,
+__device__ __forceinline__ void decide_four(const uint4 &w,
                                             uint32_t (&va)[4], uint32_t (&vb)[4],
                                             uint32_t (&vc)[4], const LdsView &lv,
                                             const StepParams &p, uint32_t &miss,
                                             bool &range_err) {
   SiteLook s0, s1, s2, s3;
-  site_dir<K0 + 0>(s0, x8, L, full, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 1>(s1, x8, L, full, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 2>(s2, x8, L, full, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 3>(s3, x8, L, full, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 0>(s0, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 1>(s1, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 2>(s2, va, vb, vc, lv, p, range_err);
+  site_dir<K0 + 3>(s3, va, vb, vc, lv, p, range_err);
   site_rec(s0, lv);
   site_rec(s1, lv);
   site_rec(s2, lv);
@@ -366,9 +454,9 @@ __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *ove
     uint32_t pm = x + v.tm;
     pm -= (pm >= v.L) ? v.L : 0u;
     const uint32_t pp = x >= v.tm ? x - v.tm : x + v.L - v.tm;
-    v.nm[pm] = (uint16_t)((N - (int32_t)bn - J) >> 1);
-    v.n0[x] = (uint16_t)bn;
-    v.np[pp] = (uint16_t)((N - (int32_t)bn + J) >> 1);
+    bstore2(v.rs(), 2u * pm, 0u, (uint32_t)((N - (int32_t)bn - J) >> 1));
+    bstore2(v.rs(), 2u * x, v.ab, bn);
+    bstore2(v.rs(), 2u * pp, 2u * v.ab, (uint32_t)((N - (int32_t)bn + J) >> 1));
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -393,31 +481,85 @@ __device__ __forceinline__ Win locate(uint32_t xs, const SlotView &v) {
   w.fast = (uint32_t)((xs + 512u <= v.L) & (w.sm + 512u <= v.L) & (w.sp + 512u <= v.L));
   return w;
 }
-// The lane-aligned vectors of a fast chunk (element 8 * lane of the aligned
-// base of each window).
+// The vectors a fast chunk loads.  A window starting at s = A + b (A a
+// multiple of 8) covers the 65 aligned vectors A, A + 8, ..., A + 512 when
+// b != 0: lane i loads A + 8 (i + 1), and the first vector A is the one the
+// previous chunk's lane 63 loaded (or an explicit load at the start of a run).
+// With b = 0 lane i loads A + 8 i.  n_0 windows are always aligned.
 struct Raw {
   uint32_t m[4], z[4], p[4];
 };
 __device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint32_t lane,
                                           Raw &r) {
-  load4(v.nm + (w.sm & ~7u) + 8u * lane, r.m);
-  load4(v.n0 + w.xs + 8u * lane, r.z);
-  load4(v.np + (w.sp & ~7u) + 8u * lane, r.p);
+  const uint32_t vo = 16u * lane;
+  bload4(v.rs(), vo, 2u * (w.sm & ~7u) + ((w.sm & 7u) ? 16u : 0u), r.m);
+  bload4(v.rs(), vo, v.ab + 2u * w.xs, r.z);
+  bload4(v.rs(), vo, 2u * v.ab + 2u * (w.sp & ~7u) + ((w.sp & 7u) ? 16u : 0u), r.p);
 }
-// Realign one misaligned window: lane i needs elements [b, b + 8) of its
-// vector followed by lane i+1's; lane 63 takes the vector after the window
-// (`ext`, wave-uniform).
-__device__ __forceinline__ void realign(const uint32_t (&raw)[4], const uint32_t (&ext)[4],
-                                        uint32_t b, uint32_t lane, uint32_t (&out)[4]) {
+// Make the loaded vectors available at this point (waits for their loads).
+__device__ __forceinline__ void touch_raw(Raw &r) {
+  for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(r.m[j]), "+v"(r.z[j]), "+v"(r.p[j]));
+}
+// Realign one window: with b != 0 lane i needs elements [b, b + 8) of the
+// vector before its own (lane i - 1's; for lane 0 the vector `first`, read
+// from the wave's LDS slot `ps` when `have_prev`, else loaded from `arr`)
+// followed by its own.  Lane 63 then leaves its own vector in the slot: it
+// is the first vector of the next chunk when that chunk is contiguous.
+__device__ __forceinline__ void realign(Rsrc rs, uint32_t base, uint32_t s,
+                                        const uint32_t (&own)[4], bool have_prev, uint4 *ps,
+                                        uint32_t lane, uint32_t (&out)[4]) {
+  const uint32_t b = s & 7u;
   if (b == 0u) {
-    for (int j = 0; j < 4; ++j) out[j] = raw[j];
+    for (int j = 0; j < 4; ++j) out[j] = own[j];
     return;
   }
-  uint32_t nx[4];
-  shfl_down4(raw, nx);
-  if (lane == 63u)
-    for (int j = 0; j < 4; ++j) nx[j] = ext[j];
-  extract8(raw, nx, b, out);
+  uint32_t pv[4];
+  shfl_up4(own, pv);
+  wave_lds_order();
+  if (lane == 0u) {
+    if (have_prev) {
+      const uint4 c = *ps;
+      pv[0] = c.x; pv[1] = c.y; pv[2] = c.z; pv[3] = c.w;
+    } else {
+      bload4(rs, 0u, base + 2u * (s - b), pv);
+    }
+  }
+  wave_lds_order();
+  if (lane == 63u) *ps = make_uint4(own[0], own[1], own[2], own[3]);
+  wave_lds_order();
+  extract8(pv, own, b, out);
+}
+// The chunk's three windows as eight consecutive sites per lane: realigned
+// vectors of a fast chunk, element by element for a chunk whose windows wrap
+// around the end of the lattice (or pass it).  Sites past the end read as
+// empty (N = 0): they do not collide and are never stored.
+__device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, bool contiguous,
+                                              uint4 *prev_m, uint4 *prev_p, const SlotView &v,
+                                              uint32_t lane, uint32_t (&va)[4],
+                                              uint32_t (&vb)[4], uint32_t (&vc)[4]) {
+  if (w.fast) {
+    realign(v.rs(), 0u, w.sm, r.m, contiguous, prev_m, lane, va);
+    for (int j = 0; j < 4; ++j) vb[j] = r.z[j];
+    realign(v.rs(), 2u * v.ab, w.sp, r.p, contiguous, prev_p, lane, vc);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t x = w.xs + 8u * lane + e;
+      uint32_t ea = 0, eb = 0, ec = 0;
+      if (x < v.L) {
+        uint32_t pm = x + v.tm;
+        pm -= (pm >= v.L) ? v.L : 0u;
+        const uint32_t pp = x >= v.tm ? x - v.tm : x + v.L - v.tm;
+        ea = bload2(v.rs(), 2u * pm, 0u);
+        eb = bload2(v.rs(), 2u * x, v.ab);
+        ec = bload2(v.rs(), 2u * pp, 2u * v.ab);
+      }
+      set16(va, e, ea); set16(vb, e, eb); set16(vc, e, ec);
+    }
+  }
+  // complete here, so that no load of this chunk is still counted when the
+  // next chunk's loads are issued
+  for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(va[j]), "+v"(vb[j]), "+v"(vc[j]));
 }
 // Store one misaligned window back to its aligned vectors.  Lanes 1..63
 // write whole vectors.  Lane 0's vector starts with the previous chunk's last
@@ -427,27 +569,29 @@ __device__ __forceinline__ void realign(const uint32_t (&raw)[4], const uint32_t
 // to the carry slot for the next chunk's lane 0, else lane 63 writes them.
 // LDS operations of a wave complete in order, so the slot is read before it
 // is rewritten.
-__device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t lane,
+__device__ __forceinline__ void store_merge(Rsrc rs, uint32_t base, uint32_t s, uint32_t lane,
                                             const uint32_t (&o)[4], bool have_carry,
                                             bool defer, uint4 *cs) {
   const uint32_t b = s & 7u, A = s - b;
   if (b == 0u) {
-    store4(arr + A + 8u * lane, o);
+    bstore4(rs, 16u * lane, base + 2u * A, o);
     return;
   }
   uint32_t prev[4], al[4];
   shfl_up4(o, prev);
+  wave_lds_order();
   if (lane == 0u && have_carry) {
     const uint4 c = *cs;
     prev[0] = c.x; prev[1] = c.y; prev[2] = c.z; prev[3] = c.w;
   }
+  wave_lds_order();
   extract8(prev, o, 8u - b, al);
   if (lane != 0u || have_carry) {
-    store4(arr + A + 8u * lane, al);
+    bstore4(rs, 16u * lane, base + 2u * A, al);
   } else {
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < 8u - b) arr[s + e] = (uint16_t)get16(o, e);
+      if ((uint32_t)e < 8u - b) bstore2(rs, 2u * e, base + 2u * s, get16(o, e));
   }
   if (lane == 63u) {
     if (defer) {
@@ -455,22 +599,24 @@ __device__ __forceinline__ void store_merge(uint16_t *arr, uint32_t s, uint32_t 
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        if ((uint32_t)e < b) arr[A + 512u + e] = (uint16_t)get16(o, 8 - (int)b + e);
+        if ((uint32_t)e < b) bstore2(rs, 2u * e, base + 2u * (A + 512u), get16(o, 8 - (int)b + e));
     }
   }
+  wave_lds_order();
 }
 // Write the deferred boundary elements of the chunk before the window at s
 // (elements 8 - b .. 7 of the carried vector) to their places, the first b
 // elements of the aligned vector that holds s.
-__device__ __forceinline__ void flush_carry(uint16_t *arr, uint32_t s, uint32_t lane,
+__device__ __forceinline__ void flush_carry(Rsrc rs, uint32_t base, uint32_t s, uint32_t lane,
                                             const uint4 *cs) {
   const uint32_t b = s & 7u, A = s - b;
+  wave_lds_order();
   if (lane == 0u && b != 0u) {
     const uint4 c4 = *cs;
     const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < b) arr[A + e] = (uint16_t)get16(c, 8 - (int)b + e);
+      if ((uint32_t)e < b) bstore2(rs, 2u * e, base + 2u * A, get16(c, 8 - (int)b + e));
   }
 }
 
@@ -497,6 +643,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
   uint4 *const carry_m = queue + kQueue;  // deferred boundary vectors of n_-1, n_+1
   uint4 *const carry_p = carry_m + 1;
+  uint4 *const prev_m = carry_m + 2;      // first vectors of the next windows
+  uint4 *const prev_p = carry_m + 3;
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
@@ -504,7 +652,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   const uint32_t ce = min(a.n_tiles, cb + per);
   uint32_t cur = 0xFFFFFFFFu;
   SlotView sv;
-  sv.nm = sv.n0 = sv.np = nullptr;
+  sv.lo = sv.hi = 0;
+  sv.ab = 0;
   sv.L = 1; sv.tm = sv.t = sv.rid = 0;
   LdsView lv;
   lv.dir = reinterpret_cast<const uint16_t *>(lds);
@@ -539,84 +688,65 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       sv.L = sl.L;
       sv.tm = p.no_stream ? 0u : sv.t % sl.L;
       sv.rid = sl.rid;
-      sv.nm = a.state + sl.off;
-      sv.n0 = sv.nm + sl.stride;
-      sv.np = sv.n0 + sl.stride;
+      const uint64_t base = reinterpret_cast<uint64_t>(a.state + sl.off);
+      sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+      sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+      sv.ab = __builtin_amdgcn_readfirstlane(2u * sl.stride);
     }
     // this wave's run of the segment's chunks
     const uint32_t n = se - i;
     const uint32_t k1 = i + ((wave + 1) * n) / nwaves;
     uint32_t k = i + (wave * n) / nwaves;
-    const uint32_t L = sv.L, tm = sv.tm, t = sv.t;
-    uint16_t *const nm = sv.nm;
-    uint16_t *const n0 = sv.n0;
-    uint16_t *const np = sv.np;
+    const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
+    const Rsrc rs = sv.rs();
+    const uint32_t ab = sv.ab;
     Win cw = locate(t0.x0 + (k - i) * 512u, sv);
-    Raw cr;
-    if (k < k1 && cw.fast) issue_raw(cw, sv, lane, cr);
+    uint32_t va[4], vb[4], vc[4];
+    if (k < k1) {
+      Raw cr;
+      if (cw.fast) issue_raw(cw, sv, lane, cr);
+      chunk_windows(cw, cr, false, prev_m, prev_p, sv, lane, va, vb, vc);
+    }
     bool carry = false;
     while (k < k1) {
       do {
+        // The next chunk's loads go out first; they are realigned only after
+        // this chunk is decided and stored.
+        const bool has_next = k + 1 < k1;
         Win nw = cw;
         Raw nr;
-        bool next_fast = false;
-        if (k + 1 < k1) {
+        if (has_next) {
           nw = locate(cw.xs + 512u, sv);
           if (nw.fast) issue_raw(nw, sv, lane, nr);
-          // contiguous in all three arrays: neither shifted window wraps to 0
-          next_fast = ((nw.fast & cw.fast) != 0u) & (nw.sm == cw.sm + 512u) &
-                      (nw.sp == cw.sp + 512u);
         }
-        // ---- the chunk's three windows ----
-        uint32_t va[4], vb[4], vc[4];
-        if (cw.fast) {
-          const uint32_t bm = cw.sm & 7u, bp = cw.sp & 7u;
-          uint32_t em[4], ep[4];
-          if (next_fast) {
-            for (int j = 0; j < 4; ++j) em[j] = __builtin_amdgcn_readlane(nr.m[j], 0);
-            for (int j = 0; j < 4; ++j) ep[j] = __builtin_amdgcn_readlane(nr.p[j], 0);
-          } else {
-            if (bm) load4(nm + (cw.sm & ~7u) + 512u, em);
-            if (bp) load4(np + (cw.sp & ~7u) + 512u, ep);
-          }
-          realign(cr.m, em, bm, lane, va);
-          for (int j = 0; j < 4; ++j) vb[j] = cr.z[j];
-          realign(cr.p, ep, bp, lane, vc);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const uint32_t x = cw.xs + 8u * lane + e;
-            uint32_t ea = 0, eb = 0, ec = 0;
-            if (x < L) {
-              uint32_t pm = x + tm;
-              pm -= (pm >= L) ? L : 0u;
-              const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-              ea = nm[pm]; eb = n0[x]; ec = np[pp];
-            }
-            set16(va, e, ea); set16(vb, e, eb); set16(vc, e, ec);
-          }
-        }
+        // contiguous in all three arrays: neither shifted window wraps to 0
+        const bool contiguous = has_next & ((nw.fast & cw.fast) != 0u) &
+                                (nw.sm == cw.sm + 512u) & (nw.sp == cw.sp + 512u);
 
         // ---- collide: LDS image first, the rest into the wave's queue ----
         {
           const uint32_t x8 = cw.xs + 8u * lane;
-          const uint4 w0 = philox10(make_uint4(x8 >> 2, t, sv.rid, 0u), key);
-          const uint4 w1 = philox10(make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u), key);
-          const bool full = cw.fast != 0u;
+          uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
+          uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
+          philox10_x2(w0, w1, key);
           uint32_t miss = 0;
           bool range_err = false;
-          decide_four<0>(x8, L, full, w0, va, vb, vc, lv, p, miss, range_err);
-          decide_four<4>(x8, L, full, w1, va, vb, vc, lv, p, miss, range_err);
+          decide_four<0>(w0, va, vb, vc, lv, p, miss, range_err);
+          decide_four<4>(w1, va, vb, vc, lv, p, miss, range_err);
           if (range_err) atomicOr(a.err, kErrOverflow);
           if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
         }
 
+        // The next chunk's vectors have had the whole decision to arrive;
+        // take them now, before this chunk's stores are queued behind them
+        // (the wait counter is in order).
+        if (has_next && nw.fast) touch_raw(nr);
+
         // ---- store ----
         if (cw.fast) {
-          store_merge(nm, cw.sm, lane, va, carry, next_fast, carry_m);
-          store4(n0 + cw.xs + 8u * lane, vb);
-          store_merge(np, cw.sp, lane, vc, carry, next_fast, carry_p);
-          carry = next_fast;
+          store_merge(rs, 0u, cw.sm, lane, va, carry, contiguous, carry_m);
+          bstore4(rs, 16u * lane, ab + 2u * cw.xs, vb);
+          store_merge(rs, 2u * ab, cw.sp, lane, vc, carry, contiguous, carry_p);
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -625,15 +755,16 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
               uint32_t pm = x + tm;
               pm -= (pm >= L) ? L : 0u;
               const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-              nm[pm] = (uint16_t)get16(va, e);
-              n0[x] = (uint16_t)get16(vb, e);
-              np[pp] = (uint16_t)get16(vc, e);
+              bstore2(rs, 2u * pm, 0u, get16(va, e));
+              bstore2(rs, 2u * x, ab, get16(vb, e));
+              bstore2(rs, 2u * pp, 2u * ab, get16(vc, e));
             }
           }
-          carry = false;
         }
+        carry = contiguous;
+        // ---- the next chunk's windows ----
+        if (has_next) chunk_windows(nw, nr, contiguous, prev_m, prev_p, sv, lane, va, vb, vc);
         cw = nw;
-        cr = nr;
         ++k;
       } while (k < k1 && F <= kDrainAt);
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
@@ -642,8 +773,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       // last chunk defers nothing.)
       if (k < k1) {
         if (carry) {
-          flush_carry(nm, cw.sm, lane, carry_m);
-          flush_carry(np, cw.sp, lane, carry_p);
+          flush_carry(rs, 0u, cw.sm, lane, carry_m);
+          flush_carry(rs, 2u * ab, cw.sp, lane, carry_p);
           carry = false;
         }
         drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);

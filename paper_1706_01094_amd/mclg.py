@@ -84,6 +84,7 @@ _SIGS = {
     "mclg_get_counts": [vp, u32, P(ct.c_uint16)],
     "mclg_check": [vp],
     "mclg_set_schedule": [vp, u32, u32, u32],
+    "mclg_set_grid_limit": [vp, u32],
     "mclg_lds_coverage": [vp, P(dbl), P(u32)],
     "mclg_destroy": [vp],
     "mclg_strerror": [ct.c_int],
@@ -189,6 +190,10 @@ def mclg_set_schedule(ctx: int, groups: int, threads: int, lds_budget: int = 96 
     _check(lib().mclg_set_schedule(ctx, groups, threads, lds_budget), "mclg_set_schedule")
 
 
+def mclg_set_grid_limit(ctx: int, max_blocks: int):
+    _check(lib().mclg_set_grid_limit(ctx, max_blocks), "mclg_set_grid_limit")
+
+
 def mclg_lds_coverage(ctx: int):
     f, b = dbl(0), u32(0)
     _check(lib().mclg_lds_coverage(ctx, ct.byref(f), ct.byref(b)), "mclg_lds_coverage")
@@ -285,6 +290,9 @@ class Lattice:
 
     def set_schedule(self, groups: int, threads: int, lds_budget: int = 96 * 1024):
         mclg_set_schedule(self.ctx, groups, threads, lds_budget)
+
+    def set_grid_limit(self, max_blocks: int):
+        mclg_set_grid_limit(self.ctx, max_blocks)
 
     def lds_coverage(self):
         return mclg_lds_coverage(self.ctx)

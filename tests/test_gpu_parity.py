@@ -83,6 +83,23 @@ def test_ragged_tiles_and_schedules(groups, threads, lds):
         same(g, o)
 
 
+@pytest.mark.parametrize("threads,blocks,lds", [(64, 1, 112 << 10), (256, 2, 96 << 10),
+                                                (1024, 1, 112 << 10), (512, 3, 0)])
+def test_long_runs_per_wave(threads, blocks, lds):
+    """A capped grid gives each wave long runs of contiguous chunks: the
+    boundary vectors passed from chunk to chunk, drains between chunks and the
+    chunks that wrap around the lattice end, over shifts t = 0..23 (every
+    misalignment of the shifted windows)."""
+    L = 3 * 2 ** 14 + 37
+    g, o = pair(L, 31, rho=30.0, u0=0.1)
+    g.set_schedule(1, threads, lds)
+    g.set_grid_limit(blocks)
+    for _ in range(8):
+        g.step(3)
+        o.step(3)
+        same(g, o)
+
+
 @pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7, 129])
 def test_tiny_lattices(L):
     counts = synth.random_counts(L, seed=L)

@@ -210,9 +210,6 @@ __device__ __forceinline__ void extract8(const uint32_t (&lo)[4], const uint32_t
       for (int j = 0; j < 4; ++j) out[j] = hi[j];
   }
 }
-__device__ __forceinline__ void shfl_down4(const uint32_t (&v)[4], uint32_t (&o)[4]) {
-  for (int j = 0; j < 4; ++j) o[j] = __shfl_down(v[j], 1u);
-}
 __device__ __forceinline__ void shfl_up4(const uint32_t (&v)[4], uint32_t (&o)[4]) {
   for (int j = 0; j < 4; ++j) o[j] = __shfl_up(v[j], 1u);
 }
@@ -366,29 +363,40 @@ __device__ __forceinline__ void apply_pair(uint32_t (&va)[4], uint32_t (&vb)[4],
   vb[J] = pk_sub16(vb[J], pk_add16(dp, dp));
 }
 
-// Sites K0..K0+3 of the lane (K0 = 0 or 4): directory reads, record reads,
-// decisions, updates.
-template <int K0>
-__device__ __forceinline__ void decide_four(const uint4 &w,
-                                            uint32_t (&va)[4], uint32_t (&vb)[4],
-                                            uint32_t (&vc)[4], const LdsView &lv,
-                                            const StepParams &p, uint32_t &miss,
-                                            bool &range_err) {
-  SiteLook s0, s1, s2, s3;
-  site_dir<K0 + 0>(s0, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 1>(s1, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 2>(s2, va, vb, vc, lv, p, range_err);
-  site_dir<K0 + 3>(s3, va, vb, vc, lv, p, range_err);
+// All eight sites of the lane: directory reads of all eight first, the
+// Philox draws while they are in flight, then record reads, decisions and
+// updates.
+__device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
+                                             uint32_t (&va)[4], uint32_t (&vb)[4],
+                                             uint32_t (&vc)[4], const LdsView &lv,
+                                             const StepParams &p, uint32_t &miss,
+                                             bool &range_err) {
+  SiteLook s0, s1, s2, s3, s4, s5, s6, s7;
+  site_dir<0>(s0, va, vb, vc, lv, p, range_err);
+  site_dir<1>(s1, va, vb, vc, lv, p, range_err);
+  site_dir<2>(s2, va, vb, vc, lv, p, range_err);
+  site_dir<3>(s3, va, vb, vc, lv, p, range_err);
+  site_dir<4>(s4, va, vb, vc, lv, p, range_err);
+  site_dir<5>(s5, va, vb, vc, lv, p, range_err);
+  site_dir<6>(s6, va, vb, vc, lv, p, range_err);
+  site_dir<7>(s7, va, vb, vc, lv, p, range_err);
+  philox10_x2(w0, w1, key);
   site_rec(s0, lv);
   site_rec(s1, lv);
   site_rec(s2, lv);
   site_rec(s3, lv);
-  const int32_t d0 = site_finish<K0 + 0>(s0, w.x, miss);
-  const int32_t d1 = site_finish<K0 + 1>(s1, w.y, miss);
-  apply_pair<K0 / 2>(va, vb, vc, d0, d1);
-  const int32_t d2 = site_finish<K0 + 2>(s2, w.z, miss);
-  const int32_t d3 = site_finish<K0 + 3>(s3, w.w, miss);
-  apply_pair<K0 / 2 + 1>(va, vb, vc, d2, d3);
+  site_rec(s4, lv);
+  site_rec(s5, lv);
+  site_rec(s6, lv);
+  site_rec(s7, lv);
+  int32_t d0 = site_finish<0>(s0, w0.x, miss), d1 = site_finish<1>(s1, w0.y, miss);
+  apply_pair<0>(va, vb, vc, d0, d1);
+  d0 = site_finish<2>(s2, w0.z, miss), d1 = site_finish<3>(s3, w0.w, miss);
+  apply_pair<1>(va, vb, vc, d0, d1);
+  d0 = site_finish<4>(s4, w1.x, miss), d1 = site_finish<5>(s5, w1.y, miss);
+  apply_pair<2>(va, vb, vc, d0, d1);
+  d0 = site_finish<6>(s6, w1.z, miss), d1 = site_finish<7>(s7, w1.w, miss);
+  apply_pair<3>(va, vb, vc, d0, d1);
 }
 
 // The wave's queue of undecided draws: a virtual array of kQueue entries in
@@ -495,10 +503,6 @@ __device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint3
   bload4(v.rs(), vo, 2u * (w.sm & ~7u) + ((w.sm & 7u) ? 16u : 0u), r.m);
   bload4(v.rs(), vo, v.ab + 2u * w.xs, r.z);
   bload4(v.rs(), vo, 2u * v.ab + 2u * (w.sp & ~7u) + ((w.sp & 7u) ? 16u : 0u), r.p);
-}
-// Make the loaded vectors available at this point (waits for their loads).
-__device__ __forceinline__ void touch_raw(Raw &r) {
-  for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(r.m[j]), "+v"(r.z[j]), "+v"(r.p[j]));
 }
 // Realign one window: with b != 0 lane i needs elements [b, b + 8) of the
 // vector before its own (lane i - 1's; for lane 0 the vector `first`, read
@@ -674,8 +678,24 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       cur = t0.slot;
       const ImageDesc im = a.images[cur];
       __syncthreads();  // previous image no longer in use
+      // eight independent 16-byte loads per thread per round, then the stores
+      // (indices clamped into the image; the stores past its end are skipped)
       const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
-      for (uint32_t k = threadIdx.x; k < im.bytes / 16u; k += blockDim.x) lds[k] = src[k];
+      const uint32_t n16 = im.bytes / 16u, bd = blockDim.x, last = n16 - 1u;
+      for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += 8u * bd) {
+        const uint4 v0 = src[min(b0, last)], v1 = src[min(b0 + bd, last)],
+                    v2 = src[min(b0 + 2u * bd, last)], v3 = src[min(b0 + 3u * bd, last)],
+                    v4 = src[min(b0 + 4u * bd, last)], v5 = src[min(b0 + 5u * bd, last)],
+                    v6 = src[min(b0 + 6u * bd, last)], v7 = src[min(b0 + 7u * bd, last)];
+        lds[b0] = v0;
+        if (b0 + bd < n16) lds[b0 + bd] = v1;
+        if (b0 + 2u * bd < n16) lds[b0 + 2u * bd] = v2;
+        if (b0 + 3u * bd < n16) lds[b0 + 3u * bd] = v3;
+        if (b0 + 4u * bd < n16) lds[b0 + 4u * bd] = v4;
+        if (b0 + 5u * bd < n16) lds[b0 + 5u * bd] = v5;
+        if (b0 + 6u * bd < n16) lds[b0 + 6u * bd] = v6;
+        if (b0 + 7u * bd < n16) lds[b0 + 7u * bd] = v7;
+      }
       __syncthreads();
       lv.dim_a = im.dim_a;
       lv.dim_c = im.dim_c;
@@ -728,19 +748,13 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
           const uint32_t x8 = cw.xs + 8u * lane;
           uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
           uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
-          philox10_x2(w0, w1, key);
           uint32_t miss = 0;
           bool range_err = false;
-          decide_four<0>(w0, va, vb, vc, lv, p, miss, range_err);
-          decide_four<4>(w1, va, vb, vc, lv, p, miss, range_err);
+          decide_eight(w0, w1, key, va, vb, vc, lv, p, miss, range_err);
           if (range_err) atomicOr(a.err, kErrOverflow);
           if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
         }
 
-        // The next chunk's vectors have had the whole decision to arrive;
-        // take them now, before this chunk's stores are queued behind them
-        // (the wait counter is in order).
-        if (has_next && nw.fast) touch_raw(nr);
 
         // ---- store ----
         if (cw.fast) {

@@ -99,8 +99,51 @@ def run_plain(args, torch, M):
     rc = lat.check()
     if rc != 0:
         raise SystemExit(f"device error {rc}")
+    run_plain.stats = plain_statistics(lat, args.stat_logs)
     lat.close()
     return L, gpu_ms, wall
+
+
+def plain_statistics(lat, logs: int) -> dict:
+    """After the timed steps: per-velocity mean and variance/mean of the
+    occupation numbers every 100 steps (exact int64 sums on the device), the
+    check that the state stays Poisson distributed around f^eq."""
+    out = {"every": 100, "t": [], "mean": [], "var_over_mean": []}
+    for _ in range(logs):
+        lat.step(100)
+        m = lat.moments()[0]
+        n = float(m["sites"])
+        mean = [m["sum_n"][i] / n for i in range(3)]
+        var = [m["sum_n2"][i] / n - mean[i] ** 2 for i in range(3)]
+        out["t"].append(int(m["t"]))
+        out["mean"].append([round(v, 5) for v in mean])
+        out["var_over_mean"].append([round(var[i] / mean[i], 5) for i in range(3)])
+    return out
+
+
+def run_probe(args, torch, M):
+    """Roofline probe: the headline workload at L = 2^27 (768 MiB of state,
+    larger than the 256 MB Infinity Cache), so the state streams from HBM."""
+    import synth
+    w = synth.PLAIN_LARGE
+    L = 1 << 27
+    lat = M.Lattice(L, w["seed"], C=10, lam=(1, 1), n_max=255, rho=w["rho"], u0=w["u0"])
+    lat.step(5)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, lat.stream)
+    e0.record(lat.stream)
+    lat.step(args.probe_steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.probe_steps
+    rc = lat.check()
+    lat.close()
+    if rc != 0:
+        raise SystemExit(f"device error {rc} in the roofline probe")
+    return {"workload": "d1q3_L128M_rho50_u0.1", "L": L, "steps": args.probe_steps,
+            "ms_per_step": ms, "site_updates_per_s": L / (ms / 1e3),
+            "achieved_GBps": BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9,
+            "frac": BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
 def _events(torch, stream):
@@ -270,6 +313,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--batched-warmup", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--probe-steps", type=int, default=200)
+    ap.add_argument("--stat-logs", type=int, default=10)
     ap.add_argument("--serve-window", type=float, default=2.0)
     ap.add_argument("--serve-limit", type=float, default=60.0)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -317,9 +362,12 @@ def main():
                    "schedule": args.schedule or "default", **getattr(run_plain, "lds", {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "statistics": getattr(run_plain, "stats", None),
     }
     if not args.no_extra:
         extra = {}
+        extra["roofline_probe"] = run_probe(args, torch, M)
+        torch.cuda.empty_cache()
         extra["batched"] = run_batched(args, torch, M)
         extra["density_wave"] = run_wave(args, torch, M)
         torch.cuda.empty_cache()

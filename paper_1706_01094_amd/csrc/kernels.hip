@@ -267,6 +267,11 @@ __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepPara
                                                 uint32_t *err) {
   const uint32_t x = e.x, a = e.y & 0xffffu, b = e.y >> 16, c = e.z, r = e.w;
   const uint32_t N = a + b + c;
+  if (N > 65535u) {  // a post-collision count might not fit: flagged, kept
+    atomicOr(err, kErrOverflow);
+    return b;
+  }
+  if (p.C == 0) return b;
   if (N <= p.n_max) {
     const uint32_t absJ = (uint32_t)abs((int32_t)c - (int32_t)a);
     const uint32_t par = (N - absJ) & 1u;
@@ -316,20 +321,34 @@ struct SiteLook {
   uint4 q;
 };
 
-template <int K>
-__device__ __forceinline__ void site_dir(SiteLook &s,
-                                         const uint32_t (&va)[4], const uint32_t (&vb)[4],
-                                         const uint32_t (&vc)[4], const LdsView &lv,
-                                         const StepParams &p, bool &range_err) {
-  const uint32_t ea = get16(va, K), eb = get16(vb, K), ec = get16(vc, K);
-  const uint32_t N = ea + eb + ec;
-  range_err |= N > 65535u;
-  const bool collide = (N >= 2u) & (N <= 65535u) & (p.C != 0);
-  const uint32_t lo = min(ea, ec), hi = max(ea, ec), bi = eb - lv.b_lo;
-  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb);
+// Phase 1 of one site from its packed 16-bit quantities: N (saturated at
+// 65535), min(a, c), max(a, c) and b - b_lo (mod 2^16).  A site whose N
+// reads 65535 (N >= 65535) always goes to the queue, where the exact N is
+// known: above 65535 it is flagged and kept.
+__device__ __forceinline__ void site_dir_one(SiteLook &s, uint32_t N, uint32_t lo, uint32_t hi,
+                                             uint32_t bi, const LdsView &lv, bool collisions) {
+  const bool collide = (collisions & (N >= 2u)) | (N == 0xFFFFu);
+  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb);  // implies N < 3072
   const uint32_t slot = inbox ? __umul24(lo, lv.dim_c) + hi : lv.never;
   s.bix = (collide & inbox) ? bi : 0u;
   s.pidx = lv.dir[collide ? slot : lv.never + 1u];
+}
+
+// Phase 1 of sites 2J and 2J + 1 with 16-bit packed arithmetic.
+template <int J>
+__device__ __forceinline__ void site_dir_pair(SiteLook &s0, SiteLook &s1,
+                                              const uint32_t (&va)[4], const uint32_t (&vb)[4],
+                                              const uint32_t (&vc)[4], const LdsView &lv,
+                                              uint32_t b_lo2, bool collisions) {
+  const u16x2 a = __builtin_bit_cast(u16x2, va[J]), b = __builtin_bit_cast(u16x2, vb[J]),
+              c = __builtin_bit_cast(u16x2, vc[J]);
+  const uint32_t N2 = __builtin_bit_cast(
+      uint32_t, __builtin_elementwise_add_sat(__builtin_elementwise_add_sat(a, b), c));
+  const uint32_t lo2 = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(a, c));
+  const uint32_t hi2 = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, c));
+  const uint32_t bi2 = pk_sub16(vb[J], b_lo2);
+  site_dir_one(s0, N2 & 0xffffu, lo2 & 0xffffu, hi2 & 0xffffu, bi2 & 0xffffu, lv, collisions);
+  site_dir_one(s1, N2 >> 16, lo2 >> 16, hi2 >> 16, bi2 >> 16, lv, collisions);
 }
 
 __device__ __forceinline__ void site_rec(SiteLook &s, const LdsView &lv) {
@@ -369,17 +388,13 @@ __device__ __forceinline__ void apply_pair(uint32_t (&va)[4], uint32_t (&vb)[4],
 __device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
                                              uint32_t (&va)[4], uint32_t (&vb)[4],
                                              uint32_t (&vc)[4], const LdsView &lv,
-                                             const StepParams &p, uint32_t &miss,
-                                             bool &range_err) {
+                                             bool collisions, uint32_t &miss) {
   SiteLook s0, s1, s2, s3, s4, s5, s6, s7;
-  site_dir<0>(s0, va, vb, vc, lv, p, range_err);
-  site_dir<1>(s1, va, vb, vc, lv, p, range_err);
-  site_dir<2>(s2, va, vb, vc, lv, p, range_err);
-  site_dir<3>(s3, va, vb, vc, lv, p, range_err);
-  site_dir<4>(s4, va, vb, vc, lv, p, range_err);
-  site_dir<5>(s5, va, vb, vc, lv, p, range_err);
-  site_dir<6>(s6, va, vb, vc, lv, p, range_err);
-  site_dir<7>(s7, va, vb, vc, lv, p, range_err);
+  const uint32_t b_lo2 = lv.b_lo * 0x10001u;
+  site_dir_pair<0>(s0, s1, va, vb, vc, lv, b_lo2, collisions);
+  site_dir_pair<1>(s2, s3, va, vb, vc, lv, b_lo2, collisions);
+  site_dir_pair<2>(s4, s5, va, vb, vc, lv, b_lo2, collisions);
+  site_dir_pair<3>(s6, s7, va, vb, vc, lv, b_lo2, collisions);
   philox10_x2(w0, w1, key);
   site_rec(s0, lv);
   site_rec(s1, lv);
@@ -749,9 +764,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
           uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
           uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
           uint32_t miss = 0;
-          bool range_err = false;
-          decide_eight(w0, w1, key, va, vb, vc, lv, p, miss, range_err);
-          if (range_err) atomicOr(a.err, kErrOverflow);
+          decide_eight(w0, w1, key, va, vb, vc, lv, p.C != 0, miss);
           if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
         }
 

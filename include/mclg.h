@@ -78,7 +78,7 @@ typedef struct {
   uint32_t lattice;            /* MCLG_D1Q3 */
   uint32_t n_replicas;         /* >= 1 */
   uint32_t flags;              /* MCLG_FLAG_* */
-  const uint64_t *L;           /* host [n_replicas]; 1 <= L < 2^31 */
+  const uint64_t *L;           /* host [n_replicas]; 1 <= L <= 2^29 */
   const uint64_t *replica_id;  /* host [n_replicas], each < 2^32, or NULL */
   uint64_t seed;               /* Philox key */
   int32_t C;                   /* sub-collisions per step, >= 0, or MCLG_C_EQUILIBRIUM */
@@ -205,7 +205,7 @@ typedef struct {
 
 typedef struct {
   uint64_t job_id;             /* RNG replica identity (< 2^32) and handle */
-  uint64_t L;                  /* sites */
+  uint64_t L;                  /* sites, 1 <= L <= 2^29 */
   uint64_t steps;              /* steps to run */
   double rho, u0;              /* Poisson initial state */
 } mclg_job;

@@ -81,7 +81,7 @@ int validate(const mclg_config *cfg) {
   if (cfg->n_replicas == 0 || !cfg->L) return MCLG_E_INVAL;
   if (cfg->flags & ~(uint32_t)MCLG_FLAG_NO_STREAM) return MCLG_E_INVAL;
   for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
-    if (cfg->L[r] == 0 || cfg->L[r] >= (1ull << 31)) return MCLG_E_INVAL;
+    if (cfg->L[r] == 0 || cfg->L[r] > kMaxSites) return MCLG_E_INVAL;
     if (cfg->replica_id && cfg->replica_id[r] >= (1ull << 32)) return MCLG_E_INVAL;
   }
   if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max)) return MCLG_E_INVAL;

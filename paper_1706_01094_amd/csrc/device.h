@@ -95,6 +95,10 @@ struct StepLaunch {
 
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 
+// Largest lattice (sites per replica or job): the step kernel addresses a
+// slot's three arrays (6 bytes per site, 256-byte padded) with 32-bit byte
+// offsets.
+constexpr uint64_t kMaxSites = 1ull << 29;
 constexpr uint32_t kQueue = 128;  // LDS queue entries (16 bytes) per wave
 // per-wave LDS after the image: the queue, then four boundary vectors
 // passed from one chunk to the next

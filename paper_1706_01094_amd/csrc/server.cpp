@@ -401,7 +401,7 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
 }
 
 int mclg_server_submit(mclg_server *sv, const mclg_job *job) {
-  if (!sv || !job || job->L == 0 || job->L >= (1ull << 31) || job->job_id >= (1ull << 32))
+  if (!sv || !job || job->L == 0 || job->L > kMaxSites || job->job_id >= (1ull << 32))
     return MCLG_E_INVAL;
   if (!(job->rho >= 0.0) || !(job->u0 >= -1.0 && job->u0 <= 1.0)) return MCLG_E_INVAL;
   if (mclg_server::job_bytes(job->L) > sv->cfg.arena_bytes / 256 * 256) return MCLG_E_INVAL;

@@ -203,6 +203,7 @@ def test_batched_replicas_step_replica_and_graph():
 
 
 def _window_check(g, L, seed, rho, u0, T, x0s, W=1500, counts=None):
+    full = g.counts(0)
     for x0 in x0s:
         lo = x0 - T
         n = W + 2 * T
@@ -214,7 +215,7 @@ def _window_check(g, L, seed, rho, u0, T, x0s, W=1500, counts=None):
             o.init_counts(0, counts[:, lo:lo + n])
         o.step(T)
         want = o.counts(0)[:, T:T + W]
-        got = g.counts(0)[:, x0:x0 + W]
+        got = full[:, x0:x0 + W]
         assert np.array_equal(got, want), f"window at {x0}"
 
 
@@ -234,6 +235,22 @@ def test_full_size_plain_large_windows():
     rng = np.random.default_rng(0)
     x0s = [T, L // 2, L - 1500 - T] + [int(v) for v in rng.integers(T, L - 1500 - T, size=3)]
     _window_check(g, L, w["seed"], w["rho"], w["u0"], T, x0s)
+
+
+def test_largest_lattice_windows():
+    """L = 2^29, the largest lattice (the step kernel's 32-bit byte offsets
+    reach their top): conservation and oracle windows at both ends and in
+    the middle after a few steps."""
+    L = 1 << 29
+    say("largest lattice", L)
+    g = Lattice(L, 41, rho=8.0, u0=0.05)
+    m0 = g.moments()[0]
+    T = 3
+    g.step(T)
+    m1 = g.moments()[0]
+    assert m1["sum_N"] == m0["sum_N"] and m1["sum_J"] == m0["sum_J"]
+    _window_check(g, L, 41, 8.0, 0.05, T, [T, L // 2 + 12345, L - 1500 - T], W=1500)
+    g.close()
 
 
 def test_full_size_density_wave():

@@ -83,7 +83,11 @@ def test_sizes_and_validation():
     lib = M.lib()
     s, w = ct.c_uint64(), ct.c_uint64()
     assert lib.mclg_sizes(ct.byref(_cfg([256], lattice=M.D2Q9)), ct.byref(s), ct.byref(w)) == M.E_UNSUPPORTED
-    for bad in [_cfg([0]), _cfg([256], C=-2), _cfg([256], lam=(2, 1)), _cfg([256], lam=(0, 1)),
+    # largest lattice: 2^29 sites (32-bit byte offsets into a slot's three arrays)
+    sb3, _ = M.mclg_sizes(_cfg([1 << 29]))
+    assert sb3 == 3 * (1 << 29) * 2
+    for bad in [_cfg([0]), _cfg([(1 << 29) + 1]), _cfg([256], C=-2), _cfg([256], lam=(2, 1)),
+                _cfg([256], lam=(0, 1)),
                 _cfg([256], n_max=2000), _cfg([256], abi=99), _cfg([256], flags=8)]:
         assert lib.mclg_sizes(ct.byref(bad), ct.byref(s), ct.byref(w)) == M.E_INVAL
     assert lib.mclg_init(None, None, None) == M.E_INVAL

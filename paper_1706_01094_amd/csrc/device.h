@@ -100,9 +100,8 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // offsets.
 constexpr uint64_t kMaxSites = 1ull << 29;
 constexpr uint32_t kQueue = 128;  // LDS queue entries (16 bytes) per wave
-// per-wave LDS after the image: the queue, then four boundary vectors
-// passed from one chunk to the next
-constexpr uint32_t kWaveLdsBytes = kQueue * 16 + 4 * 16;
+// per-wave LDS after the image: the queue of undecided draws
+constexpr uint32_t kWaveLdsBytes = kQueue * 16;
 // Entries of the global overflow area per wave (one chunk's worth of sites;
 // the queue continues there when its LDS part is full), and the number of waves the overflow region is sized for (all waves that
 // can be resident on a 256-CU device).

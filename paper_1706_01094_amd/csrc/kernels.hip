@@ -188,31 +188,6 @@ __device__ __forceinline__ void set16(uint32_t (&w)[4], int e, uint32_t v) {
   if (e & 1) w[e >> 1] = (w[e >> 1] & 0xffffu) | (v << 16);
   else w[e >> 1] = (w[e >> 1] & 0xffff0000u) | (v & 0xffffu);
 }
-// out = elements [s, s + 8) of the sixteen uint16 of (lo ++ hi); s is
-// wave-uniform, 0 <= s <= 8.
-__device__ __forceinline__ void extract8(const uint32_t (&lo)[4], const uint32_t (&hi)[4],
-                                         uint32_t s, uint32_t (&out)[4]) {
-  const uint32_t w[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-  const uint32_t sh = (s & 1u) * 2u;
-  switch (s >> 1) {
-#define MCLG_EXTRACT_CASE(K)                                                      \
-  case K:                                                                         \
-    for (int j = 0; j < 4; ++j)                                                   \
-      out[j] = (K + j + 1 < 8) ? __builtin_amdgcn_alignbyte(w[(K + j + 1) & 7], w[K + j], sh) \
-                               : w[K + j];                                        \
-    break;
-    MCLG_EXTRACT_CASE(0)
-    MCLG_EXTRACT_CASE(1)
-    MCLG_EXTRACT_CASE(2)
-    MCLG_EXTRACT_CASE(3)
-#undef MCLG_EXTRACT_CASE
-    default:
-      for (int j = 0; j < 4; ++j) out[j] = hi[j];
-  }
-}
-__device__ __forceinline__ void shfl_up4(const uint32_t (&v)[4], uint32_t (&o)[4]) {
-  for (int j = 0; j < 4; ++j) o[j] = __shfl_up(v[j], 1u);
-}
 __device__ __forceinline__ void load4(const uint16_t *p, uint32_t (&v)[4]) {
   const uint4 q = *reinterpret_cast<const uint4 *>(p);
   v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
@@ -241,14 +216,6 @@ __device__ __forceinline__ uint32_t bload2(Rsrc r, uint32_t voff, uint32_t soff)
 }
 __device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, uint32_t v) {
   __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, (int)soff, 0);
-}
-// Orders this wave's LDS accesses on either side: a vector one lane writes
-// and another lane reads passes through LDS, and a compiler reasoning per
-// thread may otherwise swap a read and a write made under exclusive lane
-// conditions.  No instruction is emitted.
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -504,62 +471,34 @@ __device__ __forceinline__ Win locate(uint32_t xs, const SlotView &v) {
   w.fast = (uint32_t)((xs + 512u <= v.L) & (w.sm + 512u <= v.L) & (w.sp + 512u <= v.L));
   return w;
 }
-// The vectors a fast chunk loads.  A window starting at s = A + b (A a
-// multiple of 8) covers the 65 aligned vectors A, A + 8, ..., A + 512 when
-// b != 0: lane i loads A + 8 (i + 1), and the first vector A is the one the
-// previous chunk's lane 63 loaded (or an explicit load at the start of a run).
-// With b = 0 lane i loads A + 8 i.  n_0 windows are always aligned.
+// A fast chunk's three windows, one 16-byte access per lane each: lane i
+// owns elements s + 8 i .. s + 8 i + 7 of every window.  The n_+-1 windows
+// start at any element (2-byte alignment); the hardware serves unaligned
+// vector accesses, and neighbouring lanes, chunks and waves touch disjoint
+// bytes, so each lane reads and writes exactly its own eight elements.
 struct Raw {
   uint32_t m[4], z[4], p[4];
 };
 __device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint32_t lane,
                                           Raw &r) {
   const uint32_t vo = 16u * lane;
-  bload4(v.rs(), vo, 2u * (w.sm & ~7u) + ((w.sm & 7u) ? 16u : 0u), r.m);
+  bload4(v.rs(), vo, 2u * w.sm, r.m);
   bload4(v.rs(), vo, v.ab + 2u * w.xs, r.z);
-  bload4(v.rs(), vo, 2u * v.ab + 2u * (w.sp & ~7u) + ((w.sp & 7u) ? 16u : 0u), r.p);
+  bload4(v.rs(), vo, 2u * v.ab + 2u * w.sp, r.p);
 }
-// Realign one window: with b != 0 lane i needs elements [b, b + 8) of the
-// vector before its own (lane i - 1's; for lane 0 the vector `first`, read
-// from the wave's LDS slot `ps` when `have_prev`, else loaded from `arr`)
-// followed by its own.  Lane 63 then leaves its own vector in the slot: it
-// is the first vector of the next chunk when that chunk is contiguous.
-__device__ __forceinline__ void realign(Rsrc rs, uint32_t base, uint32_t s,
-                                        const uint32_t (&own)[4], bool have_prev, uint4 *ps,
-                                        uint32_t lane, uint32_t (&out)[4]) {
-  const uint32_t b = s & 7u;
-  if (b == 0u) {
-    for (int j = 0; j < 4; ++j) out[j] = own[j];
-    return;
-  }
-  uint32_t pv[4];
-  shfl_up4(own, pv);
-  wave_lds_order();
-  if (lane == 0u) {
-    if (have_prev) {
-      const uint4 c = *ps;
-      pv[0] = c.x; pv[1] = c.y; pv[2] = c.z; pv[3] = c.w;
-    } else {
-      bload4(rs, 0u, base + 2u * (s - b), pv);
-    }
-  }
-  wave_lds_order();
-  if (lane == 63u) *ps = make_uint4(own[0], own[1], own[2], own[3]);
-  wave_lds_order();
-  extract8(pv, own, b, out);
-}
-// The chunk's three windows as eight consecutive sites per lane: realigned
+// The chunk's three windows as eight consecutive sites per lane: the loaded
 // vectors of a fast chunk, element by element for a chunk whose windows wrap
 // around the end of the lattice (or pass it).  Sites past the end read as
 // empty (N = 0): they do not collide and are never stored.
-__device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, bool contiguous,
-                                              uint4 *prev_m, uint4 *prev_p, const SlotView &v,
+__device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, const SlotView &v,
                                               uint32_t lane, uint32_t (&va)[4],
                                               uint32_t (&vb)[4], uint32_t (&vc)[4]) {
   if (w.fast) {
-    realign(v.rs(), 0u, w.sm, r.m, contiguous, prev_m, lane, va);
-    for (int j = 0; j < 4; ++j) vb[j] = r.z[j];
-    realign(v.rs(), 2u * v.ab, w.sp, r.p, contiguous, prev_p, lane, vc);
+    for (int j = 0; j < 4; ++j) {
+      va[j] = r.m[j];
+      vb[j] = r.z[j];
+      vc[j] = r.p[j];
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -579,64 +518,6 @@ __device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, bool c
   // complete here, so that no load of this chunk is still counted when the
   // next chunk's loads are issued
   for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(va[j]), "+v"(vb[j]), "+v"(vc[j]));
-}
-// Store one misaligned window back to its aligned vectors.  Lanes 1..63
-// write whole vectors.  Lane 0's vector starts with the previous chunk's last
-// b elements: merged from the wave's carry slot `cs` (LDS) when the previous
-// chunk deferred them, else lane 0 writes only its own elements.  The b
-// elements after the window belong to lane 63: with `defer` its vector goes
-// to the carry slot for the next chunk's lane 0, else lane 63 writes them.
-// LDS operations of a wave complete in order, so the slot is read before it
-// is rewritten.
-__device__ __forceinline__ void store_merge(Rsrc rs, uint32_t base, uint32_t s, uint32_t lane,
-                                            const uint32_t (&o)[4], bool have_carry,
-                                            bool defer, uint4 *cs) {
-  const uint32_t b = s & 7u, A = s - b;
-  if (b == 0u) {
-    bstore4(rs, 16u * lane, base + 2u * A, o);
-    return;
-  }
-  uint32_t prev[4], al[4];
-  shfl_up4(o, prev);
-  wave_lds_order();
-  if (lane == 0u && have_carry) {
-    const uint4 c = *cs;
-    prev[0] = c.x; prev[1] = c.y; prev[2] = c.z; prev[3] = c.w;
-  }
-  wave_lds_order();
-  extract8(prev, o, 8u - b, al);
-  if (lane != 0u || have_carry) {
-    bstore4(rs, 16u * lane, base + 2u * A, al);
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < 8u - b) bstore2(rs, 2u * e, base + 2u * s, get16(o, e));
-  }
-  if (lane == 63u) {
-    if (defer) {
-      *cs = make_uint4(o[0], o[1], o[2], o[3]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if ((uint32_t)e < b) bstore2(rs, 2u * e, base + 2u * (A + 512u), get16(o, 8 - (int)b + e));
-    }
-  }
-  wave_lds_order();
-}
-// Write the deferred boundary elements of the chunk before the window at s
-// (elements 8 - b .. 7 of the carried vector) to their places, the first b
-// elements of the aligned vector that holds s.
-__device__ __forceinline__ void flush_carry(Rsrc rs, uint32_t base, uint32_t s, uint32_t lane,
-                                            const uint4 *cs) {
-  const uint32_t b = s & 7u, A = s - b;
-  wave_lds_order();
-  if (lane == 0u && b != 0u) {
-    const uint4 c4 = *cs;
-    const uint32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if ((uint32_t)e < b) bstore2(rs, 2u * e, base + 2u * A, get16(c, 8 - (int)b + e));
-  }
 }
 
 // Fused stream + collide.  Persistent blocks: block i takes a contiguous run
@@ -660,10 +541,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   // wave-uniform, which the compiler cannot infer from threadIdx.x
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
-  uint4 *const carry_m = queue + kQueue;  // deferred boundary vectors of n_-1, n_+1
-  uint4 *const carry_p = carry_m + 1;
-  uint4 *const prev_m = carry_m + 2;      // first vectors of the next windows
-  uint4 *const prev_p = carry_m + 3;
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
@@ -740,13 +617,12 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     if (k < k1) {
       Raw cr;
       if (cw.fast) issue_raw(cw, sv, lane, cr);
-      chunk_windows(cw, cr, false, prev_m, prev_p, sv, lane, va, vb, vc);
+      chunk_windows(cw, cr, sv, lane, va, vb, vc);
     }
-    bool carry = false;
     while (k < k1) {
       do {
-        // The next chunk's loads go out first; they are realigned only after
-        // this chunk is decided and stored.
+        // The next chunk's loads go out first (its bytes are disjoint from
+        // this chunk's); they are taken only after this chunk is stored.
         const bool has_next = k + 1 < k1;
         Win nw = cw;
         Raw nr;
@@ -754,9 +630,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
           nw = locate(cw.xs + 512u, sv);
           if (nw.fast) issue_raw(nw, sv, lane, nr);
         }
-        // contiguous in all three arrays: neither shifted window wraps to 0
-        const bool contiguous = has_next & ((nw.fast & cw.fast) != 0u) &
-                                (nw.sm == cw.sm + 512u) & (nw.sp == cw.sp + 512u);
 
         // ---- collide: LDS image first, the rest into the wave's queue ----
         {
@@ -768,12 +641,12 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
           if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
         }
 
-
         // ---- store ----
         if (cw.fast) {
-          store_merge(rs, 0u, cw.sm, lane, va, carry, contiguous, carry_m);
-          bstore4(rs, 16u * lane, ab + 2u * cw.xs, vb);
-          store_merge(rs, 2u * ab, cw.sp, lane, vc, carry, contiguous, carry_p);
+          const uint32_t vo = 16u * lane;
+          bstore4(rs, vo, 2u * cw.sm, va);
+          bstore4(rs, vo, ab + 2u * cw.xs, vb);
+          bstore4(rs, vo, 2u * ab + 2u * cw.sp, vc);
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -788,22 +661,14 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
             }
           }
         }
-        carry = contiguous;
         // ---- the next chunk's windows ----
-        if (has_next) chunk_windows(nw, nr, contiguous, prev_m, prev_p, sv, lane, va, vb, vc);
+        if (has_next) chunk_windows(nw, nr, sv, lane, va, vb, vc);
         cw = nw;
         ++k;
       } while (k < k1 && F <= kDrainAt);
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
-      // fit.  Deferred boundary elements are written before a drain: the
-      // drain's final counts must land after every placeholder.  (The run's
-      // last chunk defers nothing.)
+      // fit.
       if (k < k1) {
-        if (carry) {
-          flush_carry(rs, 0u, cw.sm, lane, carry_m);
-          flush_carry(rs, 2u * ab, cw.sp, lane, carry_p);
-          carry = false;
-        }
         drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
       }

@@ -520,18 +520,23 @@ __device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, const 
   for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(va[j]), "+v"(vb[j]), "+v"(vc[j]));
 }
 
-// Fused stream + collide.  Persistent blocks: block i takes a contiguous run
-// of chunks; a run of one slot's chunks (a segment) is split among the
-// block's waves into contiguous runs, and each wave streams through its run
-// with one chunk of lookahead: the next chunk's vectors are requested before
-// the current one is decided, the vector after a misaligned window is the
-// next chunk's first lane vector, and the boundary vector between two
-// chunks is written whole by the second.  The slot's collision image is
-// loaded into LDS at each segment.  Each lane owns 8 consecutive sites of a
-// chunk (two Philox calls).  Every physical element belongs to exactly one
-// site per step, so the in-place update has no races.  Undecided draws wait
-// in the wave's queue, which is drained between chunks (outside the hot
-// loop) once it nears capacity, and at the end of the slot's segment.
+// The block's next chunk index (an LDS counter), wave-uniform.
+__device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
+  uint32_t v = 0;
+  if (lane == 0) v = atomicAdd(ctr, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Fused stream + collide.  Persistent blocks: block i takes a contiguous
+// range of chunks; the slot's collision image is loaded into LDS for each
+// run of one slot's chunks (a segment), whose chunks the block's waves then
+// claim one at a time.  Each wave keeps one chunk of lookahead: the next
+// chunk's vectors are requested before the current one is decided.  Each
+// lane owns 8 consecutive sites of a chunk (two Philox calls).  Every
+// physical element belongs to exactly one site per step, so the in-place
+// update has no races.  Undecided draws wait in the wave's queue, which is
+// drained between chunks once it nears capacity, and at the end of the
+// slot's segment.
 template <int MAXT>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   extern __shared__ uint4 lds[];
@@ -543,6 +548,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
+  __shared__ uint32_t next_chunk;  // the block's next unclaimed chunk of the segment
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
   const uint32_t cb = blockIdx.x * per;
   const uint32_t ce = min(a.n_tiles, cb + per);
@@ -569,7 +575,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     if (t0.slot != cur) {
       cur = t0.slot;
       const ImageDesc im = a.images[cur];
-      __syncthreads();  // previous image no longer in use
+      __syncthreads();  // previous image and chunk counter no longer in use
+      if (threadIdx.x == 0) next_chunk = i;
       // eight independent 16-byte loads per thread per round, then the stores
       // (indices clamped into the image; the stores past its end are skipped)
       const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
@@ -605,29 +612,30 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
       sv.ab = __builtin_amdgcn_readfirstlane(2u * sl.stride);
     }
-    // this wave's run of the segment's chunks
-    const uint32_t n = se - i;
-    const uint32_t k1 = i + ((wave + 1) * n) / nwaves;
-    uint32_t k = i + (wave * n) / nwaves;
+    // The segment's chunks go to the block's waves one at a time from a
+    // shared counter, so that waves issued less often (the hardware favours
+    // older waves) take fewer chunks and all finish together.
     const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
     const Rsrc rs = sv.rs();
     const uint32_t ab = sv.ab;
+    uint32_t k = grab_chunk(&next_chunk, lane);
     Win cw = locate(t0.x0 + (k - i) * 512u, sv);
     uint32_t va[4], vb[4], vc[4];
-    if (k < k1) {
+    if (k < se) {
       Raw cr;
       if (cw.fast) issue_raw(cw, sv, lane, cr);
       chunk_windows(cw, cr, sv, lane, va, vb, vc);
     }
-    while (k < k1) {
+    while (k < se) {
       do {
         // The next chunk's loads go out first (its bytes are disjoint from
         // this chunk's); they are taken only after this chunk is stored.
-        const bool has_next = k + 1 < k1;
+        const uint32_t nk = grab_chunk(&next_chunk, lane);
+        const bool has_next = nk < se;
         Win nw = cw;
         Raw nr;
         if (has_next) {
-          nw = locate(cw.xs + 512u, sv);
+          nw = locate(t0.x0 + (nk - i) * 512u, sv);
           if (nw.fast) issue_raw(nw, sv, lane, nr);
         }
 
@@ -664,11 +672,11 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
         // ---- the next chunk's windows ----
         if (has_next) chunk_windows(nw, nr, sv, lane, va, vb, vc);
         cw = nw;
-        ++k;
-      } while (k < k1 && F <= kDrainAt);
+        k = nk;
+      } while (k < se && F <= kDrainAt);
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
       // fit.
-      if (k < k1) {
+      if (k < se) {
         drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
       }

@@ -69,7 +69,7 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
   lay.o_ipool = take((uint64_t)kMaxImage * n);
   lay.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   lay.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
-  lay.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
+  lay.o_thr = take(sizeof(uint32_t) * (tab->thr.size() + 16));  // +16: see count_le_16
   lay.ws_bytes = o;
   return true;
 }

@@ -160,10 +160,28 @@ __device__ __forceinline__ uint32_t count_le_wide(const uint32_t *__restrict__ t
 }
 
 // Exact row of the global tables: the number of thresholds <= r.
+// Rows of up to 16 thresholds (every row of C <= 7, most of larger C) are
+// counted from four 16-byte loads issued together; the threshold pool is
+// padded by 16 values so that these loads stay inside it.
+__device__ __forceinline__ uint32_t count_le_16(const uint32_t *t, uint32_t n, uint32_t r) {
+  uint4 q[4];
+  for (int j = 0; j < 4; ++j) __builtin_memcpy(&q[j], t + 4 * j, 16);  // 4-byte aligned
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < 16; ++j) {
+    const uint4 &v = q[j >> 2];
+    const uint32_t x = (j & 3) == 0 ? v.x : (j & 3) == 1 ? v.y : (j & 3) == 2 ? v.z : v.w;
+    c += (j < n && x <= r) ? 1u : 0u;
+  }
+  return c;
+}
+
 __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
                                                    uint32_t b, uint32_t par, uint32_t r) {
   const uint2 d = tab.rowdesc[fiber_base(N, absJ) + ((b - par) >> 1)];  // states ascend in n0
-  return (d.y & 0xffffu) + count_le_wide(tab.thr + d.x, (d.y >> 16) - 1u, r);
+  const uint32_t n = (d.y >> 16) - 1u;
+  return (d.y & 0xffffu) +
+         (n <= 16u ? count_le_16(tab.thr + d.x, n, r) : count_le_wide(tab.thr + d.x, n, r));
 }
 
 // The slot's collision image in LDS: directory of (min(a,c), max(a,c)) pairs,

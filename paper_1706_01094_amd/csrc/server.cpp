@@ -59,7 +59,7 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_ipool = take((uint64_t)kImage * n);
   l.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
-  l.o_thr = take(sizeof(uint32_t) * std::max<size_t>(tab->thr.size(), 1));
+  l.o_thr = take(sizeof(uint32_t) * (tab->thr.size() + 16));  // +16: see count_le_16
   l.bytes = o;
   return l;
 }

@@ -38,10 +38,15 @@ struct StepParams {
   uint32_t tile_sites;
 };
 
+// Stride (uint32) of the fixed-stride copy of the collision rows: a header
+// k_first | q << 16 and up to 19 thresholds.
+constexpr uint32_t kFixedStride = 20;
+
 struct TableDev {
   const uint32_t *rowbase;
   const uint2 *rowdesc;
   const uint32_t *thr;
+  const uint4 *fixed;  // rows at a fixed stride of kFixedStride uint32, or null
 };
 
 // Exact per-slot sums, all modulo 2^64.

@@ -178,7 +178,20 @@ __device__ __forceinline__ uint32_t count_le_16(const uint32_t *t, uint32_t n, u
 
 __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
                                                    uint32_t b, uint32_t par, uint32_t r) {
-  const uint2 d = tab.rowdesc[fiber_base(N, absJ) + ((b - par) >> 1)];  // states ascend in n0
+  const uint32_t row = fiber_base(N, absJ) + ((b - par) >> 1);  // states ascend in n0
+  if (tab.fixed) {
+    // header and up to 19 thresholds, all five 16-byte pieces at once
+    const uint4 *q = tab.fixed + (size_t)row * (kFixedStride / 4);
+    const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4];
+    const uint32_t w[20] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y,
+                            q2.z, q2.w, q3.x, q3.y, q3.z, q3.w, q4.x, q4.y, q4.z, q4.w};
+    const uint32_t n = (w[0] >> 16) - 1u;
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kFixedStride - 1; ++j) c += (j < n && w[1 + j] <= r) ? 1u : 0u;
+    return (w[0] & 0xffffu) + c;
+  }
+  const uint2 d = tab.rowdesc[row];
   const uint32_t n = (d.y >> 16) - 1u;
   return (d.y & 0xffffu) +
          (n <= 16u ? count_le_16(tab.thr + d.x, n, r) : count_le_wide(tab.thr + d.x, n, r));

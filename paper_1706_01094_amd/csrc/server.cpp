@@ -31,7 +31,7 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
   uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
-      o_rowbase, o_rowdesc, o_thr, bytes, max_tiles;
+      o_rowbase, o_rowdesc, o_thr, o_fixed, bytes, max_tiles;
 };
 
 SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
@@ -60,6 +60,7 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_rowbase = take(sizeof(uint32_t) * tab->rowbase.size());
   l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
   l.o_thr = take(sizeof(uint32_t) * (tab->thr.size() + 16));  // +16: see count_le_16
+  l.o_fixed = take(sizeof(uint32_t) * tab->fixed.size());
   l.bytes = o;
   return l;
 }
@@ -110,6 +111,7 @@ struct mclg_server {
     d.rowbase = reinterpret_cast<const uint32_t *>(ws + lay.o_rowbase);
     d.rowdesc = reinterpret_cast<const uint2 *>(ws + lay.o_rowdesc);
     d.thr = reinterpret_cast<const uint32_t *>(ws + lay.o_thr);
+    d.fixed = tab->fixed.empty() ? nullptr : reinterpret_cast<const uint4 *>(ws + lay.o_fixed);
     return d;
   }
   int hip(hipError_t e) {
@@ -394,6 +396,7 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
   if (!e) e = sv->up(sv->ws + sv->lay.o_rowbase, t.rowbase.data(), 4 * t.rowbase.size());
   if (!e) e = sv->up(sv->ws + sv->lay.o_rowdesc, t.rowdesc.data(), 4 * t.rowdesc.size());
   if (!e) e = sv->up(sv->ws + sv->lay.o_thr, t.thr.data(), 4 * t.thr.size());
+  if (!e && !t.fixed.empty()) e = sv->up(sv->ws + sv->lay.o_fixed, t.fixed.data(), 4 * t.fixed.size());
   if (!e) e = hipStreamSynchronize(sv->s);
   if (e) return sv->hip(e);
   *out = sv.release();

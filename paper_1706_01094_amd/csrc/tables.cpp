@@ -17,6 +17,8 @@
 // balance (Eq. (transprob)).  Thresholds are floor(2^32 * cumulative).
 #include "tables.h"
 
+#include "device.h"  // kFixedStride
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -399,6 +401,16 @@ std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_
     tab->thr.insert(tab->thr.end(), pc.thr.begin(), pc.thr.end());
     tab->max_q = std::max(tab->max_q, pc.max_q);
     row += pc.rows;
+  }
+  const size_t nrows = tab->rowdesc.size() / 2;
+  if (tab->max_q <= kFixedStride && (uint64_t)nrows * kFixedStride * 4 < (1ull << 31)) {
+    tab->fixed.assign(nrows * kFixedStride, 0u);
+    for (size_t r = 0; r < nrows; ++r) {
+      uint32_t *row = &tab->fixed[r * kFixedStride];
+      const uint32_t off = tab->rowdesc[2 * r], hdr = tab->rowdesc[2 * r + 1];
+      row[0] = hdr;
+      for (uint32_t j = 0; j + 1 < (hdr >> 16); ++j) row[1 + j] = tab->thr[off + j];
+    }
   }
   std::shared_ptr<const CollisionTables> res = tab;
   std::lock_guard<std::mutex> lk(g_cache_mu);

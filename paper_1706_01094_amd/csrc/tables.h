@@ -24,6 +24,10 @@ struct CollisionTables {
   std::vector<uint32_t> rowdesc;  // pairs (offset, k_first | q << 16)
   std::vector<uint32_t> thr;
   uint32_t max_q = 0;             // largest number of outcomes in a row
+  // The same rows at a fixed stride of kFixedStride uint32 (when max_q allows):
+  // row r = {k_first | q << 16, thresholds..., zero padding}, so that a row
+  // is found from (N, |J|, n0) by arithmetic and read in one round of loads.
+  std::vector<uint32_t> fixed;    // empty when not built
 };
 
 // Build (or fetch from the process cache) the tables for (C, lambda, n_max).

@@ -18,7 +18,6 @@ namespace {
 
 constexpr uint32_t kErrOverflow = 1u;   // a site with N > 65535
 constexpr uint32_t kErrEqRange = 2u;    // C = infinity and N > n_max
-constexpr uint32_t kErrInternal = 4u;   // queue capacity exceeded (a bug)
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53,
 // 0xCD9E8D57, Weyl increments 0x9E3779B9, 0xBB67AE85.
@@ -197,17 +196,27 @@ __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t
          (n <= 16u ? count_le_16(tab.thr + d.x, n, r) : count_le_wide(tab.thr + d.x, n, r));
 }
 
-// The slot's collision image in LDS: directory of (min(a,c), max(a,c)) pairs,
-// then 16-byte records (k_s, top 16 bits of 7 thresholds).  A record decides
-// the outcome exactly whenever the top 16 bits of r fall strictly inside its
-// window and differ from every stored value.
+// The slot's collision image in LDS: a directory of (min(a,c), max(a,c))
+// pairs whose last row and column stand for every pair out of range, then
+// 16-byte records, nb + 1 per pair (the last one for every b out of range).
+// A record decides the outcome exactly whenever the top 16 bits of r lie in
+// its window and differ from every inner value.
+// The image sits at LDS address 0 (the step kernel has no static LDS, so its
+// dynamic LDS starts there) and is read by byte address.
 struct LdsView {
-  const uint16_t *dir;
-  const uint4 *rec;
-  uint32_t dim_a, dim_c, b_lo, nb;
-  uint32_t never;  // directory slot of the "never" records; the "skip" slot follows
+  // dim_a, dim_c, dim_c + 1, b_lo and nb, each in both 16-bit halves
+  uint32_t da2, dc2, w2, blo2, nb2;
 };
-constexpr uint32_t kSkipRecordX = 0xFFFF8000u;  // first word of the skip record
+typedef __attribute__((address_space(3))) const uint16_t lds_c16;
+typedef uint32_t lds_v4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const lds_v4 lds_c4;
+__device__ __forceinline__ uint16_t lds_u16(uint32_t addr) {
+  return *(lds_c16 *)(size_t)addr;
+}
+__device__ __forceinline__ uint4 lds_u4(uint32_t addr) {
+  const lds_v4 v = *(lds_c4 *)(size_t)addr;
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
 
 // ---------------------------------------------------------------------------
 // Wave-level helpers
@@ -218,13 +227,6 @@ __device__ __forceinline__ uint32_t get16(const uint32_t (&w)[4], int e) {
 __device__ __forceinline__ void set16(uint32_t (&w)[4], int e, uint32_t v) {
   if (e & 1) w[e >> 1] = (w[e >> 1] & 0xffffu) | (v << 16);
   else w[e >> 1] = (w[e >> 1] & 0xffff0000u) | (v & 0xffffu);
-}
-__device__ __forceinline__ void load4(const uint16_t *p, uint32_t (&v)[4]) {
-  const uint4 q = *reinterpret_cast<const uint4 *>(p);
-  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-}
-__device__ __forceinline__ void store4(uint16_t *p, const uint32_t (&v)[4]) {
-  *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
 }
 // A slot's three arrays through one buffer resource: byte address =
 // voff (per lane) + soff (wave-uniform, a scalar register).  Offsets stay
@@ -269,7 +271,7 @@ __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepPara
     atomicOr(err, kErrOverflow);
     return b;
   }
-  if (p.C == 0) return b;
+  if (p.C == 0 || N < 2u) return b;  // no collision
   if (N <= p.n_max) {
     const uint32_t absJ = (uint32_t)abs((int32_t)c - (int32_t)a);
     const uint32_t par = (N - absJ) & 1u;
@@ -296,162 +298,182 @@ struct SlotView {
 
 // Two 16-bit lanes of a 32-bit register.
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t pk_add16(uint32_t a, uint32_t b) {
-  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
-}
-__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
-  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
-}
 
 // Decision of one site from the LDS image, in three phases so that the LDS
 // reads of several sites are in flight together: (1) directory read, (2)
-// record read, (3) decision.  There is no branch per site and nothing but
-// the record is carried from one phase to the next: a site that does not
-// collide reads the skip slot, a site outside the image (or of an absent
-// pair) reads a never record, and neither record decides a draw.  A record
-// holds (b >> 1) - k_s and the top 16 bits of seven consecutive thresholds
-// t1..t7 of the site's fiber row; with the top half rh of the draw strictly
-// between t1 and t7 and equal to none of t2..t6 the drawn state index is
-// k_s + #{t2..t6 < rh}, and the move of Eq. (collcons) is
+// record read, (3) decision.  There is no branch and no range test per site:
+// the directory clamps min(a, c) to dim_a and max(a, c) to dim_c, whose row
+// and column lead to never records, and b - b_lo (mod 2^16) is clamped to nb,
+// every pair's never record.  A site outside the image (or of an absent
+// pair, or with N > n_max) thus reads a never record, a site with N < 2 a
+// record of move 0, and a site whose N does not fit 16 bits lies outside
+// (the image holds N < 3072 only).  A record holds (b >> 1) - k_s, a lower
+// bound L, inner values t2..t6 and an upper bound U (top 16 bits of seven
+// consecutive thresholds of the site's fiber row, L rounded up); with the
+// top half rh of the draw in [L, U) and equal to none of t2..t6 the drawn
+// state index is k_s + #{t2..t6 < rh}, and the move of Eq. (collcons) is
 // d = (b - b') / 2 = (b >> 1) - k_s - #{t2..t6 < rh}  (b' has b's parity).
 struct SiteLook {
-  uint32_t pidx, bix;
   uint4 q;
 };
 
-// Phase 1 of one site from its packed 16-bit quantities: N (saturated at
-// 65535), min(a, c), max(a, c) and b - b_lo (mod 2^16).  A site whose N
-// reads 65535 (N >= 65535) always goes to the queue, where the exact N is
-// known: above 65535 it is flagged and kept.
-__device__ __forceinline__ void site_dir_one(SiteLook &s, uint32_t N, uint32_t lo, uint32_t hi,
-                                             uint32_t bi, const LdsView &lv, bool collisions) {
-  const bool collide = (collisions & (N >= 2u)) | (N == 0xFFFFu);
-  const bool inbox = (lo < lv.dim_a) & (hi < lv.dim_c) & (bi < lv.nb);  // implies N < 3072
-  const uint32_t slot = inbox ? __umul24(lo, lv.dim_c) + hi : lv.never;
-  s.bix = (collide & inbox) ? bi : 0u;
-  s.pidx = lv.dir[collide ? slot : lv.never + 1u];
-}
-
 // Phase 1 of sites 2J and 2J + 1 with 16-bit packed arithmetic.
 template <int J>
-__device__ __forceinline__ void site_dir_pair(SiteLook &s0, SiteLook &s1,
-                                              const uint32_t (&va)[4], const uint32_t (&vb)[4],
-                                              const uint32_t (&vc)[4], const LdsView &lv,
-                                              uint32_t b_lo2, bool collisions) {
+__device__ __forceinline__ void site_dir_pair(uint32_t &row0, uint32_t &row1, u16x2 &bis,
+                                              const uint32_t (&va)[4],
+                                              const uint32_t (&vb)[4], const uint32_t (&vc)[4],
+                                              const LdsView &lv) {
   const u16x2 a = __builtin_bit_cast(u16x2, va[J]), b = __builtin_bit_cast(u16x2, vb[J]),
               c = __builtin_bit_cast(u16x2, vc[J]);
-  const uint32_t N2 = __builtin_bit_cast(
-      uint32_t, __builtin_elementwise_add_sat(__builtin_elementwise_add_sat(a, b), c));
-  const uint32_t lo2 = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(a, c));
-  const uint32_t hi2 = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, c));
-  const uint32_t bi2 = pk_sub16(vb[J], b_lo2);
-  site_dir_one(s0, N2 & 0xffffu, lo2 & 0xffffu, hi2 & 0xffffu, bi2 & 0xffffu, lv, collisions);
-  site_dir_one(s1, N2 >> 16, lo2 >> 16, hi2 >> 16, bi2 >> 16, lv, collisions);
+  const u16x2 lo = __builtin_elementwise_min(__builtin_elementwise_min(a, c),
+                                             __builtin_bit_cast(u16x2, lv.da2));
+  const u16x2 hi = __builtin_elementwise_min(__builtin_elementwise_max(a, c),
+                                             __builtin_bit_cast(u16x2, lv.dc2));
+  const uint32_t slot = __builtin_bit_cast(uint32_t, lo * __builtin_bit_cast(u16x2, lv.w2) + hi);
+  const uint32_t bi = __builtin_bit_cast(
+      uint32_t, __builtin_elementwise_min(b - __builtin_bit_cast(u16x2, lv.blo2),
+                                          __builtin_bit_cast(u16x2, lv.nb2)));
+  const uint32_t off = __builtin_bit_cast(uint32_t, slot + slot);  // byte offsets
+  row0 = lds_u16(off & 0xffffu);
+  row1 = lds_u16(off >> 16);
+  bis = __builtin_bit_cast(u16x2, bi);
 }
 
-__device__ __forceinline__ void site_rec(SiteLook &s, const LdsView &lv) {
-  s.q = lv.rec[__umul24(s.pidx, lv.nb) + s.bix];
+// Phase 2 of sites 2J and 2J + 1: record indices add in 16-bit lanes.
+__device__ __forceinline__ void rec_pair(SiteLook &s0, SiteLook &s1, uint32_t row0, uint32_t row1,
+                                         u16x2 bis) {
+  const u16x2 rows = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(row1, row0, 0x05040100u));
+  const uint32_t idx = __builtin_bit_cast(uint32_t, rows + bis);
+  s0.q = lds_u4((idx & 0xffffu) << 4);
+  s1.q = lds_u4((idx >> 16) << 4);
 }
 
-// Returns d (0 unless decided here); sets bit K of `miss` for a collision
-// the image did not decide.
-template <int K>
-__device__ __forceinline__ int32_t site_finish(const SiteLook &s, uint32_t r, uint32_t &miss) {
+// Phase 3: whether the record decides the draw, and d in the low 16 bits
+// (meaningless when it does not).
+__device__ __forceinline__ uint32_t site_finish(const SiteLook &s, uint32_t r, bool &hit) {
   const uint4 q = s.q;
   const uint32_t rh = r >> 16;
-  const uint32_t t1 = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
-                 t5 = q.z >> 16, t6 = q.w & 0xffffu, t7 = q.w >> 16;
-  const bool hit = (rh > t1) & (rh < t7) & (rh != t2) & (rh != t3) & (rh != t4) & (rh != t5) &
-                   (rh != t6);
-  const int32_t d = (int32_t)(int16_t)(q.x & 0xffffu) - (int32_t)(t2 < rh) - (int32_t)(t3 < rh) -
-                    (int32_t)(t4 < rh) - (int32_t)(t5 < rh) - (int32_t)(t6 < rh);
-  miss |= (!hit & (q.x != kSkipRecordX)) ? (1u << K) : 0u;
-  return hit ? d : 0;
-}
-
-// Sites 2j and 2j + 1 move by d0 and d1: n_-1 and n_+1 gain d, n_0 loses 2d
-// (16-bit lanes; every result is a count in [0, 65535]).
-template <int J>
-__device__ __forceinline__ void apply_pair(uint32_t (&va)[4], uint32_t (&vb)[4],
-                                           uint32_t (&vc)[4], int32_t d0, int32_t d1) {
-  const uint32_t dp = ((uint32_t)d0 & 0xffffu) | ((uint32_t)d1 << 16);
-  va[J] = pk_add16(va[J], dp);
-  vc[J] = pk_add16(vc[J], dp);
-  vb[J] = pk_sub16(vb[J], pk_add16(dp, dp));
-}
-
-// All eight sites of the lane: directory reads of all eight first, the
-// Philox draws while they are in flight, then record reads, decisions and
-// updates.
-__device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
-                                             uint32_t (&va)[4], uint32_t (&vb)[4],
-                                             uint32_t (&vc)[4], const LdsView &lv,
-                                             bool collisions, uint32_t &miss) {
-  SiteLook s0, s1, s2, s3, s4, s5, s6, s7;
-  const uint32_t b_lo2 = lv.b_lo * 0x10001u;
-  site_dir_pair<0>(s0, s1, va, vb, vc, lv, b_lo2, collisions);
-  site_dir_pair<1>(s2, s3, va, vb, vc, lv, b_lo2, collisions);
-  site_dir_pair<2>(s4, s5, va, vb, vc, lv, b_lo2, collisions);
-  site_dir_pair<3>(s6, s7, va, vb, vc, lv, b_lo2, collisions);
-  philox10_x2(w0, w1, key);
-  site_rec(s0, lv);
-  site_rec(s1, lv);
-  site_rec(s2, lv);
-  site_rec(s3, lv);
-  site_rec(s4, lv);
-  site_rec(s5, lv);
-  site_rec(s6, lv);
-  site_rec(s7, lv);
-  int32_t d0 = site_finish<0>(s0, w0.x, miss), d1 = site_finish<1>(s1, w0.y, miss);
-  apply_pair<0>(va, vb, vc, d0, d1);
-  d0 = site_finish<2>(s2, w0.z, miss), d1 = site_finish<3>(s3, w0.w, miss);
-  apply_pair<1>(va, vb, vc, d0, d1);
-  d0 = site_finish<4>(s4, w1.x, miss), d1 = site_finish<5>(s5, w1.y, miss);
-  apply_pair<2>(va, vb, vc, d0, d1);
-  d0 = site_finish<6>(s6, w1.z, miss), d1 = site_finish<7>(s7, w1.w, miss);
-  apply_pair<3>(va, vb, vc, d0, d1);
+  const uint32_t lb = q.x >> 16, t2 = q.y & 0xffffu, t3 = q.y >> 16, t4 = q.z & 0xffffu,
+                 t5 = q.z >> 16, t6 = q.w & 0xffffu, ub = q.w >> 16;
+  hit = (rh >= lb) & (rh < ub) & (rh != t2) & (rh != t3) & (rh != t4) & (rh != t5) & (rh != t6);
+  return q.x - (uint32_t)(t2 < rh) - (uint32_t)(t3 < rh) - (uint32_t)(t4 < rh) -
+         (uint32_t)(t5 < rh) - (uint32_t)(t6 < rh);
 }
 
 // The wave's queue of undecided draws: a virtual array of kQueue entries in
 // LDS followed by kOverflow entries in global memory, filled to F
 // (wave-uniform).  An entry is (x, a | b << 16, c, r) with the site's
-// pre-collision counts, which the state keeps until the drain.
+// pre-collision counts; the chunk stores whatever its lane computed for such
+// a site, and the drain overwrites it with the exact outcome.
 constexpr uint32_t kDrainAt = kQueue - 32;  // drain once F exceeds this
 static_assert(kDrainAt + 512 <= kQueue + kOverflow, "a chunk's draws must fit the queue");
 
+// Site K of every lane whose draw was not decided (and, in a chunk that
+// passes the end of the lattice, that exists) goes to the queue, in lane
+// order.  wa, wb, wc are the words holding the site's pre-collision counts;
+// `slow` is wave-uniform.
 template <int K>
-__device__ __forceinline__ void push_one(uint4 *queue, uint4 *over, uint32_t miss, uint32_t &pos,
-                                         uint32_t x8, const uint32_t (&va)[4],
-                                         const uint32_t (&vb)[4], const uint32_t (&vc)[4],
-                                         uint32_t r, bool lds_only) {
-  if (miss & (1u << K)) {
-    const uint4 e = make_uint4(x8 + K, get16(va, K) | (get16(vb, K) << 16), get16(vc, K), r);
-    if (lds_only || pos < kQueue) queue[pos] = e;
-    else over[pos - kQueue] = e;
-    ++pos;
+__device__ __forceinline__ void push_site(uint4 *queue, Rsrc over, uint32_t &F, bool hit,
+                                          bool slow, uint32_t x8, uint32_t L, uint32_t wa,
+                                          uint32_t wb, uint32_t wc, uint32_t r) {
+  uint64_t mk = __ballot(!hit);
+  if (mk == 0) return;
+  if (slow) mk &= __builtin_amdgcn_uicmpl(x8 + K, L, 36);  // lanes with x8 + K < L
+  const uint32_t n = (uint32_t)__popcll(mk);
+  if (!hit && (!slow || x8 + K < L)) {
+    const uint32_t pos = F + lanes_below(mk);
+    const uint32_t ab = (K & 1) ? __builtin_amdgcn_perm(wb, wa, 0x07060302u)
+                                : __builtin_amdgcn_perm(wb, wa, 0x05040100u);
+    const uint32_t c = (K & 1) ? wc >> 16 : wc & 0xffffu;
+    if (pos < kQueue) {
+      queue[pos] = make_uint4(x8 + K, ab, c, r);
+    } else {
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 e = {x8 + K, ab, c, r};
+      __builtin_amdgcn_raw_buffer_store_b128(e, over, (int)(16u * (pos - kQueue)), 0, 0);
+    }
+  }
+  F += n;
+}
+
+// Phase 3 of sites 2J and 2J + 1: d of both in one word (16-bit lanes) and
+// whether each was decided.
+__device__ __forceinline__ uint32_t finish_pair(const SiteLook &s0, const SiteLook &s1,
+                                                uint32_t r0, uint32_t r1, bool &h0, bool &h1) {
+  const uint32_t d0 = site_finish(s0, r0, h0), d1 = site_finish(s1, r1, h1);
+  return __builtin_amdgcn_perm(d1, d0, 0x05040100u);
+}
+// Sites 2J and 2J + 1 move by d: n_-1 and n_+1 gain d, n_0 loses 2d.
+__device__ __forceinline__ void apply_pair(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t dp) {
+  const u16x2 d = __builtin_bit_cast(u16x2, dp);
+  a = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + d);
+  c = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, c) + d);
+  b = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, b) - (d + d));
+}
+
+// All eight sites of the lane: directory reads of all eight first, the
+// Philox draws while they are in flight, then record reads and decisions;
+// the undecided draws are queued with the pre-collision counts.
+__device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
+                                             uint32_t (&va)[4], uint32_t (&vb)[4],
+                                             uint32_t (&vc)[4], const LdsView &lv, uint4 *queue,
+                                             Rsrc over, uint32_t &F, bool slow, uint32_t x8,
+                                             uint32_t L) {
+  SiteLook s0, s1, s2, s3, s4, s5, s6, s7;
+  uint32_t r0, r1, r2, r3, r4, r5, r6, r7;  // each site's first record
+  u16x2 b01, b23, b45, b67;                  // clamped b - b_lo of each pair
+  site_dir_pair<0>(r0, r1, b01, va, vb, vc, lv);
+  site_dir_pair<1>(r2, r3, b23, va, vb, vc, lv);
+  site_dir_pair<2>(r4, r5, b45, va, vb, vc, lv);
+  site_dir_pair<3>(r6, r7, b67, va, vb, vc, lv);
+  philox10_x2(w0, w1, key);
+  rec_pair(s0, s1, r0, r1, b01);
+  rec_pair(s2, s3, r2, r3, b23);
+  rec_pair(s4, s5, r4, r5, b45);
+  rec_pair(s6, s7, r6, r7, b67);
+  bool h0, h1, h2, h3, h4, h5, h6, h7;
+  const uint32_t d01 = finish_pair(s0, s1, w0.x, w0.y, h0, h1);
+  const uint32_t d23 = finish_pair(s2, s3, w0.z, w0.w, h2, h3);
+  const uint32_t d45 = finish_pair(s4, s5, w1.x, w1.y, h4, h5);
+  const uint32_t d67 = finish_pair(s6, s7, w1.z, w1.w, h6, h7);
+  uint32_t na[4] = {va[0], va[1], va[2], va[3]}, nb[4] = {vb[0], vb[1], vb[2], vb[3]},
+           nc[4] = {vc[0], vc[1], vc[2], vc[3]};
+  apply_pair(na[0], nb[0], nc[0], d01);
+  apply_pair(na[1], nb[1], nc[1], d23);
+  apply_pair(na[2], nb[2], nc[2], d45);
+  apply_pair(na[3], nb[3], nc[3], d67);
+#define MCLG_PUSH(K, H, R) \
+  push_site<K>(queue, over, F, H, slow, x8, L, va[K >> 1], vb[K >> 1], vc[K >> 1], R)
+  MCLG_PUSH(0, h0, w0.x); MCLG_PUSH(1, h1, w0.y); MCLG_PUSH(2, h2, w0.z); MCLG_PUSH(3, h3, w0.w);
+  MCLG_PUSH(4, h4, w1.x); MCLG_PUSH(5, h5, w1.y); MCLG_PUSH(6, h6, w1.z); MCLG_PUSH(7, h7, w1.w);
+#undef MCLG_PUSH
+  for (int j = 0; j < 4; ++j) {
+    va[j] = na[j];
+    vb[j] = nb[j];
+    vc[j] = nc[j];
   }
 }
 
-// Append every missed draw of the chunk (lane-major, then by site) to the
-// queue.  The lane's offset is the exclusive prefix sum of the per-lane miss
-// counts, assembled from ballots of the four bits of each count.
-__device__ __forceinline__ void push_misses(uint4 *queue, uint4 *over, uint32_t &F, uint32_t miss,
-                                            uint32_t x8, const uint32_t (&va)[4],
-                                            const uint32_t (&vb)[4], const uint32_t (&vc)[4],
-                                            const uint4 &w0, const uint4 &w1) {
-  const uint32_t m = (uint32_t)__builtin_popcount(miss);
-  const uint64_t b0 = __ballot(m & 1u), b1 = __ballot(m & 2u), b2 = __ballot(m & 4u),
-                 b3 = __ballot(m & 8u);
-  const uint32_t total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) +
-                         4u * (uint32_t)__popcll(b2) + 8u * (uint32_t)__popcll(b3);
-  uint32_t pos = F + lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2) +
-                 8u * lanes_below(b3);
-  const bool lds_only = F + total <= kQueue;
-#define MCLG_PUSH(K, R) push_one<K>(queue, over, miss, pos, x8, va, vb, vc, R, lds_only)
-  MCLG_PUSH(0, w0.x); MCLG_PUSH(1, w0.y); MCLG_PUSH(2, w0.z); MCLG_PUSH(3, w0.w);
-  MCLG_PUSH(4, w1.x); MCLG_PUSH(5, w1.y); MCLG_PUSH(6, w1.z); MCLG_PUSH(7, w1.w);
-#undef MCLG_PUSH
-  F += total;
+// Without collisions only a site whose N does not fit 16 bits is queued
+// (the drain flags it and keeps its counts).
+__device__ __forceinline__ void queue_saturated(const uint32_t (&va)[4], const uint32_t (&vb)[4],
+                                                const uint32_t (&vc)[4], uint4 *queue,
+                                                Rsrc over, uint32_t &F, bool slow,
+                                                uint32_t x8, uint32_t L) {
+#define MCLG_SAT(J)                                                                              \
+  {                                                                                              \
+    const uint32_t N2 = __builtin_bit_cast(                                                      \
+        uint32_t, __builtin_elementwise_add_sat(                                                 \
+                      __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, va[J]),            \
+                                                    __builtin_bit_cast(u16x2, vb[J])),           \
+                      __builtin_bit_cast(u16x2, vc[J])));                                        \
+    push_site<2 * J>(queue, over, F, (N2 & 0xffffu) != 0xffffu, slow, x8, L, va[J], vb[J],      \
+                     vc[J], 0u);                                                                 \
+    push_site<2 * J + 1>(queue, over, F, (N2 >> 16) != 0xffffu, slow, x8, L, va[J], vb[J],      \
+                         vc[J], 0u);                                                             \
+  }
+  MCLG_SAT(0) MCLG_SAT(1) MCLG_SAT(2) MCLG_SAT(3)
+#undef MCLG_SAT
 }
 
 // Resolve every queued draw of the wave (all lanes in parallel) and store
@@ -578,8 +600,13 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
+  const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
-  __shared__ uint32_t next_chunk;  // the block's next unclaimed chunk of the segment
+  // after the image and the queues: the block's next unclaimed chunk of the
+  // segment, and the last-block flag (so that the image starts at LDS 0)
+  uint32_t *const ctl =
+      reinterpret_cast<uint32_t *>(lds + a.lds_bytes / 16u + nwaves * (kWaveLdsBytes / 16u));
+  uint32_t &next_chunk = ctl[0];
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
   const uint32_t cb = blockIdx.x * per;
   const uint32_t ce = min(a.n_tiles, cb + per);
@@ -589,9 +616,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   sv.ab = 0;
   sv.L = 1; sv.tm = sv.t = sv.rid = 0;
   LdsView lv;
-  lv.dir = reinterpret_cast<const uint16_t *>(lds);
-  lv.rec = lds;
-  lv.dim_a = lv.dim_c = lv.nb = lv.b_lo = lv.never = 0;
+  lv.da2 = lv.dc2 = lv.w2 = lv.blo2 = lv.nb2 = 0;
 
   for (uint32_t i = cb;;) {
     TileDev t0;
@@ -627,12 +652,11 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
         if (b0 + 7u * bd < n16) lds[b0 + 7u * bd] = v7;
       }
       __syncthreads();
-      lv.dim_a = im.dim_a;
-      lv.dim_c = im.dim_c;
-      lv.b_lo = im.b_lo;
-      lv.nb = im.nb;
-      lv.never = im.dim_a * im.dim_c;
-      lv.rec = lds + im.dir_bytes / 16u;
+      lv.da2 = im.dim_a * 0x10001u;
+      lv.dc2 = im.dim_c * 0x10001u;
+      lv.w2 = (im.dim_c + 1u) * 0x10001u;
+      lv.blo2 = im.b_lo * 0x10001u;
+      lv.nb2 = im.nb * 0x10001u;
       const SlotDev sl = a.slots[cur];
       sv.t = a.tslot[cur];
       sv.L = sl.L;
@@ -673,11 +697,14 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
         // ---- collide: LDS image first, the rest into the wave's queue ----
         {
           const uint32_t x8 = cw.xs + 8u * lane;
-          uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
-          uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
-          uint32_t miss = 0;
-          decide_eight(w0, w1, key, va, vb, vc, lv, p.C != 0, miss);
-          if (__ballot(miss != 0u)) push_misses(queue, over, F, miss, x8, va, vb, vc, w0, w1);
+          const bool slow = __builtin_amdgcn_readfirstlane(cw.fast) == 0u;
+          if (p.C != 0) {
+            uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
+            uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
+            decide_eight(w0, w1, key, va, vb, vc, lv, queue, ovr, F, slow, x8, L);
+          } else {
+            queue_saturated(va, vb, vc, queue, ovr, F, slow, x8, L);
+          }
         }
 
         // ---- store ----
@@ -718,7 +745,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   // Every block has consumed its loads of t before it takes its ticket (the
   // values shaped its work), so nothing reads the new value during this
   // launch; the next launch sees it through the kernel boundary.
-  __shared__ uint32_t last;
+  uint32_t &last = ctl[1];
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1u;
   __syncthreads();
@@ -858,7 +885,7 @@ static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
 }
 
 uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
-  return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kWaveLdsBytes;
+  return (image_bytes + 15u) / 16u * 16u + (sch.threads / 64u) * kWaveLdsBytes + 16u;
 }
 
 // Blocks of up to 512 threads may use up to 256 VGPRs per lane.

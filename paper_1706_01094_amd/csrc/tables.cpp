@@ -442,14 +442,19 @@ inline uint64_t full_thr(const uint32_t *thr, uint32_t k_first, uint32_t q, long
   return thr[j - k_first];
 }
 inline uint16_t top16(uint64_t v) { return (uint16_t)std::min<uint64_t>(v >> 16, 0xFFFF); }
+// ceil(v / 2^16), clamped to 0xFFFF (no draw reaches it: the upper bound is
+// at most 0xFFFF and strict)
+inline uint16_t top16_up(uint64_t v) {
+  return (uint16_t)std::min<uint64_t>((v + 0xFFFF) >> 16, 0xFFFF);
+}
 }  // namespace
 
 LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t budget) {
   LdsImage im;
-  // the two special directory slots and the records they need: a "never"
-  // slot (nb records, also the target of absent pairs) and one "skip" record
+  // directory of (dim_a + 1) x (dim_c + 1) entries, then (np + 1) rows of
+  // nb + 1 records (the last row and the last record of every row: never)
   auto image_bytes = [](uint32_t da, uint32_t dc, uint32_t np, uint32_t nb) {
-    return (uint64_t)((da * dc + 2) * 2 + 15) / 16 * 16 + ((uint64_t)(np + 1) * nb + 1) * 16;
+    return (uint64_t)((da + 1) * (dc + 1) * 2 + 15) / 16 * 16 + (uint64_t)(np + 1) * (nb + 1) * 16;
   };
   uint32_t dim_a = 0, dim_c = 0, best_lo = 0, best_nb = 1, best_np = 0;
   std::vector<double> pb;
@@ -481,7 +486,7 @@ LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t 
       // directory size is bounded by the pairs' extent; reserve it generously
       const long room = (long)budget - 2048 - 16 * (long)(nb + 1);
       const uint32_t np =
-          room > 0 ? (uint32_t)std::min<size_t>(pairs.size(), room / (16 * nb)) : 0;
+          room > 0 ? (uint32_t)std::min<size_t>(pairs.size(), room / (16 * (nb + 1))) : 0;
       if (np == 0) break;
       const double cov = pbr * pair_cum[np];
       if (cov > best) { best = cov; best_lo = lo; best_nb = nb; best_np = np; }
@@ -498,38 +503,52 @@ LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t 
       }
     };
     extent(best_np);
-    // shrink the pair count until directory + records fit the budget
-    while (best_np > 0 && image_bytes(dim_a, dim_c, best_np, best_nb) > budget) extent(--best_np);
-    if (best_np == 0 || best_np + 1 >= 0xFFFF) {
-      best_np = 0;
+    // shrink the pair count until directory + records fit the budget and
+    // every directory byte offset and record index (in 16-byte units from
+    // the image start) fits 16 bits
+    auto fits = [&](uint32_t np) {
+      const uint64_t bytes = image_bytes(dim_a, dim_c, np, best_nb);
+      return bytes <= budget && (uint64_t)(dim_a + 1) * (dim_c + 1) * 2 <= 0xFFFF &&
+             bytes / 16 <= 0xFFFF;
+    };
+    while (best_np > 0 && !fits(best_np)) extent(--best_np);
+    if (best_np == 0) {
       best_nb = 1;
       best_lo = 0;
       dim_a = dim_c = 0;
     }
   }
-  const uint32_t np = best_np, nb = best_nb;
+  const uint32_t np = best_np, nb = best_nb, rs = nb + 1;
   im.dim_a = dim_a;
   im.dim_c = dim_c;
   im.b_lo = best_lo;
   im.nb = nb;
-  im.dir.assign((size_t)dim_a * dim_c + 2, (uint16_t)np);  // absent pairs: never
-  im.dir[(size_t)dim_a * dim_c + 1] = (uint16_t)(np + 1);   // skip
-  im.records.assign(((size_t)(np + 1) * nb + 1) * 8, 0);
-  for (size_t k = 0; k < (size_t)nb; ++k) im.records[((size_t)np * nb + k) * 8 + 1] = 0xFFFF;
-  im.records[(size_t)(np + 1) * nb * 8 + 0] = 0x8000;
-  im.records[(size_t)(np + 1) * nb * 8 + 1] = 0xFFFF;
+  // directory entries are record indices in 16-byte units from the image
+  // start; absent pairs and the clamped row and column: the never row
+  const uint32_t rec0 = im.dir_bytes() / 16;
+  im.dir.assign((size_t)(dim_a + 1) * (dim_c + 1), (uint16_t)(rec0 + np * rs));
+  im.records.assign((size_t)(np + 1) * rs * 8, 0);
+  auto set_never = [&](size_t rec) {  // lower bound 0xFFFF, upper 0: no draw
+    uint16_t *r = &im.records[rec * 8];
+    std::fill(r, r + 8, (uint16_t)0);
+    r[1] = 0xFFFF;
+  };
+  for (size_t k = 0; k < (size_t)(np + 1) * rs; ++k) set_never(k);
   double covered = 0.0;
   for (uint32_t pi = 0; pi < np; ++pi) {
     const Pair &pr = pairs[pi];
-    im.dir[(size_t)pr.a * dim_c + pr.c] = (uint16_t)pi;
+    im.dir[(size_t)pr.a * (dim_c + 1) + pr.c] = (uint16_t)(rec0 + pi * rs);
     for (uint32_t bi = 0; bi < nb; ++bi) {
       const uint32_t b = best_lo + bi;
-      uint16_t *rec = &im.records[((size_t)pi * nb + bi) * 8];
+      uint16_t *rec = &im.records[((size_t)pi * rs + bi) * 8];
       const uint32_t N = pr.a + b + pr.c, absJ = pr.c - pr.a;
-      if (N < 2 || N > tab.n_max) {  // never decided here
-        rec[0] = 0; rec[1] = 0xFFFF;
+      if (N < 2) {  // no collision: move 0 for every draw below 0xFFFF << 16
+        rec[0] = 0;
+        rec[1] = 0;
+        for (int j = 2; j < 8; ++j) rec[j] = 0xFFFF;
         continue;
       }
+      if (N > tab.n_max) continue;  // never decided here
       const uint32_t par = (N - absJ) & 1u;
       const uint32_t m = (N - absJ) / 2 + 1;
       const uint32_t row = tab.rowbase[(size_t)N * (N + 1) / 2 + absJ] + (b - par) / 2;
@@ -547,7 +566,8 @@ LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t 
       }
       // the kernel's move for the window's first state: (b >> 1) - k_s
       rec[0] = (uint16_t)(int16_t)((long)(b >> 1) - best_ks);
-      for (int j = 0; j < 7; ++j) rec[1 + j] = top16(full_thr(thr, kf, q, best_ks - 1 + j));
+      rec[1] = top16_up(full_thr(thr, kf, q, best_ks - 1));
+      for (int j = 1; j < 7; ++j) rec[1 + j] = top16(full_thr(thr, kf, q, best_ks - 1 + j));
       covered += pr.p * pb[b] * (double)best_w / 4294967296.0;
     }
   }

@@ -52,29 +52,36 @@ bool poisson_full(double mu, uint32_t &k_lo, std::vector<uint64_t> &thr);
 // results never depend on it).
 //
 // A row is addressed by (a', b, c') = (min(n_-1, n_+1), n_0, max(n_-1, n_+1)),
-// which fixes N, |J| and n0.  With np pairs in the image, `dir` holds
-// dim_a * dim_c + 2 entries: dir[a' * dim_c + c'] is the index p of an
-// (a', c') pair, or np for an absent pair; the two extra entries are the
-// "never" slot (np) and the "skip" slot (np + 1).  The record of (p, b) is
-// records[p * nb + b - b_lo]: eight uint16, (b >> 1) - k_s as int16, then the
-// top 16 bits of the full-fiber thresholds thr_{k_s - 1} .. thr_{k_s + 5}
-// (thr_{-1} = 0, thr_{>= m - 1} = 2^32, clamped to 0xFFFF).  With
-// rh = r >> 16 the draw is decided in LDS when T1 < rh < T7 and no inner T
-// equals rh; then the outcome index is k_s + #{inner T < rh}, i.e. the
-// site's n0 moves by -2 ((b >> 1) - k_s - #{inner T < rh}).  Records of the
-// never slot (and of rows the tables do not hold) have T1 = 0xFFFF and
-// decide nothing: the exact global row decides.  The one skip record,
-// records[(np + 1) * nb], is (0x8000, 0xFFFF, 0, ...) and marks a site that
-// does not collide.  Without room for any pair the image is just the
-// directory's two slots and these records (np = 0, nb = 1).
+// which fixes N, |J| and n0.  With np pairs in the image, records come in
+// np + 1 rows of nb + 1: row p holds the pair's records for b = b_lo ..
+// b_lo + nb - 1, then one never record; row np is all never records.  `dir`
+// holds (dim_a + 1) x (dim_c + 1) entries: dir[a' (dim_c + 1) + c'] is the
+// index of the first record of an (a', c') pair (in 16-byte units from the
+// start of the image, whose directory comes first), that of row np for an
+// absent pair, and row dim_a and column dim_c are absent pairs, so that a
+// site's record is image16[dir[min(a', dim_a) (dim_c + 1) + min(c', dim_c)] +
+// min(b - b_lo mod 2^16, nb)] without a range test.  A record is eight
+// uint16: (b >> 1) - k_s as int16, then a lower bound L = ceil(thr_{k_s-1} /
+// 2^16), the top 16 bits of thr_{k_s} .. thr_{k_s+4} (inner values), and the
+// top 16 bits of thr_{k_s+5} as upper bound U (thr_{-1} = 0, thr_{>= m - 1} =
+// 2^32; all clamped to 0xFFFF).  With rh = r >> 16 the draw is decided in LDS
+// when L <= rh < U and no inner value equals rh; then the outcome index is
+// k_s + #{inner value < rh}, i.e. the site's n0 moves by -2 ((b >> 1) - k_s -
+// #{inner value < rh}).  Never records have L = 0xFFFF and U = 0 and decide
+// nothing: the exact global row decides.  A pair with N < 2 (no collision)
+// gets records (0, 0, 0xFFFF x 6): move 0 for every rh < 0xFFFF.  Without room
+// for any pair the image is a one-entry directory and two never records
+// (np = 0, nb = 1).
 struct LdsImage {
   uint32_t dim_a = 0, dim_c = 0, b_lo = 0, nb = 0;
-  std::vector<uint16_t> dir;      // dim_a * dim_c + 2
+  std::vector<uint16_t> dir;      // (dim_a + 1) * (dim_c + 1)
   std::vector<uint16_t> records;  // 8 per record
   double coverage = 0.0;          // expected fraction of site updates decided in LDS
   // serialised: dir padded to 16 bytes, then the records
   std::vector<uint8_t> blob() const;
-  uint32_t dir_bytes() const { return (uint32_t)(((dim_a * dim_c + 2) * 2 + 15) / 16 * 16); }
+  uint32_t dir_bytes() const {
+    return (uint32_t)(((dim_a + 1) * (dim_c + 1) * 2 + 15) / 16 * 16);
+  }
 };
 
 // Build the image for a lattice near the product-Poisson law at

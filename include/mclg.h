@@ -153,7 +153,8 @@ int mclg_check(mclg_ctx *ctx);
 
 /* Select the launch schedule: chunks of eight sites per lane per tile (must
  * be 1), threads per block (64..1024, multiple of 64) and the
- * bytes of LDS each block devotes to its replica's collision image (0..131072;
+ * bytes of LDS each block devotes to its replica's collision image (0..163840,
+ * capped by what the device's LDS leaves beside the per-wave queues;
  * the image caches the most visited table rows, misses read the exact rows in
  * global memory).  Any choice gives identical bits; synchronises the stream. */
 int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t threads_per_block,

@@ -21,7 +21,7 @@ namespace {
 constexpr uint32_t kPadElems = 128;     // array stride granularity (256 B)
 constexpr uint32_t kMinTileSites = 512; // chunk of the step kernel
 constexpr uint32_t kPoisCap = 1024;     // thresholds per initial Poisson law
-constexpr uint32_t kMaxImage = 128 * 1024; // largest LDS collision image
+constexpr uint32_t kMaxImage = 160 * 1024; // largest LDS collision image
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -370,7 +370,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   int dev = 0, v = 0;
   e = hipGetDevice(&dev);
   if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (!e) c->lds_limit = (uint32_t)std::max(0, v - 1024);
+  if (!e) c->lds_limit = (uint32_t)std::max(0, v - 64);  // the block's two counters
   if (!e) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
   if (!e) c->n_cu = (uint32_t)std::max(1, v);
   if (e) return c->hip(e);

@@ -75,7 +75,7 @@ struct PoisDesc {
 struct Schedule {
   uint32_t groups = 1;       // chunks of 8 sites per lane (must be 1)
   uint32_t threads = 1024;   // threads per block
-  uint32_t lds_budget = 112 * 1024;  // bytes of collision image per block
+  uint32_t lds_budget = 160 * 1024;  // bytes of collision image per block (at most)
   uint32_t tile_sites() const { return 512; }  // one chunk: 64 lanes x 8 sites
 };
 
@@ -104,13 +104,14 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // slot's three arrays (6 bytes per site, 256-byte padded) with 32-bit byte
 // offsets.
 constexpr uint64_t kMaxSites = 1ull << 29;
-constexpr uint32_t kQueue = 128;  // LDS queue entries (16 bytes) per wave
+constexpr uint32_t kQueue = 64;  // LDS queue entries (16 bytes) per wave
 // per-wave LDS after the image: the queue of undecided draws
 constexpr uint32_t kWaveLdsBytes = kQueue * 16;
-// Entries of the global overflow area per wave (one chunk's worth of sites;
-// the queue continues there when its LDS part is full), and the number of waves the overflow region is sized for (all waves that
-// can be resident on a 256-CU device).
-constexpr uint32_t kOverflowPerWave = 512;
+// Entries of the global overflow area per wave (the queue continues there
+// when its LDS part is full: up to 32 entries beyond it plus one chunk's
+// 512 sites), and the number of waves the overflow region is sized for (all
+// waves that can be resident on a 256-CU device).
+constexpr uint32_t kOverflowPerWave = 576;
 constexpr uint32_t kOverflowWaves = 256 * 32;
 constexpr uint64_t kOverflowBytes = (uint64_t)kOverflowPerWave * kOverflowWaves * 16;
 

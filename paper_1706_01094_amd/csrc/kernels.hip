@@ -19,6 +19,11 @@ namespace {
 constexpr uint32_t kErrOverflow = 1u;   // a site with N > 65535
 constexpr uint32_t kErrEqRange = 2u;    // C = infinity and N > n_max
 
+// a ^ b ^ k in one instruction (v_bitop3_b32 with the XOR3 truth table)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53,
 // 0xCD9E8D57, Weyl increments 0x9E3779B9, 0xBB67AE85.
 __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
@@ -33,8 +38,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
     // one 32x32 -> 64-bit multiply per product (v_mad_u64_u32)
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y,
-                   (uint32_t)p0);
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k.x), (uint32_t)p1,
+                   xor3((uint32_t)(p0 >> 32), c.w, k.y), (uint32_t)p0);
   }
   return c;
 }
@@ -50,10 +55,10 @@ __device__ __forceinline__ void philox10_x2(uint4 &c0, uint4 &c1, uint2 k) {
     }
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0.x, q0 = (uint64_t)0xD2511F53u * c1.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c0.z, q1 = (uint64_t)0xCD9E8D57u * c1.z;
-    c0 = make_uint4((uint32_t)(p1 >> 32) ^ c0.y ^ k.x, (uint32_t)p1,
-                    (uint32_t)(p0 >> 32) ^ c0.w ^ k.y, (uint32_t)p0);
-    c1 = make_uint4((uint32_t)(q1 >> 32) ^ c1.y ^ k.x, (uint32_t)q1,
-                    (uint32_t)(q0 >> 32) ^ c1.w ^ k.y, (uint32_t)q0);
+    c0 = make_uint4(xor3((uint32_t)(p1 >> 32), c0.y, k.x), (uint32_t)p1,
+                    xor3((uint32_t)(p0 >> 32), c0.w, k.y), (uint32_t)p0);
+    c1 = make_uint4(xor3((uint32_t)(q1 >> 32), c1.y, k.x), (uint32_t)q1,
+                    xor3((uint32_t)(q0 >> 32), c1.w, k.y), (uint32_t)q0);
   }
 }
 
@@ -365,7 +370,7 @@ __device__ __forceinline__ uint32_t site_finish(const SiteLook &s, uint32_t r, b
 // (wave-uniform).  An entry is (x, a | b << 16, c, r) with the site's
 // pre-collision counts; the chunk stores whatever its lane computed for such
 // a site, and the drain overwrites it with the exact outcome.
-constexpr uint32_t kDrainAt = kQueue - 32;  // drain once F exceeds this
+constexpr uint32_t kDrainAt = kQueue + 32;  // drain once F exceeds this
 static_assert(kDrainAt + 512 <= kQueue + kOverflow, "a chunk's draws must fit the queue");
 
 // Site K of every lane whose draw was not decided (and, in a chunk that
@@ -413,7 +418,8 @@ __device__ __forceinline__ void apply_pair(uint32_t &a, uint32_t &b, uint32_t &c
 
 // All eight sites of the lane: directory reads of all eight first, the
 // Philox draws while they are in flight, then record reads and decisions;
-// the undecided draws are queued with the pre-collision counts.
+// the undecided draws are queued with the pre-collision counts before the
+// update.
 __device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
                                              uint32_t (&va)[4], uint32_t (&vb)[4],
                                              uint32_t (&vc)[4], const LdsView &lv, uint4 *queue,

@@ -103,6 +103,9 @@ struct mclg_ctx {
   Layout lay;
   std::shared_ptr<const CollisionTables> tab;
   std::vector<int64_t> t;
+  // steps of every slot launched (with t_off) but not yet added to tslot on
+  // the device; flushed by flush_t() before anything else reads tslot
+  uint32_t t_pending = 0;
   Schedule sch;
   std::vector<TileDev> tiles;
   std::vector<uint32_t> tile_begin, tile_end;
@@ -121,6 +124,12 @@ struct mclg_ctx {
   uint32_t *ticket() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl) + 1; }
   SlotDev *slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
   uint32_t *tslot() { return reinterpret_cast<uint32_t *>(ws + lay.o_tslot); }
+  hipError_t flush_t() {
+    if (!t_pending) return hipSuccess;
+    hipError_t e = launch_add_t(stream, tslot(), 0, n, t_pending);
+    if (!e) t_pending = 0;
+    return e;
+  }
   TileDev *tiles_dev() { return reinterpret_cast<TileDev *>(ws + lay.o_tiles); }
   MomDev *mom() { return reinterpret_cast<MomDev *>(ws + lay.o_mom); }
   TableDev table() {
@@ -161,7 +170,7 @@ struct mclg_ctx {
   }
   ImageDesc *img_desc_dev() { return reinterpret_cast<ImageDesc *>(ws + lay.o_idesc); }
   StepLaunch launch_args(uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
-                         uint32_t n_slots) {
+                         uint32_t n_slots, uint32_t t_off) {
     StepLaunch a;
     a.state = state;
     a.slots = slots();
@@ -171,7 +180,8 @@ struct mclg_ctx {
     a.slot_list = nullptr;
     a.slot_first = slot_first;
     a.n_slots = n_slots;
-    a.ticket = ticket();
+    a.ticket = nullptr;  // the host advances tslot (launch_add_t)
+    a.t_off = t_off;
     a.err = err();
     a.tab = table();
     a.p = params();
@@ -398,17 +408,25 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   return (err & 4u) ? MCLG_E_INTERNAL : err ? MCLG_E_RANGE : MCLG_OK;
 }
 
+// One step of the slots [slot_first, slot_first + n_slots) (their tiles are
+// tile_lo .. tile_hi), whose step is tslot + t_off on the device.
 static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
-                      uint32_t n_slots) {
-  hipError_t e = launch_step(c->sch, c->stream, c->launch_args(tile_lo, tile_hi, slot_first, n_slots));
+                      uint32_t n_slots, uint32_t t_off) {
+  hipError_t e = launch_step(c->sch, c->stream,
+                             c->launch_args(tile_lo, tile_hi, slot_first, n_slots, t_off));
   return c->hip(e);
 }
 
 int mclg_step(mclg_ctx *c, uint64_t n_steps) {
   if (!c) return MCLG_E_INVAL;
   for (uint64_t i = 0; i < n_steps; ++i) {
-    int rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n);
+    if (c->t_pending >= (1u << 30)) {
+      hipError_t e = c->flush_t();
+      if (e) return c->hip(e);
+    }
+    int rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n, c->t_pending);
     if (rc) return rc;
+    ++c->t_pending;
     for (auto &t : c->t) ++t;
   }
   return MCLG_OK;
@@ -416,16 +434,27 @@ int mclg_step(mclg_ctx *c, uint64_t n_steps) {
 
 int mclg_step_replica(mclg_ctx *c, uint32_t r, uint64_t n_steps) {
   if (!c || r >= c->n) return MCLG_E_INVAL;
-  for (uint64_t i = 0; i < n_steps; ++i) {
-    int rc = step_range(c, c->tile_begin[r], c->tile_end[r], r, 1);
-    if (rc) return rc;
-    ++c->t[r];
+  hipError_t e = c->flush_t();
+  if (e) return c->hip(e);
+  for (uint64_t done = 0; done < n_steps;) {
+    const uint32_t m = (uint32_t)std::min<uint64_t>(n_steps - done, 1u << 30);
+    for (uint32_t i = 0; i < m; ++i) {
+      int rc = step_range(c, c->tile_begin[r], c->tile_end[r], r, 1, i);
+      if (rc) return rc;
+      ++c->t[r];
+    }
+    e = launch_add_t(c->stream, c->tslot(), r, 1, m);
+    if (e) return c->hip(e);
+    done += m;
   }
   return MCLG_OK;
 }
 
 int mclg_step_graph(mclg_ctx *c, uint64_t n_steps) {
   if (!c || !c->stream || n_steps == 0) return MCLG_E_INVAL;
+  if (n_steps >= (1u << 30)) return MCLG_E_INVAL;
+  hipError_t fe = c->flush_t();  // the graph's steps count from tslot itself
+  if (fe) return c->hip(fe);
   auto it = c->graphs.find(n_steps);
   if (it == c->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -433,7 +462,8 @@ int mclg_step_graph(mclg_ctx *c, uint64_t n_steps) {
     if (e) return c->hip(e);
     int rc = MCLG_OK;
     for (uint64_t i = 0; i < n_steps && !rc; ++i)
-      rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n);
+      rc = step_range(c, 0, (uint32_t)c->tiles.size(), 0, c->n, (uint32_t)i);
+    if (!rc) rc = c->hip(launch_add_t(c->stream, c->tslot(), 0, c->n, (uint32_t)n_steps));
     e = hipStreamEndCapture(c->stream, &g);
     if (rc) return rc;
     if (e) return c->hip(e);
@@ -465,8 +495,10 @@ int mclg_check(mclg_ctx *c) {
 int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_moments_t *out) {
   if (!c || !out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle)) return MCLG_E_INVAL;
   hipStream_t s = c->stream;
-  hipError_t e = launch_zero(s, reinterpret_cast<unsigned long long *>(c->mom()),
-                             (uint64_t)c->n * (sizeof(MomDev) / 8));
+  hipError_t e = c->flush_t();
+  if (!e)
+    e = launch_zero(s, reinterpret_cast<unsigned long long *>(c->mom()),
+                    (uint64_t)c->n * (sizeof(MomDev) / 8));
   if (!e)
     e = launch_moments(s, c->state, c->slots(), c->tslot(), c->tiles_dev(),
                        (uint32_t)c->tiles.size(), c->sch.tile_sites(),

@@ -87,7 +87,11 @@ struct StepLaunch {
   uint32_t n_tiles;
   const uint32_t *slot_list;  // slots advanced by this launch, or null for a range
   uint32_t slot_first, n_slots;
+  // With `ticket` set, the launch's last block advances tslot of the launch's
+  // slots by one; without it the slots' step is tslot + t_off and tslot is
+  // advanced later (launch_add_t), which saves the end-of-launch ticket.
   uint32_t *ticket, *err;
+  uint32_t t_off;
   TableDev tab;
   StepParams p;
   const ImageDesc *images;    // per slot
@@ -137,6 +141,9 @@ hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *s
                           uint32_t tile_sites, uint32_t no_stream, const int32_t *twiddle,
                           uint32_t n_modes, MomDev *out);
 
+// tslot[slot_first + i] += add for i < n
+hipError_t launch_add_t(hipStream_t s, uint32_t *tslot, uint32_t slot_first, uint32_t n,
+                        uint32_t add);
 hipError_t launch_set_t(hipStream_t s, uint32_t *tslot, const uint32_t *slot_list, uint32_t n,
                         uint32_t value);
 

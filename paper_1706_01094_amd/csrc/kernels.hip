@@ -634,59 +634,62 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     }
     if (i >= ce) break;
     const uint32_t se = min(ce, t0.next);
-    if (t0.slot != cur) {
-      cur = t0.slot;
-      const ImageDesc im = a.images[cur];
-      __syncthreads();  // previous image and chunk counter no longer in use
-      if (threadIdx.x == 0) next_chunk = i;
-      // eight independent 16-byte loads per thread per round, then the stores
-      // (indices clamped into the image; the stores past its end are skipped)
+    // Each wave's first chunk of the segment is fixed, so that its loads are
+    // in flight while the image is copied; the rest go to the block's waves
+    // one at a time from a shared counter, so that waves issued less often
+    // (the hardware favours older waves) take fewer chunks and all finish
+    // together.
+    const bool new_image = t0.slot != cur;
+    cur = t0.slot;
+    const ImageDesc im = a.images[cur];
+    const SlotDev sl = a.slots[cur];
+    const uint32_t tn = a.tslot[cur] + a.t_off;
+    __syncthreads();  // previous image and chunk counter no longer in use
+    sv.t = tn;
+    sv.L = sl.L;
+    sv.tm = p.no_stream ? 0u : sv.t % sl.L;
+    sv.rid = sl.rid;
+    const uint64_t base = reinterpret_cast<uint64_t>(a.state + sl.off);
+    sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    sv.ab = __builtin_amdgcn_readfirstlane(2u * sl.stride);
+    uint32_t k = min(i + wave, se);
+    if (threadIdx.x == 0) next_chunk = i + nwaves;
+    Win cw = locate(t0.x0 + (k - i) * 512u, sv);
+    Raw cr;
+    if (k < se && cw.fast) issue_raw(cw, sv, lane, cr);
+    if (new_image) {
+      // ten independent 16-byte loads per thread per round (a 1024-thread
+      // block moves 160 KiB in one round), then the stores (indices clamped
+      // into the image; the stores past its end are skipped)
       const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
       const uint32_t n16 = im.bytes / 16u, bd = blockDim.x, last = n16 - 1u;
-      for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += 8u * bd) {
-        const uint4 v0 = src[min(b0, last)], v1 = src[min(b0 + bd, last)],
-                    v2 = src[min(b0 + 2u * bd, last)], v3 = src[min(b0 + 3u * bd, last)],
-                    v4 = src[min(b0 + 4u * bd, last)], v5 = src[min(b0 + 5u * bd, last)],
-                    v6 = src[min(b0 + 6u * bd, last)], v7 = src[min(b0 + 7u * bd, last)];
-        lds[b0] = v0;
-        if (b0 + bd < n16) lds[b0 + bd] = v1;
-        if (b0 + 2u * bd < n16) lds[b0 + 2u * bd] = v2;
-        if (b0 + 3u * bd < n16) lds[b0 + 3u * bd] = v3;
-        if (b0 + 4u * bd < n16) lds[b0 + 4u * bd] = v4;
-        if (b0 + 5u * bd < n16) lds[b0 + 5u * bd] = v5;
-        if (b0 + 6u * bd < n16) lds[b0 + 6u * bd] = v6;
-        if (b0 + 7u * bd < n16) lds[b0 + 7u * bd] = v7;
+      for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += 10u * bd) {
+        uint4 v[10];
+#pragma unroll
+        for (uint32_t j = 0; j < 10; ++j) v[j] = src[min(b0 + j * bd, last)];
+        // all ten loads are issued before the first store waits for its data
+        // (otherwise the compiler moves each load into its store's branch)
+#pragma unroll
+        for (uint32_t j = 0; j < 10; ++j)
+          asm volatile("" : "+v"(v[j].x), "+v"(v[j].y), "+v"(v[j].z), "+v"(v[j].w));
+        lds[b0] = v[0];
+#pragma unroll
+        for (uint32_t j = 1; j < 10; ++j)
+          if (b0 + j * bd < n16) lds[b0 + j * bd] = v[j];
       }
-      __syncthreads();
       lv.da2 = im.dim_a * 0x10001u;
       lv.dc2 = im.dim_c * 0x10001u;
       lv.w2 = (im.dim_c + 1u) * 0x10001u;
       lv.blo2 = im.b_lo * 0x10001u;
       lv.nb2 = im.nb * 0x10001u;
-      const SlotDev sl = a.slots[cur];
-      sv.t = a.tslot[cur];
-      sv.L = sl.L;
-      sv.tm = p.no_stream ? 0u : sv.t % sl.L;
-      sv.rid = sl.rid;
-      const uint64_t base = reinterpret_cast<uint64_t>(a.state + sl.off);
-      sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-      sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-      sv.ab = __builtin_amdgcn_readfirstlane(2u * sl.stride);
     }
-    // The segment's chunks go to the block's waves one at a time from a
-    // shared counter, so that waves issued less often (the hardware favours
-    // older waves) take fewer chunks and all finish together.
+    __syncthreads();  // the image and the counter are in place
     const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
     const Rsrc rs = sv.rs();
     const uint32_t ab = sv.ab;
-    uint32_t k = grab_chunk(&next_chunk, lane);
-    Win cw = locate(t0.x0 + (k - i) * 512u, sv);
     uint32_t va[4], vb[4], vc[4];
-    if (k < se) {
-      Raw cr;
-      if (cw.fast) issue_raw(cw, sv, lane, cr);
-      chunk_windows(cw, cr, sv, lane, va, vb, vc);
-    }
+    if (k < se) chunk_windows(cw, cr, sv, lane, va, vb, vc);
     while (k < se) {
       do {
         // The next chunk's loads go out first (its bytes are disjoint from
@@ -747,10 +750,11 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     }
     i = se;
   }
-  // The last block of the launch advances t of every slot in the launch.
-  // Every block has consumed its loads of t before it takes its ticket (the
-  // values shaped its work), so nothing reads the new value during this
-  // launch; the next launch sees it through the kernel boundary.
+  // With a ticket, the last block of the launch advances t of every slot in
+  // the launch.  Every block has consumed its loads of t before it takes its
+  // ticket (the values shaped its work), so nothing reads the new value
+  // during this launch; the next launch sees it through the kernel boundary.
+  if (!a.ticket) return;
   uint32_t &last = ctl[1];
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1u) == gridDim.x - 1u;
@@ -808,6 +812,10 @@ __global__ void k_zero(unsigned long long *p, uint64_t n) {
     p[i] = 0ull;
 }
 
+__global__ void k_add_t(uint32_t *tslot, uint32_t slot_first, uint32_t n, uint32_t add) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    tslot[slot_first + k] += add;
+}
 __global__ void k_set_t(uint32_t *tslot, const uint32_t *slot_list, uint32_t n, uint32_t value) {
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) tslot[slot_list[i]] = value;
 }
@@ -949,6 +957,13 @@ hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *s
   if (n_tiles == 0) return hipSuccess;
   k_moments<<<n_tiles, 256, 0, s>>>(state, slots, tslot, tiles, tile_sites, no_stream, twiddle,
                                     n_modes, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_t(hipStream_t s, uint32_t *tslot, uint32_t slot_first, uint32_t n,
+                        uint32_t add) {
+  if (n == 0 || add == 0) return hipSuccess;
+  k_add_t<<<std::min<uint32_t>(64, (n + 255) / 256), 256, 0, s>>>(tslot, slot_first, n, add);
   return hipGetLastError();
 }
 

@@ -166,6 +166,7 @@ struct mclg_server {
     a.slot_first = 0;
     a.n_slots = n_active;
     a.ticket = ticket();
+    a.t_off = 0;
     a.err = err();
     a.tab = table();
     a.p = params();

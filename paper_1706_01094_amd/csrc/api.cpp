@@ -115,6 +115,7 @@ struct mclg_ctx {
   // LDS collision images (a cache in front of the exact global rows)
   std::vector<double> est_rho, est_u;   // density and velocity each image targets
   std::vector<ImageDesc> img_desc;
+  std::vector<SlotDev> slot_host;  // the device's slot descriptors
   std::vector<uint8_t> img_pool;
   uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
   uint32_t grid_limit = 0;  // 0: occupancy-derived grid
@@ -182,6 +183,13 @@ struct mclg_ctx {
     a.n_slots = n_slots;
     a.ticket = nullptr;  // the host advances tslot (launch_add_t)
     a.t_off = t_off;
+    // one slot whose tiles are exactly the launch's: descriptors by value
+    a.single = (n_slots == 1 && tile_lo == tile_begin[slot_first] &&
+                tile_hi == tile_end[slot_first]) ? 1u : 0u;
+    if (a.single) {
+      a.im1 = img_desc[slot_first];
+      a.sl1 = slot_host[slot_first];
+    }
     a.err = err();
     a.tab = table();
     a.p = params();
@@ -351,6 +359,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   };
   hipError_t e = hipSuccess;
   if (!e) e = up(lay.o_ctrl, ctrl.data(), 256);
+  c->slot_host = slots;
   if (!e) e = up(lay.o_slots, slots.data(), sizeof(SlotDev) * c->n);
   if (!e) e = up(lay.o_tslot, tz.data(), sizeof(uint32_t) * c->n);
   if (!e) e = up(lay.o_tiles, c->tiles.data(), sizeof(TileDev) * c->tiles.size());

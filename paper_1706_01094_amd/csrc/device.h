@@ -92,6 +92,12 @@ struct StepLaunch {
   // advanced later (launch_add_t), which saves the end-of-launch ticket.
   uint32_t *ticket, *err;
   uint32_t t_off;
+  // A launch over one slot's tiles (0 .. n_tiles - 1 from x = 0) carries the
+  // slot's descriptors itself, so that its blocks start without dependent
+  // loads: single = 1, slot slot_first, image im1, slot sl1.
+  uint32_t single;
+  ImageDesc im1;
+  SlotDev sl1;
   TableDev tab;
   StepParams p;
   const ImageDesc *images;    // per slot

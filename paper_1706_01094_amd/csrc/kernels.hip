@@ -627,7 +627,15 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   for (uint32_t i = cb;;) {
     TileDev t0;
     t0.slot = cur;
-    if (i < ce) t0 = a.tiles[i];
+    if (i < ce) {
+      if (a.single) {
+        t0.slot = a.slot_first;
+        t0.x0 = i * 512u;
+        t0.next = a.n_tiles;
+      } else {
+        t0 = a.tiles[i];
+      }
+    }
     if (F && (i >= ce || t0.slot != cur)) {  // queued draws belong to slot `cur`
       drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
       F = 0;
@@ -639,12 +647,12 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     // one at a time from a shared counter, so that waves issued less often
     // (the hardware favours older waves) take fewer chunks and all finish
     // together.
-    const bool new_image = t0.slot != cur;
+    const bool new_image = t0.slot != cur, first = cur == 0xFFFFFFFFu;
     cur = t0.slot;
-    const ImageDesc im = a.images[cur];
-    const SlotDev sl = a.slots[cur];
+    const ImageDesc im = a.single ? a.im1 : a.images[cur];
+    const SlotDev sl = a.single ? a.sl1 : a.slots[cur];
     const uint32_t tn = a.tslot[cur] + a.t_off;
-    __syncthreads();  // previous image and chunk counter no longer in use
+    if (!first) __syncthreads();  // previous image and chunk counter no longer in use
     sv.t = tn;
     sv.L = sl.L;
     sv.tm = p.no_stream ? 0u : sv.t % sl.L;

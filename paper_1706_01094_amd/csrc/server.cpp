@@ -167,6 +167,7 @@ struct mclg_server {
     a.n_slots = n_active;
     a.ticket = ticket();
     a.t_off = 0;
+    a.single = 0;
     a.err = err();
     a.tab = table();
     a.p = params();

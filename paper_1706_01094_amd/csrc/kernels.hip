@@ -608,6 +608,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
   const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
+  const bool youngest = nwaves >= 8u && wave + 4u >= nwaves;
   // after the image and the queues: the block's next unclaimed chunk of the
   // segment, and the last-block flag (so that the image starts at LDS 0)
   uint32_t *const ctl =
@@ -702,7 +703,13 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       do {
         // The next chunk's loads go out first (its bytes are disjoint from
         // this chunk's); they are taken only after this chunk is stored.
-        const uint32_t nk = grab_chunk(&next_chunk, lane);
+        // The last wave of each SIMD (waves are spread over the SIMDs in
+        // order, and the hardware issues a SIMD's youngest wave last) leaves
+        // the segment's last nwaves chunks to the others, so that the
+        // block's final chunks are not held by its slowest waves.
+        uint32_t nk = se;
+        if (!(youngest && *(volatile uint32_t *)&next_chunk + nwaves >= se))
+          nk = grab_chunk(&next_chunk, lane);
         const bool has_next = nk < se;
         Win nw = cw;
         Raw nr;

@@ -608,7 +608,14 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
   const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
   uint32_t F = 0;  // queue fill (wave-uniform), all draws of slot `cur`
+  // Waves are spread over the four SIMDs in order, and the hardware issues
+  // a SIMD's younger waves after its older ones, so a chunk held by a young
+  // wave at the end of a segment finishes last: the youngest wave of each
+  // SIMD stops claiming once at most nwaves chunks are left, the next
+  // youngest once at most nwaves / 2 are.  The oldest wave of each SIMD
+  // always claims, so every chunk is taken.
   const bool youngest = nwaves >= 8u && wave + 4u >= nwaves;
+  const bool second = nwaves >= 12u && wave + 8u >= nwaves && !youngest;
   // after the image and the queues: the block's next unclaimed chunk of the
   // segment, and the last-block flag (so that the image starts at LDS 0)
   uint32_t *const ctl =
@@ -642,7 +649,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       F = 0;
     }
     if (i >= ce) break;
-    const uint32_t se = min(ce, t0.next);
+    t0.x0 = __builtin_amdgcn_readfirstlane(t0.x0);
+    const uint32_t se = __builtin_amdgcn_readfirstlane(min(ce, t0.next));
     // Each wave's first chunk of the segment is fixed, so that its loads are
     // in flight while the image is copied; the rest go to the block's waves
     // one at a time from a shared counter, so that waves issued less often
@@ -654,10 +662,11 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     const SlotDev sl = a.single ? a.sl1 : a.slots[cur];
     const uint32_t tn = a.tslot[cur] + a.t_off;
     if (!first) __syncthreads();  // previous image and chunk counter no longer in use
-    sv.t = tn;
-    sv.L = sl.L;
-    sv.tm = p.no_stream ? 0u : sv.t % sl.L;
-    sv.rid = sl.rid;
+    // (wave-uniform values kept in scalar registers)
+    sv.t = __builtin_amdgcn_readfirstlane(tn);
+    sv.L = __builtin_amdgcn_readfirstlane(sl.L);
+    sv.tm = p.no_stream ? 0u : sv.t % sv.L;
+    sv.rid = __builtin_amdgcn_readfirstlane(sl.rid);
     const uint64_t base = reinterpret_cast<uint64_t>(a.state + sl.off);
     sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
@@ -703,13 +712,13 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       do {
         // The next chunk's loads go out first (its bytes are disjoint from
         // this chunk's); they are taken only after this chunk is stored.
-        // The last wave of each SIMD (waves are spread over the SIMDs in
-        // order, and the hardware issues a SIMD's youngest wave last) leaves
-        // the segment's last nwaves chunks to the others, so that the
-        // block's final chunks are not held by its slowest waves.
+        // (young waves leave the segment's last chunks to the older ones)
         uint32_t nk = se;
-        if (!(youngest && *(volatile uint32_t *)&next_chunk + nwaves >= se))
+        if (!(youngest || second) ||
+            __builtin_amdgcn_readfirstlane(__atomic_load_n(&next_chunk, __ATOMIC_RELAXED)) +
+                    (youngest ? nwaves : nwaves / 2u) < se)
           nk = grab_chunk(&next_chunk, lane);
+        nk = __builtin_amdgcn_readfirstlane(nk);  // wave-uniform after the join
         const bool has_next = nk < se;
         Win nw = cw;
         Raw nr;

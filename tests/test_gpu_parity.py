@@ -84,12 +84,16 @@ def test_ragged_tiles_and_schedules(groups, threads, lds):
 
 
 @pytest.mark.parametrize("threads,blocks,lds", [(64, 1, 112 << 10), (256, 2, 96 << 10),
-                                                (1024, 1, 112 << 10), (512, 3, 0)])
+                                                (1024, 1, 112 << 10), (512, 3, 0),
+                                                (768, 2, 96 << 10), (832, 3, 64 << 10),
+                                                (576, 1, 0)])
 def test_long_runs_per_wave(threads, blocks, lds):
     """A capped grid gives each wave long runs of contiguous chunks: the
     boundary vectors passed from chunk to chunk, drains between chunks and the
     chunks that wrap around the lattice end, over shifts t = 0..23 (every
-    misalignment of the shifted windows)."""
+    misalignment of the shifted windows).  Block sizes of 8, 9, 12, 13 and 16
+    waves cover every rule by which a block's young waves stop claiming its
+    last chunks (every chunk must still be taken)."""
     L = 3 * 2 ** 14 + 37
     g, o = pair(L, 31, rho=30.0, u0=0.1)
     g.set_schedule(1, threads, lds)

@@ -545,20 +545,13 @@ __device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint3
   bload4(v.rs(), vo, v.ab + 2u * w.xs, r.z);
   bload4(v.rs(), vo, 2u * v.ab + 2u * w.sp, r.p);
 }
-// The chunk's three windows as eight consecutive sites per lane: the loaded
-// vectors of a fast chunk, element by element for a chunk whose windows wrap
-// around the end of the lattice (or pass it).  Sites past the end read as
-// empty (N = 0): they do not collide and are never stored.
-__device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, const SlotView &v,
-                                              uint32_t lane, uint32_t (&va)[4],
-                                              uint32_t (&vb)[4], uint32_t (&vc)[4]) {
-  if (w.fast) {
-    for (int j = 0; j < 4; ++j) {
-      va[j] = r.m[j];
-      vb[j] = r.z[j];
-      vc[j] = r.p[j];
-    }
-  } else {
+// The chunk's three windows as eight consecutive sites per lane, in place in
+// `r`: a fast chunk's vectors are there already; a chunk whose windows wrap
+// around the end of the lattice (or pass it) is read element by element.
+// Sites past the end read as empty (N = 0) and are never stored.
+__device__ __forceinline__ void chunk_fill(const Win &w, Raw &r, const SlotView &v,
+                                           uint32_t lane) {
+  if (!w.fast) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const uint32_t x = w.xs + 8u * lane + e;
@@ -571,12 +564,12 @@ __device__ __forceinline__ void chunk_windows(const Win &w, const Raw &r, const 
         eb = bload2(v.rs(), 2u * x, v.ab);
         ec = bload2(v.rs(), 2u * pp, 2u * v.ab);
       }
-      set16(va, e, ea); set16(vb, e, eb); set16(vc, e, ec);
+      set16(r.m, e, ea); set16(r.z, e, eb); set16(r.p, e, ec);
     }
   }
   // complete here, so that no load of this chunk is still counted when the
   // next chunk's loads are issued
-  for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(va[j]), "+v"(vb[j]), "+v"(vc[j]));
+  for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(r.m[j]), "+v"(r.z[j]), "+v"(r.p[j]));
 }
 
 // The block's next chunk index (an LDS counter), wave-uniform.
@@ -706,70 +699,74 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
     const Rsrc rs = sv.rs();
     const uint32_t ab = sv.ab;
-    uint32_t va[4], vb[4], vc[4];
-    if (k < se) chunk_windows(cw, cr, sv, lane, va, vb, vc);
-    while (k < se) {
-      do {
-        // The next chunk's loads go out first (its bytes are disjoint from
-        // this chunk's); they are taken only after this chunk is stored.
-        // (young waves leave the segment's last chunks to the older ones)
-        uint32_t nk = se;
-        if (!(youngest || second) ||
-            __builtin_amdgcn_readfirstlane(__atomic_load_n(&next_chunk, __ATOMIC_RELAXED)) +
-                    (youngest ? nwaves : nwaves / 2u) < se)
-          nk = grab_chunk(&next_chunk, lane);
-        nk = __builtin_amdgcn_readfirstlane(nk);  // wave-uniform after the join
-        const bool has_next = nk < se;
-        Win nw = cw;
-        Raw nr;
-        if (has_next) {
-          nw = locate(t0.x0 + (nk - i) * 512u, sv);
-          if (nw.fast) issue_raw(nw, sv, lane, nr);
-        }
+    // One chunk: the next chunk's loads go out first (into the other
+    // register set; its bytes are disjoint from this chunk's), then this
+    // chunk is decided and stored, then the next chunk's vectors are taken.
+    // The loop alternates the two register sets, so nothing is copied.
+    auto one = [&](Raw &cur, Raw &nxt) -> bool {
+      // (young waves leave the segment's last chunks to the older ones)
+      uint32_t nk = se;
+      if (!(youngest || second) ||
+          __builtin_amdgcn_readfirstlane(__atomic_load_n(&next_chunk, __ATOMIC_RELAXED)) +
+                  (youngest ? nwaves : nwaves / 2u) < se)
+        nk = grab_chunk(&next_chunk, lane);
+      nk = __builtin_amdgcn_readfirstlane(nk);  // wave-uniform after the join
+      const bool has_next = nk < se;
+      Win nw = cw;
+      if (has_next) {
+        nw = locate(t0.x0 + (nk - i) * 512u, sv);
+        if (nw.fast) issue_raw(nw, sv, lane, nxt);
+      }
 
-        // ---- collide: LDS image first, the rest into the wave's queue ----
-        {
-          const uint32_t x8 = cw.xs + 8u * lane;
-          const bool slow = __builtin_amdgcn_readfirstlane(cw.fast) == 0u;
-          if (p.C != 0) {
-            uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
-            uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
-            decide_eight(w0, w1, key, va, vb, vc, lv, queue, ovr, F, slow, x8, L);
-          } else {
-            queue_saturated(va, vb, vc, queue, ovr, F, slow, x8, L);
-          }
-        }
-
-        // ---- store ----
-        if (cw.fast) {
-          const uint32_t vo = 16u * lane;
-          bstore4(rs, vo, 2u * cw.sm, va);
-          bstore4(rs, vo, ab + 2u * cw.xs, vb);
-          bstore4(rs, vo, 2u * ab + 2u * cw.sp, vc);
+      // ---- collide: LDS image first, the rest into the wave's queue ----
+      {
+        const uint32_t x8 = cw.xs + 8u * lane;
+        const bool slow = __builtin_amdgcn_readfirstlane(cw.fast) == 0u;
+        if (p.C != 0) {
+          uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
+          uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
+          decide_eight(w0, w1, key, cur.m, cur.z, cur.p, lv, queue, ovr, F, slow, x8, L);
         } else {
+          queue_saturated(cur.m, cur.z, cur.p, queue, ovr, F, slow, x8, L);
+        }
+      }
+
+      // ---- store ----
+      if (cw.fast) {
+        const uint32_t vo = 16u * lane;
+        bstore4(rs, vo, 2u * cw.sm, cur.m);
+        bstore4(rs, vo, ab + 2u * cw.xs, cur.z);
+        bstore4(rs, vo, 2u * ab + 2u * cw.sp, cur.p);
+      } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const uint32_t x = cw.xs + 8u * lane + e;
-            if (x < L) {
-              uint32_t pm = x + tm;
-              pm -= (pm >= L) ? L : 0u;
-              const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-              bstore2(rs, 2u * pm, 0u, get16(va, e));
-              bstore2(rs, 2u * x, ab, get16(vb, e));
-              bstore2(rs, 2u * pp, 2u * ab, get16(vc, e));
-            }
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t x = cw.xs + 8u * lane + e;
+          if (x < L) {
+            uint32_t pm = x + tm;
+            pm -= (pm >= L) ? L : 0u;
+            const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+            bstore2(rs, 2u * pm, 0u, get16(cur.m, e));
+            bstore2(rs, 2u * x, ab, get16(cur.z, e));
+            bstore2(rs, 2u * pp, 2u * ab, get16(cur.p, e));
           }
         }
-        // ---- the next chunk's windows ----
-        if (has_next) chunk_windows(nw, nr, sv, lane, va, vb, vc);
-        cw = nw;
-        k = nk;
-      } while (k < se && F <= kDrainAt);
+      }
+      // ---- the next chunk's windows ----
+      if (has_next) chunk_fill(nw, nxt, sv, lane);
+      cw = nw;
+      k = nk;
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
       // fit.
-      if (k < se) {
+      if (has_next && F > kDrainAt) {
         drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
+      }
+      return has_next;
+    };
+    if (k < se) {
+      Raw rb;
+      chunk_fill(cw, cr, sv, lane);
+      while (one(cr, rb) && one(rb, cr)) {
       }
     }
     i = se;

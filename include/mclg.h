@@ -68,6 +68,7 @@ enum {
 enum { MCLG_INIT_COUNTS = 1, MCLG_INIT_POISSON = 2 };
 
 #define MCLG_MAX_MODES 8
+#define MCLG_MAX_HIST_BINS 4096
 
 typedef struct mclg_ctx mclg_ctx;
 
@@ -146,6 +147,19 @@ int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
 
 /* Logical counts of one replica into host_out[3][L]; synchronises. */
 int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
+
+/* Occupation-number histograms, the distributions P(n_i) compared with the
+ * Poisson law of Eq. (poisson) and, in the rest-parity sector, with Fig. 1
+ * of the D1Q3 section.  Adds, for every replica r, velocity i (0, 1, 2 for
+ * v = -1, 0, +1) and site x, one to
+ *   dev_hist[(r * 3 + i) * n_bins + min(n_i(x), n_bins - 1)],
+ * so the last bin counts every n_i >= n_bins - 1.  dev_hist is device memory
+ * of n_replicas * 3 * n_bins uint64 owned by the caller, who clears it; calls
+ * accumulate, so repeated calls sum histograms over time.  Asynchronous on the
+ * context's stream (read dev_hist after synchronising with it).  n_bins in
+ * 1..MCLG_MAX_HIST_BINS, else MCLG_E_INVAL; overflow of a site is reported by
+ * mclg_check, not here. */
+int mclg_histogram(mclg_ctx *ctx, uint32_t n_bins, uint64_t *dev_hist);
 
 /* Sticky error state of the device (MCLG_E_RANGE if any site overflowed);
  * synchronises. */

@@ -540,6 +540,14 @@ int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_mom
   return read_err(c);
 }
 
+int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {
+  if (!c || !hist || n_bins == 0 || n_bins > MCLG_MAX_HIST_BINS) return MCLG_E_INVAL;
+  const hipError_t e =
+      launch_histogram(c->stream, c->state, c->slots(), c->tiles_dev(), (uint32_t)c->tiles.size(),
+                       c->sch.tile_sites(), n_bins, reinterpret_cast<unsigned long long *>(hist));
+  return e ? c->hip(e) : MCLG_OK;
+}
+
 int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
   if (!c || !out || r >= c->n) return MCLG_E_INVAL;
   const uint64_t L = c->L[r], stride = c->lay.stride[r];

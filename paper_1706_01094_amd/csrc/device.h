@@ -147,6 +147,11 @@ hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *s
                           uint32_t tile_sites, uint32_t no_stream, const int32_t *twiddle,
                           uint32_t n_modes, MomDev *out);
 
+// hist[(slot * 3 + i) * n_bins + min(n_i, n_bins - 1)] += 1 over every site
+hipError_t launch_histogram(hipStream_t s, const uint16_t *state, const SlotDev *slots,
+                            const TileDev *tiles, uint32_t n_tiles, uint32_t tile_sites,
+                            uint32_t n_bins, unsigned long long *hist);
+
 // tslot[slot_first + i] += add for i < n
 hipError_t launch_add_t(hipStream_t s, uint32_t *tslot, uint32_t slot_first, uint32_t n,
                         uint32_t add);

@@ -909,6 +909,54 @@ __global__ void __launch_bounds__(256) k_moments(
   }
 }
 
+// Occupation-number histograms.  Each block takes a contiguous run of tiles
+// (tiles are ordered by slot), reads every velocity array in physical order
+// (a marginal histogram does not depend on which site an element belongs
+// to), bins in LDS, and adds each non-empty bin to the slot's global row with
+// one 64-bit atomic whenever the run moves to another slot or ends.
+__global__ void __launch_bounds__(256) k_histogram(
+    const uint16_t *__restrict__ state, const SlotDev *__restrict__ slots,
+    const TileDev *__restrict__ tiles, uint32_t n_tiles, uint32_t tile_sites, uint32_t n_bins,
+    unsigned long long *__restrict__ hist) {
+  extern __shared__ uint32_t bins[];  // [3][n_bins]
+  const uint32_t per = (n_tiles + gridDim.x - 1u) / gridDim.x;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  if (t_begin >= t_end) return;
+  const uint32_t nb3 = 3u * n_bins, top = n_bins - 1u;
+  for (uint32_t j = threadIdx.x; j < nb3; j += blockDim.x) bins[j] = 0u;
+  uint32_t cur = tiles[t_begin].slot;
+  auto flush = [&](uint32_t slot) {
+    __syncthreads();
+    unsigned long long *row = hist + (uint64_t)slot * nb3;
+    for (uint32_t j = threadIdx.x; j < nb3; j += blockDim.x) {
+      const uint32_t v = bins[j];
+      if (v) {
+        atomicAdd(&row[j], (unsigned long long)v);
+        bins[j] = 0u;
+      }
+    }
+    __syncthreads();
+  };
+  __syncthreads();
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    const TileDev tile = tiles[t];
+    if (tile.slot != cur) {
+      flush(cur);
+      cur = tile.slot;
+    }
+    const SlotDev sl = slots[tile.slot];
+    const uint32_t end = min(sl.L, tile.x0 + tile_sites);
+    for (uint32_t x = tile.x0 + threadIdx.x; x < end; x += blockDim.x) {
+#pragma unroll
+      for (uint32_t i = 0; i < 3u; ++i) {
+        const uint32_t n = state[sl.off + (uint64_t)i * sl.stride + x];
+        atomicAdd(&bins[i * n_bins + min(n, top)], 1u);
+      }
+    }
+  }
+  flush(cur);
+}
+
 }  // namespace
 
 template <int MAXT>
@@ -978,6 +1026,16 @@ hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *s
   if (n_tiles == 0) return hipSuccess;
   k_moments<<<n_tiles, 256, 0, s>>>(state, slots, tslot, tiles, tile_sites, no_stream, twiddle,
                                     n_modes, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_histogram(hipStream_t s, const uint16_t *state, const SlotDev *slots,
+                            const TileDev *tiles, uint32_t n_tiles, uint32_t tile_sites,
+                            uint32_t n_bins, unsigned long long *hist) {
+  if (n_tiles == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>(n_tiles, 2048u);
+  k_histogram<<<blocks, 256, 3u * n_bins * sizeof(uint32_t), s>>>(state, slots, tiles, n_tiles,
+                                                                  tile_sites, n_bins, hist);
   return hipGetLastError();
 }
 

@@ -1,0 +1,340 @@
+"""The paper's D1Q3 experiments, run on the batched GPU engine.
+
+* ``parity_histograms`` -- Fig. 1 of the D1Q3 section: occupation-number
+  distributions when every site starts with an even number of rest
+  particles (a parity that collisions never change).
+* ``equilibrium_means`` -- Fig. 3: time-averaged site means <n_i> against
+  the velocity u, beside Eq. (D1Q3equil) and the lattice Boltzmann
+  equilibrium of Eq. (LBequil).
+* ``pi_decay`` -- Fig. 5: decay of the ensemble mean of the pi moment from a
+  uniform initial state, with streaming and, as the figure's variant,
+  without it; beside Eq. (D1Q3relax) and its linearisation Eq. (D1Q3relax2).
+* ``correlations`` -- the normalised correlator of Eq. (corr) and the error
+  function E(u) of Eq. (error), here for D1Q3.
+
+Every simulated number comes from the library's kernels (``mclg.Lattice``);
+this module only sets up the inputs, calls the engine and turns its exact
+integer sums into the figures' statistics.  The predictions it prints are the
+paper's closed forms, evaluated here in double precision.
+
+Run ``python -m paper_1706_01094_amd.figures fig1|fig3|fig5|corr [--quick]``.
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import time
+from typing import Sequence
+
+import numpy as np
+
+from . import mclg
+
+SQRT2 = math.sqrt(2.0)
+
+
+# ---- closed forms ---------------------------------------------------------
+def feq(rho: float, u: float) -> np.ndarray:
+    """Eq. (D1Q3equil): the entropic D1Q3 equilibrium (f_-1, f_0, f_+1)."""
+    s = math.sqrt(1.0 + 3.0 * u * u)
+    return np.array([rho * (-1.0 - 3.0 * u + 2.0 * s) / 6.0,
+                     rho * (2.0 - s) * 2.0 / 3.0,
+                     rho * (-1.0 + 3.0 * u + 2.0 * s) / 6.0])
+
+
+def f_lb(rho: float, u: float) -> np.ndarray:
+    """Eq. (LBequil) for D1Q3: weights (1/6, 2/3, 1/6), theta = 1/3."""
+    w = np.array([1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0])
+    v = np.array([-1.0, 0.0, 1.0])
+    return rho * w * (1.0 + 3.0 * v * u + 4.5 * (v * u) ** 2 - 1.5 * u * u)
+
+
+def parity_sector_means(rho: float):
+    """(f_+-1, f_0) of the product measure restricted to even rest counts at
+    u = 0: n_+-1 ~ Poisson(f_1), n_0 ~ Poisson(f_0) conditioned on even, with
+    f_0 = 4 f_1 (the equilibrium relation f_0^2 = 16 f_-1 f_+1 of the D1Q3
+    section) and total mean density 2 f_1 + f_0 tanh(f_0) = rho."""
+    lo, hi = 0.0, rho / 2.0
+    for _ in range(200):
+        f1 = 0.5 * (lo + hi)
+        if 2.0 * f1 + 4.0 * f1 * math.tanh(4.0 * f1) < rho:
+            lo = f1
+        else:
+            hi = f1
+    f1 = 0.5 * (lo + hi)
+    return f1, 4.0 * f1
+
+
+def poisson_pmf(mu: float, n: int) -> np.ndarray:
+    k = np.arange(n)
+    lg = np.array([math.lgamma(i + 1.0) for i in k])
+    return np.exp(k * math.log(mu) - mu - lg) if mu > 0 else (k == 0).astype(float)
+
+
+def even_poisson_pmf(mu: float, n: int) -> np.ndarray:
+    p = poisson_pmf(mu, n)
+    p[1::2] = 0.0
+    return p * 2.0 / (1.0 + math.exp(-2.0 * mu))
+
+
+def pi_moment(n) -> np.ndarray:
+    """pi = sqrt(2) (n_-1 - n_0 / 2 + n_+1), the non-conserved D1Q3 moment."""
+    n = np.asarray(n, dtype=np.float64)
+    return SQRT2 * (n[..., 0] - n[..., 1] / 2.0 + n[..., 2])
+
+
+def pi_relax(pi0: float, n_coll, rho: float, u: float = 0.0, lam: float = 1.0,
+             coef: float = math.sqrt(8.0)) -> np.ndarray:
+    """Eq. (D1Q3relax): pi~ after n_coll collisions.  The printed equation
+    carries 2 sqrt(6) as ``coef``; expanding Eq. (1Ddecay) about pi^eq gives
+    sqrt(8), the default here."""
+    s = math.sqrt(1.0 + 3.0 * u * u)
+    k = coef * rho * s
+    n_coll = np.asarray(n_coll, dtype=np.float64)
+    return k * pi0 / (np.exp(n_coll * lam * s / rho) * (k + pi0) - pi0)
+
+
+def pi_relax_linear(pi0: float, n_coll, rho: float, lam: float = 1.0) -> np.ndarray:
+    """Eq. (D1Q3relax2): exp(-C lambda / rho) pi~(0)."""
+    return pi0 * np.exp(-np.asarray(n_coll, dtype=np.float64) * lam / rho)
+
+
+# ---- experiments ----------------------------------------------------------
+def uniform_counts(init: Sequence[int], L: int, replicas: int) -> np.ndarray:
+    """Counts for Lattice(counts=...): every site of every replica in state
+    init = (n_-1, n_0, n_+1)."""
+    one = np.asarray(init, dtype=np.uint16)[:, None].repeat(L, 1)
+    return np.ascontiguousarray(np.broadcast_to(one, (replicas, 3, L))).reshape(-1)
+
+
+def parity_histograms(L: int = 100, C: int = 10, rho: int = 12, equil: int = 20000,
+                      steps: int = 80000, replicas: int = 1, every: int = 1, seed: int = 1,
+                      n_bins: int = 64, init=None) -> dict:
+    """Fig. 1 set-up: every site starts as (a, b, a) with b even (by default
+    b = 2 round(rho / 3), a = (rho - b) / 2, i.e. (2, 8, 2) at rho = 12); the
+    histograms of n_i are accumulated every ``every`` steps over ``steps``
+    steps after ``equil`` steps, over all sites of ``replicas`` independent
+    lattices."""
+    if init is None:
+        b = 2 * round(rho / 3)
+        if (rho - b) % 2:
+            raise ValueError("rho must be even for the (a, b, a) initial state")
+        init = ((rho - b) // 2, b, (rho - b) // 2)
+    if init[1] % 2:
+        raise ValueError("the parity experiment starts from an even rest count")
+    lat = mclg.Lattice([L] * replicas, seed, C=C, counts=uniform_counts(init, L, replicas))
+    torch = lat.torch
+    try:
+        t0 = time.time()
+        lat.step(equil)
+        h = torch.zeros((replicas, 3, n_bins), dtype=torch.int64, device=lat.device)
+        for _ in range(steps // every):
+            lat.step(every)
+            lat.histogram(n_bins, out=h)
+        torch.cuda.synchronize(lat.device)
+        wall = time.time() - t0
+        rc = lat.check()
+        mom = lat.moments()
+    finally:
+        lat.close()
+    hist = h.sum(0).cpu().numpy()
+    P = hist / hist.sum(1, keepdims=True)
+    f1, f0 = parity_sector_means(float(sum(init)))
+    return {"init": tuple(init), "L": L, "replicas": replicas, "C": C, "equil": equil,
+            "steps": steps, "every": every, "hist": hist, "P": P,
+            "pred_moving": poisson_pmf(f1, n_bins), "pred_rest": even_poisson_pmf(f0, n_bins),
+            "pred_rest_unconstrained": poisson_pmf(f0 * math.tanh(f0), n_bins),
+            "f1": f1, "f0": f0, "sum_N": [m["sum_N"] for m in mom],
+            "sum_J": [m["sum_J"] for m in mom], "n0_odd": sum(m["n0_odd"] for m in mom),
+            "check": rc, "wall_s": wall}
+
+
+def equilibrium_means(us: Sequence[float], rho: float = 36.0, L: int = 100, C: int = 10,
+                      equil: int = 15000, steps: int = 15000, every: int = 10, seed: int = 1,
+                      blocks: int = 10) -> dict:
+    """Fig. 3 set-up: one lattice per velocity u, all in one batched context,
+    each started from the product-Poisson state at f^eq(rho, u); the site
+    means are averaged every ``every`` steps over ``steps`` steps after
+    ``equil`` steps.  The standard error comes from ``blocks`` batch means.
+    Predictions use each lattice's own conserved rho^ = sum N / L and
+    u^ = sum J / sum N."""
+    us = np.asarray(us, dtype=np.float64)
+    R = len(us)
+    lat = mclg.Lattice([L] * R, seed, C=C, rho=np.full(R, rho), u0=us)
+    try:
+        t0 = time.time()
+        lat.step(equil)
+        n_samp = steps // every
+        samples = np.zeros((n_samp, R, 3))
+        for k in range(n_samp):
+            lat.step(every)
+            m = lat.moments()
+            samples[k] = [[v / L for v in mr["sum_n"]] for mr in m]
+        wall = time.time() - t0
+        mom = lat.moments()
+    finally:
+        lat.close()
+    mean = samples.mean(0)
+    nb = max(2, min(blocks, n_samp))
+    bm = np.array([b.mean(0) for b in np.array_split(samples, nb)])
+    se = bm.std(0, ddof=1) / math.sqrt(nb)
+    rho_hat = np.array([m["sum_N"] / L for m in mom])
+    u_hat = np.array([m["sum_J"] / m["sum_N"] if m["sum_N"] else 0.0 for m in mom])
+    return {"u0": us, "rho_hat": rho_hat, "u_hat": u_hat, "mean": mean, "se": se,
+            "feq": np.array([feq(r, u) for r, u in zip(rho_hat, u_hat)]),
+            "f_lb": np.array([f_lb(r, u) for r, u in zip(rho_hat, u_hat)]),
+            "L": L, "C": C, "equil": equil, "steps": steps, "every": every, "wall_s": wall}
+
+
+def pi_decay(init: Sequence[int] = (100, 100, 100), L: int = 1000, replicas: int = 1000,
+             C: int = 10, steps: int = 100, stream: bool = True, seed: int = 1,
+             n_max: int = 300, lam=(1, 1)) -> dict:
+    """Fig. 5 set-up: ``replicas`` lattices of L sites, every site in state
+    ``init``; records the ensemble mean of pi after every step (C collisions
+    each) with or without streaming.  The per-step mean is exact (integer
+    sums); its standard error comes from the spread of the replica means."""
+    flags = 0 if stream else mclg.FLAG_NO_STREAM
+    lat = mclg.Lattice([L] * replicas, seed, C=C, lam=lam, n_max=n_max, flags=flags,
+                       counts=uniform_counts(init, L, replicas))
+    try:
+        t0 = time.time()
+        mean = np.zeros(steps + 1)
+        se = np.zeros(steps + 1)
+        for t in range(steps + 1):
+            if t:
+                lat.step(1)
+            m = lat.moments()
+            per = pi_moment(np.array([mr["sum_n"] for mr in m], dtype=np.float64)) / L
+            mean[t] = per.mean()
+            se[t] = per.std(ddof=1) / math.sqrt(replicas) if replicas > 1 else float("nan")
+        wall = time.time() - t0
+        rc = lat.check()
+        sum_N = sum(mr["sum_N"] for mr in m)
+    finally:
+        lat.close()
+    rho = float(sum(init))
+    lam_f = lam[0] / lam[1]
+    u = (init[2] - init[0]) / rho if rho else 0.0
+    pi_eq = float(pi_moment(feq(rho, u)))
+    n_coll = C * np.arange(steps + 1)
+    pi0 = float(pi_moment(np.asarray(init))) - pi_eq
+    return {"init": tuple(init), "L": L, "replicas": replicas, "C": C, "stream": stream,
+            "mean": mean, "se": se, "pi_eq": pi_eq, "n_coll": n_coll,
+            "pred_sqrt8": pi_eq + pi_relax(pi0, n_coll, rho, u, lam_f),
+            "pred_printed": pi_eq + pi_relax(pi0, n_coll, rho, u, lam_f, coef=2 * math.sqrt(6)),
+            "pred_linear": pi_eq + pi_relax_linear(pi0, n_coll, rho, lam_f),
+            "sum_N": sum_N, "check": rc, "wall_s": wall}
+
+
+def correlations(us: Sequence[float], rho: float = 36.0, L: int = 4096, C: int = 10,
+                 equil: int = 1000, steps: int = 5000, every: int = 10, seed: int = 1,
+                 blocks: int = 10, n_max: int = 255) -> dict:
+    """Eq. (corr) and Eq. (error) for D1Q3: one lattice per velocity u, each
+    started from the product-Poisson state at f^eq(rho, u); <n_i n_j> is the
+    average over sites and over samples every ``every`` steps (after
+    ``equil`` steps) of the exact sums of n_i n_j, normalised as
+    K_ij = (<n_i n_j> - f_i f_j) / sqrt(f_i f_j) with f = f^eq(rho^, u^) from
+    each lattice's conserved sums, and E(u) = sum_ij (K_ij - delta_ij)^2.
+    The standard error of K comes from ``blocks`` batch means."""
+    us = np.asarray(us, dtype=np.float64)
+    R = len(us)
+    lat = mclg.Lattice([L] * R, seed, C=C, n_max=n_max, rho=np.full(R, rho), u0=us)
+    pairs = ((0, 1), (1, 2), (0, 2))  # order of sum_nn
+    try:
+        t0 = time.time()
+        lat.step(equil)
+        n_samp = steps // every
+        samples = np.zeros((n_samp, R, 3, 3))
+        for k in range(n_samp):
+            lat.step(every)
+            for r, m in enumerate(lat.moments()):
+                for i in range(3):
+                    samples[k, r, i, i] = m["sum_n2"][i] / L
+                for (i, j), v in zip(pairs, m["sum_nn"]):
+                    samples[k, r, i, j] = samples[k, r, j, i] = v / L
+        wall = time.time() - t0
+        mom = lat.moments()
+        rc = lat.check()
+    finally:
+        lat.close()
+    rho_hat = np.array([m["sum_N"] / L for m in mom])
+    u_hat = np.array([m["sum_J"] / m["sum_N"] if m["sum_N"] else 0.0 for m in mom])
+    f = np.array([feq(a, b) for a, b in zip(rho_hat, u_hat)])
+    ff = np.sqrt(f[:, :, None] * f[:, None, :])
+    norm = lambda nn: (nn - f[:, :, None] * f[:, None, :]) / ff  # noqa: E731
+    K = norm(samples.mean(0))
+    nb = max(2, min(blocks, n_samp))
+    bK = np.array([norm(b.mean(0)) for b in np.array_split(samples, nb)])
+    se = bK.std(0, ddof=1) / math.sqrt(nb)
+    E = ((K - np.eye(3)) ** 2).sum((1, 2))
+    return {"u0": us, "rho_hat": rho_hat, "u_hat": u_hat, "K": K, "se": se, "E": E,
+            "L": L, "C": C, "equil": equil, "steps": steps, "every": every, "check": rc,
+            "wall_s": wall}
+
+
+# ---- command line -----------------------------------------------------------
+def _fig1(quick: bool):
+    kw = dict(equil=2000, steps=8000, replicas=8) if quick else {}
+    r = parity_histograms(**kw)
+    print(f"Fig. 1  init {r['init']}  L={r['L']} x {r['replicas']}  C={r['C']}  "
+          f"{r['equil']} + {r['steps']} steps  ({r['wall_s']:.1f} s)")
+    print(f"  closed form: f_1 = {r['f1']:.6f}, f_0 = {r['f0']:.6f}; "
+          f"odd rest counts at the end: {r['n0_odd']}")
+    print("   n   P(n_-1)   P(n_+1)  Poisson(f1)   P(n_0)  even-Poisson(f0)  Poisson(<n0>)")
+    for n in range(0, 21):
+        print(f"  {n:2d}  {r['P'][0, n]:.5f}   {r['P'][2, n]:.5f}   {r['pred_moving'][n]:.5f}"
+              f"     {r['P'][1, n]:.5f}   {r['pred_rest'][n]:.5f}           "
+              f"{r['pred_rest_unconstrained'][n]:.5f}")
+
+
+def _fig3(quick: bool):
+    us = np.round(np.linspace(-0.9, 0.9, 19), 6)
+    kw = dict(equil=1500, steps=1500) if quick else {}
+    r = equilibrium_means(us, **kw)
+    print(f"Fig. 3  rho=36  L={r['L']}  C={r['C']}  {r['equil']} + {r['steps']} steps, "
+          f"every {r['every']}  ({r['wall_s']:.1f} s)")
+    print("      u^   <n_-1>  f^eq_-1     <n_0>   f^eq_0    <n_+1>  f^eq_+1   |  f^LB (-1, 0, +1)")
+    for k in range(len(us)):
+        m, f, g = r["mean"][k], r["feq"][k], r["f_lb"][k]
+        print(f"  {r['u_hat'][k]:+.4f}  {m[0]:7.3f}  {f[0]:7.3f}   {m[1]:7.3f}  {f[1]:7.3f}   "
+              f"{m[2]:7.3f}  {f[2]:7.3f}   | {g[0]:7.3f} {g[1]:7.3f} {g[2]:7.3f}")
+
+
+def _fig5(quick: bool):
+    kw = dict(replicas=100, steps=60) if quick else dict(steps=150)
+    for init in ((100, 100, 100), (0, 300, 0), (150, 0, 150)):
+        for stream in (True, False):
+            r = pi_decay(init, stream=stream, **kw)
+            print(f"Fig. 5  init {init}  {'streaming' if stream else 'no streaming'}  "
+                  f"L={r['L']} x {r['replicas']}  C={r['C']}  ({r['wall_s']:.1f} s)")
+            print("   collisions   <pi>      se     Eq.relax(sqrt8)  Eq.relax(printed)  linear")
+            for t in sorted(set([0, 1, 2, 5, 10, 20, 50, 100, len(r['mean']) - 1])):
+                if t < len(r["mean"]):
+                    print(f"   {r['n_coll'][t]:9d}  {r['mean'][t]:9.3f}  {r['se'][t]:6.3f}  "
+                          f"{r['pred_sqrt8'][t]:12.3f}  {r['pred_printed'][t]:14.3f}  "
+                          f"{r['pred_linear'][t]:9.3f}")
+
+
+def _corr(quick: bool):
+    us = np.round(np.linspace(-0.8, 0.8, 9), 6)
+    kw = dict(equil=200, steps=1000) if quick else dict(L=1 << 16, steps=20000)
+    r = correlations(us, **kw)
+    print(f"Eq. (corr), Eq. (error)  rho=36  L={r['L']}  C={r['C']}  {r['equil']} + "
+          f"{r['steps']} steps, every {r['every']}  ({r['wall_s']:.1f} s)")
+    print("      u^    K_-1-1   K_00     K_11     K_-10     K_01     K_-11      E(u)")
+    for k in range(len(us)):
+        K = r["K"][k]
+        print(f"  {r['u_hat'][k]:+.4f}  {K[0, 0]:.5f}  {K[1, 1]:.5f}  {K[2, 2]:.5f}  "
+              f"{K[0, 1]:+.5f}  {K[1, 2]:+.5f}  {K[0, 2]:+.5f}  {r['E'][k]:.2e}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr"])
+    ap.add_argument("--quick", action="store_true", help="reduced step counts")
+    a = ap.parse_args(argv)
+    {"fig1": _fig1, "fig3": _fig3, "fig5": _fig5, "corr": _corr}[a.figure](a.quick)
+
+
+if __name__ == "__main__":
+    main()

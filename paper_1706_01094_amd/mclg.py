@@ -23,6 +23,7 @@ C_EQUILIBRIUM = -1
 FLAG_NO_STREAM = 1
 INIT_COUNTS, INIT_POISSON = 1, 2
 MAX_MODES = 8
+MAX_HIST_BINS = 4096
 OK, E_INVAL, E_RANGE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_FULL, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 u32, u64, i32, i64, dbl, vp = ct.c_uint32, ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_double, ct.c_void_p
@@ -81,6 +82,7 @@ _SIGS = {
     "mclg_step_replica": [vp, u32, u64],
     "mclg_step_graph": [vp, u64],
     "mclg_moments": [vp, vp, u32, P(mclg_moments_t)],
+    "mclg_histogram": [vp, u32, vp],
     "mclg_get_counts": [vp, u32, P(ct.c_uint16)],
     "mclg_check": [vp],
     "mclg_set_schedule": [vp, u32, u32, u32],
@@ -200,6 +202,10 @@ def mclg_lds_coverage(ctx: int):
     return f.value, b.value
 
 
+def mclg_histogram(ctx: int, n_bins: int, dev_hist: int):
+    _check(lib().mclg_histogram(ctx, n_bins, dev_hist), "mclg_histogram")
+
+
 def mclg_check(ctx: int) -> int:
     return lib().mclg_check(ctx)
 
@@ -312,6 +318,21 @@ class Lattice:
         if rc != OK and not (allow_range and rc == E_RANGE):
             raise MclgError(rc, "mclg_moments")
         return [o.as_dict() for o in out]
+
+    def histogram(self, n_bins: int, out=None):
+        """Add this state's occupation-number histograms to ``out`` (an int64
+        tensor [n_replicas, 3, n_bins] on the device, zeros if None) and
+        return it; the last bin counts every n >= n_bins - 1."""
+        torch = self.torch
+        if out is None:
+            out = torch.zeros((self.n, 3, n_bins), dtype=torch.int64, device=self.device)
+        if out.dtype != torch.int64 or out.numel() != 3 * self.n * n_bins or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of n_replicas * 3 * n_bins")
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        mclg_histogram(self.ctx, n_bins, out.data_ptr())
+        cur.wait_stream(self.stream)
+        return out
 
     def counts(self, replica: int = 0, allow_range=False) -> np.ndarray:
         L = int(self.L[replica])

@@ -8,8 +8,11 @@ pair with the tabulated probability.  Everything is exact (``Fraction``) and
 enumerates particles one by one, so it shares nothing with the oracle's
 tridiagonal integer weights: it is a pin for them.
 """
+import math
 from fractions import Fraction
 from functools import lru_cache
+
+import numpy as np
 
 # D1Q3 transition probabilities, "A D1Q3 implementation" (lambda symbolic).
 def transition_table(lam: Fraction):
@@ -130,3 +133,28 @@ def one_subcollision_counted(state, lam: Fraction):
                 key = (m[-1], m[0], m[1])
                 out[key] = out.get(key, Fraction(0)) + p * Fraction(mult, npairs)
     return out
+
+
+def no_stream_pi_moments(abc, C, steps):
+    """(E[pi], E[pi^2]) after ``steps`` steps of C sub-collisions at one site
+    that never streams, started in state abc, with pi = sqrt(2) (n_-1 - n_0/2
+    + n_+1): the fiber chain of ``one_subcollision_counted`` (exact
+    probabilities, propagated in float64)."""
+    N = sum(abc)
+    J = abc[2] - abc[0]
+    absJ = abs(J)
+    par = (N - absJ) % 2
+    m = (N - absJ) // 2 + 1
+    T = np.zeros((m, m))
+    for k in range(m):
+        b = par + 2 * k
+        a, c = (N - b - J) // 2, (N - b + J) // 2
+        for s2, p in one_subcollision_counted((a, b, c), Fraction(1)).items():
+            T[k, (s2[1] - par) // 2] += float(p)
+    v = np.zeros(m)
+    v[(abc[1] - par) // 2] = 1.0
+    TC = np.linalg.matrix_power(T, C * steps)
+    v = v @ TC
+    b = par + 2 * np.arange(m)
+    pi = math.sqrt(2) * ((N - b) - b / 2)
+    return float(v @ pi), float(v @ pi**2)

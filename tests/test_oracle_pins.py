@@ -416,29 +416,6 @@ def test_rest_parity_sector_histogram():
     assert _chi2_pvalue(hm, pm / pm.sum(), hm.sum()) > 1e-3
 
 
-def _exact_no_stream_pi(abc, C, steps):
-    """E[pi] after `steps` collision steps at a single site, from the exact
-    law of the enumerated loop (float64 propagation of the fiber chain)."""
-    N = sum(abc)
-    J = abc[2] - abc[0]
-    absJ = abs(J)
-    par = (N - absJ) % 2
-    m = (N - absJ) // 2 + 1
-    T = np.zeros((m, m))
-    for k in range(m):
-        b = par + 2 * k
-        a, c = (N - b - J) // 2, (N - b + J) // 2
-        for s2, p in X.one_subcollision_counted((a, b, c), Fraction(1)).items():
-            T[k, (s2[1] - par) // 2] += float(p)
-    v = np.zeros(m)
-    v[(abc[1] - par) // 2] = 1.0
-    TC = np.linalg.matrix_power(T, C * steps)
-    v = v @ TC
-    b = par + 2 * np.arange(m)
-    pi = math.sqrt(2) * ((N - b) - b / 2)
-    return float(v @ pi), float(v @ pi**2)
-
-
 @pytest.mark.slow
 def test_pi_relaxation_without_streaming():
     """Relaxation of the pi moment toward local equilibrium when collisions
@@ -452,6 +429,6 @@ def test_pi_relaxation_without_streaming():
         s.step(steps - s.t(0))
         c = s.counts(0).astype(np.float64)
         pi = math.sqrt(2) * (c[0] - c[1] / 2 + c[2])
-        mean_exact, m2 = _exact_no_stream_pi(abc, 10, steps)
+        mean_exact, m2 = X.no_stream_pi_moments(abc, 10, steps)
         sd = math.sqrt(max(m2 - mean_exact**2, 1e-12))
         assert abs(pi.mean() - mean_exact) < 3 * sd / math.sqrt(L) + 1e-9, (steps, pi.mean(), mean_exact)

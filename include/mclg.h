@@ -62,7 +62,18 @@ enum { MCLG_D1Q3 = 1, MCLG_D2Q9 = 2 };
 #define MCLG_C_EQUILIBRIUM (-1) /* C -> infinity: redraw from the fiber equilibrium */
 
 enum {
-  MCLG_FLAG_NO_STREAM = 1u /* collisions only, no streaming (Fig. 5 variant, shear-wave init) */
+  MCLG_FLAG_NO_STREAM = 1u, /* collisions only, no streaming (Fig. 5 variant, shear-wave init) */
+  /* Galilean-invariant acceptance, the remedy the paper proposes after
+   * Eq. (D1Q3relax) for the velocity dependence of the relaxation time:
+   * lambda = lambda~ / sqrt(1 + 3 U^2), lambda~ = lambda_num / lambda_den,
+   * with each site's own U = J / N.  The value is irrational, so every fiber
+   * (N, |J|) uses it rounded down to 32 fractional bits, exactly:
+   *   g = floor(2^32 N / sqrt(N^2 + 3 J^2)),  lambda = floor(g num / den) / 2^32
+   * (mclg_galilean_lambda).  The tables are exact for that lambda; sites
+   * above n_max draw their acceptances as 32-bit words compared with the
+   * numerator: a {-1,+1} pair is accepted when w < p, a {0,0} pair (total
+   * probability lambda / 8) when w1 * 8 + (w2 >> 29) < p. */
+  MCLG_FLAG_GALILEAN = 2u
 };
 
 enum { MCLG_INIT_COUNTS = 1, MCLG_INIT_POISSON = 2 };
@@ -192,9 +203,16 @@ int mclg_last_hip_error(const mclg_ctx *ctx);
 
 /* Quantised row of the collision law: for the fiber (N, absJ) and incoming
  * rest count n0, writes the full-fiber thresholds (m - 1 values as uint64,
- * value 2^32 meaning "never") to thr, m = (N - absJ)/2 + 1 to *m_out. */
-int mclg_table_row(int32_t C, uint32_t lambda_num, uint32_t lambda_den, uint32_t N,
-                   uint32_t absJ, uint32_t n0, uint64_t *thr, uint32_t cap, uint32_t *m_out);
+ * value 2^32 meaning "never") to thr, m = (N - absJ)/2 + 1 to *m_out.
+ * flags: 0 or MCLG_FLAG_GALILEAN. */
+int mclg_table_row(int32_t C, uint32_t lambda_num, uint32_t lambda_den, uint32_t flags,
+                   uint32_t N, uint32_t absJ, uint32_t n0, uint64_t *thr, uint32_t cap,
+                   uint32_t *m_out);
+
+/* Numerator over 2^32 of the Galilean-invariant acceptance of fiber
+ * (N, absJ) (MCLG_FLAG_GALILEAN) for lambda~ = num / den. */
+int mclg_galilean_lambda(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ,
+                         uint64_t *lambda_q);
 
 /* Poisson(mu) thresholds of the initial-state rule: outcomes k_lo..k_lo+cnt-1,
  * cnt - 1 thresholds (uint64) to thr. */

@@ -15,6 +15,7 @@ from . import build_oracle
 
 C_EQUILIBRIUM = -1
 FLAG_NO_STREAM = 1
+FLAG_GALILEAN = 2
 MAX_MODES = 8
 
 
@@ -61,13 +62,15 @@ def lib() -> ct.CDLL:
         L.mco_moments.argtypes = [ct.c_void_p, u32, P(ct.c_int32), u32, P(Moments)]
         L.mco_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
         L.mco_philox4x32_10.restype = None
-        L.mco_row_thresholds.argtypes = [i32, u32, u32, u32, u32, u32, P(u64), P(u32)]
+        L.mco_row_thresholds.argtypes = [i32, u32, u32, u32, u32, u32, u32, P(u64), P(u32)]
+        L.mco_galilean_lambda.argtypes = [u32, u32, u64, u64]
+        L.mco_galilean_lambda.restype = u64
         L.mco_poisson_thresholds.argtypes = [ct.c_double, P(u32), P(u32), P(u64), u32]
         L.mco_feq.argtypes = [ct.c_double, ct.c_double, P(ct.c_double)]
         L.mco_feq.restype = None
-        L.mco_collide_site.argtypes = [i32, u32, u32, u32, u64, u64, u64, u64, P(u32)]
-        L.mco_collide_site_direct.argtypes = [i32, u32, u32, u64, u64, u64, u64, P(u32)]
-        L.mco_histogram.argtypes = [i32, u32, u32, ct.c_int, u64, u64, u64, P(u32), P(u64)]
+        L.mco_collide_site.argtypes = [i32, u32, u32, u32, u32, u64, u64, u64, u64, P(u32)]
+        L.mco_collide_site_direct.argtypes = [i32, u32, u32, u32, u64, u64, u64, u64, P(u32)]
+        L.mco_histogram.argtypes = [i32, u32, u32, u32, ct.c_int, u64, u64, u64, P(u32), P(u64)]
         _lib = L
     return _lib
 
@@ -94,11 +97,12 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def row_thresholds(C: int, lam: tuple, N: int, absJ: int, n0: int) -> np.ndarray:
+def row_thresholds(C: int, lam: tuple, N: int, absJ: int, n0: int, flags: int = 0) -> np.ndarray:
     m = (N - absJ) // 2 + 1
     thr = np.zeros(max(m - 1, 1), dtype=np.uint64)
     mo = ct.c_uint32(0)
-    rc = lib().mco_row_thresholds(C, lam[0], lam[1], N, absJ, n0, _ptr(thr, ct.c_uint64), ct.byref(mo))
+    rc = lib().mco_row_thresholds(C, lam[0], lam[1], flags, N, absJ, n0, _ptr(thr, ct.c_uint64),
+                                  ct.byref(mo))
     if rc != 0:
         raise OracleError(f"row_thresholds rc={rc}")
     return thr[: mo.value - 1]
@@ -120,20 +124,27 @@ def feq(rho: float, u: float) -> np.ndarray:
     return out
 
 
-def collide_site(C, lam, n_max, seed, replica, t, x, abc, direct=False):
+def galilean_lambda(lam: tuple, N: int, absJ: int) -> int:
+    """Numerator over 2^32 of the Galilean-invariant acceptance (R7)."""
+    return int(lib().mco_galilean_lambda(lam[0], lam[1], N, absJ))
+
+
+def collide_site(C, lam, n_max, seed, replica, t, x, abc, direct=False, flags=0):
     s = np.asarray(abc, dtype=np.uint32).copy()
     if direct:
-        rc = lib().mco_collide_site_direct(C, lam[0], lam[1], seed, replica, t, x, _ptr(s, ct.c_uint32))
+        rc = lib().mco_collide_site_direct(C, lam[0], lam[1], flags, seed, replica, t, x,
+                                           _ptr(s, ct.c_uint32))
     else:
-        rc = lib().mco_collide_site(C, lam[0], lam[1], n_max, seed, replica, t, x, _ptr(s, ct.c_uint32))
+        rc = lib().mco_collide_site(C, lam[0], lam[1], flags, n_max, seed, replica, t, x,
+                                    _ptr(s, ct.c_uint32))
     return rc, s
 
 
-def histogram(C, lam, abc, n_draws, seed=1, t=0, direct=False) -> np.ndarray:
+def histogram(C, lam, abc, n_draws, seed=1, t=0, direct=False, flags=0) -> np.ndarray:
     s = np.asarray(abc, dtype=np.uint32)
     N = int(s.sum())
     h = np.zeros(N + 1, dtype=np.uint64)
-    rc = lib().mco_histogram(C, lam[0], lam[1], int(direct), seed, t, n_draws,
+    rc = lib().mco_histogram(C, lam[0], lam[1], flags, int(direct), seed, t, n_draws,
                              _ptr(s, ct.c_uint32), _ptr(h, ct.c_uint64))
     if rc != 0:
         raise OracleError(f"histogram rc={rc}")

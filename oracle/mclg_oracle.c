@@ -32,7 +32,12 @@
  *   R5  random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the
  *       64-bit seed, counter (site word, t, replica, purpose | block << 2);
  *   R6  Poisson initial counts use thresholds built with IEEE double
- *       operations in a fixed order (mco_poisson_thresholds).
+ *       operations in a fixed order (mco_poisson_thresholds);
+ *   R7  Galilean-invariant acceptance (MCO_FLAG_GALILEAN; the remedy the
+ *       paper proposes after Eq. (D1Q3relax)): lambda = lambda~ / sqrt(1 +
+ *       3 U^2) with U = J / N of the colliding site, rounded down to a
+ *       multiple of 2^-32 in two exact steps (mco_galilean_lambda); the
+ *       literal loop then accepts with 32-bit words (collide_direct).
  */
 #include "mclg_oracle.h"
 
@@ -253,8 +258,27 @@ typedef struct {
 typedef struct {
   int32_t C;
   uint32_t p, q, nmax;
+  int galilean;     /* per-fiber lambda of R7 */
   block_t **blocks; /* index N * (nmax + 1) + absJ, built on first use */
 } table_cache;
+
+/* R7: the numerator over 2^32 of lambda~ / sqrt(1 + 3 (J/N)^2) =
+ * lambda~ N / sqrt(N^2 + 3 J^2), lambda~ = num / den:
+ *   g = the largest integer with g^2 (N^2 + 3 J^2) <= 2^64 N^2 (bisection over
+ *       [0, 2^32]; for N = 0 every g qualifies and g = 2^32),
+ *   result = floor(g num / den). */
+uint64_t mco_galilean_lambda(uint32_t num, uint32_t den, uint64_t N, uint64_t absJ) {
+  typedef unsigned __int128 u128;
+  const u128 scale = (u128)N * N + 3 * (u128)absJ * absJ;
+  const u128 bound = ((u128)N * N) << 64;
+  uint64_t lo = 0, hi = (uint64_t)1 << 32;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo + 1) / 2;
+    if ((u128)mid * mid * scale <= bound) lo = mid;
+    else hi = mid - 1;
+  }
+  return (uint64_t)((u128)lo * num / den);
+}
 
 static void fiber_geometry(uint32_t N, uint32_t absJ, uint32_t k,
                            uint64_t *n0, uint64_t *a, uint64_t *c) {
@@ -264,7 +288,7 @@ static void fiber_geometry(uint32_t N, uint32_t absJ, uint32_t k,
   *c = (N - *n0 + absJ) / 2;
 }
 
-static int build_row(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t absJ,
+static int build_row(int32_t C, uint64_t p, uint64_t q, uint32_t N, uint32_t absJ,
                      uint32_t k0, uint64_t *thr) {
   uint32_t m = (N - absJ) / 2 + 1;
   if (m == 1) return MCO_OK;
@@ -299,7 +323,7 @@ static int build_row(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t abs
         uint64_t n0, a, c;
         fiber_geometry(N, absJ, k, &n0, &a, &c);
         uint64_t up = 16ull * p * a * c;
-        uint64_t down = (uint64_t)p * n0 * (n0 - (n0 > 0));
+        uint64_t down = p * n0 * (n0 - (n0 > 0));
         uint64_t stay = D1 - up - down;
         bn_addmul_u64(&w[k], &v[k], stay);
         if (up) bn_addmul_u64(&w[k + 1], &v[k], up);
@@ -329,8 +353,10 @@ static int cache_block(table_cache *tc, uint32_t N, uint32_t absJ, const block_t
     b->m = m;
     b->thr = (uint64_t *)calloc((size_t)m * (m > 1 ? m - 1 : 1), sizeof(uint64_t));
     if (!b->thr) { free(b); return MCO_E_NOMEM; }
+    uint64_t p = tc->p, q = tc->q;
+    if (tc->galilean) { p = mco_galilean_lambda(tc->p, tc->q, N, absJ); q = (uint64_t)1 << 32; }
     for (uint32_t k0 = 0; k0 < m; ++k0) {
-      int rc = build_row(tc->C, tc->p, tc->q, N, absJ, k0, b->thr + (size_t)k0 * (m - 1));
+      int rc = build_row(tc->C, p, q, N, absJ, k0, b->thr + (size_t)k0 * (m - 1));
       if (rc) { free(b->thr); free(b); return rc; }
     }
     tc->blocks[idx] = b;
@@ -339,8 +365,9 @@ static int cache_block(table_cache *tc, uint32_t N, uint32_t absJ, const block_t
   return MCO_OK;
 }
 
-static int cache_init(table_cache *tc, int32_t C, uint32_t p, uint32_t q, uint32_t nmax) {
-  tc->C = C; tc->p = p; tc->q = q; tc->nmax = nmax;
+static int cache_init(table_cache *tc, int32_t C, uint32_t p, uint32_t q, uint32_t nmax,
+                      int galilean) {
+  tc->C = C; tc->p = p; tc->q = q; tc->nmax = nmax; tc->galilean = galilean;
   tc->blocks = (block_t **)calloc((size_t)(nmax + 1) * (nmax + 1), sizeof(block_t *));
   return tc->blocks ? MCO_OK : MCO_E_NOMEM;
 }
@@ -360,9 +387,10 @@ static int params_valid(int32_t C, uint32_t p, uint32_t q, uint32_t nmax) {
   return 1;
 }
 
-int mco_row_thresholds(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t absJ,
-                       uint32_t n0, uint64_t *thr, uint32_t *m_out) {
-  if (!params_valid(C, p, q, N) || absJ > N || n0 > N - absJ || ((N - absJ - n0) & 1u))
+int mco_row_thresholds(int32_t C, uint32_t p, uint32_t q, uint32_t flags, uint32_t N,
+                       uint32_t absJ, uint32_t n0, uint64_t *thr, uint32_t *m_out) {
+  if (!params_valid(C, p, q, N) || absJ > N || n0 > N - absJ || ((N - absJ - n0) & 1u) ||
+      (flags & ~(uint32_t)MCO_FLAG_GALILEAN))
     return MCO_E_INVAL;
   uint32_t m = (N - absJ) / 2 + 1;
   *m_out = m;
@@ -371,6 +399,9 @@ int mco_row_thresholds(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t a
     return MCO_OK;
   }
   uint32_t par = (N - absJ) & 1u;
+  if (flags & MCO_FLAG_GALILEAN)
+    return build_row(C, mco_galilean_lambda(p, q, N, absJ), (uint64_t)1 << 32, N, absJ,
+                     (n0 - par) / 2, thr);
   return build_row(C, p, q, N, absJ, (n0 - par) / 2, thr);
 }
 
@@ -379,10 +410,12 @@ int mco_row_thresholds(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t a
 /* ------------------------------------------------------------------------ */
 /* The paper's literal loop for D1Q3 (Eq. (select), Eq. (omega), repeated C
  * times, each sub-collision acting on the state left by the previous one). */
-static void collide_direct(int32_t C, uint32_t p, uint32_t q, word_stream *ws,
+static void collide_direct(int32_t C, uint32_t p, uint32_t q, int galilean, word_stream *ws,
                            uint64_t *a, uint64_t *b, uint64_t *c) {
   uint64_t N = *a + *b + *c;
   if (N < 2) return;
+  /* R7: lambda = lam / 2^32 for the site's conserved (N, |J|) */
+  const uint64_t lam = galilean ? mco_galilean_lambda(p, q, N, *c > *a ? *c - *a : *a - *c) : 0;
   for (int32_t sub = 0; sub < C; ++sub) {
     uint32_t r1 = ws_uniform(ws, (uint32_t)N);
     uint32_t r2 = ws_uniform(ws, (uint32_t)(N - 1));
@@ -392,11 +425,23 @@ static void collide_direct(int32_t C, uint32_t p, uint32_t q, word_stream *ws,
     int s1 = r1 < *a ? -1 : (r1 < *a + *b ? 0 : 1);
     int s2 = r2 < *a ? -1 : (r2 < *a + *b ? 0 : 1);
     if (s1 * s2 == -1) {
-      /* {-1,+1} -> {0,0} with probability lambda */
-      if (ws_uniform(ws, q) < p) { *a -= 1; *c -= 1; *b += 2; }
+      /* {-1,+1} -> {0,0} with probability lambda: a uniform integer below q
+       * (below 2^32 under R7, one word) compared with the numerator */
+      int accept = galilean ? (uint64_t)ws_next(ws) < lam : ws_uniform(ws, q) < p;
+      if (accept) { *a -= 1; *c -= 1; *b += 2; }
     } else if (s1 == 0 && s2 == 0) {
-      /* {0,0} -> {-1,1} or {1,-1}, total probability lambda/8 */
-      if (ws_uniform(ws, 8u * q) < p) { *b -= 2; *a += 1; *c += 1; }
+      /* {0,0} -> {-1,1} or {1,-1}, total probability lambda/8: a uniform
+       * integer below 8q (below 2^35 under R7: 8 w1 + the top three bits of
+       * w2) compared with the numerator */
+      int accept;
+      if (galilean) {
+        uint64_t w1 = ws_next(ws);
+        uint64_t w2 = ws_next(ws);
+        accept = w1 * 8u + (w2 >> 29) < lam;
+      } else {
+        accept = ws_uniform(ws, 8u * q) < p;
+      }
+      if (accept) { *b -= 2; *a += 1; *c += 1; }
     }
   }
 }
@@ -404,6 +449,7 @@ static void collide_direct(int32_t C, uint32_t p, uint32_t q, word_stream *ws,
 typedef struct {
   int32_t C;
   uint32_t p, q, nmax;
+  int galilean;
   uint64_t seed;
   table_cache tc;
 } collide_params;
@@ -436,7 +482,7 @@ static int collide_site(collide_params *cp, uint32_t replica, uint32_t t, uint32
   } else {
     word_stream ws = {cp->seed, x, t, replica, 0, 4, {0, 0, 0, 0}};
     uint64_t aa = *a, bb = *b, cc = *c;
-    collide_direct(cp->C, cp->p, cp->q, &ws, &aa, &bb, &cc);
+    collide_direct(cp->C, cp->p, cp->q, cp->galilean, &ws, &aa, &bb, &cc);
     b_new = bb;
   }
   /* exact conservation of N and J (Eq. (collcons)) */
@@ -530,6 +576,7 @@ int mco_create(uint32_t n_rep, const uint64_t *L, const uint64_t *replica_id, ui
   s->n_rep = n_rep;
   s->flags = flags;
   s->cp.C = C; s->cp.p = lam_p; s->cp.q = lam_q; s->cp.nmax = n_max; s->cp.seed = seed;
+  s->cp.galilean = (flags & MCO_FLAG_GALILEAN) != 0;
   s->L = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
   s->rid = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
   s->xoff = (uint64_t *)calloc(n_rep, sizeof(uint64_t));
@@ -537,7 +584,7 @@ int mco_create(uint32_t n_rep, const uint64_t *L, const uint64_t *replica_id, ui
   s->cur = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
   s->nxt = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
   int bad = !s->L || !s->rid || !s->xoff || !s->t || !s->cur || !s->nxt ||
-            cache_init(&s->cp.tc, C, lam_p, lam_q, n_max);
+            cache_init(&s->cp.tc, C, lam_p, lam_q, n_max, s->cp.galilean);
   for (uint32_t r = 0; !bad && r < n_rep; ++r) {
     s->L[r] = L[r];
     s->rid[r] = replica_id ? replica_id[r] : r;
@@ -716,22 +763,24 @@ int mco_moments(const mco_sim *s, uint32_t rep, const int32_t *twiddle, uint32_t
 static collide_params g_cp;
 static int g_cp_valid = 0;
 
-static int global_params(int32_t C, uint32_t p, uint32_t q, uint32_t nmax, uint64_t seed) {
+static int global_params(int32_t C, uint32_t p, uint32_t q, uint32_t nmax, int galilean,
+                         uint64_t seed) {
   if (!params_valid(C, p, q, nmax)) return MCO_E_INVAL;
-  if (!g_cp_valid || g_cp.C != C || g_cp.p != p || g_cp.q != q || g_cp.nmax != nmax) {
+  if (!g_cp_valid || g_cp.C != C || g_cp.p != p || g_cp.q != q || g_cp.nmax != nmax ||
+      g_cp.galilean != galilean) {
     if (g_cp_valid) cache_free(&g_cp.tc);
     g_cp_valid = 0;
-    if (cache_init(&g_cp.tc, C, p, q, nmax)) return MCO_E_NOMEM;
-    g_cp.C = C; g_cp.p = p; g_cp.q = q; g_cp.nmax = nmax;
+    if (cache_init(&g_cp.tc, C, p, q, nmax, galilean)) return MCO_E_NOMEM;
+    g_cp.C = C; g_cp.p = p; g_cp.q = q; g_cp.nmax = nmax; g_cp.galilean = galilean;
     g_cp_valid = 1;
   }
   g_cp.seed = seed;
   return MCO_OK;
 }
 
-int mco_collide_site(int32_t C, uint32_t p, uint32_t q, uint32_t n_max, uint64_t seed,
-                     uint64_t replica, uint64_t t, uint64_t x, uint32_t abc[3]) {
-  int rc = global_params(C, p, q, n_max, seed);
+int mco_collide_site(int32_t C, uint32_t p, uint32_t q, uint32_t flags, uint32_t n_max,
+                     uint64_t seed, uint64_t replica, uint64_t t, uint64_t x, uint32_t abc[3]) {
+  int rc = global_params(C, p, q, n_max, (flags & MCO_FLAG_GALILEAN) != 0, seed);
   if (rc) return rc;
   uint64_t a = abc[0], b = abc[1], c = abc[2];
   rc = collide_site(&g_cp, (uint32_t)replica, (uint32_t)t, (uint32_t)x, &a, &b, &c, 0);
@@ -739,28 +788,28 @@ int mco_collide_site(int32_t C, uint32_t p, uint32_t q, uint32_t n_max, uint64_t
   return rc;
 }
 
-int mco_collide_site_direct(int32_t C, uint32_t p, uint32_t q, uint64_t seed, uint64_t replica,
-                            uint64_t t, uint64_t x, uint32_t abc[3]) {
+int mco_collide_site_direct(int32_t C, uint32_t p, uint32_t q, uint32_t flags, uint64_t seed,
+                            uint64_t replica, uint64_t t, uint64_t x, uint32_t abc[3]) {
   if (C < 0 || !params_valid(C, p, q, 0)) return MCO_E_INVAL;
   uint64_t a = abc[0], b = abc[1], c = abc[2];
   word_stream ws = {seed, (uint32_t)x, (uint32_t)t, (uint32_t)replica, 0, 4, {0, 0, 0, 0}};
-  collide_direct(C, p, q, &ws, &a, &b, &c);
+  collide_direct(C, p, q, (flags & MCO_FLAG_GALILEAN) != 0, &ws, &a, &b, &c);
   abc[0] = (uint32_t)a; abc[1] = (uint32_t)b; abc[2] = (uint32_t)c;
   return MCO_OK;
 }
 
-int mco_histogram(int32_t C, uint32_t p, uint32_t q, int direct, uint64_t seed, uint64_t t,
-                  uint64_t n_draws, const uint32_t abc[3], uint64_t *hist) {
+int mco_histogram(int32_t C, uint32_t p, uint32_t q, uint32_t flags, int direct, uint64_t seed,
+                  uint64_t t, uint64_t n_draws, const uint32_t abc[3], uint64_t *hist) {
   uint32_t N = abc[0] + abc[1] + abc[2];
   if (!direct) {
-    int rc = global_params(C, p, q, N, seed);
+    int rc = global_params(C, p, q, N, (flags & MCO_FLAG_GALILEAN) != 0, seed);
     if (rc) return rc;
   }
   for (uint32_t k = 0; k <= N; ++k) hist[k] = 0;
   for (uint64_t x = 0; x < n_draws; ++x) {
     uint32_t s[3] = {abc[0], abc[1], abc[2]};
-    int rc = direct ? mco_collide_site_direct(C, p, q, seed, 0, t, x, s)
-                    : mco_collide_site(C, p, q, N, seed, 0, t, x, s);
+    int rc = direct ? mco_collide_site_direct(C, p, q, flags, seed, 0, t, x, s)
+                    : mco_collide_site(C, p, q, flags, N, seed, 0, t, x, s);
     if (rc) return rc;
     hist[s[1]] += 1;
   }

@@ -24,7 +24,10 @@ extern "C" {
 #endif
 
 enum { MCO_OK = 0, MCO_E_INVAL = -1, MCO_E_RANGE = -2, MCO_E_NOMEM = -3 };
-enum { MCO_FLAG_NO_STREAM = 1u };  /* collisions only, no streaming */
+enum {
+  MCO_FLAG_NO_STREAM = 1u, /* collisions only, no streaming */
+  MCO_FLAG_GALILEAN = 2u   /* lambda = lambda~ / sqrt(1 + 3 (J/N)^2) per site (R7) */
+};
 #define MCO_C_EQUILIBRIUM (-1)      /* C -> infinity: redraw from fiber equilibrium */
 #define MCO_MAX_MODES 8
 
@@ -73,8 +76,11 @@ void mco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* Exact quantised row of the C-step collision kernel on fiber (N, |J|) from
  * incoming rest count n0.  thr receives m-1 thresholds (uint64, may equal
  * 2^32) where m = (N-|J|)/2 + 1; outcome k is n0' = ((N-|J|) mod 2) + 2k. */
-int mco_row_thresholds(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t N,
-                       uint32_t absJ, uint32_t n0, uint64_t *thr, uint32_t *m_out);
+int mco_row_thresholds(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t flags,
+                       uint32_t N, uint32_t absJ, uint32_t n0, uint64_t *thr,
+                       uint32_t *m_out);
+/* R7: numerator over 2^32 of the Galilean-invariant lambda of fiber (N, |J|). */
+uint64_t mco_galilean_lambda(uint32_t num, uint32_t den, uint64_t N, uint64_t absJ);
 /* Poisson(mu) thresholds under the stated IEEE rule: outcomes k_lo..k_lo+cnt-1,
  * thr receives cnt-1 values. Returns MCO_E_INVAL if cap too small. */
 int mco_poisson_thresholds(double mu, uint32_t *k_lo, uint32_t *cnt,
@@ -83,16 +89,16 @@ void mco_feq(double rho, double u, double out[3]);
 /* One collision of a site (a, b, c) -> (a', b', c') using the table sampler
  * (N <= n_max) or the direct sampler (N > n_max), with the RNG coordinates
  * (seed, replica, t, x).  Used by the statistical tests. */
-int mco_collide_site(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t n_max,
-                     uint64_t seed, uint64_t replica, uint64_t t, uint64_t x,
-                     uint32_t abc[3]);
+int mco_collide_site(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t flags,
+                     uint32_t n_max, uint64_t seed, uint64_t replica, uint64_t t,
+                     uint64_t x, uint32_t abc[3]);
 /* Always the direct (literal sub-collision) sampler. */
-int mco_collide_site_direct(int32_t C, uint32_t lam_p, uint32_t lam_q,
+int mco_collide_site_direct(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t flags,
                             uint64_t seed, uint64_t replica, uint64_t t,
                             uint64_t x, uint32_t abc[3]);
 /* Many draws for chi-squared tests: histogram of n0' over n_draws sites
  * x = 0..n_draws-1 at step t, all starting from (a,b,c). hist has N+1 bins. */
-int mco_histogram(int32_t C, uint32_t lam_p, uint32_t lam_q, int direct,
+int mco_histogram(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t flags, int direct,
                   uint64_t seed, uint64_t t, uint64_t n_draws,
                   const uint32_t abc[3], uint64_t *hist);
 

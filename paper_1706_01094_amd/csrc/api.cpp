@@ -80,12 +80,14 @@ int validate(const mclg_config *cfg) {
   if (cfg->lattice == MCLG_D2Q9) return MCLG_E_UNSUPPORTED;
   if (cfg->lattice != MCLG_D1Q3) return MCLG_E_INVAL;
   if (cfg->n_replicas == 0 || !cfg->L) return MCLG_E_INVAL;
-  if (cfg->flags & ~(uint32_t)MCLG_FLAG_NO_STREAM) return MCLG_E_INVAL;
+  if (cfg->flags & ~(uint32_t)(MCLG_FLAG_NO_STREAM | MCLG_FLAG_GALILEAN)) return MCLG_E_INVAL;
   for (uint32_t r = 0; r < cfg->n_replicas; ++r) {
     if (cfg->L[r] == 0 || cfg->L[r] > kMaxSites) return MCLG_E_INVAL;
     if (cfg->replica_id && cfg->replica_id[r] >= (1ull << 32)) return MCLG_E_INVAL;
   }
-  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max)) return MCLG_E_INVAL;
+  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max,
+                 (cfg->flags & MCLG_FLAG_GALILEAN) != 0))
+    return MCLG_E_INVAL;
   return MCLG_OK;
 }
 
@@ -149,6 +151,7 @@ struct mclg_ctx {
     p.lam_q = lam_q;
     p.n_max = n_max;
     p.no_stream = (flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u;
+    p.galilean = (flags & MCLG_FLAG_GALILEAN) ? 1u : 0u;
     p.tile_sites = sch.tile_sites();
     return p;
   }
@@ -274,7 +277,8 @@ extern "C" {
 int mclg_sizes(const mclg_config *cfg, uint64_t *state_bytes, uint64_t *workspace_bytes) {
   int rc = validate(cfg);
   if (rc) return rc;
-  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max,
+                              (cfg->flags & MCLG_FLAG_GALILEAN) != 0);
   if (!tab) return MCLG_E_INVAL;
   Layout lay;
   compute_layout(cfg->n_replicas, cfg->L, tab.get(), lay);
@@ -288,7 +292,8 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   int rc = validate(cfg);
   if (rc) return rc;
   if (!cfg->state || !cfg->workspace) return MCLG_E_INVAL;
-  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max,
+                              (cfg->flags & MCLG_FLAG_GALILEAN) != 0);
   if (!tab) return MCLG_E_INVAL;
   std::unique_ptr<mclg_ctx> c(new (std::nothrow) mclg_ctx());
   if (!c) return MCLG_E_NOMEM;
@@ -621,14 +626,23 @@ const char *mclg_strerror(int code) {
 
 int mclg_last_hip_error(const mclg_ctx *c) { return c ? c->last_hip : 0; }
 
-int mclg_table_row(int32_t C, uint32_t p, uint32_t q, uint32_t N, uint32_t absJ, uint32_t n0,
-                   uint64_t *thr, uint32_t cap, uint32_t *m_out) {
-  if (!thr || !m_out) return MCLG_E_INVAL;
+int mclg_table_row(int32_t C, uint32_t p, uint32_t q, uint32_t flags, uint32_t N, uint32_t absJ,
+                   uint32_t n0, uint64_t *thr, uint32_t cap, uint32_t *m_out) {
+  if (!thr || !m_out || (flags & ~(uint32_t)MCLG_FLAG_GALILEAN)) return MCLG_E_INVAL;
   std::vector<uint64_t> full;
-  if (!collision_row_full(C, p, q, N, absJ, n0, full)) return MCLG_E_INVAL;
+  if (!collision_row_full(C, p, q, (flags & MCLG_FLAG_GALILEAN) != 0, N, absJ, n0, full))
+    return MCLG_E_INVAL;
   if (full.size() > cap) return MCLG_E_INVAL;
   std::copy(full.begin(), full.end(), thr);
   *m_out = (uint32_t)full.size() + 1;
+  return MCLG_OK;
+}
+
+int mclg_galilean_lambda(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ,
+                         uint64_t *lambda_q) {
+  if (!lambda_q || den == 0 || num == 0 || num > den || den >= (1u << 28) || absJ > N)
+    return MCLG_E_INVAL;
+  *lambda_q = galilean_lambda_q(num, den, N, absJ);
   return MCLG_OK;
 }
 

@@ -36,6 +36,7 @@ struct StepParams {
   uint32_t n_max;
   uint32_t no_stream;
   uint32_t tile_sites;
+  uint32_t galilean;  // per-site lambda (see collide_direct)
 };
 
 // Stride (uint32) of the fixed-stride copy of the collision rows: a header

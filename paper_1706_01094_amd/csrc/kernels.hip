@@ -103,8 +103,33 @@ struct WordStream {
   }
 };
 
+// Galilean-invariant acceptance of fiber (N, |J|) as a numerator over 2^32:
+// floor(g num / den) with g = floor(2^32 N / sqrt(N^2 + 3 J^2)), both exact:
+// each is estimated in double and corrected by integer tests that use only
+// products (g is the largest integer with g^2 (N^2 + 3 J^2) <= 2^64 N^2).
+__device__ uint64_t galilean_lambda(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ) {
+  using u128 = unsigned __int128;
+  uint64_t g = 1ull << 32;
+  if (absJ) {
+    const uint64_t n2 = (uint64_t)N * N, d = n2 + 3ull * absJ * absJ;
+    const u128 bound = (u128)n2 << 64;
+    uint64_t s = (uint64_t)(4294967296.0 * (double)N / __dsqrt_rn((double)d));
+    while (s && (u128)s * s * d > bound) --s;
+    while ((u128)(s + 1) * (s + 1) * d <= bound) ++s;
+    g = s;
+  }
+  const uint64_t gn = g * num;  // < 2^61
+  uint64_t q = (uint64_t)((double)gn / (double)den);
+  while (q && (u128)q * den > gn) --q;
+  while ((u128)(q + 1) * den <= gn) ++q;
+  return q;
+}
+
 // The paper's C sub-collisions one by one (Eq. (select), Eq. (omega)); used
-// for sites with N > n_max.  Returns the new rest count.
+// for sites with N > n_max.  Returns the new rest count.  GAL selects the
+// Galilean-invariant acceptance (its own kernel instantiation, so that the
+// plain kernel carries none of its code).
+template <bool GAL>
 __device__ __forceinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint32_t c,
                                                 const StepParams &p, uint32_t x, uint32_t t,
                                                 uint32_t rid) {
@@ -112,6 +137,26 @@ __device__ __forceinline__ uint32_t collide_direct(uint32_t a, uint32_t b, uint3
   ws.key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
   ws.x = x; ws.t = t; ws.rid = rid; ws.block = 0; ws.used = 4;
   const uint32_t N = a + b + c;
+  if constexpr (GAL) {
+    // lambda = lq / 2^32: a {-1,+1} pair is accepted when a word is below lq,
+    // a {0,0} pair (lambda / 8) when a 35-bit uniform (w1 * 8 + w2 >> 29) is.
+    const uint64_t lq = galilean_lambda(p.lam_p, p.lam_q, N, c > a ? c - a : a - c);
+    for (int32_t s = 0; s < p.C; ++s) {
+      const uint32_t r1 = ws.uniform(N);
+      uint32_t r2 = ws.uniform(N - 1);
+      r2 += (r2 >= r1);
+      const int v1 = r1 < a ? -1 : (r1 < a + b ? 0 : 1);
+      const int v2 = r2 < a ? -1 : (r2 < a + b ? 0 : 1);
+      if (v1 + v2 == 0 && v1 != 0) {
+        if ((uint64_t)ws.next() < lq) { a -= 1; c -= 1; b += 2; }
+      } else if (v1 == 0 && v2 == 0) {
+        const uint64_t w1 = ws.next();
+        const uint32_t w2 = ws.next();
+        if (((w1 << 3) | (w2 >> 29)) < lq) { b -= 2; a += 1; c += 1; }
+      }
+    }
+    return b;
+  }
   for (int32_t s = 0; s < p.C; ++s) {
     const uint32_t r1 = ws.uniform(N);
     uint32_t r2 = ws.uniform(N - 1);
@@ -267,6 +312,7 @@ constexpr uint32_t kOverflow = kOverflowPerWave;
 // Exact outcome for a queued site: global row, or the literal loop.  It is
 // only reached from the drain, outside the unrolled per-site code, so the
 // hot loop stays small enough for the instruction cache.
+template <bool GAL>
 __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepParams &p,
                                                 const TableDev &tab, uint32_t t, uint32_t rid,
                                                 uint32_t *err) {
@@ -286,7 +332,7 @@ __device__ __forceinline__ uint32_t resolve_queued(const uint4 e, const StepPara
     atomicOr(err, kErrEqRange);
     return b;
   }
-  return collide_direct(a, b, c, p, x, t, rid);
+  return collide_direct<GAL>(a, b, c, p, x, t, rid);
 }
 
 // Where a slot's three arrays are and how they are shifted at step t.
@@ -487,6 +533,7 @@ __device__ __forceinline__ void queue_saturated(const uint32_t (&va)[4], const u
 // earlier memory operations have completed -- among them the stores that
 // wrote the pre-collision counts of these sites -- so the final counts land
 // after them.
+template <bool GAL>
 __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *over, uint32_t F,
                                             uint32_t lane, const SlotView &v,
                                             const StepParams &p, const TableDev &tab,
@@ -498,7 +545,7 @@ __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *ove
   for (uint32_t i = lane; i < F; i += 64u) {
     const uint4 e = i < kQueue ? queue[i] : over[i - kQueue];
     const uint32_t x = e.x, ea = e.y & 0xffffu, eb = e.y >> 16, ec = e.z;
-    const uint32_t bn = resolve_queued(e, p, tab, v.t, v.rid, err);
+    const uint32_t bn = resolve_queued<GAL>(e, p, tab, v.t, v.rid, err);
     const int32_t N = (int32_t)(ea + eb + ec), J = (int32_t)ec - (int32_t)ea;
     uint32_t pm = x + v.tm;
     pm -= (pm >= v.L) ? v.L : 0u;
@@ -589,7 +636,7 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 // update has no races.  Undecided draws wait in the wave's queue, which is
 // drained between chunks once it nears capacity, and at the end of the
 // slot's segment.
-template <int MAXT>
+template <int MAXT, bool GAL>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   extern __shared__ uint4 lds[];
   const StepParams &p = a.p;
@@ -638,7 +685,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       }
     }
     if (F && (i >= ce || t0.slot != cur)) {  // queued draws belong to slot `cur`
-      drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
+      drain_queue<GAL>(queue, over, F, lane, sv, p, a.tab, a.err);
       F = 0;
     }
     if (i >= ce) break;
@@ -758,7 +805,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
       // fit.
       if (has_next && F > kDrainAt) {
-        drain_queue(queue, over, F, lane, sv, p, a.tab, a.err);
+        drain_queue<GAL>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
       }
       return has_next;
@@ -959,12 +1006,23 @@ __global__ void __launch_bounds__(256) k_histogram(
 
 }  // namespace
 
+// Sets the dynamic LDS limit of both instantiations for this block size and
+// returns the smaller of their occupancies.
 template <int MAXT>
 static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<MAXT>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_step<MAXT>, (int)threads, lds);
+  int b[2] = {0, 0};
+  const void *fn[2] = {reinterpret_cast<const void *>(k_step<MAXT, false>),
+                       reinterpret_cast<const void *>(k_step<MAXT, true>)};
+  for (int i = 0; i < 2; ++i) {
+    hipError_t e = hipFuncSetAttribute(fn[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e) return e;
+    e = i ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[i], k_step<MAXT, true>, (int)threads, lds)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[i], k_step<MAXT, false>, (int)threads,
+                                                          lds);
+    if (e) return e;
+  }
+  blocks = std::min(b[0], b[1]);
+  return hipSuccess;
 }
 
 uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
@@ -990,8 +1048,13 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) 
   dim3 grid(std::max<uint32_t>(1, std::min(a.n_tiles, a.max_blocks))), block(sch.threads);
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
   if (sch.groups != 1) return hipErrorInvalidValue;
-  if (sch.threads <= 512) k_step<512><<<grid, block, lds, s>>>(a);
-  else k_step<1024><<<grid, block, lds, s>>>(a);
+  if (a.p.galilean) {
+    if (sch.threads <= 512) k_step<512, true><<<grid, block, lds, s>>>(a);
+    else k_step<1024, true><<<grid, block, lds, s>>>(a);
+  } else {
+    if (sch.threads <= 512) k_step<512, false><<<grid, block, lds, s>>>(a);
+    else k_step<1024, false><<<grid, block, lds, s>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -186,6 +186,7 @@ struct mclg_server {
     p.lam_q = cfg.lambda_den;
     p.n_max = cfg.n_max;
     p.no_stream = 0;
+    p.galilean = 0;
     p.tile_sites = sch.tile_sites();
     return p;
   }
@@ -350,8 +351,9 @@ extern "C" {
 int mclg_server_sizes(const mclg_server_config *cfg, uint64_t *workspace_bytes) {
   if (!cfg || cfg->abi_version != MCLG_ABI_VERSION || cfg->max_slots == 0 || !workspace_bytes)
     return MCLG_E_INVAL;
-  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max)) return MCLG_E_INVAL;
-  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  if (!params_ok(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max, false))
+    return MCLG_E_INVAL;
+  auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max, false);
   if (!tab) return MCLG_E_INVAL;
   Schedule sch;
   *workspace_bytes = srv_layout(cfg, tab.get(), sch.tile_sites()).bytes;
@@ -366,7 +368,7 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
   std::unique_ptr<mclg_server> sv(new (std::nothrow) mclg_server());
   if (!sv) return MCLG_E_NOMEM;
   sv->cfg = *cfg;
-  sv->tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max);
+  sv->tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max, false);
   sv->lay = srv_layout(cfg, sv->tab.get(), sv->sch.tile_sites());
   sv->ws = reinterpret_cast<uint8_t *>(cfg->workspace);
   sv->arena = reinterpret_cast<uint16_t *>(cfg->arena);

@@ -15,6 +15,13 @@
 // integers, each row sums to D1^C).  For C = infinity the law is the fiber's
 // stationary distribution, proportional to 4^n0 N!/(a! n0! c!) by detailed
 // balance (Eq. (transprob)).  Thresholds are floor(2^32 * cumulative).
+//
+// Galilean-invariant acceptance (the remark after Eq. (D1Q3relax)): lambda
+// = lambda~ / sqrt(1 + 3 U^2) with the site's own U = J / N, which is
+// lambda~ N / sqrt(N^2 + 3 J^2).  It is irrational in general, so each fiber
+// uses it rounded down to 32 fractional bits in two exact integer steps,
+//     g = floor(2^32 N / sqrt(N^2 + 3 J^2)),   p = floor(g num / den),
+// and then lambda = p / 2^32 exactly (q = 2^32 in the weights above).
 #include "tables.h"
 
 #include "device.h"  // kFixedStride
@@ -170,7 +177,7 @@ inline Fiber fiber(uint32_t N, uint32_t absJ) {
 
 // Full-fiber quantised thresholds of one row (m - 1 values).
 // Finite C: band-limited propagation of e_{k0} through the weight matrix.
-bool row_finite(const Fiber &f, int32_t C, uint32_t p, uint32_t q, uint32_t k0,
+bool row_finite(const Fiber &f, int32_t C, uint64_t p, uint64_t q, uint32_t k0,
                 std::vector<uint64_t> &out, std::vector<Big> &va, std::vector<Big> &vb) {
   const uint32_t m = f.m;
   out.assign(m ? m - 1 : 0, 0);
@@ -193,7 +200,7 @@ bool row_finite(const Fiber &f, int32_t C, uint32_t p, uint32_t q, uint32_t k0,
       if (!x.n) continue;
       uint64_t up = 16ull * p * f.a(k) * f.c(k);
       uint64_t n0 = f.n0(k);
-      uint64_t dn = n0 >= 2 ? (uint64_t)p * n0 * (n0 - 1) : 0;
+      uint64_t dn = n0 >= 2 ? p * n0 * (n0 - 1) : 0;
       if (!big_fma(vb[k - lo_lim], x, D1 - up - dn)) return false;
       if (up && !big_fma(vb[k + 1 - lo_lim], x, up)) return false;
       if (dn && !big_fma(vb[k - 1 - lo_lim], x, dn)) return false;
@@ -253,25 +260,41 @@ bool row_equilibrium(const Fiber &f, std::vector<uint64_t> &out) {
 }
 
 std::mutex g_cache_mu;
-std::map<std::tuple<int32_t, uint32_t, uint32_t, uint32_t>, std::shared_ptr<const CollisionTables>>
+std::map<std::tuple<int32_t, uint32_t, uint32_t, uint32_t, bool>,
+         std::shared_ptr<const CollisionTables>>
     g_cache;
 
 }  // namespace
 
-bool params_ok(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t n_max) {
+uint64_t galilean_lambda_q(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ) {
+  uint64_t g = (uint64_t)1 << 32;
+  if (absJ && N) {
+    const u128 n2 = (u128)N * N;
+    const uint64_t x = (uint64_t)((n2 << 64) / (n2 + 3 * (u128)absJ * absJ));  // < 2^64
+    uint64_t r = (uint64_t)std::sqrt((double)x);                            // within +-1
+    while ((u128)r * r > x) --r;
+    while ((u128)(r + 1) * (r + 1) <= x) ++r;
+    g = r;
+  }
+  return (uint64_t)((u128)g * num / den);
+}
+
+bool params_ok(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t n_max, bool galilean) {
   if (lam_q == 0 || lam_p == 0 || lam_p > lam_q || lam_q >= (1u << 28)) return false;
   if (C < -1 || C > 4096 || n_max > 1023) return false;
   if (C > 0) {
     // bits of D1^C must fit the fixed width
-    double bits = std::log2(8.0 * lam_q * (double)n_max * (double)n_max + 1.0) + 1.0;
+    const double q = galilean ? 4294967296.0 : (double)lam_q;
+    double bits = std::log2(8.0 * q * (double)n_max * (double)n_max + 1.0) + 1.0;
     if (bits * C + 64 > 64.0 * (kMaxLimbs - 1)) return false;
   }
   return true;
 }
 
-bool collision_row_full(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t N, uint32_t absJ,
-                        uint32_t n0, std::vector<uint64_t> &thr) {
-  if (!params_ok(C, lam_p, lam_q, N) || absJ > N || n0 > N - absJ || ((N - absJ - n0) & 1u))
+bool collision_row_full(int32_t C, uint32_t lam_p, uint32_t lam_q, bool galilean, uint32_t N,
+                        uint32_t absJ, uint32_t n0, std::vector<uint64_t> &thr) {
+  if (!params_ok(C, lam_p, lam_q, N, galilean) || absJ > N || n0 > N - absJ ||
+      ((N - absJ - n0) & 1u))
     return false;
   Fiber f = fiber(N, absJ);
   if (N < 2 || C == 0) {
@@ -281,6 +304,9 @@ bool collision_row_full(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t N, u
   }
   if (C == -1) return row_equilibrium(f, thr);
   std::vector<Big> va, vb;
+  if (galilean)
+    return row_finite(f, C, galilean_lambda_q(lam_p, lam_q, N, absJ), (uint64_t)1 << 32,
+                      (n0 - f.par) / 2, thr, va, vb);
   return row_finite(f, C, lam_p, lam_q, (n0 - f.par) / 2, thr, va, vb);
 }
 
@@ -303,9 +329,10 @@ CompactLaw compact(uint32_t k_lo, const std::vector<uint64_t> &full) {
 }
 
 std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_p,
-                                                        uint32_t lam_q, uint32_t n_max) {
-  if (!params_ok(C, lam_p, lam_q, n_max)) return nullptr;
-  auto key = std::make_tuple(C, lam_p, lam_q, n_max);
+                                                        uint32_t lam_q, uint32_t n_max,
+                                                        bool galilean) {
+  if (!params_ok(C, lam_p, lam_q, n_max, galilean)) return nullptr;
+  auto key = std::make_tuple(C, lam_p, lam_q, n_max, galilean);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -351,7 +378,9 @@ std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_
             pc.rowdesc_rel.push_back(shared_first | (shared_q << 16));
             pc.max_q = std::max(pc.max_q, shared_q);
           } else {
-            ok = row_finite(f, C, lam_p, lam_q, k, full, va, vb);
+            ok = galilean ? row_finite(f, C, galilean_lambda_q(lam_p, lam_q, (uint32_t)N, absJ),
+                                       (uint64_t)1 << 32, k, full, va, vb)
+                          : row_finite(f, C, lam_p, lam_q, k, full, va, vb);
             CompactLaw cl = compact(0, full);
             uint32_t qn = (uint32_t)cl.thr.size() + 1;
             pc.rowdesc_rel.push_back((uint32_t)pc.thr.size());
@@ -374,6 +403,7 @@ std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_
   tab->C = C;
   tab->lam_p = lam_p;
   tab->lam_q = lam_q;
+  tab->galilean = galilean;
   tab->n_max = n_max;
   tab->rowbase.resize((size_t)(n_max + 1) * (n_max + 2) / 2);
   uint64_t rows = 0, thr_total = 0;

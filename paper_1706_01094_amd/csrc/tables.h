@@ -20,6 +20,7 @@ namespace mclg {
 struct CollisionTables {
   int32_t C = 0;
   uint32_t lam_p = 1, lam_q = 1, n_max = 0;
+  bool galilean = false;          // per-fiber lambda of galilean_lambda_q
   std::vector<uint32_t> rowbase;
   std::vector<uint32_t> rowdesc;  // pairs (offset, k_first | q << 16)
   std::vector<uint32_t> thr;
@@ -30,16 +31,23 @@ struct CollisionTables {
   std::vector<uint32_t> fixed;    // empty when not built
 };
 
-// Build (or fetch from the process cache) the tables for (C, lambda, n_max).
+// Build (or fetch from the process cache) the tables for (C, lambda, n_max),
+// with the Galilean-invariant per-fiber lambda when `galilean` is set.
 // Returns nullptr for invalid parameters.
 std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_p,
-                                                        uint32_t lam_q, uint32_t n_max);
+                                                        uint32_t lam_q, uint32_t n_max,
+                                                        bool galilean);
 
 // Full-fiber thresholds (uint64, 2^32 = "never") of one row, for inspection.
-bool collision_row_full(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t N, uint32_t absJ,
-                        uint32_t n0, std::vector<uint64_t> &thr);
+bool collision_row_full(int32_t C, uint32_t lam_p, uint32_t lam_q, bool galilean, uint32_t N,
+                        uint32_t absJ, uint32_t n0, std::vector<uint64_t> &thr);
 
-bool params_ok(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t n_max);
+bool params_ok(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t n_max, bool galilean);
+
+// Galilean-invariant acceptance of fiber (N, |J|) for lambda~ = num / den, as
+// a numerator over 2^32: floor(floor(2^32 N / sqrt(N^2 + 3 J^2)) num / den)
+// (exact integer arithmetic; 2^32 num / den for J = 0).
+uint64_t galilean_lambda_q(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ);
 
 // Equilibrium means of Eq. (D1Q3equil) with the stated IEEE evaluation order.
 void feq(double rho, double u, double out[3]);

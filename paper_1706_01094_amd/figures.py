@@ -17,7 +17,10 @@ this module only sets up the inputs, calls the engine and turns its exact
 integer sums into the figures' statistics.  The predictions it prints are the
 paper's closed forms, evaluated here in double precision.
 
-Run ``python -m paper_1706_01094_amd.figures fig1|fig3|fig5|corr [--quick]``.
+* ``galilean`` (command line) -- the relaxation rate of pi~ against u with
+  the constant and the Galilean-invariant acceptance.
+
+Run ``python -m paper_1706_01094_amd.figures fig1|fig3|fig5|corr|galilean [--quick]``.
 """
 from __future__ import annotations
 
@@ -97,6 +100,16 @@ def pi_relax(pi0: float, n_coll, rho: float, u: float = 0.0, lam: float = 1.0,
 def pi_relax_linear(pi0: float, n_coll, rho: float, lam: float = 1.0) -> np.ndarray:
     """Eq. (D1Q3relax2): exp(-C lambda / rho) pi~(0)."""
     return pi0 * np.exp(-np.asarray(n_coll, dtype=np.float64) * lam / rho)
+
+
+def _decay_rate(pit: np.ndarray, C: int) -> np.ndarray:
+    """Per-collision decay rate -ln(pi~(t) / pi~(0)) / (C t) for t >= 1 (nan
+    at t = 0 or once pi~ has crossed zero)."""
+    out = np.full(len(pit), np.nan)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = pit[1:] / pit[0]
+        out[1:] = np.where(r > 0, -np.log(r) / (C * np.arange(1, len(pit))), np.nan)
+    return out
 
 
 # ---- experiments ----------------------------------------------------------
@@ -188,12 +201,14 @@ def equilibrium_means(us: Sequence[float], rho: float = 36.0, L: int = 100, C: i
 
 def pi_decay(init: Sequence[int] = (100, 100, 100), L: int = 1000, replicas: int = 1000,
              C: int = 10, steps: int = 100, stream: bool = True, seed: int = 1,
-             n_max: int = 300, lam=(1, 1)) -> dict:
+             n_max: int = 300, lam=(1, 1), galilean: bool = False) -> dict:
     """Fig. 5 set-up: ``replicas`` lattices of L sites, every site in state
     ``init``; records the ensemble mean of pi after every step (C collisions
-    each) with or without streaming.  The per-step mean is exact (integer
-    sums); its standard error comes from the spread of the replica means."""
-    flags = 0 if stream else mclg.FLAG_NO_STREAM
+    each) with or without streaming, and with the constant acceptance lambda
+    or the Galilean-invariant one, lambda / sqrt(1 + 3 U^2).  The per-step
+    mean is exact (integer sums); its standard error comes from the spread of
+    the replica means."""
+    flags = (0 if stream else mclg.FLAG_NO_STREAM) | (mclg.FLAG_GALILEAN if galilean else 0)
     lat = mclg.Lattice([L] * replicas, seed, C=C, lam=lam, n_max=n_max, flags=flags,
                        counts=uniform_counts(init, L, replicas))
     try:
@@ -213,12 +228,13 @@ def pi_decay(init: Sequence[int] = (100, 100, 100), L: int = 1000, replicas: int
     finally:
         lat.close()
     rho = float(sum(init))
-    lam_f = lam[0] / lam[1]
     u = (init[2] - init[0]) / rho if rho else 0.0
+    lam_f = lam[0] / lam[1] / (math.sqrt(1.0 + 3.0 * u * u) if galilean else 1.0)
     pi_eq = float(pi_moment(feq(rho, u)))
     n_coll = C * np.arange(steps + 1)
     pi0 = float(pi_moment(np.asarray(init))) - pi_eq
     return {"init": tuple(init), "L": L, "replicas": replicas, "C": C, "stream": stream,
+            "galilean": galilean, "u": u, "rate": _decay_rate(mean - pi_eq, C),
             "mean": mean, "se": se, "pi_eq": pi_eq, "n_coll": n_coll,
             "pred_sqrt8": pi_eq + pi_relax(pi0, n_coll, rho, u, lam_f),
             "pred_printed": pi_eq + pi_relax(pi0, n_coll, rho, u, lam_f, coef=2 * math.sqrt(6)),
@@ -328,12 +344,56 @@ def _corr(quick: bool):
               f"{K[0, 1]:+.5f}  {K[1, 2]:+.5f}  {K[0, 2]:+.5f}  {r['E'][k]:.2e}")
 
 
+def linear_rate(mean: np.ndarray, C: int, t1: int = 5) -> float:
+    """Per-collision linear relaxation rate from successive differences,
+    -ln(((pi(t1 + 1) - pi(t1)) / (pi(1) - pi(0)))^(1 / t1)) / C, which does
+    not need the value pi relaxes to."""
+    r = (mean[t1 + 1] - mean[t1]) / (mean[1] - mean[0])
+    return -math.log(r) / (C * t1) if r > 0 else float("nan")
+
+
+def galilean_rates(us: Sequence[float] = (0.0, 0.25, 0.5, 0.75), N: int = 240, C: int = 10,
+                   L: int = 1000, replicas: int = 500, seed: int = 1) -> dict:
+    """Linear relaxation rate of pi without streaming at N particles per site
+    and site velocity U = J / N, with the constant acceptance (lambda = 1)
+    and the Galilean-invariant one.  Every site starts 8 rest particles below
+    the even count nearest f_0^eq(N, U); the prediction of Eq. (D1Q3relax)
+    for small deviations is lambda sqrt(1 + 3 U^2) / N per collision, i.e.
+    1 / N for the Galilean-invariant lambda at every U."""
+    rows = []
+    for u in us:
+        J = int(round(u * N))
+        f = feq(float(N), J / N)
+        b = 2 * int(round(f[1] / 2)) - 8
+        a = (N - b - J) // 2
+        init = (a, N - 2 * a - J, a + J)
+        r = []
+        for gal in (False, True):
+            d = pi_decay(init, L=L, replicas=replicas, C=C, steps=6, stream=False, n_max=N,
+                         seed=seed, galilean=gal)
+            r.append(linear_rate(d["mean"], C))
+        rows.append({"u": J / N, "init": init, "rate": r[0], "rate_galilean": r[1],
+                     "pred": math.sqrt(1 + 3 * (J / N) ** 2) / N, "pred_galilean": 1.0 / N})
+    return {"N": N, "C": C, "L": L, "replicas": replicas, "rows": rows}
+
+
+def _galilean(quick: bool):
+    r = galilean_rates(replicas=50 if quick else 500)
+    print(f"Galilean-invariant acceptance: N = {r['N']} per site, C = {r['C']}, no streaming, "
+          f"L = {r['L']} x {r['replicas']}")
+    print("     U    init              rate      lambda s / N   rate Galilean  lambda / N")
+    for w in r["rows"]:
+        print(f"  {w['u']:4.2f}  {str(w['init']):16s}  {w['rate']:.6f}  {w['pred']:.6f}       "
+              f"{w['rate_galilean']:.6f}       {w['pred_galilean']:.6f}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr"])
+    ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr", "galilean"])
     ap.add_argument("--quick", action="store_true", help="reduced step counts")
     a = ap.parse_args(argv)
-    {"fig1": _fig1, "fig3": _fig3, "fig5": _fig5, "corr": _corr}[a.figure](a.quick)
+    {"fig1": _fig1, "fig3": _fig3, "fig5": _fig5, "corr": _corr,
+     "galilean": _galilean}[a.figure](a.quick)
 
 
 if __name__ == "__main__":

@@ -21,6 +21,7 @@ ABI_VERSION = 1
 D1Q3, D2Q9 = 1, 2
 C_EQUILIBRIUM = -1
 FLAG_NO_STREAM = 1
+FLAG_GALILEAN = 2
 INIT_COUNTS, INIT_POISSON = 1, 2
 MAX_MODES = 8
 MAX_HIST_BINS = 4096
@@ -91,7 +92,8 @@ _SIGS = {
     "mclg_destroy": [vp],
     "mclg_strerror": [ct.c_int],
     "mclg_last_hip_error": [vp],
-    "mclg_table_row": [i32, u32, u32, u32, u32, u32, P(u64), u32, P(u32)],
+    "mclg_table_row": [i32, u32, u32, u32, u32, u32, u32, P(u64), u32, P(u32)],
+    "mclg_galilean_lambda": [u32, u32, u32, u32, P(u64)],
     "mclg_poisson_thresholds": [dbl, P(u32), P(u32), P(u64), u32],
     "mclg_server_sizes": [P(mclg_server_config), P(u64)],
     "mclg_server_create": [P(mclg_server_config), P(vp)],
@@ -133,13 +135,21 @@ def _check(rc: int, what: str) -> int:
 
 
 # ---- host-only inspection -------------------------------------------------
-def mclg_table_row(C: int, lam: Sequence[int], N: int, absJ: int, n0: int) -> np.ndarray:
+def mclg_table_row(C: int, lam: Sequence[int], N: int, absJ: int, n0: int,
+                   flags: int = 0) -> np.ndarray:
     m = (N - absJ) // 2 + 1
     thr = np.zeros(max(m - 1, 1), dtype=np.uint64)
     mo = u32(0)
-    _check(lib().mclg_table_row(C, lam[0], lam[1], N, absJ, n0,
+    _check(lib().mclg_table_row(C, lam[0], lam[1], flags, N, absJ, n0,
                                 thr.ctypes.data_as(P(u64)), len(thr), ct.byref(mo)), "mclg_table_row")
     return thr[: mo.value - 1]
+
+
+def mclg_galilean_lambda(lam: Sequence[int], N: int, absJ: int) -> int:
+    out = u64(0)
+    _check(lib().mclg_galilean_lambda(lam[0], lam[1], N, absJ, ct.byref(out)),
+           "mclg_galilean_lambda")
+    return out.value
 
 
 def mclg_poisson_thresholds(mu: float):

@@ -135,11 +135,11 @@ def one_subcollision_counted(state, lam: Fraction):
     return out
 
 
-def no_stream_pi_moments(abc, C, steps):
+def no_stream_pi_moments(abc, C, steps, lam: Fraction = Fraction(1)):
     """(E[pi], E[pi^2]) after ``steps`` steps of C sub-collisions at one site
     that never streams, started in state abc, with pi = sqrt(2) (n_-1 - n_0/2
-    + n_+1): the fiber chain of ``one_subcollision_counted`` (exact
-    probabilities, propagated in float64)."""
+    + n_+1): the fiber chain of ``one_subcollision_counted`` at acceptance
+    ``lam`` (exact probabilities, propagated in float64)."""
     N = sum(abc)
     J = abc[2] - abc[0]
     absJ = abs(J)
@@ -149,7 +149,7 @@ def no_stream_pi_moments(abc, C, steps):
     for k in range(m):
         b = par + 2 * k
         a, c = (N - b - J) // 2, (N - b + J) // 2
-        for s2, p in one_subcollision_counted((a, b, c), Fraction(1)).items():
+        for s2, p in one_subcollision_counted((a, b, c), lam).items():
             T[k, (s2[1] - par) // 2] += float(p)
     v = np.zeros(m)
     v[(abc[1] - par) // 2] = 1.0

@@ -186,3 +186,22 @@ def test_correlator_is_identity():
     dev = np.abs(r["K"] - np.eye(3))
     assert np.all(dev < 5 * r["se"] + 1e-9), (dev / r["se"]).max()
     assert np.all(r["E"] < 1e-3), r["E"]
+
+
+@pytest.mark.parametrize("init", [(44, 152, 44), (10, 100, 130)])
+def test_galilean_no_stream_equals_exact_chain(init):
+    """Galilean-invariant acceptance without streaming (N = 240, U = 0 and
+    0.5), 200 lattices of L = 1000: the mean pi after each of 6 steps equals
+    the exact single-site chain at the fiber's rounded lambda within 4
+    standard errors."""
+    from fractions import Fraction
+    N, J = sum(init), init[2] - init[0]
+    lam = Fraction(O.galilean_lambda((1, 1), N, J), 2**32)
+    say("galilean no-stream case", init)
+    r = F.pi_decay(init, L=1000, replicas=200, C=10, steps=6, stream=False, n_max=N,
+                   galilean=True)
+    assert r["check"] == 0
+    for t in range(1, 7):
+        m1, m2 = X.no_stream_pi_moments(init, 10, t, lam)
+        se = math.sqrt(max(m2 - m1 * m1, 0.0) / (1000 * 200))
+        assert abs(r["mean"][t] - m1) < 4 * se + 1e-9, (t, r["mean"][t], m1, se)

@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 import synth
-from paper_1706_01094_amd.mclg import E_RANGE, Lattice, MclgError
+from paper_1706_01094_amd.mclg import E_RANGE, FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError
 
 pytestmark = pytest.mark.gpu
 
@@ -139,6 +139,22 @@ def test_no_stream_flag():
     for _ in range(10):
         g.step(2)
         o.step(2)
+        same(g, o)
+
+
+@pytest.mark.parametrize("n_max,rho,u0,lam,flags", [
+    (255, 12.0, 0.4, (3, 4), FLAG_GALILEAN),
+    (16, 20.0, -0.5, (1, 1), FLAG_GALILEAN),
+    (16, 20.0, 0.3, (2, 3), FLAG_GALILEAN | FLAG_NO_STREAM)])
+def test_galilean_acceptance(n_max, rho, u0, lam, flags):
+    """Galilean-invariant acceptance: L = 3000, C = 10, the per-fiber tables
+    (n_max = 255) and the device's own per-site numerator in the literal loop
+    (n_max = 16, where most sites have N > n_max); every count equal to the
+    oracle's after each of 12 steps."""
+    g, o = pair(3000, 21, C=10, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags)
+    for _ in range(12):
+        g.step(1)
+        o.step(1)
         same(g, o)
 
 

@@ -44,6 +44,30 @@ def test_table_rows_equal_oracle(C, lam):
         assert np.array_equal(a, b), (N, J, n0)
 
 
+@pytest.mark.parametrize("C,lam", [(10, (1, 1)), (3, (3, 4))])
+def test_galilean_rows_and_lambda_equal_oracle(C, lam):
+    """Galilean-invariant acceptance: the library's per-fiber numerators
+    (estimate and integer correction) and flagged rows equal the oracle's
+    (bisection) for random fibers up to N = 65535 and rows up to N = 255."""
+    rng = np.random.default_rng(C + lam[0])
+    for _ in range(2000):
+        N = int(rng.integers(0, 65536))
+        J = int(rng.integers(0, N + 1))
+        assert M.mclg_galilean_lambda(lam, N, J) == O.galilean_lambda(lam, N, J), (N, J)
+    cases = [(2, 0, 0), (2, 2, 0), (37, 3, 20), (255, 0, 171), (255, 200, 1), (120, 60, 30)]
+    for _ in range(20):
+        N = int(rng.integers(2, 256))
+        J = int(rng.integers(0, N + 1))
+        k = int(rng.integers(0, (N - J) // 2 + 1))
+        cases.append((N, J, (N - J) % 2 + 2 * k))
+    for N, J, n0 in cases:
+        a = M.mclg_table_row(C, lam, N, J, n0, flags=M.FLAG_GALILEAN)
+        b = O.row_thresholds(C, lam, N, J, n0, flags=O.FLAG_GALILEAN)
+        assert np.array_equal(a, b), (N, J, n0)
+    with pytest.raises(M.MclgError):
+        M.mclg_table_row(C, lam, 4, 0, 0, flags=M.FLAG_NO_STREAM)
+
+
 @pytest.mark.parametrize("mu", [0.0, 1e-3, 0.5, 1.6666666666666667, 6.081485941486, 32.83702811702, 88.0, 612.5])
 def test_poisson_thresholds_equal_oracle(mu):
     k1, t1 = M.mclg_poisson_thresholds(mu)

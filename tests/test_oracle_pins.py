@@ -432,3 +432,97 @@ def test_pi_relaxation_without_streaming():
         mean_exact, m2 = X.no_stream_pi_moments(abc, 10, steps)
         sd = math.sqrt(max(m2 - mean_exact**2, 1e-12))
         assert abs(pi.mean() - mean_exact) < 3 * sd / math.sqrt(L) + 1e-9, (steps, pi.mean(), mean_exact)
+
+
+# --------------------------------------------------------------------------
+# Galilean-invariant acceptance (the remedy proposed after Eq. (D1Q3relax))
+# --------------------------------------------------------------------------
+def _galilean_exact(num, den, N, J):
+    """floor(floor(2^32 N / sqrt(N^2 + 3 J^2)) num / den) with Python's exact
+    integer square root: floor(sqrt(floor(y))) = floor(sqrt(y))."""
+    g = math.isqrt((2**64 * N * N) // (N * N + 3 * J * J)) if N else 2**32
+    return g * num // den
+
+
+def test_galilean_lambda_is_the_exact_rounding():
+    """The oracle's per-fiber acceptance numerator equals the exact integer
+    rounding, is within 2^-31 of lambda~ / sqrt(1 + 3 (J/N)^2), is
+    floor(2^32 lambda~) at J = 0, and never grows with |J|."""
+    rng = np.random.default_rng(3)
+    cases = [(1, 1, 0, 0), (1, 1, 1, 1), (1, 1, 65535, 65535), (3, 4, 65535, 1),
+             (2, 3, 300, 150), ((1 << 28) - 1, (1 << 28) - 1, 1000, 999)]
+    for _ in range(3000):
+        den = int(rng.integers(1, 1 << 28))
+        num = int(rng.integers(1, den + 1))
+        N = int(rng.integers(0, 65536))
+        cases.append((num, den, N, int(rng.integers(0, N + 1))))
+    for num, den, N, J in cases:
+        got = O.galilean_lambda((num, den), N, J)
+        assert got == _galilean_exact(num, den, N, J), (num, den, N, J)
+        lam = num / den / math.sqrt(1 + 3 * (J / N) ** 2) if N else num / den
+        assert abs(got / 2**32 - lam) < 2**-31
+    for N in (2, 17, 255, 4000):
+        seq = [O.galilean_lambda((1, 1), N, J) for J in range(N + 1)]
+        assert seq[0] == 2**32 and all(x >= y for x, y in zip(seq, seq[1:]))
+
+
+@pytest.mark.parametrize("C", [1, 3])
+@pytest.mark.parametrize("lam", [(1, 1), (3, 4)])
+def test_galilean_rows_equal_brute_force(C, lam):
+    """With the flag, each fiber's quantised rows equal the enumerated law of
+    the literal loop at lambda = (its rounded numerator) / 2^32."""
+    for N in range(0, 7):
+        for a, b, c in _states(N):
+            J = abs(c - a)
+            lf = Fraction(_galilean_exact(lam[0], lam[1], N, J), 2**32)
+            want = X.quantise(X.rest_marginal(X.c_step_law((a, b, c), C, lf), N, J))
+            got = O.row_thresholds(C, lam, N, J, b, flags=O.FLAG_GALILEAN)
+            assert [int(v) for v in got] == want, (a, b, c)
+
+
+@pytest.mark.parametrize("abc", [(1, 2, 5), (30, 10, 5), (0, 40, 12)])
+def test_galilean_direct_sampler_follows_rows(abc):
+    """The literal loop with the Galilean acceptance (one word against the
+    numerator for a moving pair, a 35-bit uniform for a rest pair) draws from
+    the exact law of the flagged rows (chi-squared, p > 1e-3)."""
+    n = 400_000
+    C = 10
+    h = O.histogram(C, (1, 1), abc, n, seed=9, t=2, direct=True, flags=O.FLAG_GALILEAN)
+    N, J = sum(abc), abs(abc[2] - abc[0])
+    lf = Fraction(_galilean_exact(1, 1, N, J), 2**32)
+    if N <= 12:
+        probs = [float(p) for p in X.rest_marginal(X.c_step_law(abc, C, lf), N, J)]
+    else:
+        thr = O.row_thresholds(C, (1, 1), N, J, abc[1], flags=O.FLAG_GALILEAN).astype(np.float64)
+        cum = np.concatenate([[0.0], thr / 2**32, [1.0]])
+        probs = list(np.diff(cum))
+    par = (N - J) % 2
+    counts = [int(h[par + 2 * k]) for k in range(len(probs))]
+    assert sum(counts) == n
+    assert _chi2_pvalue(counts, probs, n) > 1e-3
+
+
+def _fiber_gap(N, J, lam):
+    par, m = (N - J) % 2, (N - J) // 2 + 1
+    T = np.zeros((m, m))
+    for k in range(m):
+        b = par + 2 * k
+        for s2, p in X.one_subcollision_counted(((N - b - J) // 2, b, (N - b + J) // 2), lam).items():
+            T[k, (s2[1] - par) // 2] += float(p)
+    ev = np.sort(np.real(np.linalg.eigvals(T)))[::-1]
+    return 1.0 - ev[1]
+
+
+def test_galilean_acceptance_removes_velocity_dependence_of_relaxation():
+    """Relaxation rate of one fiber (spectral gap of the one-sub-collision
+    chain, N = 240): with a constant lambda it grows as sqrt(1 + 3 U^2)
+    (the velocity dependence of Eq. (D1Q3relax)), with the Galilean
+    acceptance it stays at the U = 0 value within 1%."""
+    N = 240
+    g0 = _fiber_gap(N, 0, Fraction(1))
+    for J in (60, 120, 180):
+        U = J / N
+        plain = _fiber_gap(N, J, Fraction(1)) / g0
+        assert plain == pytest.approx(math.sqrt(1 + 3 * U * U), rel=0.01)
+        gal = _fiber_gap(N, J, Fraction(_galilean_exact(1, 1, N, J), 2**32)) / g0
+        assert gal == pytest.approx(1.0, abs=0.01)

@@ -71,8 +71,35 @@ def lib() -> ct.CDLL:
         L.mco_collide_site.argtypes = [i32, u32, u32, u32, u32, u64, u64, u64, u64, P(u32)]
         L.mco_collide_site_direct.argtypes = [i32, u32, u32, u32, u64, u64, u64, u64, P(u32)]
         L.mco_histogram.argtypes = [i32, u32, u32, u32, ct.c_int, u64, u64, u64, P(u32), P(u64)]
+        L.mco9_create.argtypes = [u32, P(u64), P(u64), P(u64), u64, i32, P(u32), u32,
+                                  P(ct.c_void_p)]
+        L.mco9_destroy.argtypes = [ct.c_void_p]
+        L.mco9_destroy.restype = None
+        L.mco9_init_counts.argtypes = [ct.c_void_p, u32, P(ct.c_uint16)]
+        L.mco9_init_poisson.argtypes = [ct.c_void_p, u32, ct.c_double, ct.c_double, ct.c_double]
+        L.mco9_step.argtypes = [ct.c_void_p, u64]
+        L.mco9_get_counts.argtypes = [ct.c_void_p, u32, P(ct.c_uint16)]
+        L.mco9_get_t.argtypes = [ct.c_void_p, u32]
+        L.mco9_get_t.restype = i64
+        L.mco9_moments.argtypes = [ct.c_void_p, u32, P(Moments9)]
+        L.mco9_feq.argtypes = [ct.c_double, ct.c_double, ct.c_double, P(ct.c_double)]
+        L.mco9_feq.restype = None
+        L.mco9_targets.argtypes = [P(u32), u32, u32, P(u32), P(u32), P(u32), P(u32), P(u64),
+                                   P(u64)]
+        L.mco9_collide_site.argtypes = [i32, P(u32), u64, u64, u64, u64, P(u32)]
         _lib = L
     return _lib
+
+
+class Moments9(ct.Structure):
+    _fields_ = [("t", ct.c_int64), ("sites", ct.c_int64), ("sum_n", ct.c_int64 * 9),
+                ("sum_nn", ct.c_int64 * 45), ("sum_N", ct.c_int64), ("sum_Jx", ct.c_int64),
+                ("sum_Jy", ct.c_int64), ("max_N", ct.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"t": self.t, "sites": self.sites, "sum_n": list(self.sum_n),
+                "sum_nn": list(self.sum_nn), "sum_N": self.sum_N, "sum_Jx": self.sum_Jx,
+                "sum_Jy": self.sum_Jy, "max_N": self.max_N}
 
 
 def _ptr(arr: np.ndarray, ctype):
@@ -221,4 +248,98 @@ class OracleSim:
             n_modes = tw.shape[0] // 2
             rc = lib().mco_moments(self._h, rep, _ptr(tw, ct.c_int32), n_modes, ct.byref(m))
         _check(rc, "moments")
+        return m.as_dict()
+
+
+# ---- D2Q9 -------------------------------------------------------------------
+# Velocity i of D2Q9 (columns of Eq. (MomD2Q9)).
+V9 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+# lambda_1..9 of the paper's D2Q9 equilibrium run (lambda_1 = 15/128,
+# lambda_2-7 = 1/4, lambda_8 = 1/8, lambda_9 = 18/144).
+LAMBDA9_PAPER = [(15, 128)] + [(1, 4)] * 6 + [(1, 8), (18, 144)]
+
+
+def _lam9(lams) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(lams, dtype=np.uint32).reshape(18))
+
+
+def targets9(lams, i: int, j: int):
+    """[(k, l, class, weight)], D for the ordered source pair (i, j)."""
+    lam = _lam9(lams)
+    n = ct.c_uint32(0)
+    k = (ct.c_uint32 * 8)(); l_ = (ct.c_uint32 * 8)(); c = (ct.c_uint32 * 8)()
+    w = (ct.c_uint64 * 8)(); D = ct.c_uint64(0)
+    _check(lib().mco9_targets(_ptr(lam, ct.c_uint32), i, j, ct.byref(n), k, l_, c, w,
+                              ct.byref(D)), "targets9")
+    return [(k[q], l_[q], c[q], w[q]) for q in range(n.value)], D.value
+
+
+def feq9(rho: float, ux: float, uy: float) -> np.ndarray:
+    out = np.zeros(9, dtype=np.float64)
+    lib().mco9_feq(rho, ux, uy, _ptr(out, ct.c_double))
+    return out
+
+
+def collide_site9(C, lams, seed, replica, t, s, n9):
+    n = np.ascontiguousarray(np.asarray(n9, dtype=np.uint32).copy())
+    lam = _lam9(lams)
+    _check(lib().mco9_collide_site(C, _ptr(lam, ct.c_uint32), seed, replica, t, s,
+                                   _ptr(n, ct.c_uint32)), "collide_site9")
+    return n
+
+
+class OracleSim9:
+    """n_rep independent periodic D2Q9 lattices (Lx x Ly) advanced by the oracle."""
+
+    def __init__(self, Lx, Ly, seed, C=10, lams=LAMBDA9_PAPER, replica_id=None, flags=0):
+        self.Lx = np.ascontiguousarray(np.atleast_1d(np.asarray(Lx, dtype=np.uint64)))
+        self.Ly = np.ascontiguousarray(np.broadcast_to(np.asarray(Ly, dtype=np.uint64),
+                                                       self.Lx.shape).copy())
+        self.n_rep = len(self.Lx)
+        rid = None if replica_id is None else np.ascontiguousarray(np.asarray(replica_id, dtype=np.uint64))
+        lam = _lam9(lams)
+        h = ct.c_void_p()
+        rc = lib().mco9_create(self.n_rep, _ptr(self.Lx, ct.c_uint64), _ptr(self.Ly, ct.c_uint64),
+                               None if rid is None else _ptr(rid, ct.c_uint64), seed, C,
+                               _ptr(lam, ct.c_uint32), flags, ct.byref(h))
+        if rc != 0:
+            raise OracleError(f"mco9_create rc={rc}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mco9_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sites(self, rep: int = 0) -> int:
+        return int(self.Lx[rep]) * int(self.Ly[rep])
+
+    def init_counts(self, rep: int, counts: np.ndarray):
+        c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint16).reshape(9 * self.sites(rep)))
+        _check(lib().mco9_init_counts(self._h, rep, _ptr(c, ct.c_uint16)), "init_counts9")
+
+    def init_poisson(self, rep: int, rho: float, ux: float, uy: float):
+        _check(lib().mco9_init_poisson(self._h, rep, rho, ux, uy), "init_poisson9")
+
+    def step(self, n: int = 1) -> int:
+        return lib().mco9_step(self._h, n)
+
+    def counts(self, rep: int = 0) -> np.ndarray:
+        """[9, Ly, Lx] uint16."""
+        out = np.zeros(9 * self.sites(rep), dtype=np.uint16)
+        _check(lib().mco9_get_counts(self._h, rep, _ptr(out, ct.c_uint16)), "get_counts9")
+        return out.reshape(9, int(self.Ly[rep]), int(self.Lx[rep]))
+
+    def t(self, rep: int = 0) -> int:
+        return int(lib().mco9_get_t(self._h, rep))
+
+    def moments(self, rep: int = 0) -> dict:
+        m = Moments9()
+        _check(lib().mco9_moments(self._h, rep, ct.byref(m)), "moments9")
         return m.as_dict()

@@ -815,3 +815,344 @@ int mco_histogram(int32_t C, uint32_t p, uint32_t q, uint32_t flags, int direct,
   }
   return MCO_OK;
 }
+
+/* ======================================================================== */
+/* D2Q9 (Sec. "A D2Q9 implementation").                                      */
+/*                                                                           */
+/* Velocities numbered as the columns of the moment matrix Eq. (MomD2Q9):    */
+/*   0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1),                          */
+/*   5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1);                                 */
+/* weights w = 4/9, 1/9 (axis), 1/36 (diagonal) = 576, 144, 36 / 1296.       */
+/* A sub-collision picks an ordered pair of distinct particles (R1) with     */
+/* velocities (i, j).  The binary collisions that change the state and       */
+/* conserve momentum take the unordered pair A = {i, j} to another unordered */
+/* pair B = {k, l} of the same total momentum (R8):                          */
+/*   P(A -> B) = lambda_c min(1, m_B w_k w_l / (m_A w_i w_j)),               */
+/* m = 2 for two different velocities, 1 for two equal ones: detailed       */
+/* balance with respect to the product weights, the faster direction at      */
+/* lambda_c, exactly as the D1Q3 table (lambda from {-1,1} to {0,0},         */
+/* 2 x lambda/16 back).  The class c of a transition, numbered as the        */
+/* lambda_1..9 of Eq. (D2Q9MOmega):                                          */
+/*   1 {0,5}<->{1,2} (momentum (1,1)),  2 rest <-> axis pair,                */
+/*   3 rest <-> diagonal pair,  4 axis <-> diagonal pair,                    */
+/*   5 axis <-> axis pair,  6 diagonal <-> diagonal pair,                    */
+/*   7 {0,1}<->{2,8} and {0,1}<->{4,5} (momentum (1,0), with a rest          */
+/*     particle),  8 {2,8}<->{4,5},  9 {1,1}<->{5,8} (momentum (2,0)),       */
+/* and their rotations by multiples of 90 degrees.                           */
+/* One uniform integer u in [0, D), D = lcm(lambda denominators) * 2^7,      */
+/* picks the target: targets of A in ascending (min(k,l), max(k,l)), u below */
+/* the running sum of their integer weights D P(A -> B) selects one, else    */
+/* nothing changes.                                                          */
+/* ======================================================================== */
+static const int V9[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                             {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+static const uint64_t W9[9] = {576, 144, 144, 144, 144, 36, 36, 36, 36};
+
+static int kind9(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 2); } /* rest, axis, diagonal */
+
+/* class (1..9) of the transition between unordered pairs {i,j} and {k,l}
+ * of equal momentum, 0 if they are the same pair */
+static int class9(int i, int j, int k, int l) {
+  if ((i == k && j == l) || (i == l && j == k)) return 0;
+  int px = V9[i][0] + V9[j][0], py = V9[i][1] + V9[j][1];
+  if (px == 0 && py == 0) {
+    int a = kind9(i) == 0 ? 0 : kind9(i), b = kind9(k);
+    if (a > b) { int t = a; a = b; b = t; }
+    if (a == 0 && b == 1) return 2;
+    if (a == 0 && b == 2) return 3;
+    if (a == 1 && b == 2) return 4;
+    if (a == 1 && b == 1) return 5;
+    return 6;
+  }
+  if (abs(px) + abs(py) == 1) return (i == 0 || j == 0 || k == 0 || l == 0) ? 7 : 8;
+  if (abs(px) == 1 && abs(py) == 1) return 1;
+  return 9; /* |p| = 2 along an axis */
+}
+
+typedef struct {
+  uint32_t n;         /* number of targets */
+  uint8_t k[8], l[8]; /* target pair, k <= l */
+  uint8_t cls[8];
+  uint64_t wgt[8];    /* integer weight D * P */
+} targets9;
+
+typedef struct {
+  uint64_t D;
+  targets9 tg[9][9]; /* by ordered source (i, j) */
+} rules9;
+
+static uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) { uint64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+/* lam[2c-2], lam[2c-1] = numerator, denominator of lambda_c */
+static int rules9_build(const uint32_t lam[18], rules9 *R) {
+  uint64_t L = 1;
+  for (int c = 0; c < 9; ++c) {
+    if (lam[2 * c + 1] == 0 || lam[2 * c] > lam[2 * c + 1]) return MCO_E_INVAL;
+    L = L / gcd64(L, lam[2 * c + 1]) * lam[2 * c + 1];
+    if (L >= (1u << 25)) return MCO_E_INVAL;
+  }
+  R->D = L << 7;
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      targets9 *T = &R->tg[i][j];
+      T->n = 0;
+      uint64_t mA = (i == j) ? 1 : 2, sum = 0;
+      for (int k = 0; k < 9; ++k)
+        for (int l = k; l < 9; ++l) {
+          if (V9[k][0] + V9[l][0] != V9[i][0] + V9[j][0] ||
+              V9[k][1] + V9[l][1] != V9[i][1] + V9[j][1])
+            continue;
+          int c = class9(i, j, k, l);
+          if (!c) continue;
+          uint64_t mB = (k == l) ? 1 : 2;
+          uint64_t num = mB * W9[k] * W9[l], den = mA * W9[i] * W9[j];
+          /* D * lambda_c * min(1, num / den), exact (num/den is a power of 2 >= 2^-7) */
+          uint64_t base = R->D / lam[2 * c - 1] * lam[2 * c - 2];
+          uint64_t w = num >= den ? base : base * num / den;
+          if (num < den && (base * num) % den) return MCO_E_INVAL; /* cannot happen */
+          T->k[T->n] = (uint8_t)k; T->l[T->n] = (uint8_t)l; T->cls[T->n] = (uint8_t)c;
+          T->wgt[T->n] = w;
+          T->n++;
+          sum += w;
+        }
+      if (sum > R->D) return MCO_E_INVAL; /* total probability above one */
+    }
+  return MCO_OK;
+}
+
+int mco9_targets(const uint32_t lam[18], uint32_t i, uint32_t j, uint32_t *n, uint32_t k[8],
+                 uint32_t l[8], uint32_t cls[8], uint64_t wgt[8], uint64_t *D) {
+  if (i > 8 || j > 8) return MCO_E_INVAL;
+  rules9 R;
+  int rc = rules9_build(lam, &R);
+  if (rc) return rc;
+  const targets9 *T = &R.tg[i][j];
+  *n = T->n;
+  for (uint32_t q = 0; q < T->n; ++q) {
+    k[q] = T->k[q]; l[q] = T->l[q]; cls[q] = T->cls[q]; wgt[q] = T->wgt[q];
+  }
+  *D = R.D;
+  return MCO_OK;
+}
+
+/* The literal loop of C sub-collisions at one D2Q9 site (R1, R8). */
+static void collide9(int32_t C, const rules9 *R, word_stream *ws, uint64_t n[9]) {
+  uint64_t N = 0;
+  for (int i = 0; i < 9; ++i) N += n[i];
+  if (N < 2) return;
+  for (int32_t sub = 0; sub < C; ++sub) {
+    uint32_t r1 = ws_uniform(ws, (uint32_t)N);
+    uint32_t r2 = ws_uniform(ws, (uint32_t)(N - 1));
+    if (r2 >= r1) r2 += 1;
+    /* Eq. (select): velocity by cumulative sums in the order 0..8 */
+    int v1 = 0, v2 = 0;
+    uint64_t cum = 0;
+    for (int i = 0; i < 9; ++i) { cum += n[i]; if (r1 >= cum) v1 = i + 1; }
+    cum = 0;
+    for (int i = 0; i < 9; ++i) { cum += n[i]; if (r2 >= cum) v2 = i + 1; }
+    const targets9 *T = &R->tg[v1][v2];
+    if (!T->n) continue;
+    uint32_t u = ws_uniform(ws, (uint32_t)R->D);
+    uint64_t run = 0;
+    for (uint32_t q = 0; q < T->n; ++q) {
+      run += T->wgt[q];
+      if (u < run) {
+        n[v1] -= 1; n[v2] -= 1; n[T->k[q]] += 1; n[T->l[q]] += 1; /* Eq. (omega) */
+        break;
+      }
+    }
+  }
+}
+
+int mco9_collide_site(int32_t C, const uint32_t lam[18], uint64_t seed, uint64_t replica,
+                      uint64_t t, uint64_t s, uint32_t n9[9]) {
+  if (C < 0) return MCO_E_INVAL;
+  rules9 R;
+  int rc = rules9_build(lam, &R);
+  if (rc) return rc;
+  uint64_t n[9];
+  for (int i = 0; i < 9; ++i) n[i] = n9[i];
+  word_stream ws = {seed, (uint32_t)s, (uint32_t)t, (uint32_t)replica, 0, 4, {0, 0, 0, 0}};
+  collide9(C, &R, &ws, n);
+  for (int i = 0; i < 9; ++i) n9[i] = (uint32_t)n[i];
+  return MCO_OK;
+}
+
+/* Eq. (D2Q9eqdist): the product of the D1Q3 equilibria of Eq. (D1Q3equil)
+ * at unit density, times rho, evaluated as (rho * Fx[vx]) * Fy[vy]. */
+void mco9_feq(double rho, double ux, double uy, double out[9]) {
+  double fx[3], fy[3];
+  mco_feq(1.0, ux, fx);
+  mco_feq(1.0, uy, fy);
+  for (int i = 0; i < 9; ++i) out[i] = (rho * fx[V9[i][0] + 1]) * fy[V9[i][1] + 1];
+}
+
+struct mco_sim9 {
+  uint32_t n_rep, flags;
+  int32_t C;
+  uint64_t seed;
+  rules9 R;
+  uint64_t *Lx, *Ly, *rid;
+  int64_t *t;
+  uint16_t **cur, **nxt; /* per replica [9][Ly][Lx] */
+};
+
+void mco9_destroy(mco_sim9 *s) {
+  if (!s) return;
+  for (uint32_t r = 0; r < s->n_rep; ++r) {
+    if (s->cur) free(s->cur[r]);
+    if (s->nxt) free(s->nxt[r]);
+  }
+  free(s->cur); free(s->nxt); free(s->Lx); free(s->Ly); free(s->rid); free(s->t);
+  free(s);
+}
+
+int mco9_create(uint32_t n_rep, const uint64_t *Lx, const uint64_t *Ly,
+                const uint64_t *replica_id, uint64_t seed, int32_t C, const uint32_t lam[18],
+                uint32_t flags, mco_sim9 **out) {
+  if (!out || !n_rep || !Lx || !Ly || C < 0 || C > 4096 || (flags & ~(uint32_t)MCO_FLAG_NO_STREAM))
+    return MCO_E_INVAL;
+  mco_sim9 *s = (mco_sim9 *)calloc(1, sizeof(mco_sim9));
+  if (!s) return MCO_E_NOMEM;
+  int rc = rules9_build(lam, &s->R);
+  if (rc) { free(s); return rc; }
+  s->n_rep = n_rep; s->flags = flags; s->C = C; s->seed = seed;
+  s->Lx = (uint64_t *)calloc(n_rep, 8); s->Ly = (uint64_t *)calloc(n_rep, 8);
+  s->rid = (uint64_t *)calloc(n_rep, 8); s->t = (int64_t *)calloc(n_rep, 8);
+  s->cur = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
+  s->nxt = (uint16_t **)calloc(n_rep, sizeof(uint16_t *));
+  if (!s->Lx || !s->Ly || !s->rid || !s->t || !s->cur || !s->nxt) { mco9_destroy(s); return MCO_E_NOMEM; }
+  for (uint32_t r = 0; r < n_rep; ++r) {
+    if (!Lx[r] || !Ly[r] || Lx[r] * Ly[r] >= (1ull << 32) ||
+        (replica_id && replica_id[r] >= (1ull << 32))) {
+      mco9_destroy(s);
+      return MCO_E_INVAL;
+    }
+    s->Lx[r] = Lx[r]; s->Ly[r] = Ly[r];
+    s->rid[r] = replica_id ? replica_id[r] : r;
+    s->cur[r] = (uint16_t *)calloc(9 * Lx[r] * Ly[r], 2);
+    s->nxt[r] = (uint16_t *)calloc(9 * Lx[r] * Ly[r], 2);
+    if (!s->cur[r] || !s->nxt[r]) { mco9_destroy(s); return MCO_E_NOMEM; }
+  }
+  *out = s;
+  return MCO_OK;
+}
+
+int mco9_init_counts(mco_sim9 *s, uint32_t rep, const uint16_t *counts) {
+  if (!s || rep >= s->n_rep || !counts) return MCO_E_INVAL;
+  memcpy(s->cur[rep], counts, 9 * s->Lx[rep] * s->Ly[rep] * 2);
+  s->t[rep] = 0;
+  return MCO_OK;
+}
+
+/* n_i(x, y) ~ Poisson(f_i^eq(rho, ux, uy)) with the threshold rule of R6;
+ * site s = y Lx + x draws Philox blocks (s, j, replica, INIT) for j = 0, 1,
+ * 2, word w of block j serving velocity 4 j + w. */
+int mco9_init_poisson(mco_sim9 *s, uint32_t rep, double rho, double ux, double uy) {
+  if (!s || rep >= s->n_rep || !(rho >= 0.0) || !(ux >= -1.0 && ux <= 1.0) ||
+      !(uy >= -1.0 && uy <= 1.0))
+    return MCO_E_INVAL;
+  double mu[9];
+  mco9_feq(rho, ux, uy, mu);
+  enum { CAP = 1 << 16 };
+  uint64_t *thr = (uint64_t *)malloc(sizeof(uint64_t) * CAP);
+  if (!thr) return MCO_E_NOMEM;
+  const uint64_t S = s->Lx[rep] * s->Ly[rep];
+  for (int i = 0; i < 9; ++i) {
+    uint32_t k_lo, cnt;
+    int rc = mco_poisson_thresholds(mu[i], &k_lo, &cnt, thr, CAP);
+    if (rc) { free(thr); return rc; }
+    for (uint64_t x = 0; x < S; ++x) {
+      uint32_t words[4];
+      uint32_t ctr[4] = {(uint32_t)x, (uint32_t)(i / 4), (uint32_t)s->rid[rep], PURPOSE_INIT};
+      uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
+      mco_philox4x32_10(ctr, key, words);
+      uint32_t r = words[i % 4];
+      uint32_t idx = 0;
+      for (uint32_t k = 0; k + 1 < cnt; ++k) idx += (thr[k] <= r);
+      uint32_t n = k_lo + idx;
+      if (n > 65535u) { free(thr); return MCO_E_RANGE; }
+      s->cur[rep][(uint64_t)i * S + x] = (uint16_t)n;
+    }
+  }
+  free(thr);
+  s->t[rep] = 0;
+  return MCO_OK;
+}
+
+/* One step: the literal loop at every site (pre-collision state, RNG counter
+ * t, R2), then n_i(x + vx, y + vy) <- post-collision n_i(x, y), periodic. */
+int mco9_step(mco_sim9 *s, uint64_t nsteps) {
+  if (!s) return MCO_E_INVAL;
+  int status = MCO_OK;
+  const int stream = !(s->flags & MCO_FLAG_NO_STREAM);
+  for (uint32_t r = 0; r < s->n_rep; ++r) {
+    const uint64_t Lx = s->Lx[r], Ly = s->Ly[r], S = Lx * Ly;
+    for (uint64_t st = 0; st < nsteps; ++st) {
+      const uint16_t *in = s->cur[r];
+      uint16_t *out = s->nxt[r];
+      for (uint64_t y = 0; y < Ly; ++y)
+        for (uint64_t x = 0; x < Lx; ++x) {
+          const uint64_t site = y * Lx + x;
+          uint64_t n[9], N = 0;
+          for (int i = 0; i < 9; ++i) { n[i] = in[i * S + site]; N += n[i]; }
+          if (N > 65535u) {
+            status = MCO_E_RANGE; /* not collided (R15) */
+          } else {
+            word_stream ws = {s->seed, (uint32_t)site, (uint32_t)s->t[r], (uint32_t)s->rid[r],
+                              0, 4, {0, 0, 0, 0}};
+            collide9(s->C, &s->R, &ws, n);
+          }
+          for (int i = 0; i < 9; ++i) {
+            uint64_t xd = x, yd = y;
+            if (stream) {
+              xd = (x + Lx + (uint64_t)(int64_t)V9[i][0]) % Lx;
+              yd = (y + Ly + (uint64_t)(int64_t)V9[i][1]) % Ly;
+            }
+            out[i * S + yd * Lx + xd] = (uint16_t)n[i];
+          }
+        }
+      s->nxt[r] = s->cur[r];
+      s->cur[r] = out;
+      s->t[r] += 1;
+    }
+  }
+  return status;
+}
+
+int mco9_get_counts(const mco_sim9 *s, uint32_t rep, uint16_t *out) {
+  if (!s || rep >= s->n_rep || !out) return MCO_E_INVAL;
+  memcpy(out, s->cur[rep], 9 * s->Lx[rep] * s->Ly[rep] * 2);
+  return MCO_OK;
+}
+
+int64_t mco9_get_t(const mco_sim9 *s, uint32_t rep) { return s && rep < s->n_rep ? s->t[rep] : -1; }
+
+/* Exact sums over sites: sum n_i, sum n_i n_j (i <= j, row-major upper
+ * triangle, 45 values), sum N, sum Jx, sum Jy, max N. */
+int mco9_moments(const mco_sim9 *s, uint32_t rep, mco_moments9_t *o) {
+  if (!s || rep >= s->n_rep || !o) return MCO_E_INVAL;
+  memset(o, 0, sizeof(*o));
+  const uint64_t S = s->Lx[rep] * s->Ly[rep];
+  const uint16_t *c = s->cur[rep];
+  for (uint64_t x = 0; x < S; ++x) {
+    int64_t n[9], N = 0, jx = 0, jy = 0;
+    for (int i = 0; i < 9; ++i) {
+      n[i] = c[i * S + x];
+      N += n[i]; jx += V9[i][0] * n[i]; jy += V9[i][1] * n[i];
+    }
+    int q = 0;
+    for (int i = 0; i < 9; ++i) {
+      o->sum_n[i] += n[i];
+      for (int j = i; j < 9; ++j) o->sum_nn[q++] += n[i] * n[j];
+    }
+    o->sum_N += N; o->sum_Jx += jx; o->sum_Jy += jy;
+    if (N > o->max_N) o->max_N = N;
+  }
+  o->t = s->t[rep];
+  o->sites = (int64_t)S;
+  return MCO_OK;
+}

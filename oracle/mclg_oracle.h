@@ -102,6 +102,34 @@ int mco_histogram(int32_t C, uint32_t lam_p, uint32_t lam_q, uint32_t flags, int
                   uint64_t seed, uint64_t t, uint64_t n_draws,
                   const uint32_t abc[3], uint64_t *hist);
 
+/* ---- D2Q9 (velocities numbered as the columns of Eq. (MomD2Q9)) ---- */
+typedef struct mco_sim9 mco_sim9;
+typedef struct {
+  int64_t t, sites;
+  int64_t sum_n[9];
+  int64_t sum_nn[45]; /* sum n_i n_j, i <= j, row-major upper triangle */
+  int64_t sum_N, sum_Jx, sum_Jy, max_N;
+} mco_moments9_t;
+/* lam[2c-2] / lam[2c-1] = lambda_c, c = 1..9 (classes of Eq. (D2Q9MOmega)) */
+int mco9_create(uint32_t n_rep, const uint64_t *Lx, const uint64_t *Ly,
+                const uint64_t *replica_id, uint64_t seed, int32_t C,
+                const uint32_t lam[18], uint32_t flags, mco_sim9 **out);
+void mco9_destroy(mco_sim9 *s);
+/* counts: [9][Ly][Lx] */
+int mco9_init_counts(mco_sim9 *s, uint32_t rep, const uint16_t *counts);
+int mco9_init_poisson(mco_sim9 *s, uint32_t rep, double rho, double ux, double uy);
+int mco9_step(mco_sim9 *s, uint64_t n);
+int mco9_get_counts(const mco_sim9 *s, uint32_t rep, uint16_t *out);
+int64_t mco9_get_t(const mco_sim9 *s, uint32_t rep);
+int mco9_moments(const mco_sim9 *s, uint32_t rep, mco_moments9_t *out);
+void mco9_feq(double rho, double ux, double uy, double out[9]);
+/* targets of the ordered source pair (i, j): n, pairs (k <= l), classes and
+ * integer weights over D */
+int mco9_targets(const uint32_t lam[18], uint32_t i, uint32_t j, uint32_t *n, uint32_t k[8],
+                 uint32_t l[8], uint32_t cls[8], uint64_t wgt[8], uint64_t *D);
+int mco9_collide_site(int32_t C, const uint32_t lam[18], uint64_t seed, uint64_t replica,
+                      uint64_t t, uint64_t s, uint32_t n9[9]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,7 +53,7 @@ enum {
   MCLG_E_RANGE = -2,       /* a site exceeded N = 65535 (or n_max with C = inf) */
   MCLG_E_HIP = -3,         /* HIP runtime error; see mclg_last_hip_error */
   MCLG_E_NOMEM = -4,       /* host allocation failed */
-  MCLG_E_UNSUPPORTED = -5, /* lattice or mode not implemented (D2Q9) */
+  MCLG_E_UNSUPPORTED = -5, /* entry point not available for the context's lattice */
   MCLG_E_FULL = -6,        /* server: no slot or arena space for the job */
   MCLG_E_INTERNAL = -7     /* a device-side consistency check failed (a library bug) */
 };
@@ -87,7 +87,7 @@ typedef struct mclg_ctx mclg_ctx;
  * L[r] sites and RNG identity replica_id[r] (default r). */
 typedef struct {
   uint32_t abi_version;        /* MCLG_ABI_VERSION */
-  uint32_t lattice;            /* MCLG_D1Q3 */
+  uint32_t lattice;            /* MCLG_D1Q3 or MCLG_D2Q9 */
   uint32_t n_replicas;         /* >= 1 */
   uint32_t flags;              /* MCLG_FLAG_* */
   const uint64_t *L;           /* host [n_replicas]; 1 <= L <= 2^29 */
@@ -102,6 +102,10 @@ typedef struct {
   uint64_t state_bytes;
   void *workspace;             /* device, caller-owned, >= workspace_bytes of mclg_sizes */
   uint64_t workspace_bytes;
+  /* MCLG_D2Q9 only (NULL for D1Q3, where lambda_num/den and n_max apply): */
+  const uint64_t *Ly;          /* host [n_replicas]; L[r] is then Lx; Lx Ly <= 2^28 */
+  const uint32_t *lambda9;     /* host [18]: lambda_c = lambda9[2c-2] / lambda9[2c-1] in
+                                  [0, 1], c = 1..9 (the D2Q9 classes below) */
 } mclg_config;
 
 typedef struct {
@@ -110,7 +114,11 @@ typedef struct {
                                   block is [3][L[r]] (n_-1, n_0, n_+1 rows) in
                                   logical site order; replicas packed densely */
   const double *rho;           /* POISSON: host [n_replicas], mean density >= 0 */
-  const double *u0;            /* POISSON: host [n_replicas], velocity in [-1, 1] */
+  const double *u0;            /* POISSON: host [n_replicas], velocity in [-1, 1]
+                                  (D2Q9: its x component) */
+  const double *u0y;           /* D2Q9 POISSON: host [n_replicas], y velocity, or NULL
+                                  for 0.  D2Q9 COUNTS: replica r's block is
+                                  [9][Ly][Lx] in logical order */
 } mclg_init_spec;
 
 /* Exact integer sums over the sites of one replica (modulo 2^64). */
@@ -127,6 +135,50 @@ typedef struct {
   int64_t max_N;       /* max_x N(x) */
   int64_t fourier[MCLG_MAX_MODES][2]; /* sum N(x) tw[2m][x], sum N(x) tw[2m+1][x] */
 } mclg_moments_t;
+
+/* ---- D2Q9 (Sec. "A D2Q9 implementation") ----
+ * Velocities numbered as the columns of the moment matrix Eq. (MomD2Q9):
+ * 0 (0,0), 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1), 7 (-1,-1),
+ * 8 (1,-1); weights 4/9, 1/9, 1/36.  The paper leaves the binary collision
+ * rules to a missing figure; the library (and its tests) take every swap of
+ * an unordered velocity pair A = {i, j} for another pair B = {k, l} of the
+ * same total momentum, with
+ *   P(A -> B) = lambda_c min(1, m_B w_k w_l / (m_A w_i w_j)),
+ * m = 2 for two different velocities and 1 for two equal ones (detailed
+ * balance with respect to the product weights; the D1Q3 table is the same
+ * rule), and number the classes c as the lambda_c of the linearised collision
+ * term Eq. (D2Q9MOmega), whose coefficients this rule reproduces:
+ *   1 {0,5}<->{1,2},  2 rest <-> axis pair,  3 rest <-> diagonal pair,
+ *   4 axis <-> diagonal pair,  5 axis <-> axis pair,  6 diagonal <-> diagonal,
+ *   7 {0,1}<->{2,8}, {0,1}<->{4,5},  8 {2,8}<->{4,5},  9 {1,1}<->{5,8},
+ * and rotations by 90 degrees.  A sub-collision draws the ordered pair of
+ * distinct particles as in D1Q3, then one uniform integer u in [0, D), D =
+ * 128 lcm(lambda denominators) < 2^32: the targets of A in ascending
+ * (min(k,l), max(k,l)) take consecutive ranges of D P(A -> B) values of u.
+ * Every site runs this literal loop (the (N, Jx, Jy) fibers are too many to
+ * tabulate).  Streaming: n_i(x + vx, y + vy, t + 1) <- n_i(x, y, t),
+ * periodic; site s = y Lx + x keys the RNG as x does in D1Q3, and the Poisson
+ * start of site s uses Philox blocks (s, j, replica, 1), j = 0..2, word w of
+ * block j for velocity 4j + w, at f^eq of Eq. (D2Q9eqdist) evaluated as
+ * (rho Fx[vx]) Fy[vy] with F the unit-density D1Q3 equilibrium.
+ * D2Q9 contexts support mclg_sizes, mclg_init, mclg_step, mclg_get_counts
+ * (host_out [9][Ly][Lx]), mclg_moments9, mclg_check and mclg_destroy; the
+ * other entry points return MCLG_E_UNSUPPORTED. */
+typedef struct {
+  int64_t t, sites;
+  int64_t sum_n[9];
+  int64_t sum_nn[45];  /* sum n_i n_j for i <= j, row-major upper triangle */
+  int64_t sum_N, sum_Jx, sum_Jy, max_N;
+} mclg_moments9_t;
+
+/* Exact moments of every replica of a D2Q9 context; synchronises. */
+int mclg_moments9(mclg_ctx *ctx, mclg_moments9_t *host_out);
+
+/* Host-only inspection of the D2Q9 rule table for lambda9 (18 values): per
+ * ordered source pair (v1, v2), 9 uint32 at host_out[(v1 * 9 + v2) * 9]:
+ * {number of targets, then per target (k | l << 8, cumulative weight)},
+ * and the denominator D. */
+int mclg_d2q9_rules(const uint32_t *lambda9, uint32_t *host_out, uint32_t *D);
 
 /* Bytes of device state and workspace needed by a configuration (state,
  * workspace and stream fields are ignored).  The state holds, per replica,

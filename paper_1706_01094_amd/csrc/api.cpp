@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/mclg.h"
+#include "d2q9.h"
 #include "device.h"
 #include "tables.h"
 
@@ -77,7 +78,6 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
 
 int validate(const mclg_config *cfg) {
   if (!cfg || cfg->abi_version != MCLG_ABI_VERSION) return MCLG_E_INVAL;
-  if (cfg->lattice == MCLG_D2Q9) return MCLG_E_UNSUPPORTED;
   if (cfg->lattice != MCLG_D1Q3) return MCLG_E_INVAL;
   if (cfg->n_replicas == 0 || !cfg->L) return MCLG_E_INVAL;
   if (cfg->flags & ~(uint32_t)(MCLG_FLAG_NO_STREAM | MCLG_FLAG_GALILEAN)) return MCLG_E_INVAL;
@@ -94,6 +94,7 @@ int validate(const mclg_config *cfg) {
 }  // namespace
 
 struct mclg_ctx {
+  std::unique_ptr<D2Ctx> d2;  // set for a D2Q9 context; then nothing below is used
   uint32_t n = 0, flags = 0;
   uint64_t seed = 0;
   int32_t C = 0;
@@ -275,6 +276,15 @@ struct mclg_ctx {
 extern "C" {
 
 int mclg_sizes(const mclg_config *cfg, uint64_t *state_bytes, uint64_t *workspace_bytes) {
+  if (cfg && cfg->abi_version == MCLG_ABI_VERSION && cfg->lattice == MCLG_D2Q9) {
+    if (cfg->n_replicas == 0 || !cfg->L) return MCLG_E_INVAL;
+    D2Ctx d;
+    int rc = d2q9_layout(cfg, d);
+    if (rc) return rc;
+    if (state_bytes) *state_bytes = d.state_bytes;
+    if (workspace_bytes) *workspace_bytes = d.ws_bytes;
+    return MCLG_OK;
+  }
   int rc = validate(cfg);
   if (rc) return rc;
   auto tab = collision_tables(cfg->C, cfg->lambda_num, cfg->lambda_den, cfg->n_max,
@@ -289,6 +299,18 @@ int mclg_sizes(const mclg_config *cfg, uint64_t *state_bytes, uint64_t *workspac
 
 int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out) {
   if (!out || !init) return MCLG_E_INVAL;
+  if (cfg && cfg->abi_version == MCLG_ABI_VERSION && cfg->lattice == MCLG_D2Q9) {
+    if (cfg->n_replicas == 0 || !cfg->L || !cfg->state || !cfg->workspace) return MCLG_E_INVAL;
+    std::unique_ptr<mclg_ctx> c(new (std::nothrow) mclg_ctx());
+    if (!c) return MCLG_E_NOMEM;
+    c->d2.reset(new (std::nothrow) D2Ctx());
+    if (!c->d2) return MCLG_E_NOMEM;
+    int rc = d2q9_layout(cfg, *c->d2);
+    if (!rc) rc = d2q9_init(*c->d2, cfg, init);
+    if (rc) return rc;
+    *out = c.release();
+    return MCLG_OK;
+  }
   int rc = validate(cfg);
   if (rc) return rc;
   if (!cfg->state || !cfg->workspace) return MCLG_E_INVAL;
@@ -433,6 +455,7 @@ static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t 
 
 int mclg_step(mclg_ctx *c, uint64_t n_steps) {
   if (!c) return MCLG_E_INVAL;
+  if (c->d2) return d2q9_step(*c->d2, n_steps);
   for (uint64_t i = 0; i < n_steps; ++i) {
     if (c->t_pending >= (1u << 30)) {
       hipError_t e = c->flush_t();
@@ -447,6 +470,7 @@ int mclg_step(mclg_ctx *c, uint64_t n_steps) {
 }
 
 int mclg_step_replica(mclg_ctx *c, uint32_t r, uint64_t n_steps) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || r >= c->n) return MCLG_E_INVAL;
   hipError_t e = c->flush_t();
   if (e) return c->hip(e);
@@ -465,6 +489,7 @@ int mclg_step_replica(mclg_ctx *c, uint32_t r, uint64_t n_steps) {
 }
 
 int mclg_step_graph(mclg_ctx *c, uint64_t n_steps) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || !c->stream || n_steps == 0) return MCLG_E_INVAL;
   if (n_steps >= (1u << 30)) return MCLG_E_INVAL;
   hipError_t fe = c->flush_t();  // the graph's steps count from tslot itself
@@ -503,10 +528,18 @@ static int read_err(mclg_ctx *c) {
 
 int mclg_check(mclg_ctx *c) {
   if (!c) return MCLG_E_INVAL;
+  if (c->d2) return d2q9_check(*c->d2);
   return read_err(c);
 }
 
+int mclg_moments9(mclg_ctx *c, mclg_moments9_t *out) {
+  if (!c || !out) return MCLG_E_INVAL;
+  if (!c->d2) return MCLG_E_UNSUPPORTED;
+  return d2q9_moments(*c->d2, out);
+}
+
 int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_moments_t *out) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || !out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle)) return MCLG_E_INVAL;
   hipStream_t s = c->stream;
   hipError_t e = c->flush_t();
@@ -546,6 +579,7 @@ int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_mom
 }
 
 int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || !hist || n_bins == 0 || n_bins > MCLG_MAX_HIST_BINS) return MCLG_E_INVAL;
   const hipError_t e =
       launch_histogram(c->stream, c->state, c->slots(), c->tiles_dev(), (uint32_t)c->tiles.size(),
@@ -554,6 +588,7 @@ int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {
 }
 
 int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
+  if (c && c->d2) return d2q9_get_counts(*c->d2, r, out);
   if (!c || !out || r >= c->n) return MCLG_E_INVAL;
   const uint64_t L = c->L[r], stride = c->lay.stride[r];
   std::vector<uint16_t> raw(3 * stride);
@@ -571,6 +606,7 @@ int mclg_get_counts(mclg_ctx *c, uint32_t r, uint16_t *out) {
 }
 
 int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t lds_budget) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c) return MCLG_E_INVAL;
   if (groups != 1) return MCLG_E_INVAL;
   if (threads < 64 || threads > 1024 || threads % 64) return MCLG_E_INVAL;
@@ -588,6 +624,7 @@ int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t l
 }
 
 int mclg_set_grid_limit(mclg_ctx *c, uint32_t max_blocks) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c) return MCLG_E_INVAL;
   hipError_t e = hipStreamSynchronize(c->stream);
   c->grid_limit = max_blocks;
@@ -596,6 +633,7 @@ int mclg_set_grid_limit(mclg_ctx *c, uint32_t max_blocks) {
 }
 
 int mclg_lds_coverage(const mclg_ctx *c, double *expected_fraction, uint32_t *lds_bytes) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || !expected_fraction || !lds_bytes) return MCLG_E_INVAL;
   *expected_fraction = c->coverage;
   *lds_bytes = c->lds_bytes;
@@ -604,6 +642,11 @@ int mclg_lds_coverage(const mclg_ctx *c, double *expected_fraction, uint32_t *ld
 
 int mclg_destroy(mclg_ctx *c) {
   if (!c) return MCLG_E_INVAL;
+  if (c->d2) {
+    if (c->d2->stream) (void)hipStreamSynchronize(c->d2->stream);
+    delete c;
+    return MCLG_OK;
+  }
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   c->drop_graphs();
   delete c;
@@ -624,7 +667,9 @@ const char *mclg_strerror(int code) {
   }
 }
 
-int mclg_last_hip_error(const mclg_ctx *c) { return c ? c->last_hip : 0; }
+int mclg_last_hip_error(const mclg_ctx *c) {
+  return c ? (c->d2 ? c->d2->last_hip : c->last_hip) : 0;
+}
 
 int mclg_table_row(int32_t C, uint32_t p, uint32_t q, uint32_t flags, uint32_t N, uint32_t absJ,
                    uint32_t n0, uint64_t *thr, uint32_t cap, uint32_t *m_out) {
@@ -643,6 +688,14 @@ int mclg_galilean_lambda(uint32_t num, uint32_t den, uint32_t N, uint32_t absJ,
   if (!lambda_q || den == 0 || num == 0 || num > den || den >= (1u << 28) || absJ > N)
     return MCLG_E_INVAL;
   *lambda_q = galilean_lambda_q(num, den, N, absJ);
+  return MCLG_OK;
+}
+
+int mclg_d2q9_rules(const uint32_t *lambda9, uint32_t *out, uint32_t *D) {
+  if (!lambda9 || !out || !D) return MCLG_E_INVAL;
+  std::vector<uint32_t> rules;
+  if (!build_rules9(lambda9, rules, *D)) return MCLG_E_INVAL;
+  std::copy(rules.begin(), rules.end(), out);
   return MCLG_OK;
 }
 

@@ -159,4 +159,44 @@ hipError_t launch_add_t(hipStream_t s, uint32_t *tslot, uint32_t slot_first, uin
 hipError_t launch_set_t(hipStream_t s, uint32_t *tslot, const uint32_t *slot_list, uint32_t n,
                         uint32_t value);
 
+// ---- D2Q9 --------------------------------------------------------------
+// One replica: nine uint16 arrays of `stride` elements from `off`; logical
+// n_i(x, y, t) lives at physical ((x - vx t) mod Lx, (y - vy t) mod Ly),
+// element y Lx + x, so streaming is free as for D1Q3.
+struct Rep9 {
+  uint64_t off;
+  uint32_t Lx, Ly, S, stride;
+  uint32_t rid, pad;
+};
+struct Tile9 {
+  uint32_t rep, s0;  // replica, first site (multiple of 256)
+};
+// Collision rules, per ordered source pair (v1, v2), kRule9Words uint32:
+// {number of targets, then per target (k | l << 8, cumulative weight)}; a
+// uniform u in [0, D) selects the first target whose cumulative weight
+// exceeds u.
+constexpr uint32_t kRule9Words = 9;
+constexpr uint32_t kMom9Vals = 9 + 45 + 4;  // sum n_i, sum n_i n_j (i <= j), N, Jx, Jy, max N
+struct Step9 {
+  uint16_t *state;
+  const Rep9 *reps;
+  const Tile9 *tiles;
+  const uint32_t *rules;
+  uint32_t *err;
+  uint64_t seed;
+  uint64_t t;          // steps taken (the RNG counter uses its low 32 bits)
+  uint32_t D, no_stream;
+  int32_t C;
+};
+hipError_t launch_step9(hipStream_t s, const Step9 &a, uint32_t n_tiles);
+hipError_t launch_init9_poisson(hipStream_t s, uint16_t *state, const Rep9 *reps,
+                                const Tile9 *tiles, uint32_t n_tiles, const PoisDesc *desc,
+                                const uint32_t *pool, uint64_t seed, uint32_t *err);
+hipError_t launch_init9_counts(hipStream_t s, uint16_t *state, const Rep9 *reps,
+                               const Tile9 *tiles, uint32_t n_tiles, const uint64_t *dense,
+                               const uint16_t *counts);
+hipError_t launch_moments9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
+                           const Tile9 *tiles, uint32_t n_tiles, uint64_t t, uint32_t no_stream,
+                           unsigned long long *out);
+
 }  // namespace mclg

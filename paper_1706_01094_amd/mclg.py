@@ -35,11 +35,22 @@ class mclg_config(ct.Structure):
     _fields_ = [("abi_version", u32), ("lattice", u32), ("n_replicas", u32), ("flags", u32),
                 ("L", P(u64)), ("replica_id", P(u64)), ("seed", u64), ("C", i32),
                 ("lambda_num", u32), ("lambda_den", u32), ("n_max", u32), ("stream", vp),
-                ("state", vp), ("state_bytes", u64), ("workspace", vp), ("workspace_bytes", u64)]
+                ("state", vp), ("state_bytes", u64), ("workspace", vp), ("workspace_bytes", u64),
+                ("Ly", P(u64)), ("lambda9", P(u32))]
 
 
 class mclg_init_spec(ct.Structure):
-    _fields_ = [("kind", u32), ("counts", vp), ("rho", P(dbl)), ("u0", P(dbl))]
+    _fields_ = [("kind", u32), ("counts", vp), ("rho", P(dbl)), ("u0", P(dbl)), ("u0y", P(dbl))]
+
+
+class mclg_moments9_t(ct.Structure):
+    _fields_ = [("t", i64), ("sites", i64), ("sum_n", i64 * 9), ("sum_nn", i64 * 45),
+                ("sum_N", i64), ("sum_Jx", i64), ("sum_Jy", i64), ("max_N", i64)]
+
+    def as_dict(self) -> dict:
+        return {"t": self.t, "sites": self.sites, "sum_n": list(self.sum_n),
+                "sum_nn": list(self.sum_nn), "sum_N": self.sum_N, "sum_Jx": self.sum_Jx,
+                "sum_Jy": self.sum_Jy, "max_N": self.max_N}
 
 
 class mclg_moments_t(ct.Structure):
@@ -84,6 +95,8 @@ _SIGS = {
     "mclg_step_graph": [vp, u64],
     "mclg_moments": [vp, vp, u32, P(mclg_moments_t)],
     "mclg_histogram": [vp, u32, vp],
+    "mclg_moments9": [vp, P(mclg_moments9_t)],
+    "mclg_d2q9_rules": [P(u32), P(u32), P(u32)],
     "mclg_get_counts": [vp, u32, P(ct.c_uint16)],
     "mclg_check": [vp],
     "mclg_set_schedule": [vp, u32, u32, u32],
@@ -143,6 +156,16 @@ def mclg_table_row(C: int, lam: Sequence[int], N: int, absJ: int, n0: int,
     _check(lib().mclg_table_row(C, lam[0], lam[1], flags, N, absJ, n0,
                                 thr.ctypes.data_as(P(u64)), len(thr), ct.byref(mo)), "mclg_table_row")
     return thr[: mo.value - 1]
+
+
+def mclg_d2q9_rules(lams):
+    """(rules [81, 9] uint32, D) of the D2Q9 rule table (host only)."""
+    lam = np.ascontiguousarray(np.asarray(lams, dtype=np.uint32).reshape(18))
+    out = np.zeros(81 * 9, dtype=np.uint32)
+    D = u32(0)
+    _check(lib().mclg_d2q9_rules(lam.ctypes.data_as(P(u32)), out.ctypes.data_as(P(u32)),
+                                 ct.byref(D)), "mclg_d2q9_rules")
+    return out.reshape(81, 9), D.value
 
 
 def mclg_galilean_lambda(lam: Sequence[int], N: int, absJ: int) -> int:
@@ -351,6 +374,103 @@ class Lattice:
         if rc != OK and not (allow_range and rc == E_RANGE):
             raise MclgError(rc, "mclg_get_counts")
         return out
+
+
+# lambda_1..9 of the paper's D2Q9 equilibrium run: 15/128, 1/4 (x6), 1/8, 18/144
+LAMBDA9_PAPER = [(15, 128)] + [(1, 4)] * 6 + [(1, 8), (18, 144)]
+
+
+class Lattice9:
+    """n_replicas periodic D2Q9 lattices (Lx[r] x Ly[r]) resident on the GPU."""
+
+    def __init__(self, Lx, Ly, seed: int, C: int = 10, lams=LAMBDA9_PAPER, replica_id=None,
+                 flags: int = 0, rho=None, ux=None, uy=None, counts=None, stream=None,
+                 device: str = "cuda:0"):
+        torch = _require_gpu()
+        self.torch = torch
+        self.Lx = np.ascontiguousarray(np.atleast_1d(np.asarray(Lx, dtype=np.uint64)))
+        self.n = len(self.Lx)
+        self.Ly = np.ascontiguousarray(np.broadcast_to(np.asarray(Ly, dtype=np.uint64),
+                                                       (self.n,)).copy())
+        self._lam = np.ascontiguousarray(np.asarray(lams, dtype=np.uint32).reshape(18))
+        self._rid = None if replica_id is None else np.ascontiguousarray(
+            np.asarray(replica_id, dtype=np.uint64))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        cfg = mclg_config()
+        cfg.abi_version = ABI_VERSION
+        cfg.lattice = D2Q9
+        cfg.n_replicas = self.n
+        cfg.flags = flags
+        cfg.L = self.Lx.ctypes.data_as(P(u64))
+        cfg.Ly = self.Ly.ctypes.data_as(P(u64))
+        cfg.lambda9 = self._lam.ctypes.data_as(P(u32))
+        cfg.replica_id = None if self._rid is None else self._rid.ctypes.data_as(P(u64))
+        cfg.seed = seed
+        cfg.C = C
+        cfg.lambda_num, cfg.lambda_den = 1, 1
+        cfg.stream = _stream_ptr(self.stream)
+        sb, wb = mclg_sizes(cfg)
+        self.state = torch.empty(sb // 2 + 64, dtype=torch.int16, device=self.device)
+        self.workspace = torch.empty(wb // 8 + 32, dtype=torch.int64, device=self.device)
+        cfg.state = self.state.data_ptr()
+        cfg.state_bytes = sb
+        cfg.workspace = self.workspace.data_ptr()
+        cfg.workspace_bytes = wb
+        spec = mclg_init_spec()
+        keep = []
+        sites = int((self.Lx * self.Ly).sum())
+        if counts is not None:
+            ct_ = counts if isinstance(counts, torch.Tensor) else torch.as_tensor(
+                np.ascontiguousarray(counts).reshape(-1).view(np.int16))
+            ct_ = ct_.to(self.device).contiguous()
+            if ct_.numel() != 9 * sites or ct_.element_size() != 2:
+                raise ValueError("counts must hold 9 * sum(Lx * Ly) uint16 values")
+            keep.append(ct_)
+            spec.kind = INIT_COUNTS
+            spec.counts = ct_.data_ptr()
+        else:
+            vals = [np.ascontiguousarray(np.broadcast_to(np.asarray(0.0 if v is None else v,
+                                                                    dtype=np.float64), (self.n,)))
+                    for v in (rho, ux, uy)]
+            keep += vals
+            spec.kind = INIT_POISSON
+            spec.rho, spec.u0, spec.u0y = (v.ctypes.data_as(P(dbl)) for v in vals)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self.ctx = mclg_init(cfg, spec)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mclg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        mclg_step(self.ctx, n)
+
+    def check(self) -> int:
+        return mclg_check(self.ctx)
+
+    def counts(self, replica: int = 0, allow_range=False) -> np.ndarray:
+        """[9, Ly, Lx] uint16 in logical order."""
+        Lx, Ly = int(self.Lx[replica]), int(self.Ly[replica])
+        out = np.zeros((9, Ly, Lx), dtype=np.uint16)
+        rc = lib().mclg_get_counts(self.ctx, replica, out.ctypes.data_as(P(ct.c_uint16)))
+        if rc != OK and not (allow_range and rc == E_RANGE):
+            raise MclgError(rc, "mclg_get_counts")
+        return out
+
+    def moments(self, allow_range=False):
+        out = (mclg_moments9_t * self.n)()
+        rc = lib().mclg_moments9(self.ctx, out)
+        if rc != OK and not (allow_range and rc == E_RANGE):
+            raise MclgError(rc, "mclg_moments9")
+        return [o.as_dict() for o in out]
 
 
 class Server:

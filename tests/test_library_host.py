@@ -68,6 +68,25 @@ def test_galilean_rows_and_lambda_equal_oracle(C, lam):
         M.mclg_table_row(C, lam, 4, 0, 0, flags=M.FLAG_NO_STREAM)
 
 
+@pytest.mark.parametrize("lams", [O.LAMBDA9_PAPER, [(1, 8)] * 9, [(3, 7), (0, 1), (1, 5), (2, 9), (1, 3), (0, 1), (1, 6), (1, 11), (1, 13)]])
+def test_d2q9_rules_equal_oracle(lams):
+    """The library's D2Q9 rule table (targets in order, cumulative integer
+    weights, denominator D) equals the oracle's, built independently."""
+    rules, D = M.mclg_d2q9_rules(lams)
+    for i in range(9):
+        for j in range(9):
+            tg, D2 = O.targets9(lams, i, j)
+            assert D == D2
+            e = rules[i * 9 + j]
+            assert e[0] == len(tg)
+            cum = 0
+            for q, (k, l, _, w) in enumerate(tg):
+                cum += w
+                assert e[1 + 2 * q] == k | (l << 8) and e[2 + 2 * q] == cum, (i, j, q)
+    with pytest.raises(M.MclgError):
+        M.mclg_d2q9_rules([(1, 1)] * 9)  # targets of one source would exceed probability one
+
+
 @pytest.mark.parametrize("mu", [0.0, 1e-3, 0.5, 1.6666666666666667, 6.081485941486, 32.83702811702, 88.0, 612.5])
 def test_poisson_thresholds_equal_oracle(mu):
     k1, t1 = M.mclg_poisson_thresholds(mu)
@@ -106,7 +125,17 @@ def test_sizes_and_validation():
     assert sb2 == 3 * (384 + 128) * 2
     lib = M.lib()
     s, w = ct.c_uint64(), ct.c_uint64()
-    assert lib.mclg_sizes(ct.byref(_cfg([256], lattice=M.D2Q9)), ct.byref(s), ct.byref(w)) == M.E_UNSUPPORTED
+    # D2Q9 needs Ly and lambda9; nine arrays of Lx Ly (padded to 128) per replica
+    assert lib.mclg_sizes(ct.byref(_cfg([256], lattice=M.D2Q9)), ct.byref(s), ct.byref(w)) == M.E_INVAL
+    c9 = _cfg([100, 7], lattice=M.D2Q9)
+    Ly = np.array([10, 3], dtype=np.uint64)
+    lam9 = np.asarray(M.LAMBDA9_PAPER, dtype=np.uint32).reshape(18)
+    c9.Ly = Ly.ctypes.data_as(ct.POINTER(ct.c_uint64))
+    c9.lambda9 = lam9.ctypes.data_as(ct.POINTER(ct.c_uint32))
+    assert lib.mclg_sizes(ct.byref(c9), ct.byref(s), ct.byref(w)) == M.OK
+    assert s.value == 9 * (1024 + 128) * 2
+    Ly[1] = 1 << 26  # 7 x 2^26 sites > 2^28
+    assert lib.mclg_sizes(ct.byref(c9), ct.byref(s), ct.byref(w)) == M.E_INVAL
     # largest lattice: 2^29 sites (32-bit byte offsets into a slot's three arrays)
     sb3, _ = M.mclg_sizes(_cfg([1 << 29]))
     assert sb3 == 3 * (1 << 29) * 2

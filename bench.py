@@ -300,6 +300,30 @@ def run_wave(args, torch, M):
             "amplitude_first": amp[0], "amplitude_last": amp[-1]}
 
 
+def run_d2q9(args, torch, M):
+    """D2Q9 (the paper's second lattice): 4096 x 4096 sites, Poisson start at
+    rho = 36, u = 0, C = 10, the lambda_c of the paper's D2Q9 equilibrium run;
+    every site runs the literal sub-collision loop (ALU-bound)."""
+    Lx = Ly = 4096
+    lat = M.Lattice9(Lx, Ly, 9, C=10, rho=36.0, ux=0.0, uy=0.0)
+    lat.step(args.d2q9_warmup)
+    e0, e1 = _events(torch, lat.stream)
+    e0.record(lat.stream)
+    lat.step(args.d2q9_steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rc = lat.check()
+    m = lat.moments()[0]
+    lat.close()
+    sites = Lx * Ly
+    return {"workload": "d2q9_4096x4096_rho36_u0", "C": 10, "lambda9": "15/128, 1/4 x6, 1/8, 18/144",
+            "steps": args.d2q9_steps, "ms_per_step": ms / args.d2q9_steps,
+            "site_updates_per_s": sites * args.d2q9_steps / (ms / 1e3),
+            "hbm_GBps": 36.0 * sites * args.d2q9_steps / (ms / 1e3) / 1e9,
+            "check": rc, "mass_per_site": m["sum_N"] / sites}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +341,9 @@ def main():
     ap.add_argument("--stat-logs", type=int, default=10)
     ap.add_argument("--serve-window", type=float, default=2.0)
     ap.add_argument("--serve-limit", type=float, default=60.0)
+    ap.add_argument("--d2q9-steps", type=int, default=50)
+    ap.add_argument("--d2q9-warmup", type=int, default=5)
+    ap.add_argument("--d2q9-only", action="store_true", help="only the D2Q9 measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 8 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -339,6 +366,9 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
 
+    if args.d2q9_only:
+        print(json.dumps({"d2q9": run_d2q9(args, torch, M)}), flush=True)
+        return
     L, gpu_ms, wall = run_plain(args, torch, M)
     ms_per_step = gpu_ms / args.steps
     value = L * args.steps / (gpu_ms / 1e3)
@@ -372,6 +402,8 @@ def main():
         extra["density_wave"] = run_wave(args, torch, M)
         torch.cuda.empty_cache()
         extra["served"] = run_served(args, torch, M, extra["batched"]["batched"]["site_updates_per_s"])
+        torch.cuda.empty_cache()
+        extra["d2q9"] = run_d2q9(args, torch, M)
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

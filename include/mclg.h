@@ -155,8 +155,12 @@ typedef struct {
  * distinct particles as in D1Q3, then one uniform integer u in [0, D), D =
  * 128 lcm(lambda denominators) < 2^32: the targets of A in ascending
  * (min(k,l), max(k,l)) take consecutive ranges of D P(A -> B) values of u.
- * Every site runs this literal loop (the (N, Jx, Jy) fibers are too many to
- * tabulate).  Streaming: n_i(x + vx, y + vy, t + 1) <- n_i(x, y, t),
+ * Sub-collision k of site s at step t reads Philox block (s, t, replica,
+ * 2 | k << 2): Lemire draws of the first particle (word 0, of N), the second
+ * (word 1, of N - 1) and u (word 2), the last one always; a rejected draw
+ * continues on the words of blocks (s, t, replica, 2 | (C + j) << 2), j = 0,
+ * 1, ... .  Every site runs this literal loop (the (N, Jx, Jy) fibers are too
+ * many to tabulate).  Streaming: n_i(x + vx, y + vy, t + 1) <- n_i(x, y, t),
  * periodic; site s = y Lx + x keys the RNG as x does in D1Q3, and the Poisson
  * start of site s uses Philox blocks (s, j, replica, 1), j = 0..2, word w of
  * block j for velocity 4j + w, at f^eq of Eq. (D2Q9eqdist) evaluated as
@@ -175,8 +179,11 @@ typedef struct {
 int mclg_moments9(mclg_ctx *ctx, mclg_moments9_t *host_out);
 
 /* Host-only inspection of the D2Q9 rule table for lambda9 (18 values): per
- * ordered source pair (v1, v2), 9 uint32 at host_out[(v1 * 9 + v2) * 9]:
- * {number of targets, then per target (k | l << 8, cumulative weight)},
+ * ordered source pair (v1, v2), 12 uint32 at host_out[(v1 * 9 + v2) * 12]:
+ * the cumulative integer weights of its (up to four) targets in order, D for
+ * absent ones; then for q = 0..4 the change of the nine counts when the
+ * target draw u in [0, D) has q cumulative weights <= u (q = number of
+ * targets: no change), 3 bits per velocity i at bit 3i holding 2 + change;
  * and the denominator D. */
 int mclg_d2q9_rules(const uint32_t *lambda9, uint32_t *host_out, uint32_t *D);
 

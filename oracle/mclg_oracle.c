@@ -842,7 +842,7 @@ int mco_histogram(int32_t C, uint32_t p, uint32_t q, uint32_t flags, int direct,
 /* One uniform integer u in [0, D), D = lcm(lambda denominators) * 2^7,      */
 /* picks the target: targets of A in ascending (min(k,l), max(k,l)), u below */
 /* the running sum of their integer weights D P(A -> B) selects one, else    */
-/* nothing changes.                                                          */
+/* nothing changes.  Random words: R9 (collide9).                            */
 /* ======================================================================== */
 static const int V9[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
                              {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
@@ -938,14 +938,39 @@ int mco9_targets(const uint32_t lam[18], uint32_t i, uint32_t j, uint32_t *n, ui
   return MCO_OK;
 }
 
-/* The literal loop of C sub-collisions at one D2Q9 site (R1, R8). */
-static void collide9(int32_t C, const rules9 *R, word_stream *ws, uint64_t n[9]) {
+/* Lemire's draw of a uniform integer in [0, s) whose first word is given;
+ * rejected draws continue with words of the stream `more`. */
+static uint32_t uniform_from(uint32_t first, uint32_t s, word_stream *more) {
+  uint64_t m = (uint64_t)first * (uint64_t)s;
+  uint32_t l = (uint32_t)m;
+  if (l < s) {
+    uint32_t thresh = (uint32_t)(-s) % s;
+    while (l < thresh) {
+      m = (uint64_t)ws_next(more) * (uint64_t)s;
+      l = (uint32_t)m;
+    }
+  }
+  return (uint32_t)(m >> 32);
+}
+
+/* The literal loop of C sub-collisions at one D2Q9 site (R1, R8).  R9:
+ * sub-collision k takes Philox block (s, t, replica, DIRECT | k << 2): word
+ * 0 draws the first particle (of N), word 1 the second (of N - 1), word 2
+ * the target (of D), always; a rejected draw continues with the words of
+ * the blocks (s, t, replica, DIRECT | (C + j) << 2), j = 0, 1, ..., shared by
+ * the site's step. */
+static void collide9(int32_t C, const rules9 *R, uint64_t seed, uint32_t s, uint32_t t,
+                     uint32_t replica, uint64_t n[9]) {
   uint64_t N = 0;
   for (int i = 0; i < 9; ++i) N += n[i];
   if (N < 2) return;
+  word_stream more = {seed, s, t, replica, (uint32_t)C, 4, {0, 0, 0, 0}};
   for (int32_t sub = 0; sub < C; ++sub) {
-    uint32_t r1 = ws_uniform(ws, (uint32_t)N);
-    uint32_t r2 = ws_uniform(ws, (uint32_t)(N - 1));
+    uint32_t w[4];
+    rng_block(seed, s, t, replica, PURPOSE_DIRECT, (uint32_t)sub, w);
+    uint32_t r1 = uniform_from(w[0], (uint32_t)N, &more);
+    uint32_t r2 = uniform_from(w[1], (uint32_t)(N - 1), &more);
+    uint32_t u = uniform_from(w[2], (uint32_t)R->D, &more);
     if (r2 >= r1) r2 += 1;
     /* Eq. (select): velocity by cumulative sums in the order 0..8 */
     int v1 = 0, v2 = 0;
@@ -954,8 +979,6 @@ static void collide9(int32_t C, const rules9 *R, word_stream *ws, uint64_t n[9])
     cum = 0;
     for (int i = 0; i < 9; ++i) { cum += n[i]; if (r2 >= cum) v2 = i + 1; }
     const targets9 *T = &R->tg[v1][v2];
-    if (!T->n) continue;
-    uint32_t u = ws_uniform(ws, (uint32_t)R->D);
     uint64_t run = 0;
     for (uint32_t q = 0; q < T->n; ++q) {
       run += T->wgt[q];
@@ -975,8 +998,7 @@ int mco9_collide_site(int32_t C, const uint32_t lam[18], uint64_t seed, uint64_t
   if (rc) return rc;
   uint64_t n[9];
   for (int i = 0; i < 9; ++i) n[i] = n9[i];
-  word_stream ws = {seed, (uint32_t)s, (uint32_t)t, (uint32_t)replica, 0, 4, {0, 0, 0, 0}};
-  collide9(C, &R, &ws, n);
+  collide9(C, &R, seed, (uint32_t)s, (uint32_t)t, (uint32_t)replica, n);
   for (int i = 0; i < 9; ++i) n9[i] = (uint32_t)n[i];
   return MCO_OK;
 }
@@ -1102,9 +1124,7 @@ int mco9_step(mco_sim9 *s, uint64_t nsteps) {
           if (N > 65535u) {
             status = MCO_E_RANGE; /* not collided (R15) */
           } else {
-            word_stream ws = {s->seed, (uint32_t)site, (uint32_t)s->t[r], (uint32_t)s->rid[r],
-                              0, 4, {0, 0, 0, 0}};
-            collide9(s->C, &s->R, &ws, n);
+            collide9(s->C, &s->R, s->seed, (uint32_t)site, (uint32_t)s->t[r], (uint32_t)s->rid[r], n);
           }
           for (int i = 0; i < 9; ++i) {
             uint64_t xd = x, yd = y;

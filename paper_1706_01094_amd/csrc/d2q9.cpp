@@ -54,13 +54,16 @@ bool build_rules9(const uint32_t *lam, std::vector<uint32_t> &rules, uint32_t &D
   }
   const uint64_t D64 = L * 128;
   D = (uint32_t)D64;
+  constexpr uint32_t kNoChange = 0x2492492u;  // 2 in each of the nine 3-bit fields
   rules.assign(81 * kRule9Words, 0u);
   for (int i = 0; i < 9; ++i)
     for (int j = 0; j < 9; ++j) {
       uint32_t *e = &rules[(i * 9 + j) * kRule9Words];
+      for (int q = 0; q < 4; ++q) e[q] = (uint32_t)D64;
+      for (int q = 0; q < 5; ++q) e[4 + q] = kNoChange;
       const uint64_t mA = i == j ? 1 : 2;
       uint64_t cum = 0;
-      uint32_t nt = 0;
+      int nt = 0;
       for (int k = 0; k < 9; ++k)
         for (int l = k; l < 9; ++l) {
           if (kVx[k] + kVx[l] != kVx[i] + kVx[j] || kVy[k] + kVy[l] != kVy[i] + kVy[j]) continue;
@@ -73,12 +76,18 @@ bool build_rules9(const uint32_t *lam, std::vector<uint32_t> &rules, uint32_t &D
           const uint64_t w = to >= from ? base : base * to / from;
           if (nt >= 4) return false;
           cum += w;
-          e[1 + 2 * nt] = (uint32_t)k | ((uint32_t)l << 8);
-          e[2 + 2 * nt] = (uint32_t)cum;
+          e[nt] = (uint32_t)cum;
+          int delta[9] = {2, 2, 2, 2, 2, 2, 2, 2, 2};
+          delta[i] -= 1;
+          delta[j] -= 1;
+          delta[k] += 1;
+          delta[l] += 1;
+          uint32_t packed = 0;
+          for (int v = 0; v < 9; ++v) packed |= (uint32_t)delta[v] << (3 * v);
+          e[4 + nt] = packed;
           ++nt;
         }
       if (cum > D64) return false;
-      e[0] = nt;
     }
   return true;
 }

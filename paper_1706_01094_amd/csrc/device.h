@@ -172,10 +172,11 @@ struct Tile9 {
   uint32_t rep, s0;  // replica, first site (multiple of 256)
 };
 // Collision rules, per ordered source pair (v1, v2), kRule9Words uint32:
-// {number of targets, then per target (k | l << 8, cumulative weight)}; a
-// uniform u in [0, D) selects the first target whose cumulative weight
-// exceeds u.
-constexpr uint32_t kRule9Words = 9;
+// words 0-3 the cumulative integer weights of the (up to four) targets, D
+// where there is none; words 4-8 the change of the nine counts for target
+// q = #{cumulative weights <= u} (word 4 + q; q = number of targets means no
+// change), 3 bits per velocity i at bit 3i holding 2 + the change; 9-11 pad.
+constexpr uint32_t kRule9Words = 12;
 constexpr uint32_t kMom9Vals = 9 + 45 + 4;  // sum n_i, sum n_i n_j (i <= j), N, Jx, Jy, max N
 struct Step9 {
   uint16_t *state;

@@ -92,6 +92,15 @@ struct WordStream {
     }
     return word_of(buf, used++);
   }
+  // the same with its first word given; rejections continue on this stream
+  __device__ uint32_t uniform_from(uint32_t first, uint32_t s) {
+    uint64_t m = (uint64_t)first * s;
+    if ((uint32_t)m < s) {
+      const uint32_t floor_ = (0u - s) % s;
+      while ((uint32_t)m < floor_) m = (uint64_t)next() * s;
+    }
+    return (uint32_t)(m >> 32);
+  }
   // exact uniform integer in [0, s): multiply-and-reject (Lemire, 2019)
   __device__ uint32_t uniform(uint32_t s) {
     uint64_t m = (uint64_t)next() * s;
@@ -1024,7 +1033,7 @@ struct Site9 {
 // (Eq. (select), Eq. (omega) with the D2Q9 rules), in place in the shifted
 // layout.  Sites with N < 2 (or C = 0) are left untouched.
 __global__ void __launch_bounds__(256) k_step9(Step9 a) {
-  __shared__ uint32_t rules[81 * kRule9Words];
+  __shared__ __align__(16) uint32_t rules[81 * kRule9Words];
   for (uint32_t i = threadIdx.x; i < 81 * kRule9Words; i += blockDim.x) rules[i] = a.rules[i];
   __syncthreads();
   const Tile9 tile = a.tiles[blockIdx.x];
@@ -1047,12 +1056,19 @@ __global__ void __launch_bounds__(256) k_step9(Step9 a) {
     return;
   }
   if (N < 2u || a.C <= 0) return;
-  WordStream ws;
-  ws.key = make_uint2((uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-  ws.x = s; ws.t = (uint32_t)a.t; ws.rid = rp.rid; ws.block = 0; ws.used = 4;
+  // Sub-collision k reads Philox block (s, t, replica, 2 | k << 2): words 0,
+  // 1, 2 draw the first particle, the second and the target; a rejected
+  // draw continues on the blocks (s, t, replica, 2 | (C + j) << 2).
+  const uint2 key = make_uint2((uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  WordStream more;
+  more.key = key;
+  more.x = s; more.t = (uint32_t)a.t; more.rid = rp.rid;
+  more.block = (uint32_t)a.C; more.used = 4;
   for (int32_t sub = 0; sub < a.C; ++sub) {
-    const uint32_t r1 = ws.uniform(N);
-    uint32_t r2 = ws.uniform(N - 1);
+    const uint4 w = philox10(make_uint4(s, (uint32_t)a.t, rp.rid, 2u | ((uint32_t)sub << 2)), key);
+    const uint32_t r1 = more.uniform_from(w.x, N);
+    uint32_t r2 = more.uniform_from(w.y, N - 1);
+    const uint32_t u = more.uniform_from(w.z, a.D);
     r2 += (r2 >= r1);
     uint32_t cum = 0, v1 = 0, v2 = 0;
 #pragma unroll
@@ -1061,21 +1077,12 @@ __global__ void __launch_bounds__(256) k_step9(Step9 a) {
       v1 += (r1 >= cum);
       v2 += (r2 >= cum);
     }
-    const uint32_t *e = &rules[(v1 * 9u + v2) * kRule9Words];
-    const uint32_t nt = e[0];
-    if (!nt) continue;
-    const uint32_t u = ws.uniform(a.D);
-    uint32_t kl = 0xFFFFFFFFu;
-    for (uint32_t q = 0; q < nt; ++q)
-      if (u < e[2 + 2 * q]) {
-        kl = e[1 + 2 * q];
-        break;
-      }
-    if (kl == 0xFFFFFFFFu) continue;
-    const uint32_t k = kl & 0xFFu, l = kl >> 8;
+    const uint32_t rec = (v1 * 9u + v2) * kRule9Words;
+    const uint4 c = *reinterpret_cast<const uint4 *>(&rules[rec]);
+    const uint32_t q = (u >= c.x) + (u >= c.y) + (u >= c.z) + (u >= c.w);
+    const uint32_t delta = rules[rec + 4u + q];
 #pragma unroll
-    for (uint32_t i = 0; i < 9; ++i)
-      n[i] = n[i] + (i == k) + (i == l) - (i == v1) - (i == v2);
+    for (uint32_t i = 0; i < 9; ++i) n[i] = n[i] + __builtin_amdgcn_ubfe(delta, 3u * i, 3u) - 2u;
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) base[(uint64_t)i * rp.stride + ph.e[i]] = (uint16_t)n[i];

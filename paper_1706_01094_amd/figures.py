@@ -19,8 +19,12 @@ paper's closed forms, evaluated here in double precision.
 
 * ``galilean`` (command line) -- the relaxation rate of pi~ against u with
   the constant and the Galilean-invariant acceptance.
+* ``d2q9_statistics`` -- D2Q9: the equilibrium means against u_x at
+  u_y = 0.25 (Eq. (D2Q9eqdist) against Eq. (LBequil)) and the correlator of
+  Eq. (corr) / Table 1 with E(u) of Eq. (error).
 
-Run ``python -m paper_1706_01094_amd.figures fig1|fig3|fig5|corr|galilean [--quick]``.
+Run ``python -m paper_1706_01094_amd.figures fig1|fig3|fig5|corr|galilean|d2q9eq|table1
+[--quick]``.
 """
 from __future__ import annotations
 
@@ -288,6 +292,79 @@ def correlations(us: Sequence[float], rho: float = 36.0, L: int = 4096, C: int =
             "wall_s": wall}
 
 
+# ---- D2Q9 -------------------------------------------------------------------
+V9 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+
+def feq9(rho: float, ux: float, uy: float) -> np.ndarray:
+    """Eq. (D2Q9eqdist): rho times the product of the unit-density D1Q3
+    equilibria of the two velocity components."""
+    fx, fy = feq(1.0, ux), feq(1.0, uy)
+    return np.array([rho * fx[vx + 1] * fy[vy + 1] for vx, vy in V9])
+
+
+def d2q9_statistics(us: Sequence[Sequence[float]], rho: float, Lx: int, Ly: int, C: int = 10,
+                    equil: int = 20000, steps: int = 10000, every: int = 10, seed: int = 1,
+                    blocks: int = 10, lams=None) -> dict:
+    """One D2Q9 lattice per velocity (ux, uy), all in one context, each
+    started from the product-Poisson state at Eq. (D2Q9eqdist); time averages
+    every ``every`` steps over ``steps`` steps after ``equil`` of the site
+    means <n_i> and of <n_i n_j>.  Returns the means, the normalised
+    correlator K_ij = (<n_i n_j> - f_i f_j) / sqrt(f_i f_j) of Eq. (corr) at
+    f = f^eq(rho^, u^) from each lattice's conserved sums, E(u) of
+    Eq. (error), and batch-means standard errors."""
+    us = np.asarray(us, dtype=np.float64).reshape(-1, 2)
+    R = len(us)
+    kw = {} if lams is None else {"lams": lams}
+    lat = mclg.Lattice9([Lx] * R, Ly, seed, C=C, rho=np.full(R, rho), ux=us[:, 0], uy=us[:, 1], **kw)
+    S = Lx * Ly
+    iu = np.triu_indices(9)
+    try:
+        t0 = time.time()
+        lat.step(equil)
+        n_samp = steps // every
+        mean_s = np.zeros((n_samp, R, 9))
+        nn_s = np.zeros((n_samp, R, 9, 9))
+        for k in range(n_samp):
+            lat.step(every)
+            for r, m in enumerate(lat.moments()):
+                mean_s[k, r] = np.asarray(m["sum_n"], dtype=np.float64) / S
+                up = np.zeros((9, 9))
+                up[iu] = np.asarray(m["sum_nn"], dtype=np.float64) / S
+                nn_s[k, r] = up + np.triu(up, 1).T
+        wall = time.time() - t0
+        mom = lat.moments()
+        rc = lat.check()
+    finally:
+        lat.close()
+    Vx = np.array([v[0] for v in V9])
+    Vy = np.array([v[1] for v in V9])
+    rho_hat = np.array([m["sum_N"] / S for m in mom])
+    u_hat = np.array([[m["sum_Jx"] / m["sum_N"], m["sum_Jy"] / m["sum_N"]] for m in mom])
+    f = np.array([feq9(a, *b) for a, b in zip(rho_hat, u_hat)])
+    ff = np.sqrt(f[:, :, None] * f[:, None, :])
+    norm = lambda nn: (nn - f[:, :, None] * f[:, None, :]) / ff  # noqa: E731
+    nb = max(2, min(blocks, n_samp))
+    mean = mean_s.mean(0)
+    se = np.array([b.mean(0) for b in np.array_split(mean_s, nb)]).std(0, ddof=1) / math.sqrt(nb)
+    K = norm(nn_s.mean(0))
+    bK = np.array([norm(b.mean(0)) for b in np.array_split(nn_s, nb)])
+    Kse = bK.std(0, ddof=1) / math.sqrt(nb)
+    E = ((K - np.eye(9)) ** 2).sum((1, 2))
+    assert np.allclose(Vx @ f.T, rho_hat * u_hat[:, 0]) and np.allclose(Vy @ f.T, rho_hat * u_hat[:, 1])
+    return {"u0": us, "rho_hat": rho_hat, "u_hat": u_hat, "mean": mean, "se": se, "feq": f,
+            "f_lb": np.array([f_lb9(a, *b) for a, b in zip(rho_hat, u_hat)]),
+            "K": K, "K_se": Kse, "E": E, "Lx": Lx, "Ly": Ly, "C": C, "equil": equil,
+            "steps": steps, "every": every, "check": rc, "wall_s": wall}
+
+
+def f_lb9(rho: float, ux: float, uy: float) -> np.ndarray:
+    """Eq. (LBequil) for D2Q9 (weights 4/9, 1/9, 1/36, theta = 1/3)."""
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    vu = np.array([vx * ux + vy * uy for vx, vy in V9])
+    return rho * w * (1 + 3 * vu + 4.5 * vu ** 2 - 1.5 * (ux * ux + uy * uy))
+
+
 # ---- command line -----------------------------------------------------------
 def _fig1(quick: bool):
     kw = dict(equil=2000, steps=8000, replicas=8) if quick else {}
@@ -387,13 +464,43 @@ def _galilean(quick: bool):
               f"{w['rate_galilean']:.6f}       {w['pred_galilean']:.6f}")
 
 
+def _d2q9eq(quick: bool):
+    uxs = np.round(np.linspace(-0.6, 0.6, 13), 6)
+    kw = dict(equil=2000, steps=1000) if quick else {}
+    r = d2q9_statistics([(u, 0.25) for u in uxs], 36.0, 100, 10, **kw)
+    print(f"D2Q9 equilibrium (Fig. of Eq. (D2Q9eqdist)): rho=36, uy=0.25, 100x10, C={r['C']}, "
+          f"{r['equil']} + {r['steps']} steps, every {r['every']} ({r['wall_s']:.1f} s)")
+    print("   ux^     " + "  ".join(f"<n{i}>/f{i}".rjust(11) for i in range(9)))
+    for k in range(len(uxs)):
+        cells = "  ".join(f"{r['mean'][k, i]:5.2f}/{r['feq'][k, i]:5.2f}" for i in range(9))
+        print(f"  {r['u_hat'][k, 0]:+.3f}  {cells}")
+
+
+def _table1(quick: bool):
+    uxs = [0.0, 0.1, 0.25, 0.4]
+    kw = dict(equil=1500, steps=5000) if quick else dict(equil=150000, steps=500000)
+    r = d2q9_statistics([(u, 0.0) for u in uxs], 360.0, 100, 10, every=10, **kw)
+    print(f"D2Q9 correlators (Eq. (corr), Table 1 set-up): rho=360, uy=0, 100x10, C={r['C']}, "
+          f"{r['equil']} + {r['steps']} steps ({r['wall_s']:.1f} s)")
+    for k in range(len(uxs)):
+        K = r["K"][k]
+        off = K - np.diag(np.diag(K))
+        print(f"  ux^ = {r['u_hat'][k, 0]:+.4f}: diagonal {np.diag(K).min():.6f} .. "
+              f"{np.diag(K).max():.6f}, largest |off-diagonal| {np.abs(off).max():.2e}, "
+              f"E(u) = {r['E'][k]:.3e}")
+    print("  K at the first velocity:")
+    for row in r["K"][0]:
+        print("   " + " ".join(f"{v:+.5f}" for v in row))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr", "galilean"])
+    ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr", "galilean", "d2q9eq",
+                                       "table1"])
     ap.add_argument("--quick", action="store_true", help="reduced step counts")
     a = ap.parse_args(argv)
     {"fig1": _fig1, "fig3": _fig3, "fig5": _fig5, "corr": _corr,
-     "galilean": _galilean}[a.figure](a.quick)
+     "galilean": _galilean, "d2q9eq": _d2q9eq, "table1": _table1}[a.figure](a.quick)
 
 
 if __name__ == "__main__":

@@ -159,13 +159,13 @@ def mclg_table_row(C: int, lam: Sequence[int], N: int, absJ: int, n0: int,
 
 
 def mclg_d2q9_rules(lams):
-    """(rules [81, 9] uint32, D) of the D2Q9 rule table (host only)."""
+    """(rules [81, 12] uint32, D) of the D2Q9 rule table (host only)."""
     lam = np.ascontiguousarray(np.asarray(lams, dtype=np.uint32).reshape(18))
-    out = np.zeros(81 * 9, dtype=np.uint32)
+    out = np.zeros(81 * 12, dtype=np.uint32)
     D = u32(0)
     _check(lib().mclg_d2q9_rules(lam.ctypes.data_as(P(u32)), out.ctypes.data_as(P(u32)),
                                  ct.byref(D)), "mclg_d2q9_rules")
-    return out.reshape(81, 9), D.value
+    return out.reshape(81, 12), D.value
 
 
 def mclg_galilean_lambda(lam: Sequence[int], N: int, absJ: int) -> int:

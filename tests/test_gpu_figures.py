@@ -205,3 +205,23 @@ def test_galilean_no_stream_equals_exact_chain(init):
         m1, m2 = X.no_stream_pi_moments(init, 10, t, lam)
         se = math.sqrt(max(m2 - m1 * m1, 0.0) / (1000 * 200))
         assert abs(r["mean"][t] - m1) < 4 * se + 1e-9, (t, r["mean"][t], m1, se)
+
+
+def test_d2q9_means_and_correlator():
+    """D2Q9: product-Poisson starts at Eq. (D2Q9eqdist) are exactly
+    stationary (the rules keep detailed balance with respect to the product
+    weights), so at u = (0, 0), (0.3, 0.25), (-0.5, 0.25) on 128 x 64 sites,
+    rho = 36, 300 + 1500 steps, the time-averaged means equal Eq. (D2Q9eqdist)
+    at the conserved (rho^, u^) within 5 standard errors, the normalised
+    correlators of Eq. (corr) equal delta_ij within 5 standard errors, and at
+    u_x = -0.5 the means are far from Eq. (LBequil)."""
+    us = [(0.0, 0.0), (0.3, 0.25), (-0.5, 0.25)]
+    say("d2q9 statistics case", us)
+    r = F.d2q9_statistics(us, 36.0, 128, 64, equil=300, steps=1500, every=10, blocks=10)
+    assert r["check"] == 0
+    dev = np.abs(r["mean"] - r["feq"])
+    assert np.all(dev < 5 * r["se"] + 1e-9), (dev / r["se"]).max()
+    kdev = np.abs(r["K"] - np.eye(9))
+    assert np.all(kdev < 5 * r["K_se"] + 1e-9), (kdev / r["K_se"]).max()
+    assert np.abs(r["mean"][2] - r["f_lb"][2]).max() > 50 * r["se"][2].max()
+    assert np.allclose(F.feq9(36.0, 0.0, 0.0), 36.0 * np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4))

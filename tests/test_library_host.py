@@ -73,16 +73,29 @@ def test_d2q9_rules_equal_oracle(lams):
     """The library's D2Q9 rule table (targets in order, cumulative integer
     weights, denominator D) equals the oracle's, built independently."""
     rules, D = M.mclg_d2q9_rules(lams)
+
+    def change(word):
+        return [((int(word) >> (3 * v)) & 7) - 2 for v in range(9)]
+
     for i in range(9):
         for j in range(9):
             tg, D2 = O.targets9(lams, i, j)
             assert D == D2
             e = rules[i * 9 + j]
-            assert e[0] == len(tg)
             cum = 0
-            for q, (k, l, _, w) in enumerate(tg):
-                cum += w
-                assert e[1 + 2 * q] == k | (l << 8) and e[2 + 2 * q] == cum, (i, j, q)
+            for q in range(4):
+                if q < len(tg):
+                    k, l, _, w = tg[q]
+                    cum += w
+                    want = [0] * 9
+                    want[i] -= 1
+                    want[j] -= 1
+                    want[k] += 1
+                    want[l] += 1
+                    assert e[q] == cum and change(e[4 + q]) == want, (i, j, q)
+                else:
+                    assert e[q] == D
+            assert change(e[4 + len(tg)]) == [0] * 9
     with pytest.raises(M.MclgError):
         M.mclg_d2q9_rules([(1, 1)] * 9)  # targets of one source would exceed probability one
 

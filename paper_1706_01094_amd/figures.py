@@ -485,9 +485,11 @@ def _table1(quick: bool):
     for k in range(len(uxs)):
         K = r["K"][k]
         off = K - np.diag(np.diag(K))
+        z = np.abs(K - np.eye(9)) / r["K_se"][k]
         print(f"  ux^ = {r['u_hat'][k, 0]:+.4f}: diagonal {np.diag(K).min():.6f} .. "
               f"{np.diag(K).max():.6f}, largest |off-diagonal| {np.abs(off).max():.2e}, "
-              f"E(u) = {r['E'][k]:.3e}")
+              f"E(u) = {r['E'][k]:.3e}; standard errors {r['K_se'][k].min():.1e} .. "
+              f"{r['K_se'][k].max():.1e}, largest |K - delta| / se {z.max():.1f}")
     print("  K at the first velocity:")
     for row in r["K"][0]:
         print("   " + " ".join(f"{v:+.5f}" for v in row))

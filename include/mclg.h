@@ -166,8 +166,8 @@ typedef struct {
  * block j for velocity 4j + w, at f^eq of Eq. (D2Q9eqdist) evaluated as
  * (rho Fx[vx]) Fy[vy] with F the unit-density D1Q3 equilibrium.
  * D2Q9 contexts support mclg_sizes, mclg_init, mclg_step, mclg_get_counts
- * (host_out [9][Ly][Lx]), mclg_moments9, mclg_check and mclg_destroy; the
- * other entry points return MCLG_E_UNSUPPORTED. */
+ * (host_out [9][Ly][Lx]), mclg_moments9, mclg_histogram, mclg_check and
+ * mclg_destroy; the other entry points return MCLG_E_UNSUPPORTED. */
 typedef struct {
   int64_t t, sites;
   int64_t sum_n[9];
@@ -219,16 +219,17 @@ int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
 int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
 
 /* Occupation-number histograms, the distributions P(n_i) compared with the
- * Poisson law of Eq. (poisson) and, in the rest-parity sector, with Fig. 1
- * of the D1Q3 section.  Adds, for every replica r, velocity i (0, 1, 2 for
- * v = -1, 0, +1) and site x, one to
- *   dev_hist[(r * 3 + i) * n_bins + min(n_i(x), n_bins - 1)],
+ * Poisson law of Eq. (poisson) (Fig. of the Poisson section for D2Q9) and,
+ * in the rest-parity sector, with Fig. 1 of the D1Q3 section.  Adds, for
+ * every replica r, velocity i (D1Q3: 0, 1, 2 for v = -1, 0, +1; D2Q9: the
+ * nine velocities, V = 9) and site x, one to
+ *   dev_hist[(r * V + i) * n_bins + min(n_i(x), n_bins - 1)],   V = 3 or 9,
  * so the last bin counts every n_i >= n_bins - 1.  dev_hist is device memory
- * of n_replicas * 3 * n_bins uint64 owned by the caller, who clears it; calls
+ * of n_replicas * V * n_bins uint64 owned by the caller, who clears it; calls
  * accumulate, so repeated calls sum histograms over time.  Asynchronous on the
  * context's stream (read dev_hist after synchronising with it).  n_bins in
- * 1..MCLG_MAX_HIST_BINS, else MCLG_E_INVAL; overflow of a site is reported by
- * mclg_check, not here. */
+ * 1..MCLG_MAX_HIST_BINS (D2Q9: 1..1024), else MCLG_E_INVAL; overflow of a
+ * site is reported by mclg_check, not here. */
 int mclg_histogram(mclg_ctx *ctx, uint32_t n_bins, uint64_t *dev_hist);
 
 /* Sticky error state of the device (MCLG_E_RANGE if any site overflowed);

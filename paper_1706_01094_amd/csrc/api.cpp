@@ -579,8 +579,8 @@ int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_mom
 }
 
 int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {
-  if (c && c->d2) return MCLG_E_UNSUPPORTED;
   if (!c || !hist || n_bins == 0 || n_bins > MCLG_MAX_HIST_BINS) return MCLG_E_INVAL;
+  if (c->d2) return n_bins > 1024 ? MCLG_E_INVAL : d2q9_histogram(*c->d2, n_bins, hist);
   const hipError_t e =
       launch_histogram(c->stream, c->state, c->slots(), c->tiles_dev(), (uint32_t)c->tiles.size(),
                        c->sch.tile_sites(), n_bins, reinterpret_cast<unsigned long long *>(hist));

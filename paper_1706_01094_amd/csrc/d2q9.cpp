@@ -235,6 +235,15 @@ int d2q9_step(D2Ctx &d, uint64_t n_steps) {
   return MCLG_OK;
 }
 
+int d2q9_histogram(D2Ctx &d, uint32_t n_bins, uint64_t *hist) {
+  // 9 * n_bins uint32 of LDS per block: at most 36 KB
+  const hipError_t e = launch_histogram9(
+      d.stream, d.state, reinterpret_cast<const Rep9 *>(d.ws + d.o_reps),
+      reinterpret_cast<const Tile9 *>(d.ws + d.o_tiles), (uint32_t)d.tiles.size(), n_bins,
+      reinterpret_cast<unsigned long long *>(hist));
+  return hip_rc(d, e);
+}
+
 int d2q9_check(D2Ctx &d) {
   uint32_t err = 0;
   hipError_t e = hipMemcpyAsync(&err, d.ws + d.o_err, sizeof(err), hipMemcpyDeviceToHost, d.stream);

@@ -41,5 +41,6 @@ int d2q9_step(D2Ctx &d, uint64_t n_steps);
 int d2q9_get_counts(D2Ctx &d, uint32_t r, uint16_t *out);
 int d2q9_moments(D2Ctx &d, mclg_moments9_t *out);
 int d2q9_check(D2Ctx &d);
+int d2q9_histogram(D2Ctx &d, uint32_t n_bins, uint64_t *dev_hist);
 
 }  // namespace mclg

@@ -196,6 +196,9 @@ hipError_t launch_init9_poisson(hipStream_t s, uint16_t *state, const Rep9 *reps
 hipError_t launch_init9_counts(hipStream_t s, uint16_t *state, const Rep9 *reps,
                                const Tile9 *tiles, uint32_t n_tiles, const uint64_t *dense,
                                const uint16_t *counts);
+hipError_t launch_histogram9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
+                             const Tile9 *tiles, uint32_t n_tiles, uint32_t n_bins,
+                             unsigned long long *hist);
 hipError_t launch_moments9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
                            const Tile9 *tiles, uint32_t n_tiles, uint64_t t, uint32_t no_stream,
                            unsigned long long *out);

@@ -1132,6 +1132,53 @@ __global__ void __launch_bounds__(256) k_init9_counts(uint16_t *__restrict__ sta
     state[rp.off + (uint64_t)i * rp.stride + s] = src[(uint64_t)i * rp.S + s];
 }
 
+// Occupation-number histograms of D2Q9 replicas, as k_histogram: each block
+// takes a run of tiles, bins the nine arrays of their sites in LDS and adds
+// the non-empty bins to its replica's row whenever the run changes replica.
+__global__ void __launch_bounds__(256) k_histogram9(const uint16_t *__restrict__ state,
+                                                    const Rep9 *__restrict__ reps,
+                                                    const Tile9 *__restrict__ tiles,
+                                                    uint32_t n_tiles, uint32_t n_bins,
+                                                    unsigned long long *__restrict__ hist) {
+  extern __shared__ uint32_t bins[];  // [9][n_bins]
+  const uint32_t per = (n_tiles + gridDim.x - 1u) / gridDim.x;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  if (t_begin >= t_end) return;
+  const uint32_t nb9 = 9u * n_bins, top = n_bins - 1u;
+  for (uint32_t j = threadIdx.x; j < nb9; j += blockDim.x) bins[j] = 0u;
+  uint32_t cur = tiles[t_begin].rep;
+  auto flush = [&](uint32_t rep) {
+    __syncthreads();
+    unsigned long long *row = hist + (uint64_t)rep * nb9;
+    for (uint32_t j = threadIdx.x; j < nb9; j += blockDim.x) {
+      const uint32_t v = bins[j];
+      if (v) {
+        atomicAdd(&row[j], (unsigned long long)v);
+        bins[j] = 0u;
+      }
+    }
+    __syncthreads();
+  };
+  __syncthreads();
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    const Tile9 tile = tiles[t];
+    if (tile.rep != cur) {
+      flush(cur);
+      cur = tile.rep;
+    }
+    const Rep9 rp = reps[tile.rep];
+    const uint32_t s = tile.s0 + threadIdx.x;
+    if (s < rp.S) {
+#pragma unroll
+      for (uint32_t i = 0; i < 9u; ++i) {
+        const uint32_t n = state[rp.off + (uint64_t)i * rp.stride + s];
+        atomicAdd(&bins[i * n_bins + min(n, top)], 1u);
+      }
+    }
+  }
+  flush(cur);
+}
+
 // Exact sums of one tile in logical site order, reduced over the wave with
 // shuffles, over the block in LDS, then one atomic per value.
 __global__ void __launch_bounds__(256) k_moments9(const uint16_t *__restrict__ state,
@@ -1321,6 +1368,16 @@ hipError_t launch_init9_counts(hipStream_t s, uint16_t *state, const Rep9 *reps,
                                const uint16_t *counts) {
   if (n_tiles == 0) return hipSuccess;
   k_init9_counts<<<n_tiles, 256, 0, s>>>(state, reps, tiles, dense, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_histogram9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
+                             const Tile9 *tiles, uint32_t n_tiles, uint32_t n_bins,
+                             unsigned long long *hist) {
+  if (n_tiles == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>(n_tiles, 2048u);
+  k_histogram9<<<blocks, 256, 9u * n_bins * sizeof(uint32_t), s>>>(state, reps, tiles, n_tiles,
+                                                                   n_bins, hist);
   return hipGetLastError();
 }
 

@@ -358,6 +358,27 @@ def d2q9_statistics(us: Sequence[Sequence[float]], rho: float, Lx: int, Ly: int,
             "steps": steps, "every": every, "check": rc, "wall_s": wall}
 
 
+def d2q9_histograms(ux: float = -0.25, uy: float = 0.25, rho: float = 18.0, Lx: int = 512,
+                    Ly: int = 512, C: int = 10, equil: int = 200, n_bins: int = 48,
+                    seed: int = 1) -> dict:
+    """The Poisson-histogram figure of the D2Q9 section: occupation-number
+    distributions of every velocity after ``equil`` steps from the
+    product-Poisson start at (rho, ux, uy) (one snapshot of Lx * Ly
+    independent sites), beside Poisson(f_i^eq) of Eq. (D2Q9eqdist)."""
+    lat = mclg.Lattice9(Lx, Ly, seed, C=C, rho=rho, ux=ux, uy=uy)
+    try:
+        lat.step(equil)
+        h = lat.histogram(n_bins).cpu().numpy()[0]
+        rc = lat.check()
+        m = lat.moments()[0]
+    finally:
+        lat.close()
+    S = Lx * Ly
+    f = feq9(m["sum_N"] / S, m["sum_Jx"] / m["sum_N"], m["sum_Jy"] / m["sum_N"])
+    return {"hist": h, "P": h / S, "pred": np.array([poisson_pmf(fi, n_bins) for fi in f]),
+            "f": f, "check": rc, "sites": S}
+
+
 def f_lb9(rho: float, ux: float, uy: float) -> np.ndarray:
     """Eq. (LBequil) for D2Q9 (weights 4/9, 1/9, 1/36, theta = 1/3)."""
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
@@ -476,6 +497,15 @@ def _d2q9eq(quick: bool):
         print(f"  {r['u_hat'][k, 0]:+.3f}  {cells}")
 
 
+def _d2q9hist(quick: bool):
+    r = d2q9_histograms(Lx=128 if quick else 512, Ly=128 if quick else 512)
+    print(f"D2Q9 occupation numbers at U = (-0.25, 0.25), rho = 18, {r['sites']} sites "
+          f"(one snapshot after 200 steps)")
+    print("   n   " + "   ".join(f"P(n{i}) Poisson".rjust(15) for i in (0, 1, 2, 7)))
+    for n in range(0, 16):
+        print(f"  {n:2d}  " + "   ".join(f"{r['P'][i, n]:.5f} {r['pred'][i, n]:.5f}" for i in (0, 1, 2, 7)))
+
+
 def _table1(quick: bool):
     uxs = [0.0, 0.1, 0.25, 0.4]
     kw = dict(equil=1500, steps=5000) if quick else dict(equil=150000, steps=500000)
@@ -498,11 +528,12 @@ def _table1(quick: bool):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("figure", choices=["fig1", "fig3", "fig5", "corr", "galilean", "d2q9eq",
-                                       "table1"])
+                                       "d2q9hist", "table1"])
     ap.add_argument("--quick", action="store_true", help="reduced step counts")
     a = ap.parse_args(argv)
     {"fig1": _fig1, "fig3": _fig3, "fig5": _fig5, "corr": _corr,
-     "galilean": _galilean, "d2q9eq": _d2q9eq, "table1": _table1}[a.figure](a.quick)
+     "galilean": _galilean, "d2q9eq": _d2q9eq, "d2q9hist": _d2q9hist,
+     "table1": _table1}[a.figure](a.quick)
 
 
 if __name__ == "__main__":

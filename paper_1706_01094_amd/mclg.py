@@ -465,6 +465,21 @@ class Lattice9:
             raise MclgError(rc, "mclg_get_counts")
         return out
 
+    def histogram(self, n_bins: int, out=None):
+        """Add the occupation-number histograms to ``out`` (int64 [n_replicas,
+        9, n_bins] on the device, zeros if None) and return it; the last bin
+        counts every n >= n_bins - 1."""
+        torch = self.torch
+        if out is None:
+            out = torch.zeros((self.n, 9, n_bins), dtype=torch.int64, device=self.device)
+        if out.dtype != torch.int64 or out.numel() != 9 * self.n * n_bins or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of n_replicas * 9 * n_bins")
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        mclg_histogram(self.ctx, n_bins, out.data_ptr())
+        cur.wait_stream(self.stream)
+        return out
+
     def moments(self, allow_range=False):
         out = (mclg_moments9_t * self.n)()
         rc = lib().mclg_moments9(self.ctx, out)

@@ -96,3 +96,23 @@ def test_d2q9_counts_start_and_larger_lattice():
         M.mclg_step_graph(g.ctx, 2)
     assert e.value.code == E_UNSUPPORTED
     g.close()
+
+
+def test_d2q9_histogram_equals_oracle_bincount():
+    """mclg_histogram on D2Q9 replicas (37x5, 64x64, 1x3): after 5 steps every
+    velocity's histogram equals np.bincount of the oracle's counts (last bin
+    clipped); a second call adds the same again."""
+    Lx, Ly = [37, 64, 1], [5, 64, 3]
+    g, o = pair9(Lx, Ly, 4, rho=[18.0, 36.0, 5.0], ux=[-0.25, 0.1, 0.0], uy=[0.25, 0.0, 0.3])
+    g.step(5)
+    o.step(5)
+    for n_bins in (1, 12, 40):
+        h = g.histogram(n_bins).cpu().numpy()
+        for r in range(3):
+            c = o.counts(r).reshape(9, -1)
+            for i in range(9):
+                want = np.bincount(np.minimum(c[i], n_bins - 1), minlength=n_bins)
+                assert np.array_equal(h[r, i], want), (n_bins, r, i)
+        h2 = g.histogram(n_bins, out=g.histogram(n_bins)).cpu().numpy()
+        assert np.array_equal(h2, 2 * h)
+    g.close()

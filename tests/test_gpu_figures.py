@@ -225,3 +225,14 @@ def test_d2q9_means_and_correlator():
     assert np.all(kdev < 5 * r["K_se"] + 1e-9), (kdev / r["K_se"]).max()
     assert np.abs(r["mean"][2] - r["f_lb"][2]).max() > 50 * r["se"][2].max()
     assert np.allclose(F.feq9(36.0, 0.0, 0.0), 36.0 * np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4))
+
+
+def test_d2q9_poisson_histograms():
+    """The D2Q9 Poisson-histogram set-up (U = (-0.25, 0.25), rho = 18), one
+    snapshot of 2^18 sites after 200 steps from the product-Poisson start:
+    every velocity's histogram is Poisson(f_i^eq) (chi-squared, p > 1e-4
+    each, nine velocities)."""
+    r = F.d2q9_histograms(Lx=512, Ly=512)
+    assert r["check"] == 0
+    for i in range(9):
+        assert _pvalue(r["hist"][i], r["pred"][i]) > 1e-4, (i, r["hist"][i][:12], r["pred"][i][:12])

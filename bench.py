@@ -22,12 +22,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_SITE_UPDATE = 12     # 3 x uint16 read + 3 x uint16 written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_L16M.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1706_01094_amd", "csrc", "kernels.hip")
+# the sources the D1Q3 step kernel is compiled from
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
+               for f in ("kernels.hip", "rng.h", "device.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():

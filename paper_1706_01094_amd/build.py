@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclg.so")
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp", "tables.cpp", "d2q9.cpp"]
+SOURCES = ["kernels.hip", "kernels_d2q9.hip", "api.cpp", "server.cpp", "tables.cpp", "d2q9.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops off: no packed FP32 instructions are generated.

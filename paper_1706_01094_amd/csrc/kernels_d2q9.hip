@@ -1,0 +1,280 @@
+// HIP kernels of the D2Q9 path of the MCLG library (Sec. "A D2Q9
+// implementation"): one thread per site runs the literal loop of C
+// sub-collisions with the rule table in LDS, in place in the shifted 2D
+// layout; Poisson start, counts start, exact moments and histograms.  The
+// rules and the layout are stated in mclg.h.
+#include "device.h"
+#include "rng.h"
+
+#include <algorithm>
+
+namespace mclg {
+namespace {
+
+// ---- D2Q9 --------------------------------------------------------------
+__constant__ int32_t kV9x[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int32_t kV9y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Physical element of velocity i of logical site (x, y) at shift (tx, ty):
+// ((x - vx tx) mod Lx, (y - vy ty) mod Ly).
+struct Site9 {
+  uint32_t e[9];
+  __device__ Site9(uint32_t x, uint32_t y, uint32_t tx, uint32_t ty, uint32_t Lx, uint32_t Ly) {
+    const uint32_t xs[3] = {x + tx >= Lx ? x + tx - Lx : x + tx, x, x >= tx ? x - tx : x + Lx - tx};
+    const uint32_t ys[3] = {y + ty >= Ly ? y + ty - Ly : y + ty, y, y >= ty ? y - ty : y + Ly - ty};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) e[i] = ys[kV9y[i] + 1] * Lx + xs[kV9x[i] + 1];
+  }
+};
+
+// One step of every site of one tile: the literal loop of C sub-collisions
+// (Eq. (select), Eq. (omega) with the D2Q9 rules), in place in the shifted
+// layout.  Sites with N < 2 (or C = 0) are left untouched.
+__global__ void __launch_bounds__(256) k_step9(Step9 a) {
+  __shared__ __align__(16) uint32_t rules[81 * kRule9Words];
+  for (uint32_t i = threadIdx.x; i < 81 * kRule9Words; i += blockDim.x) rules[i] = a.rules[i];
+  __syncthreads();
+  const Tile9 tile = a.tiles[blockIdx.x];
+  const Rep9 rp = a.reps[tile.rep];
+  const uint32_t s = tile.s0 + threadIdx.x;
+  if (s >= rp.S) return;
+  const uint32_t y = s / rp.Lx, x = s - y * rp.Lx;
+  const uint32_t tx = a.no_stream ? 0u : (uint32_t)(a.t % rp.Lx);
+  const uint32_t ty = a.no_stream ? 0u : (uint32_t)(a.t % rp.Ly);
+  const Site9 ph(x, y, tx, ty, rp.Lx, rp.Ly);
+  uint16_t *base = a.state + rp.off;
+  uint32_t n[9], N = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    n[i] = base[(uint64_t)i * rp.stride + ph.e[i]];
+    N += n[i];
+  }
+  if (N > 65535u) {
+    atomicOr(a.err, kErrOverflow);
+    return;
+  }
+  if (N < 2u || a.C <= 0) return;
+  // Sub-collision k reads Philox block (s, t, replica, 2 | k << 2): words 0,
+  // 1, 2 draw the first particle, the second and the target; a rejected
+  // draw continues on the blocks (s, t, replica, 2 | (C + j) << 2).
+  const uint2 key = make_uint2((uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+  WordStream more;
+  more.key = key;
+  more.x = s; more.t = (uint32_t)a.t; more.rid = rp.rid;
+  more.block = (uint32_t)a.C; more.used = 4;
+  for (int32_t sub = 0; sub < a.C; ++sub) {
+    const uint4 w = philox10(make_uint4(s, (uint32_t)a.t, rp.rid, 2u | ((uint32_t)sub << 2)), key);
+    const uint32_t r1 = more.uniform_from(w.x, N);
+    uint32_t r2 = more.uniform_from(w.y, N - 1);
+    const uint32_t u = more.uniform_from(w.z, a.D);
+    r2 += (r2 >= r1);
+    uint32_t cum = 0, v1 = 0, v2 = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      cum += n[i];
+      v1 += (r1 >= cum);
+      v2 += (r2 >= cum);
+    }
+    const uint32_t rec = (v1 * 9u + v2) * kRule9Words;
+    const uint4 c = *reinterpret_cast<const uint4 *>(&rules[rec]);
+    const uint32_t q = (u >= c.x) + (u >= c.y) + (u >= c.z) + (u >= c.w);
+    const uint32_t delta = rules[rec + 4u + q];
+#pragma unroll
+    for (uint32_t i = 0; i < 9; ++i) n[i] = n[i] + __builtin_amdgcn_ubfe(delta, 3u * i, 3u) - 2u;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) base[(uint64_t)i * rp.stride + ph.e[i]] = (uint16_t)n[i];
+}
+
+// Poisson start: site s draws Philox blocks (s, j, replica, 1), j = 0, 1, 2;
+// word w of block j serves velocity 4 j + w.  At t = 0 the layout is
+// unshifted.
+__global__ void __launch_bounds__(256) k_init9_poisson(
+    uint16_t *__restrict__ state, const Rep9 *__restrict__ reps, const Tile9 *__restrict__ tiles,
+    const PoisDesc *__restrict__ desc, const uint32_t *__restrict__ pool, uint64_t seed,
+    uint32_t *err) {
+  const Tile9 tile = tiles[blockIdx.x];
+  const Rep9 rp = reps[tile.rep];
+  const uint32_t s = tile.s0 + threadIdx.x;
+  if (s >= rp.S) return;
+  const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+#pragma unroll
+  for (uint32_t j = 0; j < 3; ++j) {
+    const uint4 w = philox10(make_uint4(s, j, rp.rid, 1u), key);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t i = 4 * j + q;
+      if (i >= 9) break;
+      const PoisDesc d = desc[9u * tile.rep + i];
+      const uint32_t n = d.k_first + count_le(pool + d.off, d.nthr, word_of(w, q));
+      if (n > 65535u) atomicOr(err, kErrOverflow);
+      state[rp.off + (uint64_t)i * rp.stride + s] = (uint16_t)n;
+    }
+  }
+}
+
+// Counts given in logical order ([9][Ly][Lx] per replica, replicas packed
+// from dense[rep]); at t = 0 the layout is unshifted.
+__global__ void __launch_bounds__(256) k_init9_counts(uint16_t *__restrict__ state,
+                                                      const Rep9 *__restrict__ reps,
+                                                      const Tile9 *__restrict__ tiles,
+                                                      const uint64_t *__restrict__ dense,
+                                                      const uint16_t *__restrict__ counts) {
+  const Tile9 tile = tiles[blockIdx.x];
+  const Rep9 rp = reps[tile.rep];
+  const uint32_t s = tile.s0 + threadIdx.x;
+  if (s >= rp.S) return;
+  const uint16_t *src = counts + dense[tile.rep];
+#pragma unroll
+  for (uint32_t i = 0; i < 9; ++i)
+    state[rp.off + (uint64_t)i * rp.stride + s] = src[(uint64_t)i * rp.S + s];
+}
+
+// Occupation-number histograms of D2Q9 replicas, as k_histogram: each block
+// takes a run of tiles, bins the nine arrays of their sites in LDS and adds
+// the non-empty bins to its replica's row whenever the run changes replica.
+__global__ void __launch_bounds__(256) k_histogram9(const uint16_t *__restrict__ state,
+                                                    const Rep9 *__restrict__ reps,
+                                                    const Tile9 *__restrict__ tiles,
+                                                    uint32_t n_tiles, uint32_t n_bins,
+                                                    unsigned long long *__restrict__ hist) {
+  extern __shared__ uint32_t bins[];  // [9][n_bins]
+  const uint32_t per = (n_tiles + gridDim.x - 1u) / gridDim.x;
+  const uint32_t t_begin = blockIdx.x * per, t_end = min(n_tiles, t_begin + per);
+  if (t_begin >= t_end) return;
+  const uint32_t nb9 = 9u * n_bins, top = n_bins - 1u;
+  for (uint32_t j = threadIdx.x; j < nb9; j += blockDim.x) bins[j] = 0u;
+  uint32_t cur = tiles[t_begin].rep;
+  auto flush = [&](uint32_t rep) {
+    __syncthreads();
+    unsigned long long *row = hist + (uint64_t)rep * nb9;
+    for (uint32_t j = threadIdx.x; j < nb9; j += blockDim.x) {
+      const uint32_t v = bins[j];
+      if (v) {
+        atomicAdd(&row[j], (unsigned long long)v);
+        bins[j] = 0u;
+      }
+    }
+    __syncthreads();
+  };
+  __syncthreads();
+  for (uint32_t t = t_begin; t < t_end; ++t) {
+    const Tile9 tile = tiles[t];
+    if (tile.rep != cur) {
+      flush(cur);
+      cur = tile.rep;
+    }
+    const Rep9 rp = reps[tile.rep];
+    const uint32_t s = tile.s0 + threadIdx.x;
+    if (s < rp.S) {
+#pragma unroll
+      for (uint32_t i = 0; i < 9u; ++i) {
+        const uint32_t n = state[rp.off + (uint64_t)i * rp.stride + s];
+        atomicAdd(&bins[i * n_bins + min(n, top)], 1u);
+      }
+    }
+  }
+  flush(cur);
+}
+
+// Exact sums of one tile in logical site order, reduced over the wave with
+// shuffles, over the block in LDS, then one atomic per value.
+__global__ void __launch_bounds__(256) k_moments9(const uint16_t *__restrict__ state,
+                                                  const Rep9 *__restrict__ reps,
+                                                  const Tile9 *__restrict__ tiles, uint64_t t,
+                                                  uint32_t no_stream,
+                                                  unsigned long long *__restrict__ out) {
+  __shared__ unsigned long long red[4][kMom9Vals];
+  const Tile9 tile = tiles[blockIdx.x];
+  const Rep9 rp = reps[tile.rep];
+  const uint32_t s = tile.s0 + threadIdx.x;
+  uint32_t n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (s < rp.S) {
+    const uint32_t y = s / rp.Lx, x = s - y * rp.Lx;
+    const uint32_t tx = no_stream ? 0u : (uint32_t)(t % rp.Lx);
+    const uint32_t ty = no_stream ? 0u : (uint32_t)(t % rp.Ly);
+    const Site9 ph(x, y, tx, ty, rp.Lx, rp.Ly);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) n[i] = state[rp.off + (uint64_t)i * rp.stride + ph.e[i]];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t q = 0;
+  auto put = [&](unsigned long long v, bool is_max) {
+    for (int m = 32; m >= 1; m >>= 1) {
+      const unsigned long long o = shfl_xor_u64(v, m);
+      v = is_max ? (v > o ? v : o) : v + o;
+    }
+    if (lane == 0) red[wave][q] = v;
+    ++q;
+  };
+  long long N = 0, jx = 0, jy = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    N += n[i];
+    jx += kV9x[i] * (long long)n[i];
+    jy += kV9y[i] * (long long)n[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) put(n[i], false);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = i; j < 9; ++j) put((unsigned long long)n[i] * n[j], false);
+  put((unsigned long long)N, false);
+  put((unsigned long long)jx, false);
+  put((unsigned long long)jy, false);
+  put((unsigned long long)N, true);
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  for (uint32_t v = threadIdx.x; v < kMom9Vals; v += blockDim.x) {
+    const bool is_max = v == kMom9Vals - 1;
+    unsigned long long acc = 0ull;
+    for (int w = 0; w < nw; ++w) acc = is_max ? (acc > red[w][v] ? acc : red[w][v]) : acc + red[w][v];
+    if (is_max) atomicMax(&out[(uint64_t)tile.rep * kMom9Vals + v], acc);
+    else atomicAdd(&out[(uint64_t)tile.rep * kMom9Vals + v], acc);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step9(hipStream_t s, const Step9 &a, uint32_t n_tiles) {
+  if (n_tiles == 0) return hipSuccess;
+  k_step9<<<n_tiles, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init9_poisson(hipStream_t s, uint16_t *state, const Rep9 *reps,
+                                const Tile9 *tiles, uint32_t n_tiles, const PoisDesc *desc,
+                                const uint32_t *pool, uint64_t seed, uint32_t *err) {
+  if (n_tiles == 0) return hipSuccess;
+  k_init9_poisson<<<n_tiles, 256, 0, s>>>(state, reps, tiles, desc, pool, seed, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_init9_counts(hipStream_t s, uint16_t *state, const Rep9 *reps,
+                               const Tile9 *tiles, uint32_t n_tiles, const uint64_t *dense,
+                               const uint16_t *counts) {
+  if (n_tiles == 0) return hipSuccess;
+  k_init9_counts<<<n_tiles, 256, 0, s>>>(state, reps, tiles, dense, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_histogram9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
+                             const Tile9 *tiles, uint32_t n_tiles, uint32_t n_bins,
+                             unsigned long long *hist) {
+  if (n_tiles == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>(n_tiles, 2048u);
+  k_histogram9<<<blocks, 256, 9u * n_bins * sizeof(uint32_t), s>>>(state, reps, tiles, n_tiles,
+                                                                   n_bins, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
+                           const Tile9 *tiles, uint32_t n_tiles, uint64_t t, uint32_t no_stream,
+                           unsigned long long *out) {
+  if (n_tiles == 0) return hipSuccess;
+  k_moments9<<<n_tiles, 256, 0, s>>>(state, reps, tiles, t, no_stream, out);
+  return hipGetLastError();
+}
+
+}  // namespace mclg

@@ -116,3 +116,31 @@ def test_d2q9_histogram_equals_oracle_bincount():
         h2 = g.histogram(n_bins, out=g.histogram(n_bins)).cpu().numpy()
         assert np.array_equal(h2, 2 * h)
     g.close()
+
+
+def test_d2q9_overflow_is_flagged_and_site_kept():
+    """A D2Q9 site with N > 65535 (8000 per velocity) is not collided, only
+    streamed, and raises the sticky range error on both sides."""
+    rng = np.random.default_rng(8)
+    c = rng.integers(0, 6, size=(9, 6, 10)).astype(np.uint16)
+    c[:, 2, 3] = 8000
+    g, o = pair9(10, 6, 12, counts=c.reshape(-1))
+    g.step(1)
+    assert o.step(1) == -2
+    from paper_1706_01094_amd.mclg import E_RANGE
+    assert g.check() == E_RANGE
+    a = g.counts(0, allow_range=True)
+    assert np.array_equal(a, o.counts(0))
+    g.close()
+
+
+@pytest.mark.parametrize("Lx,Ly", [(1, 7), (7, 1), (2, 2), (1, 1)])
+def test_d2q9_thin_lattices(Lx, Ly):
+    """Degenerate tori (a single row or column, 2 x 2, one site): every count
+    equal after each of 10 steps at rho = 20."""
+    g, o = pair9(Lx, Ly, 13, rho=20.0, ux=0.2, uy=-0.3)
+    for _ in range(10):
+        g.step(1)
+        o.step(1)
+        same9(g, o, 1)
+    g.close()

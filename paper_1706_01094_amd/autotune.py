@@ -22,8 +22,8 @@ from . import mclg as M
 Schedule = Tuple[int, int, int]
 
 DEFAULT_CANDIDATES: Sequence[Schedule] = (
-    (1, 1024, 112 * 1024), (1, 1024, 96 * 1024), (1, 1024, 64 * 1024),
-    (1, 768, 112 * 1024), (1, 512, 64 * 1024), (1, 256, 32 * 1024),
+    (1, 1024, 146176), (1, 1024, 128 * 1024), (1, 1024, 112 * 1024), (1, 1024, 96 * 1024),
+    (1, 1024, 64 * 1024), (1, 768, 112 * 1024), (1, 512, 64 * 1024), (1, 256, 32 * 1024),
 )
 
 CACHE_PATH = os.environ.get(

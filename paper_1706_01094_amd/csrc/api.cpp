@@ -3,7 +3,6 @@
 
 #include <algorithm>
 #include <atomic>
-#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <thread>
@@ -32,7 +31,7 @@ struct Layout {
   std::vector<uint64_t> off, stride, dense;
   uint64_t total_sites = 0, max_tiles = 0;
   // workspace byte offsets
-  uint64_t o_ctrl, o_flags, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, o_fixed, ws_bytes;
 };
 
@@ -59,7 +58,6 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
     return at;
   };
   lay.o_ctrl = take(256);
-  lay.o_flags = take(sizeof(uint32_t) * kMaxStepFlags);
   lay.o_slots = take(sizeof(SlotDev) * n);
   lay.o_tslot = take(sizeof(uint32_t) * n);
   lay.o_tiles = take(sizeof(TileDev) * tiles);
@@ -189,8 +187,6 @@ struct mclg_ctx {
     a.n_slots = n_slots;
     a.ticket = nullptr;  // the host advances tslot (launch_add_t)
     a.t_off = t_off;
-    a.n_steps = 1;
-    a.flags = reinterpret_cast<uint32_t *>(ws + lay.o_flags);
     // one slot whose tiles are exactly the launch's: descriptors by value
     a.single = (n_slots == 1 && tile_lo == tile_begin[slot_first] &&
                 tile_hi == tile_end[slot_first]) ? 1u : 0u;
@@ -390,8 +386,6 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   };
   hipError_t e = hipSuccess;
   if (!e) e = up(lay.o_ctrl, ctrl.data(), 256);
-  std::vector<uint32_t> zflags(kMaxStepFlags, 0u);
-  if (!e) e = up(lay.o_flags, zflags.data(), sizeof(uint32_t) * kMaxStepFlags);
   c->slot_host = slots;
   if (!e) e = up(lay.o_slots, slots.data(), sizeof(SlotDev) * c->n);
   if (!e) e = up(lay.o_tslot, tz.data(), sizeof(uint32_t) * c->n);
@@ -459,43 +453,9 @@ static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t 
   return c->hip(e);
 }
 
-// Steps per multi-step launch: a one-slot context whose lattice gives every
-// block of the grid at least four chunks runs up to this many steps in one
-// launch (see k_step); MCLG_MULTISTEP=0 in the environment turns it off.
-constexpr uint32_t kMultiSteps = 64;
-
-static bool multistep_ok(const mclg_ctx *c) {
-  static const bool off = [] {
-    const char *v = std::getenv("MCLG_MULTISTEP");
-    return v && v[0] == '0';
-  }();
-  if (off || c->n != 1 || c->sch.groups != 1) return false;
-  const uint32_t grid = c->grid_limit ? std::min(c->max_blocks, c->grid_limit) : c->max_blocks;
-  const uint64_t tiles = c->tiles.size();
-  return grid >= 1 && grid <= kMaxStepFlags && tiles >= 4ull * grid;
-}
-
 int mclg_step(mclg_ctx *c, uint64_t n_steps) {
   if (!c) return MCLG_E_INVAL;
   if (c->d2) return d2q9_step(*c->d2, n_steps);
-  if (n_steps >= 2 && multistep_ok(c)) {
-    for (uint64_t done = 0; done < n_steps;) {
-      if (c->t_pending >= (1u << 30)) {
-        hipError_t e = c->flush_t();
-        if (e) return c->hip(e);
-      }
-      const uint32_t k = (uint32_t)std::min<uint64_t>(n_steps - done, kMultiSteps);
-      StepLaunch a = c->launch_args(0, (uint32_t)c->tiles.size(), 0, 1, c->t_pending);
-      a.n_steps = a.single ? k : 1u;
-      const uint32_t ran = a.n_steps;
-      int rc = c->hip(launch_step(c->sch, c->stream, a));
-      if (rc) return rc;
-      c->t_pending += ran;
-      for (auto &t : c->t) t += ran;
-      done += ran;
-    }
-    return MCLG_OK;
-  }
   for (uint64_t i = 0; i < n_steps; ++i) {
     if (c->t_pending >= (1u << 30)) {
       hipError_t e = c->flush_t();

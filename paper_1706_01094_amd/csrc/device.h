@@ -93,10 +93,6 @@ struct StepLaunch {
   // advanced later (launch_add_t), which saves the end-of-launch ticket.
   uint32_t *ticket, *err;
   uint32_t t_off;
-  // Steps in this launch (> 1 only for a single-slot launch; see k_step) and
-  // the per-block progress flags they synchronise on (zeroed at init).
-  uint32_t n_steps = 1;
-  uint32_t *flags = nullptr;
   // A launch over one slot's tiles (0 .. n_tiles - 1 from x = 0) carries the
   // slot's descriptors itself, so that its blocks start without dependent
   // loads: single = 1, slot slot_first, image im1, slot sl1.
@@ -128,7 +124,6 @@ constexpr uint32_t kWaveLdsBytes = kQueue * 16;
 // waves that can be resident on a 256-CU device).
 constexpr uint32_t kOverflowPerWave = 576;
 constexpr uint32_t kOverflowWaves = 256 * 32;
-constexpr uint32_t kMaxStepFlags = 4096;  // blocks of a multi-step launch
 constexpr uint64_t kOverflowBytes = (uint64_t)kOverflowPerWave * kOverflowWaves * 16;
 
 // Persistent grid size: resident blocks per CU for this LDS footprint x CUs.

@@ -208,16 +208,11 @@ __device__ __forceinline__ void bstore4(Rsrc r, uint32_t voff, uint32_t soff,
   const u32x4 q = {v[0], v[1], v[2], v[3]};
   __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, (int)soff, 0);
 }
-// The element-wise accesses (chunks that wrap, edge chunks of multi-step
-// launches, queue drains) are device-coherent (sc1): in a multi-step launch
-// they carry every count that one block writes and another reads, across
-// XCDs whose L2s are not coherent with each other.
-constexpr int kCoherent = 16;  // sc1
 __device__ __forceinline__ uint32_t bload2(Rsrc r, uint32_t voff, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kCoherent);
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
 }
 __device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, uint32_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, (int)soff, kCoherent);
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, (int)soff, 0);
 }
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -583,19 +578,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   const uint32_t per = (a.n_tiles + gridDim.x - 1) / gridDim.x;
   const uint32_t cb = blockIdx.x * per;
   const uint32_t ce = min(a.n_tiles, cb + per);
-  // Multi-step launch (one slot, a.n_steps > 1): the block keeps its chunks
-  // and its image for every step; before step s it waits only for the
-  // blocks holding the neighbouring chunks to finish step s - 1 (a site
-  // reads its two neighbours' counts of the previous step).  Counts that
-  // cross blocks are those of the two chunks at each end of a block's
-  // range: these chunks take the element-wise coherent path.
-  const bool ms = a.single && a.n_steps > 1u && a.flags != nullptr;
-  if (ms && cb >= ce) return;  // no chunks: no part in the steps
-  const uint32_t used = (a.n_tiles + per - 1u) / per;  // blocks with chunks
-  const uint32_t left = blockIdx.x ? blockIdx.x - 1u : used - 1u;
-  const uint32_t right = blockIdx.x + 1u < used ? blockIdx.x + 1u : 0u;
-  auto edge = [&](uint32_t kk) { return ms && (kk < cb + 2u || kk + 2u >= ce); };
-  uint32_t &abort_flag = ctl[2];
   uint32_t cur = 0xFFFFFFFFu;
   SlotView sv;
   sv.lo = sv.hi = 0;
@@ -604,35 +586,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   LdsView lv;
   lv.da2 = lv.dc2 = lv.w2 = lv.blo2 = lv.nb2 = 0;
 
-  const uint32_t n_steps = ms ? a.n_steps : 1u;
-  for (uint32_t step = 0; step < n_steps; ++step) {
-  if (step) {
-    // publish step - 1 of this block, then wait for both neighbours' (bounded:
-    // a wait that does not end flags an internal error and every block exits)
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are complete
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const uint32_t done = a.tslot[a.slot_first] + a.t_off + step;  // step - 1 finished
-      __hip_atomic_store(&a.flags[blockIdx.x], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t spins = 0, bad = 0;
-      if (used > 1u) {
-        while ((int32_t)(__hip_atomic_load(&a.flags[left], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT) - done) < 0 ||
-               (int32_t)(__hip_atomic_load(&a.flags[right], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT) - done) < 0) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > (1u << 22)) {
-            atomicOr(a.err, 4u);
-            bad = 1;
-            break;
-          }
-        }
-      }
-      abort_flag = bad;
-    }
-    __syncthreads();
-    if (abort_flag) return;
-  }
   for (uint32_t i = cb;;) {
     TileDev t0;
     t0.slot = cur;
@@ -661,7 +614,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     cur = t0.slot;
     const ImageDesc im = a.single ? a.im1 : a.images[cur];
     const SlotDev sl = a.single ? a.sl1 : a.slots[cur];
-    const uint32_t tn = a.tslot[cur] + a.t_off + step;
+    const uint32_t tn = a.tslot[cur] + a.t_off;
     if (!first) __syncthreads();  // previous image and chunk counter no longer in use
     // (wave-uniform values kept in scalar registers)
     sv.t = __builtin_amdgcn_readfirstlane(tn);
@@ -675,7 +628,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     uint32_t k = min(i + wave, se);
     if (threadIdx.x == 0) next_chunk = i + nwaves;
     Win cw = locate(t0.x0 + (k - i) * 512u, sv);
-    if (edge(k)) cw.fast = 0u;
     Raw cr;
     if (k < se && cw.fast) issue_raw(cw, sv, lane, cr);
     if (new_image) {
@@ -724,7 +676,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       Win nw = cw;
       if (has_next) {
         nw = locate(t0.x0 + (nk - i) * 512u, sv);
-        if (edge(nk)) nw.fast = 0u;
         if (nw.fast) issue_raw(nw, sv, lane, nxt);
       }
 
@@ -781,7 +732,6 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     }
     i = se;
   }
-  }  // step
   // With a ticket, the last block of the launch advances t of every slot in
   // the launch.  Every block has consumed its loads of t before it takes its
   // ticket (the values shaped its work), so nothing reads the new value

@@ -167,8 +167,6 @@ struct mclg_server {
     a.n_slots = n_active;
     a.ticket = ticket();
     a.t_off = 0;
-    a.n_steps = 1;  // the served batch is a multi-slot launch: one step each
-    a.flags = nullptr;
     a.single = 0;
     a.err = err();
     a.tab = table();

@@ -158,28 +158,6 @@ def test_galilean_acceptance(n_max, rho, u0, lam, flags):
         same(g, o)
 
 
-@pytest.mark.parametrize("L,steps,kw", [
-    ((1 << 20) + 777, 25, {}),
-    ((1 << 19) + 5, 12, dict(n_max=16, rho=20.0)),
-    (1 << 20, 20, dict(flags=FLAG_NO_STREAM)),
-    (1 << 20, 70, dict(rho=40.0, u0=0.2)),
-])
-def test_multistep_launches_full_state(L, steps, kw):
-    """One mclg_step call of many steps on a one-slot lattice of at least four
-    chunks per block runs up to 64 steps per launch, each block waiting only
-    for its neighbours between steps.  Every count equals the oracle's after
-    the call (ragged L; the literal loop and its queue drains at n_max = 16;
-    no streaming; two launches of 64 + 6 steps), and again after 3 more."""
-    g, o = pair(L, 31, **kw)
-    g.step(steps)
-    o.step(steps)
-    same(g, o)
-    g.step(3)
-    o.step(3)
-    same(g, o)
-    assert g.check() == 0
-
-
 def test_moments_with_fourier_modes():
     import torch
     L = 5000

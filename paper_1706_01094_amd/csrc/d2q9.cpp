@@ -92,10 +92,30 @@ bool build_rules9(const uint32_t *lam, std::vector<uint32_t> &rules, uint32_t &D
   return true;
 }
 
+std::vector<uint32_t> device_rules9(const std::vector<uint32_t> &rules) {
+  std::vector<uint32_t> dev(81 * kRule9DevWords, 0u);
+  for (int p = 0; p < 81; ++p) {
+    const uint32_t *e = &rules[p * kRule9Words];
+    uint32_t *o = &dev[p * kRule9DevWords];
+    for (int q = 0; q < 4; ++q) o[q] = e[q];
+    for (int q = 0; q < 5; ++q) {
+      int32_t K = 0;
+      uint16_t dk[8];
+      for (int j = 0; j < 8; ++j) {
+        K += (int32_t)((e[4 + q] >> (3 * j)) & 7u) - 2;
+        dk[j] = (uint16_t)K;
+      }
+      for (int m = 0; m < 4; ++m) o[4 + 4 * q + m] = dk[2 * m] | (uint32_t)dk[2 * m + 1] << 16;
+    }
+  }
+  return dev;
+}
+
 int d2q9_layout(const mclg_config *cfg, D2Ctx &d) {
   if (!cfg->Ly || !cfg->lambda9 || cfg->C < 0 || cfg->C > 4096) return MCLG_E_INVAL;
   if (cfg->flags & ~(uint32_t)MCLG_FLAG_NO_STREAM) return MCLG_E_INVAL;
   if (!build_rules9(cfg->lambda9, d.rules, d.D)) return MCLG_E_INVAL;
+  d.rules_dev = device_rules9(d.rules);
   d.n = cfg->n_replicas;
   d.flags = cfg->flags;
   d.C = cfg->C;
@@ -136,7 +156,7 @@ int d2q9_layout(const mclg_config *cfg, D2Ctx &d) {
   d.o_err = take(256);
   d.o_reps = take(sizeof(Rep9) * d.n);
   d.o_tiles = take(sizeof(Tile9) * d.tiles.size());
-  d.o_rules = take(sizeof(uint32_t) * d.rules.size());
+  d.o_rules = take(sizeof(uint32_t) * d.rules_dev.size());
   d.o_mom = take(sizeof(uint64_t) * kMom9Vals * d.n);
   d.o_pdesc = take(sizeof(PoisDesc) * 9 * d.n);
   d.o_pool = take(sizeof(uint32_t) * kPoisCap9 * 9 * d.n);
@@ -195,7 +215,7 @@ int d2q9_init(D2Ctx &d, const mclg_config *cfg, const mclg_init_spec *init) {
   hipError_t e = put(d.o_err, zero.data(), 256);
   if (!e) e = put(d.o_reps, d.reps.data(), sizeof(Rep9) * d.n);
   if (!e) e = put(d.o_tiles, d.tiles.data(), sizeof(Tile9) * d.tiles.size());
-  if (!e) e = put(d.o_rules, d.rules.data(), sizeof(uint32_t) * d.rules.size());
+  if (!e) e = put(d.o_rules, d.rules_dev.data(), sizeof(uint32_t) * d.rules_dev.size());
   if (!e) e = put(d.o_dense, d.dense.data(), sizeof(uint64_t) * d.n);
   if (!e && !pool.empty()) e = put(d.o_pdesc, pdesc.data(), sizeof(PoisDesc) * pdesc.size());
   if (!e && !pool.empty()) e = put(d.o_pool, pool.data(), sizeof(uint32_t) * pool.size());

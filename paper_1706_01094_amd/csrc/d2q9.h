@@ -19,7 +19,8 @@ struct D2Ctx {
   std::vector<uint64_t> Lx, Ly, rid, dense;
   std::vector<Rep9> reps;
   std::vector<Tile9> tiles;
-  std::vector<uint32_t> rules;  // 81 x kRule9Words
+  std::vector<uint32_t> rules;      // 81 x kRule9Words
+  std::vector<uint32_t> rules_dev;  // 81 x kRule9DevWords
   uint64_t state_bytes = 0, ws_bytes = 0;
   uint64_t o_err = 0, o_reps = 0, o_tiles = 0, o_rules = 0, o_mom = 0, o_pdesc = 0, o_pool = 0,
            o_dense = 0;
@@ -33,6 +34,14 @@ struct D2Ctx {
 // lambda is not in [0, 1], D would reach 2^32, or a source's targets would
 // add up to more than one.
 bool build_rules9(const uint32_t *lambda9, std::vector<uint32_t> &rules, uint32_t &D);
+
+// The rules as the step kernel reads them, per ordered source pair,
+// kRule9DevWords uint32: words 0-3 the cumulative weights (as in the table
+// of mclg.h); then, for q = 0..4, four words holding the change of the
+// partial sums K_j = n_0 + ... + n_j (j = 0..7) as 16-bit two's-complement
+// pairs, K_2m in the low and K_2m+1 in the high half.
+constexpr uint32_t kRule9DevWords = 24;
+std::vector<uint32_t> device_rules9(const std::vector<uint32_t> &rules);
 
 // Validate a D2Q9 configuration and fill the layout (sizes and offsets).
 int d2q9_layout(const mclg_config *cfg, D2Ctx &d);

@@ -3,6 +3,7 @@
 // sub-collisions with the rule table in LDS, in place in the shifted 2D
 // layout; Poisson start, counts start, exact moments and histograms.  The
 // rules and the layout are stated in mclg.h.
+#include "d2q9.h"
 #include "device.h"
 #include "rng.h"
 
@@ -12,6 +13,8 @@ namespace mclg {
 namespace {
 
 // ---- D2Q9 --------------------------------------------------------------
+// Step9::rules holds the rules in the form device_rules9 builds (d2q9.h):
+// kRule9DevWords per ordered source pair.
 __constant__ int32_t kV9x[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int32_t kV9y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
@@ -27,12 +30,34 @@ struct Site9 {
   }
 };
 
+// Packed pairs of 16-bit partial sums (element 0 = low half).
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// #{j < 8 : K_j <= r} for the partial sums K held as four 16-bit pairs and
+// r < 65535: max(0, r + 1 - K_j) is at least 1 exactly when K_j <= r.  `one`
+// holds 1 in both halves; passed in a register it keeps the saturated
+// difference and the minimum as two packed instructions per pair.
+__device__ __forceinline__ uint32_t count_partial_le(const u16x2 (&K)[4], uint32_t r, u16x2 one) {
+  const u16x2 R = as_u16x2((r + 1u) * 0x10001u);
+  u16x2 acc = __builtin_elementwise_min(__builtin_elementwise_sub_sat(R, K[0]), one);
+#pragma unroll
+  for (int m = 1; m < 4; ++m) acc += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R, K[m]), one);
+  return (uint32_t)acc.x + (uint32_t)acc.y;
+}
+
 // One step of every site of one tile: the literal loop of C sub-collisions
 // (Eq. (select), Eq. (omega) with the D2Q9 rules), in place in the shifted
-// layout.  Sites with N < 2 (or C = 0) are left untouched.
+// layout.  Sites with N < 2 (or C = 0) are left untouched.  The loop keeps
+// the partial sums K_j = n_0 + ... + n_j (j < 8) as packed 16-bit pairs: the
+// velocity of particle r is #{j : K_j <= r}, and a collision adds one of the
+// rule table's packed changes.
 __global__ void __launch_bounds__(256) k_step9(Step9 a) {
-  __shared__ __align__(16) uint32_t rules[81 * kRule9Words];
-  for (uint32_t i = threadIdx.x; i < 81 * kRule9Words; i += blockDim.x) rules[i] = a.rules[i];
+  __shared__ __align__(16) uint4 rules[81 * kRule9DevWords / 4];
+  const uint4 *src = reinterpret_cast<const uint4 *>(a.rules);
+  for (uint32_t i = threadIdx.x; i < 81 * kRule9DevWords / 4; i += blockDim.x) rules[i] = src[i];
   __syncthreads();
   const Tile9 tile = a.tiles[blockIdx.x];
   const Rep9 rp = a.reps[tile.rep];
@@ -54,6 +79,17 @@ __global__ void __launch_bounds__(256) k_step9(Step9 a) {
     return;
   }
   if (N < 2u || a.C <= 0) return;
+  u16x2 K[4];
+  {
+    uint32_t k = 0, lo;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      k += n[2 * m];
+      lo = k;
+      k += n[2 * m + 1];
+      K[m] = as_u16x2(lo | k << 16);
+    }
+  }
   // Sub-collision k reads Philox block (s, t, replica, 2 | k << 2): words 0,
   // 1, 2 draw the first particle, the second and the target; a rejected
   // draw continues on the blocks (s, t, replica, 2 | (C + j) << 2).
@@ -62,26 +98,42 @@ __global__ void __launch_bounds__(256) k_step9(Step9 a) {
   more.key = key;
   more.x = s; more.t = (uint32_t)a.t; more.rid = rp.rid;
   more.block = (uint32_t)a.C; more.used = 4;
+  uint32_t one_ = 0x10001u, one32_ = 1u;
+  // opaque constants: no compare-and-select rewrite of the minima below
+  asm volatile("" : "+v"(one_), "+v"(one32_));
+  const u16x2 one = as_u16x2(one_);
   for (int32_t sub = 0; sub < a.C; ++sub) {
     const uint4 w = philox10(make_uint4(s, (uint32_t)a.t, rp.rid, 2u | ((uint32_t)sub << 2)), key);
-    const uint32_t r1 = more.uniform_from(w.x, N);
+    uint32_t r1 = more.uniform_from(w.x, N);
     uint32_t r2 = more.uniform_from(w.y, N - 1);
     const uint32_t u = more.uniform_from(w.z, a.D);
+    asm volatile("" : "+v"(r1), "+v"(r2));  // compared as 32-bit values
     r2 += (r2 >= r1);
-    uint32_t cum = 0, v1 = 0, v2 = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      cum += n[i];
-      v1 += (r1 >= cum);
-      v2 += (r2 >= cum);
-    }
-    const uint32_t rec = (v1 * 9u + v2) * kRule9Words;
-    const uint4 c = *reinterpret_cast<const uint4 *>(&rules[rec]);
-    const uint32_t q = (u >= c.x) + (u >= c.y) + (u >= c.z) + (u >= c.w);
-    const uint32_t delta = rules[rec + 4u + q];
-#pragma unroll
-    for (uint32_t i = 0; i < 9; ++i) n[i] = n[i] + __builtin_amdgcn_ubfe(delta, 3u * i, 3u) - 2u;
+    const uint32_t v1 = count_partial_le(K, r1, one), v2 = count_partial_le(K, r2, one);
+    const uint32_t rec = (v1 * 9u + v2) * (kRule9DevWords / 4);
+    const uint4 c = rules[rec];
+    // q = #{cumulative weights <= u} (u + 1 <= D < 2^32)
+    const uint32_t u1 = u + 1u, one32 = one32_;
+    uint32_t q = __builtin_elementwise_min(__builtin_elementwise_sub_sat(u1, c.x), one32) +
+                       __builtin_elementwise_min(__builtin_elementwise_sub_sat(u1, c.y), one32) +
+                       __builtin_elementwise_min(__builtin_elementwise_sub_sat(u1, c.z), one32) +
+                       __builtin_elementwise_min(__builtin_elementwise_sub_sat(u1, c.w), one32);
+    asm volatile("" : "+v"(q));  // one shift for the record offset
+    const uint4 d = rules[rec + 1u + q];
+    K[0] += as_u16x2(d.x);
+    K[1] += as_u16x2(d.y);
+    K[2] += as_u16x2(d.z);
+    K[3] += as_u16x2(d.w);
   }
+  uint32_t prev = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t k = as_u32(K[m]), lo = k & 0xFFFFu, hi = k >> 16;
+    n[2 * m] = lo - prev;
+    n[2 * m + 1] = hi - lo;
+    prev = hi;
+  }
+  n[8] = N - prev;
 #pragma unroll
   for (int i = 0; i < 9; ++i) base[(uint64_t)i * rp.stride + ph.e[i]] = (uint16_t)n[i];
 }

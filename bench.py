@@ -27,9 +27,18 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
                for f in ("kernels.hip", "rng.h", "device.h")]
 
 
-def kernel_hash() -> str:
+# the D2Q9 step kernel: its sources and its counted VALU instructions per site
+D2Q9_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
+             for f in ("kernels_d2q9.hip", "rng.h", "device.h", "d2q9.h")]
+D2Q9_VALU_FILE = os.path.join(ROOT, "profiles", "valu_d2q9_4096x4096.json")
+# VALU issue of MI355X: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes wide), 2.4 GHz
+VALU_PEAK_G = 256 * 4 / 4 * 2.4
+
+
+def kernel_hash(paths=None) -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for path in paths or KERNEL_SRCS:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -322,11 +331,24 @@ def run_d2q9(args, torch, M):
     m = lat.moments()[0]
     lat.close()
     sites = Lx * Ly
-    return {"workload": "d2q9_4096x4096_rho36_u0", "C": 10, "lambda9": "15/128, 1/4 x6, 1/8, 18/144",
-            "steps": args.d2q9_steps, "ms_per_step": ms / args.d2q9_steps,
-            "site_updates_per_s": sites * args.d2q9_steps / (ms / 1e3),
-            "hbm_GBps": 36.0 * sites * args.d2q9_steps / (ms / 1e3) / 1e9,
-            "check": rc, "mass_per_site": m["sum_N"] / sites}
+    rate = sites * args.d2q9_steps / (ms / 1e3)
+    out = {"workload": "d2q9_4096x4096_rho36_u0", "C": 10, "lambda9": "15/128, 1/4 x6, 1/8, 18/144",
+           "steps": args.d2q9_steps, "ms_per_step": ms / args.d2q9_steps,
+           "site_updates_per_s": rate, "hbm_GBps": 36.0 * rate / 1e9,
+           "check": rc, "mass_per_site": m["sum_N"] / sites, "roofline": None}
+    # ALU roofline: VALU wave instructions per site (one lane per site) from
+    # the committed counter run, valid while the kernel's sources are the same
+    try:
+        with open(D2Q9_VALU_FILE) as f:
+            v = json.load(f)
+    except (OSError, ValueError):
+        v = {}
+    if v.get("kernel_sha256_16") == kernel_hash(D2Q9_SRCS):
+        achieved = v["valu_insts_per_wave"] * rate / 64 / 1e9
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_G,
+                           "unit": "G VALU wave-instructions/s", "frac": achieved / VALU_PEAK_G,
+                           "valu_insts_per_wave": v["valu_insts_per_wave"]}
+    return out
 
 
 def main():

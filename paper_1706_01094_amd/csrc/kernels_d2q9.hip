@@ -18,15 +18,18 @@ namespace {
 __constant__ int32_t kV9x[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int32_t kV9y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-// Physical element of velocity i of logical site (x, y) at shift (tx, ty):
-// ((x - vx tx) mod Lx, (y - vy ty) mod Ly).
+// Physical element of velocity i of logical site s = y Lx + x at shift
+// (tx, ty): ((x - vx tx) mod Lx, (y - vy ty) mod Ly), element y' Lx + x'.
+// The row offsets y' Lx are (y Lx -/+ ty Lx) mod S, with y Lx = s - x.
 struct Site9 {
   uint32_t e[9];
-  __device__ Site9(uint32_t x, uint32_t y, uint32_t tx, uint32_t ty, uint32_t Lx, uint32_t Ly) {
+  __device__ Site9(uint32_t s, uint32_t x, uint32_t tx, uint32_t ty, uint32_t Lx, uint32_t S) {
     const uint32_t xs[3] = {x + tx >= Lx ? x + tx - Lx : x + tx, x, x >= tx ? x - tx : x + Lx - tx};
-    const uint32_t ys[3] = {y + ty >= Ly ? y + ty - Ly : y + ty, y, y >= ty ? y - ty : y + Ly - ty};
+    const uint32_t yL = s - x, tyL = ty * Lx;
+    const uint32_t rows[3] = {yL + tyL >= S ? yL + tyL - S : yL + tyL, yL,
+                              yL >= tyL ? yL - tyL : yL + S - tyL};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) e[i] = ys[kV9y[i] + 1] * Lx + xs[kV9x[i] + 1];
+    for (int i = 0; i < 9; ++i) e[i] = rows[kV9y[i] + 1] + xs[kV9x[i] + 1];
   }
 };
 
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(256) k_step9(Step9 a) {
   const uint32_t y = s / rp.Lx, x = s - y * rp.Lx;
   const uint32_t tx = a.no_stream ? 0u : (uint32_t)(a.t % rp.Lx);
   const uint32_t ty = a.no_stream ? 0u : (uint32_t)(a.t % rp.Ly);
-  const Site9 ph(x, y, tx, ty, rp.Lx, rp.Ly);
+  const Site9 ph(s, x, tx, ty, rp.Lx, rp.S);
   uint16_t *base = a.state + rp.off;
   uint32_t n[9], N = 0;
 #pragma unroll
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(256) k_moments9(const uint16_t *__restrict__ s
     const uint32_t y = s / rp.Lx, x = s - y * rp.Lx;
     const uint32_t tx = no_stream ? 0u : (uint32_t)(t % rp.Lx);
     const uint32_t ty = no_stream ? 0u : (uint32_t)(t % rp.Ly);
-    const Site9 ph(x, y, tx, ty, rp.Lx, rp.Ly);
+    const Site9 ph(s, x, tx, ty, rp.Lx, rp.S);
 #pragma unroll
     for (int i = 0; i < 9; ++i) n[i] = state[rp.off + (uint64_t)i * rp.stride + ph.e[i]];
   }

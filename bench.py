@@ -371,6 +371,8 @@ def main():
     ap.add_argument("--d2q9-steps", type=int, default=50)
     ap.add_argument("--d2q9-warmup", type=int, default=5)
     ap.add_argument("--d2q9-only", action="store_true", help="only the D2Q9 measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 1024-replica batched measurement")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 8 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -395,6 +397,9 @@ def main():
 
     if args.d2q9_only:
         print(json.dumps({"d2q9": run_d2q9(args, torch, M)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": run_batched(args, torch, M)}), flush=True)
         return
     L, gpu_ms, wall = run_plain(args, torch, M)
     ms_per_step = gpu_ms / args.steps

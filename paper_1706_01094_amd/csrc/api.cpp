@@ -197,6 +197,9 @@ struct mclg_ctx {
     a.err = err();
     a.tab = table();
     a.p = params();
+    uint64_t bytes = 0;  // state the launch streams: 6 bytes per site
+    for (uint32_t s = slot_first; s < slot_first + n_slots; ++s) bytes += 6ull * L[s];
+    a.p.drain_at = drain_threshold(bytes);
     a.images = img_desc_dev();
     a.image_pool = ws + lay.o_ipool;
     a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);

@@ -29,6 +29,9 @@ struct TileDev {
   uint32_t pad;
 };
 
+// Queued draws a wave may keep between chunks (the LDS queue and 32 more).
+constexpr uint32_t kDrainAt = 64 + 32;
+
 struct StepParams {
   uint64_t seed;
   int32_t C;
@@ -37,7 +40,21 @@ struct StepParams {
   uint32_t no_stream;
   uint32_t tile_sites;
   uint32_t galilean;  // per-site lambda (see collide_direct)
+  // kDrainAt: a wave keeps up to kDrainAt queued draws between chunks; 0:
+  // it resolves them after every chunk (set by drain_threshold)
+  uint32_t drain_at = kDrainAt;
 };
+
+// Queued draws are resolved later with 2-byte writes into the lines the
+// chunk stored.  While a launch's state fits the 256 MB Infinity Cache those
+// lines are still cached and the writes are cheap, so draws are kept until
+// more than kDrainAt are queued.  A larger state has left the caches by then,
+// and partial-line writes into it are slow, so every chunk's draws are
+// resolved right after its store.
+constexpr uint64_t kCachedStateBytes = 256ull << 20;
+inline uint32_t drain_threshold(uint64_t launch_state_bytes) {
+  return launch_state_bytes > kCachedStateBytes ? 0u : kDrainAt;
+}
 
 // Stride (uint32) of the fixed-stride copy of the collision rows: a header
 // k_first | q << 16 and up to 19 thresholds.
@@ -116,6 +133,7 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // offsets.
 constexpr uint64_t kMaxSites = 1ull << 29;
 constexpr uint32_t kQueue = 64;  // LDS queue entries (16 bytes) per wave
+static_assert(kDrainAt == kQueue + 32, "drain threshold follows the LDS queue");
 // per-wave LDS after the image: the queue of undecided draws
 constexpr uint32_t kWaveLdsBytes = kQueue * 16;
 // Entries of the global overflow area per wave (the queue continues there

@@ -330,7 +330,6 @@ __device__ __forceinline__ uint32_t site_finish(const SiteLook &s, uint32_t r, b
 // (wave-uniform).  An entry is (x, a | b << 16, c, r) with the site's
 // pre-collision counts; the chunk stores whatever its lane computed for such
 // a site, and the drain overwrites it with the exact outcome.
-constexpr uint32_t kDrainAt = kQueue + 32;  // drain once F exceeds this
 static_assert(kDrainAt + 512 <= kQueue + kOverflow, "a chunk's draws must fit the queue");
 
 // Site K of every lane whose draw was not decided (and, in a chunk that
@@ -550,7 +549,7 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 // update has no races.  Undecided draws wait in the wave's queue, which is
 // drained between chunks once it nears capacity, and at the end of the
 // slot's segment.
-template <int MAXT, bool GAL>
+template <int MAXT, bool GAL, bool EAGER>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   extern __shared__ uint4 lds[];
   const StepParams &p = a.p;
@@ -716,9 +715,10 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       if (has_next) chunk_fill(nw, nxt, sv, lane);
       cw = nw;
       k = nk;
-      // At most kDrainAt draws stay queued, so the next chunk's 64 x 8 always
-      // fit.
-      if (has_next && F > kDrainAt) {
+      // At most kDrainAt draws stay queued, so the next chunk's 64 x 8
+      // always fit; EAGER (a state larger than the caches) resolves every
+      // chunk's draws while its lines are still in the L2.
+      if (has_next && F > (EAGER ? 0u : kDrainAt)) {
         drain_queue<GAL>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
       }
@@ -914,23 +914,26 @@ __global__ void __launch_bounds__(256) k_histogram(
 
 }  // namespace
 
-// Sets the dynamic LDS limit of both instantiations for this block size and
-// returns the smaller of their occupancies.
+// Sets the dynamic LDS limit of the four instantiations for this block size
+// and returns the smallest of their occupancies.
+template <int MAXT, bool GAL, bool EAGER>
+static hipError_t occupancy_one(uint32_t threads, uint32_t lds, int &blocks) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<MAXT, GAL, EAGER>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  int b = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step<MAXT, GAL, EAGER>, (int)threads, lds);
+  blocks = std::min(blocks, b);
+  return e;
+}
 template <int MAXT>
 static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
-  int b[2] = {0, 0};
-  const void *fn[2] = {reinterpret_cast<const void *>(k_step<MAXT, false>),
-                       reinterpret_cast<const void *>(k_step<MAXT, true>)};
-  for (int i = 0; i < 2; ++i) {
-    hipError_t e = hipFuncSetAttribute(fn[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e) return e;
-    e = i ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[i], k_step<MAXT, true>, (int)threads, lds)
-          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[i], k_step<MAXT, false>, (int)threads,
-                                                          lds);
-    if (e) return e;
-  }
-  blocks = std::min(b[0], b[1]);
-  return hipSuccess;
+  blocks = 1 << 30;
+  hipError_t e = occupancy_one<MAXT, false, false>(threads, lds, blocks);
+  if (!e) e = occupancy_one<MAXT, false, true>(threads, lds, blocks);
+  if (!e) e = occupancy_one<MAXT, true, false>(threads, lds, blocks);
+  if (!e) e = occupancy_one<MAXT, true, true>(threads, lds, blocks);
+  return e;
 }
 
 uint32_t step_lds_bytes(const Schedule &sch, uint32_t image_bytes) {
@@ -956,12 +959,23 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) 
   dim3 grid(std::max<uint32_t>(1, std::min(a.n_tiles, a.max_blocks))), block(sch.threads);
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
   if (sch.groups != 1) return hipErrorInvalidValue;
+  const bool small = sch.threads <= 512, eager = a.p.drain_at == 0;
   if (a.p.galilean) {
-    if (sch.threads <= 512) k_step<512, true><<<grid, block, lds, s>>>(a);
-    else k_step<1024, true><<<grid, block, lds, s>>>(a);
+    if (eager) {
+      if (small) k_step<512, true, true><<<grid, block, lds, s>>>(a);
+      else k_step<1024, true, true><<<grid, block, lds, s>>>(a);
+    } else {
+      if (small) k_step<512, true, false><<<grid, block, lds, s>>>(a);
+      else k_step<1024, true, false><<<grid, block, lds, s>>>(a);
+    }
   } else {
-    if (sch.threads <= 512) k_step<512, false><<<grid, block, lds, s>>>(a);
-    else k_step<1024, false><<<grid, block, lds, s>>>(a);
+    if (eager) {
+      if (small) k_step<512, false, true><<<grid, block, lds, s>>>(a);
+      else k_step<1024, false, true><<<grid, block, lds, s>>>(a);
+    } else {
+      if (small) k_step<512, false, false><<<grid, block, lds, s>>>(a);
+      else k_step<1024, false, false><<<grid, block, lds, s>>>(a);
+    }
   }
   return hipGetLastError();
 }

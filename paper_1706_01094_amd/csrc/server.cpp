@@ -171,6 +171,7 @@ struct mclg_server {
     a.err = err();
     a.tab = table();
     a.p = params();
+    a.p.drain_at = drain_threshold(arena_used);  // the resident jobs' state
     a.images = d_idesc();
     a.image_pool = ws + lay.o_ipool;
     a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);

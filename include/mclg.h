@@ -134,7 +134,17 @@ typedef struct {
   int64_t n0_odd;      /* sites with odd n_0 (conserved per site) */
   int64_t max_N;       /* max_x N(x) */
   int64_t fourier[MCLG_MAX_MODES][2]; /* sum N(x) tw[2m][x], sum N(x) tw[2m+1][x] */
+  /* With MCLG_MOMENTS_DIGEST (else 0): a checksum of the whole logical state,
+   *   sum over x < L and i = 0, 1, 2 (v = -1, 0, +1) of
+   *   fmix32(fmix32(4 x + i + 1) ^ n_i(x))   (mod 2^64),
+   * fmix32 the 32-bit finaliser of MurmurHash3 (k ^= k >> 16; k *= 0x85ebca6b;
+   * k ^= k >> 13; k *= 0xc2b2ae35; k ^= k >> 16).  Two states with equal
+   * digests are equal unless a 2^-32-probability coincidence occurs; used to
+   * compare runs without copying the state. */
+  int64_t digest;
 } mclg_moments_t;
+
+#define MCLG_MOMENTS_DIGEST 1u  /* mclg_moments flag: also compute the state digest */
 
 /* ---- D2Q9 (Sec. "A D2Q9 implementation") ----
  * Velocities numbered as the columns of the moment matrix Eq. (MomD2Q9):
@@ -209,10 +219,15 @@ int mclg_step_replica(mclg_ctx *ctx, uint32_t replica, uint64_t n_steps);
  * and launch it; same results as mclg_step. */
 int mclg_step_graph(mclg_ctx *ctx, uint64_t n_steps);
 
-/* Exact moments of every replica into host_out[n_replicas]; synchronises.
+/* Exact moments of every replica into host_out[n_replicas]: the integer
+ * sums behind the paper's statistics -- means and variances of n_i
+ * (Eq. (poisson)), the correlator of Eq. (corr), the conserved N and J, and
+ * Fourier projections of the density (Eq. (A), S(k)).  Synchronises.
  * twiddle: device int32, NULL when n_modes = 0; replica r's block is
- * [2 n_modes][L[r]], blocks packed densely in replica order. */
-int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
+ * [2 n_modes][L[r]], blocks packed densely in replica order.  flags: 0 or
+ * MCLG_MOMENTS_DIGEST.  Uses the workspace; MCLG_E_INVAL for n_modes > 8,
+ * a missing twiddle or unknown flags. */
+int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes, uint32_t flags,
                  mclg_moments_t *host_out);
 
 /* Logical counts of one replica into host_out[3][L]; synchronises. */
@@ -250,6 +265,20 @@ int mclg_set_schedule(mclg_ctx *ctx, uint32_t groups_per_thread, uint32_t thread
  * runs of chunks (and leaves CUs to other work); any value gives identical
  * bits.  Drops captured graphs; synchronises the stream. */
 int mclg_set_grid_limit(mclg_ctx *ctx, uint32_t max_blocks);
+
+/* When the step kernel resolves the draws its LDS image cannot decide (from
+ * the exact tables in the workspace): every policy gives identical bits.
+ *   MCLG_DRAIN_AUTO (default): DEFERRED when a launch's state fits the 256 MB
+ *     Infinity Cache, else PATCH;
+ *   MCLG_DRAIN_DEFERRED: a wave queues up to 96 draws across chunks and
+ *     writes their outcomes afterwards (2-byte stores into stored lines);
+ *   MCLG_DRAIN_CHUNK: the same after every chunk;
+ *   MCLG_DRAIN_PATCH: each chunk's draws are resolved before the chunk's
+ *     stores, so every count is written once.
+ * Drops captured graphs; synchronises the stream; MCLG_E_INVAL for an
+ * unknown policy. */
+enum { MCLG_DRAIN_AUTO = 0, MCLG_DRAIN_DEFERRED = 1, MCLG_DRAIN_CHUNK = 2, MCLG_DRAIN_PATCH = 3 };
+int mclg_set_drain(mclg_ctx *ctx, uint32_t policy);
 
 /* Expected fraction of site updates whose draw is decided from LDS (from the
  * product-Poisson law the images were built for) and the LDS bytes per block. */

@@ -5,7 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmclg.so")
-SOURCES = ["kernels.hip", "kernels_d2q9.hip", "api.cpp", "server.cpp", "tables.cpp", "d2q9.cpp"]
+SOURCES = ["kernels.hip", "kernels_d2q9.hip", "moments.hip", "api.cpp", "server.cpp", "tables.cpp",
+           "d2q9.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops off: no packed FP32 instructions are generated.
@@ -16,7 +17,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=
 
 def build(force: bool = True, verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    deps = srcs + [os.path.join(CSRC, h) for h in ("device.h", "tables.h", "rng.h", "d2q9.h")] + \
+    deps = srcs + [os.path.join(CSRC, h) for h in ("device.h", "tables.h", "rng.h", "d2q9.h", "moments.h")] + \
         [os.path.join(HERE, "..", "include", "mclg.h")]
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):

@@ -13,6 +13,7 @@
 #include "../../include/mclg.h"
 #include "d2q9.h"
 #include "device.h"
+#include "moments.h"
 #include "tables.h"
 
 using namespace mclg;
@@ -31,8 +32,11 @@ struct Layout {
   std::vector<uint64_t> off, stride, dense;
   uint64_t total_sites = 0, max_tiles = 0;
   // workspace byte offsets
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, o_fixed, ws_bytes;
+  // moment kernels: segments, runs (one per slot), partial records, results
+  MomPlan mplan;
+  uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout;
 };
 
 bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, Layout &lay) {
@@ -62,7 +66,16 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
   lay.o_tslot = take(sizeof(uint32_t) * n);
   lay.o_tiles = take(sizeof(TileDev) * tiles);
   lay.o_list = take(sizeof(uint32_t) * n);
-  lay.o_mom = take(sizeof(MomDev) * n);
+  {
+    std::vector<uint32_t> ids(n);
+    for (uint32_t r = 0; r < n; ++r) ids[r] = r;
+    lay.mplan = plan_moments(ids.data(), L, n);
+  }
+  lay.o_mseg = take(sizeof(MomSeg) * lay.mplan.segs.size());
+  lay.o_mrun = take(sizeof(uint32_t) * lay.mplan.run_seg.size());
+  lay.o_mslot = take(sizeof(uint32_t) * lay.mplan.run_slot.size());
+  lay.o_mpart = take(sizeof(uint64_t) * kMom3Rec * lay.mplan.segs.size());
+  lay.o_mout = take(sizeof(uint64_t) * kMom3Out * n);
   lay.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   lay.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
   lay.o_idesc = take(sizeof(ImageDesc) * n);
@@ -122,6 +135,7 @@ struct mclg_ctx {
   std::vector<uint8_t> img_pool;
   uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
   uint32_t grid_limit = 0;  // 0: occupancy-derived grid
+  uint32_t drain_policy = MCLG_DRAIN_AUTO;
   double coverage = 0.0;                // expected LDS hit fraction (site-weighted)
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
@@ -135,7 +149,23 @@ struct mclg_ctx {
     return e;
   }
   TileDev *tiles_dev() { return reinterpret_cast<TileDev *>(ws + lay.o_tiles); }
-  MomDev *mom() { return reinterpret_cast<MomDev *>(ws + lay.o_mom); }
+  // The moment kernels' arguments; partial records and results go to
+  // `partial` and `out` (device).
+  MomArgs mom_args(unsigned long long *partial, long long *out) {
+    MomArgs m;
+    m.state = state;
+    m.slots = slots();
+    m.tslot = tslot();
+    m.no_stream = (flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u;
+    m.segs = reinterpret_cast<const MomSeg *>(ws + lay.o_mseg);
+    m.n_segs = (uint32_t)lay.mplan.segs.size();
+    m.run_seg = reinterpret_cast<const uint32_t *>(ws + lay.o_mrun);
+    m.run_slot = reinterpret_cast<const uint32_t *>(ws + lay.o_mslot);
+    m.n_runs = n;
+    m.partial = partial;
+    m.out = out;
+    return m;
+  }
   TableDev table() {
     TableDev d;
     d.rowbase = reinterpret_cast<const uint32_t *>(ws + lay.o_rowbase);
@@ -176,7 +206,7 @@ struct mclg_ctx {
   ImageDesc *img_desc_dev() { return reinterpret_cast<ImageDesc *>(ws + lay.o_idesc); }
   StepLaunch launch_args(uint32_t tile_lo, uint32_t tile_hi, uint32_t slot_first,
                          uint32_t n_slots, uint32_t t_off) {
-    StepLaunch a;
+    StepLaunch a{};
     a.state = state;
     a.slots = slots();
     a.tslot = tslot();
@@ -199,7 +229,7 @@ struct mclg_ctx {
     a.p = params();
     uint64_t bytes = 0;  // state the launch streams: 6 bytes per site
     for (uint32_t s = slot_first; s < slot_first + n_slots; ++s) bytes += 6ull * L[s];
-    a.p.drain_at = drain_threshold(bytes);
+    a.p.drain = drain_policy == MCLG_DRAIN_AUTO ? auto_drain(bytes) : drain_policy - 1u;
     a.images = img_desc_dev();
     a.image_pool = ws + lay.o_ipool;
     a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);
@@ -394,6 +424,9 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   if (!e) e = up(lay.o_tslot, tz.data(), sizeof(uint32_t) * c->n);
   if (!e) e = up(lay.o_tiles, c->tiles.data(), sizeof(TileDev) * c->tiles.size());
   if (!e) e = up(lay.o_list, list.data(), sizeof(uint32_t) * c->n);
+  if (!e) e = up(lay.o_mseg, lay.mplan.segs.data(), sizeof(MomSeg) * lay.mplan.segs.size());
+  if (!e) e = up(lay.o_mrun, lay.mplan.run_seg.data(), sizeof(uint32_t) * lay.mplan.run_seg.size());
+  if (!e) e = up(lay.o_mslot, lay.mplan.run_slot.data(), sizeof(uint32_t) * lay.mplan.run_slot.size());
   if (!e) e = up(lay.o_rowbase, tab->rowbase.data(), sizeof(uint32_t) * tab->rowbase.size());
   if (!e) e = up(lay.o_rowdesc, tab->rowdesc.data(), sizeof(uint32_t) * tab->rowdesc.size());
   if (!e) e = up(lay.o_thr, tab->thr.data(), sizeof(uint32_t) * tab->thr.size());
@@ -431,7 +464,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
     for (uint32_t r = 0; r < c->n; ++r) { c->est_rho[r] = init->rho[r]; c->est_u[r] = init->u0[r]; }
   } else {
     std::vector<mclg_moments_t> m(c->n);
-    int rc2 = mclg_moments(c.get(), nullptr, 0, m.data());
+    int rc2 = mclg_moments(c.get(), nullptr, 0, 0, m.data());
     if (rc2 && rc2 != MCLG_E_RANGE) return rc2;
     for (uint32_t r = 0; r < c->n; ++r) {
       c->est_rho[r] = (double)m[r].sum_N / (double)c->L[r];
@@ -541,43 +574,26 @@ int mclg_moments9(mclg_ctx *c, mclg_moments9_t *out) {
   return d2q9_moments(*c->d2, out);
 }
 
-int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, mclg_moments_t *out) {
+int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, uint32_t flags,
+                 mclg_moments_t *out) {
   if (c && c->d2) return MCLG_E_UNSUPPORTED;
-  if (!c || !out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle)) return MCLG_E_INVAL;
+  if (!c || !out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle) ||
+      (flags & ~(uint32_t)MCLG_MOMENTS_DIGEST))
+    return MCLG_E_INVAL;
+  static_assert(sizeof(mclg_moments_t) == kMom3Out * sizeof(int64_t), "result layout");
   hipStream_t s = c->stream;
+  MomArgs m = c->mom_args(reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart),
+                          reinterpret_cast<long long *>(c->ws + c->lay.o_mout));
+  m.twiddle = twiddle;
+  m.n_modes = n_modes;
+  m.digest = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
   hipError_t e = c->flush_t();
-  if (!e)
-    e = launch_zero(s, reinterpret_cast<unsigned long long *>(c->mom()),
-                    (uint64_t)c->n * (sizeof(MomDev) / 8));
-  if (!e)
-    e = launch_moments(s, c->state, c->slots(), c->tslot(), c->tiles_dev(),
-                       (uint32_t)c->tiles.size(), c->sch.tile_sites(),
-                       (c->flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u, twiddle, n_modes, c->mom());
-  std::vector<MomDev> h(c->n);
-  if (!e) e = hipMemcpyAsync(h.data(), c->mom(), sizeof(MomDev) * c->n, hipMemcpyDeviceToHost, s);
+  if (!e) e = launch_moments3(s, m);
+  if (!e) e = hipMemcpyAsync(out, c->ws + c->lay.o_mout, sizeof(mclg_moments_t) * c->n,
+                             hipMemcpyDeviceToHost, s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return c->hip(e);
-  for (uint32_t r = 0; r < c->n; ++r) {
-    mclg_moments_t &o = out[r];
-    std::memset(&o, 0, sizeof(o));
-    const unsigned long long *v = h[r].v;
-    o.t = c->t[r];
-    o.sites = (int64_t)c->L[r];
-    for (int i = 0; i < 3; ++i) {
-      o.sum_n[i] = (int64_t)v[i];
-      o.sum_n2[i] = (int64_t)v[3 + i];
-      o.sum_nn[i] = (int64_t)v[6 + i];
-    }
-    o.sum_N = (int64_t)v[9];
-    o.sum_J = (int64_t)v[10];
-    o.sum_N2 = (int64_t)v[11];
-    o.n0_odd = (int64_t)v[12];
-    o.max_N = (int64_t)v[13];
-    for (uint32_t m = 0; m < n_modes; ++m) {
-      o.fourier[m][0] = (int64_t)v[14 + 2 * m];
-      o.fourier[m][1] = (int64_t)v[15 + 2 * m];
-    }
-  }
+  for (uint32_t r = 0; r < c->n; ++r) out[r].t = c->t[r];  // exact beyond 2^32 steps
   return read_err(c);
 }
 
@@ -617,9 +633,12 @@ int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t l
   c->sch.groups = groups;
   c->sch.threads = threads;
   c->sch.lds_budget = lds_budget;
+  // graphs still in flight on the stream use the old tiles and images
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e) return c->hip(e);
   c->build_tiles();
   c->drop_graphs();
-  hipError_t e = hipMemcpyAsync(c->tiles_dev(), c->tiles.data(), sizeof(TileDev) * c->tiles.size(),
+  e = hipMemcpyAsync(c->tiles_dev(), c->tiles.data(), sizeof(TileDev) * c->tiles.size(),
                                 hipMemcpyHostToDevice, c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
   if (!e) e = c->prepare_images();
@@ -631,6 +650,15 @@ int mclg_set_grid_limit(mclg_ctx *c, uint32_t max_blocks) {
   if (!c) return MCLG_E_INVAL;
   hipError_t e = hipStreamSynchronize(c->stream);
   c->grid_limit = max_blocks;
+  c->drop_graphs();
+  return c->hip(e);
+}
+
+int mclg_set_drain(mclg_ctx *c, uint32_t policy) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
+  if (!c || policy > MCLG_DRAIN_PATCH) return MCLG_E_INVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);  // captured graphs hold the old policy
+  c->drain_policy = policy;
   c->drop_graphs();
   return c->hip(e);
 }

@@ -157,7 +157,20 @@ int d2q9_layout(const mclg_config *cfg, D2Ctx &d) {
   d.o_reps = take(sizeof(Rep9) * d.n);
   d.o_tiles = take(sizeof(Tile9) * d.tiles.size());
   d.o_rules = take(sizeof(uint32_t) * d.rules_dev.size());
-  d.o_mom = take(sizeof(uint64_t) * kMom9Vals * d.n);
+  {
+    std::vector<uint32_t> ids(d.n);
+    std::vector<uint64_t> S(d.n);
+    for (uint32_t r = 0; r < d.n; ++r) {
+      ids[r] = r;
+      S[r] = d.Lx[r] * d.Ly[r];
+    }
+    d.mplan = plan_moments(ids.data(), S.data(), d.n);
+  }
+  d.o_mseg = take(sizeof(MomSeg) * d.mplan.segs.size());
+  d.o_mrun = take(sizeof(uint32_t) * d.mplan.run_seg.size());
+  d.o_mslot = take(sizeof(uint32_t) * d.mplan.run_slot.size());
+  d.o_mpart = take(sizeof(uint64_t) * kMom9Rec * d.mplan.segs.size());
+  d.o_mout = take(sizeof(uint64_t) * kMom9Out * d.n);
   d.o_pdesc = take(sizeof(PoisDesc) * 9 * d.n);
   d.o_pool = take(sizeof(uint32_t) * kPoisCap9 * 9 * d.n);
   d.o_dense = take(sizeof(uint64_t) * d.n);
@@ -217,6 +230,9 @@ int d2q9_init(D2Ctx &d, const mclg_config *cfg, const mclg_init_spec *init) {
   if (!e) e = put(d.o_tiles, d.tiles.data(), sizeof(Tile9) * d.tiles.size());
   if (!e) e = put(d.o_rules, d.rules_dev.data(), sizeof(uint32_t) * d.rules_dev.size());
   if (!e) e = put(d.o_dense, d.dense.data(), sizeof(uint64_t) * d.n);
+  if (!e) e = put(d.o_mseg, d.mplan.segs.data(), sizeof(MomSeg) * d.mplan.segs.size());
+  if (!e) e = put(d.o_mrun, d.mplan.run_seg.data(), sizeof(uint32_t) * d.mplan.run_seg.size());
+  if (!e) e = put(d.o_mslot, d.mplan.run_slot.data(), sizeof(uint32_t) * d.mplan.run_slot.size());
   if (!e && !pool.empty()) e = put(d.o_pdesc, pdesc.data(), sizeof(PoisDesc) * pdesc.size());
   if (!e && !pool.empty()) e = put(d.o_pool, pool.data(), sizeof(uint32_t) * pool.size());
   const Rep9 *reps = reinterpret_cast<const Rep9 *>(d.ws + d.o_reps);
@@ -236,7 +252,7 @@ int d2q9_init(D2Ctx &d, const mclg_config *cfg, const mclg_init_spec *init) {
 }
 
 int d2q9_step(D2Ctx &d, uint64_t n_steps) {
-  Step9 a;
+  Step9 a{};
   a.state = d.state;
   a.reps = reinterpret_cast<const Rep9 *>(d.ws + d.o_reps);
   a.tiles = reinterpret_cast<const Tile9 *>(d.ws + d.o_tiles);
@@ -298,30 +314,24 @@ int d2q9_get_counts(D2Ctx &d, uint32_t r, uint16_t *out) {
 
 int d2q9_moments(D2Ctx &d, mclg_moments9_t *out) {
   if (!out) return MCLG_E_INVAL;
-  unsigned long long *mom = reinterpret_cast<unsigned long long *>(d.ws + d.o_mom);
-  hipError_t e = launch_zero(d.stream, mom, (uint64_t)kMom9Vals * d.n);
-  if (!e)
-    e = launch_moments9(d.stream, d.state, reinterpret_cast<const Rep9 *>(d.ws + d.o_reps),
-                        reinterpret_cast<const Tile9 *>(d.ws + d.o_tiles),
-                        (uint32_t)d.tiles.size(), (uint64_t)d.t,
-                        (d.flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u, mom);
-  std::vector<unsigned long long> h((size_t)kMom9Vals * d.n);
-  if (!e) e = hipMemcpyAsync(h.data(), mom, h.size() * 8, hipMemcpyDeviceToHost, d.stream);
+  static_assert(sizeof(mclg_moments9_t) == kMom9Out * sizeof(int64_t), "result layout");
+  MomArgs m;
+  m.state = d.state;
+  m.reps = reinterpret_cast<const Rep9 *>(d.ws + d.o_reps);
+  m.t9 = (uint64_t)d.t;
+  m.no_stream = (d.flags & MCLG_FLAG_NO_STREAM) ? 1u : 0u;
+  m.segs = reinterpret_cast<const MomSeg *>(d.ws + d.o_mseg);
+  m.n_segs = (uint32_t)d.mplan.segs.size();
+  m.run_seg = reinterpret_cast<const uint32_t *>(d.ws + d.o_mrun);
+  m.run_slot = reinterpret_cast<const uint32_t *>(d.ws + d.o_mslot);
+  m.n_runs = d.n;
+  m.partial = reinterpret_cast<unsigned long long *>(d.ws + d.o_mpart);
+  m.out = reinterpret_cast<long long *>(d.ws + d.o_mout);
+  hipError_t e = launch_moments9(d.stream, m);
+  if (!e) e = hipMemcpyAsync(out, d.ws + d.o_mout, sizeof(mclg_moments9_t) * d.n,
+                             hipMemcpyDeviceToHost, d.stream);
   if (!e) e = hipStreamSynchronize(d.stream);
   if (e) return hip_rc(d, e);
-  for (uint32_t r = 0; r < d.n; ++r) {
-    const unsigned long long *v = &h[(size_t)r * kMom9Vals];
-    mclg_moments9_t &o = out[r];
-    std::memset(&o, 0, sizeof(o));
-    o.t = d.t;
-    o.sites = (int64_t)d.reps[r].S;
-    for (int i = 0; i < 9; ++i) o.sum_n[i] = (int64_t)v[i];
-    for (int q = 0; q < 45; ++q) o.sum_nn[q] = (int64_t)v[9 + q];
-    o.sum_N = (int64_t)v[54];
-    o.sum_Jx = (int64_t)v[55];
-    o.sum_Jy = (int64_t)v[56];
-    o.max_N = (int64_t)v[57];
-  }
   return d2q9_check(d);
 }
 

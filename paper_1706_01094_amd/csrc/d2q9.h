@@ -8,6 +8,7 @@
 
 #include "../../include/mclg.h"
 #include "device.h"
+#include "moments.h"
 
 namespace mclg {
 
@@ -22,8 +23,10 @@ struct D2Ctx {
   std::vector<uint32_t> rules;      // 81 x kRule9Words
   std::vector<uint32_t> rules_dev;  // 81 x kRule9DevWords
   uint64_t state_bytes = 0, ws_bytes = 0;
-  uint64_t o_err = 0, o_reps = 0, o_tiles = 0, o_rules = 0, o_mom = 0, o_pdesc = 0, o_pool = 0,
+  uint64_t o_err = 0, o_reps = 0, o_tiles = 0, o_rules = 0, o_pdesc = 0, o_pool = 0,
            o_dense = 0;
+  MomPlan mplan;  // moment kernels: segments and runs (one per replica)
+  uint64_t o_mseg = 0, o_mrun = 0, o_mslot = 0, o_mpart = 0, o_mout = 0;
   uint16_t *state = nullptr;
   uint8_t *ws = nullptr;
   hipStream_t stream = nullptr;

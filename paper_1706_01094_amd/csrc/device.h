@@ -13,47 +13,55 @@ namespace mclg {
 // streaming costs nothing and every element is read and written by exactly
 // one site per step.  With MCLG_FLAG_NO_STREAM the layout is unshifted.
 struct SlotDev {
-  uint64_t off;      // element offset of the n_-1 array in the state buffer
-  uint64_t dense;    // packed site offset (init counts, twiddles)
-  uint32_t L;        // sites
-  uint32_t stride;   // elements per array (L rounded up to 128)
-  uint32_t rid;      // RNG replica identity
-  uint32_t pad;
+  uint64_t off = 0;      // element offset of the n_-1 array in the state buffer
+  uint64_t dense = 0;    // packed site offset (init counts, twiddles)
+  uint32_t L = 0;        // sites
+  uint32_t stride = 0;   // elements per array (L rounded up to 128)
+  uint32_t rid = 0;      // RNG replica identity
+  uint32_t pad = 0;
 };
 
 // A chunk of 512 sites of one slot (the last chunk of a slot may be short).
 struct TileDev {
-  uint32_t slot;     // slot index
-  uint32_t x0;       // first site (multiple of 512)
-  uint32_t next;     // index of the first chunk after this slot's run of chunks
-  uint32_t pad;
+  uint32_t slot = 0;     // slot index
+  uint32_t x0 = 0;       // first site (multiple of 512)
+  uint32_t next = 0;     // index of the first chunk after this slot's run of chunks
+  uint32_t pad = 0;
 };
 
 // Queued draws a wave may keep between chunks (the LDS queue and 32 more).
 constexpr uint32_t kDrainAt = 64 + 32;
 
+// When the draws the LDS image cannot decide are resolved (from the exact
+// global rows), per wave:
+//   kDrainDeferred: queued until more than kDrainAt wait, then resolved after
+//     the chunk's store and written with 2-byte stores into the lines the
+//     chunks stored before;
+//   kDrainChunk: the same after every chunk's store;
+//   kDrainPatch: before the chunk's store -- the exact outcomes go into the
+//     chunk's registers, so the chunk's 16-byte stores write final values and
+//     nothing is written twice.
+enum : uint32_t { kDrainDeferred = 0, kDrainChunk = 1, kDrainPatch = 2 };
+
 struct StepParams {
-  uint64_t seed;
-  int32_t C;
-  uint32_t lam_p, lam_q;
-  uint32_t n_max;
-  uint32_t no_stream;
-  uint32_t tile_sites;
-  uint32_t galilean;  // per-site lambda (see collide_direct)
-  // kDrainAt: a wave keeps up to kDrainAt queued draws between chunks; 0:
-  // it resolves them after every chunk (set by drain_threshold)
-  uint32_t drain_at = kDrainAt;
+  uint64_t seed = 0;
+  int32_t C = 0;
+  uint32_t lam_p = 1, lam_q = 1;
+  uint32_t n_max = 0;
+  uint32_t no_stream = 0;
+  uint32_t tile_sites = 512;
+  uint32_t galilean = 0;  // per-site lambda (see collide_direct)
+  uint32_t drain = kDrainDeferred;
 };
 
-// Queued draws are resolved later with 2-byte writes into the lines the
-// chunk stored.  While a launch's state fits the 256 MB Infinity Cache those
-// lines are still cached and the writes are cheap, so draws are kept until
-// more than kDrainAt are queued.  A larger state has left the caches by then,
-// and partial-line writes into it are slow, so every chunk's draws are
-// resolved right after its store.
+// Deferred 2-byte writes land in lines the chunks stored long before.  While
+// a launch's state fits the 256 MB Infinity Cache those lines are still
+// cached and the writes are cheap; a larger state has left the caches by
+// then, and partial-line writes into it are slow, so each chunk's draws are
+// resolved before its store.
 constexpr uint64_t kCachedStateBytes = 256ull << 20;
-inline uint32_t drain_threshold(uint64_t launch_state_bytes) {
-  return launch_state_bytes > kCachedStateBytes ? 0u : kDrainAt;
+inline uint32_t auto_drain(uint64_t launch_state_bytes) {
+  return launch_state_bytes > kCachedStateBytes ? kDrainPatch : kDrainDeferred;
 }
 
 // Stride (uint32) of the fixed-stride copy of the collision rows: a header
@@ -61,32 +69,25 @@ inline uint32_t drain_threshold(uint64_t launch_state_bytes) {
 constexpr uint32_t kFixedStride = 20;
 
 struct TableDev {
-  const uint32_t *rowbase;
-  const uint2 *rowdesc;
-  const uint32_t *thr;
-  const uint4 *fixed;  // rows at a fixed stride of kFixedStride uint32, or null
-};
-
-// Exact per-slot sums, all modulo 2^64.
-struct MomDev {
-  unsigned long long v[32];
-  // 0..2 sum n, 3..5 sum n^2, 6..8 sum nn, 9 sum N, 10 sum J, 11 sum N^2,
-  // 12 n0 odd, 13 max N, 14..29 fourier (m, cos/sin)
+  const uint32_t *rowbase = nullptr;
+  const uint2 *rowdesc = nullptr;
+  const uint32_t *thr = nullptr;
+  const uint4 *fixed = nullptr;  // rows at a fixed stride of kFixedStride uint32, or null
 };
 
 // Where a slot's LDS image lives in the image pool (see LdsImage).
 struct ImageDesc {
-  uint64_t off;        // byte offset in the image pool (16-byte aligned)
-  uint32_t bytes;      // every slot has one (at least the two special slots)
-  uint32_t dir_bytes;
-  uint32_t dim_a, dim_c, b_lo, nb;
+  uint64_t off = 0;        // byte offset in the image pool (16-byte aligned)
+  uint32_t bytes = 0;      // every slot has one (at least the two special slots)
+  uint32_t dir_bytes = 0;
+  uint32_t dim_a = 0, dim_c = 0, b_lo = 0, nb = 0;
 };
 
 struct PoisDesc {
-  uint32_t off;      // offset in the threshold pool
-  uint32_t k_first;
-  uint32_t nthr;     // q - 1
-  uint32_t pad;
+  uint32_t off = 0;      // offset in the threshold pool
+  uint32_t k_first = 0;
+  uint32_t nthr = 0;     // q - 1
+  uint32_t pad = 0;
 };
 
 // Launch configuration of the fused stream+collide kernel.
@@ -97,33 +98,35 @@ struct Schedule {
   uint32_t tile_sites() const { return 512; }  // one chunk: 64 lanes x 8 sites
 };
 
+// Every field has an initialiser, so that a launch record built field by
+// field never carries an indeterminate value.
 struct StepLaunch {
-  uint16_t *state;
-  const SlotDev *slots;
-  uint32_t *tslot;
-  const TileDev *tiles;
-  uint32_t n_tiles;
-  const uint32_t *slot_list;  // slots advanced by this launch, or null for a range
-  uint32_t slot_first, n_slots;
+  uint16_t *state = nullptr;
+  const SlotDev *slots = nullptr;
+  uint32_t *tslot = nullptr;
+  const TileDev *tiles = nullptr;
+  uint32_t n_tiles = 0;
+  const uint32_t *slot_list = nullptr;  // slots advanced by this launch, or null for a range
+  uint32_t slot_first = 0, n_slots = 0;
   // With `ticket` set, the launch's last block advances tslot of the launch's
   // slots by one; without it the slots' step is tslot + t_off and tslot is
   // advanced later (launch_add_t), which saves the end-of-launch ticket.
-  uint32_t *ticket, *err;
-  uint32_t t_off;
+  uint32_t *ticket = nullptr, *err = nullptr;
+  uint32_t t_off = 0;
   // A launch over one slot's tiles (0 .. n_tiles - 1 from x = 0) carries the
   // slot's descriptors itself, so that its blocks start without dependent
   // loads: single = 1, slot slot_first, image im1, slot sl1.
-  uint32_t single;
+  uint32_t single = 0;
   ImageDesc im1;
   SlotDev sl1;
   TableDev tab;
   StepParams p;
-  const ImageDesc *images;    // per slot
-  const uint8_t *image_pool;
-  uint4 *overflow;            // kOverflowPerWave entries per resident wave
-  uint32_t lds_bytes;         // LDS per block for the image (largest image, 16-byte multiple);
-                              // the per-wave miss queues follow it
-  uint32_t max_blocks;        // persistent grid size
+  const ImageDesc *images = nullptr;  // per slot
+  const uint8_t *image_pool = nullptr;
+  uint4 *overflow = nullptr;          // kOverflowPerWave entries per resident wave
+  uint32_t lds_bytes = 0;             // LDS per block for the image (largest image, 16-byte
+                                      // multiple); the per-wave miss queues follow it
+  uint32_t max_blocks = 1;            // persistent grid size
 };
 
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
@@ -159,13 +162,6 @@ hipError_t launch_init_counts(hipStream_t s, uint16_t *state, const SlotDev *slo
                               const TileDev *tiles, uint32_t n_tiles, uint32_t tile_sites,
                               const uint16_t *counts);
 
-hipError_t launch_zero(hipStream_t s, unsigned long long *p, uint64_t n);
-
-hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *slots,
-                          const uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
-                          uint32_t tile_sites, uint32_t no_stream, const int32_t *twiddle,
-                          uint32_t n_modes, MomDev *out);
-
 // hist[(slot * 3 + i) * n_bins + min(n_i, n_bins - 1)] += 1 over every site
 hipError_t launch_histogram(hipStream_t s, const uint16_t *state, const SlotDev *slots,
                             const TileDev *tiles, uint32_t n_tiles, uint32_t tile_sites,
@@ -195,7 +191,6 @@ struct Tile9 {
 // q = #{cumulative weights <= u} (word 4 + q; q = number of targets means no
 // change), 3 bits per velocity i at bit 3i holding 2 + the change; 9-11 pad.
 constexpr uint32_t kRule9Words = 12;
-constexpr uint32_t kMom9Vals = 9 + 45 + 4;  // sum n_i, sum n_i n_j (i <= j), N, Jx, Jy, max N
 struct Step9 {
   uint16_t *state;
   const Rep9 *reps;
@@ -217,8 +212,4 @@ hipError_t launch_init9_counts(hipStream_t s, uint16_t *state, const Rep9 *reps,
 hipError_t launch_histogram9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
                              const Tile9 *tiles, uint32_t n_tiles, uint32_t n_bins,
                              unsigned long long *hist);
-hipError_t launch_moments9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
-                           const Tile9 *tiles, uint32_t n_tiles, uint64_t t, uint32_t no_stream,
-                           unsigned long long *out);
-
 }  // namespace mclg

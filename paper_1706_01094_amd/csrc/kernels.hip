@@ -329,17 +329,19 @@ __device__ __forceinline__ uint32_t site_finish(const SiteLook &s, uint32_t r, b
 // LDS followed by kOverflow entries in global memory, filled to F
 // (wave-uniform).  An entry is (x, a | b << 16, c, r) with the site's
 // pre-collision counts; the chunk stores whatever its lane computed for such
-// a site, and the drain overwrites it with the exact outcome.
+// a site, and the drain overwrites it with the exact outcome.  When the
+// chunk's draws are resolved before its store (kDrainPatch), the first word
+// is instead the site's position in the chunk, 8 lane + K.
 static_assert(kDrainAt + 512 <= kQueue + kOverflow, "a chunk's draws must fit the queue");
 
 // Site K of every lane whose draw was not decided (and, in a chunk that
 // passes the end of the lattice, that exists) goes to the queue, in lane
 // order.  wa, wb, wc are the words holding the site's pre-collision counts;
 // `slow` is wave-uniform.
-template <int K>
+template <int K, bool PATCH>
 __device__ __forceinline__ void push_site(uint4 *queue, Rsrc over, uint32_t &F, bool hit,
                                           bool slow, uint32_t x8, uint32_t L, uint32_t wa,
-                                          uint32_t wb, uint32_t wc, uint32_t r) {
+                                          uint32_t wb, uint32_t wc, uint32_t r, uint32_t xs) {
   uint64_t mk = __ballot(!hit);
   if (mk == 0) return;
   if (slow) mk &= __builtin_amdgcn_uicmpl(x8 + K, L, 36);  // lanes with x8 + K < L
@@ -349,11 +351,18 @@ __device__ __forceinline__ void push_site(uint4 *queue, Rsrc over, uint32_t &F, 
     const uint32_t ab = (K & 1) ? __builtin_amdgcn_perm(wb, wa, 0x07060302u)
                                 : __builtin_amdgcn_perm(wb, wa, 0x05040100u);
     const uint32_t c = (K & 1) ? wc >> 16 : wc & 0xffffu;
+    uint32_t w0 = x8 + K;
+    if constexpr (PATCH) {
+      // the position in the chunk (xs: its first site), computed here rather
+      // than hoisted out of the chunk loop as a per-lane constant
+      w0 -= xs;
+      asm volatile("" : "+v"(w0));
+    }
     if (pos < kQueue) {
-      queue[pos] = make_uint4(x8 + K, ab, c, r);
+      queue[pos] = make_uint4(w0, ab, c, r);
     } else {
       typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-      const u32x4 e = {x8 + K, ab, c, r};
+      const u32x4 e = {w0, ab, c, r};
       __builtin_amdgcn_raw_buffer_store_b128(e, over, (int)(16u * (pos - kQueue)), 0, 0);
     }
   }
@@ -379,11 +388,12 @@ __device__ __forceinline__ void apply_pair(uint32_t &a, uint32_t &b, uint32_t &c
 // Philox draws while they are in flight, then record reads and decisions;
 // the undecided draws are queued with the pre-collision counts before the
 // update.
+template <bool PATCH>
 __device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
                                              uint32_t (&va)[4], uint32_t (&vb)[4],
                                              uint32_t (&vc)[4], const LdsView &lv, uint4 *queue,
                                              Rsrc over, uint32_t &F, bool slow, uint32_t x8,
-                                             uint32_t L) {
+                                             uint32_t L, uint32_t xs) {
   SiteLook s0, s1, s2, s3, s4, s5, s6, s7;
   uint32_t r0, r1, r2, r3, r4, r5, r6, r7;  // each site's first record
   u16x2 b01, b23, b45, b67;                  // clamped b - b_lo of each pair
@@ -407,8 +417,9 @@ __device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
   apply_pair(na[1], nb[1], nc[1], d23);
   apply_pair(na[2], nb[2], nc[2], d45);
   apply_pair(na[3], nb[3], nc[3], d67);
-#define MCLG_PUSH(K, H, R) \
-  push_site<K>(queue, over, F, H, slow, x8, L, va[K >> 1], vb[K >> 1], vc[K >> 1], R)
+#define MCLG_PUSH(K, H, R)                                                                \
+  push_site<K, PATCH>(queue, over, F, H, slow, x8, L, va[K >> 1], vb[K >> 1], vc[K >> 1], R, \
+                      xs)
   MCLG_PUSH(0, h0, w0.x); MCLG_PUSH(1, h1, w0.y); MCLG_PUSH(2, h2, w0.z); MCLG_PUSH(3, h3, w0.w);
   MCLG_PUSH(4, h4, w1.x); MCLG_PUSH(5, h5, w1.y); MCLG_PUSH(6, h6, w1.z); MCLG_PUSH(7, h7, w1.w);
 #undef MCLG_PUSH
@@ -421,10 +432,11 @@ __device__ __forceinline__ void decide_eight(uint4 &w0, uint4 &w1, uint2 key,
 
 // Without collisions only a site whose N does not fit 16 bits is queued
 // (the drain flags it and keeps its counts).
+template <bool PATCH>
 __device__ __forceinline__ void queue_saturated(const uint32_t (&va)[4], const uint32_t (&vb)[4],
                                                 const uint32_t (&vc)[4], uint4 *queue,
                                                 Rsrc over, uint32_t &F, bool slow,
-                                                uint32_t x8, uint32_t L) {
+                                                uint32_t x8, uint32_t L, uint32_t xs) {
 #define MCLG_SAT(J)                                                                              \
   {                                                                                              \
     const uint32_t N2 = __builtin_bit_cast(                                                      \
@@ -432,10 +444,10 @@ __device__ __forceinline__ void queue_saturated(const uint32_t (&va)[4], const u
                       __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, va[J]),            \
                                                     __builtin_bit_cast(u16x2, vb[J])),           \
                       __builtin_bit_cast(u16x2, vc[J])));                                        \
-    push_site<2 * J>(queue, over, F, (N2 & 0xffffu) != 0xffffu, slow, x8, L, va[J], vb[J],      \
-                     vc[J], 0u);                                                                 \
-    push_site<2 * J + 1>(queue, over, F, (N2 >> 16) != 0xffffu, slow, x8, L, va[J], vb[J],      \
-                         vc[J], 0u);                                                             \
+    push_site<2 * J, PATCH>(queue, over, F, (N2 & 0xffffu) != 0xffffu, slow, x8, L, va[J],      \
+                            vb[J], vc[J], 0u, xs);                                               \
+    push_site<2 * J + 1, PATCH>(queue, over, F, (N2 >> 16) != 0xffffu, slow, x8, L, va[J],      \
+                                vb[J], vc[J], 0u, xs);                                           \
   }
   MCLG_SAT(0) MCLG_SAT(1) MCLG_SAT(2) MCLG_SAT(3)
 #undef MCLG_SAT
@@ -468,6 +480,72 @@ __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *ove
     bstore2(v.rs(), 2u * pp, 2u * v.ab, (uint32_t)((N - (int32_t)bn + J) >> 1));
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The move decide_eight applied to one undecided site (a, b, c; draw r):
+// the same directory and record reads from the LDS image, one site in
+// 32-bit arithmetic with the 16-bit wrap-around of the packed form.
+__device__ __forceinline__ uint32_t image_move(uint32_t a, uint32_t b, uint32_t c, uint32_t r,
+                                               const LdsView &lv) {
+  const uint32_t lo = min(min(a, c), lv.da2 & 0xffffu), hi = min(max(a, c), lv.dc2 & 0xffffu);
+  const uint32_t slot = (lo * (lv.w2 & 0xffffu) + hi) & 0xffffu;
+  const uint32_t row = lds_u16((2u * slot) & 0xffffu);
+  const uint32_t bi = min((b - (lv.blo2 & 0xffffu)) & 0xffffu, lv.nb2 & 0xffffu);
+  SiteLook sl;
+  sl.q = lds_u4(((row + bi) & 0xffffu) << 4);
+  bool hit;
+  return site_finish(sl, r, hit) & 0xffffu;
+}
+
+// Resolve the draws queued by the current chunk before its store
+// (kDrainPatch): each lane takes one entry at a time, finds the exact outcome
+// and writes the correction of the move the site's lane applied (found again
+// from the image), as a 16-bit patch at the site's position; the LDS queue's
+// 1 KB holds the chunk's 512 patches once its entries have been read.  Every
+// lane then adds its eight patches to its counts (zero for decided sites), so
+// the chunk's vector stores write the final counts.
+template <bool GAL>
+__device__ __forceinline__ void patch_chunk(uint4 *queue, const uint4 *over, uint32_t F,
+                                            uint32_t lane, uint32_t xs, const SlotView &v,
+                                            const LdsView &lv, const StepParams &p,
+                                            const TableDev &tab, uint32_t *err, uint32_t (&m)[4],
+                                            uint32_t (&z)[4], uint32_t (&c)[4]) {
+  if (F > kQueue) {
+    // entries past the LDS queue were written to global memory by other
+    // lanes: wait for those stores before reading them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  const uint4 e0 = lane < F ? queue[lane] : make_uint4(0u, 0u, 0u, 0u);
+  // each lane clears its own 16 bytes (its eight sites' patches) after
+  // reading the entry stored there
+  queue[lane] = make_uint4(0u, 0u, 0u, 0u);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint16_t *const patch = reinterpret_cast<uint16_t *>(queue);
+  for (uint32_t i = lane; i < F; i += 64u) {
+    uint4 e = i < kQueue ? e0 : over[i - kQueue];
+    const uint32_t pos = e.x, b = e.y >> 16;
+    // C = 0 queues only overflowing sites and applies no move
+    const uint32_t dw = p.C != 0 ? image_move(e.y & 0xffffu, b, e.z, e.w, lv) : 0u;
+    e.x = xs + pos;
+    const uint32_t bn = resolve_queued<GAL>(e, p, tab, v.t, v.rid, err);
+    const uint32_t d = (uint32_t)(((int32_t)b - (int32_t)bn) >> 1);
+    patch[pos] = (uint16_t)(d - dw);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint4 pv = queue[lane];
+  apply_pair(m[0], z[0], c[0], pv.x);
+  apply_pair(m[1], z[1], c[1], pv.y);
+  apply_pair(m[2], z[2], c[2], pv.z);
+  apply_pair(m[3], z[3], c[3], pv.w);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -549,8 +627,9 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 // update has no races.  Undecided draws wait in the wave's queue, which is
 // drained between chunks once it nears capacity, and at the end of the
 // slot's segment.
-template <int MAXT, bool GAL, bool EAGER>
+template <int MAXT, bool GAL, int MODE>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
+  constexpr bool PATCH = MODE == kDrainPatch;
   extern __shared__ uint4 lds[];
   const StepParams &p = a.p;
   const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
@@ -597,7 +676,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
         t0 = a.tiles[i];
       }
     }
-    if (F && (i >= ce || t0.slot != cur)) {  // queued draws belong to slot `cur`
+    if (!PATCH && F && (i >= ce || t0.slot != cur)) {  // queued draws belong to slot `cur`
       drain_queue<GAL>(queue, over, F, lane, sv, p, a.tab, a.err);
       F = 0;
     }
@@ -685,9 +764,17 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
         if (p.C != 0) {
           uint4 w0 = make_uint4(x8 >> 2, t, sv.rid, 0u);
           uint4 w1 = make_uint4((x8 >> 2) + 1u, t, sv.rid, 0u);
-          decide_eight(w0, w1, key, cur.m, cur.z, cur.p, lv, queue, ovr, F, slow, x8, L);
+          decide_eight<PATCH>(w0, w1, key, cur.m, cur.z, cur.p, lv, queue, ovr, F, slow, x8, L,
+                              cw.xs);
         } else {
-          queue_saturated(cur.m, cur.z, cur.p, queue, ovr, F, slow, x8, L);
+          queue_saturated<PATCH>(cur.m, cur.z, cur.p, queue, ovr, F, slow, x8, L, cw.xs);
+        }
+        if constexpr (PATCH) {
+          if (F) {
+            patch_chunk<GAL>(queue, over, F, lane, cw.xs, sv, lv, p, a.tab, a.err, cur.m,
+                             cur.z, cur.p);
+            F = 0;
+          }
         }
       }
 
@@ -716,9 +803,9 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       cw = nw;
       k = nk;
       // At most kDrainAt draws stay queued, so the next chunk's 64 x 8
-      // always fit; EAGER (a state larger than the caches) resolves every
-      // chunk's draws while its lines are still in the L2.
-      if (has_next && F > (EAGER ? 0u : kDrainAt)) {
+      // always fit; kDrainChunk resolves every chunk's draws while its lines
+      // are still in the L2 (kDrainPatch has none left here).
+      if (!PATCH && has_next && F > (MODE == kDrainChunk ? 0u : kDrainAt)) {
         drain_queue<GAL>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
       }
@@ -788,80 +875,12 @@ __global__ void __launch_bounds__(256) k_init_counts(uint16_t *__restrict__ stat
       state[sl.off + (uint64_t)i * sl.stride + x] = src[(uint64_t)i * sl.L + x];
 }
 
-__global__ void k_zero(unsigned long long *p, uint64_t n) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0ull;
-}
-
 __global__ void k_add_t(uint32_t *tslot, uint32_t slot_first, uint32_t n, uint32_t add) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
     tslot[slot_first + k] += add;
 }
 __global__ void k_set_t(uint32_t *tslot, const uint32_t *slot_list, uint32_t n, uint32_t value) {
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) tslot[slot_list[i]] = value;
-}
-
-constexpr int kMomVals = 14 + 2 * 8;
-
-// Exact integer sums of one tile (logical site order), reduced over the
-// wave with shuffles, over the block in LDS, then one atomic per value.
-__global__ void __launch_bounds__(256) k_moments(
-    const uint16_t *__restrict__ state, const SlotDev *__restrict__ slots,
-    const uint32_t *__restrict__ tslot, const TileDev *__restrict__ tiles, uint32_t tile_sites,
-    uint32_t no_stream, const int32_t *__restrict__ twiddle, uint32_t n_modes,
-    MomDev *__restrict__ out) {
-  const TileDev tile = tiles[blockIdx.x];
-  const SlotDev sl = slots[tile.slot];
-  const uint32_t L = sl.L;
-  const uint32_t tm = no_stream ? 0u : tslot[tile.slot] % L;
-  const uint16_t *nm = state + sl.off;
-  const uint16_t *n0 = nm + sl.stride;
-  const uint16_t *np = n0 + sl.stride;
-  const int32_t *tw = twiddle ? twiddle + 2ull * n_modes * sl.dense : nullptr;
-  unsigned long long v[kMomVals];
-#pragma unroll
-  for (int i = 0; i < kMomVals; ++i) v[i] = 0ull;
-  const uint32_t end = min(L, tile.x0 + tile_sites);
-  for (uint32_t x = tile.x0 + threadIdx.x; x < end; x += blockDim.x) {
-    uint32_t pm = x + tm;
-    pm -= (pm >= L) ? L : 0u;
-    const uint32_t pp = x >= tm ? x - tm : x + L - tm;
-    const unsigned long long a = nm[pm], b = n0[x], c = np[pp];
-    const unsigned long long N = a + b + c;
-    v[0] += a; v[1] += b; v[2] += c;
-    v[3] += a * a; v[4] += b * b; v[5] += c * c;
-    v[6] += a * b; v[7] += b * c; v[8] += a * c;
-    v[9] += N;
-    v[10] += c - a;
-    v[11] += N * N;
-    v[12] += b & 1ull;
-    v[13] = v[13] > N ? v[13] : N;
-    for (uint32_t m = 0; m < n_modes; ++m) {
-      v[14 + 2 * m] += N * (unsigned long long)(long long)tw[(2ull * m) * L + x];
-      v[15 + 2 * m] += N * (unsigned long long)(long long)tw[(2ull * m + 1) * L + x];
-    }
-  }
-  __shared__ unsigned long long red[16][kMomVals];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < kMomVals; ++i) {
-    unsigned long long x = v[i];
-    for (int m = 32; m >= 1; m >>= 1) {
-      const unsigned long long y = shfl_xor_u64(x, m);
-      x = (i == 13) ? (x > y ? x : y) : x + y;
-    }
-    if (lane == 0) red[wave][i] = x;
-  }
-  __syncthreads();
-  const int nw = (blockDim.x + 63) >> 6;
-  if (threadIdx.x < kMomVals) {
-    const int i = threadIdx.x;
-    unsigned long long s = 0ull;
-    for (int w = 0; w < nw; ++w) s = (i == 13) ? (s > red[w][i] ? s : red[w][i]) : s + red[w][i];
-    if (i == 13) atomicMax(&out[tile.slot].v[13], s);
-    else if (i < 14 + 2 * (int)n_modes) atomicAdd(&out[tile.slot].v[i], s);
-  }
 }
 
 // Occupation-number histograms.  Each block takes a contiguous run of tiles
@@ -914,25 +933,30 @@ __global__ void __launch_bounds__(256) k_histogram(
 
 }  // namespace
 
-// Sets the dynamic LDS limit of the four instantiations for this block size
+// Sets the dynamic LDS limit of the six instantiations for this block size
 // and returns the smallest of their occupancies.
-template <int MAXT, bool GAL, bool EAGER>
+template <int MAXT, bool GAL, int MODE>
 static hipError_t occupancy_one(uint32_t threads, uint32_t lds, int &blocks) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<MAXT, GAL, EAGER>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step<MAXT, GAL, MODE>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
   int b = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step<MAXT, GAL, EAGER>, (int)threads, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step<MAXT, GAL, MODE>, (int)threads, lds);
   blocks = std::min(blocks, b);
+  return e;
+}
+template <int MAXT, bool GAL>
+static hipError_t occupancy_modes(uint32_t threads, uint32_t lds, int &blocks) {
+  hipError_t e = occupancy_one<MAXT, GAL, kDrainDeferred>(threads, lds, blocks);
+  if (!e) e = occupancy_one<MAXT, GAL, kDrainChunk>(threads, lds, blocks);
+  if (!e) e = occupancy_one<MAXT, GAL, kDrainPatch>(threads, lds, blocks);
   return e;
 }
 template <int MAXT>
 static hipError_t occupancy_of(uint32_t threads, uint32_t lds, int &blocks) {
   blocks = 1 << 30;
-  hipError_t e = occupancy_one<MAXT, false, false>(threads, lds, blocks);
-  if (!e) e = occupancy_one<MAXT, false, true>(threads, lds, blocks);
-  if (!e) e = occupancy_one<MAXT, true, false>(threads, lds, blocks);
-  if (!e) e = occupancy_one<MAXT, true, true>(threads, lds, blocks);
+  hipError_t e = occupancy_modes<MAXT, false>(threads, lds, blocks);
+  if (!e) e = occupancy_modes<MAXT, true>(threads, lds, blocks);
   return e;
 }
 
@@ -954,28 +978,28 @@ hipError_t step_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu
   return hipSuccess;
 }
 
+template <int MAXT, bool GAL>
+static void launch_mode(dim3 grid, dim3 block, uint32_t lds, hipStream_t s, const StepLaunch &a) {
+  switch (a.p.drain) {
+    case kDrainChunk: k_step<MAXT, GAL, kDrainChunk><<<grid, block, lds, s>>>(a); break;
+    case kDrainPatch: k_step<MAXT, GAL, kDrainPatch><<<grid, block, lds, s>>>(a); break;
+    default: k_step<MAXT, GAL, kDrainDeferred><<<grid, block, lds, s>>>(a); break;
+  }
+}
+
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) {
   if (a.n_tiles == 0) return hipSuccess;
   dim3 grid(std::max<uint32_t>(1, std::min(a.n_tiles, a.max_blocks))), block(sch.threads);
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
   if (sch.groups != 1) return hipErrorInvalidValue;
-  const bool small = sch.threads <= 512, eager = a.p.drain_at == 0;
+  if (a.p.drain > kDrainPatch) return hipErrorInvalidValue;
+  const bool small = sch.threads <= 512;
   if (a.p.galilean) {
-    if (eager) {
-      if (small) k_step<512, true, true><<<grid, block, lds, s>>>(a);
-      else k_step<1024, true, true><<<grid, block, lds, s>>>(a);
-    } else {
-      if (small) k_step<512, true, false><<<grid, block, lds, s>>>(a);
-      else k_step<1024, true, false><<<grid, block, lds, s>>>(a);
-    }
+    if (small) launch_mode<512, true>(grid, block, lds, s, a);
+    else launch_mode<1024, true>(grid, block, lds, s, a);
   } else {
-    if (eager) {
-      if (small) k_step<512, false, true><<<grid, block, lds, s>>>(a);
-      else k_step<1024, false, true><<<grid, block, lds, s>>>(a);
-    } else {
-      if (small) k_step<512, false, false><<<grid, block, lds, s>>>(a);
-      else k_step<1024, false, false><<<grid, block, lds, s>>>(a);
-    }
+    if (small) launch_mode<512, false>(grid, block, lds, s, a);
+    else launch_mode<1024, false>(grid, block, lds, s, a);
   }
   return hipGetLastError();
 }
@@ -994,23 +1018,6 @@ hipError_t launch_init_counts(hipStream_t s, uint16_t *state, const SlotDev *slo
                               const uint16_t *counts) {
   if (n_tiles == 0) return hipSuccess;
   k_init_counts<<<n_tiles, 256, 0, s>>>(state, slots, tiles, tile_sites, counts);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero(hipStream_t s, unsigned long long *p, uint64_t n) {
-  if (n == 0) return hipSuccess;
-  uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 1024);
-  k_zero<<<blocks, 256, 0, s>>>(p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_moments(hipStream_t s, const uint16_t *state, const SlotDev *slots,
-                          const uint32_t *tslot, const TileDev *tiles, uint32_t n_tiles,
-                          uint32_t tile_sites, uint32_t no_stream, const int32_t *twiddle,
-                          uint32_t n_modes, MomDev *out) {
-  if (n_tiles == 0) return hipSuccess;
-  k_moments<<<n_tiles, 256, 0, s>>>(state, slots, tslot, tiles, tile_sites, no_stream, twiddle,
-                                    n_modes, out);
   return hipGetLastError();
 }
 

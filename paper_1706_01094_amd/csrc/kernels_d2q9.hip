@@ -232,64 +232,6 @@ __global__ void __launch_bounds__(256) k_histogram9(const uint16_t *__restrict__
   flush(cur);
 }
 
-// Exact sums of one tile in logical site order, reduced over the wave with
-// shuffles, over the block in LDS, then one atomic per value.
-__global__ void __launch_bounds__(256) k_moments9(const uint16_t *__restrict__ state,
-                                                  const Rep9 *__restrict__ reps,
-                                                  const Tile9 *__restrict__ tiles, uint64_t t,
-                                                  uint32_t no_stream,
-                                                  unsigned long long *__restrict__ out) {
-  __shared__ unsigned long long red[4][kMom9Vals];
-  const Tile9 tile = tiles[blockIdx.x];
-  const Rep9 rp = reps[tile.rep];
-  const uint32_t s = tile.s0 + threadIdx.x;
-  uint32_t n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (s < rp.S) {
-    const uint32_t y = s / rp.Lx, x = s - y * rp.Lx;
-    const uint32_t tx = no_stream ? 0u : (uint32_t)(t % rp.Lx);
-    const uint32_t ty = no_stream ? 0u : (uint32_t)(t % rp.Ly);
-    const Site9 ph(s, x, tx, ty, rp.Lx, rp.S);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) n[i] = state[rp.off + (uint64_t)i * rp.stride + ph.e[i]];
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t q = 0;
-  auto put = [&](unsigned long long v, bool is_max) {
-    for (int m = 32; m >= 1; m >>= 1) {
-      const unsigned long long o = shfl_xor_u64(v, m);
-      v = is_max ? (v > o ? v : o) : v + o;
-    }
-    if (lane == 0) red[wave][q] = v;
-    ++q;
-  };
-  long long N = 0, jx = 0, jy = 0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    N += n[i];
-    jx += kV9x[i] * (long long)n[i];
-    jy += kV9y[i] * (long long)n[i];
-  }
-#pragma unroll
-  for (int i = 0; i < 9; ++i) put(n[i], false);
-#pragma unroll
-  for (int i = 0; i < 9; ++i)
-#pragma unroll
-    for (int j = i; j < 9; ++j) put((unsigned long long)n[i] * n[j], false);
-  put((unsigned long long)N, false);
-  put((unsigned long long)jx, false);
-  put((unsigned long long)jy, false);
-  put((unsigned long long)N, true);
-  __syncthreads();
-  const int nw = (blockDim.x + 63) >> 6;
-  for (uint32_t v = threadIdx.x; v < kMom9Vals; v += blockDim.x) {
-    const bool is_max = v == kMom9Vals - 1;
-    unsigned long long acc = 0ull;
-    for (int w = 0; w < nw; ++w) acc = is_max ? (acc > red[w][v] ? acc : red[w][v]) : acc + red[w][v];
-    if (is_max) atomicMax(&out[(uint64_t)tile.rep * kMom9Vals + v], acc);
-    else atomicAdd(&out[(uint64_t)tile.rep * kMom9Vals + v], acc);
-  }
-}
-
 }  // namespace
 
 hipError_t launch_step9(hipStream_t s, const Step9 &a, uint32_t n_tiles) {
@@ -321,14 +263,6 @@ hipError_t launch_histogram9(hipStream_t s, const uint16_t *state, const Rep9 *r
   const uint32_t blocks = std::min<uint32_t>(n_tiles, 2048u);
   k_histogram9<<<blocks, 256, 9u * n_bins * sizeof(uint32_t), s>>>(state, reps, tiles, n_tiles,
                                                                    n_bins, hist);
-  return hipGetLastError();
-}
-
-hipError_t launch_moments9(hipStream_t s, const uint16_t *state, const Rep9 *reps,
-                           const Tile9 *tiles, uint32_t n_tiles, uint64_t t, uint32_t no_stream,
-                           unsigned long long *out) {
-  if (n_tiles == 0) return hipSuccess;
-  k_moments9<<<n_tiles, 256, 0, s>>>(state, reps, tiles, t, no_stream, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,72 @@
+// Exact moment sums of the MCLG state (D1Q3 and D2Q9): per-segment partial
+// sums written by one kernel, combined per replica by a second one.  Every
+// sum is an integer sum modulo 2^64, so the result does not depend on how
+// the sites are split.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "device.h"
+
+namespace mclg {
+
+// Sites [x0, x1) of slot `slot` (D2Q9: sites s = y Lx + x of replica `slot`).
+struct MomSeg {
+  uint32_t slot = 0, x0 = 0, x1 = 0, pad = 0;
+};
+
+// The moment kernels' work for a list of slots: the segments of slot
+// list[j] are segs[run_seg[j] .. run_seg[j + 1]).
+struct MomPlan {
+  std::vector<MomSeg> segs;
+  std::vector<uint32_t> run_seg;   // runs + 1
+  std::vector<uint32_t> run_slot;  // runs
+};
+
+// Segments of at least 8192 sites (a multiple of 2048) and about 4096 of them
+// in all, so that at most 4096 + n segments are made for n slots.
+constexpr uint32_t kMomMaxSegsBase = 4096;
+MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n);
+inline uint64_t max_mom_segs(uint32_t n) { return kMomMaxSegsBase + n; }
+
+// Partial record of one D1Q3 segment: kMom3Rec uint64.  Slots 0-2 sum n_i,
+// 3-5 sum n_i^2, 6-8 sum n_-1 n_0, n_0 n_+1, n_-1 n_+1, 9 sites with odd
+// n_0, 10 the state digest, 11 + 2m and 12 + 2m the Fourier sums of mode m,
+// 31 max N.
+constexpr uint32_t kMom3Rec = 32;
+// One replica's result in the field order of mclg_moments_t (33 int64).
+constexpr uint32_t kMom3Out = 33;
+// Partial record of one D2Q9 segment: slots 0-8 sum n_i, 9-53 sum n_i n_j
+// (i <= j, row-major), 63 max N.
+constexpr uint32_t kMom9Rec = 64;
+// One replica's result in the field order of mclg_moments9_t (60 int64).
+constexpr uint32_t kMom9Out = 60;
+
+// Where the kernels of one moments call read and write.
+struct MomArgs {
+  const uint16_t *state = nullptr;
+  const SlotDev *slots = nullptr;    // D1Q3
+  const Rep9 *reps = nullptr;        // D2Q9
+  const uint32_t *tslot = nullptr;   // D1Q3: per-slot step counters
+  uint64_t t9 = 0;                   // D2Q9: steps taken
+  uint32_t no_stream = 0;
+  const MomSeg *segs = nullptr;
+  uint32_t n_segs = 0;
+  const uint32_t *run_seg = nullptr, *run_slot = nullptr;
+  uint32_t n_runs = 0;
+  const int32_t *twiddle = nullptr;  // D1Q3: [2 n_modes][L] per slot from its dense offset
+  uint32_t n_modes = 0;
+  uint32_t digest = 0;               // D1Q3: also sum the state digest
+  unsigned long long *partial = nullptr;  // n_segs records
+  // run j's result goes to out[out_index * kMom*Out]: out_index = j, or the
+  // run's slot when by_slot is set
+  long long *out = nullptr;
+  uint32_t by_slot = 0;
+};
+
+hipError_t launch_moments3(hipStream_t s, const MomArgs &a);
+hipError_t launch_moments9(hipStream_t s, const MomArgs &a);
+
+}  // namespace mclg

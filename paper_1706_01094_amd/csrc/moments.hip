@@ -1,0 +1,536 @@
+// Exact moment sums of the MCLG state: the observables of the paper's
+// statistics -- sums of n_i and n_i n_j for the Poisson and correlation
+// checks (Eq. (poisson), Eq. (corr)), N and J for the conserved mass and
+// momentum, Fourier projections of the density for the decaying density wave
+// (Eq. (A)) and S(k) -- plus a digest of the whole state for comparing runs.
+//
+// One block per segment of a slot's sites accumulates in registers (each
+// lane eight consecutive sites per pass, 16-byte loads from the shifted
+// layout), reduces its sums once, and writes one partial record; a second
+// kernel adds a replica's records.  No atomics, nothing to clear, and the
+// result is independent of the split (integer sums modulo 2^64).
+#include "moments.h"
+#include "rng.h"
+
+#include <algorithm>
+
+namespace mclg {
+namespace {
+
+typedef unsigned long long u64;
+typedef long long i64;
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ void load16(Rsrc r, uint32_t off, uint32_t (&v)[4]) {
+  const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+}
+__device__ __forceinline__ uint32_t load2(Rsrc r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+
+// MurmurHash3's 32-bit finaliser (Appleby): a bijective mix of 32 bits.
+__device__ __forceinline__ uint32_t fmix32(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x85ebca6bu;
+  k ^= k >> 13;
+  k *= 0xc2b2ae35u;
+  k ^= k >> 16;
+  return k;
+}
+
+// Reduce-scatter of V (a power of two up to 64) 64-bit sums over the 64
+// lanes of a wave: each level exchanges half of the values with the lane
+// whose id differs in one bit and adds, so V - 1 exchanges move what V x 6
+// would in a plain butterfly.  Afterwards lane l holds the wave's total of
+// value l >> (6 - log2 V).
+template <int V>
+__device__ __forceinline__ u64 wave_sum_scatter(u64 (&v)[V], uint32_t lane) {
+  int w = V, m = 32;
+#pragma unroll
+  for (int lvl = 0; (1 << lvl) < V; ++lvl) {
+    const bool up = (lane & (uint32_t)m) != 0;
+    const int h = w >> 1;
+#pragma unroll
+    for (int j = 0; j < V / 2; ++j) {
+      if (j < h) {
+        const u64 send = up ? v[j] : v[j + h];
+        const u64 keep = up ? v[j + h] : v[j];
+        v[j] = keep + shfl_xor_u64(send, m);
+      }
+    }
+    w = h;
+    m >>= 1;
+  }
+  u64 s = v[0];
+#pragma unroll
+  for (; m >= 1; m >>= 1) s += shfl_xor_u64(s, m);
+  return s;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, (uint32_t)__shfl_xor(v, m));
+  return v;
+}
+
+// Block-wide combination of the lanes' sums and maxima into one partial
+// record of REC values: sums of values 0 .. V-1 in record slots 0 .. V-1,
+// zero in V .. REC-2, the maximum in slot REC-1.
+template <int V, int REC>
+__device__ __forceinline__ void write_partial(u64 (&v)[V], uint32_t mx, u64 *rec) {
+  __shared__ u64 red[16][V];
+  __shared__ uint32_t redmx[16];
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  constexpr int sh = V >= 64 ? 0 : V >= 32 ? 1 : V >= 16 ? 2 : V >= 8 ? 3 : V >= 4 ? 4 : 5;
+  const u64 s = wave_sum_scatter<V>(v, lane);
+  mx = wave_max(mx);
+  if ((lane & ((1u << sh) - 1u)) == 0u) red[wave][lane >> sh] = s;
+  if (lane == 0) redmx[wave] = mx;
+  __syncthreads();
+  const uint32_t nw = blockDim.x >> 6;
+  for (uint32_t k = threadIdx.x; k < (uint32_t)REC; k += blockDim.x) {
+    u64 out = 0;
+    if (k == REC - 1) {
+      uint32_t m = 0;
+      for (uint32_t w = 0; w < nw; ++w) m = max(m, redmx[w]);
+      out = m;
+    } else if (k < (uint32_t)V) {
+      for (uint32_t w = 0; w < nw; ++w) out += red[w][k];
+    }
+    rec[k] = out;
+  }
+}
+
+// ---- D1Q3 ----------------------------------------------------------------
+// The eight sites x .. x+7 of a lane in logical order: n_-1 from physical
+// (x + tm) mod L, n_0 from x, n_+1 from (x - tm) mod L, two sites per 32-bit
+// word; sites at or past L read as zero.  Returns how many of the eight exist.
+__device__ __forceinline__ uint32_t load_eight(Rsrc rs, uint32_t ab, uint32_t L, uint32_t tm,
+                                               uint32_t x, uint32_t (&va)[4], uint32_t (&vb)[4],
+                                               uint32_t (&vc)[4]) {
+  uint32_t pm = x + tm;
+  pm -= (pm >= L) ? L : 0u;
+  const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+  if (x + 8u <= L && pm + 8u <= L && pp + 8u <= L) {
+    load16(rs, 2u * pm, va);
+    load16(rs, ab + 2u * x, vb);
+    load16(rs, 2u * ab + 2u * pp, vc);
+    return 8u;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) va[j] = vb[j] = vc[j] = 0u;
+#pragma unroll
+  for (uint32_t e = 0; e < 8u; ++e) {
+    const uint32_t xe = x + e;
+    if (xe < L) {
+      uint32_t m = xe + tm;
+      m -= (m >= L) ? L : 0u;
+      const uint32_t p = xe >= tm ? xe - tm : xe + L - tm;
+      const uint32_t sh = 16u * (e & 1u);
+      va[e >> 1] |= load2(rs, 2u * m) << sh;
+      vb[e >> 1] |= load2(rs, ab + 2u * xe) << sh;
+      vc[e >> 1] |= load2(rs, 2u * ab + 2u * p) << sh;
+    }
+  }
+  return x < L ? min(8u, L - x) : 0u;
+}
+
+// Accumulators of one lane (record slots 0 .. 10 + 2 NM, max N apart).
+template <int NM>
+struct Acc3 {
+  u64 s[11 + 2 * NM];
+  uint32_t mx;
+};
+
+template <int NM, bool DIG>
+__device__ __forceinline__ void add_eight(Acc3<NM> &A, const uint32_t (&va)[4],
+                                          const uint32_t (&vb)[4], const uint32_t (&vc)[4],
+                                          uint32_t x, uint32_t nvalid, const int32_t *tw,
+                                          uint32_t L) {
+  uint32_t sa = 0, sb = 0, sc = 0, odd = 0;
+  uint32_t Ns[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a0 = va[j] & 0xffffu, a1 = va[j] >> 16;
+    const uint32_t b0 = vb[j] & 0xffffu, b1 = vb[j] >> 16;
+    const uint32_t c0 = vc[j] & 0xffffu, c1 = vc[j] >> 16;
+    sa += a0 + a1;
+    sb += b0 + b1;
+    sc += c0 + c1;
+    A.s[3] += (u64)a0 * a0 + (u64)a1 * a1;
+    A.s[4] += (u64)b0 * b0 + (u64)b1 * b1;
+    A.s[5] += (u64)c0 * c0 + (u64)c1 * c1;
+    A.s[6] += (u64)a0 * b0 + (u64)a1 * b1;
+    A.s[7] += (u64)b0 * c0 + (u64)b1 * c1;
+    A.s[8] += (u64)a0 * c0 + (u64)a1 * c1;
+    odd += __popc(vb[j] & 0x00010001u);
+    Ns[2 * j] = a0 + b0 + c0;
+    Ns[2 * j + 1] = a1 + b1 + c1;
+    A.mx = max(A.mx, max(Ns[2 * j], Ns[2 * j + 1]));
+    if constexpr (DIG) {
+      // digest: sum over existing sites and velocities of
+      // fmix32(fmix32(4 x + i + 1) ^ n_i(x)), i = 0, 1, 2 for v = -1, 0, +1
+      const uint32_t k0 = 4u * (x + 2u * j) + 1u, k1 = k0 + 4u;
+      u64 d = 0;
+      if (2u * j < nvalid)
+        d += (u64)fmix32(fmix32(k0) ^ a0) + fmix32(fmix32(k0 + 1u) ^ b0) +
+             fmix32(fmix32(k0 + 2u) ^ c0);
+      if (2u * j + 1u < nvalid)
+        d += (u64)fmix32(fmix32(k1) ^ a1) + fmix32(fmix32(k1 + 1u) ^ b1) +
+             fmix32(fmix32(k1 + 2u) ^ c1);
+      A.s[10] += d;
+    }
+  }
+  A.s[0] += sa;
+  A.s[1] += sb;
+  A.s[2] += sc;
+  A.s[9] += odd;
+  if constexpr (NM > 0) {
+    // twiddle rows of the slot: row r at tw + r L (4-byte aligned); one mode
+    // (two rows) at a time, so that at most 16 of their values are live
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      int32_t w[2][8];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t *row = tw + (uint64_t)(2 * m + h) * L + x;
+        if (nvalid == 8u) {
+          __builtin_memcpy(&w[h][0], row, 16);
+          __builtin_memcpy(&w[h][4], row + 4, 16);
+        } else {
+#pragma unroll
+          for (uint32_t e = 0; e < 8u; ++e) w[h][e] = e < nvalid ? row[e] : 0;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        i64 f = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f += (i64)(int32_t)Ns[e] * (i64)w[h][e];
+        A.s[11 + 2 * m + h] += (u64)f;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int NM, bool DIG>
+__global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state,
+                                              const SlotDev *__restrict__ slots,
+                                              const uint32_t *__restrict__ tslot,
+                                              const MomSeg *__restrict__ segs, uint32_t no_stream,
+                                              const int32_t *__restrict__ twiddle,
+                                              u64 *__restrict__ partial) {
+  const MomSeg sg = segs[blockIdx.x];
+  const SlotDev sl = slots[sg.slot];
+  const uint32_t L = sl.L;
+  const uint32_t tm = no_stream ? 0u : tslot[sg.slot] % L;
+  const Rsrc rs = make_rsrc(state + sl.off, 6u * sl.stride);
+  const uint32_t ab = 2u * sl.stride;
+  const int32_t *tw = NM > 0 ? twiddle + 2ull * NM * sl.dense : nullptr;
+  Acc3<NM> A;
+#pragma unroll
+  for (int k = 0; k < 11 + 2 * NM; ++k) A.s[k] = 0;
+  A.mx = 0;
+  const uint32_t step = 8u * blockDim.x;
+  uint32_t x = sg.x0 + 8u * threadIdx.x;
+  // without twiddle rows, two passes' loads are in flight before either is
+  // summed
+  if constexpr (NM == 0)
+  for (; x + step < sg.x1; x += 2u * step) {
+    uint32_t a0[4], b0[4], c0[4], a1[4], b1[4], c1[4];
+    const uint32_t n0 = load_eight(rs, ab, L, tm, x, a0, b0, c0);
+    const uint32_t n1 = load_eight(rs, ab, L, tm, x + step, a1, b1, c1);
+    add_eight<NM, DIG>(A, a0, b0, c0, x, n0, tw, L);
+    add_eight<NM, DIG>(A, a1, b1, c1, x + step, n1, tw, L);
+  }
+  for (; x < sg.x1; x += step) {
+    uint32_t a0[4], b0[4], c0[4];
+    const uint32_t n0 = load_eight(rs, ab, L, tm, x, a0, b0, c0);
+    add_eight<NM, DIG>(A, a0, b0, c0, x, n0, tw, L);
+  }
+  constexpr int V = 11 + 2 * NM <= 16 ? 16 : 32;
+  u64 v[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) v[k] = k < 11 + 2 * NM ? A.s[k < 11 + 2 * NM ? k : 0] : 0ull;
+  write_partial<V, kMom3Rec>(v, A.mx, partial + (uint64_t)blockIdx.x * kMom3Rec);
+}
+
+// Adds the partial records of each run (one block per run) and writes the
+// replica's result in the field order of mclg_moments_t: t (the device step
+// counter), sites, sum n_i, sum n_i^2, sum n_i n_j, sum N = sum of the three
+// sums, sum J = sum n_+1 - sum n_-1, sum N^2 = sum n_i^2 + 2 sum n_i n_j,
+// sites with odd n_0, max N, Fourier sums, digest.
+__global__ void __launch_bounds__(64) k_mom3_final(const u64 *__restrict__ partial,
+                                                   const uint32_t *__restrict__ run_seg,
+                                                   const uint32_t *__restrict__ run_slot,
+                                                   const SlotDev *__restrict__ slots,
+                                                   const uint32_t *__restrict__ tslot,
+                                                   uint32_t by_slot, i64 *__restrict__ out) {
+  __shared__ u64 tot[kMom3Rec];
+  const uint32_t j = blockIdx.x, k = threadIdx.x;
+  const uint32_t s0 = run_seg[j], s1 = run_seg[j + 1], slot = run_slot[j];
+  if (k < kMom3Rec) {
+    u64 acc = 0;
+    for (uint32_t s = s0; s < s1; ++s) {
+      const u64 v = partial[(uint64_t)s * kMom3Rec + k];
+      acc = k == kMom3Rec - 1 ? (acc > v ? acc : v) : acc + v;
+    }
+    tot[k] = acc;
+  }
+  __syncthreads();
+  if (k == 0) {
+    i64 *o = out + (uint64_t)(by_slot ? slot : j) * kMom3Out;
+    const u64 *T = tot;
+    o[0] = (i64)tslot[slot];
+    o[1] = (i64)slots[slot].L;
+    for (int i = 0; i < 9; ++i) o[2 + i] = (i64)T[i];
+    o[11] = (i64)(T[0] + T[1] + T[2]);
+    o[12] = (i64)(T[2] - T[0]);
+    o[13] = (i64)(T[3] + T[4] + T[5] + 2ull * (T[6] + T[7] + T[8]));
+    o[14] = (i64)T[9];
+    o[15] = (i64)T[31];
+    for (int i = 0; i < 16; ++i) o[16 + i] = (i64)T[11 + i];
+    o[32] = (i64)T[10];
+  }
+}
+
+// ---- D2Q9 ----------------------------------------------------------------
+__constant__ int32_t kVx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int32_t kVy9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// One block per segment of a replica's sites s = y Lx + x, one site per lane
+// and pass: logical n_i(x, y, t) is at physical ((x - vx t) mod Lx,
+// (y - vy t) mod Ly), so a wave's 64 consecutive sites read mostly
+// consecutive elements of each array.  The lane walks its sites with
+// (x, y) advanced by the block's stride, no division per site.  The 54 sums
+// are kept in 32 bits: a lane adds at most 2^16 sites (segments hold at
+// most 2^24 sites), so the sums of n_i fit, and so do the sums of products
+// of sites whose nine counts are all below 256; a site with a larger count
+// adds its products to 64-bit sums in LDS instead.
+__global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state,
+                                              const Rep9 *__restrict__ reps, uint64_t t,
+                                              uint32_t no_stream,
+                                              const MomSeg *__restrict__ segs,
+                                              u64 *__restrict__ partial) {
+  __shared__ u64 big[45];
+  __shared__ u64 red64[4][64];
+  __shared__ uint32_t redmx[4];
+  for (uint32_t k = threadIdx.x; k < 45u; k += blockDim.x) big[k] = 0;
+  __syncthreads();
+  const MomSeg sg = segs[blockIdx.x];
+  const Rep9 rp = reps[sg.slot];
+  const uint32_t Lx = rp.Lx, Ly = rp.Ly;
+  const uint32_t tx = no_stream ? 0u : (uint32_t)(t % Lx);
+  const uint32_t ty = no_stream ? 0u : (uint32_t)(t % Ly);
+  const uint16_t *base = state + rp.off;
+  const uint32_t stride = rp.stride;
+  uint32_t acc[64];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) acc[k] = 0;
+  uint32_t mx = 0;
+  const uint32_t bs = blockDim.x;
+  const uint32_t qy = bs / Lx, qx = bs - qy * Lx;  // the block's stride in (x, y)
+  uint32_t s = sg.x0 + threadIdx.x;
+  uint32_t y = s / Lx, x = s - y * Lx;
+  for (; s < sg.x1; s += bs) {
+    // physical columns for vx = -1, 0, +1 and row offsets for vy = -1, 0, +1
+    const uint32_t xc[3] = {x + tx >= Lx ? x + tx - Lx : x + tx, x,
+                            x >= tx ? x - tx : x + Lx - tx};
+    const uint32_t yr[3] = {(y + ty >= Ly ? y + ty - Ly : y + ty) * Lx, y * Lx,
+                            (y >= ty ? y - ty : y + Ly - ty) * Lx};
+    uint32_t n[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      n[i] = base[(uint64_t)i * stride + yr[kVy9[i] + 1] + xc[kVx9[i] + 1]];
+    uint32_t N = 0, top = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      N += n[i];
+      top = max(top, n[i]);
+      acc[i] += n[i];
+    }
+    mx = max(mx, N);
+    if (top < 256u) {
+      int k = 9;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = i; j < 9; ++j) acc[k++] += n[i] * n[j];
+    } else {
+      int k = 0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = i; j < 9; ++j) atomicAdd(&big[k++], (u64)n[i] * n[j]);
+    }
+    x += qx;
+    y += qy;
+    if (x >= Lx) { x -= Lx; y += 1u; }
+  }
+  // first level of the reduce-scatter in 32-bit inputs (lanes with bit 5
+  // set keep values 32..63), then 64-bit sums
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  u64 v[32];
+  {
+    const bool up = (lane & 32u) != 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const uint32_t send = up ? acc[j] : acc[j + 32];
+      const uint32_t keep = up ? acc[j + 32] : acc[j];
+      v[j] = (u64)keep + (uint32_t)__shfl_xor(send, 32);
+    }
+  }
+  int w = 32, m = 16;
+#pragma unroll
+  for (int lvl = 0; lvl < 5; ++lvl) {
+    const bool up = (lane & (uint32_t)m) != 0;
+    const int h = w >> 1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j < h) {
+        const u64 send = up ? v[j] : v[j + h];
+        const u64 keep = up ? v[j + h] : v[j];
+        v[j] = keep + shfl_xor_u64(send, m);
+      }
+    }
+    w = h;
+    m >>= 1;
+  }
+  // lane l now holds the wave's total of value l
+  mx = wave_max(mx);
+  red64[wave][lane] = v[0];
+  if (lane == 0) redmx[wave] = mx;
+  __syncthreads();
+  const uint32_t nw = blockDim.x >> 6;
+  u64 *rec = partial + (uint64_t)blockIdx.x * kMom9Rec;
+  for (uint32_t k = threadIdx.x; k < kMom9Rec; k += blockDim.x) {
+    u64 o = 0;
+    if (k == kMom9Rec - 1) {
+      uint32_t mm = 0;
+      for (uint32_t q = 0; q < nw; ++q) mm = max(mm, redmx[q]);
+      o = mm;
+    } else if (k < 54u) {
+      for (uint32_t q = 0; q < nw; ++q) o += red64[q][k];
+      if (k >= 9u) o += big[k - 9u];
+    }
+    rec[k] = o;
+  }
+}
+
+// One block per run: the replica's result in the field order of
+// mclg_moments9_t: t, sites, sum n_i, sum n_i n_j (i <= j), sum N, sum Jx,
+// sum Jy (from the per-velocity sums), max N.
+__global__ void __launch_bounds__(64) k_mom9_final(const u64 *__restrict__ partial,
+                                                   const uint32_t *__restrict__ run_seg,
+                                                   const uint32_t *__restrict__ run_slot,
+                                                   const Rep9 *__restrict__ reps, uint64_t t,
+                                                   uint32_t by_slot, i64 *__restrict__ out) {
+  __shared__ u64 tot[kMom9Rec];
+  const uint32_t j = blockIdx.x, k = threadIdx.x;
+  const uint32_t s0 = run_seg[j], s1 = run_seg[j + 1], slot = run_slot[j];
+  if (k < kMom9Rec) {
+    u64 acc = 0;
+    for (uint32_t s = s0; s < s1; ++s) {
+      const u64 v = partial[(uint64_t)s * kMom9Rec + k];
+      acc = k == kMom9Rec - 1 ? (acc > v ? acc : v) : acc + v;
+    }
+    tot[k] = acc;
+  }
+  __syncthreads();
+  if (k == 0) {
+    i64 *o = out + (uint64_t)(by_slot ? slot : j) * kMom9Out;
+    o[0] = (i64)t;
+    o[1] = (i64)reps[slot].S;
+    u64 N = 0;
+    i64 jx = 0, jy = 0;
+    for (int i = 0; i < 9; ++i) {
+      o[2 + i] = (i64)tot[i];
+      N += tot[i];
+      jx += kVx9[i] * (i64)tot[i];
+      jy += kVy9[i] * (i64)tot[i];
+    }
+    for (int i = 0; i < 45; ++i) o[11 + i] = (i64)tot[9 + i];
+    o[56] = (i64)N;
+    o[57] = jx;
+    o[58] = jy;
+    o[59] = (i64)tot[kMom9Rec - 1];
+  }
+}
+
+template <int NM>
+hipError_t launch3(hipStream_t s, const MomArgs &a) {
+  if (a.digest)
+    k_mom3<NM, true><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
+                                              a.twiddle, a.partial);
+  else
+    k_mom3<NM, false><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
+                                               a.twiddle, a.partial);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n) {
+  MomPlan p;
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n; ++j) total += sites[j];
+  uint64_t seg = (total + kMomMaxSegsBase - 1) / kMomMaxSegsBase;
+  seg = std::max<uint64_t>(8192, (seg + 2047) / 2048 * 2048);
+  p.run_seg.push_back(0);
+  for (uint32_t j = 0; j < n; ++j) {
+    for (uint64_t x0 = 0; x0 < sites[j]; x0 += seg) {
+      MomSeg m;
+      m.slot = slots[j];
+      m.x0 = (uint32_t)x0;
+      m.x1 = (uint32_t)std::min<uint64_t>(sites[j], x0 + seg);
+      p.segs.push_back(m);
+    }
+    if (sites[j] == 0) {  // an empty run still gets its (zero) record
+      MomSeg m;
+      m.slot = slots[j];
+      p.segs.push_back(m);
+    }
+    p.run_seg.push_back((uint32_t)p.segs.size());
+    p.run_slot.push_back(slots[j]);
+  }
+  return p;
+}
+
+hipError_t launch_moments3(hipStream_t s, const MomArgs &a) {
+  if (a.n_runs == 0) return hipSuccess;
+  if (a.n_modes > 8 || (a.n_modes && !a.twiddle)) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  switch (a.n_modes) {
+    case 0: e = launch3<0>(s, a); break;
+    case 1: e = launch3<1>(s, a); break;
+    case 2: e = launch3<2>(s, a); break;
+    case 3: e = launch3<3>(s, a); break;
+    case 4: e = launch3<4>(s, a); break;
+    case 5: e = launch3<5>(s, a); break;
+    case 6: e = launch3<6>(s, a); break;
+    case 7: e = launch3<7>(s, a); break;
+    default: e = launch3<8>(s, a); break;
+  }
+  if (e) return e;
+  k_mom3_final<<<a.n_runs, 64, 0, s>>>(a.partial, a.run_seg, a.run_slot, a.slots, a.tslot,
+                                       a.by_slot, a.out);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments9(hipStream_t s, const MomArgs &a) {
+  if (a.n_runs == 0) return hipSuccess;
+  k_mom9<<<a.n_segs, 256, 0, s>>>(a.state, a.reps, a.t9, a.no_stream, a.segs, a.partial);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  k_mom9_final<<<a.n_runs, 64, 0, s>>>(a.partial, a.run_seg, a.run_slot, a.reps, a.t9,
+                                       a.by_slot, a.out);
+  return hipGetLastError();
+}
+
+}  // namespace mclg

@@ -18,6 +18,7 @@
 
 #include "../../include/mclg.h"
 #include "device.h"
+#include "moments.h"
 #include "tables.h"
 
 using namespace mclg;
@@ -30,8 +31,10 @@ constexpr uint32_t kImage = 96 * 1024;  // LDS collision image budget per job
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
-  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_mom, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
+  uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, o_fixed, bytes, max_tiles;
+  // moments of retiring jobs: segments, runs, partial records, results
+  uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout;
 };
 
 SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
@@ -51,7 +54,11 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_tslot = take(sizeof(uint32_t) * n);
   l.o_tiles = take(sizeof(TileDev) * l.max_tiles);
   l.o_list = take(sizeof(uint32_t) * n);
-  l.o_mom = take(sizeof(MomDev) * n);
+  l.o_mseg = take(sizeof(MomSeg) * max_mom_segs((uint32_t)n));
+  l.o_mrun = take(sizeof(uint32_t) * (n + 1));
+  l.o_mslot = take(sizeof(uint32_t) * n);
+  l.o_mpart = take(sizeof(uint64_t) * kMom3Rec * max_mom_segs((uint32_t)n));
+  l.o_mout = take(sizeof(uint64_t) * kMom3Out * n);
   l.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   l.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
   l.o_idesc = take(sizeof(ImageDesc) * n);
@@ -95,6 +102,7 @@ struct mclg_server {
   std::vector<PoisDesc> h_pdesc;
   std::vector<uint32_t> h_pool;
   std::vector<ImageDesc> h_idesc;
+  MomPlan h_mplan;  // segments of the jobs being retired
   uint32_t n_tiles = 0, n_active = 0;
   uint32_t lds_bytes = 16, max_blocks = 1, image_budget = kImage, n_cu = 1;
   int last_hip = 0;
@@ -105,7 +113,6 @@ struct mclg_server {
   uint32_t *d_tslot() { return reinterpret_cast<uint32_t *>(ws + lay.o_tslot); }
   TileDev *d_tiles() { return reinterpret_cast<TileDev *>(ws + lay.o_tiles); }
   uint32_t *d_list() { return reinterpret_cast<uint32_t *>(ws + lay.o_list); }
-  MomDev *d_mom() { return reinterpret_cast<MomDev *>(ws + lay.o_mom); }
   TableDev table() {
     TableDev d;
     d.rowbase = reinterpret_cast<const uint32_t *>(ws + lay.o_rowbase);
@@ -156,7 +163,7 @@ struct mclg_server {
 
   ImageDesc *d_idesc() { return reinterpret_cast<ImageDesc *>(ws + lay.o_idesc); }
   StepLaunch launch_args() {
-    StepLaunch a;
+    StepLaunch a{};
     a.state = arena;
     a.slots = d_slots();
     a.tslot = d_tslot();
@@ -171,7 +178,7 @@ struct mclg_server {
     a.err = err();
     a.tab = table();
     a.p = params();
-    a.p.drain_at = drain_threshold(arena_used);  // the resident jobs' state
+    a.p.drain = auto_drain(arena_used);  // by the resident jobs' state
     a.images = d_idesc();
     a.image_pool = ws + lay.o_ipool;
     a.overflow = reinterpret_cast<uint4 *>(ws + lay.o_over);
@@ -298,45 +305,46 @@ struct mclg_server {
     return hip(e);
   }
 
-  // Moments of finished jobs, then free their slots.
+  // Moments (with the state digest) of finished jobs, then free their slots.
   int retire() {
     std::vector<uint32_t> fin;
+    std::vector<uint64_t> sites;
     for (uint32_t i = 0; i < slot.size(); ++i)
-      if (slot[i].active && slot[i].t >= slot[i].job.steps) fin.push_back(i);
+      if (slot[i].active && slot[i].t >= slot[i].job.steps) {
+        fin.push_back(i);
+        sites.push_back(slot[i].job.L);
+      }
     if (fin.empty()) return MCLG_OK;
-    std::vector<TileDev> tl;
-    const uint32_t ts = sch.tile_sites();
-    for (uint32_t i : fin)
-      for (uint64_t x0 = 0; x0 < slot[i].job.L; x0 += ts) tl.push_back(TileDev{i, (uint32_t)x0, 0, 0});
-    if (tl.size() > lay.max_tiles) return MCLG_E_INVAL;
-    hipError_t e = up(d_tiles(), tl.data(), sizeof(TileDev) * tl.size());
-    if (!e) e = launch_zero(s, reinterpret_cast<unsigned long long *>(d_mom()),
-                            (uint64_t)slot.size() * (sizeof(MomDev) / 8));
-    if (!e)
-      e = launch_moments(s, arena, d_slots(), d_tslot(), d_tiles(), (uint32_t)tl.size(), ts, 0u,
-                         nullptr, 0u, d_mom());
-    std::vector<MomDev> h(slot.size());
-    if (!e) e = hipMemcpyAsync(h.data(), d_mom(), sizeof(MomDev) * h.size(), hipMemcpyDeviceToHost, s);
+    h_mplan = plan_moments(fin.data(), sites.data(), (uint32_t)fin.size());
+    if (h_mplan.segs.size() > max_mom_segs((uint32_t)slot.size())) return MCLG_E_INTERNAL;
+    MomArgs m;
+    m.state = arena;
+    m.slots = d_slots();
+    m.tslot = d_tslot();
+    m.segs = reinterpret_cast<const MomSeg *>(ws + lay.o_mseg);
+    m.n_segs = (uint32_t)h_mplan.segs.size();
+    m.run_seg = reinterpret_cast<const uint32_t *>(ws + lay.o_mrun);
+    m.run_slot = reinterpret_cast<const uint32_t *>(ws + lay.o_mslot);
+    m.n_runs = (uint32_t)fin.size();
+    m.digest = 1u;
+    m.partial = reinterpret_cast<unsigned long long *>(ws + lay.o_mpart);
+    m.out = reinterpret_cast<long long *>(ws + lay.o_mout);
+    hipError_t e = up(ws + lay.o_mseg, h_mplan.segs.data(), sizeof(MomSeg) * h_mplan.segs.size());
+    if (!e) e = up(ws + lay.o_mrun, h_mplan.run_seg.data(), 4 * h_mplan.run_seg.size());
+    if (!e) e = up(ws + lay.o_mslot, h_mplan.run_slot.data(), 4 * h_mplan.run_slot.size());
+    if (!e) e = launch_moments3(s, m);
+    std::vector<mclg_moments_t> h(fin.size());
+    if (!e) e = hipMemcpyAsync(h.data(), ws + lay.o_mout, sizeof(mclg_moments_t) * h.size(),
+                               hipMemcpyDeviceToHost, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) return hip(e);
-    for (uint32_t i : fin) {
+    for (size_t k = 0; k < fin.size(); ++k) {
+      const uint32_t i = fin[k];
       mclg_job_result res;
       std::memset(&res, 0, sizeof(res));
       res.job_id = slot[i].job.job_id;
-      mclg_moments_t &o = res.moments;
-      const unsigned long long *v = h[i].v;
-      o.t = (int64_t)slot[i].t;
-      o.sites = (int64_t)slot[i].job.L;
-      for (int k = 0; k < 3; ++k) {
-        o.sum_n[k] = (int64_t)v[k];
-        o.sum_n2[k] = (int64_t)v[3 + k];
-        o.sum_nn[k] = (int64_t)v[6 + k];
-      }
-      o.sum_N = (int64_t)v[9];
-      o.sum_J = (int64_t)v[10];
-      o.sum_N2 = (int64_t)v[11];
-      o.n0_odd = (int64_t)v[12];
-      o.max_N = (int64_t)v[13];
+      res.moments = h[k];
+      res.moments.t = (int64_t)slot[i].t;
       done.push_back(res);
       slot[i].active = false;
       release(slot[i].arena_off, slot[i].bytes);

@@ -25,6 +25,8 @@ FLAG_GALILEAN = 2
 INIT_COUNTS, INIT_POISSON = 1, 2
 MAX_MODES = 8
 MAX_HIST_BINS = 4096
+MOMENTS_DIGEST = 1
+DRAIN_AUTO, DRAIN_DEFERRED, DRAIN_CHUNK, DRAIN_PATCH = 0, 1, 2, 3
 OK, E_INVAL, E_RANGE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_FULL, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 
 u32, u64, i32, i64, dbl, vp = ct.c_uint32, ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_double, ct.c_void_p
@@ -56,13 +58,15 @@ class mclg_moments9_t(ct.Structure):
 class mclg_moments_t(ct.Structure):
     _fields_ = [("t", i64), ("sites", i64), ("sum_n", i64 * 3), ("sum_n2", i64 * 3),
                 ("sum_nn", i64 * 3), ("sum_N", i64), ("sum_J", i64), ("sum_N2", i64),
-                ("n0_odd", i64), ("max_N", i64), ("fourier", (i64 * 2) * MAX_MODES)]
+                ("n0_odd", i64), ("max_N", i64), ("fourier", (i64 * 2) * MAX_MODES),
+                ("digest", i64)]
 
     def as_dict(self) -> dict:
         return {"t": self.t, "sites": self.sites, "sum_n": list(self.sum_n),
                 "sum_n2": list(self.sum_n2), "sum_nn": list(self.sum_nn), "sum_N": self.sum_N,
                 "sum_J": self.sum_J, "sum_N2": self.sum_N2, "n0_odd": self.n0_odd,
-                "max_N": self.max_N, "fourier": [list(self.fourier[m]) for m in range(MAX_MODES)]}
+                "max_N": self.max_N, "fourier": [list(self.fourier[m]) for m in range(MAX_MODES)],
+                "digest": self.digest & 0xFFFFFFFFFFFFFFFF}
 
 
 class mclg_server_config(ct.Structure):
@@ -93,7 +97,7 @@ _SIGS = {
     "mclg_step": [vp, u64],
     "mclg_step_replica": [vp, u32, u64],
     "mclg_step_graph": [vp, u64],
-    "mclg_moments": [vp, vp, u32, P(mclg_moments_t)],
+    "mclg_moments": [vp, vp, u32, u32, P(mclg_moments_t)],
     "mclg_histogram": [vp, u32, vp],
     "mclg_moments9": [vp, P(mclg_moments9_t)],
     "mclg_d2q9_rules": [P(u32), P(u32), P(u32)],
@@ -101,6 +105,7 @@ _SIGS = {
     "mclg_check": [vp],
     "mclg_set_schedule": [vp, u32, u32, u32],
     "mclg_set_grid_limit": [vp, u32],
+    "mclg_set_drain": [vp, u32],
     "mclg_lds_coverage": [vp, P(dbl), P(u32)],
     "mclg_destroy": [vp],
     "mclg_strerror": [ct.c_int],
@@ -229,6 +234,10 @@ def mclg_set_grid_limit(ctx: int, max_blocks: int):
     _check(lib().mclg_set_grid_limit(ctx, max_blocks), "mclg_set_grid_limit")
 
 
+def mclg_set_drain(ctx: int, policy: int):
+    _check(lib().mclg_set_drain(ctx, policy), "mclg_set_drain")
+
+
 def mclg_lds_coverage(ctx: int):
     f, b = dbl(0), u32(0)
     _check(lib().mclg_lds_coverage(ctx, ct.byref(f), ct.byref(b)), "mclg_lds_coverage")
@@ -333,13 +342,18 @@ class Lattice:
     def set_grid_limit(self, max_blocks: int):
         mclg_set_grid_limit(self.ctx, max_blocks)
 
+    def set_drain(self, policy: int):
+        mclg_set_drain(self.ctx, policy)
+
     def lds_coverage(self):
         return mclg_lds_coverage(self.ctx)
 
     def check(self) -> int:
         return mclg_check(self.ctx)
 
-    def moments(self, twiddle=None, n_modes: int = 0, allow_range=False):
+    def moments(self, twiddle=None, n_modes: int = 0, allow_range=False, digest=False):
+        """Exact moments of every replica; with digest=True also the state
+        digest (see state_digest)."""
         out = (mclg_moments_t * self.n)()
         tw = 0
         if twiddle is not None:
@@ -347,7 +361,7 @@ class Lattice:
                 raise ValueError("twiddle must hold 2 * n_modes * sum(L) int32 values")
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
             tw = twiddle.data_ptr()
-        rc = lib().mclg_moments(self.ctx, tw, n_modes, out)
+        rc = lib().mclg_moments(self.ctx, tw, n_modes, MOMENTS_DIGEST if digest else 0, out)
         if rc != OK and not (allow_range and rc == E_RANGE):
             raise MclgError(rc, "mclg_moments")
         return [o.as_dict() for o in out]

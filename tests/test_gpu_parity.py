@@ -3,8 +3,12 @@
 The state is integer counts, so the bar is exact equality of every count
 after every compared step.  Inputs are seeded (synth/); the oracle computes
 its own initial state from the same rule or takes the same synthetic counts.
-Full-size runs are checked on light-cone windows the oracle recomputes
-independently, and by exact conservation.
+Every small case runs under each policy by which the step kernel resolves
+the draws its LDS image cannot decide (deferred, after each chunk, before
+each chunk's store), since the library picks between them by state size.
+The largest lattice is checked on light-cone windows the oracle recomputes
+independently, and by exact conservation; the full-size workloads are in
+test_gpu_scale.py.
 """
 import sys
 
@@ -13,9 +17,14 @@ import pytest
 
 import oracle as O
 import synth
-from paper_1706_01094_amd.mclg import E_RANGE, FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError
+from paper_1706_01094_amd.mclg import (DRAIN_CHUNK, DRAIN_DEFERRED, DRAIN_PATCH, E_RANGE,
+                                      FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError)
+from tests.state_digest import digest
 
 pytestmark = pytest.mark.gpu
+
+DRAINS = [DRAIN_DEFERRED, DRAIN_CHUNK, DRAIN_PATCH]
+drains = pytest.mark.parametrize("drain", DRAINS, ids=["deferred", "chunk", "patch"])
 
 
 def say(*a):
@@ -24,10 +33,13 @@ def say(*a):
 
 
 def pair(L, seed, C=10, lam=(1, 1), n_max=255, rho=10.0, u0=0.0, counts=None, flags=0,
-         replica_id=None):
-    say("case", dict(L=L, seed=seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags))
+         replica_id=None, drain=None):
+    say("case", dict(L=L, seed=seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags,
+                     drain=drain))
     g = Lattice(L, seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, counts=counts, flags=flags,
                 replica_id=replica_id)
+    if drain is not None:
+        g.set_drain(drain)
     o = O.OracleSim(L, seed, C=C, lam=lam, n_max=n_max, flags=flags, replica_id=replica_id)
     Ls = np.atleast_1d(L)
     rhos = np.broadcast_to(np.asarray(rho, dtype=float), (len(Ls),))
@@ -70,11 +82,12 @@ def test_plain_small_every_step():
 @pytest.mark.parametrize("groups,threads,lds", [(1, 64, 96 << 10), (1, 256, 0), (1, 128, 4096),
                                                 (1, 1024, 112 << 10), (1, 512, 32 << 10),
                                                 (1, 1024, 0), (1, 64, 128 << 10)])
-def test_ragged_tiles_and_schedules(groups, threads, lds):
+@drains
+def test_ragged_tiles_and_schedules(groups, threads, lds, drain):
     """Several tiles plus a ragged tail, at u != 0; every schedule and LDS
     image size (0 = every draw from the global rows) gives the oracle's bits."""
     L = 3 * 2048 + 37
-    g, o = pair(L, 7, rho=30.0, u0=0.15)
+    g, o = pair(L, 7, rho=30.0, u0=0.15, drain=drain)
     g.set_schedule(groups, threads, lds)
     say("lds coverage", g.lds_coverage())
     for _ in range(12):
@@ -87,7 +100,8 @@ def test_ragged_tiles_and_schedules(groups, threads, lds):
                                                 (1024, 1, 112 << 10), (512, 3, 0),
                                                 (768, 2, 96 << 10), (832, 3, 64 << 10),
                                                 (576, 1, 0)])
-def test_long_runs_per_wave(threads, blocks, lds):
+@drains
+def test_long_runs_per_wave(threads, blocks, lds, drain):
     """A capped grid gives each wave long runs of contiguous chunks: the
     boundary vectors passed from chunk to chunk, drains between chunks and the
     chunks that wrap around the lattice end, over shifts t = 0..23 (every
@@ -95,7 +109,7 @@ def test_long_runs_per_wave(threads, blocks, lds):
     waves cover every rule by which a block's young waves stop claiming its
     last chunks (every chunk must still be taken)."""
     L = 3 * 2 ** 14 + 37
-    g, o = pair(L, 31, rho=30.0, u0=0.1)
+    g, o = pair(L, 31, rho=30.0, u0=0.1, drain=drain)
     g.set_schedule(1, threads, lds)
     g.set_grid_limit(blocks)
     for _ in range(8):
@@ -105,18 +119,20 @@ def test_long_runs_per_wave(threads, blocks, lds):
 
 
 @pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7, 129])
-def test_tiny_lattices(L):
+@drains
+def test_tiny_lattices(L, drain):
     counts = synth.random_counts(L, seed=L)
-    g, o = pair(L, 3, counts=counts)
+    g, o = pair(L, 3, counts=counts, drain=drain)
     for _ in range(20):
         g.step(1)
         o.step(1)
         same(g, o)
 
 
-def test_direct_path_above_n_max():
+@drains
+def test_direct_path_above_n_max(drain):
     """Sites with N > n_max take the paper's literal sub-collision loop."""
-    g, o = pair(3000, 11, n_max=24, rho=30.0, u0=-0.05)
+    g, o = pair(3000, 11, n_max=24, rho=30.0, u0=-0.05, drain=drain)
     m = g.moments()[0]
     assert m["max_N"] > 24
     for _ in range(10):
@@ -125,17 +141,52 @@ def test_direct_path_above_n_max():
         same(g, o)
 
 
+# lambda with denominator q = 3 * 2^26: the literal loop's uniform integer
+# below q rejects 1/64 of its 32-bit words (2^32 mod q = 2^26) and the one
+# below 8 q a quarter (2^32 mod 8q = 2^30), so both rejection branches run
+LAMBDA_REJECT = (3 * 2**25 + 1, 3 * 2**26)
+
+
+@drains
+@pytest.mark.parametrize("C", [1, 10])
+def test_literal_loop_with_rejected_draws(C, drain):
+    """n_max = 24 sends most sites (rho = 30) to the literal loop, whose
+    Bernoulli draws with lambda = (3 2^25 + 1) / (3 2^26) take Lemire's
+    rejection step often; every count equals the oracle's after every step."""
+    g, o = pair(3000, 43, C=C, lam=LAMBDA_REJECT, n_max=24, rho=30.0, u0=0.1, drain=drain)
+    for _ in range(10):
+        g.step(1)
+        o.step(1)
+        same(g, o)
+
+
+def test_state_digest_equals_host_digest():
+    """The digest the moments kernel sums equals the host-side definition,
+    for the GPU's own counts and the oracle's, over ragged replicas."""
+    L = [1, 7, 513, 2048, 5000]
+    g, o = pair(L, 47, rho=[3.0, 20.0, 40.0, 8.0, 60.0], u0=[0.0, 0.1, -0.2, 0.05, 0.3])
+    for _ in range(3):
+        g.step(5)
+        o.step(5)
+        m = g.moments(digest=True)
+        for r in range(len(L)):
+            assert m[r]["digest"] == digest(g.counts(r)) == digest(o.counts(r)), r
+    assert g.moments()[0]["digest"] == 0
+
+
 @pytest.mark.parametrize("C,lam", [(0, (1, 1)), (1, (1, 1)), (3, (1, 2)), (10, (3, 4)), (-1, (1, 1))])
-def test_collision_parameters(C, lam):
-    g, o = pair(2500, 13, C=C, lam=lam, rho=20.0, u0=0.1)
+@drains
+def test_collision_parameters(C, lam, drain):
+    g, o = pair(2500, 13, C=C, lam=lam, rho=20.0, u0=0.1, drain=drain)
     for _ in range(8):
         g.step(4)
         o.step(4)
         same(g, o)
 
 
-def test_no_stream_flag():
-    g, o = pair(2000, 17, rho=40.0, flags=1)
+@drains
+def test_no_stream_flag(drain):
+    g, o = pair(2000, 17, rho=40.0, flags=1, drain=drain)
     for _ in range(10):
         g.step(2)
         o.step(2)
@@ -146,12 +197,13 @@ def test_no_stream_flag():
     (255, 12.0, 0.4, (3, 4), FLAG_GALILEAN),
     (16, 20.0, -0.5, (1, 1), FLAG_GALILEAN),
     (16, 20.0, 0.3, (2, 3), FLAG_GALILEAN | FLAG_NO_STREAM)])
-def test_galilean_acceptance(n_max, rho, u0, lam, flags):
+@drains
+def test_galilean_acceptance(n_max, rho, u0, lam, flags, drain):
     """Galilean-invariant acceptance: L = 3000, C = 10, the per-fiber tables
     (n_max = 255) and the device's own per-site numerator in the literal loop
     (n_max = 16, where most sites have N > n_max); every count equal to the
     oracle's after each of 12 steps."""
-    g, o = pair(3000, 21, C=10, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags)
+    g, o = pair(3000, 21, C=10, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags, drain=drain)
     for _ in range(12):
         g.step(1)
         o.step(1)
@@ -174,13 +226,14 @@ def test_moments_with_fourier_modes():
             assert m[k] == mo[k], k
 
 
-def test_overflow_is_flagged_and_site_kept():
+@drains
+def test_overflow_is_flagged_and_site_kept(drain):
     """A site with N > 65535 is not collided and raises the sticky range
     error on both sides."""
     L = 64
     counts = synth.random_counts(L, seed=5)
     counts[:, 10] = 30000
-    g, o = pair(L, 23, counts=counts)
+    g, o = pair(L, 23, counts=counts, drain=drain)
     g.step(1)
     rc = o.step(1)
     assert rc == -2
@@ -190,7 +243,8 @@ def test_overflow_is_flagged_and_site_kept():
         g.counts(0)
 
 
-def test_batched_replicas_step_replica_and_graph():
+@drains
+def test_batched_replicas_step_replica_and_graph(drain):
     """Uneven replicas in one launch, single-replica launches and a captured
     HIP graph all reproduce the oracle; graph replays are checked one by one
     with eager work in between."""
@@ -198,7 +252,7 @@ def test_batched_replicas_step_replica_and_graph():
     rid = [10, 11, 12, 13, 14, 99]
     rho = [5.0, 10.0, 50.0, 80.0, 20.0, 33.0]
     u0 = [0.0, 0.1, -0.2, 0.05, 0.0, 0.15]
-    g, o = pair(L, 29, rho=rho, u0=u0, replica_id=rid)
+    g, o = pair(L, 29, rho=rho, u0=u0, replica_id=rid, drain=drain)
     for r in range(len(L)):
         same(g, o, r)
     g.step(10)
@@ -220,91 +274,3 @@ def test_batched_replicas_step_replica_and_graph():
         o.step(1)
     for r in range(len(L)):
         same(g, o, r)
-
-
-def _window_check(g, L, seed, rho, u0, T, x0s, W=1500, counts=None):
-    full = g.counts(0)
-    for x0 in x0s:
-        lo = x0 - T
-        n = W + 2 * T
-        o = O.OracleSim([n], seed, C=10)
-        o.set_site_offset(0, lo, 0)
-        if counts is None:
-            o.init_poisson(0, rho, u0)
-        else:
-            o.init_counts(0, counts[:, lo:lo + n])
-        o.step(T)
-        want = o.counts(0)[:, T:T + W]
-        got = full[:, x0:x0 + W]
-        assert np.array_equal(got, want), f"window at {x0}"
-
-
-def test_full_size_plain_large_windows():
-    """L = 2^24, rho = 50, u0 = 0.1 in the benchmark's launch schedule: exact
-    conservation over the whole lattice and the oracle's light-cone windows."""
-    w = synth.PLAIN_LARGE
-    L = w["L"]
-    say("full-size", L)
-    g = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
-    m0 = g.moments()[0]
-    T = 16
-    g.step(T)
-    m1 = g.moments()[0]
-    assert m1["sum_N"] == m0["sum_N"] and m1["sum_J"] == m0["sum_J"]
-    assert m1["n0_odd"] == m0["n0_odd"]
-    rng = np.random.default_rng(0)
-    x0s = [T, L // 2, L - 1500 - T] + [int(v) for v in rng.integers(T, L - 1500 - T, size=3)]
-    _window_check(g, L, w["seed"], w["rho"], w["u0"], T, x0s)
-
-
-def test_largest_lattice_windows():
-    """L = 2^29, the largest lattice (the step kernel's 32-bit byte offsets
-    reach their top): conservation and oracle windows at both ends and in
-    the middle after a few steps."""
-    L = 1 << 29
-    say("largest lattice", L)
-    g = Lattice(L, 41, rho=8.0, u0=0.05)
-    m0 = g.moments()[0]
-    T = 3
-    g.step(T)
-    m1 = g.moments()[0]
-    assert m1["sum_N"] == m0["sum_N"] and m1["sum_J"] == m0["sum_J"]
-    _window_check(g, L, 41, 8.0, 0.05, T, [T, L // 2 + 12345, L - 1500 - T], W=1500)
-    g.close()
-
-
-def test_full_size_density_wave():
-    """L = 2^22 density wave from synthetic counts: whole-lattice state and
-    the int64 Fourier amplitude equal the oracle after 6 steps."""
-    import torch
-    w = synth.DENSITY_WAVE
-    L = w["L"]
-    counts = synth.density_wave_counts()
-    say("density wave", L)
-    g = Lattice(L, w["seed"], counts=counts)
-    o = O.OracleSim([L], w["seed"], C=10)
-    o.init_counts(0, counts)
-    tw = synth.twiddles(L, 1)
-    twd = torch.as_tensor(tw).to("cuda:0")
-    for _ in range(2):
-        g.step(3)
-        o.step(3)
-        same(g, o)
-        assert g.moments(twd, 1)[0]["fourier"][0] == o.moments(0, tw)["fourier"][0]
-
-
-def test_full_size_batched_sampled_replicas():
-    """All 1024 replicas of the batched workload in one launch per step;
-    a sample of replicas recomputed whole by the oracle."""
-    man = synth.replica_manifest()
-    say("batched", len(man["L"]), int(man["L"].sum()))
-    g = Lattice(man["L"], synth.BATCHED["seed"], rho=man["rho"], u0=man["u0"],
-                replica_id=man["replica_id"])
-    T = 6
-    g.step(T)
-    for r in [0, 1, 511, 777, 1023]:
-        o = O.OracleSim([int(man["L"][r])], synth.BATCHED["seed"], C=10,
-                        replica_id=[int(man["replica_id"][r])])
-        o.init_poisson(0, float(man["rho"][r]), float(man["u0"][r]))
-        o.step(T)
-        assert np.array_equal(g.counts(r), o.counts(0)), r

@@ -1,12 +1,16 @@
 """Serving (continuous batching) on the GPU: every job's result is the same
-alone and in the mix, and equals the oracle's run of that job."""
+alone and in the mix, and equals the oracle's run of that job -- its exact
+moments and the digest of its whole final state."""
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_1706_01094_amd.mclg import E_INVAL, MclgError, Server
+from tests.state_digest import digest
 
 pytestmark = pytest.mark.gpu
 
@@ -43,14 +47,20 @@ def run(jobs, arena_bytes=1 << 24, max_slots=4, k=5):
 
 
 def oracle_moments(job):
+    """The oracle's moments of the job's final state, with the host digest of
+    that state."""
     jid, L, steps, rho, u0 = job
     o = O.OracleSim([L], SEED, C=10, replica_id=[jid])
     o.init_poisson(0, rho, u0)
     o.step(steps)
-    return o.moments(0)
+    m = o.moments(0)
+    m["digest"] = digest(o.counts(0))
+    o.close()
+    return m
 
 
-KEYS = ("t", "sum_n", "sum_n2", "sum_nn", "sum_N", "sum_J", "sum_N2", "n0_odd", "max_N")
+KEYS = ("t", "sum_n", "sum_n2", "sum_nn", "sum_N", "sum_J", "sum_N2", "n0_odd", "max_N",
+        "digest")
 
 
 def test_jobs_alone_equal_jobs_in_mix_equal_oracle():
@@ -82,3 +92,33 @@ def test_job_larger_than_arena_is_rejected():
         srv.submit(1, 1 << 20, 10, 10.0, 0.0)
     assert e.value.code == E_INVAL
     srv.close()
+
+
+# Trace-like sizes: 2^21 .. 2^23 sites per job, 12 jobs resident together
+# hold 303 MB, more than the 256 MB Infinity Cache, so the batched launches
+# resolve each chunk's undecided draws before its store; alone, each job's
+# state is cached and its draws are resolved after the stores.
+SCALE_JOBS = [  # job_id, L, steps, rho, u0
+    (1000 + i, L, steps, rho, 0.0)
+    for i, (L, steps, rho) in enumerate([
+        (1 << 21, 30, 5.0), (3_000_001, 12, 100.0), (1 << 23, 9, 50.0), (2_500_000, 25, 77.0),
+        (6_000_017, 16, 20.0), (2_097_153, 21, 35.0), (4_444_444, 10, 90.0), (5_123_457, 14, 12.0),
+        (3_333_333, 18, 64.0), (7_000_000, 8, 41.0), (2_600_000, 27, 8.0), (3_900_001, 11, 99.0)])
+]
+
+
+def test_jobs_at_scale_alone_equal_mix_equal_oracle():
+    total = sum(3 * (-(-j[1] // 128) * 128) * 2 for j in SCALE_JOBS)
+    assert total > 256 << 20
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        want = {j[0]: ex.submit(oracle_moments, j) for j in SCALE_JOBS}
+        say("scale mix of", len(SCALE_JOBS), "resident bytes", total)
+        mix = run(SCALE_JOBS, arena_bytes=1 << 30, max_slots=16, k=4)
+        assert sorted(mix) == sorted(j[0] for j in SCALE_JOBS)
+        for job in SCALE_JOBS:
+            say("alone", job)
+            alone = run([job], arena_bytes=64 << 20, max_slots=2, k=7)[job[0]]
+            w = want[job[0]].result()
+            for k in KEYS:
+                assert mix[job[0]][k] == alone[k] == w[k], (job, k)

@@ -229,6 +229,36 @@ def test_conservation_and_streaming():
         assert np.array_equal(got[i], np.roll(c[i], (3 * V[i, 1], 3 * V[i, 0]), axis=(0, 1)))
 
 
+def test_moments_are_the_plain_sums():
+    """Every moment of the D2Q9 oracle equals numpy's sums over the same
+    counts: per velocity, all 45 products n_i n_j (i <= j, row-major upper
+    triangle), N, Jx, Jy, max N -- on counts large enough that any wrong
+    index or transposed pair shows."""
+    rng = np.random.default_rng(5)
+    Lx, Ly = 11, 7
+    c = rng.integers(0, 3000, size=(9, Ly, Lx)).astype(np.uint16)
+    sim = O.OracleSim9([Lx], [Ly], 3, C=0)
+    sim.init_counts(0, c)
+    m = sim.moments(0)
+    n = c.reshape(9, -1).astype(np.int64)
+    assert m["t"] == 0 and m["sites"] == Lx * Ly
+    assert m["sum_n"] == [int(v) for v in n.sum(1)]
+    want = [int((n[i] * n[j]).sum()) for i in range(9) for j in range(i, 9)]
+    assert m["sum_nn"] == want
+    N = n.sum(0)
+    assert m["sum_N"] == int(N.sum()) and m["max_N"] == int(N.max())
+    assert m["sum_Jx"] == int((V[:, 0][:, None] * n).sum())
+    assert m["sum_Jy"] == int((V[:, 1][:, None] * n).sum())
+    # the sums follow the logical sites through streaming: after five steps
+    # of a pure shift they are those of the shifted arrays
+    sim.step(5)
+    r = np.stack([np.roll(c[i], (5 * V[i, 1], 5 * V[i, 0]), axis=(0, 1)) for i in range(9)])
+    r = r.reshape(9, -1).astype(np.int64)
+    m5 = sim.moments(0)
+    assert m5["sum_nn"] == [int((r[i] * r[j]).sum()) for i in range(9) for j in range(i, 9)]
+    assert m5["sum_nn"] != want and m5["max_N"] == int(r.sum(0).max())
+
+
 def test_poisson_start_means():
     """Poisson start at (rho, u): site means within 4 standard errors of
     Eq. (D2Q9eqdist), per velocity, on 2^15 sites."""

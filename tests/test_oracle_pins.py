@@ -221,6 +221,29 @@ def test_sampler_chi_squared(abc, C, direct):
     assert _chi2_pvalue(counts, [float(p) for p in probs], n) > 1e-3
 
 
+# lambda = (3 2^25 + 1) / (3 2^26): the literal loop's uniform integers below
+# q = 3 2^26 and 8 q reject 1/64 and 1/4 of their 32-bit words (2^32 mod q =
+# 2^26, 2^32 mod 8q = 2^30), so Lemire's rejection step runs often
+LAMBDA_REJECT = (3 * 2**25 + 1, 3 * 2**26)
+
+
+@pytest.mark.parametrize("abc,C", [((1, 2, 1), 1), ((2, 6, 3), 10), ((0, 8, 0), 3)])
+@pytest.mark.parametrize("direct", [False, True])
+def test_sampler_chi_squared_with_rejections(abc, C, direct):
+    """With a lambda whose Bernoulli draws reject often, the table sampler
+    and the literal loop still follow the exact law (p > 1e-3 each)."""
+    n = 1_000_000
+    h = O.histogram(C, LAMBDA_REJECT, abc, n, seed=13, t=5, direct=direct)
+    N = sum(abc)
+    J = abc[2] - abc[0]
+    lam = Fraction(*LAMBDA_REJECT)
+    probs = X.rest_marginal(X.c_step_law(abc, C, lam), N, abs(J))
+    par = (N - abs(J)) % 2
+    counts = [int(h[par + 2 * k]) for k in range(len(probs))]
+    assert sum(counts) == n
+    assert _chi2_pvalue(counts, [float(p) for p in probs], n) > 1e-3
+
+
 def test_direct_and_table_have_equal_law_large_n():
     """At N = 40 the direct loop and the table draw agree in distribution
     (two-sample chi-squared)."""

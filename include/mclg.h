@@ -55,7 +55,9 @@ enum {
   MCLG_E_NOMEM = -4,       /* host allocation failed */
   MCLG_E_UNSUPPORTED = -5, /* entry point not available for the context's lattice */
   MCLG_E_FULL = -6,        /* server: no slot or arena space for the job */
-  MCLG_E_INTERNAL = -7     /* a device-side consistency check failed (a library bug) */
+  MCLG_E_INTERNAL = -7,    /* a device-side consistency check failed (a library bug) */
+  MCLG_E_TOO_LARGE = -8    /* more work than the static scratch area of
+                              mclg_moments_noalloc holds */
 };
 
 enum { MCLG_D1Q3 = 1, MCLG_D2Q9 = 2 };
@@ -229,6 +231,27 @@ int mclg_step_graph(mclg_ctx *ctx, uint64_t n_steps);
  * a missing twiddle or unknown flags. */
 int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes, uint32_t flags,
                  mclg_moments_t *host_out);
+
+/* For callers that cannot allocate memory or synchronise -- code under HIP
+ * graph capture, tight serving or logging loops, harnesses that forbid
+ * hipMalloc: mclg_moments with the same arguments and results, but written
+ * to device memory and without any allocation (no hipMalloc, hipFree or
+ * host allocation) or synchronisation.
+ *   dev_out: device, caller-owned, n_replicas mclg_moments_t in replica
+ *     order, written in stream order on the context's stream (read it after
+ *     synchronising with that stream); t is the device's step counter (the
+ *     steps taken modulo 2^32).
+ *   Partial sums live in a static 8 MiB area of device memory, one per GPU,
+ *     allocated with the library's code and kept until the process ends; a
+ *     call needs 256 bytes per segment of the context's sites (about
+ *     4096 + n_replicas segments): MCLG_E_TOO_LARGE when that exceeds
+ *     8 MiB, i.e. for more than about 28000 replicas.
+ *   Every call on a GPU uses that GPU's one area and overwrites what it
+ *     reads, so nothing needs clearing between calls, but calls that overlap
+ *     on one GPU (other streams, other threads) race: serialise them.
+ * D2Q9 contexts: MCLG_E_UNSUPPORTED. */
+int mclg_moments_noalloc(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
+                         uint32_t flags, mclg_moments_t *dev_out);
 
 /* Logical counts of one replica into host_out[3][L]; synchronises. */
 int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);

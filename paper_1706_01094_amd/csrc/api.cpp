@@ -136,6 +136,9 @@ struct mclg_ctx {
   uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
   uint32_t grid_limit = 0;  // 0: occupancy-derived grid
   uint32_t drain_policy = MCLG_DRAIN_AUTO;
+  // the device address of this device's static scratch area (moments.hip),
+  // looked up in mclg_init with the context's device current
+  unsigned long long *scratch = nullptr;
   double coverage = 0.0;                // expected LDS hit fraction (site-weighted)
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
@@ -457,6 +460,8 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   if (!e) c->n_cu = (uint32_t)std::max(1, v);
   if (e) return c->hip(e);
   if (c->n_cu > 256) return MCLG_E_UNSUPPORTED;  // overflow region sized for 256 CUs
+  e = moments_scratch(&c->scratch);
+  if (e) return c->hip(e);
   // what density and velocity each replica's image should target
   c->est_rho.assign(c->n, 0.0);
   c->est_u.assign(c->n, 0.0);
@@ -597,6 +602,23 @@ int mclg_moments(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, uint32_t
   return read_err(c);
 }
 
+int mclg_moments_noalloc(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, uint32_t flags,
+                         mclg_moments_t *dev_out) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
+  if (!c || !dev_out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle) ||
+      (flags & ~(uint32_t)MCLG_MOMENTS_DIGEST))
+    return MCLG_E_INVAL;
+  if ((uint64_t)c->lay.mplan.segs.size() * kMom3Rec * 8 > kMomScratchBytes) return MCLG_E_TOO_LARGE;
+  if (!c->scratch) return MCLG_E_INTERNAL;
+  MomArgs m = c->mom_args(c->scratch, reinterpret_cast<long long *>(dev_out));
+  m.twiddle = twiddle;
+  m.n_modes = n_modes;
+  m.digest = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
+  hipError_t e = c->flush_t();
+  if (!e) e = launch_moments3(c->stream, m);
+  return c->hip(e);
+}
+
 int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {
   if (!c || !hist || n_bins == 0 || n_bins > MCLG_MAX_HIST_BINS) return MCLG_E_INVAL;
   if (c->d2) return n_bins > 1024 ? MCLG_E_INVAL : d2q9_histogram(*c->d2, n_bins, hist);
@@ -694,6 +716,7 @@ const char *mclg_strerror(int code) {
     case MCLG_E_UNSUPPORTED: return "unsupported lattice or mode";
     case MCLG_E_FULL: return "server full";
     case MCLG_E_INTERNAL: return "internal consistency check failed";
+    case MCLG_E_TOO_LARGE: return "input larger than the static scratch area";
     default: return "unknown error";
   }
 }

@@ -66,6 +66,14 @@ struct MomArgs {
   uint32_t by_slot = 0;
 };
 
+// Static partial-record area of the allocation-free moments call: 8 MiB per
+// GPU (32768 D1Q3 records), for devices 0 .. kMomScratchDevices - 1.
+constexpr uint64_t kMomScratchBytes = 8ull << 20;
+constexpr uint32_t kMomScratchDevices = 64;
+// Device address of the current device's area (looked up once per device;
+// call it with the device current).
+hipError_t moments_scratch(unsigned long long **ptr);
+
 hipError_t launch_moments3(hipStream_t s, const MomArgs &a);
 hipError_t launch_moments9(hipStream_t s, const MomArgs &a);
 

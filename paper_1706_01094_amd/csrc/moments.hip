@@ -13,6 +13,7 @@
 #include "rng.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace mclg {
 namespace {
@@ -475,6 +476,32 @@ hipError_t launch3(hipStream_t s, const MomArgs &a) {
 }
 
 }  // namespace
+
+// Partial records of mclg_moments_noalloc: a fixed array in device memory
+// (one per GPU, alive until the process ends), so that the call needs no
+// workspace.  Host code must not pass this name to a kernel -- on the host it
+// is only a stand-in for the symbol; moments_scratch() returns the device
+// address.
+static __device__ __align__(256) unsigned long long scratch[kMomScratchBytes / 8];
+
+hipError_t moments_scratch(unsigned long long **ptr) {
+  // device addresses of `scratch`, looked up once per device
+  static std::mutex mu;
+  static unsigned long long *addr[kMomScratchDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return e;
+  if (dev < 0 || dev >= (int)kMomScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e) return e;
+    addr[dev] = static_cast<unsigned long long *>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n) {
   MomPlan p;

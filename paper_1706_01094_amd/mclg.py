@@ -28,6 +28,7 @@ MAX_HIST_BINS = 4096
 MOMENTS_DIGEST = 1
 DRAIN_AUTO, DRAIN_DEFERRED, DRAIN_CHUNK, DRAIN_PATCH = 0, 1, 2, 3
 OK, E_INVAL, E_RANGE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_FULL, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+E_TOO_LARGE = -8
 
 u32, u64, i32, i64, dbl, vp = ct.c_uint32, ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_double, ct.c_void_p
 P = ct.POINTER
@@ -98,6 +99,7 @@ _SIGS = {
     "mclg_step_replica": [vp, u32, u64],
     "mclg_step_graph": [vp, u64],
     "mclg_moments": [vp, vp, u32, u32, P(mclg_moments_t)],
+    "mclg_moments_noalloc": [vp, vp, u32, u32, vp],
     "mclg_histogram": [vp, u32, vp],
     "mclg_moments9": [vp, P(mclg_moments9_t)],
     "mclg_d2q9_rules": [P(u32), P(u32), P(u32)],
@@ -365,6 +367,24 @@ class Lattice:
         if rc != OK and not (allow_range and rc == E_RANGE):
             raise MclgError(rc, "mclg_moments")
         return [o.as_dict() for o in out]
+
+    def moments_to_device(self, out, twiddle=None, n_modes: int = 0, digest=False):
+        """mclg_moments_noalloc: the moments of every replica written, in the
+        stream order of this lattice's stream and without allocating or
+        synchronising, into ``out`` (a contiguous int64 tensor of at least
+        n_replicas * 33 elements on the device, one mclg_moments_t per
+        replica); t is the device's step counter."""
+        words = ct.sizeof(mclg_moments_t) // 8
+        if out.dtype != self.torch.int64 or out.numel() < words * self.n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of n_replicas * 33 values")
+        tw = 0
+        if twiddle is not None:
+            if twiddle.numel() < 2 * n_modes * int(self.L.sum()) or twiddle.element_size() != 4:
+                raise ValueError("twiddle must hold 2 * n_modes * sum(L) int32 values")
+            tw = twiddle.data_ptr()
+        _check(lib().mclg_moments_noalloc(self.ctx, tw, n_modes, MOMENTS_DIGEST if digest else 0,
+                                          out.data_ptr()), "mclg_moments_noalloc")
+        return out
 
     def histogram(self, n_bins: int, out=None):
         """Add this state's occupation-number histograms to ``out`` (an int64

@@ -3,13 +3,18 @@
 One step = one fused stream + Monte Carlo collide pass over every site of the
 workload (D1Q3, L = 2^24, rho = 50, u0 = 0.1, C = 10, lambda = 1, Poisson
 initial state, seed 2).  Prints one JSON line with site updates per second,
-the HBM roofline of the fused kernel, and the oracle timed on the host.
+the HBM roofline of the fused kernel, and the oracle timed on the host; the
+other workloads (an HBM-resident lattice, the 1024-replica batch, the
+density wave, the served trace, D2Q9) follow under "extra".
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--extra]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu]
+    python bench.py --only plain|probe|batched|wave|served|d2q9|moments
+    python bench.py --copy-probe BYTES     (counter calibration: device copies)
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as ct
 import hashlib
 import json
 import os
@@ -21,16 +26,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_SITE_UPDATE = 12     # 3 x uint16 read + 3 x uint16 written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_L16M.json")
+INFINITY_CACHE_BYTES = 256 << 20
+PROFILES = os.path.join(ROOT, "profiles")
+# HBM traffic of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# per workload (valid while the kernel's sources are unchanged)
+TRAFFIC_FILES = {
+    "plain": os.path.join(PROFILES, "traffic_stream_collide_L16M.json"),
+    "probe": os.path.join(PROFILES, "traffic_stream_collide_L128M.json"),
+    "batched": os.path.join(PROFILES, "traffic_stream_collide_1024_replicas.json"),
+}
+TRAFFIC_FILE = TRAFFIC_FILES["plain"]
 # the sources the D1Q3 step kernel is compiled from
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
                for f in ("kernels.hip", "rng.h", "device.h")]
 
-
 # the D2Q9 step kernel: its sources and its counted VALU instructions per site
 D2Q9_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
              for f in ("kernels_d2q9.hip", "rng.h", "device.h", "d2q9.h")]
-D2Q9_VALU_FILE = os.path.join(ROOT, "profiles", "valu_d2q9_4096x4096.json")
+D2Q9_VALU_FILE = os.path.join(PROFILES, "valu_d2q9_4096x4096.json")
 # VALU issue of MI355X: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
 # every 4 cycles (16 lanes wide), 2.4 GHz
 VALU_PEAK_G = 256 * 4 / 4 * 2.4
@@ -44,11 +57,11 @@ def kernel_hash(paths=None) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source."""
+def measured_traffic(which: str = "plain"):
+    """HBM bytes per launch from the committed rocprofv3 counter runs of this
+    workload, if they were taken on the current kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[which]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -57,10 +70,27 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
 def cpu_baseline(budget_s: float = 15.0) -> dict:
     """The oracle (single-threaded C) on a bounded sample of the workload:
-    the first 2^20 sites' worth of lattice (its own periodic lattice of that
-    length, same rho, u0, seed), stepped until ~budget_s of CPU time."""
+    a periodic lattice of 2^20 sites of the same density, velocity and seed,
+    stepped until ~budget_s of CPU time."""
     import oracle as O
     import synth
     w = synth.PLAIN_LARGE
@@ -77,7 +107,14 @@ def cpu_baseline(budget_s: float = 15.0) -> dict:
     sim.close()
     return {"value": steps * L / dt, "unit": "site updates/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle on a periodic L=2^20 lattice of the same workload "
-                      f"(rho=50, u0=0.1, C=10), {steps} steps timed after 1 warm-up step"}
+                      f"(rho=50, u0=0.1, C=10), {steps} steps timed after 1 warm-up step",
+            "host": host_info()}
+
+
+def _events(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return e0, e1
 
 
 def run_plain(args, torch, M):
@@ -90,11 +127,13 @@ def run_plain(args, torch, M):
         lat.set_schedule(g, t, b)
     stream = lat.stream
     cov, lds_bytes = lat.lds_coverage()
-    run_plain.lds = {"expected_lds_fraction": round(cov, 5), "lds_bytes": lds_bytes}
+    info = {"expected_lds_fraction": round(cov, 5), "lds_bytes": lds_bytes,
+            "state_bytes": 6 * L,
+            "state_resident_in": "infinity cache (96 MiB of 256 MB)"
+            if 6 * L <= INFINITY_CACHE_BYTES else "hbm"}
     lat.step(args.warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = _events(torch, stream)
     t0 = time.perf_counter()
     e0.record(stream)
     if args.graph:
@@ -113,9 +152,9 @@ def run_plain(args, torch, M):
     rc = lat.check()
     if rc != 0:
         raise SystemExit(f"device error {rc}")
-    run_plain.stats = plain_statistics(lat, args.stat_logs)
+    stats = plain_statistics(lat, args.stat_logs)
     lat.close()
-    return L, gpu_ms, wall
+    return L, gpu_ms, wall, info, stats
 
 
 def plain_statistics(lat, logs: int) -> dict:
@@ -154,16 +193,69 @@ def run_probe(args, torch, M):
     lat.close()
     if rc != 0:
         raise SystemExit(f"device error {rc} in the roofline probe")
+    achieved = BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9
+    traffic = measured_traffic("probe")
     return {"workload": "d1q3_L128M_rho50_u0.1", "L": L, "steps": args.probe_steps,
+            "state_resident_in": "hbm (768 MiB)",
             "ms_per_step": ms, "site_updates_per_s": L / (ms / 1e3),
-            "achieved_GBps": BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9,
-            "frac": BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+            "achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "traffic_over_algorithmic": None if traffic is None else
+            traffic / (BYTES_PER_SITE_UPDATE * L)}
 
 
-def _events(torch, stream):
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    return e0, e1
+def sk_twiddles(torch, Ls, n_modes: int, device):
+    """int32 twiddles of S(k) for every replica, built on the device: replica
+    r's block is [2 n_modes][L_r] with rows round(2^24 cos(2 pi m x / L_r)),
+    round(2^24 sin(...)), m = 1..n_modes (input data of the moments call)."""
+    Ls = [int(v) for v in Ls]
+    total = sum(Ls)
+    out = torch.empty(2 * n_modes * total, dtype=torch.int32, device=device)
+    L_t = torch.tensor(Ls, dtype=torch.int64, device=device)
+    rep = torch.repeat_interleave(torch.arange(len(Ls), device=device), L_t)
+    dense = torch.cumsum(L_t, 0) - L_t
+    x = torch.arange(total, dtype=torch.int64, device=device) - dense[rep]
+    Lr = L_t[rep]
+    base = 2 * n_modes * dense[rep] + x
+    for m in range(1, n_modes + 1):
+        ph = (2.0 * torch.pi) * ((m * x) % Lr).to(torch.float64) / Lr.to(torch.float64)
+        s = float(1 << 24)
+        out[base + (2 * (m - 1)) * Lr] = torch.round(s * torch.cos(ph)).to(torch.int32)
+        out[base + (2 * (m - 1) + 1) * Lr] = torch.round(s * torch.sin(ph)).to(torch.int32)
+    return out
+
+
+def batched_observables(lat, torch, man, samples: int, every: int) -> dict:
+    """After the timed steps: exact int64 per-replica sums every `every`
+    steps -- mean and variance of n_i (Poisson: var/mean = 1) and the static
+    structure factor S(k) = <|sum_x N(x) e^(i k x)|^2> / L for k = 2 pi m / L,
+    m = 1..8, over all replicas (an ideal gas gives S(k) = rho)."""
+    import numpy as np
+    n_modes = 8
+    tw = sk_twiddles(torch, man["L"], n_modes, lat.device)
+    L = man["L"].astype(np.float64)
+    rho = man["rho"]
+    vm, sk = [], []
+    for _ in range(samples):
+        lat.step(every)
+        ms = lat.moments(tw, n_modes)
+        v = np.zeros(3)
+        s = np.zeros(n_modes)
+        for r, m in enumerate(ms):
+            mean = np.array(m["sum_n"], dtype=np.float64) / L[r]
+            var = np.array(m["sum_n2"], dtype=np.float64) / L[r] - mean ** 2
+            v += var / mean
+            f = np.array(m["fourier"][:n_modes], dtype=np.float64) / float(1 << 24)
+            s += (f[:, 0] ** 2 + f[:, 1] ** 2) / L[r] / rho[r]
+        vm.append(v / len(ms))
+        sk.append(s / len(ms))
+    del tw
+    vm, sk = np.array(vm), np.array(sk)
+    return {"samples": samples, "every": every, "replicas": len(man["L"]),
+            "var_over_mean": [round(float(x), 5) for x in vm.mean(0)],
+            "S_k_over_rho": [round(float(x), 4) for x in sk.mean(0)],
+            "S_k_over_rho_se": [round(float(x), 4) for x in sk.std(0, ddof=1) /
+                                np.sqrt(len(sk))] if samples > 1 else None}
 
 
 def run_batched(args, torch, M):
@@ -179,7 +271,7 @@ def run_batched(args, torch, M):
                           steps=10, use_cache=False)
     lat.set_schedule(*tuned["schedule"])
     out = {"workload": "d1q3_1024_replicas", "replicas": len(man["L"]), "sites": sites,
-           "schedule": list(tuned["schedule"]),
+           "state_bytes": int(lat.state_bytes), "schedule": list(tuned["schedule"]),
            "autotune_trials": [[*t["schedule"], round(t.get("seconds_per_step", -1) * 1e6, 1)]
                                for t in tuned["trials"]]}
     lat.step(args.batched_warmup)
@@ -197,8 +289,14 @@ def run_batched(args, torch, M):
         e1.record(lat.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        out[mode] = {"steps": args.batched_steps, "ms": ms,
-                     "site_updates_per_s": sites * args.batched_steps / (ms / 1e3)}
+        rate = sites * args.batched_steps / (ms / 1e3)
+        out[mode] = {"steps": args.batched_steps, "ms": ms, "us_per_step":
+                     1e3 * ms / args.batched_steps, "site_updates_per_s": rate,
+                     "hbm_frac": BYTES_PER_SITE_UPDATE * rate / 1e9 / HBM_PEAK_GBS}
+    traffic = measured_traffic("batched")
+    out["traffic"] = traffic
+    out["traffic_over_algorithmic"] = None if traffic is None else \
+        traffic / (BYTES_PER_SITE_UPDATE * sites)
     # plain: one launch per replica per step
     n = len(man["L"])
     e0, e1 = _events(torch, lat.stream)
@@ -220,20 +318,67 @@ def run_batched(args, torch, M):
         out["plain_per_replica"]["site_updates_per_s"]
     if lat.check() != 0:
         raise SystemExit("device error in the batched run")
-    m = lat.moments()
-    out["t"] = int(m[0]["t"])
+    if args.batched_samples:
+        out["observables"] = batched_observables(lat, torch, man, args.batched_samples, 100)
+    out["t"] = int(lat.moments()[0]["t"])
     lat.close()
     return out
 
 
-def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, time_limit):
+def run_wave(args, torch, M):
+    """Decaying density wave, L = 2^22, 5000 steps, the int64 Fourier
+    projection of the density every 10 steps, logged on the device (the
+    allocation-free moments call writes each record into a device array; the
+    host reads the 500 records once).  A(t) is Eq. (A)'s least-squares
+    amplitude of the profile N(x) against sin(2 pi x / L)."""
+    import numpy as np
+    import synth
+    w = synth.DENSITY_WAVE
+    L = w["L"]
+    counts = synth.density_wave_counts()
+    tw = synth.twiddles(L, 1)
+    lat = M.Lattice(L, w["seed"], counts=counts)
+    twd = torch.as_tensor(tw).to(lat.device)
+    logs = w["steps"] // w["log_every"]
+    words = ct.sizeof(M.mclg_moments_t) // 8
+    rec = torch.zeros((logs, words), dtype=torch.int64, device=lat.device)
+    lat.stream.wait_stream(torch.cuda.current_stream(lat.device))
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, lat.stream)
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    for k in range(logs):
+        lat.step(w["log_every"])
+        lat.moments_to_device(rec[k], twd, 1)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    host = rec.cpu().numpy()
+    lat.close()
+    # field offsets (in int64 words) of the record
+    off_sin = (M.mclg_moments_t.fourier.offset // 8) + 1
+    off_t = M.mclg_moments_t.t.offset // 8
+    # Eq. (A): A = sum_x sin(2 pi x / L) N(x) / sum_x sin^2(2 pi x / L); the
+    # twiddles are s(x) = round(2^24 sin), so A = 2^24 sum N s / sum s^2
+    ss = float(np.sum(tw[1].astype(np.float64) ** 2))
+    amp = host[:, off_sin].astype(np.float64) * float(1 << 24) / ss
+    return {"workload": "d1q3_L4M_wave_rho40", "steps": w["steps"], "logs": logs,
+            "gpu_ms": ms, "wall_s": wall,
+            "site_updates_per_s_incl_logging": L * w["steps"] / (ms / 1e3),
+            "amplitude_expected_initial": w["rho"] * w["amp"],
+            "amplitude_first": float(amp[0]), "amplitude_last": float(amp[-1]),
+            "t_first": int(host[0, off_t]), "t_last": int(host[-1, off_t])}
+
+
+def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, window, time_limit):
     """Real-time driver: jobs are submitted when their arrival time has
     passed; the server advances all resident jobs k steps per tick."""
     srv = M.Server(arena_bytes, max_slots, seed)
     t0 = time.perf_counter()
     nxt = 0
     done = {}
-    work = 0
+    backlog = None
     while len(done) < len(jobs):
         now = time.perf_counter() - t0
         if now > time_limit:
@@ -243,6 +388,8 @@ def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, time_limit):
             srv.submit(j["job_id"], j["L"], j["steps"], j["rho"], j["u0"])
             nxt += 1
         q, r, _ = srv.stats()
+        if backlog is None and now >= window:
+            backlog = {"queued": int(q), "resident": int(r), "completed": len(done)}
         if q == 0 and r == 0:
             if nxt < len(jobs):
                 time.sleep(max(0.0, min(0.01, jobs[nxt]["arrival"] - now)))
@@ -258,6 +405,7 @@ def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, time_limit):
     span = max(done.values()) - jobs[0]["arrival"] if done else 0.0
     pct = (lambda f: lat[min(len(lat) - 1, int(f * len(lat)))] if lat else None)
     return {"jobs": len(jobs), "completed": len(done), "queued_at_end": q, "resident_at_end": r,
+            "backlog_at_window_end": backlog,
             "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99),
             "site_updates_per_s": work / span if span > 0 else 0.0,
             "span_s": span, "site_updates": work}
@@ -265,7 +413,10 @@ def _serve(M, torch, jobs, arena_bytes, max_slots, seed, k, time_limit):
 
 def run_served(args, torch, M, capacity):
     """Poisson arrivals (200 jobs/s) of jobs with L log-uniform in
-    [2^12, 2^24], steps U{100..5000}, rho U{5..100}; 200 GB arena."""
+    [2^12, 2^24], steps U{100..5000}, rho U{5..100}; 200 GB arena.  The
+    offered work exceeds the device's capacity by design, so latency grows
+    with the arrival window; a second trace arrives at 0.8 x the measured
+    batched capacity."""
     import synth
     cfg = synth.SERVED
     out = {"workload": "d1q3_served_200_per_s", "arena_bytes": cfg["budget"]}
@@ -274,44 +425,15 @@ def run_served(args, torch, M, capacity):
     out["trace"] = {"window_s": args.serve_window, "jobs": len(jobs),
                     "offered_site_updates_per_s": offered}
     out["overloaded"] = _serve(M, torch, jobs, cfg["budget"], 8192, cfg["seed"], 50,
-                               args.serve_limit)
-    # sustainable rate: 0.8 x measured batched capacity
+                               args.serve_window, args.serve_limit)
     mean_work = offered / cfg["rate"]
     rate = 0.8 * capacity / mean_work
-    jobs2 = synth.job_trace(args.serve_window * 2, rate=rate, seed=cfg["seed"] + 1)
-    out["sustainable"] = {"rate_jobs_per_s": rate, "jobs": len(jobs2),
+    jobs2 = synth.job_trace(args.serve_window, rate=rate, seed=cfg["seed"] + 1)
+    out["sustainable"] = {"rate_jobs_per_s": rate, "window_s": args.serve_window,
+                          "jobs": len(jobs2),
                           **_serve(M, torch, jobs2, cfg["budget"], 8192, cfg["seed"], 50,
-                                   args.serve_limit)}
+                                   args.serve_window, args.serve_limit)}
     return out
-
-
-def run_wave(args, torch, M):
-    """Decaying density wave, L = 2^22, 5000 steps, int64 Fourier projection
-    (Eq. (A)) every 10 steps."""
-    import numpy as np
-    import synth
-    w = synth.DENSITY_WAVE
-    L = w["L"]
-    counts = synth.density_wave_counts()
-    tw = synth.twiddles(L, 1)
-    lat = M.Lattice(L, w["seed"], counts=counts)
-    twd = torch.as_tensor(tw).to(lat.device)
-    den = float(np.sum(tw[1].astype(np.float64) ** 2))
-    amp = []
-    e0, e1 = _events(torch, lat.stream)
-    t0 = time.perf_counter()
-    e0.record(lat.stream)
-    for _ in range(w["steps"] // w["log_every"]):
-        lat.step(w["log_every"])
-        m = lat.moments(twd, 1)[0]
-        amp.append(m["fourier"][0][1] / den)
-    e1.record(lat.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat.close()
-    return {"workload": "d1q3_L4M_wave_rho40", "steps": w["steps"], "logs": len(amp),
-            "wall_s": wall, "site_updates_per_s_incl_logging": L * w["steps"] / wall,
-            "amplitude_first": amp[0], "amplitude_last": amp[-1]}
 
 
 def run_d2q9(args, torch, M):
@@ -351,6 +473,36 @@ def run_d2q9(args, torch, M):
     return out
 
 
+def run_moments(args, torch, M):
+    """The moment kernels alone (for kernel traces): exact moments of the
+    L = 2^24 lattice (no modes), of the L = 2^22 density wave (one mode), and
+    of the 4096 x 4096 D2Q9 lattice, 20 calls each."""
+    import synth
+    out = {}
+    w = synth.PLAIN_LARGE
+    lat = M.Lattice(w["L"], w["seed"], rho=w["rho"], u0=w["u0"])
+    t0 = time.perf_counter()
+    for _ in range(20):
+        lat.moments()
+    out["d1q3_L16M"] = {"calls": 20, "wall_ms_per_call": (time.perf_counter() - t0) * 50}
+    lat.close()
+    wv = synth.DENSITY_WAVE
+    lat = M.Lattice(wv["L"], wv["seed"], counts=synth.density_wave_counts())
+    twd = torch.as_tensor(synth.twiddles(wv["L"], 1)).to(lat.device)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        lat.moments(twd, 1)
+    out["d1q3_L4M_one_mode"] = {"calls": 20, "wall_ms_per_call": (time.perf_counter() - t0) * 50}
+    lat.close()
+    lat = M.Lattice9(4096, 4096, 9, C=10, rho=36.0, ux=0.0, uy=0.0)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        lat.moments()
+    out["d2q9_4096x4096"] = {"calls": 20, "wall_ms_per_call": (time.perf_counter() - t0) * 50}
+    lat.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,22 +512,30 @@ def main():
     ap.add_argument("--graph", action="store_true", help="launch steps from captured HIP graphs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="only the plain headline (skip batched, served, density wave)")
+                    help="only the plain headline (skip the other workloads)")
+    ap.add_argument("--only", default="",
+                    choices=["", "plain", "probe", "batched", "wave", "served", "d2q9", "moments"],
+                    help="run one workload and print its result")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--batched-warmup", type=int, default=20)
+    ap.add_argument("--batched-samples", type=int, default=10,
+                    help="S(k) and var/mean samples after the timed batched steps")
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--probe-steps", type=int, default=200)
     ap.add_argument("--stat-logs", type=int, default=10)
-    ap.add_argument("--serve-window", type=float, default=2.0)
-    ap.add_argument("--serve-limit", type=float, default=60.0)
+    ap.add_argument("--serve-window", type=float, default=10.0)
+    ap.add_argument("--serve-limit", type=float, default=120.0)
     ap.add_argument("--d2q9-steps", type=int, default=50)
     ap.add_argument("--d2q9-warmup", type=int, default=5)
-    ap.add_argument("--d2q9-only", action="store_true", help="only the D2Q9 measurement")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="only the 1024-replica batched measurement")
+    ap.add_argument("--d2q9-only", action="store_true", help="same as --only d2q9")
+    ap.add_argument("--batched-only", action="store_true", help="same as --only batched")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 8 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.d2q9_only:
+        args.only = "d2q9"
+    if args.batched_only:
+        args.only = "batched"
     if args.copy_probe:
         import torch
         src = torch.empty(args.copy_probe // 4, dtype=torch.int32, device="cuda:0").fill_(1)
@@ -395,17 +555,19 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
 
-    if args.d2q9_only:
-        print(json.dumps({"d2q9": run_d2q9(args, torch, M)}), flush=True)
+    legs = {"probe": run_probe, "batched": run_batched, "wave": run_wave,
+            "d2q9": run_d2q9, "moments": run_moments}
+    if args.only in legs:
+        print(json.dumps({args.only: legs[args.only](args, torch, M)}), flush=True)
         return
-    if args.batched_only:
-        print(json.dumps({"batched": run_batched(args, torch, M)}), flush=True)
+    if args.only == "served":
+        cap = run_batched(args, torch, M)["batched"]["site_updates_per_s"]
+        print(json.dumps({"served": run_served(args, torch, M, cap)}), flush=True)
         return
-    L, gpu_ms, wall = run_plain(args, torch, M)
+    L, gpu_ms, wall, info, stats = run_plain(args, torch, M)
     ms_per_step = gpu_ms / args.steps
     value = L * args.steps / (gpu_ms / 1e3)
     achieved = BYTES_PER_SITE_UPDATE * L / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic()
     out = {
         "metric": "site updates/s (stream+MC collide, D1Q3), % HBM peak; batched vs plain",
         "value": value,
@@ -421,16 +583,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "d1q3_L16M_rho50_u0.1", "L": L, "rho": 50.0, "u0": 0.1, "C": 10,
                    "lambda": 1, "n_max": 255, "seed": 2, "launch": "graph" if args.graph else "plain",
-                   "schedule": args.schedule or "default", **getattr(run_plain, "lds", {})},
+                   "schedule": args.schedule or "default", **info},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "statistics": getattr(run_plain, "stats", None),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("plain")},
+        "statistics": stats,
     }
+    if args.only == "plain":
+        args.no_extra = True
     if not args.no_extra:
         extra = {}
         extra["roofline_probe"] = run_probe(args, torch, M)
         torch.cuda.empty_cache()
         extra["batched"] = run_batched(args, torch, M)
+        torch.cuda.empty_cache()
         extra["density_wave"] = run_wave(args, torch, M)
         torch.cuda.empty_cache()
         extra["served"] = run_served(args, torch, M, extra["batched"]["batched"]["site_updates_per_s"])

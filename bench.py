@@ -267,8 +267,12 @@ def run_batched(args, torch, M):
     sites = int(man["L"].sum())
     lat = M.Lattice(man["L"], synth.BATCHED["seed"], rho=man["rho"], u0=man["u0"],
                     replica_id=man["replica_id"])
-    tuned = autotune.tune(man["L"], man["rho"], man["u0"], replica_id=man["replica_id"],
-                          steps=10, use_cache=False)
+    if args.batched_schedule == "auto":
+        tuned = autotune.tune(man["L"], man["rho"], man["u0"], replica_id=man["replica_id"],
+                              steps=10, use_cache=False)
+    else:  # a given schedule (profiling runs: no tuning launches)
+        tuned = {"schedule": tuple(int(v) for v in args.batched_schedule.split(",")),
+                 "trials": []}
     lat.set_schedule(*tuned["schedule"])
     out = {"workload": "d1q3_1024_replicas", "replicas": len(man["L"]), "sites": sites,
            "state_bytes": int(lat.state_bytes), "schedule": list(tuned["schedule"]),
@@ -518,6 +522,8 @@ def main():
                     help="run one workload and print its result")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--batched-warmup", type=int, default=20)
+    ap.add_argument("--batched-schedule", default="auto",
+                    help="'auto' (autotuned) or groups,threads,lds_bytes")
     ap.add_argument("--batched-samples", type=int, default=10,
                     help="S(k) and var/mean samples after the timed batched steps")
     ap.add_argument("--plain-steps", type=int, default=20)

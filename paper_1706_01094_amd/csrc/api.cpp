@@ -33,7 +33,7 @@ struct Layout {
   uint64_t total_sites = 0, max_tiles = 0;
   // workspace byte offsets
   uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
-      o_rowbase, o_rowdesc, o_thr, o_fixed, ws_bytes;
+      o_rowbase, o_rowdesc, o_thr, o_fixed, o_row16, ws_bytes;
   // moment kernels: segments, runs (one per slot), partial records, results
   MomPlan mplan;
   uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout;
@@ -85,6 +85,7 @@ bool compute_layout(uint32_t n, const uint64_t *L, const CollisionTables *tab, L
   lay.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
   lay.o_thr = take(sizeof(uint32_t) * (tab->thr.size() + 16));  // +16: see count_le_16
   lay.o_fixed = take(sizeof(uint32_t) * tab->fixed.size());
+  lay.o_row16 = take(sizeof(uint16_t) * tab->row16.size());
   lay.ws_bytes = o;
   return true;
 }
@@ -175,6 +176,7 @@ struct mclg_ctx {
     d.rowdesc = reinterpret_cast<const uint2 *>(ws + lay.o_rowdesc);
     d.thr = reinterpret_cast<const uint32_t *>(ws + lay.o_thr);
     d.fixed = tab->fixed.empty() ? nullptr : reinterpret_cast<const uint4 *>(ws + lay.o_fixed);
+    d.row16 = tab->row16.empty() ? nullptr : reinterpret_cast<const uint4 *>(ws + lay.o_row16);
     return d;
   }
   StepParams params() const {
@@ -434,6 +436,7 @@ int mclg_init(const mclg_config *cfg, const mclg_init_spec *init, mclg_ctx **out
   if (!e) e = up(lay.o_rowdesc, tab->rowdesc.data(), sizeof(uint32_t) * tab->rowdesc.size());
   if (!e) e = up(lay.o_thr, tab->thr.data(), sizeof(uint32_t) * tab->thr.size());
   if (!e && !tab->fixed.empty()) e = up(lay.o_fixed, tab->fixed.data(), sizeof(uint32_t) * tab->fixed.size());
+  if (!e && !tab->row16.empty()) e = up(lay.o_row16, tab->row16.data(), sizeof(uint16_t) * tab->row16.size());
   const uint32_t ts = c->sch.tile_sites();
   if (init->kind == MCLG_INIT_POISSON) {
     if (!e) e = up(lay.o_pdesc, pdesc.data(), sizeof(PoisDesc) * pdesc.size());

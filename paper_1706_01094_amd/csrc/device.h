@@ -68,11 +68,16 @@ inline uint32_t auto_drain(uint64_t launch_state_bytes) {
 // k_first | q << 16 and up to 19 thresholds.
 constexpr uint32_t kFixedStride = 20;
 
+// uint16 values per row of the 64-byte copy of the collision rows: k_first,
+// q and the top 16 bits of up to 30 thresholds (0xFFFF beyond q - 1).
+constexpr uint32_t kRow16 = 32;
+
 struct TableDev {
   const uint32_t *rowbase = nullptr;
   const uint2 *rowdesc = nullptr;
   const uint32_t *thr = nullptr;
   const uint4 *fixed = nullptr;  // rows at a fixed stride of kFixedStride uint32, or null
+  const uint4 *row16 = nullptr;  // rows of kRow16 uint16 (64 bytes), or null
 };
 
 // Where a slot's LDS image lives in the image pool (see LdsImage).

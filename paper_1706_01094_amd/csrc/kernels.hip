@@ -139,9 +139,40 @@ __device__ __forceinline__ uint32_t count_le_16(const uint32_t *t, uint32_t n, u
   return c;
 }
 
+// Two 16-bit lanes of a 32-bit register.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
                                                    uint32_t b, uint32_t par, uint32_t r) {
   const uint32_t row = fiber_base(N, absJ) + ((b - par) >> 1);  // states ascend in n0
+  if (tab.row16 && (r >> 16) < 0xffffu) {
+    // one 64-byte row of 16-bit values: k_first, q, the thresholds' top 16
+    // bits (0xFFFF padding).  With lt = #{t < rh} and le = #{t <= rh}, the
+    // outcome is k_first + lt when lt = le; a threshold whose top bits equal
+    // rh is decided only by its full 32 bits (the rows below).  The second
+    // half of the row holds thresholds 14..29 and is counted when q > 15.
+    const uint4 *q = tab.row16 + (size_t)row * (kRow16 / 8);
+    uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];  // all four loads at once
+    // (kept together: the second half is not to be loaded only under the
+    // branch below, a second round trip)
+    asm volatile("" : "+v"(q2.x), "+v"(q2.y), "+v"(q2.z), "+v"(q2.w), "+v"(q3.x), "+v"(q3.y),
+                 "+v"(q3.z), "+v"(q3.w));
+    const uint32_t rh = r >> 16;
+    const u16x2 R = __builtin_bit_cast(u16x2, rh * 0x10001u);
+    const u16x2 R1 = __builtin_bit_cast(u16x2, (rh + 1u) * 0x10001u), one = {1, 1};
+    u16x2 lt = {0, 0}, le = {0, 0};
+    auto add = [&](uint32_t w) {
+      const u16x2 t = __builtin_bit_cast(u16x2, w);
+      lt += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R, t), one);
+      le += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R1, t), one);
+    };
+    add(q0.y); add(q0.z); add(q0.w); add(q1.x); add(q1.y); add(q1.z); add(q1.w);
+    if ((q0.x >> 16) > 15u) {
+      add(q2.x); add(q2.y); add(q2.z); add(q2.w); add(q3.x); add(q3.y); add(q3.z); add(q3.w);
+    }
+    const uint32_t nlt = (uint32_t)lt.x + (uint32_t)lt.y, nle = (uint32_t)le.x + (uint32_t)le.y;
+    if (nlt == nle) return (q0.x & 0xffffu) + nlt;
+  }
   if (tab.fixed) {
     // header and up to 19 thresholds, all five 16-byte pieces at once
     const uint4 *q = tab.fixed + (size_t)row * (kFixedStride / 4);
@@ -260,9 +291,6 @@ struct SlotView {
         reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), 0, (int)(3u * ab), kRsrcWord3);
   }
 };
-
-// Two 16-bit lanes of a 32-bit register.
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // Decision of one site from the LDS image, in three phases so that the LDS
 // reads of several sites are in flight together: (1) directory read, (2)

@@ -32,7 +32,7 @@ inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
   uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
-      o_rowbase, o_rowdesc, o_thr, o_fixed, bytes, max_tiles;
+      o_rowbase, o_rowdesc, o_thr, o_fixed, o_row16, bytes, max_tiles;
   // moments of retiring jobs: segments, runs, partial records, results
   uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout;
 };
@@ -68,6 +68,7 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_rowdesc = take(sizeof(uint32_t) * tab->rowdesc.size());
   l.o_thr = take(sizeof(uint32_t) * (tab->thr.size() + 16));  // +16: see count_le_16
   l.o_fixed = take(sizeof(uint32_t) * tab->fixed.size());
+  l.o_row16 = take(sizeof(uint16_t) * tab->row16.size());
   l.bytes = o;
   return l;
 }
@@ -119,6 +120,7 @@ struct mclg_server {
     d.rowdesc = reinterpret_cast<const uint2 *>(ws + lay.o_rowdesc);
     d.thr = reinterpret_cast<const uint32_t *>(ws + lay.o_thr);
     d.fixed = tab->fixed.empty() ? nullptr : reinterpret_cast<const uint4 *>(ws + lay.o_fixed);
+    d.row16 = tab->row16.empty() ? nullptr : reinterpret_cast<const uint4 *>(ws + lay.o_row16);
     return d;
   }
   int hip(hipError_t e) {
@@ -410,6 +412,7 @@ int mclg_server_create(const mclg_server_config *cfg, mclg_server **out) {
   if (!e) e = sv->up(sv->ws + sv->lay.o_rowdesc, t.rowdesc.data(), 4 * t.rowdesc.size());
   if (!e) e = sv->up(sv->ws + sv->lay.o_thr, t.thr.data(), 4 * t.thr.size());
   if (!e && !t.fixed.empty()) e = sv->up(sv->ws + sv->lay.o_fixed, t.fixed.data(), 4 * t.fixed.size());
+  if (!e && !t.row16.empty()) e = sv->up(sv->ws + sv->lay.o_row16, t.row16.data(), 2 * t.row16.size());
   if (!e) e = hipStreamSynchronize(sv->s);
   if (e) return sv->hip(e);
   *out = sv.release();

@@ -442,6 +442,16 @@ std::shared_ptr<const CollisionTables> collision_tables(int32_t C, uint32_t lam_
       for (uint32_t j = 0; j + 1 < (hdr >> 16); ++j) row[1 + j] = tab->thr[off + j];
     }
   }
+  if (tab->max_q <= kRow16 - 1 && (uint64_t)nrows * kRow16 * 2 < (1ull << 31)) {
+    tab->row16.assign(nrows * kRow16, (uint16_t)0xFFFF);
+    for (size_t r = 0; r < nrows; ++r) {
+      uint16_t *row = &tab->row16[r * kRow16];
+      const uint32_t off = tab->rowdesc[2 * r], hdr = tab->rowdesc[2 * r + 1];
+      row[0] = (uint16_t)(hdr & 0xFFFFu);  // k_first
+      row[1] = (uint16_t)(hdr >> 16);      // q
+      for (uint32_t j = 0; j + 1 < (hdr >> 16); ++j) row[2 + j] = (uint16_t)(tab->thr[off + j] >> 16);
+    }
+  }
   std::shared_ptr<const CollisionTables> res = tab;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache[key] = res;

@@ -29,6 +29,11 @@ struct CollisionTables {
   // row r = {k_first | q << 16, thresholds..., zero padding}, so that a row
   // is found from (N, |J|, n0) by arithmetic and read in one round of loads.
   std::vector<uint32_t> fixed;    // empty when not built
+  // The same rows as 64 bytes of 16-bit values: k_first, q, the top 16 bits
+  // of the q - 1 thresholds, then 0xFFFF (when max_q <= 31).  A draw r whose
+  // top 16 bits equal none of them is decided by the row alone: a threshold
+  // with smaller top bits is <= r, one with larger top bits is > r.
+  std::vector<uint16_t> row16;    // empty when not built
 };
 
 // Build (or fetch from the process cache) the tables for (C, lambda, n_max),

@@ -358,6 +358,86 @@ def d2q9_statistics(us: Sequence[Sequence[float]], rho: float, Lx: int, Ly: int,
             "steps": steps, "every": every, "check": rc, "wall_s": wall}
 
 
+# Table 1 of the paper (the correlator of Eq. (corr) at its worst outlier,
+# u_x = -0.68), rows and columns in the velocity numbering of Eq. (MomD2Q9)
+TABLE1_PAPER = np.array([
+    [0.998863, -0.000028, -0.000482, -0.000170, -0.000343, 0.000001, -0.000114, -0.000082, 0.000010],
+    [-0.000028, 0.999171, 0.000001, 0.000143, -0.000072, -0.000127, -0.000047, 0.000013, 0.000057],
+    [-0.000482, 0.000001, 0.999809, -0.000112, 0.000177, -0.000515, -0.000110, -0.000022, 0.000482],
+    [-0.000170, 0.000143, -0.000112, 1.000230, -0.000079, 0.000014, 0.000008, -0.000048, -0.000067],
+    [-0.000343, -0.000072, 0.000177, -0.000079, 0.999648, 0.000492, -0.000023, -0.000103, -0.000480],
+    [0.000001, -0.000127, -0.000515, 0.000014, 0.000492, 0.999567, -0.000065, -0.000046, 0.000593],
+    [-0.000114, -0.000047, -0.000110, 0.000008, -0.000023, -0.000065, 0.999801, -0.000085, 0.000086],
+    [-0.000082, 0.000013, -0.000022, -0.000048, -0.000103, -0.000046, -0.000022, 0.999687, -0.000117],
+    [0.000010, 0.000057, 0.000482, -0.000067, -0.000480, 0.000593, 0.000086, -0.000117, 0.999215]])
+# (the n_5 diagonal is printed -0.999567; Eq. (corr) makes it +0.999567)
+
+
+def finite_size_correlator(f: np.ndarray, S: int) -> np.ndarray:
+    """The correlator of Eq. (corr) that exact conservation predicts on a
+    lattice of S sites: the stationary law is the product-Poisson measure
+    conditioned on the totals of N, Jx, Jy, whose single-site covariance is
+    D - D M^T (M D M^T)^-1 M D / S to leading order (D = diag f, M the rows
+    1, v_x, v_y), while the mean stays f^eq at the conserved (rho, u); hence
+    K = 1 - P / S with P = D^1/2 M^T (M D M^T)^-1 M D^1/2, a projector of
+    rank 3 (the sum of its diagonal is 3)."""
+    M = np.array([[1.0] * 9, [float(v[0]) for v in V9], [float(v[1]) for v in V9]])
+    D = np.diag(f)
+    sq = np.diag(np.sqrt(f))
+    P = sq @ M.T @ np.linalg.inv(M @ D @ M.T) @ M @ sq
+    return np.eye(9) - P / S
+
+
+def table1_correlator(ux: float = -0.68, uy: float = 0.0, rho: float = 360.0, Lx: int = 100,
+                      Ly: int = 10, C: int = 10, replicas: int = 4096, equil: int = 2000,
+                      steps: int = 300_000, every: int = 25, seed: int = 360) -> dict:
+    """The paper's Table 1 set-up (rho = 360, 100 x 10, C = 10, the lambda_c
+    of its D2Q9 runs) as `replicas` independent lattices in one context,
+    Poisson-started at Eq. (D2Q9eqdist), sampled every `every` steps.  Per
+    replica: the correlator of Eq. (corr) with f = f^eq at the replica's
+    conserved (rho^, u^) ("K"), the same with the replica's measured means
+    ("K_cov"), and the finite-size prediction; the replicas are independent,
+    so the standard errors come from their scatter."""
+    iu = np.triu_indices(9)
+    S = Lx * Ly
+    lat = mclg.Lattice9([Lx] * replicas, Ly, seed, C=C, rho=np.full(replicas, rho),
+                        ux=np.full(replicas, ux), uy=np.full(replicas, uy))
+    t0 = time.time()
+    try:
+        lat.step(equil)
+        n_samp = steps // every
+        sn = np.zeros((replicas, 9))
+        snn = np.zeros((replicas, 45))
+        for _ in range(n_samp):
+            lat.step(every)
+            a = lat.moments_array()
+            sn += a[:, 2:11]
+            snn += a[:, 11:56]
+        a = lat.moments_array()
+        rc = lat.check()
+    finally:
+        lat.close()
+    wall = time.time() - t0
+    N, Jx, Jy = a[:, 56].astype(np.float64), a[:, 57].astype(np.float64), a[:, 58].astype(np.float64)
+    rho_hat, u_hat = N / S, np.stack([Jx / N, Jy / N], 1)
+    mean = sn / (n_samp * S)
+    nn = np.zeros((replicas, 9, 9))
+    nn[:, iu[0], iu[1]] = snn / (n_samp * S)
+    nn = nn + np.triu(nn, 1).transpose(0, 2, 1)
+    f = np.array([feq9(r, *u) for r, u in zip(rho_hat, u_hat)])
+    K_r = (nn - f[:, :, None] * f[:, None, :]) / np.sqrt(f[:, :, None] * f[:, None, :])
+    Kc_r = (nn - mean[:, :, None] * mean[:, None, :]) / np.sqrt(mean[:, :, None] * mean[:, None, :])
+    pred_r = np.array([finite_size_correlator(x, S) for x in f])
+    se = lambda x: x.std(0, ddof=1) / np.sqrt(replicas)  # noqa: E731
+    K, Kc, pred = K_r.mean(0), Kc_r.mean(0), pred_r.mean(0)
+    return {"ux": ux, "uy": uy, "rho": rho, "Lx": Lx, "Ly": Ly, "C": C, "replicas": replicas,
+            "equil": equil, "steps": steps, "every": every, "wall_s": wall, "check": rc,
+            "rho_hat": float(rho_hat.mean()), "u_hat": u_hat.mean(0),
+            "K": K, "K_se": se(K_r), "K_cov": Kc, "K_cov_se": se(Kc_r), "pred": pred,
+            "E": float(((K - np.eye(9)) ** 2).sum()), "E_pred": float(((pred - np.eye(9)) ** 2).sum()),
+            "paper": TABLE1_PAPER * np.where(np.eye(9, dtype=bool) & (TABLE1_PAPER < 0), -1, 1)}
+
+
 def d2q9_histograms(ux: float = -0.25, uy: float = 0.25, rho: float = 18.0, Lx: int = 512,
                     Ly: int = 512, C: int = 10, equil: int = 200, n_bins: int = 48,
                     seed: int = 1) -> dict:
@@ -507,22 +587,25 @@ def _d2q9hist(quick: bool):
 
 
 def _table1(quick: bool):
-    uxs = [0.0, 0.1, 0.25, 0.4]
-    kw = dict(equil=1500, steps=5000) if quick else dict(equil=150000, steps=500000)
-    r = d2q9_statistics([(u, 0.0) for u in uxs], 360.0, 100, 10, every=10, **kw)
-    print(f"D2Q9 correlators (Eq. (corr), Table 1 set-up): rho=360, uy=0, 100x10, C={r['C']}, "
-          f"{r['equil']} + {r['steps']} steps ({r['wall_s']:.1f} s)")
-    for k in range(len(uxs)):
-        K = r["K"][k]
-        off = K - np.diag(np.diag(K))
-        z = np.abs(K - np.eye(9)) / r["K_se"][k]
-        print(f"  ux^ = {r['u_hat'][k, 0]:+.4f}: diagonal {np.diag(K).min():.6f} .. "
-              f"{np.diag(K).max():.6f}, largest |off-diagonal| {np.abs(off).max():.2e}, "
-              f"E(u) = {r['E'][k]:.3e}; standard errors {r['K_se'][k].min():.1e} .. "
-              f"{r['K_se'][k].max():.1e}, largest |K - delta| / se {z.max():.1f}")
-    print("  K at the first velocity:")
-    for row in r["K"][0]:
-        print("   " + " ".join(f"{v:+.5f}" for v in row))
+    kw = dict(replicas=1024, steps=20_000) if quick else {}
+    r = table1_correlator(**kw)
+    print(f"Table 1 set-up (Eq. (corr)): rho={r['rho']}, ux={r['ux']}, uy={r['uy']}, "
+          f"{r['Lx']}x{r['Ly']}, C={r['C']}, {r['replicas']} replicas, {r['equil']} + "
+          f"{r['steps']} steps sampled every {r['every']} ({r['wall_s']:.1f} s, check {r['check']})")
+    for name, key in (("measured K (f = f^eq at the conserved rho, u)", "K"),
+                      ("measured K with the replicas' own means", "K_cov"),
+                      ("finite-size prediction 1 - P/S", "pred"),
+                      ("paper, Table 1 (n_5 diagonal sign restored)", "paper")):
+        print(f"  {name}:")
+        for i in range(9):
+            print("   " + " ".join(f"{v:+.6f}" for v in r[key][i]))
+    print(f"  standard errors of K: {r['K_se'].min():.1e} .. {r['K_se'].max():.1e}; of K_cov: "
+          f"{r['K_cov_se'].min():.1e} .. {r['K_cov_se'].max():.1e}")
+    z = np.abs(r["K"] - r["pred"]) / r["K_se"]
+    zc = np.abs(r["K_cov"] - r["pred"]) / r["K_cov_se"]
+    print(f"  largest |K - prediction| / se {z.max():.2f}, |K_cov - prediction| / se {zc.max():.2f}")
+    print(f"  E(u) measured {r['E']:.3e}, predicted {r['E_pred']:.3e}, paper "
+          f"{((r['paper'] - np.eye(9)) ** 2).sum():.3e}")
 
 
 def main(argv=None):

@@ -515,11 +515,21 @@ class Lattice9:
         return out
 
     def moments(self, allow_range=False):
+        return [o.as_dict() for o in self._moments9(allow_range)]
+
+    def moments_array(self, allow_range=False) -> np.ndarray:
+        """The same sums as an int64 array [n_replicas, 60] in the field
+        order of mclg_moments9_t (t, sites, sum_n[9], sum_nn[45], sum_N,
+        sum_Jx, sum_Jy, max_N)."""
+        out = self._moments9(allow_range)
+        return np.frombuffer(out, dtype=np.int64).reshape(self.n, -1).copy()
+
+    def _moments9(self, allow_range):
         out = (mclg_moments9_t * self.n)()
         rc = lib().mclg_moments9(self.ctx, out)
         if rc != OK and not (allow_range and rc == E_RANGE):
             raise MclgError(rc, "mclg_moments9")
-        return [o.as_dict() for o in out]
+        return out
 
 
 class Server:

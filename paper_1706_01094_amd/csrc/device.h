@@ -80,6 +80,18 @@ struct TableDev {
   const uint4 *row16 = nullptr;  // rows of kRow16 uint16 (64 bytes), or null
 };
 
+// The 64-byte rows cost a missed draw fewer memory bytes than the 80-byte
+// ones but about 60 more VALU instructions.  They pay when the missed rows
+// come from memory rather than the L2: when the draws of many densities miss
+// (a batch of replicas with their own images), or when one density misses
+// very often.  Measured on MI355X at L = 2^27 (us per step, 80-byte / 64-byte
+// rows): rho = 50, 0.5 % misses 346 / 356; rho = 80, 1.6 % misses 364 / 379;
+// rho = 100, u = 0.2, 10 % misses 447 / 420; the 1024-replica batch (2 %
+// misses over 1024 images) 495 / 465.
+inline bool use_compact_rows(double miss_fraction, uint32_t n_images) {
+  return miss_fraction > 0.06 || (n_images >= 16 && miss_fraction > 0.01);
+}
+
 // Where a slot's LDS image lives in the image pool (see LdsImage).
 struct ImageDesc {
   uint64_t off = 0;        // byte offset in the image pool (16-byte aligned)

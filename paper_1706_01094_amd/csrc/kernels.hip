@@ -145,33 +145,27 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t global_outcome(const TableDev &tab, uint32_t N, uint32_t absJ,
                                                    uint32_t b, uint32_t par, uint32_t r) {
   const uint32_t row = fiber_base(N, absJ) + ((b - par) >> 1);  // states ascend in n0
-  if (tab.row16 && (r >> 16) < 0xffffu) {
+  if (tab.row16) {
     // one 64-byte row of 16-bit values: k_first, q, the thresholds' top 16
-    // bits (0xFFFF padding).  With lt = #{t < rh} and le = #{t <= rh}, the
-    // outcome is k_first + lt when lt = le; a threshold whose top bits equal
-    // rh is decided only by its full 32 bits (the rows below).  The second
-    // half of the row holds thresholds 14..29 and is counted when q > 15.
+    // bits (0xFFFF padding); the outcome is k_first + #{t < rh} unless some
+    // t equals rh, when only the full 32-bit threshold decides (the rows
+    // below)
     const uint4 *q = tab.row16 + (size_t)row * (kRow16 / 8);
-    uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];  // all four loads at once
-    // (kept together: the second half is not to be loaded only under the
-    // branch below, a second round trip)
-    asm volatile("" : "+v"(q2.x), "+v"(q2.y), "+v"(q2.z), "+v"(q2.w), "+v"(q3.x), "+v"(q3.y),
-                 "+v"(q3.z), "+v"(q3.w));
-    const uint32_t rh = r >> 16;
-    const u16x2 R = __builtin_bit_cast(u16x2, rh * 0x10001u);
-    const u16x2 R1 = __builtin_bit_cast(u16x2, (rh + 1u) * 0x10001u), one = {1, 1};
-    u16x2 lt = {0, 0}, le = {0, 0};
-    auto add = [&](uint32_t w) {
-      const u16x2 t = __builtin_bit_cast(u16x2, w);
-      lt += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R, t), one);
-      le += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R1, t), one);
-    };
-    add(q0.y); add(q0.z); add(q0.w); add(q1.x); add(q1.y); add(q1.z); add(q1.w);
-    if ((q0.x >> 16) > 15u) {
-      add(q2.x); add(q2.y); add(q2.z); add(q2.w); add(q3.x); add(q3.y); add(q3.z); add(q3.w);
+    const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+    const uint32_t w[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                            q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    const uint32_t rr = (r >> 16) * 0x10001u;
+    const u16x2 R = __builtin_bit_cast(u16x2, rr), one = {1, 1};
+    u16x2 acc = {0, 0};
+    uint32_t eq = 0;
+#pragma unroll
+    for (int j = 1; j < 16; ++j) {
+      acc += __builtin_elementwise_min(__builtin_elementwise_sub_sat(R, __builtin_bit_cast(u16x2, w[j])),
+                                       one);
+      const uint32_t x = w[j] ^ rr;  // a zero half: that threshold's top bits equal rh
+      eq |= (x - 0x00010001u) & ~x & 0x80008000u;
     }
-    const uint32_t nlt = (uint32_t)lt.x + (uint32_t)lt.y, nle = (uint32_t)le.x + (uint32_t)le.y;
-    if (nlt == nle) return (q0.x & 0xffffu) + nlt;
+    if (eq == 0u) return (w[0] & 0xffffu) + (uint32_t)acc.x + (uint32_t)acc.y;
   }
   if (tab.fixed) {
     // header and up to 19 thresholds, all five 16-byte pieces at once
@@ -685,6 +679,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   const uint32_t cb = blockIdx.x * per;
   const uint32_t ce = min(a.n_tiles, cb + per);
   uint32_t cur = 0xFFFFFFFFu;
+  uint64_t img_off = ~0ull;  // pool offset of the image in LDS
   SlotView sv;
   sv.lo = sv.hi = 0;
   sv.ab = 0;
@@ -716,9 +711,12 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     // one at a time from a shared counter, so that waves issued less often
     // (the hardware favours older waves) take fewer chunks and all finish
     // together.
-    const bool new_image = t0.slot != cur, first = cur == 0xFFFFFFFFu;
+    const bool first = cur == 0xFFFFFFFFu;
     cur = t0.slot;
     const ImageDesc im = a.single ? a.im1 : a.images[cur];
+    // replicas that share an image keep it in LDS from segment to segment
+    const bool new_image = first || im.off != img_off;
+    img_off = im.off;
     const SlotDev sl = a.single ? a.sl1 : a.slots[cur];
     const uint32_t tn = a.tslot[cur] + a.t_off;
     if (!first) __syncthreads();  // previous image and chunk counter no longer in use

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -27,7 +28,8 @@ namespace {
 
 constexpr uint32_t kPad = 128;
 constexpr uint32_t kPoisCap = 1024;
-constexpr uint32_t kImage = 96 * 1024;  // LDS collision image budget per job
+constexpr uint32_t kImage = 160 * 1024;  // LDS collision image budget per job (at most)
+constexpr size_t kImageCacheMax = 4096;   // host images kept for reuse
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct SrvLayout {
@@ -104,6 +106,14 @@ struct mclg_server {
   std::vector<uint32_t> h_pool;
   std::vector<ImageDesc> h_idesc;
   MomPlan h_mplan;  // segments of the jobs being retired
+  // Host images by the (rho, |u0|) they are built for: jobs of equal density
+  // and speed reuse one (the image depends on u0 only through |u0|), and the
+  // cached bytes stay alive while their upload is in flight.
+  struct CachedImage {
+    std::vector<uint8_t> blob;
+    uint32_t dir_bytes = 0, dim_a = 0, dim_c = 0, b_lo = 0, nb = 0;
+  };
+  std::map<std::pair<double, double>, CachedImage> image_cache;
   uint32_t n_tiles = 0, n_active = 0;
   uint32_t lds_bytes = 16, max_blocks = 1, image_budget = kImage, n_cu = 1;
   int last_hip = 0;
@@ -257,21 +267,37 @@ struct mclg_server {
         d.nthr = (uint32_t)cl.thr.size();
         std::copy(cl.thr.begin(), cl.thr.end(), h_pool.begin() + d.off);
       }
-      // collision image for this job's density and velocity
-      LdsImage im = build_image(*tab, j.rho, j.u0, image_budget);
-      auto blob = im.blob();
+      // collision image for this job's density and speed (cached on the host)
+      const auto key = std::make_pair(j.rho, std::fabs(j.u0));
+      auto ci = image_cache.find(key);
+      if (ci == image_cache.end()) {
+        if (image_cache.size() >= kImageCacheMax) {
+          hipError_t e = hipStreamSynchronize(s);  // no upload may still read them
+          if (e) return hip(e);
+          image_cache.clear();
+        }
+        LdsImage im = build_image(*tab, j.rho, std::fabs(j.u0), image_budget);
+        CachedImage c;
+        c.blob = im.blob();
+        c.dir_bytes = im.dir_bytes();
+        c.dim_a = im.dim_a;
+        c.dim_c = im.dim_c;
+        c.b_lo = im.b_lo;
+        c.nb = im.nb;
+        ci = image_cache.emplace(key, std::move(c)).first;
+      }
+      const CachedImage &img = ci->second;
       ImageDesc &idd = h_idesc[free_slot];
       idd.off = (uint64_t)free_slot * kImage;
-      idd.bytes = (uint32_t)blob.size();
-      idd.dir_bytes = im.dir_bytes();
-      idd.dim_a = im.dim_a;
-      idd.dim_c = im.dim_c;
-      idd.b_lo = im.b_lo;
-      idd.nb = im.nb;
+      idd.bytes = (uint32_t)img.blob.size();
+      idd.dir_bytes = img.dir_bytes;
+      idd.dim_a = img.dim_a;
+      idd.dim_c = img.dim_c;
+      idd.b_lo = img.b_lo;
+      idd.nb = img.nb;
       if (idd.bytes) {
-        hipError_t e = hipMemcpyAsync(ws + lay.o_ipool + idd.off, blob.data(), blob.size(),
+        hipError_t e = hipMemcpyAsync(ws + lay.o_ipool + idd.off, img.blob.data(), img.blob.size(),
                                       hipMemcpyHostToDevice, s);
-        if (!e) e = hipStreamSynchronize(s);  // blob is a local buffer
         if (e) return hip(e);
       }
       fresh.push_back(free_slot);

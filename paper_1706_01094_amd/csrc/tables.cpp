@@ -586,6 +586,7 @@ LdsImage build_image(const CollisionTables &tab, double rho, double u, uint32_t 
         rec[0] = 0;
         rec[1] = 0;
         for (int j = 2; j < 8; ++j) rec[j] = 0xFFFF;
+        covered += pr.p * pb[b];
         continue;
       }
       if (N > tab.n_max) continue;  // never decided here

@@ -12,9 +12,10 @@
 
 namespace mclg {
 
-// Sites [x0, x1) of slot `slot` (D2Q9: sites s = y Lx + x of replica `slot`).
+// Sites [x0, x1) of slot `slot` (D2Q9: sites s = y Lx + x of replica `slot`),
+// part of run `run` (the run's result row).
 struct MomSeg {
-  uint32_t slot = 0, x0 = 0, x1 = 0, pad = 0;
+  uint32_t slot = 0, x0 = 0, x1 = 0, run = 0;
 };
 
 // The moment kernels' work for a list of slots: the segments of slot
@@ -25,22 +26,30 @@ struct MomPlan {
   std::vector<uint32_t> run_slot;  // runs
 };
 
-// Segments of at least 8192 sites (a multiple of 2048) and about 4096 of them
-// in all, so that at most 4096 + n segments are made for n slots.
-constexpr uint32_t kMomMaxSegsBase = 4096;
+// Segments of 8192 to 2^23 sites (a multiple of 2048) and about 512 of them
+// in all (two blocks per compute unit, one wave of blocks), so that at most
+// 512 + n + total / 2^23 segments are made for n slots of `total` sites
+// (2^23 bounds the 32-bit packed sums).
+constexpr uint32_t kMomMaxSegsBase = 512;
+constexpr uint64_t kMomMaxSegSites = 1ull << 23;
 MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n);
-inline uint64_t max_mom_segs(uint32_t n) { return kMomMaxSegsBase + n; }
+inline uint64_t max_mom_segs(uint32_t n, uint64_t total_sites) {
+  return kMomMaxSegsBase + n + total_sites / kMomMaxSegSites;
+}
 
-// Partial record of one D1Q3 segment: kMom3Rec uint64.  Slots 0-2 sum n_i,
-// 3-5 sum n_i^2, 6-8 sum n_-1 n_0, n_0 n_+1, n_-1 n_+1, 9 sites with odd
-// n_0, 10 the state digest, 11 + 2m and 12 + 2m the Fourier sums of mode m,
-// 31 max N.
+// Partial record of one D1Q3 segment: kMom3Rec uint64, of which the first
+// 12 + 2 n_modes are written.  Slots 0-2 sum n_i, 3-5 sum n_i^2, 6-8 sum
+// n_-1 n_0, n_0 n_+1, n_-1 n_+1, 9 sites with odd n_0, 10 the state digest,
+// 11 max N, 12 + 2m and 13 + 2m the Fourier sums of mode m.
 constexpr uint32_t kMom3Rec = 32;
 // One replica's result in the field order of mclg_moments_t (33 int64).
 constexpr uint32_t kMom3Out = 33;
-// Partial record of one D2Q9 segment: slots 0-8 sum n_i, 9-53 sum n_i n_j
-// (i <= j, row-major), 63 max N.
+// Partial record of one D2Q9 segment (kMom9Rec uint64, the first kMom9Used
+// written): slots 0-8 sum n_i, 9-53 sum n_i n_j (i <= j, row-major), 54
+// max N, 55 zero.
 constexpr uint32_t kMom9Rec = 64;
+constexpr uint32_t kMom9Used = 56;
+constexpr uint32_t kMom9Max = 54;
 // One replica's result in the field order of mclg_moments9_t (60 int64).
 constexpr uint32_t kMom9Out = 60;
 
@@ -60,10 +69,7 @@ struct MomArgs {
   uint32_t n_modes = 0;
   uint32_t digest = 0;               // D1Q3: also sum the state digest
   unsigned long long *partial = nullptr;  // n_segs records
-  // run j's result goes to out[out_index * kMom*Out]: out_index = j, or the
-  // run's slot when by_slot is set
-  long long *out = nullptr;
-  uint32_t by_slot = 0;
+  long long *out = nullptr;                // run j's result at out[j * kMom*Out]
 };
 
 // Static partial-record area of the allocation-free moments call: 8 MiB per

@@ -20,6 +20,7 @@ namespace {
 
 typedef unsigned long long u64;
 typedef long long i64;
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
 
@@ -80,9 +81,9 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 }
 
 // Block-wide combination of the lanes' sums and maxima into one partial
-// record of REC values: sums of values 0 .. V-1 in record slots 0 .. V-1,
-// zero in V .. REC-2, the maximum in slot REC-1.
-template <int V, int REC>
+// record: sums of values 0 .. V-1 in record slots 0 .. W-1 except MS, the
+// maximum in slot MS (value MS is zero).
+template <int V, int W, int MS>
 __device__ __forceinline__ void write_partial(u64 (&v)[V], uint32_t mx, u64 *rec) {
   __shared__ u64 red[16][V];
   __shared__ uint32_t redmx[16];
@@ -94,17 +95,24 @@ __device__ __forceinline__ void write_partial(u64 (&v)[V], uint32_t mx, u64 *rec
   if (lane == 0) redmx[wave] = mx;
   __syncthreads();
   const uint32_t nw = blockDim.x >> 6;
-  for (uint32_t k = threadIdx.x; k < (uint32_t)REC; k += blockDim.x) {
+  for (uint32_t k = threadIdx.x; k < (uint32_t)W; k += blockDim.x) {
     u64 out = 0;
-    if (k == REC - 1) {
+    if (k == (uint32_t)MS) {
       uint32_t m = 0;
       for (uint32_t w = 0; w < nw; ++w) m = max(m, redmx[w]);
       out = m;
-    } else if (k < (uint32_t)V) {
+    } else {
       for (uint32_t w = 0; w < nw; ++w) out += red[w][k];
     }
     rec[k] = out;
   }
+}
+
+// The first segment of each run (x0 = 0) clears the run's result row before
+// the final pass adds into it.
+__device__ __forceinline__ void clear_result(const MomSeg &sg, uint32_t n_out, i64 *out) {
+  if (sg.x0 == 0u)
+    for (uint32_t k = threadIdx.x; k < n_out; k += blockDim.x) out[(uint64_t)sg.run * n_out + k] = 0;
 }
 
 // ---- D1Q3 ----------------------------------------------------------------
@@ -142,55 +150,96 @@ __device__ __forceinline__ uint32_t load_eight(Rsrc rs, uint32_t ab, uint32_t L,
 }
 
 // Accumulators of one lane (record slots 0 .. 10 + 2 NM, max N apart).
+// Windows whose counts are all below 256 add their sums and products with
+// packed dot products into 32-bit sums (f, in the order of record slots
+// 0..8): each adds at most 8 x 255^2 per window, and a lane sums at most
+// 2^23 / 256 windows of a segment (segments hold at most 2^23 sites), which
+// stays below 2^32.  Other windows add exact 64-bit sums.
 template <int NM>
 struct Acc3 {
   u64 s[11 + 2 * NM];
+  uint32_t f[9];
   uint32_t mx;
+  uint32_t mxp;  // packed 16-bit maxima of N of the packed windows
 };
+
+__device__ __forceinline__ uint32_t dot2(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), c,
+                                false);
+}
 
 template <int NM, bool DIG>
 __device__ __forceinline__ void add_eight(Acc3<NM> &A, const uint32_t (&va)[4],
                                           const uint32_t (&vb)[4], const uint32_t (&vc)[4],
                                           uint32_t x, uint32_t nvalid, const int32_t *tw,
                                           uint32_t L) {
-  uint32_t sa = 0, sb = 0, sc = 0, odd = 0;
   uint32_t Ns[8];
+  uint32_t any = 0, odd = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t a0 = va[j] & 0xffffu, a1 = va[j] >> 16;
-    const uint32_t b0 = vb[j] & 0xffffu, b1 = vb[j] >> 16;
-    const uint32_t c0 = vc[j] & 0xffffu, c1 = vc[j] >> 16;
-    sa += a0 + a1;
-    sb += b0 + b1;
-    sc += c0 + c1;
-    A.s[3] += (u64)a0 * a0 + (u64)a1 * a1;
-    A.s[4] += (u64)b0 * b0 + (u64)b1 * b1;
-    A.s[5] += (u64)c0 * c0 + (u64)c1 * c1;
-    A.s[6] += (u64)a0 * b0 + (u64)a1 * b1;
-    A.s[7] += (u64)b0 * c0 + (u64)b1 * c1;
-    A.s[8] += (u64)a0 * c0 + (u64)a1 * c1;
-    odd += __popc(vb[j] & 0x00010001u);
-    Ns[2 * j] = a0 + b0 + c0;
-    Ns[2 * j + 1] = a1 + b1 + c1;
-    A.mx = max(A.mx, max(Ns[2 * j], Ns[2 * j + 1]));
-    if constexpr (DIG) {
-      // digest: sum over existing sites and velocities of
-      // fmix32(fmix32(4 x + i + 1) ^ n_i(x)), i = 0, 1, 2 for v = -1, 0, +1
-      const uint32_t k0 = 4u * (x + 2u * j) + 1u, k1 = k0 + 4u;
-      u64 d = 0;
-      if (2u * j < nvalid)
-        d += (u64)fmix32(fmix32(k0) ^ a0) + fmix32(fmix32(k0 + 1u) ^ b0) +
-             fmix32(fmix32(k0 + 2u) ^ c0);
-      if (2u * j + 1u < nvalid)
-        d += (u64)fmix32(fmix32(k1) ^ a1) + fmix32(fmix32(k1 + 1u) ^ b1) +
-             fmix32(fmix32(k1 + 2u) ^ c1);
-      A.s[10] += d;
+  for (int j = 0; j < 4; ++j) any |= va[j] | vb[j] | vc[j];
+  if ((any & 0xff00ff00u) == 0u) {
+    // every count below 256: packed products, packed N (below 768)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      A.f[0] = dot2(va[j], 0x00010001u, A.f[0]);
+      A.f[1] = dot2(vb[j], 0x00010001u, A.f[1]);
+      A.f[2] = dot2(vc[j], 0x00010001u, A.f[2]);
+      A.f[3] = dot2(va[j], va[j], A.f[3]);
+      A.f[4] = dot2(vb[j], vb[j], A.f[4]);
+      A.f[5] = dot2(vc[j], vc[j], A.f[5]);
+      A.f[6] = dot2(va[j], vb[j], A.f[6]);
+      A.f[7] = dot2(vb[j], vc[j], A.f[7]);
+      A.f[8] = dot2(va[j], vc[j], A.f[8]);
+      const u16x2 n2 = __builtin_bit_cast(u16x2, va[j]) + __builtin_bit_cast(u16x2, vb[j]) +
+                       __builtin_bit_cast(u16x2, vc[j]);
+      A.mxp = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, A.mxp), n2));
+      const uint32_t nw = __builtin_bit_cast(uint32_t, n2);
+      Ns[2 * j] = nw & 0xffffu;
+      Ns[2 * j + 1] = nw >> 16;
+      odd += __popc(vb[j] & 0x00010001u);
     }
+  } else {
+    uint32_t sa = 0, sb = 0, sc = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a0 = va[j] & 0xffffu, a1 = va[j] >> 16;
+      const uint32_t b0 = vb[j] & 0xffffu, b1 = vb[j] >> 16;
+      const uint32_t c0 = vc[j] & 0xffffu, c1 = vc[j] >> 16;
+      sa += a0 + a1;
+      sb += b0 + b1;
+      sc += c0 + c1;
+      A.s[3] += (u64)a0 * a0 + (u64)a1 * a1;
+      A.s[4] += (u64)b0 * b0 + (u64)b1 * b1;
+      A.s[5] += (u64)c0 * c0 + (u64)c1 * c1;
+      A.s[6] += (u64)a0 * b0 + (u64)a1 * b1;
+      A.s[7] += (u64)b0 * c0 + (u64)b1 * c1;
+      A.s[8] += (u64)a0 * c0 + (u64)a1 * c1;
+      odd += __popc(vb[j] & 0x00010001u);
+      Ns[2 * j] = a0 + b0 + c0;
+      Ns[2 * j + 1] = a1 + b1 + c1;
+      A.mx = max(A.mx, max(Ns[2 * j], Ns[2 * j + 1]));
+    }
+    A.s[0] += sa;
+    A.s[1] += sb;
+    A.s[2] += sc;
   }
-  A.s[0] += sa;
-  A.s[1] += sb;
-  A.s[2] += sc;
   A.s[9] += odd;
+  if constexpr (DIG) {
+    // digest: sum over existing sites and velocities of
+    // fmix32(fmix32(4 x + i + 1) ^ n_i(x)), i = 0, 1, 2 for v = -1, 0, +1
+    u64 d = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t k0 = 4u * (x + 2u * j) + 1u, k1 = k0 + 4u;
+      if (2u * j < nvalid)
+        d += (u64)fmix32(fmix32(k0) ^ (va[j] & 0xffffu)) + fmix32(fmix32(k0 + 1u) ^ (vb[j] & 0xffffu)) +
+             fmix32(fmix32(k0 + 2u) ^ (vc[j] & 0xffffu));
+      if (2u * j + 1u < nvalid)
+        d += (u64)fmix32(fmix32(k1) ^ (va[j] >> 16)) + fmix32(fmix32(k1 + 1u) ^ (vb[j] >> 16)) +
+             fmix32(fmix32(k1 + 2u) ^ (vc[j] >> 16));
+    }
+    A.s[10] += d;
+  }
   if constexpr (NM > 0) {
     // twiddle rows of the slot: row r at tw + r L (4-byte aligned); one mode
     // (two rows) at a time, so that at most 16 of their values are live
@@ -226,8 +275,9 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
                                               const uint32_t *__restrict__ tslot,
                                               const MomSeg *__restrict__ segs, uint32_t no_stream,
                                               const int32_t *__restrict__ twiddle,
-                                              u64 *__restrict__ partial) {
+                                              u64 *__restrict__ partial, i64 *__restrict__ out) {
   const MomSeg sg = segs[blockIdx.x];
+  clear_result(sg, kMom3Out, out);
   const SlotDev sl = slots[sg.slot];
   const uint32_t L = sl.L;
   const uint32_t tm = no_stream ? 0u : tslot[sg.slot] % L;
@@ -237,143 +287,253 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
   Acc3<NM> A;
 #pragma unroll
   for (int k = 0; k < 11 + 2 * NM; ++k) A.s[k] = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A.f[k] = 0;
   A.mx = 0;
+  A.mxp = 0;
   const uint32_t step = 8u * blockDim.x;
   uint32_t x = sg.x0 + 8u * threadIdx.x;
-  // without twiddle rows, two passes' loads are in flight before either is
+  // without twiddle rows, four passes' loads are in flight before any is
   // summed
-  if constexpr (NM == 0)
-  for (; x + step < sg.x1; x += 2u * step) {
-    uint32_t a0[4], b0[4], c0[4], a1[4], b1[4], c1[4];
-    const uint32_t n0 = load_eight(rs, ab, L, tm, x, a0, b0, c0);
-    const uint32_t n1 = load_eight(rs, ab, L, tm, x + step, a1, b1, c1);
-    add_eight<NM, DIG>(A, a0, b0, c0, x, n0, tw, L);
-    add_eight<NM, DIG>(A, a1, b1, c1, x + step, n1, tw, L);
+  if constexpr (NM == 0 && !DIG)
+  for (; x + 3u * step < sg.x1; x += 4u * step) {
+    uint32_t a[4][4], b[4][4], c[4][4], n[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) n[u] = load_eight(rs, ab, L, tm, x + u * step, a[u], b[u], c[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add_eight<NM, DIG>(A, a[u], b[u], c[u], x + u * step, n[u], tw, L);
   }
   for (; x < sg.x1; x += step) {
     uint32_t a0[4], b0[4], c0[4];
     const uint32_t n0 = load_eight(rs, ab, L, tm, x, a0, b0, c0);
     add_eight<NM, DIG>(A, a0, b0, c0, x, n0, tw, L);
   }
-  constexpr int V = 11 + 2 * NM <= 16 ? 16 : 32;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) A.s[k] += A.f[k];
+  A.mx = max(A.mx, max(A.mxp & 0xffffu, A.mxp >> 16));
+  // record slots: the 11 sums, the maximum, then the Fourier sums
+  constexpr int W = 12 + 2 * NM;
+  constexpr int V = W <= 16 ? 16 : 32;
   u64 v[V];
 #pragma unroll
-  for (int k = 0; k < V; ++k) v[k] = k < 11 + 2 * NM ? A.s[k < 11 + 2 * NM ? k : 0] : 0ull;
-  write_partial<V, kMom3Rec>(v, A.mx, partial + (uint64_t)blockIdx.x * kMom3Rec);
+  for (int k = 0; k < V; ++k)
+    v[k] = k < 11 ? A.s[k < 11 ? k : 0] : (k >= 12 && k < W) ? A.s[(k >= 12 && k < W) ? k - 1 : 0] : 0ull;
+  write_partial<V, W, 11>(v, A.mx, partial + (uint64_t)blockIdx.x * kMom3Rec);
 }
 
-// Adds the partial records of each run (one block per run) and writes the
+// Sums of the partial records of one run in the final pass.  Block
+// (f, j) of a grid of F x runs takes records s0 + f G + g, s0 + (f + F) G + g,
+// ... of run j with G = 256 / (REC / 2) groups g of REC / 2 threads; thread p
+// of a group loads values 2p and 2p + 1 of a record in one 16-byte load
+// (pairs at or past npairs are not read).  Value MS is a maximum, the others
+// are sums modulo 2^64.  Returns false (for the whole block) when the block
+// has no record; otherwise tot[k] holds the slice's value k.
+template <int REC, int MS>
+__device__ __forceinline__ bool sum_slice(const u64 *__restrict__ partial, uint32_t s0,
+                                          uint32_t s1, uint32_t npairs, u64 *tot) {
+  constexpr uint32_t P = REC / 2, G = 256 / P;
+  __shared__ u64 red[2][256];
+  const uint32_t f = blockIdx.x, F = gridDim.x;
+  if (s0 + f * G >= s1) return false;
+  const uint32_t p = threadIdx.x % P, g = threadIdx.x / P;
+  const bool m0 = 2u * p == (uint32_t)MS, m1 = 2u * p + 1u == (uint32_t)MS;
+  u64 a0 = 0, a1 = 0;
+  auto add = [&](uint4 q) {
+    const u64 v0 = ((u64)q.y << 32) | q.x, v1 = ((u64)q.w << 32) | q.z;
+    a0 = m0 ? max(a0, v0) : a0 + v0;
+    a1 = m1 ? max(a1, v1) : a1 + v1;
+  };
+  if (p < npairs) {
+    const uint4 *base = reinterpret_cast<const uint4 *>(partial) + p;
+    const uint32_t st = F * G;
+    uint32_t r = s0 + f * G + g;
+    for (; r + 3u * st < s1; r += 4u * st) {  // four loads in flight
+      const uint4 q0 = base[(uint64_t)r * P], q1 = base[(uint64_t)(r + st) * P];
+      const uint4 q2 = base[(uint64_t)(r + 2u * st) * P], q3 = base[(uint64_t)(r + 3u * st) * P];
+      add(q0);
+      add(q1);
+      add(q2);
+      add(q3);
+    }
+    for (; r < s1; r += st) add(base[(uint64_t)r * P]);
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  __syncthreads();
+  if (threadIdx.x < 2u * P) {
+    const uint32_t k = threadIdx.x, h = k & 1u, q = k >> 1;
+    u64 t = 0;
+    for (uint32_t gg = 0; gg < G; ++gg) {
+      const u64 v = red[h][gg * P + q];
+      t = k == (uint32_t)MS ? max(t, v) : t + v;
+    }
+    tot[k] = t;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Final pass, block (f, j): adds its slice of run j's records into the
 // replica's result in the field order of mclg_moments_t: t (the device step
 // counter), sites, sum n_i, sum n_i^2, sum n_i n_j, sum N = sum of the three
 // sums, sum J = sum n_+1 - sum n_-1, sum N^2 = sum n_i^2 + 2 sum n_i n_j,
-// sites with odd n_0, max N, Fourier sums, digest.
-__global__ void __launch_bounds__(64) k_mom3_final(const u64 *__restrict__ partial,
-                                                   const uint32_t *__restrict__ run_seg,
-                                                   const uint32_t *__restrict__ run_slot,
-                                                   const SlotDev *__restrict__ slots,
-                                                   const uint32_t *__restrict__ tslot,
-                                                   uint32_t by_slot, i64 *__restrict__ out) {
-  __shared__ u64 tot[kMom3Rec];
-  const uint32_t j = blockIdx.x, k = threadIdx.x;
-  const uint32_t s0 = run_seg[j], s1 = run_seg[j + 1], slot = run_slot[j];
-  if (k < kMom3Rec) {
-    u64 acc = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-      const u64 v = partial[(uint64_t)s * kMom3Rec + k];
-      acc = k == kMom3Rec - 1 ? (acc > v ? acc : v) : acc + v;
-    }
-    tot[k] = acc;
+// sites with odd n_0, max N, Fourier sums, digest.  Every field but t and
+// sites (written by block 0) is a sum of the slices' contributions or their
+// maximum, combined with 64-bit integer atomics, so the result does not
+// depend on their order.
+__global__ void __launch_bounds__(256) k_mom3_final(const u64 *__restrict__ partial,
+                                                    const uint32_t *__restrict__ run_seg,
+                                                    const uint32_t *__restrict__ run_slot,
+                                                    const SlotDev *__restrict__ slots,
+                                                    const uint32_t *__restrict__ tslot,
+                                                    uint32_t n_modes, i64 *__restrict__ out) {
+  __shared__ u64 T[kMom3Rec];
+  const uint32_t j = blockIdx.y, slot = run_slot[j];
+  if (!sum_slice<kMom3Rec, 11>(partial, run_seg[j], run_seg[j + 1], 6u + n_modes, T)) return;
+  u64 *o = reinterpret_cast<u64 *>(out + (uint64_t)j * kMom3Out);
+  const uint32_t k = threadIdx.x;
+  if (k >= kMom3Out) return;
+  if (k <= 1u) {
+    if (blockIdx.x == 0) o[k] = k == 0 ? tslot[slot] : slots[slot].L;
+    return;
   }
-  __syncthreads();
-  if (k == 0) {
-    i64 *o = out + (uint64_t)(by_slot ? slot : j) * kMom3Out;
-    const u64 *T = tot;
-    o[0] = (i64)tslot[slot];
-    o[1] = (i64)slots[slot].L;
-    for (int i = 0; i < 9; ++i) o[2 + i] = (i64)T[i];
-    o[11] = (i64)(T[0] + T[1] + T[2]);
-    o[12] = (i64)(T[2] - T[0]);
-    o[13] = (i64)(T[3] + T[4] + T[5] + 2ull * (T[6] + T[7] + T[8]));
-    o[14] = (i64)T[9];
-    o[15] = (i64)T[31];
-    for (int i = 0; i < 16; ++i) o[16 + i] = (i64)T[11 + i];
-    o[32] = (i64)T[10];
+  if (k == 15u) {
+    atomicMax(&o[k], T[11]);
+    return;
   }
+  u64 v;
+  if (k <= 10u) v = T[k - 2u];
+  else if (k == 11u) v = T[0] + T[1] + T[2];
+  else if (k == 12u) v = T[2] - T[0];
+  else if (k == 13u) v = T[3] + T[4] + T[5] + 2ull * (T[6] + T[7] + T[8]);
+  else if (k == 14u) v = T[9];
+  else if (k < 32u) {
+    if (k - 16u >= 2u * n_modes) return;
+    v = T[k - 4u];
+  } else {
+    v = T[10];
+  }
+  atomicAdd(&o[k], v);
 }
 
 // ---- D2Q9 ----------------------------------------------------------------
 __constant__ int32_t kVx9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int32_t kVy9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-// One block per segment of a replica's sites s = y Lx + x, one site per lane
-// and pass: logical n_i(x, y, t) is at physical ((x - vx t) mod Lx,
-// (y - vy t) mod Ly), so a wave's 64 consecutive sites read mostly
-// consecutive elements of each array.  The lane walks its sites with
-// (x, y) advanced by the block's stride, no division per site.  The 54 sums
-// are kept in 32 bits: a lane adds at most 2^16 sites (segments hold at
-// most 2^24 sites), so the sums of n_i fit, and so do the sums of products
-// of sites whose nine counts are all below 256; a site with a larger count
-// adds its products to 64-bit sums in LDS instead.
+// One block per segment of a replica's sites s = y Lx + x; each lane takes
+// eight consecutive sites of a row per pass.  Logical n_i(x, y, t) sits at
+// physical ((x - vx t) mod Lx, (y - vy t) mod Ly), so eight sites of a row
+// are eight consecutive elements of each array unless a shifted window wraps
+// around Lx: one 16-byte load per velocity (nine per pass), else element by
+// element.  Windows whose counts are all below 256 add the 9 sums and 45
+// products n_i n_j with packed dot products into 32-bit sums (each adds at
+// most 8 x 255^2 per window; a lane sums at most 2^23 / 2048 windows of a
+// segment); other windows add each site's exact products to 64-bit sums in
+// LDS.
+__device__ __forceinline__ void load_row9(Rsrc rs, uint32_t stride, uint32_t Lx, uint32_t Ly,
+                                          uint32_t tx, uint32_t ty, uint32_t x, uint32_t y,
+                                          uint32_t (&w)[9][4]) {
+  const uint32_t xc[3] = {x + tx >= Lx ? x + tx - Lx : x + tx, x, x >= tx ? x - tx : x + Lx - tx};
+  const uint32_t yr[3] = {(y + ty >= Ly ? y + ty - Ly : y + ty) * Lx, y * Lx,
+                          (y >= ty ? y - ty : y + Ly - ty) * Lx};
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    load16(rs, 2u * ((uint32_t)i * stride + yr[kVy9[i] + 1] + xc[kVx9[i] + 1]), w[i]);
+}
+
 __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state,
                                               const Rep9 *__restrict__ reps, uint64_t t,
                                               uint32_t no_stream,
                                               const MomSeg *__restrict__ segs,
-                                              u64 *__restrict__ partial) {
+                                              u64 *__restrict__ partial, i64 *__restrict__ out) {
   __shared__ u64 big[45];
   __shared__ u64 red64[4][64];
   __shared__ uint32_t redmx[4];
   for (uint32_t k = threadIdx.x; k < 45u; k += blockDim.x) big[k] = 0;
   __syncthreads();
   const MomSeg sg = segs[blockIdx.x];
+  clear_result(sg, kMom9Out, out);
   const Rep9 rp = reps[sg.slot];
   const uint32_t Lx = rp.Lx, Ly = rp.Ly;
   const uint32_t tx = no_stream ? 0u : (uint32_t)(t % Lx);
   const uint32_t ty = no_stream ? 0u : (uint32_t)(t % Ly);
-  const uint16_t *base = state + rp.off;
+  const Rsrc rs = make_rsrc(state + rp.off, 18u * rp.stride);
   const uint32_t stride = rp.stride;
   uint32_t acc[64];
 #pragma unroll
   for (int k = 0; k < 64; ++k) acc[k] = 0;
-  uint32_t mx = 0;
-  const uint32_t bs = blockDim.x;
-  const uint32_t qy = bs / Lx, qx = bs - qy * Lx;  // the block's stride in (x, y)
-  uint32_t s = sg.x0 + threadIdx.x;
-  uint32_t y = s / Lx, x = s - y * Lx;
-  for (; s < sg.x1; s += bs) {
-    // physical columns for vx = -1, 0, +1 and row offsets for vy = -1, 0, +1
-    const uint32_t xc[3] = {x + tx >= Lx ? x + tx - Lx : x + tx, x,
-                            x >= tx ? x - tx : x + Lx - tx};
-    const uint32_t yr[3] = {(y + ty >= Ly ? y + ty - Ly : y + ty) * Lx, y * Lx,
-                            (y >= ty ? y - ty : y + Ly - ty) * Lx};
-    uint32_t n[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-      n[i] = base[(uint64_t)i * stride + yr[kVy9[i] + 1] + xc[kVx9[i] + 1]];
-    uint32_t N = 0, top = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      N += n[i];
-      top = max(top, n[i]);
-      acc[i] += n[i];
-    }
-    mx = max(mx, N);
-    if (top < 256u) {
-      int k = 9;
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-#pragma unroll
-        for (int j = i; j < 9; ++j) acc[k++] += n[i] * n[j];
+  uint32_t mx = 0, mxp = 0;
+  const uint32_t step = 8u * blockDim.x;
+  for (uint32_t s = sg.x0 + 8u * threadIdx.x; s < sg.x1; s += step) {
+    const uint32_t y = s / Lx, x = s - y * Lx;
+    uint32_t w[9][4];
+    const uint32_t xm = x + tx >= Lx ? x + tx - Lx : x + tx, xp = x >= tx ? x - tx : x + Lx - tx;
+    const bool fast = s + 8u <= sg.x1 && x + 8u <= Lx && xm + 8u <= Lx && xp + 8u <= Lx;
+    if (fast) {
+      load_row9(rs, stride, Lx, Ly, tx, ty, x, y, w);
     } else {
-      int k = 0;
 #pragma unroll
       for (int i = 0; i < 9; ++i)
 #pragma unroll
-        for (int j = i; j < 9; ++j) atomicAdd(&big[k++], (u64)n[i] * n[j]);
+        for (int j = 0; j < 4; ++j) w[i][j] = 0;
+      uint32_t xe = x, ye = y;
+#pragma unroll
+      for (uint32_t e = 0; e < 8u; ++e) {
+        if (s + e < sg.x1) {
+          const uint32_t xc[3] = {xe + tx >= Lx ? xe + tx - Lx : xe + tx, xe,
+                                  xe >= tx ? xe - tx : xe + Lx - tx};
+          const uint32_t yr[3] = {(ye + ty >= Ly ? ye + ty - Ly : ye + ty) * Lx, ye * Lx,
+                                  (ye >= ty ? ye - ty : ye + Ly - ty) * Lx};
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            w[i][e >> 1] |= load2(rs, 2u * ((uint32_t)i * stride + yr[kVy9[i] + 1] +
+                                            xc[kVx9[i] + 1])) << (16u * (e & 1u));
+        }
+        if (++xe == Lx) { xe = 0; ++ye; }
+      }
     }
-    x += qx;
-    y += qy;
-    if (x >= Lx) { x -= Lx; y += 1u; }
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) any |= w[i][0] | w[i][1] | w[i][2] | w[i][3];
+    if ((any & 0xff00ff00u) == 0u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        u16x2 n2 = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          acc[i] = dot2(w[i][j], 0x00010001u, acc[i]);
+          n2 += __builtin_bit_cast(u16x2, w[i][j]);
+        }
+        int k = 9;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+          for (int l = i; l < 9; ++l) { acc[k] = dot2(w[i][j], w[l][j], acc[k]); ++k; }
+        mxp = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, mxp), n2));
+      }
+    } else {
+#pragma unroll
+      for (uint32_t e = 0; e < 8u; ++e) {
+        uint32_t n[9], N = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          n[i] = (w[i][e >> 1] >> (16u * (e & 1u))) & 0xffffu;
+          N += n[i];
+          acc[i] += n[i];
+        }
+        mx = max(mx, N);
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+          for (int l = i; l < 9; ++l) {
+            if (n[i] && n[l]) atomicAdd(&big[k], (u64)n[i] * n[l]);
+            ++k;
+          }
+      }
+    }
   }
+  mx = max(mx, max(mxp & 0xffffu, mxp >> 16));
   // first level of the reduce-scatter in 32-bit inputs (lanes with bit 5
   // set keep values 32..63), then 64-bit sums
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -387,11 +547,11 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
       v[j] = (u64)keep + (uint32_t)__shfl_xor(send, 32);
     }
   }
-  int w = 32, m = 16;
+  int wd = 32, m = 16;
 #pragma unroll
   for (int lvl = 0; lvl < 5; ++lvl) {
     const bool up = (lane & (uint32_t)m) != 0;
-    const int h = w >> 1;
+    const int h = wd >> 1;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       if (j < h) {
@@ -400,7 +560,7 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
         v[j] = keep + shfl_xor_u64(send, m);
       }
     }
-    w = h;
+    wd = h;
     m >>= 1;
   }
   // lane l now holds the wave's total of value l
@@ -410,9 +570,9 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
   __syncthreads();
   const uint32_t nw = blockDim.x >> 6;
   u64 *rec = partial + (uint64_t)blockIdx.x * kMom9Rec;
-  for (uint32_t k = threadIdx.x; k < kMom9Rec; k += blockDim.x) {
+  for (uint32_t k = threadIdx.x; k < kMom9Used; k += blockDim.x) {
     u64 o = 0;
-    if (k == kMom9Rec - 1) {
+    if (k == kMom9Max) {
       uint32_t mm = 0;
       for (uint32_t q = 0; q < nw; ++q) mm = max(mm, redmx[q]);
       o = mm;
@@ -424,54 +584,56 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
   }
 }
 
-// One block per run: the replica's result in the field order of
-// mclg_moments9_t: t, sites, sum n_i, sum n_i n_j (i <= j), sum N, sum Jx,
-// sum Jy (from the per-velocity sums), max N.
-__global__ void __launch_bounds__(64) k_mom9_final(const u64 *__restrict__ partial,
-                                                   const uint32_t *__restrict__ run_seg,
-                                                   const uint32_t *__restrict__ run_slot,
-                                                   const Rep9 *__restrict__ reps, uint64_t t,
-                                                   uint32_t by_slot, i64 *__restrict__ out) {
-  __shared__ u64 tot[kMom9Rec];
-  const uint32_t j = blockIdx.x, k = threadIdx.x;
-  const uint32_t s0 = run_seg[j], s1 = run_seg[j + 1], slot = run_slot[j];
-  if (k < kMom9Rec) {
-    u64 acc = 0;
-    for (uint32_t s = s0; s < s1; ++s) {
-      const u64 v = partial[(uint64_t)s * kMom9Rec + k];
-      acc = k == kMom9Rec - 1 ? (acc > v ? acc : v) : acc + v;
-    }
-    tot[k] = acc;
+// Final pass, block (f, j): adds its slice of run j's records into the
+// replica's result in the field order of mclg_moments9_t: t, sites, sum n_i,
+// sum n_i n_j (i <= j), sum N, sum Jx, sum Jy (from the per-velocity sums),
+// max N; combined over slices as in the D1Q3 pass.
+__global__ void __launch_bounds__(256) k_mom9_final(const u64 *__restrict__ partial,
+                                                    const uint32_t *__restrict__ run_seg,
+                                                    const uint32_t *__restrict__ run_slot,
+                                                    const Rep9 *__restrict__ reps, uint64_t t,
+                                                    i64 *__restrict__ out) {
+  __shared__ u64 T[kMom9Rec];
+  const uint32_t j = blockIdx.y, slot = run_slot[j];
+  if (!sum_slice<kMom9Rec, kMom9Max>(partial, run_seg[j], run_seg[j + 1], kMom9Used / 2u, T))
+    return;
+  u64 *o = reinterpret_cast<u64 *>(out + (uint64_t)j * kMom9Out);
+  const uint32_t k = threadIdx.x;
+  if (k >= kMom9Out) return;
+  if (k <= 1u) {
+    if (blockIdx.x == 0) o[k] = k == 0 ? t : reps[slot].S;
+    return;
   }
-  __syncthreads();
-  if (k == 0) {
-    i64 *o = out + (uint64_t)(by_slot ? slot : j) * kMom9Out;
-    o[0] = (i64)t;
-    o[1] = (i64)reps[slot].S;
-    u64 N = 0;
-    i64 jx = 0, jy = 0;
-    for (int i = 0; i < 9; ++i) {
-      o[2 + i] = (i64)tot[i];
-      N += tot[i];
-      jx += kVx9[i] * (i64)tot[i];
-      jy += kVy9[i] * (i64)tot[i];
-    }
-    for (int i = 0; i < 45; ++i) o[11 + i] = (i64)tot[9 + i];
-    o[56] = (i64)N;
-    o[57] = jx;
-    o[58] = jy;
-    o[59] = (i64)tot[kMom9Rec - 1];
+  if (k == 59u) {
+    atomicMax(&o[k], T[kMom9Max]);
+    return;
   }
+  u64 v = 0;
+  if (k < 56u) {
+    v = T[k - 2u];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      v += (u64)(k == 56u ? 1 : k == 57u ? kVx9[i] : kVy9[i]) * T[i];
+  }
+  atomicAdd(&o[k], v);
+}
+
+// Blocks per run of the final pass: about 32 records each (from the mean
+// segments per run), at most 32.
+uint32_t final_slices(const MomArgs &a) {
+  const uint32_t per_run = (a.n_segs + a.n_runs - 1) / a.n_runs;
+  return std::max(1u, std::min(32u, (per_run + 31u) / 32u));
 }
 
 template <int NM>
 hipError_t launch3(hipStream_t s, const MomArgs &a) {
   if (a.digest)
     k_mom3<NM, true><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
-                                              a.twiddle, a.partial);
+                                              a.twiddle, a.partial, a.out);
   else
     k_mom3<NM, false><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
-                                               a.twiddle, a.partial);
+                                               a.twiddle, a.partial, a.out);
   return hipGetLastError();
 }
 
@@ -508,12 +670,13 @@ MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n) {
   uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) total += sites[j];
   uint64_t seg = (total + kMomMaxSegsBase - 1) / kMomMaxSegsBase;
-  seg = std::max<uint64_t>(8192, (seg + 2047) / 2048 * 2048);
+  seg = std::min<uint64_t>(kMomMaxSegSites, std::max<uint64_t>(8192, (seg + 2047) / 2048 * 2048));
   p.run_seg.push_back(0);
   for (uint32_t j = 0; j < n; ++j) {
     for (uint64_t x0 = 0; x0 < sites[j]; x0 += seg) {
       MomSeg m;
       m.slot = slots[j];
+      m.run = j;
       m.x0 = (uint32_t)x0;
       m.x1 = (uint32_t)std::min<uint64_t>(sites[j], x0 + seg);
       p.segs.push_back(m);
@@ -521,6 +684,7 @@ MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n) {
     if (sites[j] == 0) {  // an empty run still gets its (zero) record
       MomSeg m;
       m.slot = slots[j];
+      m.run = j;
       p.segs.push_back(m);
     }
     p.run_seg.push_back((uint32_t)p.segs.size());
@@ -545,18 +709,18 @@ hipError_t launch_moments3(hipStream_t s, const MomArgs &a) {
     default: e = launch3<8>(s, a); break;
   }
   if (e) return e;
-  k_mom3_final<<<a.n_runs, 64, 0, s>>>(a.partial, a.run_seg, a.run_slot, a.slots, a.tslot,
-                                       a.by_slot, a.out);
+  k_mom3_final<<<dim3(final_slices(a), a.n_runs), 256, 0, s>>>(
+      a.partial, a.run_seg, a.run_slot, a.slots, a.tslot, a.n_modes, a.out);
   return hipGetLastError();
 }
 
 hipError_t launch_moments9(hipStream_t s, const MomArgs &a) {
   if (a.n_runs == 0) return hipSuccess;
-  k_mom9<<<a.n_segs, 256, 0, s>>>(a.state, a.reps, a.t9, a.no_stream, a.segs, a.partial);
+  k_mom9<<<a.n_segs, 256, 0, s>>>(a.state, a.reps, a.t9, a.no_stream, a.segs, a.partial, a.out);
   hipError_t e = hipGetLastError();
   if (e) return e;
-  k_mom9_final<<<a.n_runs, 64, 0, s>>>(a.partial, a.run_seg, a.run_slot, a.reps, a.t9,
-                                       a.by_slot, a.out);
+  k_mom9_final<<<dim3(final_slices(a), a.n_runs), 256, 0, s>>>(a.partial, a.run_seg, a.run_slot,
+                                                               a.reps, a.t9, a.out);
   return hipGetLastError();
 }
 

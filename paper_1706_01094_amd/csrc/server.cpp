@@ -36,7 +36,7 @@ struct SrvLayout {
   uint64_t o_ctrl, o_slots, o_tslot, o_tiles, o_list, o_pdesc, o_pool, o_idesc, o_over, o_ipool,
       o_rowbase, o_rowdesc, o_thr, o_fixed, o_row16, bytes, max_tiles;
   // moments of retiring jobs: segments, runs, partial records, results
-  uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout;
+  uint64_t o_mseg, o_mrun, o_mslot, o_mpart, o_mout, max_mom_segs;
 };
 
 SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
@@ -56,10 +56,11 @@ SrvLayout srv_layout(const mclg_server_config *cfg, const CollisionTables *tab,
   l.o_tslot = take(sizeof(uint32_t) * n);
   l.o_tiles = take(sizeof(TileDev) * l.max_tiles);
   l.o_list = take(sizeof(uint32_t) * n);
-  l.o_mseg = take(sizeof(MomSeg) * max_mom_segs((uint32_t)n));
+  l.max_mom_segs = max_mom_segs((uint32_t)n, cfg->arena_bytes / 6u);
+  l.o_mseg = take(sizeof(MomSeg) * l.max_mom_segs);
   l.o_mrun = take(sizeof(uint32_t) * (n + 1));
   l.o_mslot = take(sizeof(uint32_t) * n);
-  l.o_mpart = take(sizeof(uint64_t) * kMom3Rec * max_mom_segs((uint32_t)n));
+  l.o_mpart = take(sizeof(uint64_t) * kMom3Rec * l.max_mom_segs);
   l.o_mout = take(sizeof(uint64_t) * kMom3Out * n);
   l.o_pdesc = take(sizeof(PoisDesc) * 3 * n);
   l.o_pool = take(sizeof(uint32_t) * kPoisCap * 3 * n);
@@ -344,7 +345,7 @@ struct mclg_server {
       }
     if (fin.empty()) return MCLG_OK;
     h_mplan = plan_moments(fin.data(), sites.data(), (uint32_t)fin.size());
-    if (h_mplan.segs.size() > max_mom_segs((uint32_t)slot.size())) return MCLG_E_INTERNAL;
+    if (h_mplan.segs.size() > lay.max_mom_segs) return MCLG_E_INTERNAL;
     MomArgs m;
     m.state = arena;
     m.slots = d_slots();

@@ -168,11 +168,44 @@ __device__ __forceinline__ uint32_t dot2(uint32_t a, uint32_t b, uint32_t c) {
                                 false);
 }
 
+// Eight sites of a lane as loaded: counts two to a word, and for up to two
+// modes the twiddle values of the eight sites (more modes load theirs when
+// they are summed, so that few registers are live).
+template <int NM>
+struct Eight {
+  static constexpr int PR = NM <= 2 ? 2 * NM : 0;
+  uint32_t a[4], b[4], c[4];
+  int32_t w[PR > 0 ? PR : 1][8];
+  uint32_t x, n;
+};
+
+// The eight twiddle values of row `row` at sites x .. x + n - 1 (zero past).
+__device__ __forceinline__ void load_tw8(const int32_t *row, uint32_t n, int32_t (&w)[8]) {
+  if (n == 8u) {
+    __builtin_memcpy(&w[0], row, 16);
+    __builtin_memcpy(&w[4], row + 4, 16);
+  } else {
+#pragma unroll
+    for (uint32_t e = 0; e < 8u; ++e) w[e] = e < n ? row[e] : 0;
+  }
+}
+
+template <int NM>
+__device__ __forceinline__ void load_window(Rsrc rs, uint32_t ab, uint32_t L, uint32_t tm,
+                                            uint32_t x, const int32_t *tw, Eight<NM> &E) {
+  E.x = x;
+  E.n = load_eight(rs, ab, L, tm, x, E.a, E.b, E.c);
+#pragma unroll
+  for (int r = 0; r < Eight<NM>::PR; ++r) load_tw8(tw + (uint64_t)r * L + x, E.n, E.w[r]);
+}
+
 template <int NM, bool DIG>
-__device__ __forceinline__ void add_eight(Acc3<NM> &A, const uint32_t (&va)[4],
-                                          const uint32_t (&vb)[4], const uint32_t (&vc)[4],
-                                          uint32_t x, uint32_t nvalid, const int32_t *tw,
+__device__ __forceinline__ void add_eight(Acc3<NM> &A, const Eight<NM> &E, const int32_t *tw,
                                           uint32_t L) {
+  const uint32_t(&va)[4] = E.a;
+  const uint32_t(&vb)[4] = E.b;
+  const uint32_t(&vc)[4] = E.c;
+  const uint32_t x = E.x, nvalid = E.n;
   uint32_t Ns[8];
   uint32_t any = 0, odd = 0;
 #pragma unroll
@@ -241,20 +274,19 @@ __device__ __forceinline__ void add_eight(Acc3<NM> &A, const uint32_t (&va)[4],
     A.s[10] += d;
   }
   if constexpr (NM > 0) {
-    // twiddle rows of the slot: row r at tw + r L (4-byte aligned); one mode
-    // (two rows) at a time, so that at most 16 of their values are live
+    // twiddle rows of the slot: row r at tw + r L (4-byte aligned); beyond
+    // two modes, one mode (two rows) at a time, so that at most 16 of their
+    // values are live
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
       int32_t w[2][8];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int32_t *row = tw + (uint64_t)(2 * m + h) * L + x;
-        if (nvalid == 8u) {
-          __builtin_memcpy(&w[h][0], row, 16);
-          __builtin_memcpy(&w[h][4], row + 4, 16);
-        } else {
+        if constexpr (Eight<NM>::PR > 0) {
 #pragma unroll
-          for (uint32_t e = 0; e < 8u; ++e) w[h][e] = e < nvalid ? row[e] : 0;
+          for (int e = 0; e < 8; ++e) w[h][e] = E.w[Eight<NM>::PR > 0 ? 2 * m + h : 0][e];
+        } else {
+          load_tw8(tw + (uint64_t)(2 * m + h) * L + x, nvalid, w[h]);
         }
       }
 #pragma unroll
@@ -264,7 +296,7 @@ __device__ __forceinline__ void add_eight(Acc3<NM> &A, const uint32_t (&va)[4],
         for (int e = 0; e < 8; ++e) f += (i64)(int32_t)Ns[e] * (i64)w[h][e];
         A.s[11 + 2 * m + h] += (u64)f;
       }
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (Eight<NM>::PR == 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -293,20 +325,21 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
   A.mxp = 0;
   const uint32_t step = 8u * blockDim.x;
   uint32_t x = sg.x0 + 8u * threadIdx.x;
-  // without twiddle rows, four passes' loads are in flight before any is
-  // summed
-  if constexpr (NM == 0 && !DIG)
-  for (; x + 3u * step < sg.x1; x += 4u * step) {
-    uint32_t a[4][4], b[4][4], c[4][4], n[4];
+  // U passes' loads are in flight before any is summed (fewer with more
+  // twiddle rows or with the digest, which need registers or time of their
+  // own)
+  constexpr int U = DIG ? 1 : NM == 0 ? 4 : NM <= 2 ? 2 : 1;
+  for (; x + (U - 1) * step < sg.x1; x += U * step) {
+    Eight<NM> E[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) n[u] = load_eight(rs, ab, L, tm, x + u * step, a[u], b[u], c[u]);
+    for (int u = 0; u < U; ++u) load_window<NM>(rs, ab, L, tm, x + u * step, tw, E[u]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) add_eight<NM, DIG>(A, a[u], b[u], c[u], x + u * step, n[u], tw, L);
+    for (int u = 0; u < U; ++u) add_eight<NM, DIG>(A, E[u], tw, L);
   }
   for (; x < sg.x1; x += step) {
-    uint32_t a0[4], b0[4], c0[4];
-    const uint32_t n0 = load_eight(rs, ab, L, tm, x, a0, b0, c0);
-    add_eight<NM, DIG>(A, a0, b0, c0, x, n0, tw, L);
+    Eight<NM> E;
+    load_window<NM>(rs, ab, L, tm, x, tw, E);
+    add_eight<NM, DIG>(A, E, tw, L);
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) A.s[k] += A.f[k];

@@ -20,8 +20,14 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_record_follows_from_its_counters():
-    d = json.load(open(bench.TRAFFIC_FILE))
+# sites per launch of each counted workload: L = 2^24, L = 2^27, and the
+# 1024-replica manifest
+TRAFFIC_SITES = {"plain": 1 << 24, "probe": 1 << 27, "batched": 137_671_148}
+
+
+@pytest.mark.parametrize("which", sorted(TRAFFIC_SITES))
+def test_traffic_record_follows_from_its_counters(which):
+    d = json.load(open(bench.TRAFFIC_FILES[which]))
     cal = d["copy_calibration"]
     # the calibration copy moves a known number of bytes each way
     assert cal["fetch_factor"] == pytest.approx(cal["bytes_read"] / 1024 / cal["fetch_size_kib"])
@@ -29,11 +35,17 @@ def test_traffic_record_follows_from_its_counters():
     want = 1024 * (d["fetch_size_kib_per_dispatch"] * cal["fetch_factor"] +
                    d["write_size_kib_per_dispatch"] * cal["write_factor"])
     assert d["bytes_per_launch"] == pytest.approx(want, rel=1e-9)
-    # 12 bytes per site update at L = 2^24
-    assert d["algorithmic_bytes_per_launch"] == bench.BYTES_PER_SITE_UPDATE * (1 << 24)
+    # 12 bytes per site update
+    assert d["algorithmic_bytes_per_launch"] == bench.BYTES_PER_SITE_UPDATE * TRAFFIC_SITES[which]
     assert d["ratio_to_algorithmic"] == pytest.approx(d["bytes_per_launch"] /
                                                       d["algorithmic_bytes_per_launch"])
     assert len(d["kernel_sha256_16"]) == 16
+    assert [os.path.basename(p) for p in bench.KERNEL_SRCS] == d["kernel_sources"]
+
+
+def test_batched_manifest_size():
+    import synth
+    assert int(sum(synth.replica_manifest()["L"])) == TRAFFIC_SITES["batched"]
 
 
 def test_valu_record_follows_from_its_counters():

@@ -235,27 +235,29 @@ def batched_observables(lat, torch, man, samples: int, every: int) -> dict:
     tw = sk_twiddles(torch, man["L"], n_modes, lat.device)
     L = man["L"].astype(np.float64)
     rho = man["rho"]
-    vm, sk = [], []
-    for _ in range(samples):
+    vm = []
+    sk = np.zeros((samples, len(L), n_modes))
+    for k in range(samples):
         lat.step(every)
         ms = lat.moments(tw, n_modes)
         v = np.zeros(3)
-        s = np.zeros(n_modes)
         for r, m in enumerate(ms):
             mean = np.array(m["sum_n"], dtype=np.float64) / L[r]
             var = np.array(m["sum_n2"], dtype=np.float64) / L[r] - mean ** 2
             v += var / mean
             f = np.array(m["fourier"][:n_modes], dtype=np.float64) / float(1 << 24)
-            s += (f[:, 0] ** 2 + f[:, 1] ** 2) / L[r] / rho[r]
+            sk[k, r] = (f[:, 0] ** 2 + f[:, 1] ** 2) / L[r] / rho[r]
         vm.append(v / len(ms))
-        sk.append(s / len(ms))
     del tw
-    vm, sk = np.array(vm), np.array(sk)
+    # the long-wavelength modes change little between samples, so the
+    # standard error is taken over the independent replicas (each replica's
+    # mean over its samples)
+    per_rep = sk.mean(0)
     return {"samples": samples, "every": every, "replicas": len(man["L"]),
-            "var_over_mean": [round(float(x), 5) for x in vm.mean(0)],
-            "S_k_over_rho": [round(float(x), 4) for x in sk.mean(0)],
-            "S_k_over_rho_se": [round(float(x), 4) for x in sk.std(0, ddof=1) /
-                                np.sqrt(len(sk))] if samples > 1 else None}
+            "var_over_mean": [round(float(x), 5) for x in np.array(vm).mean(0)],
+            "S_k_over_rho": [round(float(x), 4) for x in per_rep.mean(0)],
+            "S_k_over_rho_se": [round(float(x), 4) for x in per_rep.std(0, ddof=1) /
+                                np.sqrt(per_rep.shape[0])]}
 
 
 def run_batched(args, torch, M):

@@ -13,7 +13,7 @@
 namespace mclg {
 
 // Sites [x0, x1) of slot `slot` (D2Q9: sites s = y Lx + x of replica `slot`),
-// part of run `run` (the run's result row).
+// part of run `run`.
 struct MomSeg {
   uint32_t slot = 0, x0 = 0, x1 = 0, run = 0;
 };
@@ -26,7 +26,8 @@ struct MomPlan {
   std::vector<uint32_t> run_slot;  // runs
 };
 
-// Segments of 8192 to 2^23 sites (a multiple of 2048) and about 512 of them
+// Segments of 16384 to 2^23 sites (a multiple of 16384: eight passes of a
+// 256-thread block over eight sites per lane) and about 512 of them
 // in all (two blocks per compute unit, one wave of blocks), so that at most
 // 512 + n + total / 2^23 segments are made for n slots of `total` sites
 // (2^23 bounds the 32-bit packed sums).

@@ -108,13 +108,6 @@ __device__ __forceinline__ void write_partial(u64 (&v)[V], uint32_t mx, u64 *rec
   }
 }
 
-// The first segment of each run (x0 = 0) clears the run's result row before
-// the final pass adds into it.
-__device__ __forceinline__ void clear_result(const MomSeg &sg, uint32_t n_out, i64 *out) {
-  if (sg.x0 == 0u)
-    for (uint32_t k = threadIdx.x; k < n_out; k += blockDim.x) out[(uint64_t)sg.run * n_out + k] = 0;
-}
-
 // ---- D1Q3 ----------------------------------------------------------------
 // The eight sites x .. x+7 of a lane in logical order: n_-1 from physical
 // (x + tm) mod L, n_0 from x, n_+1 from (x - tm) mod L, two sites per 32-bit
@@ -197,6 +190,54 @@ __device__ __forceinline__ void load_window(Rsrc rs, uint32_t ab, uint32_t L, ui
   E.n = load_eight(rs, ab, L, tm, x, E.a, E.b, E.c);
 #pragma unroll
   for (int r = 0; r < Eight<NM>::PR; ++r) load_tw8(tw + (uint64_t)r * L + x, E.n, E.w[r]);
+}
+
+// Whether the eight sites x .. x + 7 are all in the lattice and none of
+// their three shifted windows wraps around its end.
+__device__ __forceinline__ bool window_fast(uint32_t L, uint32_t tm, uint32_t x) {
+  uint32_t pm = x + tm;
+  pm -= (pm >= L) ? L : 0u;
+  const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+  return x + 8u <= L && pm + 8u <= L && pp + 8u <= L;
+}
+
+// The loads of a window without a branch, for the pipelined passes: a fast
+// window loads its vectors; any other loads from in-bounds offset 0 and is
+// cleared by clear_slow once its loads have arrived (its sites are summed
+// afterwards on the element-wise path).
+template <int NM>
+__device__ __forceinline__ void issue_fast(Rsrc rs, uint32_t ab, uint32_t L, uint32_t tm,
+                                           uint32_t x, Rsrc twr, Eight<NM> &E) {
+  uint32_t pm = x + tm;
+  pm -= (pm >= L) ? L : 0u;
+  const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+  const bool f = x + 8u <= L && pm + 8u <= L && pp + 8u <= L;
+  load16(rs, f ? 2u * pm : 0u, E.a);
+  load16(rs, f ? ab + 2u * x : 0u, E.b);
+  load16(rs, f ? 2u * ab + 2u * pp : 0u, E.c);
+#pragma unroll
+  for (int r = 0; r < Eight<NM>::PR; ++r) {
+    const uint32_t o = 4u * ((uint32_t)r * L + (f ? x : 0u));
+    uint32_t q[4];
+    load16(twr, o, q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) E.w[r][e] = (int32_t)q[e];
+    load16(twr, o + 16u, q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) E.w[r][4 + e] = (int32_t)q[e];
+  }
+  E.x = x;
+  E.n = f ? 8u : 0u;
+}
+template <int NM>
+__device__ __forceinline__ void clear_slow(Eight<NM> &E) {
+  const bool f = E.n != 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    E.a[j] = f ? E.a[j] : 0u;
+    E.b[j] = f ? E.b[j] : 0u;
+    E.c[j] = f ? E.c[j] : 0u;
+  }
 }
 
 template <int NM, bool DIG>
@@ -307,9 +348,8 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
                                               const uint32_t *__restrict__ tslot,
                                               const MomSeg *__restrict__ segs, uint32_t no_stream,
                                               const int32_t *__restrict__ twiddle,
-                                              u64 *__restrict__ partial, i64 *__restrict__ out) {
+                                              u64 *__restrict__ partial) {
   const MomSeg sg = segs[blockIdx.x];
-  clear_result(sg, kMom3Out, out);
   const SlotDev sl = slots[sg.slot];
   const uint32_t L = sl.L;
   const uint32_t tm = no_stream ? 0u : tslot[sg.slot] % L;
@@ -324,19 +364,56 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
   A.mx = 0;
   A.mxp = 0;
   const uint32_t step = 8u * blockDim.x;
-  uint32_t x = sg.x0 + 8u * threadIdx.x;
-  // U passes' loads are in flight before any is summed (fewer with more
-  // twiddle rows or with the digest, which need registers or time of their
-  // own)
-  constexpr int U = DIG ? 1 : NM == 0 ? 4 : NM <= 2 ? 2 : 1;
-  for (; x + (U - 1) * step < sg.x1; x += U * step) {
-    Eight<NM> E[U];
+  const uint32_t xb = sg.x0 + 8u * threadIdx.x;
+  // Full passes (every lane's eight sites inside the segment) go in batches
+  // of U passes, software-pipelined over two register sets: a batch's loads
+  // are issued before the previous batch is summed.  Every batch issues the
+  // same loads whatever its windows, so each wait covers exactly the batch
+  // being summed.  Segments hold a multiple of 2 U passes except a run's
+  // last; what the batches leave is summed on the element-wise path.
+  constexpr int U = NM == 0 && !DIG ? 4 : NM == 1 && !DIG ? 2 : 1;
+  // (more than two modes: one pass at a time, unpipelined)
+  const uint32_t nb2 = NM <= 2 ? ((sg.x1 - sg.x0) / step / U) & ~1u : 0u;  // batches, even
+  if (nb2) {
+    // the slot's twiddle rows through a buffer resource (2 modes x 2 rows of
+    // L int32 at most, below 2^31 bytes for L up to 2^27)
+    const Rsrc twr = make_rsrc(NM > 0 ? tw : nullptr, NM > 0 ? 8u * NM * L : 0u);
+    Eight<NM> E0[U], E1[U];
+    // (the scheduling barrier keeps the sums of the previous batch from
+    // being hoisted above these loads, which would wait for that batch first)
+    auto issue = [&](Eight<NM>(&E)[U], uint32_t b) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) load_window<NM>(rs, ab, L, tm, x + u * step, tw, E[u]);
+      for (int u = 0; u < U; ++u) issue_fast<NM>(rs, ab, L, tm, xb + (b * U + u) * step, twr, E[u]);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto sum = [&](Eight<NM>(&E)[U]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) add_eight<NM, DIG>(A, E[u], tw, L);
+      for (int u = 0; u < U; ++u) {
+        clear_slow<NM>(E[u]);
+        add_eight<NM, DIG>(A, E[u], tw, L);
+      }
+    };
+    // (after the last pair the loop loads batch nb2 - 1 once more, from
+    // the L2, and does not sum it: no iteration ends differently)
+    issue(E0, 0);
+    for (uint32_t b = 0; b < nb2; b += 2) {
+      issue(E1, b + 1);
+      sum(E0);
+      issue(E0, min(b + 2, nb2 - 1));
+      sum(E1);
+    }
+    // the windows of those passes that wrap (at most three per lattice)
+    for (uint32_t q = 0; q < nb2 * U; ++q) {
+      const uint32_t x = xb + q * step;
+      if (!window_fast(L, tm, x)) {
+        Eight<NM> E;
+        load_window<NM>(rs, ab, L, tm, x, tw, E);
+        add_eight<NM, DIG>(A, E, tw, L);
+      }
+    }
   }
-  for (; x < sg.x1; x += step) {
+  for (uint32_t x = xb + nb2 * U * step; x < sg.x1; x += step) {
     Eight<NM> E;
     load_window<NM>(rs, ab, L, tm, x, tw, E);
     add_eight<NM, DIG>(A, E, tw, L);
@@ -354,20 +431,18 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
   write_partial<V, W, 11>(v, A.mx, partial + (uint64_t)blockIdx.x * kMom3Rec);
 }
 
-// Sums of the partial records of one run in the final pass.  Block
-// (f, j) of a grid of F x runs takes records s0 + f G + g, s0 + (f + F) G + g,
-// ... of run j with G = 256 / (REC / 2) groups g of REC / 2 threads; thread p
-// of a group loads values 2p and 2p + 1 of a record in one 16-byte load
-// (pairs at or past npairs are not read).  Value MS is a maximum, the others
-// are sums modulo 2^64.  Returns false (for the whole block) when the block
-// has no record; otherwise tot[k] holds the slice's value k.
+// Sums of the partial records [s0, s1) of one run in the final pass (one
+// block per run): the block's threads form G = blockDim / (REC / 2) groups
+// of REC / 2; thread p of group g loads values 2p and 2p + 1 of records
+// s0 + g, s0 + g + G, ... with 16-byte loads, eight in flight (pairs at or
+// past npairs are not read), and the groups are added in LDS.  Value MS is
+// a maximum, the others are sums modulo 2^64.  tot[k] holds value k after.
 template <int REC, int MS>
-__device__ __forceinline__ bool sum_slice(const u64 *__restrict__ partial, uint32_t s0,
-                                          uint32_t s1, uint32_t npairs, u64 *tot) {
-  constexpr uint32_t P = REC / 2, G = 256 / P;
-  __shared__ u64 red[2][256];
-  const uint32_t f = blockIdx.x, F = gridDim.x;
-  if (s0 + f * G >= s1) return false;
+__device__ __forceinline__ void sum_run(const u64 *__restrict__ partial, uint32_t s0,
+                                        uint32_t s1, uint32_t npairs, u64 *tot) {
+  constexpr uint32_t P = REC / 2;
+  __shared__ u64 red[2][1024];
+  const uint32_t G = blockDim.x / P;
   const uint32_t p = threadIdx.x % P, g = threadIdx.x / P;
   const bool m0 = 2u * p == (uint32_t)MS, m1 = 2u * p + 1u == (uint32_t)MS;
   u64 a0 = 0, a1 = 0;
@@ -378,17 +453,15 @@ __device__ __forceinline__ bool sum_slice(const u64 *__restrict__ partial, uint3
   };
   if (p < npairs) {
     const uint4 *base = reinterpret_cast<const uint4 *>(partial) + p;
-    const uint32_t st = F * G;
-    uint32_t r = s0 + f * G + g;
-    for (; r + 3u * st < s1; r += 4u * st) {  // four loads in flight
-      const uint4 q0 = base[(uint64_t)r * P], q1 = base[(uint64_t)(r + st) * P];
-      const uint4 q2 = base[(uint64_t)(r + 2u * st) * P], q3 = base[(uint64_t)(r + 3u * st) * P];
-      add(q0);
-      add(q1);
-      add(q2);
-      add(q3);
+    uint32_t r = s0 + g;
+    for (; r + 7u * G < s1; r += 8u * G) {
+      uint4 q[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8u; ++i) q[i] = base[(uint64_t)(r + i * G) * P];
+#pragma unroll
+      for (uint32_t i = 0; i < 8u; ++i) add(q[i]);
     }
-    for (; r < s1; r += st) add(base[(uint64_t)r * P]);
+    for (; r < s1; r += G) add(base[(uint64_t)r * P]);
   }
   red[0][threadIdx.x] = a0;
   red[1][threadIdx.x] = a1;
@@ -403,50 +476,36 @@ __device__ __forceinline__ bool sum_slice(const u64 *__restrict__ partial, uint3
     tot[k] = t;
   }
   __syncthreads();
-  return true;
 }
 
-// Final pass, block (f, j): adds its slice of run j's records into the
-// replica's result in the field order of mclg_moments_t: t (the device step
-// counter), sites, sum n_i, sum n_i^2, sum n_i n_j, sum N = sum of the three
-// sums, sum J = sum n_+1 - sum n_-1, sum N^2 = sum n_i^2 + 2 sum n_i n_j,
-// sites with odd n_0, max N, Fourier sums, digest.  Every field but t and
-// sites (written by block 0) is a sum of the slices' contributions or their
-// maximum, combined with 64-bit integer atomics, so the result does not
-// depend on their order.
-__global__ void __launch_bounds__(256) k_mom3_final(const u64 *__restrict__ partial,
-                                                    const uint32_t *__restrict__ run_seg,
-                                                    const uint32_t *__restrict__ run_slot,
-                                                    const SlotDev *__restrict__ slots,
-                                                    const uint32_t *__restrict__ tslot,
-                                                    uint32_t n_modes, i64 *__restrict__ out) {
+// Final pass, one block per run j: the replica's result in the field order
+// of mclg_moments_t: t (the device step counter), sites, sum n_i, sum n_i^2,
+// sum n_i n_j, sum N = sum of the three sums, sum J = sum n_+1 - sum n_-1,
+// sum N^2 = sum n_i^2 + 2 sum n_i n_j, sites with odd n_0, max N, Fourier
+// sums, digest.
+__global__ void __launch_bounds__(1024) k_mom3_final(const u64 *__restrict__ partial,
+                                                     const uint32_t *__restrict__ run_seg,
+                                                     const uint32_t *__restrict__ run_slot,
+                                                     const SlotDev *__restrict__ slots,
+                                                     const uint32_t *__restrict__ tslot,
+                                                     uint32_t n_modes, i64 *__restrict__ out) {
   __shared__ u64 T[kMom3Rec];
-  const uint32_t j = blockIdx.y, slot = run_slot[j];
-  if (!sum_slice<kMom3Rec, 11>(partial, run_seg[j], run_seg[j + 1], 6u + n_modes, T)) return;
-  u64 *o = reinterpret_cast<u64 *>(out + (uint64_t)j * kMom3Out);
+  const uint32_t j = blockIdx.x, slot = run_slot[j];
+  sum_run<kMom3Rec, 11>(partial, run_seg[j], run_seg[j + 1], 6u + n_modes, T);
   const uint32_t k = threadIdx.x;
   if (k >= kMom3Out) return;
-  if (k <= 1u) {
-    if (blockIdx.x == 0) o[k] = k == 0 ? tslot[slot] : slots[slot].L;
-    return;
-  }
-  if (k == 15u) {
-    atomicMax(&o[k], T[11]);
-    return;
-  }
-  u64 v;
-  if (k <= 10u) v = T[k - 2u];
+  u64 v = 0;
+  if (k == 0u) v = tslot[slot];
+  else if (k == 1u) v = slots[slot].L;
+  else if (k <= 10u) v = T[k - 2u];
   else if (k == 11u) v = T[0] + T[1] + T[2];
   else if (k == 12u) v = T[2] - T[0];
   else if (k == 13u) v = T[3] + T[4] + T[5] + 2ull * (T[6] + T[7] + T[8]);
   else if (k == 14u) v = T[9];
-  else if (k < 32u) {
-    if (k - 16u >= 2u * n_modes) return;
-    v = T[k - 4u];
-  } else {
-    v = T[10];
-  }
-  atomicAdd(&o[k], v);
+  else if (k == 15u) v = T[11];
+  else if (k < 32u) v = k - 16u < 2u * n_modes ? T[k - 4u] : 0ull;
+  else v = T[10];
+  out[(uint64_t)j * kMom3Out + k] = (i64)v;
 }
 
 // ---- D2Q9 ----------------------------------------------------------------
@@ -478,14 +537,13 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
                                               const Rep9 *__restrict__ reps, uint64_t t,
                                               uint32_t no_stream,
                                               const MomSeg *__restrict__ segs,
-                                              u64 *__restrict__ partial, i64 *__restrict__ out) {
+                                              u64 *__restrict__ partial) {
   __shared__ u64 big[45];
   __shared__ u64 red64[4][64];
   __shared__ uint32_t redmx[4];
   for (uint32_t k = threadIdx.x; k < 45u; k += blockDim.x) big[k] = 0;
   __syncthreads();
   const MomSeg sg = segs[blockIdx.x];
-  clear_result(sg, kMom9Out, out);
   const Rep9 rp = reps[sg.slot];
   const uint32_t Lx = rp.Lx, Ly = rp.Ly;
   const uint32_t tx = no_stream ? 0u : (uint32_t)(t % Lx);
@@ -617,56 +675,50 @@ __global__ void __launch_bounds__(256) k_mom9(const uint16_t *__restrict__ state
   }
 }
 
-// Final pass, block (f, j): adds its slice of run j's records into the
-// replica's result in the field order of mclg_moments9_t: t, sites, sum n_i,
-// sum n_i n_j (i <= j), sum N, sum Jx, sum Jy (from the per-velocity sums),
-// max N; combined over slices as in the D1Q3 pass.
-__global__ void __launch_bounds__(256) k_mom9_final(const u64 *__restrict__ partial,
-                                                    const uint32_t *__restrict__ run_seg,
-                                                    const uint32_t *__restrict__ run_slot,
-                                                    const Rep9 *__restrict__ reps, uint64_t t,
-                                                    i64 *__restrict__ out) {
+// Final pass, one block per run j: the replica's result in the field order
+// of mclg_moments9_t: t, sites, sum n_i, sum n_i n_j (i <= j), sum N, sum
+// Jx, sum Jy (from the per-velocity sums), max N.
+__global__ void __launch_bounds__(1024) k_mom9_final(const u64 *__restrict__ partial,
+                                                     const uint32_t *__restrict__ run_seg,
+                                                     const uint32_t *__restrict__ run_slot,
+                                                     const Rep9 *__restrict__ reps, uint64_t t,
+                                                     i64 *__restrict__ out) {
   __shared__ u64 T[kMom9Rec];
-  const uint32_t j = blockIdx.y, slot = run_slot[j];
-  if (!sum_slice<kMom9Rec, kMom9Max>(partial, run_seg[j], run_seg[j + 1], kMom9Used / 2u, T))
-    return;
-  u64 *o = reinterpret_cast<u64 *>(out + (uint64_t)j * kMom9Out);
+  const uint32_t j = blockIdx.x, slot = run_slot[j];
+  sum_run<kMom9Rec, kMom9Max>(partial, run_seg[j], run_seg[j + 1], kMom9Used / 2u, T);
   const uint32_t k = threadIdx.x;
   if (k >= kMom9Out) return;
-  if (k <= 1u) {
-    if (blockIdx.x == 0) o[k] = k == 0 ? t : reps[slot].S;
-    return;
-  }
-  if (k == 59u) {
-    atomicMax(&o[k], T[kMom9Max]);
-    return;
-  }
   u64 v = 0;
-  if (k < 56u) {
+  if (k == 0u) {
+    v = t;
+  } else if (k == 1u) {
+    v = reps[slot].S;
+  } else if (k < 56u) {
     v = T[k - 2u];
+  } else if (k == 59u) {
+    v = T[kMom9Max];
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i)
       v += (u64)(k == 56u ? 1 : k == 57u ? kVx9[i] : kVy9[i]) * T[i];
   }
-  atomicAdd(&o[k], v);
+  out[(uint64_t)j * kMom9Out + k] = (i64)v;
 }
 
-// Blocks per run of the final pass: about 32 records each (from the mean
-// segments per run), at most 32.
-uint32_t final_slices(const MomArgs &a) {
-  const uint32_t per_run = (a.n_segs + a.n_runs - 1) / a.n_runs;
-  return std::max(1u, std::min(32u, (per_run + 31u) / 32u));
+// Threads per block of the final pass: 1024 when runs have many records
+// (about 512 segments for one lattice), else 256.
+uint32_t final_threads(const MomArgs &a) {
+  return a.n_segs >= 64u * a.n_runs ? 1024u : 256u;
 }
 
 template <int NM>
 hipError_t launch3(hipStream_t s, const MomArgs &a) {
   if (a.digest)
     k_mom3<NM, true><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
-                                              a.twiddle, a.partial, a.out);
+                                              a.twiddle, a.partial);
   else
     k_mom3<NM, false><<<a.n_segs, 256, 0, s>>>(a.state, a.slots, a.tslot, a.segs, a.no_stream,
-                                               a.twiddle, a.partial, a.out);
+                                               a.twiddle, a.partial);
   return hipGetLastError();
 }
 
@@ -703,7 +755,7 @@ MomPlan plan_moments(const uint32_t *slots, const uint64_t *sites, uint32_t n) {
   uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) total += sites[j];
   uint64_t seg = (total + kMomMaxSegsBase - 1) / kMomMaxSegsBase;
-  seg = std::min<uint64_t>(kMomMaxSegSites, std::max<uint64_t>(8192, (seg + 2047) / 2048 * 2048));
+  seg = std::min<uint64_t>(kMomMaxSegSites, std::max<uint64_t>(16384, (seg + 16383) / 16384 * 16384));
   p.run_seg.push_back(0);
   for (uint32_t j = 0; j < n; ++j) {
     for (uint64_t x0 = 0; x0 < sites[j]; x0 += seg) {
@@ -742,18 +794,18 @@ hipError_t launch_moments3(hipStream_t s, const MomArgs &a) {
     default: e = launch3<8>(s, a); break;
   }
   if (e) return e;
-  k_mom3_final<<<dim3(final_slices(a), a.n_runs), 256, 0, s>>>(
-      a.partial, a.run_seg, a.run_slot, a.slots, a.tslot, a.n_modes, a.out);
+  k_mom3_final<<<a.n_runs, final_threads(a), 0, s>>>(a.partial, a.run_seg, a.run_slot, a.slots,
+                                                     a.tslot, a.n_modes, a.out);
   return hipGetLastError();
 }
 
 hipError_t launch_moments9(hipStream_t s, const MomArgs &a) {
   if (a.n_runs == 0) return hipSuccess;
-  k_mom9<<<a.n_segs, 256, 0, s>>>(a.state, a.reps, a.t9, a.no_stream, a.segs, a.partial, a.out);
+  k_mom9<<<a.n_segs, 256, 0, s>>>(a.state, a.reps, a.t9, a.no_stream, a.segs, a.partial);
   hipError_t e = hipGetLastError();
   if (e) return e;
-  k_mom9_final<<<dim3(final_slices(a), a.n_runs), 256, 0, s>>>(a.partial, a.run_seg, a.run_slot,
-                                                               a.reps, a.t9, a.out);
+  k_mom9_final<<<a.n_runs, final_threads(a), 0, s>>>(a.partial, a.run_seg, a.run_slot, a.reps,
+                                                     a.t9, a.out);
   return hipGetLastError();
 }
 

@@ -223,15 +223,21 @@ __device__ __forceinline__ void set16(uint32_t (&w)[4], int e, uint32_t v) {
 // 16 * lane for every window.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+// CP: the cache policy bits of the access (0, or kStreamingPolicy for
+// states that do not fit the caches: non-temporal, the lines are not
+// expected to be reused before they leave).
+constexpr int kStreamingPolicy = 2;  // nt
+template <int CP = 0>
 __device__ __forceinline__ void bload4(Rsrc r, uint32_t voff, uint32_t soff, uint32_t (&v)[4]) {
-  const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CP);
   v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore4(Rsrc r, uint32_t voff, uint32_t soff,
                                         const uint32_t (&v)[4]) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const u32x4 q = {v[0], v[1], v[2], v[3]};
-  __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, (int)soff, CP);
 }
 __device__ __forceinline__ uint32_t bload2(Rsrc r, uint32_t voff, uint32_t soff) {
   return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
@@ -598,12 +604,13 @@ __device__ __forceinline__ Win locate(uint32_t xs, const SlotView &v) {
 struct Raw {
   uint32_t m[4], z[4], p[4];
 };
+template <int CP>
 __device__ __forceinline__ void issue_raw(const Win &w, const SlotView &v, uint32_t lane,
                                           Raw &r) {
   const uint32_t vo = 16u * lane;
-  bload4(v.rs(), vo, 2u * w.sm, r.m);
-  bload4(v.rs(), vo, v.ab + 2u * w.xs, r.z);
-  bload4(v.rs(), vo, 2u * v.ab + 2u * w.sp, r.p);
+  bload4<CP>(v.rs(), vo, 2u * w.sm, r.m);
+  bload4<CP>(v.rs(), vo, v.ab + 2u * w.xs, r.z);
+  bload4<CP>(v.rs(), vo, 2u * v.ab + 2u * w.sp, r.p);
 }
 // The chunk's three windows as eight consecutive sites per lane, in place in
 // `r`: a fast chunk's vectors are there already; a chunk whose windows wrap
@@ -652,6 +659,9 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 template <int MAXT, bool GAL, int MODE>
 __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   constexpr bool PATCH = MODE == kDrainPatch;
+  // patched drains are the policy for states larger than the caches: their
+  // chunk vectors are read and written as streaming (non-temporal) accesses
+  constexpr int CP = PATCH ? kStreamingPolicy : 0;
   extern __shared__ uint4 lds[];
   const StepParams &p = a.p;
   const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
@@ -733,7 +743,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     if (threadIdx.x == 0) next_chunk = i + nwaves;
     Win cw = locate(t0.x0 + (k - i) * 512u, sv);
     Raw cr;
-    if (k < se && cw.fast) issue_raw(cw, sv, lane, cr);
+    if (k < se && cw.fast) issue_raw<CP>(cw, sv, lane, cr);
     if (new_image) {
       // ten independent 16-byte loads per thread per round (a 1024-thread
       // block moves 160 KiB in one round), then the stores (indices clamped
@@ -780,7 +790,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       Win nw = cw;
       if (has_next) {
         nw = locate(t0.x0 + (nk - i) * 512u, sv);
-        if (nw.fast) issue_raw(nw, sv, lane, nxt);
+        if (nw.fast) issue_raw<CP>(nw, sv, lane, nxt);
       }
 
       // ---- collide: LDS image first, the rest into the wave's queue ----
@@ -807,9 +817,9 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       // ---- store ----
       if (cw.fast) {
         const uint32_t vo = 16u * lane;
-        bstore4(rs, vo, 2u * cw.sm, cur.m);
-        bstore4(rs, vo, ab + 2u * cw.xs, cur.z);
-        bstore4(rs, vo, 2u * ab + 2u * cw.sp, cur.p);
+        bstore4<CP>(rs, vo, 2u * cw.sm, cur.m);
+        bstore4<CP>(rs, vo, ab + 2u * cw.xs, cur.z);
+        bstore4<CP>(rs, vo, 2u * ab + 2u * cw.sp, cur.p);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {

@@ -57,17 +57,30 @@ def kernel_hash(paths=None) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(which: str = "plain"):
-    """HBM bytes per launch from the committed rocprofv3 counter runs of this
-    workload, if they were taken on the current kernel source."""
+def _counter_record(which: str):
+    """The committed rocprofv3 counter record of this workload, if it was
+    taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILES[which]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != kernel_hash():
+    return d if d.get("kernel_sha256_16") == kernel_hash() else None
+
+
+def measured_traffic(which: str = "plain"):
+    """HBM bytes per launch from the committed counter runs, or None."""
+    d = _counter_record(which)
+    return None if d is None else d.get("bytes_per_launch")
+
+
+def valu_issue_frac(which: str, seconds_per_launch: float):
+    """The step launch's VALU issue time (its counted VALU wave instructions
+    at the 614.4 G/s issue peak) over its measured duration, or None."""
+    d = _counter_record(which)
+    if d is None or "sq_insts_valu_per_dispatch" not in d:
         return None
-    return d.get("bytes_per_launch")
+    return d["sq_insts_valu_per_dispatch"] / (VALU_PEAK_G * 1e9) / seconds_per_launch
 
 
 def host_info() -> dict:
@@ -201,7 +214,8 @@ def run_probe(args, torch, M):
             "achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_over_algorithmic": None if traffic is None else
-            traffic / (BYTES_PER_SITE_UPDATE * L)}
+            traffic / (BYTES_PER_SITE_UPDATE * L),
+            "valu_issue_frac": valu_issue_frac("probe", ms / 1e3)}
 
 
 def sk_twiddles(torch, Ls, n_modes: int, device):
@@ -303,6 +317,7 @@ def run_batched(args, torch, M):
     out["traffic"] = traffic
     out["traffic_over_algorithmic"] = None if traffic is None else \
         traffic / (BYTES_PER_SITE_UPDATE * sites)
+    out["valu_issue_frac"] = valu_issue_frac("batched", out["batched"]["us_per_step"] / 1e6)
     # plain: one launch per replica per step
     n = len(man["L"])
     e0, e1 = _events(torch, lat.stream)
@@ -593,7 +608,8 @@ def main():
                    "lambda": 1, "n_max": 255, "seed": 2, "launch": "graph" if args.graph else "plain",
                    "schedule": args.schedule or "default", **info},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("plain")},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("plain"),
+                     "valu_issue_frac": valu_issue_frac("plain", ms_per_step / 1e3)},
         "statistics": stats,
     }
     if args.only == "plain":

@@ -60,3 +60,17 @@ def test_valu_record_follows_from_its_counters():
 def test_valu_issue_peak():
     # 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles, 2.4 GHz
     assert bench.VALU_PEAK_G == pytest.approx(614.4)
+
+
+@pytest.mark.parametrize("which", sorted(TRAFFIC_SITES))
+def test_valu_issue_fraction_from_the_record(which):
+    d = json.load(open(bench.TRAFFIC_FILES[which]))
+    # 256 persistent blocks of 16 waves
+    assert d["sq_waves_per_dispatch"] == 4096
+    assert d["sq_insts_valu_per_dispatch"] > 0
+    if d["kernel_sha256_16"] == bench.kernel_hash():
+        t = 1e-3
+        assert bench.valu_issue_frac(which, t) == pytest.approx(
+            d["sq_insts_valu_per_dispatch"] / (bench.VALU_PEAK_G * 1e9) / t)
+    else:
+        assert bench.valu_issue_frac(which, 1e-3) is None

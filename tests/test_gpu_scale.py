@@ -128,11 +128,19 @@ def test_batched_replicas_50_steps():
                 _diff(got[r][k], want[k], f"replica {r} t={(k + 1) * every}")
 
 
-def _oracle_window(L, seed, rho, u0, T, x0, W):
+def _oracle_window(L, seed, rho, u0, T, x0, W, counts=None, rid=None):
+    """Counts of sites x0 .. x0 + W - 1 after T steps, from the oracle run on
+    their light cone x0 - T .. x0 + W + T - 1 alone (its own ends are wrong
+    after t steps only within t sites of them).  The sites keep their
+    logical positions (and the replica its id) for the random numbers; the
+    start is the Poisson draw or the given counts."""
     lo = x0 - T
-    o = O.OracleSim([W + 2 * T], seed, C=10)
+    o = O.OracleSim([W + 2 * T], seed, C=10, replica_id=None if rid is None else [rid])
     o.set_site_offset(0, lo, 0)
-    o.init_poisson(0, rho, u0)
+    if counts is None:
+        o.init_poisson(0, rho, u0)
+    else:
+        o.init_counts(0, counts[:, lo:lo + W + 2 * T])
     o.step(T)
     out = o.counts(0)[:, T:T + W]
     o.close()
@@ -184,3 +192,92 @@ def test_largest_lattice_windows():
     assert m1["sum_N"] == m0["sum_N"] and m1["sum_J"] == m0["sum_J"]
     _windows(g, L, 41, 8.0, 0.05, T, [T, L // 2 + 12345, L - 1500 - T])
     g.close()
+
+
+def _full_run_windows(g, L, seed, rho, u0, steps, every, per, W=256, counts=None, pick_seed=7):
+    """Steps the one-lattice g to `steps` and compares `per` oracle
+    light-cone windows with its counts at every multiple of `every`."""
+    rng = np.random.default_rng(pick_seed)
+    marks = list(range(every, steps + 1, every))
+    with ThreadPoolExecutor(WORKERS) as ex:
+        futs = {}
+        for T in marks:
+            x0s = [int(v) for v in rng.integers(T, L - W - T, size=per)]
+            futs[T] = [(x0, ex.submit(_oracle_window, L, seed, rho, u0, T, x0, W, counts))
+                       for x0 in x0s]
+        t = 0
+        for T in marks:
+            g.step(T - t)
+            t = T
+            full = g.counts(0)
+            for x0, f in futs[T]:
+                _diff(full[:, x0:x0 + W], f.result(), f"t={T} window at {x0}")
+            say("t", T, "windows equal")
+
+
+def test_plain_large_full_run_windows():
+    """The whole 10^4-step run of the L = 2^24 workload: three oracle
+    light-cone windows of 256 sites equal the GPU's counts after every 1000
+    steps (the oracle recomputes each window from the Poisson start)."""
+    w = synth.PLAIN_LARGE
+    L = w["L"]
+    say("plain full run", L)
+    g = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    _full_run_windows(g, L, w["seed"], w["rho"], w["u0"], steps=10_000, every=1000, per=3)
+    g.close()
+
+
+def test_density_wave_full_run_windows():
+    """The whole 5000-step density-wave run: three oracle windows from the
+    synthetic counts after every 1000 steps."""
+    w = synth.DENSITY_WAVE
+    L = w["L"]
+    counts = synth.density_wave_counts()
+    say("density wave full run", L)
+    g = Lattice(L, w["seed"], counts=counts)
+    _full_run_windows(g, L, w["seed"], None, None, steps=5000, every=1000, per=3, counts=counts)
+    g.close()
+
+
+def test_batched_full_run():
+    """The whole 2000-step batched run: the 12 smallest replicas equal the
+    oracle's whole runs at t = 1000 and 2000, and two oracle windows in each
+    of the 8 densest and 4 largest replicas equal the GPU's there."""
+    man = synth.replica_manifest()
+    seed = synth.BATCHED["seed"]
+    Ls = man["L"].astype(np.int64)
+    small = [int(r) for r in np.argsort(Ls, kind="stable")[:12]]
+    dense = [int(r) for r in np.argsort(-man["rho"], kind="stable")[:8]]
+    big = [int(r) for r in np.argsort(-Ls, kind="stable")[:4]]
+    T, every, W = 2000, 1000, 256
+    rng = np.random.default_rng(11)
+    say("batched full run", len(Ls))
+    with ThreadPoolExecutor(WORKERS) as ex:
+        whole = {r: ex.submit(_oracle_replica, man, seed, r, T, every) for r in small}
+        wins = {}
+        for r in dense + big:
+            if r in whole:
+                continue
+            L = int(Ls[r])
+            if L < W + 2 * T + 1:  # too short for a window: the whole replica
+                whole[r] = ex.submit(_oracle_replica, man, seed, r, T, every)
+                continue
+            for t in range(every, T + 1, every):
+                for x0 in (int(v) for v in rng.integers(t, L - W - t, size=2)):
+                    wins.setdefault((r, t), []).append(
+                        (x0, ex.submit(_oracle_window, L, seed, float(man["rho"][r]),
+                                       float(man["u0"][r]), t, x0, W, None,
+                                       int(man["replica_id"][r]))))
+        g = Lattice(man["L"], seed, rho=man["rho"], u0=man["u0"], replica_id=man["replica_id"])
+        for k, t in enumerate(range(every, T + 1, every)):
+            g.step(every)
+            for r, f in whole.items():
+                _diff(g.counts(r), f.result()[k], f"replica {r} t={t}")
+            for (r, tt), lst in wins.items():
+                if tt != t:
+                    continue
+                full = g.counts(r)
+                for x0, f in lst:
+                    _diff(full[:, x0:x0 + W], f.result(), f"replica {r} t={t} window at {x0}")
+            say("t", t, "replicas and windows equal")
+        g.close()

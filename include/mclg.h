@@ -243,9 +243,9 @@ int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes, uint32
  *     steps taken modulo 2^32).
  *   Partial sums live in a static 8 MiB area of device memory, one per GPU,
  *     allocated with the library's code and kept until the process ends; a
- *     call needs 256 bytes per segment of the context's sites (about
- *     4096 + n_replicas segments): MCLG_E_TOO_LARGE when that exceeds
- *     8 MiB, i.e. for more than about 28000 replicas.
+ *     call needs 256 bytes per segment of the context's sites (at most
+ *     512 + n_replicas + sites / 2^23 segments): MCLG_E_TOO_LARGE when that
+ *     exceeds 8 MiB, i.e. for more than about 32000 replicas.
  *   Every call on a GPU uses that GPU's one area and overwrites what it
  *     reads, so nothing needs clearing between calls, but calls that overlap
  *     on one GPU (other streams, other threads) race: serialise them.

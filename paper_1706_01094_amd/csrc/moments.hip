@@ -146,8 +146,9 @@ __device__ __forceinline__ uint32_t load_eight(Rsrc rs, uint32_t ab, uint32_t L,
 // Windows whose counts are all below 256 add their sums and products with
 // packed dot products into 32-bit sums (f, in the order of record slots
 // 0..8): each adds at most 8 x 255^2 per window, and a lane sums at most
-// 2^23 / 256 windows of a segment (segments hold at most 2^23 sites), which
-// stays below 2^32.  Other windows add exact 64-bit sums.
+// 2^23 / 2048 = 4096 windows of a segment (segments hold at most 2^23 sites,
+// a pass of 256 lanes covers 2048), so f stays below 4096 x 8 x 255^2 <
+// 2^32.  Other windows add exact 64-bit sums.
 template <int NM>
 struct Acc3 {
   u64 s[11 + 2 * NM];
@@ -372,11 +373,13 @@ __global__ void __launch_bounds__(256) k_mom3(const uint16_t *__restrict__ state
   // being summed.  Segments hold a multiple of 2 U passes except a run's
   // last; what the batches leave is summed on the element-wise path.
   constexpr int U = NM == 0 && !DIG ? 4 : NM == 1 && !DIG ? 2 : 1;
-  // (more than two modes: one pass at a time, unpipelined)
-  const uint32_t nb2 = NM <= 2 ? ((sg.x1 - sg.x0) / step / U) & ~1u : 0u;  // batches, even
+  // (more than two modes, or twiddle rows too long for 32-bit byte offsets:
+  // one pass at a time, unpipelined)
+  const bool pipelined = NM == 0 || (NM <= 2 && 8ull * NM * L < (1ull << 31));
+  const uint32_t nb2 = pipelined ? ((sg.x1 - sg.x0) / step / U) & ~1u : 0u;  // batches, even
   if (nb2) {
-    // the slot's twiddle rows through a buffer resource (2 modes x 2 rows of
-    // L int32 at most, below 2^31 bytes for L up to 2^27)
+    // the slot's twiddle rows through a buffer resource (at most 2 modes x 2
+    // rows of L int32, below 2^31 bytes when pipelined)
     const Rsrc twr = make_rsrc(NM > 0 ? tw : nullptr, NM > 0 ? 8u * NM * L : 0u);
     Eight<NM> E0[U], E1[U];
     // (the scheduling barrier keeps the sums of the previous batch from

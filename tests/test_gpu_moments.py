@@ -76,3 +76,32 @@ def test_moments_equal_numpy_sums(Ls, rho, u0, C):
                     assert all(v == [0, 0] for v in have["fourier"][m:]), (k, m, dig, r)
                     assert have["digest"] == (digest(c) if dig else 0), (k, m, dig, r)
     g.close()
+
+
+def test_fourier_sums_on_a_lattice_past_2_28_sites():
+    """L = 2^28 + 4097 (twiddle rows past 2^31 bytes, where the moments
+    kernel takes its unpipelined path with 64-bit row addressing): the
+    Fourier sums of one and two modes, and the plain sums, equal numpy's,
+    summed in slices of the read-back counts."""
+    import torch
+    L = (1 << 28) + 4097
+    say("large fourier", L)
+    g = Lattice(L, 67, C=0, rho=6.0, u0=0.1)
+    g.step(3)
+    c = g.counts(0)
+    tw = synth.twiddles(L, 2)
+    twd = torch.as_tensor(tw.reshape(-1)).to("cuda:0")
+    for m in (1, 2):
+        got = g.moments(twd[: 2 * m * L], m)[0]
+        f = np.zeros((m, 2), dtype=np.int64)
+        sN = 0
+        step = 1 << 24
+        for lo in range(0, L, step):
+            N = c[:, lo:lo + step].astype(np.int64).sum(0)
+            sN += int(N.sum())
+            for k in range(m):
+                f[k, 0] += int((N * tw[2 * k, lo:lo + step].astype(np.int64)).sum())
+                f[k, 1] += int((N * tw[2 * k + 1, lo:lo + step].astype(np.int64)).sum())
+        assert got["sum_N"] == sN, m
+        assert got["fourier"][:m] == f.tolist(), m
+    g.close()

@@ -57,27 +57,30 @@ def kernel_hash(paths=None) -> str:
     return h.hexdigest()[:16]
 
 
-def _counter_record(which: str):
+def _counter_record(which: str, steps_per_launch: int = 1):
     """The committed rocprofv3 counter record of this workload, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source with launches of the same number of
+    steps."""
     try:
         with open(TRAFFIC_FILES[which]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    return d if d.get("kernel_sha256_16") == kernel_hash() else None
+    if d.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return d if d.get("steps_per_launch", 1) == steps_per_launch else None
 
 
-def measured_traffic(which: str = "plain"):
-    """HBM bytes per launch from the committed counter runs, or None."""
-    d = _counter_record(which)
+def measured_traffic(which: str = "plain", steps_per_launch: int = 1):
+    """Memory-side bytes per launch from the committed counter runs, or None."""
+    d = _counter_record(which, steps_per_launch)
     return None if d is None else d.get("bytes_per_launch")
 
 
-def valu_issue_frac(which: str, seconds_per_launch: float):
+def valu_issue_frac(which: str, seconds_per_launch: float, steps_per_launch: int = 1):
     """The step launch's VALU issue time (its counted VALU wave instructions
     at the 614.4 G/s issue peak) over its measured duration, or None."""
-    d = _counter_record(which)
+    d = _counter_record(which, steps_per_launch)
     if d is None or "sq_insts_valu_per_dispatch" not in d:
         return None
     return d["sq_insts_valu_per_dispatch"] / (VALU_PEAK_G * 1e9) / seconds_per_launch
@@ -144,6 +147,10 @@ def run_plain(args, torch, M):
             "state_bytes": 6 * L,
             "state_resident_in": "infinity cache (96 MiB of 256 MB)"
             if 6 * L <= INFINITY_CACHE_BYTES else "hbm"}
+    K = args.blocked if not args.graph else 1
+    if K > 1:
+        lat.set_blocked(K)  # K steps per launch (temporal blocking)
+    info["steps_per_launch"] = max(1, K)
     lat.step(args.warmup)
     torch.cuda.synchronize()
     e0, e1 = _events(torch, stream)
@@ -165,6 +172,21 @@ def run_plain(args, torch, M):
     rc = lat.check()
     if rc != 0:
         raise SystemExit(f"device error {rc}")
+    if K > 1 and args.single_steps:
+        # the same lattice with one step per launch, for comparison
+        lat.set_blocked(1)
+        lat.step(20)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, stream)
+        e0.record(stream)
+        lat.step(args.single_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / args.single_steps
+        info["single_step_launches"] = {
+            "steps": args.single_steps, "ms_per_step": ms1,
+            "site_updates_per_s": L / (ms1 / 1e3),
+            "frac": BYTES_PER_SITE_UPDATE * L / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS}
     stats = plain_statistics(lat, args.stat_logs)
     lat.close()
     return L, gpu_ms, wall, info, stats
@@ -359,6 +381,10 @@ def run_wave(args, torch, M):
     counts = synth.density_wave_counts()
     tw = synth.twiddles(L, 1)
     lat = M.Lattice(L, w["seed"], counts=counts)
+    K = args.wave_blocked
+    if K > 1:
+        assert w["log_every"] % K == 0
+        lat.set_blocked(K)  # each logging interval in launches of K steps
     twd = torch.as_tensor(tw).to(lat.device)
     logs = w["steps"] // w["log_every"]
     words = ct.sizeof(M.mclg_moments_t) // 8
@@ -385,7 +411,7 @@ def run_wave(args, torch, M):
     ss = float(np.sum(tw[1].astype(np.float64) ** 2))
     amp = host[:, off_sin].astype(np.float64) * float(1 << 24) / ss
     return {"workload": "d1q3_L4M_wave_rho40", "steps": w["steps"], "logs": logs,
-            "gpu_ms": ms, "wall_s": wall,
+            "steps_per_launch": max(1, K), "gpu_ms": ms, "wall_s": wall,
             "site_updates_per_s_incl_logging": L * w["steps"] / (ms / 1e3),
             "amplitude_expected_initial": w["rho"] * w["amp"],
             "amplitude_first": float(amp[0]), "amplitude_last": float(amp[-1]),
@@ -546,6 +572,12 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--probe-steps", type=int, default=200)
     ap.add_argument("--stat-logs", type=int, default=10)
+    ap.add_argument("--blocked", type=int, default=256,
+                    help="steps per launch of the L = 2^24 workload (temporal blocking; 1: off)")
+    ap.add_argument("--single-steps", type=int, default=2000,
+                    help="steps of the one-step-per-launch comparison of the blocked run")
+    ap.add_argument("--wave-blocked", type=int, default=10,
+                    help="steps per launch of the density wave (its logging interval; 1: off)")
     ap.add_argument("--serve-window", type=float, default=10.0)
     ap.add_argument("--serve-limit", type=float, default=120.0)
     ap.add_argument("--d2q9-steps", type=int, default=50)
@@ -607,9 +639,15 @@ def main():
         "config": {"workload": "d1q3_L16M_rho50_u0.1", "L": L, "rho": 50.0, "u0": 0.1, "C": 10,
                    "lambda": 1, "n_max": 255, "seed": 2, "launch": "graph" if args.graph else "plain",
                    "schedule": args.schedule or "default", **info},
+        # the dominant kernel's launches: K steps each (12 B per site update
+        # algorithmic, K L site updates per launch); traffic per launch
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("plain"),
-                     "valu_issue_frac": valu_issue_frac("plain", ms_per_step / 1e3)},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "steps_per_launch": info["steps_per_launch"],
+                     "traffic": measured_traffic("plain", info["steps_per_launch"]),
+                     "valu_issue_frac": valu_issue_frac(
+                         "plain", ms_per_step * info["steps_per_launch"] / 1e3,
+                         info["steps_per_launch"])},
         "statistics": stats,
     }
     if args.only == "plain":

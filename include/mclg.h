@@ -303,6 +303,27 @@ int mclg_set_grid_limit(mclg_ctx *ctx, uint32_t max_blocks);
 enum { MCLG_DRAIN_AUTO = 0, MCLG_DRAIN_DEFERRED = 1, MCLG_DRAIN_CHUNK = 2, MCLG_DRAIN_PATCH = 3 };
 int mclg_set_drain(mclg_ctx *ctx, uint32_t policy);
 
+/* Several steps per launch (temporal blocking) for a context of one lattice
+ * (Sec. "The D1Q3 model": the update of a site at t + 1 reads only its
+ * neighbours at t, so a block that holds its sites and `steps` more on each
+ * side can advance them `steps` steps alone).  mclg_step then launches
+ * whole groups of `steps` steps, each group as one launch: every block copies
+ * its range of the state and the extra sites into its part of `scratch`,
+ * waits for all blocks (a grid-wide barrier), advances its copy, and writes
+ * its own sites back; the rest of a mclg_step call takes single steps.  The
+ * bits are the same as with one step per launch.
+ *   mclg_blocked_bytes: the scratch bytes `steps` steps per launch need.
+ *   mclg_set_blocked: steps in [2, 256] with scratch (device, caller-owned,
+ *     at least mclg_blocked_bytes, kept until blocking is switched off or the
+ *     context destroyed); steps <= 1 switches it off (scratch unused).
+ * MCLG_E_UNSUPPORTED for D2Q9 or more than one replica, L not a multiple of
+ * 8, a schedule other than 1024 threads, or a lattice too short for the
+ * extra sites of 256 or so blocks; MCLG_E_INVAL for steps > 256 or too small a
+ * scratch.  mclg_set_schedule switches blocking off.  Graph launches
+ * (mclg_step_graph) take one step per launch. */
+int mclg_blocked_bytes(mclg_ctx *ctx, uint32_t steps, uint64_t *scratch_bytes);
+int mclg_set_blocked(mclg_ctx *ctx, uint32_t steps, void *scratch, uint64_t scratch_bytes);
+
 /* Expected fraction of site updates whose draw is decided from LDS (from the
  * product-Poisson law the images were built for) and the LDS bytes per block. */
 int mclg_lds_coverage(const mclg_ctx *ctx, double *expected_fraction, uint32_t *lds_bytes);

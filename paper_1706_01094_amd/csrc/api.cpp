@@ -142,6 +142,10 @@ struct mclg_ctx {
   std::vector<uint8_t> img_pool;
   uint32_t lds_bytes = 0, max_blocks = 1, lds_limit = 64 * 1024, n_cu = 1;
   uint32_t grid_limit = 0;  // 0: occupancy-derived grid
+  // several steps per launch (mclg_set_blocked): geometry, grid, caller's
+  // scratch; tb.steps <= 1 means one step per launch
+  TbLaunch tb;
+  uint32_t tb_grid = 0;
   uint32_t drain_policy = MCLG_DRAIN_AUTO;
   // the device address of this device's static scratch area (moments.hip),
   // looked up in mclg_init with the context's device current
@@ -510,9 +514,80 @@ static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t 
   return c->hip(e);
 }
 
+// The geometry of `steps` steps per launch for the context's one lattice:
+// every block of the grid resident at once, R owned sites per block (a
+// multiple of 8), kh = steps rounded up to 8 extra sites on each side.
+static int blocked_geometry(mclg_ctx *c, uint32_t steps, TbLaunch &tb, uint32_t &grid,
+                            uint64_t &bytes) {
+  if (c->d2) return MCLG_E_UNSUPPORTED;
+  if (steps < 2 || steps > kTbMaxSteps) return MCLG_E_INVAL;
+  if (c->n != 1 || c->L[0] % 8 != 0 || c->sch.threads != 1024) return MCLG_E_UNSUPPORTED;
+  uint32_t g = 0;
+  hipError_t e = step_blocked_occupancy(c->sch, c->lds_bytes, c->n_cu, g);
+  if (e) return c->hip(e);
+  g = std::min(g, kOverflowWaves / (c->sch.threads / 64u));  // waves with an overflow area
+  const uint64_t L = c->L[0];
+  TbLaunch t;
+  t.R = (uint32_t)(((L + g - 1) / g + 7) / 8 * 8);
+  t.kh = (steps + 7u) / 8u * 8u;
+  t.es = t.R + 2u * t.kh;
+  t.stride = (t.es + 63u) / 64u * 64u;
+  t.steps = steps;
+  // the copy's random-number keys wrap around the lattice at most once
+  if ((uint64_t)t.es + 512u > L) return MCLG_E_UNSUPPORTED;
+  tb = t;
+  grid = g;
+  bytes = (uint64_t)g * 3u * t.stride * sizeof(uint16_t);
+  return MCLG_OK;
+}
+
+int mclg_blocked_bytes(mclg_ctx *c, uint32_t steps, uint64_t *scratch_bytes) {
+  if (!c || !scratch_bytes) return MCLG_E_INVAL;
+  TbLaunch tb;
+  uint32_t grid = 0;
+  return blocked_geometry(c, steps, tb, grid, *scratch_bytes);
+}
+
+int mclg_set_blocked(mclg_ctx *c, uint32_t steps, void *scratch, uint64_t scratch_bytes) {
+  if (!c) return MCLG_E_INVAL;
+  if (c->d2) return MCLG_E_UNSUPPORTED;
+  if (steps <= 1) {
+    c->tb = TbLaunch{};
+    c->tb_grid = 0;
+    return MCLG_OK;
+  }
+  TbLaunch tb;
+  uint32_t grid = 0;
+  uint64_t need = 0;
+  int rc = blocked_geometry(c, steps, tb, grid, need);
+  if (rc) return rc;
+  if (!scratch || scratch_bytes < need) return MCLG_E_INVAL;
+  tb.scratch = static_cast<uint16_t *>(scratch);
+  c->tb = tb;
+  c->tb_grid = grid;
+  return MCLG_OK;
+}
+
 int mclg_step(mclg_ctx *c, uint64_t n_steps) {
   if (!c) return MCLG_E_INVAL;
   if (c->d2) return d2q9_step(*c->d2, n_steps);
+  // whole blocks of tb.steps steps first
+  const uint32_t K = c->tb.steps;
+  if (K > 1) {
+    for (; n_steps >= K; n_steps -= K) {
+      if (c->t_pending >= (1u << 30)) {
+        hipError_t e = c->flush_t();
+        if (e) return c->hip(e);
+      }
+      hipError_t e = launch_step_blocked(c->sch, c->stream,
+                                         c->launch_args(0, (uint32_t)c->tiles.size(), 0, 1,
+                                                        c->t_pending),
+                                         c->tb, c->tb_grid);
+      if (e) return c->hip(e);
+      c->t_pending += K;
+      c->t[0] += K;
+    }
+  }
   for (uint64_t i = 0; i < n_steps; ++i) {
     if (c->t_pending >= (1u << 30)) {
       hipError_t e = c->flush_t();
@@ -671,6 +746,8 @@ int mclg_set_schedule(mclg_ctx *c, uint32_t groups, uint32_t threads, uint32_t l
   c->sch.groups = groups;
   c->sch.threads = threads;
   c->sch.lds_budget = lds_budget;
+  c->tb = TbLaunch{};  // its geometry depends on the schedule: set it again
+  c->tb_grid = 0;
   // graphs still in flight on the stream use the old tiles and images
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e) return c->hip(e);

@@ -148,6 +148,31 @@ struct StepLaunch {
 
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 
+// Several steps of one lattice per launch (temporal blocking).  Block b owns
+// the sites [b R, b R + R) and keeps a copy of them and of kh more sites on
+// each side (es = R + 2 kh sites) in its own part of `scratch`, a periodic
+// lattice of es sites in the shifted layout.  It copies the region in at
+// step t, and after a grid-wide barrier (every block has read the state)
+// advances its copy `steps` steps (steps <= kh): the sites within j of the
+// copy's ends are wrong after j steps, the owned sites stay exact, and the
+// random numbers are keyed by each site's place in the lattice.  It then
+// writes its owned sites back at step t + steps.
+constexpr uint32_t kTbMaxSteps = 256;
+struct TbLaunch {
+  uint16_t *scratch = nullptr;  // grid x 3 x stride elements
+  uint32_t stride = 0;          // elements per array of a block's copy (>= es)
+  uint32_t R = 0;               // owned sites per block (a multiple of 8)
+  uint32_t kh = 0;              // extra sites on each side (a multiple of 8)
+  uint32_t es = 0;              // R + 2 kh
+  uint32_t steps = 0;           // steps of the launch
+};
+hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
+                               const TbLaunch &tb, uint32_t grid);
+// Blocks of the blocked kernel that fit the device at once (the grid it
+// needs: every block must be resident for the barrier).
+hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,
+                                  uint32_t &max_blocks);
+
 // Largest lattice (sites per replica or job): the step kernel addresses a
 // slot's three arrays (6 bytes per site, 256-byte padded) with 32-bit byte
 // offsets.

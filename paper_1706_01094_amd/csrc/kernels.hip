@@ -12,6 +12,8 @@
 #include "device.h"
 #include "rng.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 
 namespace mclg {
@@ -285,6 +287,17 @@ struct SlotView {
   uint32_t lo, hi;  // address of the slot's n_-1 array; n_0 and n_+1 follow
   uint32_t ab;      // bytes per array
   uint32_t L, tm, t, rid;
+  // Site x of the view is site (x + xoff) mod lg of the lattice, which keys
+  // its random numbers: xoff = 0 and lg = L for a slot itself, the region's
+  // first site and the lattice's size for a block's copy of a region (a
+  // multiple of 8 each, so that a lane's eight sites never wrap).
+  uint32_t xoff, lg;
+  template <bool TB>
+  __device__ __forceinline__ uint32_t logical(uint32_t x) const {
+    if constexpr (!TB) return x;
+    const uint32_t y = x + xoff;
+    return y >= lg ? y - lg : y;
+  }
   // the buffer resource, rebuilt at each use from wave-uniform scalars
   __device__ __forceinline__ Rsrc rs() const {
     return __builtin_amdgcn_make_buffer_rsrc(
@@ -486,7 +499,7 @@ __device__ __forceinline__ void queue_saturated(const uint32_t (&va)[4], const u
 // earlier memory operations have completed -- among them the stores that
 // wrote the pre-collision counts of these sites -- so the final counts land
 // after them.
-template <bool GAL>
+template <bool GAL, bool TB = false>
 __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *over, uint32_t F,
                                             uint32_t lane, const SlotView &v,
                                             const StepParams &p, const TableDev &tab,
@@ -498,7 +511,8 @@ __device__ __forceinline__ void drain_queue(const uint4 *queue, const uint4 *ove
   for (uint32_t i = lane; i < F; i += 64u) {
     const uint4 e = i < kQueue ? queue[i] : over[i - kQueue];
     const uint32_t x = e.x, ea = e.y & 0xffffu, eb = e.y >> 16, ec = e.z;
-    const uint32_t bn = resolve_queued<GAL>(e, p, tab, v.t, v.rid, err);
+    const uint32_t bn =
+        resolve_queued<GAL>(make_uint4(v.logical<TB>(x), e.y, e.z, e.w), p, tab, v.t, v.rid, err);
     const int32_t N = (int32_t)(ea + eb + ec), J = (int32_t)ec - (int32_t)ea;
     uint32_t pm = x + v.tm;
     pm -= (pm >= v.L) ? v.L : 0u;
@@ -533,7 +547,7 @@ __device__ __forceinline__ uint32_t image_move(uint32_t a, uint32_t b, uint32_t 
 // 1 KB holds the chunk's 512 patches once its entries have been read.  Every
 // lane then adds its eight patches to its counts (zero for decided sites), so
 // the chunk's vector stores write the final counts.
-template <bool GAL>
+template <bool GAL, bool TB = false>
 __device__ __forceinline__ void patch_chunk(uint4 *queue, const uint4 *over, uint32_t F,
                                             uint32_t lane, uint32_t xs, const SlotView &v,
                                             const LdsView &lv, const StepParams &p,
@@ -560,7 +574,7 @@ __device__ __forceinline__ void patch_chunk(uint4 *queue, const uint4 *over, uin
     const uint32_t pos = e.x, b = e.y >> 16;
     // C = 0 queues only overflowing sites and applies no move
     const uint32_t dw = p.C != 0 ? image_move(e.y & 0xffffu, b, e.z, e.w, lv) : 0u;
-    e.x = xs + pos;
+    e.x = v.logical<TB>(xs + pos);
     const uint32_t bn = resolve_queued<GAL>(e, p, tab, v.t, v.rid, err);
     const uint32_t d = (uint32_t)(((int32_t)b - (int32_t)bn) >> 1);
     patch[pos] = (uint16_t)(d - dw);
@@ -646,6 +660,104 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// The chunks [k0, se) of one segment of a slot (chunk j at x0 + (j - i)
+// 512): the wave's first chunk k (its loads already issued into cr when
+// fast), then chunks claimed one at a time from the block's counter.  One
+// chunk: the next chunk's loads go out first (into the other register set;
+// its bytes are disjoint from this chunk's), then this chunk is decided and
+// stored, then the next chunk's vectors are taken.  The loop alternates the
+// two register sets, so nothing is copied.
+template <bool GAL, int MODE, bool TB = false>
+__device__ __forceinline__ void run_segment(const StepParams &p, const TableDev &tab,
+                                            uint32_t *err, const SlotView &sv,
+                                            const LdsView &lv, uint2 key, uint4 *queue,
+                                            uint4 *over, Rsrc ovr, uint32_t &F, uint32_t lane,
+                                            uint32_t nwaves, bool youngest, bool second,
+                                            uint32_t &next_chunk, uint32_t i, uint32_t se,
+                                            uint32_t x0, uint32_t k, Win cw, Raw &cr) {
+  constexpr bool PATCH = MODE == kDrainPatch;
+  constexpr int CP = PATCH ? kStreamingPolicy : 0;
+  const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
+  const Rsrc rs = sv.rs();
+  const uint32_t ab = sv.ab;
+  auto one = [&](Raw &cur, Raw &nxt) -> bool {
+    // (young waves leave the segment's last chunks to the older ones)
+    uint32_t nk = se;
+    if (!(youngest || second) ||
+        __builtin_amdgcn_readfirstlane(__atomic_load_n(&next_chunk, __ATOMIC_RELAXED)) +
+                (youngest ? nwaves : nwaves / 2u) < se)
+      nk = grab_chunk(&next_chunk, lane);
+    nk = __builtin_amdgcn_readfirstlane(nk);  // wave-uniform after the join
+    const bool has_next = nk < se;
+    Win nw = cw;
+    if (has_next) {
+      nw = locate(x0 + (nk - i) * 512u, sv);
+      if (nw.fast) issue_raw<CP>(nw, sv, lane, nxt);
+    }
+
+    // ---- collide: LDS image first, the rest into the wave's queue ----
+    {
+      const uint32_t x8 = cw.xs + 8u * lane;
+      const bool slow = __builtin_amdgcn_readfirstlane(cw.fast) == 0u;
+      if (p.C != 0) {
+        const uint32_t xl = sv.logical<TB>(x8);  // the lattice site keying the draws
+        uint4 w0 = make_uint4(xl >> 2, t, sv.rid, 0u);
+        uint4 w1 = make_uint4((xl >> 2) + 1u, t, sv.rid, 0u);
+        decide_eight<PATCH>(w0, w1, key, cur.m, cur.z, cur.p, lv, queue, ovr, F, slow, x8, L,
+                            cw.xs);
+      } else {
+        queue_saturated<PATCH>(cur.m, cur.z, cur.p, queue, ovr, F, slow, x8, L, cw.xs);
+      }
+      if constexpr (PATCH) {
+        if (F) {
+          patch_chunk<GAL, TB>(queue, over, F, lane, cw.xs, sv, lv, p, tab, err, cur.m,
+                           cur.z, cur.p);
+          F = 0;
+        }
+      }
+    }
+
+    // ---- store ----
+    if (cw.fast) {
+      const uint32_t vo = 16u * lane;
+      bstore4<CP>(rs, vo, 2u * cw.sm, cur.m);
+      bstore4<CP>(rs, vo, ab + 2u * cw.xs, cur.z);
+      bstore4<CP>(rs, vo, 2u * ab + 2u * cw.sp, cur.p);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t x = cw.xs + 8u * lane + e;
+        if (x < L) {
+          uint32_t pm = x + tm;
+          pm -= (pm >= L) ? L : 0u;
+          const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+          bstore2(rs, 2u * pm, 0u, get16(cur.m, e));
+          bstore2(rs, 2u * x, ab, get16(cur.z, e));
+          bstore2(rs, 2u * pp, 2u * ab, get16(cur.p, e));
+        }
+      }
+    }
+    // ---- the next chunk's windows ----
+    if (has_next) chunk_fill(nw, nxt, sv, lane);
+    cw = nw;
+    k = nk;
+    // At most kDrainAt draws stay queued, so the next chunk's 64 x 8
+    // always fit; kDrainChunk resolves every chunk's draws while its lines
+    // are still in the L2 (kDrainPatch has none left here).
+    if (!PATCH && has_next && F > (MODE == kDrainChunk ? 0u : kDrainAt)) {
+      drain_queue<GAL, TB>(queue, over, F, lane, sv, p, tab, err);
+      F = 0;
+    }
+    return has_next;
+  };
+  if (k < se) {
+    Raw rb;
+    chunk_fill(cw, cr, sv, lane);
+    while (one(cr, rb) && one(rb, cr)) {
+    }
+  }
+}
+
 // Fused stream + collide.  Persistent blocks: block i takes a contiguous
 // range of chunks; the slot's collision image is loaded into LDS for each
 // run of one slot's chunks (a segment), whose chunks the block's waves then
@@ -694,6 +806,8 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
   sv.lo = sv.hi = 0;
   sv.ab = 0;
   sv.L = 1; sv.tm = sv.t = sv.rid = 0;
+  sv.xoff = 0;
+  sv.lg = 1;
   LdsView lv;
   lv.da2 = lv.dc2 = lv.w2 = lv.blo2 = lv.nb2 = 0;
 
@@ -739,6 +853,7 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
     sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
     sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
     sv.ab = __builtin_amdgcn_readfirstlane(2u * sl.stride);
+    sv.lg = sv.L;
     uint32_t k = min(i + wave, se);
     if (threadIdx.x == 0) next_chunk = i + nwaves;
     Win cw = locate(t0.x0 + (k - i) * 512u, sv);
@@ -870,6 +985,162 @@ __global__ void __launch_bounds__(MAXT) k_step(StepLaunch a) {
       a.tslot[s] += 1u;
     }
     if (threadIdx.x == 0) atomicExch(a.ticket, 0u);
+  }
+}
+
+// Eight consecutive elements pos .. pos + 7 (mod n) of the array at byte
+// offset `arr` of r: one 16-byte access unless they wrap around n.
+__device__ __forceinline__ void load8_wrap(Rsrc r, uint32_t arr, uint32_t pos, uint32_t n,
+                                           uint32_t (&v)[4]) {
+  if (pos + 8u <= n) {
+    bload4(r, 2u * pos, arr, v);
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint32_t q = pos + (uint32_t)e;
+    q -= q >= n ? n : 0u;
+    set16(v, e, bload2(r, 2u * q, arr));
+  }
+}
+__device__ __forceinline__ void store8_wrap(Rsrc r, uint32_t arr, uint32_t pos, uint32_t n,
+                                            const uint32_t (&v)[4]) {
+  if (pos + 8u <= n) {
+    bstore4(r, 2u * pos, arr, v);
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    uint32_t q = pos + (uint32_t)e;
+    q -= q >= n ? n : 0u;
+    bstore2(r, 2u * q, arr, get16(v, e));
+  }
+}
+
+// Several steps of one lattice per launch (see TbLaunch).  Deferred drains:
+// the block's copy stays in the caches, and each step ends with the drain of
+// every wave's queue and a block barrier, so step s + 1 reads what step s
+// wrote.
+template <int MAXT, bool GAL>
+__global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
+  constexpr int MODE = kDrainDeferred;
+  extern __shared__ uint4 lds[];
+  const StepParams &p = a.p;
+  const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
+  const uint32_t lane = threadIdx.x & 63u, nwaves = blockDim.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
+  uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
+  const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
+  uint32_t F = 0;
+  const bool youngest = nwaves >= 8u && wave + 4u >= nwaves;
+  const bool second = nwaves >= 12u && wave + 8u >= nwaves && !youngest;
+  uint32_t *const ctl =
+      reinterpret_cast<uint32_t *>(lds + a.lds_bytes / 16u + nwaves * (kWaveLdsBytes / 16u));
+  uint32_t &next_chunk = ctl[0];
+
+  // the lattice: one slot, its descriptors carried by value
+  const SlotDev sl = a.sl1;
+  const ImageDesc im = a.im1;
+  const uint32_t L = sl.L;
+  const uint32_t t0 = __builtin_amdgcn_readfirstlane(a.tslot[a.slot_first] + a.t_off);
+  const uint32_t X0 = blockIdx.x * tb.R;  // first owned site
+  const bool active = X0 < L;
+  const uint32_t xoff = X0 >= tb.kh ? X0 - tb.kh : X0 + L - tb.kh;  // site of copy index 0
+  uint16_t *const main_m = a.state + sl.off;
+  uint16_t *const scr = tb.scratch + (uint64_t)blockIdx.x * 3ull * tb.stride;
+  const uint32_t es = tb.es;
+
+  // (1) the region and its extra sites at step t0, in logical order, eight
+  // sites per thread (the region's first site, L and es are multiples of 8)
+  const uint32_t mab = 2u * sl.stride, sab = 2u * tb.stride;
+  const Rsrc mrs = __builtin_amdgcn_make_buffer_rsrc(main_m, 0, (int)(3u * mab), kRsrcWord3);
+  const Rsrc srs = __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(3u * sab), kRsrcWord3);
+  if (active) {
+    const uint32_t tm = p.no_stream ? 0u : t0 % L;
+    for (uint32_t i = 8u * threadIdx.x; i < es; i += 8u * blockDim.x) {
+      uint32_t x = xoff + i;
+      x -= x >= L ? L : 0u;
+      uint32_t pm = x + tm;
+      pm -= pm >= L ? L : 0u;
+      const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+      uint32_t m[4], z[4], q[4];
+      load8_wrap(mrs, 0u, pm, L, m);
+      load8_wrap(mrs, mab, x, L, z);
+      load8_wrap(mrs, 2u * mab, pp, L, q);
+      bstore4(srs, 2u * i, 0u, m);
+      bstore4(srs, 2u * i, sab, z);
+      bstore4(srs, 2u * i, 2u * sab, q);
+    }
+  }
+  // the collision image, once for all steps
+  LdsView lv;
+  {
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
+    const uint32_t n16 = im.bytes / 16u, bd = blockDim.x;
+    for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += bd) lds[b0] = src[b0];
+    lv.da2 = im.dim_a * 0x10001u;
+    lv.dc2 = im.dim_c * 0x10001u;
+    lv.w2 = (im.dim_c + 1u) * 0x10001u;
+    lv.blo2 = im.b_lo * 0x10001u;
+    lv.nb2 = im.nb * 0x10001u;
+  }
+  // (2) every block has read the state before any writes it
+  cooperative_groups::this_grid().sync();
+
+  // (3) the steps on the block's copy: a periodic lattice of es sites
+  SlotView sv;
+  const uint64_t base = reinterpret_cast<uint64_t>(scr);
+  sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  sv.ab = 2u * tb.stride;
+  sv.L = es;
+  sv.rid = sl.rid;
+  sv.xoff = xoff;
+  sv.lg = L;
+  const uint32_t nch = (es + 511u) / 512u;
+  for (uint32_t s = 0; s < tb.steps; ++s) {
+    sv.t = t0 + s;
+    sv.tm = p.no_stream ? 0u : s % es;
+    const uint32_t k = min(wave, nch);
+    if (threadIdx.x == 0) next_chunk = nwaves;
+    const Win cw = locate(k * 512u, sv);
+    Raw cr;
+    if (active && k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
+    __syncthreads();  // the counter is reset
+    if (active) {
+      run_segment<GAL, MODE, true>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+      if (F) {
+        drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
+        F = 0;
+      }
+    }
+    __syncthreads();  // step s is written before step s + 1 reads it
+  }
+
+  // (4) the owned sites back into the state at step t0 + steps, eight per
+  // thread
+  if (active) {
+    const uint32_t tms = p.no_stream ? 0u : tb.steps % es;
+    const uint32_t tmk = p.no_stream ? 0u : (uint32_t)(((uint64_t)t0 + tb.steps) % L);
+    const uint32_t x1 = min(L - X0, tb.R);
+    for (uint32_t j = 8u * threadIdx.x; j < x1; j += 8u * blockDim.x) {
+      const uint32_t i = tb.kh + j, x = X0 + j;
+      uint32_t im_ = i + tms;
+      im_ -= im_ >= es ? es : 0u;
+      const uint32_t ip = i >= tms ? i - tms : i + es - tms;
+      uint32_t pm = x + tmk;
+      pm -= pm >= L ? L : 0u;
+      const uint32_t pp = x >= tmk ? x - tmk : x + L - tmk;
+      uint32_t m[4], z[4], q[4];
+      load8_wrap(srs, 0u, im_, es, m);
+      bload4(srs, 2u * i, sab, z);
+      load8_wrap(srs, 2u * sab, ip, es, q);
+      store8_wrap(mrs, 0u, pm, L, m);
+      bstore4(mrs, 2u * x, mab, z);
+      store8_wrap(mrs, 2u * mab, pp, L, q);
+    }
   }
 }
 
@@ -1021,6 +1292,44 @@ static void launch_mode(dim3 grid, dim3 block, uint32_t lds, hipStream_t s, cons
     case kDrainPatch: k_step<MAXT, GAL, kDrainPatch><<<grid, block, lds, s>>>(a); break;
     default: k_step<MAXT, GAL, kDrainDeferred><<<grid, block, lds, s>>>(a); break;
   }
+}
+
+template <bool GAL>
+static hipError_t blocked_occupancy_one(uint32_t lds, int &blocks) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step_tb<1024, GAL>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  int b = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step_tb<1024, GAL>, 1024, lds);
+  blocks = std::min(blocks, b);
+  return e;
+}
+
+hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint32_t n_cu,
+                                  uint32_t &max_blocks) {
+  if (sch.groups != 1 || sch.threads != 1024) return hipErrorInvalidValue;
+  const uint32_t lds = step_lds_bytes(sch, lds_bytes);
+  int b = 1 << 30;
+  hipError_t e = blocked_occupancy_one<false>(lds, b);
+  if (!e) e = blocked_occupancy_one<true>(lds, b);
+  if (e) return e;
+  if (b < 1) return hipErrorInvalidConfiguration;
+  max_blocks = (uint32_t)b * n_cu;
+  return hipSuccess;
+}
+
+hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
+                               const TbLaunch &tb, uint32_t grid) {
+  if (sch.groups != 1 || sch.threads != 1024 || !a.single || tb.steps == 0 ||
+      tb.steps > tb.kh || tb.es != tb.R + 2u * tb.kh || tb.stride < tb.es)
+    return hipErrorInvalidValue;
+  const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
+  StepLaunch av = a;
+  TbLaunch tv = tb;
+  void *args[] = {&av, &tv};
+  const void *f = a.p.galilean ? reinterpret_cast<const void *>(k_step_tb<1024, true>)
+                               : reinterpret_cast<const void *>(k_step_tb<1024, false>);
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(1024), args, lds, s);
 }
 
 hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a) {

@@ -35,8 +35,9 @@ def test_traffic_record_follows_from_its_counters(which):
     want = 1024 * (d["fetch_size_kib_per_dispatch"] * cal["fetch_factor"] +
                    d["write_size_kib_per_dispatch"] * cal["write_factor"])
     assert d["bytes_per_launch"] == pytest.approx(want, rel=1e-9)
-    # 12 bytes per site update
-    assert d["algorithmic_bytes_per_launch"] == bench.BYTES_PER_SITE_UPDATE * TRAFFIC_SITES[which]
+    # 12 bytes per site update, every site once per step of the launch
+    assert d["algorithmic_bytes_per_launch"] == (bench.BYTES_PER_SITE_UPDATE * TRAFFIC_SITES[which]
+                                                 * d.get("steps_per_launch", 1))
     assert d["ratio_to_algorithmic"] == pytest.approx(d["bytes_per_launch"] /
                                                       d["algorithmic_bytes_per_launch"])
     assert len(d["kernel_sha256_16"]) == 16
@@ -68,9 +69,11 @@ def test_valu_issue_fraction_from_the_record(which):
     # 256 persistent blocks of 16 waves
     assert d["sq_waves_per_dispatch"] == 4096
     assert d["sq_insts_valu_per_dispatch"] > 0
+    K = d.get("steps_per_launch", 1)
     if d["kernel_sha256_16"] == bench.kernel_hash():
         t = 1e-3
-        assert bench.valu_issue_frac(which, t) == pytest.approx(
+        assert bench.valu_issue_frac(which, t, K) == pytest.approx(
             d["sq_insts_valu_per_dispatch"] / (bench.VALU_PEAK_G * 1e9) / t)
+        assert bench.valu_issue_frac(which, t, K + 1) is None
     else:
-        assert bench.valu_issue_frac(which, 1e-3) is None
+        assert bench.valu_issue_frac(which, 1e-3, K) is None

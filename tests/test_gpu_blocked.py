@@ -1,0 +1,166 @@
+"""Several steps per launch (temporal blocking, mclg_set_blocked): every
+count equals the oracle's, and the state equals the one-step-per-launch
+state, for group sizes from 2 to 256, calls that are not multiples of the
+group, the flags and collision parameters, and the full-size workloads."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_1706_01094_amd.mclg import FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError
+from tests.state_digest import digest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(L, seed, K, C=10, lam=(1, 1), n_max=255, rho=20.0, u0=0.1, flags=0):
+    say("case", dict(L=L, seed=seed, K=K, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags))
+    g = Lattice(L, seed, C=C, lam=lam, n_max=n_max, rho=rho, u0=u0, flags=flags)
+    g.set_blocked(K)
+    o = O.OracleSim([L], seed, C=C, lam=lam, n_max=n_max, flags=flags)
+    o.init_poisson(0, rho, u0)
+    return g, o
+
+
+def same(g, o, what):
+    a, b = g.counts(0), o.counts(0)
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{what}: {len(bad)} counts differ, first {bad[:5].tolist()}")
+
+
+@pytest.mark.parametrize("L,K", [(1 << 17, 2), (1 << 17, 8), (3 * (1 << 16) + 8 * 37, 5),
+                                 (1 << 18, 16), (1 << 20, 64), (1 << 20, 256)])
+def test_blocked_equals_oracle(L, K):
+    g, o = pair(L, 71, K)
+    t = 0
+    for n in (K, 2 * K + 3, 1, K - 1 if K > 1 else 1, 3 * K):
+        g.step(n)
+        o.step(n)
+        t += n
+        same(g, o, f"L={L} K={K} t={t}")
+    g.close()
+
+
+@pytest.mark.parametrize("C,lam,n_max,flags", [
+    (0, (1, 1), 255, 0),
+    (3, (1, 2), 255, 0),
+    (-1, (1, 1), 255, 0),
+    (10, (1, 1), 24, 0),
+    (10, (1, 1), 255, FLAG_NO_STREAM),
+    (10, (3, 4), 255, FLAG_GALILEAN),
+    (10, (1, 1), 16, FLAG_GALILEAN),
+])
+def test_blocked_flags_and_parameters(C, lam, n_max, flags):
+    """The literal loop for N > n_max (n_max = 24 and 16: its random numbers
+    are keyed by the lattice site, not the site of the block's copy), C = 0,
+    C = infinity, no streaming and the Galilean acceptance, 8 steps per
+    launch."""
+    L = 1 << 17
+    g, o = pair(L, 73, 8, C=C, lam=lam, n_max=n_max, rho=30.0, u0=0.15, flags=flags)
+    for n in (8, 11, 16):
+        g.step(n)
+        o.step(n)
+        same(g, o, f"C={C} n_max={n_max} flags={flags}")
+    g.close()
+
+
+def test_blocked_equals_single_steps_full_size():
+    """L = 2^24 (the benchmark's workload): 10 steps per launch give the same
+    state as one step per launch after 100 and 205 steps."""
+    w = synth.PLAIN_LARGE
+    L = w["L"]
+    a = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    b = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    b.set_blocked(10)
+    for n in (100, 105):
+        a.step(n)
+        b.step(n)
+        ma, mb = a.moments(digest=True)[0], b.moments(digest=True)[0]
+        assert ma == mb
+    assert digest(a.counts(0)) == digest(b.counts(0))
+    a.close()
+    b.close()
+
+
+def test_blocked_density_wave_windows():
+    """The L = 2^22 density wave, 10 steps per launch: oracle light-cone
+    windows after 500 steps."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = synth.DENSITY_WAVE
+    L = w["L"]
+    counts = synth.density_wave_counts()
+    g = Lattice(L, w["seed"], counts=counts)
+    g.set_blocked(10)
+    T, W = 500, 512
+
+    def window(x0):
+        lo = x0 - T
+        o = O.OracleSim([W + 2 * T], w["seed"], C=10)
+        o.set_site_offset(0, lo, 0)
+        o.init_counts(0, counts[:, lo:lo + W + 2 * T])
+        o.step(T)
+        out = o.counts(0)[:, T:T + W]
+        o.close()
+        return out
+
+    x0s = [T, L // 3, L - W - T]
+    with ThreadPoolExecutor(3) as ex:
+        futs = [(x0, ex.submit(window, x0)) for x0 in x0s]
+        g.step(T)
+        full = g.counts(0)
+        for x0, f in futs:
+            assert np.array_equal(full[:, x0:x0 + W], f.result()), x0
+    g.close()
+
+
+def test_blocked_refused_where_it_does_not_apply():
+    g = Lattice([4096, 4096], 3, rho=5.0, u0=0.0)
+    with pytest.raises(MclgError):
+        g.set_blocked(4)  # more than one replica
+    g.close()
+    g = Lattice(1 << 17, 3, rho=5.0, u0=0.0)
+    with pytest.raises(MclgError):
+        g.set_blocked(257)  # more than 256 steps
+    g.set_blocked(1)  # off
+    g.step(3)
+    g.close()
+
+
+def test_blocked_full_size_256_steps_per_launch_windows():
+    """The benchmark's launch shape, L = 2^24 with 256 steps per launch: oracle
+    light-cone windows after 528 steps (two launches and 16 single steps)."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = synth.PLAIN_LARGE
+    L = w["L"]
+    g = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    g.set_blocked(256)
+    T, W = 528, 256
+
+    def window(x0):
+        lo = x0 - T
+        o = O.OracleSim([W + 2 * T], w["seed"], C=10)
+        o.set_site_offset(0, lo, 0)
+        o.init_poisson(0, w["rho"], w["u0"])
+        o.step(T)
+        out = o.counts(0)[:, T:T + W]
+        o.close()
+        return out
+
+    # the first block's extra sites wrap around the lattice's start; others
+    # sit at block boundaries (65536 sites per block) and in the middle
+    x0s = [T, 65536 - W // 2, L // 2 + 12345, L - W - T]
+    with ThreadPoolExecutor(4) as ex:
+        futs = [(x0, ex.submit(window, x0)) for x0 in x0s]
+        g.step(T)
+        full = g.counts(0)
+        for x0, f in futs:
+            assert np.array_equal(full[:, x0:x0 + W], f.result()), x0
+    g.close()

@@ -584,8 +584,7 @@ int mclg_step(mclg_ctx *c, uint64_t n_steps) {
                                                         c->t_pending),
                                          c->tb, c->tb_grid);
       if (e) return c->hip(e);
-      c->t_pending += K;
-      c->t[0] += K;
+      c->t[0] += K;  // (the launch advances the device counter itself)
     }
   }
   for (uint64_t i = 0; i < n_steps; ++i) {

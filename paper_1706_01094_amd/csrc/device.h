@@ -156,7 +156,8 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // advances its copy `steps` steps (steps <= kh): the sites within j of the
 // copy's ends are wrong after j steps, the owned sites stay exact, and the
 // random numbers are keyed by each site's place in the lattice.  It then
-// writes its owned sites back at step t + steps.
+// writes its owned sites back at step t + steps.  Block 0 advances the
+// slot's step counter by `steps` once every block has read it.
 constexpr uint32_t kTbMaxSteps = 256;
 struct TbLaunch {
   uint16_t *scratch = nullptr;  // grid x 3 x stride elements

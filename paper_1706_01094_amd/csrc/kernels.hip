@@ -1085,8 +1085,10 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
     lv.blo2 = im.b_lo * 0x10001u;
     lv.nb2 = im.nb * 0x10001u;
   }
-  // (2) every block has read the state before any writes it
+  // (2) every block has read the state (and its step counter) before any
+  // writes it; the launch advances the counter itself
   cooperative_groups::this_grid().sync();
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.tslot[a.slot_first] += tb.steps;
 
   // (3) the steps on the block's copy: a periodic lattice of es sites
   SlotView sv;

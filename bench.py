@@ -370,9 +370,9 @@ def run_batched(args, torch, M):
 
 def run_wave(args, torch, M):
     """Decaying density wave, L = 2^22, 5000 steps, the int64 Fourier
-    projection of the density every 10 steps, logged on the device (the
-    allocation-free moments call writes each record into a device array; the
-    host reads the 500 records once).  A(t) is Eq. (A)'s least-squares
+    projection of the density every 10 steps, logged on the device (each
+    mclg_step_moments call writes its record into a device array; the host
+    reads the 500 records once).  A(t) is Eq. (A)'s least-squares
     amplitude of the profile N(x) against sin(2 pi x / L)."""
     import numpy as np
     import synth
@@ -381,20 +381,24 @@ def run_wave(args, torch, M):
     counts = synth.density_wave_counts()
     tw = synth.twiddles(L, 1)
     K = args.wave_blocked
+    words = ct.sizeof(M.mclg_moments_t) // 8
     # a throwaway lattice warms the launch paths; the timed run starts at t = 0
     warm = M.Lattice(L, w["seed"], counts=counts)
     if K > 1:
         warm.set_blocked(K)
-    warm.step(2 * max(K, 10))
+    twd = torch.as_tensor(tw).to(warm.device)
+    junk = torch.zeros(words, dtype=torch.int64, device=warm.device)
+    warm.stream.wait_stream(torch.cuda.current_stream(warm.device))
+    for _ in range(2):
+        warm.step_moments(w["log_every"], junk, twd, 1)
+    warm.stream.synchronize()
     warm.close()
     del warm
     lat = M.Lattice(L, w["seed"], counts=counts)
     if K > 1:
         assert w["log_every"] % K == 0
         lat.set_blocked(K)  # each logging interval in launches of K steps
-    twd = torch.as_tensor(tw).to(lat.device)
     logs = w["steps"] // w["log_every"]
-    words = ct.sizeof(M.mclg_moments_t) // 8
     rec = torch.zeros((logs, words), dtype=torch.int64, device=lat.device)
     lat.stream.wait_stream(torch.cuda.current_stream(lat.device))
     torch.cuda.synchronize()
@@ -402,8 +406,9 @@ def run_wave(args, torch, M):
     t0 = time.perf_counter()
     e0.record(lat.stream)
     for k in range(logs):
-        lat.step(w["log_every"])
-        lat.moments_to_device(rec[k], twd, 1)
+        # the steps and the moments of the state they reach (with blocking,
+        # summed by the last launch as it writes the sites back)
+        lat.step_moments(w["log_every"], rec[k], twd, 1)
     e1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -253,6 +253,23 @@ int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes, uint32
 int mclg_moments_noalloc(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
                          uint32_t flags, mclg_moments_t *dev_out);
 
+/* Enqueue n_steps steps (as mclg_step), then the moments of the state they
+ * reach into dev_out (as mclg_moments: same arguments, same values), written
+ * in stream order on the context's stream without synchronising: the
+ * logging loop of a run that records its observables every n_steps steps.
+ *   dev_out: device, caller-owned, n_replicas mclg_moments_t; t is the
+ *     device's step counter (the steps taken modulo 2^32).
+ *   With several steps per launch (mclg_set_blocked) and n_steps a positive
+ *     multiple of that group, at most two modes and not two modes with
+ *     MCLG_MOMENTS_DIGEST, the last launch sums the moments of the sites it
+ *     writes back (the state is not read again); otherwise the moment
+ *     kernels run after the steps.  Either way the partial sums live in the
+ *     workspace, so calls on one context are stream-ordered and need no
+ *     clearing.
+ * MCLG_E_INVAL as mclg_moments; D2Q9 contexts: MCLG_E_UNSUPPORTED. */
+int mclg_step_moments(mclg_ctx *ctx, uint64_t n_steps, const int32_t *twiddle, uint32_t n_modes,
+                      uint32_t flags, mclg_moments_t *dev_out);
+
 /* Logical counts of one replica into host_out[3][L]; synchronises. */
 int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
 

@@ -17,7 +17,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=
 
 def build(force: bool = True, verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    deps = srcs + [os.path.join(CSRC, h) for h in ("device.h", "tables.h", "rng.h", "d2q9.h", "moments.h")] + \
+    deps = srcs + [os.path.join(CSRC, h) for h in ("device.h", "tables.h", "rng.h", "d2q9.h", "moments.h", "mom3_sum.h")] + \
         [os.path.join(HERE, "..", "include", "mclg.h")]
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):

@@ -146,6 +146,7 @@ struct mclg_ctx {
   // scratch; tb.steps <= 1 means one step per launch
   TbLaunch tb;
   uint32_t tb_grid = 0;
+  uint32_t tb_arrivals = 0;  // blocks of every blocked launch so far (the barrier's count)
   uint32_t drain_policy = MCLG_DRAIN_AUTO;
   // the device address of this device's static scratch area (moments.hip),
   // looked up in mclg_init with the context's device current
@@ -155,6 +156,17 @@ struct mclg_ctx {
 
   uint32_t *err() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl); }
   uint32_t *ticket() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl) + 1; }
+  uint32_t *barrier() { return reinterpret_cast<uint32_t *>(ws + lay.o_ctrl) + 2; }
+  // One launch of tb.steps steps (temporal blocking) at step t + t_pending.
+  hipError_t launch_blocked(TbLaunch b) {
+    b.bar = barrier();
+    b.bar_target = tb_arrivals + tb_grid;
+    hipError_t e = launch_step_blocked(sch, stream,
+                                       launch_args(0, (uint32_t)tiles.size(), 0, 1, t_pending), b,
+                                       tb_grid);
+    if (!e) tb_arrivals += tb_grid;
+    return e;
+  }
   SlotDev *slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
   uint32_t *tslot() { return reinterpret_cast<uint32_t *>(ws + lay.o_tslot); }
   hipError_t flush_t() {
@@ -579,10 +591,7 @@ int mclg_step(mclg_ctx *c, uint64_t n_steps) {
         hipError_t e = c->flush_t();
         if (e) return c->hip(e);
       }
-      hipError_t e = launch_step_blocked(c->sch, c->stream,
-                                         c->launch_args(0, (uint32_t)c->tiles.size(), 0, 1,
-                                                        c->t_pending),
-                                         c->tb, c->tb_grid);
+      hipError_t e = c->launch_blocked(c->tb);
       if (e) return c->hip(e);
       c->t[0] += K;  // (the launch advances the device counter itself)
     }
@@ -707,6 +716,48 @@ int mclg_moments_noalloc(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, 
   hipError_t e = c->flush_t();
   if (!e) e = launch_moments3(c->stream, m);
   return c->hip(e);
+}
+
+int mclg_step_moments(mclg_ctx *c, uint64_t n_steps, const int32_t *twiddle, uint32_t n_modes,
+                      uint32_t flags, mclg_moments_t *dev_out) {
+  if (c && c->d2) return MCLG_E_UNSUPPORTED;
+  if (!c || !dev_out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle) ||
+      (flags & ~(uint32_t)MCLG_MOMENTS_DIGEST))
+    return MCLG_E_INVAL;
+  const uint32_t dig = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
+  const uint32_t K = c->tb.steps;
+  unsigned long long *part = reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart);
+  // the last launch of the call is a blocked one: it sums the moments of the
+  // sites it writes back (one partial record per block in the workspace)
+  const bool fused = K > 1 && n_steps >= K && n_steps % K == 0 && n_modes <= 2 &&
+                     !(n_modes == 2 && dig) && c->tb_grid <= c->lay.mplan.segs.size();
+  if (!fused) {
+    int rc = mclg_step(c, n_steps);
+    if (rc) return rc;
+    MomArgs m = c->mom_args(part, reinterpret_cast<long long *>(dev_out));
+    m.twiddle = twiddle;
+    m.n_modes = n_modes;
+    m.digest = dig;
+    hipError_t e = c->flush_t();
+    if (!e) e = launch_moments3(c->stream, m);
+    return c->hip(e);
+  }
+  int rc = mclg_step(c, n_steps - K);
+  if (rc) return rc;
+  if (c->t_pending >= (1u << 30)) {
+    hipError_t e = c->flush_t();
+    if (e) return c->hip(e);
+  }
+  TbLaunch tb = c->tb;
+  tb.log = 1u + 2u * n_modes + dig;
+  tb.tw = twiddle;
+  tb.partial = part;
+  tb.out = reinterpret_cast<long long *>(dev_out);
+  tb.ticket = c->ticket();
+  hipError_t e = c->launch_blocked(tb);
+  if (e) return c->hip(e);
+  c->t[0] += K;
+  return MCLG_OK;
 }
 
 int mclg_histogram(mclg_ctx *c, uint32_t n_bins, uint64_t *hist) {

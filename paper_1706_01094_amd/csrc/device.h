@@ -157,7 +157,9 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // copy's ends are wrong after j steps, the owned sites stay exact, and the
 // random numbers are keyed by each site's place in the lattice.  It then
 // writes its owned sites back at step t + steps.  Block 0 advances the
-// slot's step counter by `steps` once every block has read it.
+// slot's step counter by `steps` once every block has read it.  The barrier
+// counts arrivals in `bar` across launches (never reset): this launch's
+// blocks have all arrived when it reaches bar_target.
 constexpr uint32_t kTbMaxSteps = 256;
 struct TbLaunch {
   uint16_t *scratch = nullptr;  // grid x 3 x stride elements
@@ -166,6 +168,19 @@ struct TbLaunch {
   uint32_t kh = 0;              // extra sites on each side (a multiple of 8)
   uint32_t es = 0;              // R + 2 kh
   uint32_t steps = 0;           // steps of the launch
+  uint32_t *bar = nullptr;      // arrivals of every blocked launch of the context
+  uint32_t bar_target = 0;      // arrivals before this launch + its grid
+  // A logging launch (log != 0) also sums the moments of the state it writes
+  // back (mclg_moments_t): log = 1 + 2 n_modes + digest, at most 5 (two modes
+  // without the digest).
+  // Each block writes one partial record (kMom3Rec values) at partial + b
+  // kMom3Rec; the last block to finish (a ticket, zero before the launch and
+  // after it) adds them into out.  tw: the lattice's [2 n_modes][L] twiddles.
+  uint32_t log = 0;
+  const int32_t *tw = nullptr;
+  unsigned long long *partial = nullptr;
+  long long *out = nullptr;
+  uint32_t *ticket = nullptr;
 };
 hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
                                const TbLaunch &tb, uint32_t grid);

@@ -10,9 +10,9 @@
 // Algorithmic traffic: 6 B read + 6 B written per site update; there is no
 // dense contraction, so no MFMA.
 #include "device.h"
+#include "mom3_sum.h"
 #include "rng.h"
 
-#include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
 
@@ -1017,6 +1017,150 @@ __device__ __forceinline__ void store8_wrap(Rsrc r, uint32_t arr, uint32_t pos, 
   }
 }
 
+// The grid-wide barrier of a blocked launch, without memory fences.  What it
+// orders: every block's reads of the state (and of its step counter) before
+// any block writes them.  A block's reads have returned once their values
+// are stored into its copy, before it arrives; nothing else crosses blocks,
+// and fences would write back and invalidate the L2s that hold the copies.
+// `bar` counts arrivals across launches; this launch's blocks have all
+// arrived when it reaches `target`.  Every block is resident (a cooperative
+// launch), so the wait ends; one that has not ended after 2^24 polls flags an
+// internal error and goes on, so that no launch can hang.
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, uint32_t *err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(bar, 1u);
+    for (uint32_t n = 0;
+         (int32_t)(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0;
+         ++n) {
+      if (n == (1u << 24)) {
+        atomicOr(err, kErrInternal);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
+// The last part of a blocked launch: the block's owned sites, read from its
+// copy at step t0 + steps, back into the state, eight per thread.  A logging
+// launch (LOG) also sums their moments (NM Fourier modes, the digest with
+// DIG) in the lanes, writes the block's partial record, and the last block
+// to take a ticket adds the grid's records into the result.  red: LDS of at
+// least 8 KiB that nothing else uses any more.
+template <int NM, bool DIG, bool LOG>
+__device__ __forceinline__ void write_back(const TbLaunch &tb, Rsrc srs, Rsrc mrs, uint32_t sab,
+                                           uint32_t mab, bool active, uint32_t L, uint32_t X0,
+                                           uint32_t t0, bool no_stream, uint4 *red) {
+  using namespace mom3;
+  const uint32_t es = tb.es;
+  Acc3<NM> A;
+  if constexpr (LOG) acc_clear<NM>(A);
+  if (active) {
+    const uint32_t tms = no_stream ? 0u : tb.steps % es;
+    const uint32_t tmk = no_stream ? 0u : (uint32_t)(((uint64_t)t0 + tb.steps) % L);
+    const uint32_t x1 = min(L - X0, tb.R);
+    for (uint32_t j = 8u * threadIdx.x; j < x1; j += 8u * blockDim.x) {
+      const uint32_t i = tb.kh + j, x = X0 + j;
+      uint32_t im_ = i + tms;
+      im_ -= im_ >= es ? es : 0u;
+      const uint32_t ip = i >= tms ? i - tms : i + es - tms;
+      uint32_t pm = x + tmk;
+      pm -= pm >= L ? L : 0u;
+      const uint32_t pp = x >= tmk ? x - tmk : x + L - tmk;
+      uint32_t m[4], z[4], q[4];
+      load8_wrap(srs, 0u, im_, es, m);
+      bload4(srs, 2u * i, sab, z);
+      load8_wrap(srs, 2u * sab, ip, es, q);
+      store8_wrap(mrs, 0u, pm, L, m);
+      bstore4(mrs, 2u * x, mab, z);
+      store8_wrap(mrs, 2u * mab, pp, L, q);
+      if constexpr (LOG) {
+        // the eight sites x .. x + 7 (L and R are multiples of 8)
+        Eight<NM> E;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          E.a[k] = m[k];
+          E.b[k] = z[k];
+          E.c[k] = q[k];
+        }
+        E.x = x;
+        E.n = 8u;
+#pragma unroll
+        for (int r = 0; r < 2 * NM; ++r) {
+          const uint4 *row = reinterpret_cast<const uint4 *>(tb.tw + (uint64_t)r * L + x);
+          const uint4 w0 = row[0], w1 = row[1];
+          E.w[r][0] = (int32_t)w0.x; E.w[r][1] = (int32_t)w0.y;
+          E.w[r][2] = (int32_t)w0.z; E.w[r][3] = (int32_t)w0.w;
+          E.w[r][4] = (int32_t)w1.x; E.w[r][5] = (int32_t)w1.y;
+          E.w[r][6] = (int32_t)w1.z; E.w[r][7] = (int32_t)w1.w;
+        }
+        add_eight<NM, DIG>(A, E, tb.tw, L);
+      }
+    }
+  }
+  if constexpr (LOG) {
+    constexpr int W = 12 + 2 * NM, V = 16;
+    u64 v[V];
+    const uint32_t mx = fold<NM, V>(A, v);
+    u64 *const rd = reinterpret_cast<u64 *>(red);        // 16 x V values
+    uint32_t *const rmx = reinterpret_cast<uint32_t *>(rd + 16 * V);  // 16
+    uint32_t *const last = rmx + 16;
+    u64 *const fin = rd + 16 * V + 16;                   // 16 waves x 32 values
+    // The record goes past the L2 (device-coherent stores) and is complete
+    // (the wait) before the block takes its ticket; the last block reads the
+    // records with device-coherent loads.  No fences: they would write back
+    // and invalidate whole L2s while other blocks still read their copies.
+    block_record<V, W, 11, true>(v, mx, tb.partial + (uint64_t)blockIdx.x * kMom3Rec, rd, rmx);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) *last = atomicAdd(tb.ticket, 1u) == gridDim.x - 1u;
+    __syncthreads();
+    if (!*last) return;
+    // thread (g, p) adds pair p (values 2p, 2p + 1) of records g, g + 64, ...
+    const uint32_t p = threadIdx.x & 15u, g = threadIdx.x >> 4;
+    const bool m0 = 2u * p == 11u, m1 = 2u * p + 1u == 11u;
+    u64 a0 = 0, a1 = 0;
+    if (p < (uint32_t)(W + 1) / 2u) {
+      for (uint32_t r = g; r < gridDim.x; r += 64u) {
+        u64 *const q = tb.partial + (uint64_t)r * kMom3Rec + 2u * p;
+        const u64 v0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const u64 v1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a0 = m0 ? max(a0, v0) : a0 + v0;
+        a1 = m1 ? max(a1, v1) : a1 + v1;
+      }
+    }
+    // the four groups of a wave, then the 16 waves
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      const u64 b0 = shfl_xor_u64(a0, o), b1 = shfl_xor_u64(a1, o);
+      a0 = m0 ? max(a0, b0) : a0 + b0;
+      a1 = m1 ? max(a1, b1) : a1 + b1;
+    }
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) < 16u) {
+      fin[wave * 32u + 2u * p] = a0;
+      fin[wave * 32u + 2u * p + 1u] = a1;
+    }
+    __syncthreads();
+    u64 *const T = fin + 16 * 32;  // the grid's sums, kMom3Rec values
+    if (threadIdx.x < kMom3Rec) {
+      const uint32_t k = threadIdx.x;
+      u64 t = 0;
+      for (uint32_t w = 0; w < 16u; ++w) {
+        const u64 y = fin[w * 32u + k];
+        t = k == 11u ? max(t, y) : t + y;
+      }
+      T[k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMom3Out)
+      tb.out[threadIdx.x] = (i64)result_field(threadIdx.x, T, t0 + tb.steps, L, NM);
+    if (threadIdx.x == 0) atomicExch(tb.ticket, 0u);
+  }
+}
+
 // Several steps of one lattice per launch (see TbLaunch).  Deferred drains:
 // the block's copy stays in the caches, and each step ends with the drain of
 // every wave's queue and a block barrier, so step s + 1 reads what step s
@@ -1087,7 +1231,7 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
   }
   // (2) every block has read the state (and its step counter) before any
   // writes it; the launch advances the counter itself
-  cooperative_groups::this_grid().sync();
+  grid_barrier(tb.bar, tb.bar_target, a.err);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.tslot[a.slot_first] += tb.steps;
 
   // (3) the steps on the block's copy: a periodic lattice of es sites
@@ -1121,28 +1265,19 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
     __syncthreads();  // step s is written before step s + 1 reads it
   }
 
-  // (4) the owned sites back into the state at step t0 + steps, eight per
-  // thread
-  if (active) {
-    const uint32_t tms = p.no_stream ? 0u : tb.steps % es;
-    const uint32_t tmk = p.no_stream ? 0u : (uint32_t)(((uint64_t)t0 + tb.steps) % L);
-    const uint32_t x1 = min(L - X0, tb.R);
-    for (uint32_t j = 8u * threadIdx.x; j < x1; j += 8u * blockDim.x) {
-      const uint32_t i = tb.kh + j, x = X0 + j;
-      uint32_t im_ = i + tms;
-      im_ -= im_ >= es ? es : 0u;
-      const uint32_t ip = i >= tms ? i - tms : i + es - tms;
-      uint32_t pm = x + tmk;
-      pm -= pm >= L ? L : 0u;
-      const uint32_t pp = x >= tmk ? x - tmk : x + L - tmk;
-      uint32_t m[4], z[4], q[4];
-      load8_wrap(srs, 0u, im_, es, m);
-      bload4(srs, 2u * i, sab, z);
-      load8_wrap(srs, 2u * sab, ip, es, q);
-      store8_wrap(mrs, 0u, pm, L, m);
-      bstore4(mrs, 2u * x, mab, z);
-      store8_wrap(mrs, 2u * mab, pp, L, q);
-    }
+  // (4) the owned sites back into the state at step t0 + steps (and their
+  // moments on a logging launch: two modes with the digest would spill
+  // registers, and the host sums those separately); the miss queues' LDS is
+  // free now
+  uint4 *const red = lds + a.lds_bytes / 16u;
+  const bool ns = p.no_stream != 0;
+  switch (tb.log) {
+    case 1: write_back<0, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
+    case 2: write_back<0, true, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
+    case 3: write_back<1, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
+    case 4: write_back<1, true, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
+    case 5: write_back<2, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
+    default: write_back<0, false, false>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red);
   }
 }
 
@@ -1324,6 +1459,9 @@ hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLau
                                const TbLaunch &tb, uint32_t grid) {
   if (sch.groups != 1 || sch.threads != 1024 || !a.single || tb.steps == 0 ||
       tb.steps > tb.kh || tb.es != tb.R + 2u * tb.kh || tb.stride < tb.es)
+    return hipErrorInvalidValue;
+  if (!tb.bar) return hipErrorInvalidValue;
+  if (tb.log && (tb.log > 5u || !tb.partial || !tb.out || !tb.ticket || (tb.log >= 3u && !tb.tw)))
     return hipErrorInvalidValue;
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
   StepLaunch av = a;

@@ -9,6 +9,7 @@ namespace {
 
 constexpr uint32_t kErrOverflow = 1u;   // a site with N > 65535
 constexpr uint32_t kErrEqRange = 2u;    // C = infinity and N > n_max
+constexpr uint32_t kErrInternal = 4u;   // a blocked launch's grid barrier timed out
 
 // a ^ b ^ k in one instruction (v_bitop3_b32 with the XOR3 truth table)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {

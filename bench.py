@@ -370,9 +370,9 @@ def run_batched(args, torch, M):
 
 def run_wave(args, torch, M):
     """Decaying density wave, L = 2^22, 5000 steps, the int64 Fourier
-    projection of the density every 10 steps, logged on the device (each
-    mclg_step_moments call writes its record into a device array; the host
-    reads the 500 records once).  A(t) is Eq. (A)'s least-squares
+    projection of the density every 10 steps, logged on the device (one
+    mclg_step_log call writes the 500 records into a device array; the host
+    reads them once).  A(t) is Eq. (A)'s least-squares
     amplitude of the profile N(x) against sin(2 pi x / L)."""
     import numpy as np
     import synth
@@ -387,17 +387,16 @@ def run_wave(args, torch, M):
     if K > 1:
         warm.set_blocked(K)
     twd = torch.as_tensor(tw).to(warm.device)
-    junk = torch.zeros(words, dtype=torch.int64, device=warm.device)
+    junk = torch.zeros((2 * max(1, K // w["log_every"]), words), dtype=torch.int64,
+                       device=warm.device)
     warm.stream.wait_stream(torch.cuda.current_stream(warm.device))
-    for _ in range(2):
-        warm.step_moments(w["log_every"], junk, twd, 1)
+    warm.step_log(w["log_every"], junk.shape[0], junk, twd, 1)
     warm.stream.synchronize()
     warm.close()
     del warm
     lat = M.Lattice(L, w["seed"], counts=counts)
     if K > 1:
-        assert w["log_every"] % K == 0
-        lat.set_blocked(K)  # each logging interval in launches of K steps
+        lat.set_blocked(K)  # launches of K steps, each summing the logs in it
     logs = w["steps"] // w["log_every"]
     rec = torch.zeros((logs, words), dtype=torch.int64, device=lat.device)
     lat.stream.wait_stream(torch.cuda.current_stream(lat.device))
@@ -405,10 +404,9 @@ def run_wave(args, torch, M):
     e0, e1 = _events(torch, lat.stream)
     t0 = time.perf_counter()
     e0.record(lat.stream)
-    for k in range(logs):
-        # the steps and the moments of the state they reach (with blocking,
-        # summed by the last launch as it writes the sites back)
-        lat.step_moments(w["log_every"], rec[k], twd, 1)
+    # the whole run: 500 intervals of 10 steps, each followed by the moments
+    # of the state it reaches
+    lat.step_log(w["log_every"], logs, rec, twd, 1)
     e1.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -588,8 +586,9 @@ def main():
                     help="steps per launch of the L = 2^24 workload (temporal blocking; 1: off)")
     ap.add_argument("--single-steps", type=int, default=2000,
                     help="steps of the one-step-per-launch comparison of the blocked run")
-    ap.add_argument("--wave-blocked", type=int, default=10,
-                    help="steps per launch of the density wave (its logging interval; 1: off)")
+    ap.add_argument("--wave-blocked", type=int, default=250,
+                    help="steps per launch of the density wave (each launch sums the logs "
+                         "that fall in it; 1: off)")
     ap.add_argument("--serve-window", type=float, default=10.0)
     ap.add_argument("--serve-limit", type=float, default=120.0)
     ap.add_argument("--d2q9-steps", type=int, default=50)

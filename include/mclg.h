@@ -253,22 +253,26 @@ int mclg_moments(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes, uint32
 int mclg_moments_noalloc(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes,
                          uint32_t flags, mclg_moments_t *dev_out);
 
-/* Enqueue n_steps steps (as mclg_step), then the moments of the state they
- * reach into dev_out (as mclg_moments: same arguments, same values), written
- * in stream order on the context's stream without synchronising: the
- * logging loop of a run that records its observables every n_steps steps.
- *   dev_out: device, caller-owned, n_replicas mclg_moments_t; t is the
- *     device's step counter (the steps taken modulo 2^32).
- *   With several steps per launch (mclg_set_blocked) and n_steps a positive
- *     multiple of that group, at most two modes and not two modes with
- *     MCLG_MOMENTS_DIGEST, the last launch sums the moments of the sites it
- *     writes back (the state is not read again); otherwise the moment
- *     kernels run after the steps.  Either way the partial sums live in the
- *     workspace, so calls on one context are stream-ordered and need no
- *     clearing.
- * MCLG_E_INVAL as mclg_moments; D2Q9 contexts: MCLG_E_UNSUPPORTED. */
-int mclg_step_moments(mclg_ctx *ctx, uint64_t n_steps, const int32_t *twiddle, uint32_t n_modes,
-                      uint32_t flags, mclg_moments_t *dev_out);
+/* The logging loop of a run that records its observables: n_logs times,
+ * enqueue `every` steps (as mclg_step) and then the moments of the state
+ * they reach (as mclg_moments: same arguments, same values) into dev_out,
+ * in stream order on the context's stream, without synchronising.
+ *   dev_out: device, caller-owned, n_logs x n_replicas mclg_moments_t (log j
+ *     of replica r at j n_replicas + r); t is the device's step counter (the
+ *     steps taken modulo 2^32).
+ *   With several steps per launch (mclg_set_blocked), at most two modes and
+ *     not two modes with MCLG_MOMENTS_DIGEST, the run goes in launches of
+ *     that many steps (the last one shorter) and each launch sums the logs
+ *     that fall in it from the blocks' copies, the last one as it writes the
+ *     sites back: the state is not read again, and one launch covers several
+ *     logs when `every` is below its steps.  Otherwise the moment kernels run
+ *     after each interval's steps.  Either way the partial sums live in the
+ *     blocked scratch or the workspace, so calls on one context are
+ *     stream-ordered and need no clearing.
+ * MCLG_E_INVAL for every = 0, every x n_logs >= 2^62 and as mclg_moments;
+ * D2Q9 contexts: MCLG_E_UNSUPPORTED. */
+int mclg_step_log(mclg_ctx *ctx, uint64_t every, uint64_t n_logs, const int32_t *twiddle,
+                  uint32_t n_modes, uint32_t flags, mclg_moments_t *dev_out);
 
 /* Logical counts of one replica into host_out[3][L]; synchronises. */
 int mclg_get_counts(mclg_ctx *ctx, uint32_t replica, uint16_t *host_out);
@@ -329,7 +333,8 @@ int mclg_set_drain(mclg_ctx *ctx, uint32_t policy);
  * waits for all blocks (a grid-wide barrier), advances its copy, and writes
  * its own sites back; the rest of a mclg_step call takes single steps.  The
  * bits are the same as with one step per launch.
- *   mclg_blocked_bytes: the scratch bytes `steps` steps per launch need.
+ *   mclg_blocked_bytes: the scratch bytes `steps` steps per launch need (the
+ *     blocks' copies, and room for the partial sums of mclg_step_log).
  *   mclg_set_blocked: steps in [2, 256] with scratch (device, caller-owned,
  *     at least mclg_blocked_bytes, kept until blocking is switched off or the
  *     context destroyed); steps <= 1 switches it off (scratch unused).

@@ -164,7 +164,7 @@ struct mclg_ctx {
     hipError_t e = launch_step_blocked(sch, stream,
                                        launch_args(0, (uint32_t)tiles.size(), 0, 1, t_pending), b,
                                        tb_grid);
-    if (!e) tb_arrivals += tb_grid;
+    if (!e) tb_arrivals += b.n_logs ? 2u * tb_grid : tb_grid;
     return e;
   }
   SlotDev *slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
@@ -528,9 +528,11 @@ static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t 
 
 // The geometry of `steps` steps per launch for the context's one lattice:
 // every block of the grid resident at once, R owned sites per block (a
-// multiple of 8), kh = steps rounded up to 8 extra sites on each side.
+// multiple of 8), kh = steps rounded up to 8 extra sites on each side.  The
+// scratch holds the blocks' copies, then the partial records of up to
+// `steps` logs per launch (records_at bytes in).
 static int blocked_geometry(mclg_ctx *c, uint32_t steps, TbLaunch &tb, uint32_t &grid,
-                            uint64_t &bytes) {
+                            uint64_t &bytes, uint64_t &records_at) {
   if (c->d2) return MCLG_E_UNSUPPORTED;
   if (steps < 2 || steps > kTbMaxSteps) return MCLG_E_INVAL;
   if (c->n != 1 || c->L[0] % 8 != 0 || c->sch.threads != 1024) return MCLG_E_UNSUPPORTED;
@@ -549,7 +551,8 @@ static int blocked_geometry(mclg_ctx *c, uint32_t steps, TbLaunch &tb, uint32_t 
   if ((uint64_t)t.es + 512u > L) return MCLG_E_UNSUPPORTED;
   tb = t;
   grid = g;
-  bytes = (uint64_t)g * 3u * t.stride * sizeof(uint16_t);
+  records_at = align_up((uint64_t)g * 3u * t.stride * sizeof(uint16_t), 256);
+  bytes = records_at + (uint64_t)steps * g * kMom3Rec * sizeof(uint64_t);
   return MCLG_OK;
 }
 
@@ -557,7 +560,8 @@ int mclg_blocked_bytes(mclg_ctx *c, uint32_t steps, uint64_t *scratch_bytes) {
   if (!c || !scratch_bytes) return MCLG_E_INVAL;
   TbLaunch tb;
   uint32_t grid = 0;
-  return blocked_geometry(c, steps, tb, grid, *scratch_bytes);
+  uint64_t records_at = 0;
+  return blocked_geometry(c, steps, tb, grid, *scratch_bytes, records_at);
 }
 
 int mclg_set_blocked(mclg_ctx *c, uint32_t steps, void *scratch, uint64_t scratch_bytes) {
@@ -570,11 +574,12 @@ int mclg_set_blocked(mclg_ctx *c, uint32_t steps, void *scratch, uint64_t scratc
   }
   TbLaunch tb;
   uint32_t grid = 0;
-  uint64_t need = 0;
-  int rc = blocked_geometry(c, steps, tb, grid, need);
+  uint64_t need = 0, records_at = 0;
+  int rc = blocked_geometry(c, steps, tb, grid, need, records_at);
   if (rc) return rc;
   if (!scratch || scratch_bytes < need) return MCLG_E_INVAL;
   tb.scratch = static_cast<uint16_t *>(scratch);
+  tb.records = reinterpret_cast<unsigned long long *>(static_cast<uint8_t *>(scratch) + records_at);
   c->tb = tb;
   c->tb_grid = grid;
   return MCLG_OK;
@@ -718,45 +723,59 @@ int mclg_moments_noalloc(mclg_ctx *c, const int32_t *twiddle, uint32_t n_modes, 
   return c->hip(e);
 }
 
-int mclg_step_moments(mclg_ctx *c, uint64_t n_steps, const int32_t *twiddle, uint32_t n_modes,
-                      uint32_t flags, mclg_moments_t *dev_out) {
+int mclg_step_log(mclg_ctx *c, uint64_t every, uint64_t n_logs, const int32_t *twiddle,
+                  uint32_t n_modes, uint32_t flags, mclg_moments_t *dev_out) {
   if (c && c->d2) return MCLG_E_UNSUPPORTED;
-  if (!c || !dev_out || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle) ||
-      (flags & ~(uint32_t)MCLG_MOMENTS_DIGEST))
+  if (!c || !dev_out || every == 0 || n_modes > MCLG_MAX_MODES || (n_modes && !twiddle) ||
+      (flags & ~(uint32_t)MCLG_MOMENTS_DIGEST) || n_logs > (1ull << 62) / every)
     return MCLG_E_INVAL;
   const uint32_t dig = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
   const uint32_t K = c->tb.steps;
-  unsigned long long *part = reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart);
-  // the last launch of the call is a blocked one: it sums the moments of the
-  // sites it writes back (one partial record per block in the workspace)
-  const bool fused = K > 1 && n_steps >= K && n_steps % K == 0 && n_modes <= 2 &&
-                     !(n_modes == 2 && dig) && c->tb_grid <= c->lay.mplan.segs.size();
-  if (!fused) {
-    int rc = mclg_step(c, n_steps);
-    if (rc) return rc;
-    MomArgs m = c->mom_args(part, reinterpret_cast<long long *>(dev_out));
-    m.twiddle = twiddle;
-    m.n_modes = n_modes;
-    m.digest = dig;
-    hipError_t e = c->flush_t();
-    if (!e) e = launch_moments3(c->stream, m);
-    return c->hip(e);
+  if (!(K > 1 && n_modes <= 2 && !(n_modes == 2 && dig))) {
+    // steps, then the moment kernels, per log (partial sums in the workspace)
+    unsigned long long *part = reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart);
+    for (uint64_t j = 0; j < n_logs; ++j) {
+      int rc = mclg_step(c, every);
+      if (rc) return rc;
+      MomArgs m = c->mom_args(part, reinterpret_cast<long long *>(dev_out + j * c->n));
+      m.twiddle = twiddle;
+      m.n_modes = n_modes;
+      m.digest = dig;
+      hipError_t e = c->flush_t();
+      if (!e) e = launch_moments3(c->stream, m);
+      if (e) return c->hip(e);
+    }
+    return MCLG_OK;
   }
-  int rc = mclg_step(c, n_steps - K);
-  if (rc) return rc;
-  if (c->t_pending >= (1u << 30)) {
-    hipError_t e = c->flush_t();
+  // launches of K steps (the last one shorter); each sums the logs that fall
+  // in it, at steps every, 2 every, ... of the call.  With the digest or the
+  // Galilean acceptance a launch also ends at each log (the kernel sums those
+  // only as it writes the sites back).
+  const bool at_end_only = dig || (c->flags & MCLG_FLAG_GALILEAN);
+  const uint64_t total = every * n_logs;
+  for (uint64_t c0 = 0; c0 < total;) {
+    if (c->t_pending >= (1u << 30)) {
+      hipError_t e = c->flush_t();
+      if (e) return c->hip(e);
+    }
+    const uint64_t o1 = every - c0 % every;  // the first log after c0, relative
+    const uint32_t S =
+        (uint32_t)std::min<uint64_t>(std::min<uint64_t>(K, total - c0), at_end_only ? o1 : K);
+    TbLaunch b = c->tb;
+    b.steps = S;
+    if (o1 <= S) {
+      b.n_logs = (uint32_t)((S - o1) / every + 1u);
+      b.log = 1u + 2u * n_modes + dig;
+      b.log_first = (uint32_t)o1;
+      b.log_every = (uint32_t)std::min<uint64_t>(every, K);  // (one log when every > K)
+      b.tw = twiddle;
+      b.out = reinterpret_cast<long long *>(dev_out + ((c0 + o1) / every - 1u) * c->n);
+    }
+    hipError_t e = c->launch_blocked(b);
     if (e) return c->hip(e);
+    c->t[0] += S;
+    c0 += S;
   }
-  TbLaunch tb = c->tb;
-  tb.log = 1u + 2u * n_modes + dig;
-  tb.tw = twiddle;
-  tb.partial = part;
-  tb.out = reinterpret_cast<long long *>(dev_out);
-  tb.ticket = c->ticket();
-  hipError_t e = c->launch_blocked(tb);
-  if (e) return c->hip(e);
-  c->t[0] += K;
   return MCLG_OK;
 }
 

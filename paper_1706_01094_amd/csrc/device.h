@@ -170,17 +170,19 @@ struct TbLaunch {
   uint32_t steps = 0;           // steps of the launch
   uint32_t *bar = nullptr;      // arrivals of every blocked launch of the context
   uint32_t bar_target = 0;      // arrivals before this launch + its grid
-  // A logging launch (log != 0) also sums the moments of the state it writes
-  // back (mclg_moments_t): log = 1 + 2 n_modes + digest, at most 5 (two modes
-  // without the digest).
-  // Each block writes one partial record (kMom3Rec values) at partial + b
-  // kMom3Rec; the last block to finish (a ticket, zero before the launch and
-  // after it) adds them into out.  tw: the lattice's [2 n_modes][L] twiddles.
-  uint32_t log = 0;
+  // Logs (n_logs > 0): the moments (mclg_moments_t) of the state after steps
+  // log_first, log_first + log_every, ... (the last at most `steps`) of the
+  // launch; log = 1 + 2 n_modes + digest, at most 5 (two modes without the
+  // digest).  Logs before the last step: only without the digest and the
+  // Galilean acceptance.  Block b writes its partial record of log j (kMom3Rec values) at
+  // records + (j grid + b) kMom3Rec with device-coherent stores; after a
+  // second barrier (bar_target + grid) block b adds the records of logs b,
+  // b + grid, ... into out + j kMom3Out.  tw: the lattice's [2 n_modes][L]
+  // twiddles.
+  uint32_t log = 0, n_logs = 0, log_first = 0, log_every = 0;
   const int32_t *tw = nullptr;
-  unsigned long long *partial = nullptr;
+  unsigned long long *records = nullptr;
   long long *out = nullptr;
-  uint32_t *ticket = nullptr;
 };
 hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
                                const TbLaunch &tb, uint32_t grid);

@@ -1043,52 +1043,60 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, uin
   __syncthreads();
 }
 
-// The last part of a blocked launch: the block's owned sites, read from its
-// copy at step t0 + steps, back into the state, eight per thread.  A logging
-// launch (LOG) also sums their moments (NM Fourier modes, the digest with
-// DIG) in the lanes, writes the block's partial record, and the last block
-// to take a ticket adds the grid's records into the result.  red: LDS of at
-// least 8 KiB that nothing else uses any more.
-template <int NM, bool DIG, bool LOG>
-__device__ __forceinline__ void write_back(const TbLaunch &tb, Rsrc srs, Rsrc mrs, uint32_t sab,
+// A pass of a blocked launch over the block's owned sites, eight per thread,
+// read from its copy after `done` steps: WB writes them back into the state
+// (the launch's last part, done = steps); LOG sums their moments (NM Fourier
+// modes, the digest with DIG) in the lanes and writes the block's partial
+// record of log `j` with device-coherent stores.  red: LDS of at least 8 KiB
+// that no other part of the block uses meanwhile.
+template <int NM, bool DIG, bool WB, bool LOG>
+__device__ __forceinline__ void owned_pass(const TbLaunch &tb, Rsrc srs, Rsrc mrs, uint32_t sab,
                                            uint32_t mab, bool active, uint32_t L, uint32_t X0,
-                                           uint32_t t0, bool no_stream, uint4 *red) {
+                                           uint32_t t0, uint32_t done, bool no_stream,
+                                           uint32_t j, uint4 *red) {
   using namespace mom3;
+  // Between steps (!WB) the Fourier sums take a second loop over the sites
+  // (from the L2), so that the step loop's registers hold both.
+  constexpr bool SPLIT = !WB && NM > 0;
+  constexpr int NA = SPLIT ? 0 : NM;
   const uint32_t es = tb.es;
-  Acc3<NM> A;
-  if constexpr (LOG) acc_clear<NM>(A);
+  Acc3<NA> A;
+  i64 fs[2 * NM > 0 ? 2 * NM : 1] = {};
+  if constexpr (LOG) acc_clear<NA>(A);
   if (active) {
-    const uint32_t tms = no_stream ? 0u : tb.steps % es;
-    const uint32_t tmk = no_stream ? 0u : (uint32_t)(((uint64_t)t0 + tb.steps) % L);
+    const uint32_t tms = no_stream ? 0u : done % es;
+    const uint32_t tmk = no_stream ? 0u : (uint32_t)(((uint64_t)t0 + done) % L);
     const uint32_t x1 = min(L - X0, tb.R);
-    for (uint32_t j = 8u * threadIdx.x; j < x1; j += 8u * blockDim.x) {
-      const uint32_t i = tb.kh + j, x = X0 + j;
+    for (uint32_t k = 8u * threadIdx.x; k < x1; k += 8u * blockDim.x) {
+      const uint32_t i = tb.kh + k, x = X0 + k;
       uint32_t im_ = i + tms;
       im_ -= im_ >= es ? es : 0u;
       const uint32_t ip = i >= tms ? i - tms : i + es - tms;
-      uint32_t pm = x + tmk;
-      pm -= pm >= L ? L : 0u;
-      const uint32_t pp = x >= tmk ? x - tmk : x + L - tmk;
       uint32_t m[4], z[4], q[4];
       load8_wrap(srs, 0u, im_, es, m);
       bload4(srs, 2u * i, sab, z);
       load8_wrap(srs, 2u * sab, ip, es, q);
-      store8_wrap(mrs, 0u, pm, L, m);
-      bstore4(mrs, 2u * x, mab, z);
-      store8_wrap(mrs, 2u * mab, pp, L, q);
+      if constexpr (WB) {
+        uint32_t pm = x + tmk;
+        pm -= pm >= L ? L : 0u;
+        const uint32_t pp = x >= tmk ? x - tmk : x + L - tmk;
+        store8_wrap(mrs, 0u, pm, L, m);
+        bstore4(mrs, 2u * x, mab, z);
+        store8_wrap(mrs, 2u * mab, pp, L, q);
+      }
       if constexpr (LOG) {
         // the eight sites x .. x + 7 (L and R are multiples of 8)
-        Eight<NM> E;
+        Eight<NA> E;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          E.a[k] = m[k];
-          E.b[k] = z[k];
-          E.c[k] = q[k];
+        for (int e = 0; e < 4; ++e) {
+          E.a[e] = m[e];
+          E.b[e] = z[e];
+          E.c[e] = q[e];
         }
         E.x = x;
         E.n = 8u;
 #pragma unroll
-        for (int r = 0; r < 2 * NM; ++r) {
+        for (int r = 0; r < 2 * NA; ++r) {
           const uint4 *row = reinterpret_cast<const uint4 *>(tb.tw + (uint64_t)r * L + x);
           const uint4 w0 = row[0], w1 = row[1];
           E.w[r][0] = (int32_t)w0.x; E.w[r][1] = (int32_t)w0.y;
@@ -1096,68 +1104,132 @@ __device__ __forceinline__ void write_back(const TbLaunch &tb, Rsrc srs, Rsrc mr
           E.w[r][4] = (int32_t)w1.x; E.w[r][5] = (int32_t)w1.y;
           E.w[r][6] = (int32_t)w1.z; E.w[r][7] = (int32_t)w1.w;
         }
-        add_eight<NM, DIG>(A, E, tb.tw, L);
+        add_eight<NA, DIG>(A, E, tb.tw, L);
+      }
+    }
+    if constexpr (LOG && SPLIT) {
+      for (uint32_t k = 8u * threadIdx.x; k < x1; k += 8u * blockDim.x) {
+        const uint32_t i = tb.kh + k, x = X0 + k;
+        uint32_t im_ = i + tms;
+        im_ -= im_ >= es ? es : 0u;
+        const uint32_t ip = i >= tms ? i - tms : i + es - tms;
+        uint32_t m[4], z[4], q[4];
+        load8_wrap(srs, 0u, im_, es, m);
+        bload4(srs, 2u * i, sab, z);
+        load8_wrap(srs, 2u * sab, ip, es, q);
+        int32_t N[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) N[e] = (int32_t)(get16(m, e) + get16(z, e) + get16(q, e));
+#pragma unroll
+        for (int r = 0; r < 2 * NM; ++r) {
+          const uint4 *row = reinterpret_cast<const uint4 *>(tb.tw + (uint64_t)r * L + x);
+          const uint4 w0 = row[0], w1 = row[1];
+          fs[r] += (i64)N[0] * (int32_t)w0.x + (i64)N[1] * (int32_t)w0.y +
+                   (i64)N[2] * (int32_t)w0.z + (i64)N[3] * (int32_t)w0.w +
+                   (i64)N[4] * (int32_t)w1.x + (i64)N[5] * (int32_t)w1.y +
+                   (i64)N[6] * (int32_t)w1.z + (i64)N[7] * (int32_t)w1.w;
+        }
       }
     }
   }
   if constexpr (LOG) {
     constexpr int W = 12 + 2 * NM, V = 16;
     u64 v[V];
-    const uint32_t mx = fold<NM, V>(A, v);
-    u64 *const rd = reinterpret_cast<u64 *>(red);        // 16 x V values
-    uint32_t *const rmx = reinterpret_cast<uint32_t *>(rd + 16 * V);  // 16
-    uint32_t *const last = rmx + 16;
-    u64 *const fin = rd + 16 * V + 16;                   // 16 waves x 32 values
-    // The record goes past the L2 (device-coherent stores) and is complete
-    // (the wait) before the block takes its ticket; the last block reads the
-    // records with device-coherent loads.  No fences: they would write back
-    // and invalidate whole L2s while other blocks still read their copies.
-    block_record<V, W, 11, true>(v, mx, tb.partial + (uint64_t)blockIdx.x * kMom3Rec, rd, rmx);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) *last = atomicAdd(tb.ticket, 1u) == gridDim.x - 1u;
-    __syncthreads();
-    if (!*last) return;
-    // thread (g, p) adds pair p (values 2p, 2p + 1) of records g, g + 64, ...
-    const uint32_t p = threadIdx.x & 15u, g = threadIdx.x >> 4;
-    const bool m0 = 2u * p == 11u, m1 = 2u * p + 1u == 11u;
-    u64 a0 = 0, a1 = 0;
-    if (p < (uint32_t)(W + 1) / 2u) {
-      for (uint32_t r = g; r < gridDim.x; r += 64u) {
-        u64 *const q = tb.partial + (uint64_t)r * kMom3Rec + 2u * p;
-        const u64 v0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const u64 v1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a0 = m0 ? max(a0, v0) : a0 + v0;
-        a1 = m1 ? max(a1, v1) : a1 + v1;
-      }
-    }
-    // the four groups of a wave, then the 16 waves
+    const uint32_t mx = fold<NA, V>(A, v);
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int o = 16; o <= 32; o <<= 1) {
-      const u64 b0 = shfl_xor_u64(a0, o), b1 = shfl_xor_u64(a1, o);
-      a0 = m0 ? max(a0, b0) : a0 + b0;
-      a1 = m1 ? max(a1, b1) : a1 + b1;
+      for (int r = 0; r < 2 * NM; ++r) v[12 + r] = (u64)fs[r];
     }
-    const uint32_t wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63u) < 16u) {
-      fin[wave * 32u + 2u * p] = a0;
-      fin[wave * 32u + 2u * p + 1u] = a1;
+    u64 *const rd = reinterpret_cast<u64 *>(red);                     // 16 x V values
+    uint32_t *const rmx = reinterpret_cast<uint32_t *>(rd + 16 * V);  // 16
+    block_record<V, W, 11, true>(
+        v, mx, tb.records + ((uint64_t)j * gridDim.x + blockIdx.x) * kMom3Rec, rd, rmx);
+  }
+}
+
+// One launch's log j from the grid's partial records (read with
+// device-coherent loads once every block has written them): the result row
+// at tb.out + j kMom3Out, at step t.  red: LDS as for owned_pass.
+__device__ __forceinline__ void log_final(const TbLaunch &tb, uint32_t j, uint32_t t, uint32_t L,
+                                          uint4 *red) {
+  using namespace mom3;
+  const uint32_t n_modes = (tb.log - 1u) >> 1;
+  const uint32_t npairs = 6u + n_modes;  // values 0 .. 11 + 2 n_modes
+  u64 *const fin = reinterpret_cast<u64 *>(red);  // 16 waves x 32 values
+  u64 *const T = fin + 16 * 32;                   // the grid's sums
+  // thread (g, p) adds pair p (values 2p, 2p + 1) of records g, g + 64, ...
+  const uint32_t p = threadIdx.x & 15u, g = threadIdx.x >> 4;
+  const bool m0 = 2u * p == 11u, m1 = 2u * p + 1u == 11u;
+  u64 a0 = 0, a1 = 0;
+  if (p < npairs) {
+    const u64 *const base = tb.records + (uint64_t)j * gridDim.x * kMom3Rec + 2u * p;
+    for (uint32_t r = g; r < gridDim.x; r += 64u) {
+      const u64 *const q = base + (uint64_t)r * kMom3Rec;
+      const u64 v0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const u64 v1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a0 = m0 ? max(a0, v0) : a0 + v0;
+      a1 = m1 ? max(a1, v1) : a1 + v1;
     }
-    __syncthreads();
-    u64 *const T = fin + 16 * 32;  // the grid's sums, kMom3Rec values
-    if (threadIdx.x < kMom3Rec) {
-      const uint32_t k = threadIdx.x;
-      u64 t = 0;
-      for (uint32_t w = 0; w < 16u; ++w) {
-        const u64 y = fin[w * 32u + k];
-        t = k == 11u ? max(t, y) : t + y;
-      }
-      T[k] = t;
+  }
+  // the four groups of a wave, then the 16 waves
+#pragma unroll
+  for (int o = 16; o <= 32; o <<= 1) {
+    const u64 b0 = shfl_xor_u64(a0, o), b1 = shfl_xor_u64(a1, o);
+    a0 = m0 ? max(a0, b0) : a0 + b0;
+    a1 = m1 ? max(a1, b1) : a1 + b1;
+  }
+  const uint32_t wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) < 16u) {
+    fin[wave * 32u + 2u * p] = a0;
+    fin[wave * 32u + 2u * p + 1u] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMom3Rec) {
+    const uint32_t k = threadIdx.x;
+    u64 s = 0;
+    for (uint32_t w = 0; w < 16u; ++w) {
+      const u64 y = fin[w * 32u + k];
+      s = k == 11u ? max(s, y) : s + y;
     }
-    __syncthreads();
-    if (threadIdx.x < kMom3Out)
-      tb.out[threadIdx.x] = (i64)result_field(threadIdx.x, T, t0 + tb.steps, L, NM);
-    if (threadIdx.x == 0) atomicExch(tb.ticket, 0u);
+    T[k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMom3Out)
+    tb.out[(uint64_t)j * kMom3Out + threadIdx.x] = (i64)result_field(threadIdx.x, T, t, L, n_modes);
+  __syncthreads();  // (fin and T are reused by the next log)
+}
+
+// The log kinds of TbLaunch::log as instantiations of owned_pass.
+template <bool WB, bool LOG>
+__device__ __forceinline__ void owned_pass_kind(uint32_t kind, const TbLaunch &tb, Rsrc srs,
+                                                Rsrc mrs, uint32_t sab, uint32_t mab, bool active,
+                                                uint32_t L, uint32_t X0, uint32_t t0,
+                                                uint32_t done, bool ns, uint32_t j, uint4 *red) {
+  if constexpr (!LOG) {
+    owned_pass<0, false, WB, false>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red);
+  } else {
+    switch (kind) {
+      case 1: owned_pass<0, false, WB, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+      case 2: owned_pass<0, true, WB, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+      case 3: owned_pass<1, false, WB, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+      case 4: owned_pass<1, true, WB, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+      default: owned_pass<2, false, WB, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+    }
+  }
+}
+
+// A log between two steps of a blocked launch: without the digest (whose
+// mixing would make the step loop spill registers; the host ends a launch at
+// each log with the digest instead).
+__device__ __forceinline__ void log_between_steps(const TbLaunch &tb, Rsrc srs, Rsrc mrs,
+                                                  uint32_t sab, uint32_t mab, bool active,
+                                                  uint32_t L, uint32_t X0, uint32_t t0,
+                                                  uint32_t done, bool ns, uint32_t j,
+                                                  uint4 *red) {
+  switch (tb.log) {
+    case 1: owned_pass<0, false, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+    case 3: owned_pass<1, false, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
+    default: owned_pass<2, false, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, done, ns, j, red); break;
   }
 }
 
@@ -1263,21 +1335,32 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
       }
     }
     __syncthreads();  // step s is written before step s + 1 reads it
+    // a log after this step (the write-back sums the one after the last)
+    const uint32_t done = s + 1u;
+    if (!GAL && tb.n_logs && done < tb.steps && done >= tb.log_first &&
+        (done - tb.log_first) % tb.log_every == 0u)
+      log_between_steps(tb, srs, mrs, sab, mab, active, L, X0, t0, done, p.no_stream != 0,
+                        (done - tb.log_first) / tb.log_every, lds + a.lds_bytes / 16u);
   }
 
-  // (4) the owned sites back into the state at step t0 + steps (and their
-  // moments on a logging launch: two modes with the digest would spill
-  // registers, and the host sums those separately); the miss queues' LDS is
-  // free now
+  // (4) the owned sites back into the state at step t0 + steps, with the
+  // moments of a log after the last step; the miss queues' LDS is free now
   uint4 *const red = lds + a.lds_bytes / 16u;
   const bool ns = p.no_stream != 0;
-  switch (tb.log) {
-    case 1: write_back<0, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
-    case 2: write_back<0, true, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
-    case 3: write_back<1, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
-    case 4: write_back<1, true, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
-    case 5: write_back<2, false, true>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red); break;
-    default: write_back<0, false, false>(tb, srs, mrs, sab, mab, active, L, X0, t0, ns, red);
+  const uint32_t last = tb.n_logs ? tb.log_first + (tb.n_logs - 1u) * tb.log_every : 0u;
+  if (tb.n_logs && last == tb.steps)
+    owned_pass_kind<true, true>(tb.log, tb, srs, mrs, sab, mab, active, L, X0, t0, tb.steps, ns,
+                                tb.n_logs - 1u, red);
+  else
+    owned_pass_kind<true, false>(0u, tb, srs, mrs, sab, mab, active, L, X0, t0, tb.steps, ns, 0u,
+                                 red);
+  // (5) the logs: once every block's records are stored (a second barrier),
+  // block b adds logs b, b + grid, ...
+  if (tb.n_logs) {
+    __builtin_amdgcn_s_waitcnt(0);
+    grid_barrier(tb.bar, tb.bar_target + gridDim.x, a.err);
+    for (uint32_t j = blockIdx.x; j < tb.n_logs; j += gridDim.x)
+      log_final(tb, j, t0 + tb.log_first + j * tb.log_every, L, red);
   }
 }
 
@@ -1461,7 +1544,12 @@ hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLau
       tb.steps > tb.kh || tb.es != tb.R + 2u * tb.kh || tb.stride < tb.es)
     return hipErrorInvalidValue;
   if (!tb.bar) return hipErrorInvalidValue;
-  if (tb.log && (tb.log > 5u || !tb.partial || !tb.out || !tb.ticket || (tb.log >= 3u && !tb.tw)))
+  if (tb.n_logs && (tb.log < 1u || tb.log > 5u || !tb.records || !tb.out || tb.log_first < 1u ||
+                    tb.log_every < 1u || tb.log_first + (tb.n_logs - 1u) * tb.log_every > tb.steps ||
+                    (tb.log >= 3u && !tb.tw)))
+    return hipErrorInvalidValue;
+  // logs before the last step: not with the digest or the Galilean acceptance
+  if (tb.n_logs && tb.log_first < tb.steps && ((tb.log & 1u) == 0u || a.p.galilean))
     return hipErrorInvalidValue;
   const uint32_t lds = step_lds_bytes(sch, a.lds_bytes);
   StepLaunch av = a;

@@ -100,7 +100,7 @@ _SIGS = {
     "mclg_step_graph": [vp, u64],
     "mclg_moments": [vp, vp, u32, u32, P(mclg_moments_t)],
     "mclg_moments_noalloc": [vp, vp, u32, u32, vp],
-    "mclg_step_moments": [vp, u64, vp, u32, u32, vp],
+    "mclg_step_log": [vp, u64, u64, vp, u32, u32, vp],
     "mclg_histogram": [vp, u32, vp],
     "mclg_moments9": [vp, P(mclg_moments9_t)],
     "mclg_d2q9_rules": [P(u32), P(u32), P(u32)],
@@ -397,22 +397,28 @@ class Lattice:
                                           out.data_ptr()), "mclg_moments_noalloc")
         return out
 
-    def step_moments(self, n: int, out, twiddle=None, n_modes: int = 0, digest=False):
-        """mclg_step_moments: n steps, then the moments of every replica
-        written into ``out`` (as moments_to_device) in stream order, without
-        synchronising; with blocking on and n a multiple of its group, the
-        last launch sums them while it writes its sites back."""
-        tw = self._device_out(out, twiddle, n_modes)
-        _check(lib().mclg_step_moments(self.ctx, n, tw, n_modes, MOMENTS_DIGEST if digest else 0,
-                                       out.data_ptr()), "mclg_step_moments")
+    def step_log(self, every: int, n_logs: int, out, twiddle=None, n_modes: int = 0,
+                 digest=False):
+        """mclg_step_log: n_logs times `every` steps and the moments of every
+        replica after them, written into ``out`` (a contiguous int64 tensor of
+        at least n_logs * n_replicas * 33 values on the device; log j of
+        replica r is row j * n_replicas + r) in stream order, without
+        synchronising; with blocking on, each launch sums the logs that fall
+        in it."""
+        tw = self._device_out(out, twiddle, n_modes, n_logs)
+        _check(lib().mclg_step_log(self.ctx, every, n_logs, tw, n_modes,
+                                   MOMENTS_DIGEST if digest else 0, out.data_ptr()),
+               "mclg_step_log")
         return out
 
-    def _device_out(self, out, twiddle, n_modes):
-        """Checks of a device result tensor and twiddle input; the twiddle
-        pointer (0 without)."""
+    def _device_out(self, out, twiddle, n_modes, n_records=1):
+        """Checks of a device result tensor (n_records records per replica)
+        and twiddle input; the twiddle pointer (0 without)."""
         words = ct.sizeof(mclg_moments_t) // 8
-        if out.dtype != self.torch.int64 or out.numel() < words * self.n or not out.is_contiguous():
-            raise ValueError("out must be a contiguous int64 tensor of n_replicas * 33 values")
+        if out.dtype != self.torch.int64 or out.numel() < words * self.n * n_records or \
+                not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of records * n_replicas * 33 "
+                             "values")
         if twiddle is None:
             return 0
         if twiddle.numel() < 2 * n_modes * int(self.L.sum()) or twiddle.element_size() != 4:

@@ -1,10 +1,12 @@
-"""Steps followed by the moments of the state they reach, in one call
-(mclg_step_moments): with several steps per launch the last launch sums the
-moments of the sites it writes back.  Every record equals plain numpy sums of
-the counts read back at the same step (and the state digest), and the state
-stays equal to the oracle's; calls that fall back to the separate moment
-kernels (steps not a multiple of the group, two modes with the digest, no
-blocking, several replicas) give the same records."""
+"""The logging loop in one call (mclg_step_log): n_logs times `every` steps
+and the moments of the state they reach.  With several steps per launch each
+launch sums the logs that fall in it from the blocks' copies (the last one as
+it writes the sites back).  Every record equals plain numpy sums of the
+oracle's counts at the same step (and the state digest), and the state stays
+equal to the oracle's; logs between a launch's steps, at its end, several per
+launch, one per several launches, launches cut at the logs (digest, Galilean
+acceptance) and the fallback to the separate moment kernels (two modes with
+the digest, no blocking, several replicas) are all covered."""
 import ctypes as ct
 import sys
 
@@ -14,13 +16,14 @@ import pytest
 import oracle as O
 import synth
 from paper_1706_01094_amd import mclg as M
-from paper_1706_01094_amd.mclg import Lattice
+from paper_1706_01094_amd.mclg import FLAG_GALILEAN, Lattice
 from tests.state_digest import digest
 from tests.test_gpu_moments import plain_moments
 
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("sites", "sum_n", "sum_n2", "sum_nn", "sum_N", "sum_J", "sum_N2", "n0_odd", "max_N")
+WORDS = ct.sizeof(M.mclg_moments_t) // 8
 
 
 def say(*a):
@@ -28,16 +31,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def records(lat, out):
+def records(lat, out, n):
     lat.stream.synchronize()
-    host = np.ascontiguousarray(out.cpu().numpy())
-    return [M.mclg_moments_t.from_buffer_copy(host[r].tobytes()).as_dict() for r in range(lat.n)]
+    host = np.ascontiguousarray(out.cpu().numpy()).reshape(-1, WORDS)
+    return [M.mclg_moments_t.from_buffer_copy(host[k].tobytes()).as_dict() for k in range(n)]
 
 
-def new_out(lat):
+def new_out(lat, n_logs):
     import torch
-    words = ct.sizeof(M.mclg_moments_t) // 8
-    return torch.full((lat.n, words), -1, dtype=torch.int64, device=lat.device)
+    return torch.full((n_logs * lat.n, WORDS), -1, dtype=torch.int64, device=lat.device)
 
 
 def expect(have, c, tw, n_modes, dig, t, what):
@@ -50,38 +52,52 @@ def expect(have, c, tw, n_modes, dig, t, what):
     assert have["t"] == t, (what, "t", have["t"], t)
 
 
-@pytest.mark.parametrize("L,K", [(1 << 17, 4), ((1 << 17) + 8, 8), (3 * (1 << 16) + 8 * 37, 5)])
-def test_step_moments_blocked_equal_plain_sums_and_oracle(L, K):
-    """Every mode count and digest flag, at lattices where every block owns
-    sites and where the last blocks own none (2^17 + 8 sites); calls of one
-    group, of several groups, and one not a multiple of the group."""
+def run_against_oracle(L, K, calls, seed=83, flags=0, lam=(1, 1)):
     import torch
-    say("case", dict(L=L, K=K))
-    g = Lattice(L, 83, C=10, rho=20.0, u0=0.1)
+    say("case", dict(L=L, K=K, calls=calls, flags=flags))
+    g = Lattice(L, seed, C=10, lam=lam, rho=20.0, u0=0.1, flags=flags)
     g.set_blocked(K)
-    o = O.OracleSim([L], 83, C=10)
+    o = O.OracleSim([L], seed, C=10, lam=lam, flags=flags)
     o.init_poisson(0, 20.0, 0.1)
     tw = synth.twiddles(L, 2)
     twd = torch.as_tensor(np.ascontiguousarray(tw.reshape(-1))).to(g.device)
     g.stream.wait_stream(torch.cuda.current_stream(g.device))
     t = 0
-    for n, n_modes, dig in ((K, 0, False), (2 * K, 1, False), (K, 2, False), (K, 0, True),
-                            (3 * K, 1, True), (K, 2, True), (K + 1, 1, False), (K, 1, False)):
-        out = new_out(g)
-        g.step_moments(n, out, twd[: 2 * n_modes * L] if n_modes else None, n_modes, digest=dig)
-        t += n
-        rec = records(g, out)[0]
-        o.step(n)
-        c = g.counts(0)
-        assert np.array_equal(c, o.counts(0)), ("state", t)
-        expect(rec, c, tw, n_modes, dig, t, (L, K, n, n_modes, dig))
+    for every, n_logs, n_modes, dig in calls:
+        out = new_out(g, n_logs)
+        g.step_log(every, n_logs, out, twd[: 2 * n_modes * L] if n_modes else None, n_modes,
+                   digest=dig)
+        recs = records(g, out, n_logs)
+        for j in range(n_logs):
+            o.step(every)
+            t += every
+            expect(recs[j], o.counts(0), tw, n_modes, dig, t, (L, K, every, n_logs, n_modes, dig, j))
+        assert np.array_equal(g.counts(0), o.counts(0)), ("state", t)
     g.close()
     o.close()
 
 
-def test_step_moments_without_blocking_and_several_replicas():
+@pytest.mark.parametrize("L,K", [(1 << 17, 8), ((1 << 17) + 8, 12), (3 * (1 << 16) + 8 * 37, 5)])
+def test_step_log_blocked_equal_oracle(L, K):
+    """Logs between a launch's steps (every < K), at its end (every = K), not
+    aligned with launches (every not dividing K), one per several launches
+    (every > K), with 0, 1 and 2 modes; the digest (launches cut at the
+    logs) and two modes with the digest (the separate moment kernels); at
+    lattices where every block owns sites and where the last blocks own none
+    (2^17 + 8 sites)."""
+    run_against_oracle(L, K, [(2, 5, 1, False), (K, 2, 0, False), (3, 7, 2, False),
+                              (K + 3, 2, 1, False), (1, 3, 0, False), (3, 4, 1, True),
+                              (K, 1, 0, True), (2, 3, 2, True)])
+
+
+def test_step_log_galilean_cuts_launches_at_logs():
+    run_against_oracle(1 << 17, 8, [(3, 5, 1, False), (8, 2, 0, False)], seed=85,
+                       flags=FLAG_GALILEAN, lam=(3, 4))
+
+
+def test_step_log_without_blocking_and_several_replicas():
     """The fallback path: several replicas (no blocking possible), three
-    modes."""
+    modes, against numpy's sums of the counts read back after each call."""
     import torch
     Ls = [4099, 33000, 7]
     g = Lattice(Ls, 5, rho=[10.0, 40.0, 3.0], u0=[0.0, 0.1, -0.2])
@@ -89,21 +105,21 @@ def test_step_moments_without_blocking_and_several_replicas():
     twd = torch.as_tensor(np.concatenate([w.reshape(-1) for w in tw])).to(g.device)
     g.stream.wait_stream(torch.cuda.current_stream(g.device))
     t = 0
-    for n, dig in ((3, False), (5, True)):
-        out = new_out(g)
-        g.step_moments(n, out, twd, 3, digest=dig)
-        t += n
-        recs = records(g, out)
+    for every, dig in ((3, False), (5, True)):
+        out = new_out(g, 1)
+        g.step_log(every, 1, out, twd, 3, digest=dig)
+        t += every
+        recs = records(g, out, len(Ls))
         for r, L in enumerate(Ls):
-            expect(recs[r], g.counts(r), tw[r], 3, dig, t, (r, n, dig))
+            expect(recs[r], g.counts(r), tw[r], 3, dig, t, (r, every, dig))
     g.close()
 
 
-def test_step_moments_density_wave_full_size():
-    """The L = 2^22 density wave, 10 steps per launch, one mode logged every
-    10 steps for 300 steps: every record equals the separate moments call on
-    a second lattice stepped alongside, and the last one equals numpy's sums
-    of the counts."""
+def test_step_log_density_wave_full_size():
+    """The L = 2^22 density wave, 100 steps per launch (ten logs in each),
+    one mode every 10 steps for 300 steps: every record equals the separate
+    moments call on a second lattice stepped 10 steps at a time, and the last
+    one equals numpy's sums of the counts."""
     import torch
     w = synth.DENSITY_WAVE
     L = w["L"]
@@ -111,36 +127,35 @@ def test_step_moments_density_wave_full_size():
     tw = synth.twiddles(L, 1)
     a = Lattice(L, w["seed"], counts=counts)
     b = Lattice(L, w["seed"], counts=counts)
-    a.set_blocked(10)
+    a.set_blocked(100)
     b.set_blocked(10)
     twd = torch.as_tensor(np.ascontiguousarray(tw.reshape(-1))).to(a.device)
     a.stream.wait_stream(torch.cuda.current_stream(a.device))
     b.stream.wait_stream(torch.cuda.current_stream(b.device))
     n = 30
-    ra, rb = new_out(a), new_out(b)
-    words = ra.shape[1]
-    la = torch.zeros((n, words), dtype=torch.int64, device=a.device)
-    lb = torch.zeros((n, words), dtype=torch.int64, device=b.device)
+    la = new_out(a, n)
+    lb = torch.zeros((n, WORDS), dtype=torch.int64, device=b.device)
+    a.step_log(10, n, la, twd, 1)
     for k in range(n):
-        a.step_moments(10, la[k], twd, 1)
         b.step(10)
         b.moments_to_device(lb[k], twd, 1)
     a.stream.synchronize()
     b.stream.synchronize()
     assert torch.equal(la.cpu(), lb.cpu())
-    rec = M.mclg_moments_t.from_buffer_copy(np.ascontiguousarray(la[-1].cpu().numpy()).tobytes())
-    expect(rec.as_dict(), a.counts(0), tw, 1, False, 10 * n, "wave")
+    rec = records(a, la, n)[-1]
+    expect(rec, a.counts(0), tw, 1, False, 10 * n, "wave")
     a.close()
     b.close()
 
 
-def test_step_moments_refuses_bad_arguments():
+def test_step_log_refuses_bad_arguments():
     g = Lattice(1 << 17, 3, rho=5.0, u0=0.0)
     g.set_blocked(4)
-    out = new_out(g)
-    for args in ((4, 0, 1, 0), (4, 0, 9, 0), (4, 0, 0, 2)):  # no twiddles, 9 modes, bad flag
-        rc = M.lib().mclg_step_moments(g.ctx, args[0], args[1], args[2], args[3], out.data_ptr())
-        assert rc == M.E_INVAL, args
-    rc = M.lib().mclg_step_moments(g.ctx, 4, 0, 0, 0, 0)
-    assert rc == M.E_INVAL
+    out = new_out(g, 2)
+    f = M.lib().mclg_step_log
+    for every, n_modes, flags in ((4, 1, 0), (4, 9, 0), (4, 0, 2), (0, 0, 0)):
+        # no twiddles, 9 modes, an unknown flag, every = 0
+        assert f(g.ctx, every, 2, 0, n_modes, flags, out.data_ptr()) == M.E_INVAL
+    assert f(g.ctx, 4, 2, 0, 0, 0, 0) == M.E_INVAL
+    assert f(g.ctx, 1 << 40, 1 << 40, 0, 0, 0, out.data_ptr()) == M.E_INVAL
     g.close()

@@ -217,13 +217,31 @@ def run_probe(args, torch, M):
     L = 1 << 27
     lat = M.Lattice(L, w["seed"], C=10, lam=(1, 1), n_max=255, rho=w["rho"], u0=w["u0"])
     lat.step(5)
-    torch.cuda.synchronize()
-    e0, e1 = _events(torch, lat.stream)
-    e0.record(lat.stream)
-    lat.step(args.probe_steps)
-    e1.record(lat.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.probe_steps
+
+    def timed(steps):
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, lat.stream)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # one step per launch: the kernel streams the state from HBM at every step
+    ms = timed(args.probe_steps)
+    blocked = None
+    K = args.probe_blocked
+    if K > 1:
+        # several steps per launch in tiles whose copies stay in the L2: the
+        # state is read and written once per launch
+        lat.set_blocked(K)
+        lat.step(K)
+        n = max(1, args.probe_steps // K) * K
+        bms = timed(n)
+        ach = BYTES_PER_SITE_UPDATE * L / (bms / 1e3) / 1e9
+        blocked = {"steps_per_launch": K, "steps": n, "ms_per_step": bms,
+                   "site_updates_per_s": L / (bms / 1e3), "achieved_GBps": ach,
+                   "frac": ach / HBM_PEAK_GBS}
     rc = lat.check()
     lat.close()
     if rc != 0:
@@ -237,7 +255,8 @@ def run_probe(args, torch, M):
             "traffic": traffic,
             "traffic_over_algorithmic": None if traffic is None else
             traffic / (BYTES_PER_SITE_UPDATE * L),
-            "valu_issue_frac": valu_issue_frac("probe", ms / 1e3)}
+            "valu_issue_frac": valu_issue_frac("probe", ms / 1e3),
+            "blocked": blocked}
 
 
 def sk_twiddles(torch, Ls, n_modes: int, device):
@@ -586,6 +605,9 @@ def main():
                     help="steps per launch of the L = 2^24 workload (temporal blocking; 1: off)")
     ap.add_argument("--single-steps", type=int, default=2000,
                     help="steps of the one-step-per-launch comparison of the blocked run")
+    ap.add_argument("--probe-blocked", type=int, default=64,
+                    help="steps per launch of the L = 2^27 probe's blocked run, in tiles "
+                         "(1: off)")
     ap.add_argument("--wave-blocked", type=int, default=250,
                     help="steps per launch of the density wave (each launch sums the logs "
                          "that fall in it; 1: off)")

@@ -528,11 +528,16 @@ static int step_range(mclg_ctx *c, uint32_t tile_lo, uint32_t tile_hi, uint32_t 
 
 // The geometry of `steps` steps per launch for the context's one lattice:
 // every block of the grid resident at once, R owned sites per block (a
-// multiple of 8), kh = steps rounded up to 8 extra sites on each side.  The
-// scratch holds the blocks' copies, then the partial records of up to
-// `steps` logs per launch (records_at bytes in).
-static int blocked_geometry(mclg_ctx *c, uint32_t steps, TbLaunch &tb, uint32_t &grid,
-                            uint64_t &bytes, uint64_t &records_at) {
+// multiple of 8), kh = steps rounded up to 8 extra sites on each side.
+// Whole regions: each block's copy holds its R + 2 kh sites; tiles: copies
+// of `tile` sites, T = tile - 2 kh of them the tile's own (tile = 0 picks
+// whole regions while all copies fit kTbCachedCopies bytes, else tiles of
+// kTbTileSites).  The scratch holds the blocks' areas, then the partial
+// records of up to `steps` logs per launch (records_at bytes in).
+constexpr uint64_t kTbCachedCopies = 128ull << 20;
+constexpr uint32_t kTbTileSites = 65536;  // 128 chunks of 512: 100 MB of copies in all
+static int blocked_geometry(mclg_ctx *c, uint32_t steps, uint32_t tile, TbLaunch &tb,
+                            uint32_t &grid, uint64_t &bytes, uint64_t &records_at) {
   if (c->d2) return MCLG_E_UNSUPPORTED;
   if (steps < 2 || steps > kTbMaxSteps) return MCLG_E_INVAL;
   if (c->n != 1 || c->L[0] % 8 != 0 || c->sch.threads != 1024) return MCLG_E_UNSUPPORTED;
@@ -544,27 +549,40 @@ static int blocked_geometry(mclg_ctx *c, uint32_t steps, TbLaunch &tb, uint32_t 
   TbLaunch t;
   t.R = (uint32_t)(((L + g - 1) / g + 7) / 8 * 8);
   t.kh = (steps + 7u) / 8u * 8u;
-  t.es = t.R + 2u * t.kh;
-  t.stride = (t.es + 63u) / 64u * 64u;
   t.steps = steps;
+  if (tile == 0)
+    tile = (uint64_t)g * (t.R + 2u * t.kh) * 6u > kTbCachedCopies ? kTbTileSites : 1u;
+  if (tile == 1) {
+    t.es = t.R + 2u * t.kh;
+    t.stride = (t.es + 63u) / 64u * 64u;
+    t.bstride = 3ull * t.stride;
+  } else {
+    if (tile % 8u != 0 || tile <= 2u * t.kh || tile > (1u << 20)) return MCLG_E_INVAL;
+    t.T = tile - 2u * t.kh;
+    t.es = tile;
+    t.stride = (t.es + 63u) / 64u * 64u;
+    t.bstride = align_up(3ull * t.stride + 18ull * t.kh, 128);
+    if (2ull * t.bstride * g >= (1ull << 31)) return MCLG_E_UNSUPPORTED;
+  }
   // the copy's random-number keys wrap around the lattice at most once
   if ((uint64_t)t.es + 512u > L) return MCLG_E_UNSUPPORTED;
   tb = t;
   grid = g;
-  records_at = align_up((uint64_t)g * 3u * t.stride * sizeof(uint16_t), 256);
+  records_at = align_up((uint64_t)g * t.bstride * sizeof(uint16_t), 256);
   bytes = records_at + (uint64_t)steps * g * kMom3Rec * sizeof(uint64_t);
   return MCLG_OK;
 }
 
-int mclg_blocked_bytes(mclg_ctx *c, uint32_t steps, uint64_t *scratch_bytes) {
+int mclg_blocked_bytes(mclg_ctx *c, uint32_t steps, uint32_t tile, uint64_t *scratch_bytes) {
   if (!c || !scratch_bytes) return MCLG_E_INVAL;
   TbLaunch tb;
   uint32_t grid = 0;
   uint64_t records_at = 0;
-  return blocked_geometry(c, steps, tb, grid, *scratch_bytes, records_at);
+  return blocked_geometry(c, steps, tile, tb, grid, *scratch_bytes, records_at);
 }
 
-int mclg_set_blocked(mclg_ctx *c, uint32_t steps, void *scratch, uint64_t scratch_bytes) {
+int mclg_set_blocked(mclg_ctx *c, uint32_t steps, uint32_t tile, void *scratch,
+                     uint64_t scratch_bytes) {
   if (!c) return MCLG_E_INVAL;
   if (c->d2) return MCLG_E_UNSUPPORTED;
   if (steps <= 1) {
@@ -575,7 +593,7 @@ int mclg_set_blocked(mclg_ctx *c, uint32_t steps, void *scratch, uint64_t scratc
   TbLaunch tb;
   uint32_t grid = 0;
   uint64_t need = 0, records_at = 0;
-  int rc = blocked_geometry(c, steps, tb, grid, need, records_at);
+  int rc = blocked_geometry(c, steps, tile, tb, grid, need, records_at);
   if (rc) return rc;
   if (!scratch || scratch_bytes < need) return MCLG_E_INVAL;
   tb.scratch = static_cast<uint16_t *>(scratch);
@@ -731,7 +749,7 @@ int mclg_step_log(mclg_ctx *c, uint64_t every, uint64_t n_logs, const int32_t *t
     return MCLG_E_INVAL;
   const uint32_t dig = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
   const uint32_t K = c->tb.steps;
-  if (!(K > 1 && n_modes <= 2 && !(n_modes == 2 && dig))) {
+  if (!(K > 1 && c->tb.T == 0 && n_modes <= 2 && !(n_modes == 2 && dig))) {
     // steps, then the moment kernels, per log (partial sums in the workspace)
     unsigned long long *part = reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart);
     for (uint64_t j = 0; j < n_logs; ++j) {

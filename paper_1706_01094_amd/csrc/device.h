@@ -162,12 +162,18 @@ hipError_t launch_step(const Schedule &sch, hipStream_t s, const StepLaunch &a);
 // blocks have all arrived when it reaches bar_target.
 constexpr uint32_t kTbMaxSteps = 256;
 struct TbLaunch {
-  uint16_t *scratch = nullptr;  // grid x 3 x stride elements
+  uint16_t *scratch = nullptr;  // grid x bstride elements
   uint32_t stride = 0;          // elements per array of a block's copy (>= es)
   uint32_t R = 0;               // owned sites per block (a multiple of 8)
   uint32_t kh = 0;              // extra sites on each side (a multiple of 8)
   uint32_t es = 0;              // R + 2 kh
   uint32_t steps = 0;           // steps of the launch
+  // Tiles (T > 0, for lattices whose blocks' copies would not stay in the
+  // caches): block b goes through its region in tiles of T sites, each copied
+  // with kh extra sites on each side (es = T + 2 kh) into the copy area,
+  // advanced `steps` steps and written back before the next; see k_step_tt.
+  uint32_t T = 0;
+  uint64_t bstride = 0;         // elements of scratch per block
   uint32_t *bar = nullptr;      // arrivals of every blocked launch of the context
   uint32_t bar_target = 0;      // arrivals before this launch + its grid
   // Logs (n_logs > 0): the moments (mclg_moments_t) of the state after steps

@@ -229,6 +229,9 @@ constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
 // states that do not fit the caches: non-temporal, the lines are not
 // expected to be reused before they leave).
 constexpr int kStreamingPolicy = 2;  // nt
+// sc1: coherent across the device's L2s (data another block reads in the
+// same launch)
+constexpr int kDevicePolicy = 16;
 template <int CP = 0>
 __device__ __forceinline__ void bload4(Rsrc r, uint32_t voff, uint32_t soff, uint32_t (&v)[4]) {
   const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CP);
@@ -1264,7 +1267,7 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
   const bool active = X0 < L;
   const uint32_t xoff = X0 >= tb.kh ? X0 - tb.kh : X0 + L - tb.kh;  // site of copy index 0
   uint16_t *const main_m = a.state + sl.off;
-  uint16_t *const scr = tb.scratch + (uint64_t)blockIdx.x * 3ull * tb.stride;
+  uint16_t *const scr = tb.scratch + (uint64_t)blockIdx.x * tb.bstride;
   const uint32_t es = tb.es;
 
   // (1) the region and its extra sites at step t0, in logical order, eight
@@ -1361,6 +1364,213 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
     grid_barrier(tb.bar, tb.bar_target + gridDim.x, a.err);
     for (uint32_t j = blockIdx.x; j < tb.n_logs; j += gridDim.x)
       log_final(tb, j, t0 + tb.log_first + j * tb.log_every, L, red);
+  }
+}
+
+// Several steps per launch in tiles (TbLaunch::T > 0), for lattices whose
+// blocks' whole copies would stream from memory at every step.  Block b owns
+// the sites [X0, end) = [b R, min(L, b R + R)) and goes through them in
+// tiles of T sites from left to right: tile [a, a + n) is copied with kh
+// extra sites on each side into the copy area (es = n + 2 kh sites, which
+// stay in the L2 while they are stepped), advanced `steps` steps as in
+// k_step_tb, and written back at step t + steps before the next tile.
+// Every site a tile reads is at step t: its own sites and the extra sites
+// on its right that lie in the block's region are not written yet; the
+// extra sites on its left were written back with the previous tile, so
+// that tile kept them (at step t) in a carry area; extra sites in other
+// blocks' regions come from the side areas, where each block put its
+// region's first and last kh sites before the grid-wide barrier (with
+// device-coherent stores and loads: the barrier has no fence).
+// Per-block scratch (elements): the copy (3 x stride), two carry areas (3 x
+// 2 kh each) and the two side areas (3 x kh each).
+template <int MAXT, bool GAL>
+__global__ void __launch_bounds__(MAXT) k_step_tt(StepLaunch a, TbLaunch tb) {
+  constexpr int MODE = kDrainDeferred;
+  extern __shared__ uint4 lds[];
+  const StepParams &p = a.p;
+  const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
+  const uint32_t lane = threadIdx.x & 63u, nwaves = blockDim.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
+  uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
+  const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
+  uint32_t F = 0;
+  const bool youngest = nwaves >= 8u && wave + 4u >= nwaves;
+  const bool second = nwaves >= 12u && wave + 8u >= nwaves && !youngest;
+  uint32_t *const ctl =
+      reinterpret_cast<uint32_t *>(lds + a.lds_bytes / 16u + nwaves * (kWaveLdsBytes / 16u));
+  uint32_t &next_chunk = ctl[0];
+
+  const SlotDev sl = a.sl1;
+  const ImageDesc im = a.im1;
+  const uint32_t L = sl.L, kh = tb.kh;
+  const uint32_t t0 = __builtin_amdgcn_readfirstlane(a.tslot[a.slot_first] + a.t_off);
+  const uint32_t nact = (L + tb.R - 1u) / tb.R;  // blocks that own sites
+  const uint32_t X0 = blockIdx.x * tb.R;
+  const bool active = blockIdx.x < nact;
+  const uint32_t end = active ? min(L, X0 + tb.R) : X0;
+  const uint32_t pb = blockIdx.x > 0u ? blockIdx.x - 1u : nact - 1u;  // neighbours' areas
+  const uint32_t nb = blockIdx.x + 1u < nact ? blockIdx.x + 1u : 0u;
+  uint16_t *const main_m = a.state + sl.off;
+  const uint32_t mab = 2u * sl.stride, sab = 2u * tb.stride;
+  const Rsrc mrs = __builtin_amdgcn_make_buffer_rsrc(main_m, 0, (int)(3u * mab), kRsrcWord3);
+  uint16_t *const scr = tb.scratch + (uint64_t)blockIdx.x * tb.bstride;
+  // the block's whole scratch (the copy and the small areas after it)
+  const Rsrc srs = __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(2u * tb.bstride), kRsrcWord3);
+  // a block's small areas, as byte offsets from its scratch: carry c (2 kh
+  // sites, array i at + 4 kh i), the region's first and last kh sites (array
+  // i at + 2 kh i)
+  const uint32_t kc = 12u * kh, ks = 6u * kh;  // bytes per carry, per side area
+  auto carry_at = [&](uint32_t c) { return 3u * sab + c * kc; };
+  const uint32_t first_at = 3u * sab + 2u * kc, last_at = first_at + ks;
+  const Rsrc all = __builtin_amdgcn_make_buffer_rsrc(tb.scratch, 0, 0x7fffffff, kRsrcWord3);
+  const uint64_t area_bytes = 2ull * tb.bstride;
+  const uint32_t tm = p.no_stream ? 0u : t0 % L;
+
+  // (1) the region's first and last kh sites at step t0 into the side areas
+  if (active) {
+    for (uint32_t i = 8u * threadIdx.x; i < 2u * kh; i += 8u * blockDim.x) {
+      const bool last = i >= kh;
+      const uint32_t o = last ? i - kh : i;
+      uint32_t x = last ? end + L - kh + o : X0 + o;
+      x -= x >= L ? L : 0u;
+      x -= x >= L ? L : 0u;
+      uint32_t pm = x + tm;
+      pm -= pm >= L ? L : 0u;
+      const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+      uint32_t m[4], z[4], q[4];
+      load8_wrap(mrs, 0u, pm, L, m);
+      load8_wrap(mrs, mab, x, L, z);
+      load8_wrap(mrs, 2u * mab, pp, L, q);
+      const uint32_t at = (last ? last_at : first_at) + 2u * o;
+      bstore4<kDevicePolicy>(srs, at, 0u, m);
+      bstore4<kDevicePolicy>(srs, at, 2u * kh, z);
+      bstore4<kDevicePolicy>(srs, at, 4u * kh, q);
+    }
+  }
+  // the side areas are complete before this block arrives at the barrier
+  __builtin_amdgcn_s_waitcnt(0);
+  LdsView lv;
+  {
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
+    const uint32_t n16 = im.bytes / 16u, bd = blockDim.x;
+    for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += bd) lds[b0] = src[b0];
+    lv.da2 = im.dim_a * 0x10001u;
+    lv.dc2 = im.dim_c * 0x10001u;
+    lv.w2 = (im.dim_c + 1u) * 0x10001u;
+    lv.blo2 = im.b_lo * 0x10001u;
+    lv.nb2 = im.nb * 0x10001u;
+  }
+  // (2) every block's side areas are written and every block has read its
+  // step counter before any block writes the state
+  grid_barrier(tb.bar, tb.bar_target, a.err);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.tslot[a.slot_first] += tb.steps;
+  if (!active) return;
+
+  SlotView sv;
+  const uint64_t base = reinterpret_cast<uint64_t>(scr);
+  sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  sv.ab = sab;
+  sv.rid = sl.rid;
+  sv.lg = L;
+  const uint32_t pbo = (uint32_t)((uint64_t)pb * area_bytes), nbo = (uint32_t)((uint64_t)nb * area_bytes);
+  uint32_t c = 0;
+  for (uint32_t x0 = X0; x0 < end; x0 += tb.T, c ^= 1u) {
+    const uint32_t n = min(tb.T, end - x0), es = n + 2u * kh;
+    const uint32_t xoff = x0 >= kh ? x0 - kh : x0 + L - kh;  // site of copy index 0
+    // (3) the tile and its extra sites at step t0, eight sites per thread.
+    // A write-back at step t0 + steps moves the n_-1 of sites up to `steps`
+    // to the right of the written ones and the n_+1 of sites up to `steps`
+    // to their left (in-place shifted layout), so what earlier tiles, and
+    // the neighbouring blocks, may have written over is taken from copies
+    // made before: copy index i < 2 kh (sites within kh of the tile's
+    // start) from the previous tile's carry, or for the first tile from the
+    // side areas; sites within kh of the region's end from its side area;
+    // sites past it from the next block's.  Copy indices [n, n + 2 kh) also
+    // go into carry c for the next tile.
+    for (uint32_t i = 8u * threadIdx.x; i < es; i += 8u * blockDim.x) {
+      uint32_t m[4], z[4], q[4];
+      const uint32_t y = x0 + i;  // the site plus kh, unwrapped
+      uint32_t at = 0, ah = 0;    // an area: byte offset, bytes per array
+      bool area = true, dev = false;
+      if (x0 != X0 && i < 2u * kh) {
+        at = carry_at(c ^ 1u) + 2u * i;
+        ah = 4u * kh;
+      } else if (x0 == X0 && i < kh) {
+        dev = true;  // the previous block's last sites (another block's area)
+        at = pbo + last_at + 2u * i;
+        ah = 2u * kh;
+      } else if (x0 == X0 && i < 2u * kh) {
+        at = first_at + 2u * (i - kh);
+        ah = 2u * kh;
+      } else if (y - kh >= end) {
+        dev = true;  // the next block's first sites
+        at = nbo + first_at + 2u * (y - kh - end);
+        ah = 2u * kh;
+      } else if (y >= end) {
+        at = last_at + 2u * (y - end);  // (y - kh) - (end - kh)
+        ah = 2u * kh;
+      } else {
+        area = false;
+      }
+      if (!area) {
+        uint32_t x = y - kh;
+        x -= x >= L ? L : 0u;
+        uint32_t pm = x + tm;
+        pm -= pm >= L ? L : 0u;
+        const uint32_t pp = x >= tm ? x - tm : x + L - tm;
+        load8_wrap(mrs, 0u, pm, L, m);
+        load8_wrap(mrs, mab, x, L, z);
+        load8_wrap(mrs, 2u * mab, pp, L, q);
+      } else if (dev) {
+        bload4<kDevicePolicy>(all, at, 0u, m);
+        bload4<kDevicePolicy>(all, at, ah, z);
+        bload4<kDevicePolicy>(all, at, 2u * ah, q);
+      } else {
+        bload4(srs, at, 0u, m);
+        bload4(srs, at, ah, z);
+        bload4(srs, at, 2u * ah, q);
+      }
+      bstore4(srs, 2u * i, 0u, m);
+      bstore4(srs, 2u * i, sab, z);
+      bstore4(srs, 2u * i, 2u * sab, q);
+      if (i >= n) {
+        const uint32_t cat = carry_at(c) + 2u * (i - n);
+        bstore4(srs, cat, 0u, m);
+        bstore4(srs, cat, 4u * kh, z);
+        bstore4(srs, cat, 8u * kh, q);
+      }
+    }
+    __syncthreads();
+    // (4) the steps on the tile's copy: a periodic lattice of es sites
+    sv.L = es;
+    sv.xoff = xoff;
+    const uint32_t nch = (es + 511u) / 512u;
+    for (uint32_t s = 0; s < tb.steps; ++s) {
+      sv.t = t0 + s;
+      sv.tm = p.no_stream ? 0u : s % es;
+      const uint32_t k = min(wave, nch);
+      if (threadIdx.x == 0) next_chunk = nwaves;
+      const Win cw = locate(k * 512u, sv);
+      Raw cr;
+      if (k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
+      __syncthreads();  // the counter is reset
+      run_segment<GAL, MODE, true>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+      if (F) {
+        drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
+        F = 0;
+      }
+      __syncthreads();  // step s is written before step s + 1 reads it
+    }
+    // (5) the tile back into the state at step t0 + steps
+    TbLaunch tt = tb;
+    tt.R = n;
+    tt.es = es;
+    owned_pass<0, false, true, false>(tt, srs, mrs, sab, mab, true, L, x0, t0, tb.steps,
+                                      p.no_stream != 0, 0u, nullptr);
+    __syncthreads();  // the copy area is read before the next tile fills it
   }
 }
 
@@ -1514,13 +1724,13 @@ static void launch_mode(dim3 grid, dim3 block, uint32_t lds, hipStream_t s, cons
   }
 }
 
-template <bool GAL>
-static hipError_t blocked_occupancy_one(uint32_t lds, int &blocks) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_step_tb<1024, GAL>),
+template <typename K>
+static hipError_t blocked_occupancy_one(K kernel, uint32_t lds, int &blocks) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
   int b = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_step_tb<1024, GAL>, 1024, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, 1024, lds);
   blocks = std::min(blocks, b);
   return e;
 }
@@ -1530,8 +1740,10 @@ hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint3
   if (sch.groups != 1 || sch.threads != 1024) return hipErrorInvalidValue;
   const uint32_t lds = step_lds_bytes(sch, lds_bytes);
   int b = 1 << 30;
-  hipError_t e = blocked_occupancy_one<false>(lds, b);
-  if (!e) e = blocked_occupancy_one<true>(lds, b);
+  hipError_t e = blocked_occupancy_one(k_step_tb<1024, false>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tb<1024, true>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tt<1024, false>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tt<1024, true>, lds, b);
   if (e) return e;
   if (b < 1) return hipErrorInvalidConfiguration;
   max_blocks = (uint32_t)b * n_cu;
@@ -1541,7 +1753,13 @@ hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint3
 hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
                                const TbLaunch &tb, uint32_t grid) {
   if (sch.groups != 1 || sch.threads != 1024 || !a.single || tb.steps == 0 ||
-      tb.steps > tb.kh || tb.es != tb.R + 2u * tb.kh || tb.stride < tb.es)
+      tb.steps > tb.kh || tb.stride < tb.es || tb.bstride < 3ull * tb.stride ||
+      tb.es != (tb.T ? tb.T : tb.R) + 2u * tb.kh)
+    return hipErrorInvalidValue;
+  // tiles: the copy area, two carries and two side areas per block, each
+  // block's areas addressed with 32-bit byte offsets; no logs
+  if (tb.T && (tb.bstride < 3ull * tb.stride + 18ull * tb.kh ||
+               2ull * tb.bstride * grid >= (1ull << 31) || tb.n_logs))
     return hipErrorInvalidValue;
   if (!tb.bar) return hipErrorInvalidValue;
   if (tb.n_logs && (tb.log < 1u || tb.log > 5u || !tb.records || !tb.out || tb.log_first < 1u ||
@@ -1555,8 +1773,10 @@ hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLau
   StepLaunch av = a;
   TbLaunch tv = tb;
   void *args[] = {&av, &tv};
-  const void *f = a.p.galilean ? reinterpret_cast<const void *>(k_step_tb<1024, true>)
-                               : reinterpret_cast<const void *>(k_step_tb<1024, false>);
+  const void *f = tb.T ? (a.p.galilean ? reinterpret_cast<const void *>(k_step_tt<1024, true>)
+                                       : reinterpret_cast<const void *>(k_step_tt<1024, false>))
+                       : (a.p.galilean ? reinterpret_cast<const void *>(k_step_tb<1024, true>)
+                                       : reinterpret_cast<const void *>(k_step_tb<1024, false>));
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(1024), args, lds, s);
 }
 

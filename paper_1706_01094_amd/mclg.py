@@ -109,8 +109,8 @@ _SIGS = {
     "mclg_set_schedule": [vp, u32, u32, u32],
     "mclg_set_grid_limit": [vp, u32],
     "mclg_set_drain": [vp, u32],
-    "mclg_blocked_bytes": [vp, u32, P(u64)],
-    "mclg_set_blocked": [vp, u32, vp, u64],
+    "mclg_blocked_bytes": [vp, u32, u32, P(u64)],
+    "mclg_set_blocked": [vp, u32, u32, vp, u64],
     "mclg_lds_coverage": [vp, P(dbl), P(u32)],
     "mclg_destroy": [vp],
     "mclg_strerror": [ct.c_int],
@@ -350,18 +350,19 @@ class Lattice:
     def set_drain(self, policy: int):
         mclg_set_drain(self.ctx, policy)
 
-    def set_blocked(self, steps: int):
-        """mclg_set_blocked: `steps` steps per launch (temporal blocking),
-        with a scratch tensor of this lattice's device owned here; steps <= 1
-        switches it off."""
+    def set_blocked(self, steps: int, tile: int = 0):
+        """mclg_set_blocked: `steps` steps per launch (temporal blocking) on
+        whole block ranges (tile = 1) or in tiles of `tile` sites (>= 2;
+        0 picks), with a scratch tensor of this lattice's device owned here;
+        steps <= 1 switches it off."""
         if steps <= 1:
-            _check(lib().mclg_set_blocked(self.ctx, 0, None, 0), "mclg_set_blocked")
+            _check(lib().mclg_set_blocked(self.ctx, 0, 0, None, 0), "mclg_set_blocked")
             self._tb = None
             return
         n = u64(0)
-        _check(lib().mclg_blocked_bytes(self.ctx, steps, ct.byref(n)), "mclg_blocked_bytes")
+        _check(lib().mclg_blocked_bytes(self.ctx, steps, tile, ct.byref(n)), "mclg_blocked_bytes")
         buf = self.torch.empty(int(n.value), dtype=self.torch.uint8, device=self.device)
-        _check(lib().mclg_set_blocked(self.ctx, steps, buf.data_ptr(), int(n.value)),
+        _check(lib().mclg_set_blocked(self.ctx, steps, tile, buf.data_ptr(), int(n.value)),
                "mclg_set_blocked")
         self._tb = buf
 

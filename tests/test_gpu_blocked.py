@@ -164,3 +164,89 @@ def test_blocked_full_size_256_steps_per_launch_windows():
         for x0, f in futs:
             assert np.array_equal(full[:, x0:x0 + W], f.result()), x0
     g.close()
+
+
+# ---- tiles: each block goes through its range in tiles of `tile` sites ----
+
+def pair_tiled(L, seed, K, tile, **kw):
+    g, o = pair(L, seed, K, **kw)
+    g.set_blocked(K, tile)
+    return g, o
+
+
+@pytest.mark.parametrize("L,K,tile", [
+    (1 << 20, 8, 2048),             # two full tiles per block, carries between them
+    (1 << 20, 16, 1024),            # five tiles per block, the last one short
+    (1 << 20, 2, 4096 + 16),        # a tile longer than the block's range
+    (3 * (1 << 16) + 8 * 37, 5, 256),  # a ragged lattice: the last block's range is short
+    ((1 << 17) + 8, 64, 192),       # blocks that own no sites; side areas wider than a range
+    (1 << 18, 16, 48),              # tiles of kh sites (shorter than the carry)
+    (1 << 18, 16, 40),              # tiles of 8 sites
+])
+def test_tiled_equals_oracle(L, K, tile):
+    g, o = pair_tiled(L, 91, K, tile)
+    t = 0
+    for n in (K, 2 * K + 3, 1, 3 * K):
+        g.step(n)
+        o.step(n)
+        t += n
+        same(g, o, f"tiles L={L} K={K} tile={tile} t={t}")
+    g.close()
+
+
+@pytest.mark.parametrize("C,lam,n_max,flags", [
+    (0, (1, 1), 255, 0),
+    (10, (1, 1), 24, 0),
+    (10, (1, 1), 255, FLAG_NO_STREAM),
+    (10, (3, 4), 255, FLAG_GALILEAN),
+])
+def test_tiled_flags_and_parameters(C, lam, n_max, flags):
+    L = 1 << 18
+    g, o = pair_tiled(L, 93, 8, 512, C=C, lam=lam, n_max=n_max, rho=30.0, u0=0.15, flags=flags)
+    for n in (8, 11, 16):
+        g.step(n)
+        o.step(n)
+        same(g, o, f"tiles C={C} n_max={n_max} flags={flags}")
+    g.close()
+
+
+def test_tiled_refuses_bad_tiles():
+    g = Lattice(1 << 18, 3, rho=5.0, u0=0.0)
+    for tile in (2000 + 4, 32, 1 << 21):  # not a multiple of 8, no own sites, too long
+        with pytest.raises(MclgError):
+            g.set_blocked(16, tile)
+    g.close()
+
+
+def test_tiled_full_size_hbm_resident_windows():
+    """L = 2^27 (more than the caches hold: tiles of 65536 sites by default),
+    16 steps per launch: oracle light-cone windows after 37 steps (two
+    launches and 5 single steps) at a tile boundary, a block boundary, the
+    lattice's wrap and inside a tile."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = synth.PLAIN_LARGE
+    L = 1 << 27
+    g = Lattice(L, w["seed"], rho=w["rho"], u0=w["u0"])
+    g.set_blocked(16)
+    T, W = 37, 256
+    R = L // 256
+    tile_body = 65536 - 32
+
+    def window(x0):
+        lo = x0 - T
+        o = O.OracleSim([W + 2 * T], w["seed"], C=10)
+        o.set_site_offset(0, lo, 0)
+        o.init_poisson(0, w["rho"], w["u0"])
+        o.step(T)
+        out = o.counts(0)[:, T:T + W]
+        o.close()
+        return out
+
+    x0s = [T, tile_body - W // 2, R - W // 2, 5 * R + 3 * tile_body + 1000, L - W - T]
+    with ThreadPoolExecutor(5) as ex:
+        futs = [(x0, ex.submit(window, x0)) for x0 in x0s]
+        g.step(T)
+        full = g.counts(0)
+        for x0, f in futs:
+            assert np.array_equal(full[:, x0:x0 + W], f.result()), x0
+    g.close()

@@ -34,11 +34,12 @@ TRAFFIC_FILES = {
     "plain": os.path.join(PROFILES, "traffic_stream_collide_L16M.json"),
     "probe": os.path.join(PROFILES, "traffic_stream_collide_L128M.json"),
     "batched": os.path.join(PROFILES, "traffic_stream_collide_1024_replicas.json"),
+    "probe_blocked": os.path.join(PROFILES, "traffic_stream_collide_L128M_tiles.json"),
 }
 TRAFFIC_FILE = TRAFFIC_FILES["plain"]
 # the sources the D1Q3 step kernel is compiled from
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
-               for f in ("kernels.hip", "rng.h", "device.h")]
+               for f in ("kernels.hip", "rng.h", "device.h", "mom3_sum.h", "moments.h")]
 
 # the D2Q9 step kernel: its sources and its counted VALU instructions per site
 D2Q9_SRCS = [os.path.join(ROOT, "paper_1706_01094_amd", "csrc", f)
@@ -239,9 +240,14 @@ def run_probe(args, torch, M):
         n = max(1, args.probe_steps // K) * K
         bms = timed(n)
         ach = BYTES_PER_SITE_UPDATE * L / (bms / 1e3) / 1e9
+        btr = measured_traffic("probe_blocked", K)
         blocked = {"steps_per_launch": K, "steps": n, "ms_per_step": bms,
                    "site_updates_per_s": L / (bms / 1e3), "achieved_GBps": ach,
-                   "frac": ach / HBM_PEAK_GBS}
+                   "frac": ach / HBM_PEAK_GBS,
+                   "traffic_per_launch": btr,
+                   "traffic_over_algorithmic": None if btr is None else
+                   btr / (BYTES_PER_SITE_UPDATE * L * K),
+                   "valu_issue_frac": valu_issue_frac("probe_blocked", bms * K / 1e3, K)}
     rc = lat.check()
     lat.close()
     if rc != 0:
@@ -605,7 +611,7 @@ def main():
                     help="steps per launch of the L = 2^24 workload (temporal blocking; 1: off)")
     ap.add_argument("--single-steps", type=int, default=2000,
                     help="steps of the one-step-per-launch comparison of the blocked run")
-    ap.add_argument("--probe-blocked", type=int, default=64,
+    ap.add_argument("--probe-blocked", type=int, default=128,
                     help="steps per launch of the L = 2^27 probe's blocked run, in tiles "
                          "(1: off)")
     ap.add_argument("--wave-blocked", type=int, default=250,

@@ -20,9 +20,10 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-# sites per launch of each counted workload: L = 2^24, L = 2^27, and the
-# 1024-replica manifest
-TRAFFIC_SITES = {"plain": 1 << 24, "probe": 1 << 27, "batched": 137_671_148}
+# sites per launch of each counted workload: L = 2^24, L = 2^27 (one step
+# per launch, and in tiles), and the 1024-replica manifest
+TRAFFIC_SITES = {"plain": 1 << 24, "probe": 1 << 27, "batched": 137_671_148,
+                 "probe_blocked": 1 << 27}
 
 
 @pytest.mark.parametrize("which", sorted(TRAFFIC_SITES))

@@ -35,6 +35,7 @@ TRAFFIC_FILES = {
     "probe": os.path.join(PROFILES, "traffic_stream_collide_L128M.json"),
     "batched": os.path.join(PROFILES, "traffic_stream_collide_1024_replicas.json"),
     "probe_blocked": os.path.join(PROFILES, "traffic_stream_collide_L128M_tiles.json"),
+    "batched_blocked": os.path.join(PROFILES, "traffic_stream_collide_1024_replicas_blocked.json"),
 }
 TRAFFIC_FILE = TRAFFIC_FILES["plain"]
 # the sources the D1Q3 step kernel is compiled from
@@ -360,6 +361,36 @@ def run_batched(args, torch, M):
         out[mode] = {"steps": args.batched_steps, "ms": ms, "us_per_step":
                      1e3 * ms / args.batched_steps, "site_updates_per_s": rate,
                      "hbm_frac": BYTES_PER_SITE_UPDATE * rate / 1e9 / HBM_PEAK_GBS}
+    # several steps per launch: each block advances whole replicas, K steps
+    # on copies in the caches (the state is read and written once per launch)
+    K = args.batched_blocked
+    out["blocked"] = None
+    if K > 1:
+        try:
+            lat.set_blocked(K)
+        except M.MclgError as e:  # (a schedule other than 1024 threads)
+            out["blocked"] = {"refused": str(e)}
+        else:
+            lat.step(K)
+            nb = max(1, args.batched_steps // K) * K
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch, lat.stream)
+            e0.record(lat.stream)
+            lat.step(nb)
+            e1.record(lat.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rate = sites * nb / (ms / 1e3)
+            btr = measured_traffic("batched_blocked", K)
+            out["blocked"] = {"steps_per_launch": K, "steps": nb, "ms": ms,
+                              "us_per_step": 1e3 * ms / nb, "site_updates_per_s": rate,
+                              "hbm_frac": BYTES_PER_SITE_UPDATE * rate / 1e9 / HBM_PEAK_GBS,
+                              "traffic_per_launch": btr,
+                              "traffic_over_algorithmic": None if btr is None else
+                              btr / (BYTES_PER_SITE_UPDATE * sites * K),
+                              "valu_issue_frac": valu_issue_frac("batched_blocked",
+                                                                 ms / 1e3 * K / nb, K)}
+            lat.set_blocked(1)
     traffic = measured_traffic("batched")
     out["traffic"] = traffic
     out["traffic_over_algorithmic"] = None if traffic is None else \
@@ -611,6 +642,8 @@ def main():
                     help="steps per launch of the L = 2^24 workload (temporal blocking; 1: off)")
     ap.add_argument("--single-steps", type=int, default=2000,
                     help="steps of the one-step-per-launch comparison of the blocked run")
+    ap.add_argument("--batched-blocked", type=int, default=128,
+                    help="steps per launch of the batched run's blocked variant (1: off)")
     ap.add_argument("--probe-blocked", type=int, default=128,
                     help="steps per launch of the L = 2^27 probe's blocked run, in tiles "
                          "(1: off)")

@@ -162,9 +162,10 @@ struct mclg_ctx {
     b.bar = barrier();
     b.bar_target = tb_arrivals + tb_grid;
     hipError_t e = launch_step_blocked(sch, stream,
-                                       launch_args(0, (uint32_t)tiles.size(), 0, 1, t_pending), b,
+                                       launch_args(0, (uint32_t)tiles.size(), 0, n, t_pending), b,
                                        tb_grid);
-    if (!e) tb_arrivals += b.n_logs ? 2u * tb_grid : tb_grid;
+    // (the replicas' kernel has no barrier)
+    if (!e && !b.reps) tb_arrivals += b.n_logs ? 2u * tb_grid : tb_grid;
     return e;
   }
   SlotDev *slots() { return reinterpret_cast<SlotDev *>(ws + lay.o_slots); }
@@ -540,11 +541,29 @@ static int blocked_geometry(mclg_ctx *c, uint32_t steps, uint32_t tile, TbLaunch
                             uint32_t &grid, uint64_t &bytes, uint64_t &records_at) {
   if (c->d2) return MCLG_E_UNSUPPORTED;
   if (steps < 2 || steps > kTbMaxSteps) return MCLG_E_INVAL;
-  if (c->n != 1 || c->L[0] % 8 != 0 || c->sch.threads != 1024) return MCLG_E_UNSUPPORTED;
+  if (c->sch.threads != 1024) return MCLG_E_UNSUPPORTED;
   uint32_t g = 0;
   hipError_t e = step_blocked_occupancy(c->sch, c->lds_bytes, c->n_cu, g);
   if (e) return c->hip(e);
   g = std::min(g, kOverflowWaves / (c->sch.threads / 64u));  // waves with an overflow area
+  if (c->n > 1) {
+    // replicas: each block copies whole replicas, so its copy area holds
+    // the largest; then the blocks' replica lists (records_at: where)
+    if (tile > 1) return MCLG_E_INVAL;
+    const uint64_t maxL = *std::max_element(c->L.begin(), c->L.end());
+    TbLaunch t;
+    t.steps = steps;
+    t.reps = 1;
+    t.stride = (uint32_t)align_up(maxL + 8u, 64);
+    t.bstride = 3ull * t.stride;
+    if (6ull * t.stride >= (1ull << 31)) return MCLG_E_UNSUPPORTED;
+    tb = t;
+    grid = g;
+    records_at = align_up((uint64_t)g * t.bstride * sizeof(uint16_t), 256);
+    bytes = records_at + sizeof(uint32_t) * ((uint64_t)c->n + g + 1u);
+    return MCLG_OK;
+  }
+  if (c->L[0] % 8 != 0) return MCLG_E_UNSUPPORTED;
   const uint64_t L = c->L[0];
   TbLaunch t;
   t.R = (uint32_t)(((L + g - 1) / g + 7) / 8 * 8);
@@ -597,7 +616,47 @@ int mclg_set_blocked(mclg_ctx *c, uint32_t steps, uint32_t tile, void *scratch,
   if (rc) return rc;
   if (!scratch || scratch_bytes < need) return MCLG_E_INVAL;
   tb.scratch = static_cast<uint16_t *>(scratch);
-  tb.records = reinterpret_cast<unsigned long long *>(static_cast<uint8_t *>(scratch) + records_at);
+  if (tb.reps) {
+    // each block's replicas: the longest-work-first greedy assignment, with a
+    // replica's work per step taken as its chunks of 512 sites plus 10 (a
+    // step's fixed cost, about ten chunks')
+    std::vector<uint32_t> order(c->n);
+    for (uint32_t r = 0; r < c->n; ++r) order[r] = r;
+    auto work = [&](uint32_t r) { return (c->L[r] + 511u) / 512u + 10u; };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return work(x) > work(y); });
+    std::vector<std::vector<uint32_t>> lists(grid);
+    std::vector<std::pair<uint64_t, uint32_t>> heap;  // (work, block), min-heap
+    for (uint32_t b = 0; b < grid; ++b) heap.push_back({0, b});
+    auto cmp = [](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
+      return x > y;
+    };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    for (uint32_t r : order) {
+      std::pop_heap(heap.begin(), heap.end(), cmp);
+      heap.back().first += work(r);
+      lists[heap.back().second].push_back(r);
+      std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    std::vector<uint32_t> first(grid + 1u, 0), items;
+    for (uint32_t b = 0; b < grid; ++b) {
+      first[b] = (uint32_t)items.size();
+      items.insert(items.end(), lists[b].begin(), lists[b].end());
+    }
+    first[grid] = (uint32_t)items.size();
+    uint32_t *lst = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(scratch) + records_at);
+    hipError_t e = hipMemcpyAsync(lst, items.data(), sizeof(uint32_t) * items.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (!e) e = hipMemcpyAsync(lst + items.size(), first.data(), sizeof(uint32_t) * first.size(),
+                               hipMemcpyHostToDevice, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (e) return c->hip(e);
+    tb.items = lst;
+    tb.item_first = lst + items.size();
+  } else {
+    tb.records =
+        reinterpret_cast<unsigned long long *>(static_cast<uint8_t *>(scratch) + records_at);
+  }
   c->tb = tb;
   c->tb_grid = grid;
   return MCLG_OK;
@@ -616,7 +675,7 @@ int mclg_step(mclg_ctx *c, uint64_t n_steps) {
       }
       hipError_t e = c->launch_blocked(c->tb);
       if (e) return c->hip(e);
-      c->t[0] += K;  // (the launch advances the device counter itself)
+      for (auto &t : c->t) t += K;  // (the launch advances the device counters itself)
     }
   }
   for (uint64_t i = 0; i < n_steps; ++i) {
@@ -749,7 +808,7 @@ int mclg_step_log(mclg_ctx *c, uint64_t every, uint64_t n_logs, const int32_t *t
     return MCLG_E_INVAL;
   const uint32_t dig = (flags & MCLG_MOMENTS_DIGEST) ? 1u : 0u;
   const uint32_t K = c->tb.steps;
-  if (!(K > 1 && c->tb.T == 0 && n_modes <= 2 && !(n_modes == 2 && dig))) {
+  if (!(K > 1 && c->tb.T == 0 && !c->tb.reps && n_modes <= 2 && !(n_modes == 2 && dig))) {
     // steps, then the moment kernels, per log (partial sums in the workspace)
     unsigned long long *part = reinterpret_cast<unsigned long long *>(c->ws + c->lay.o_mpart);
     for (uint64_t j = 0; j < n_logs; ++j) {

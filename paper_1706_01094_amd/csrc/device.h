@@ -174,6 +174,11 @@ struct TbLaunch {
   // advanced `steps` steps and written back before the next; see k_step_tt.
   uint32_t T = 0;
   uint64_t bstride = 0;         // elements of scratch per block
+  // Replicas (reps != 0, a context of several lattices; see k_step_tr): block
+  // b advances whole replicas, items[item_first[b] .. item_first[b + 1]),
+  // each copied whole (stride >= the largest L), with no grid barrier.
+  uint32_t reps = 0;
+  const uint32_t *items = nullptr, *item_first = nullptr;
   uint32_t *bar = nullptr;      // arrivals of every blocked launch of the context
   uint32_t bar_target = 0;      // arrivals before this launch + its grid
   // Logs (n_logs > 0): the moments (mclg_moments_t) of the state after steps

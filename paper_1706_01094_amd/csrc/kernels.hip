@@ -670,7 +670,7 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 // its bytes are disjoint from this chunk's), then this chunk is decided and
 // stored, then the next chunk's vectors are taken.  The loop alternates the
 // two register sets, so nothing is copied.
-template <bool GAL, int MODE, bool TB = false>
+template <bool GAL, int MODE, bool TB = false, int CPO = -1>
 __device__ __forceinline__ void run_segment(const StepParams &p, const TableDev &tab,
                                             uint32_t *err, const SlotView &sv,
                                             const LdsView &lv, uint2 key, uint4 *queue,
@@ -679,7 +679,9 @@ __device__ __forceinline__ void run_segment(const StepParams &p, const TableDev 
                                             uint32_t &next_chunk, uint32_t i, uint32_t se,
                                             uint32_t x0, uint32_t k, Win cw, Raw &cr) {
   constexpr bool PATCH = MODE == kDrainPatch;
-  constexpr int CP = PATCH ? kStreamingPolicy : 0;
+  // (CPO: the chunk accesses' cache policy when given, else streaming with
+  // patched drains)
+  constexpr int CP = CPO >= 0 ? CPO : PATCH ? kStreamingPolicy : 0;
   const uint32_t L = sv.L, tm = sv.tm, t = sv.t;  // of the segment's slot
   const Rsrc rs = sv.rs();
   const uint32_t ab = sv.ab;
@@ -1574,6 +1576,150 @@ __global__ void __launch_bounds__(MAXT) k_step_tt(StepLaunch a, TbLaunch tb) {
   }
 }
 
+// Several steps per launch for a context of several replicas (TbLaunch::reps):
+// block b advances the replicas of its list one after the other, each as a
+// whole.  A replica is copied at its step t into the block's copy area (a
+// periodic lattice of L sites, so no extra sites: its own periodic boundary
+// is the copy's), advanced `steps` steps there with its own collision image,
+// and written back at step t + steps; then its step counter moves.  No data
+// crosses blocks, so there is no grid-wide barrier.
+template <int MAXT, bool GAL, int MODE>
+__global__ void __launch_bounds__(MAXT) k_step_tr(StepLaunch a, TbLaunch tb) {
+  extern __shared__ uint4 lds[];
+  const StepParams &p = a.p;
+  const uint2 key = make_uint2((uint32_t)p.seed, (uint32_t)(p.seed >> 32));
+  const uint32_t lane = threadIdx.x & 63u, nwaves = blockDim.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint4 *const queue = lds + a.lds_bytes / 16u + wave * (kWaveLdsBytes / 16u);
+  uint4 *const over = a.overflow + (size_t)(blockIdx.x * nwaves + wave) * kOverflow;
+  const Rsrc ovr = __builtin_amdgcn_make_buffer_rsrc(over, 0, (int)(16u * kOverflow), kRsrcWord3);
+  uint32_t F = 0;
+  const bool youngest = nwaves >= 8u && wave + 4u >= nwaves;
+  const bool second = nwaves >= 12u && wave + 8u >= nwaves && !youngest;
+  uint32_t *const ctl =
+      reinterpret_cast<uint32_t *>(lds + a.lds_bytes / 16u + nwaves * (kWaveLdsBytes / 16u));
+  uint32_t &next_chunk = ctl[0];
+  uint16_t *const scr = tb.scratch + (uint64_t)blockIdx.x * tb.bstride;
+  const uint32_t sab = 2u * tb.stride;
+  const Rsrc srs = __builtin_amdgcn_make_buffer_rsrc(scr, 0, (int)(3u * sab), kRsrcWord3);
+  SlotView sv;
+  const uint64_t base = reinterpret_cast<uint64_t>(scr);
+  sv.lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  sv.hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  sv.ab = sab;
+  sv.xoff = 0;
+  LdsView lv;
+  uint64_t loaded = ~0ull;  // pool offset of the image in LDS
+  const uint32_t i0 = tb.item_first[blockIdx.x], i1 = tb.item_first[blockIdx.x + 1u];
+  for (uint32_t it = i0; it < i1; ++it) {
+    const uint32_t r = __builtin_amdgcn_readfirstlane(tb.items[it]);
+    const SlotDev sl = a.slots[r];
+    const ImageDesc im = a.images[r];
+    const uint32_t L = sl.L;
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(a.tslot[r] + a.t_off);
+    const Rsrc mrs =
+        __builtin_amdgcn_make_buffer_rsrc(a.state + sl.off, 0, (int)(6u * sl.stride), kRsrcWord3);
+    const uint32_t mab = 2u * sl.stride;
+    // the previous replica is written back (the copy area and the image are
+    // free) and its counter read
+    __syncthreads();
+    if (im.off != loaded) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(a.image_pool + im.off);
+      const uint32_t n16 = im.bytes / 16u;
+      for (uint32_t b0 = threadIdx.x; b0 < n16; b0 += blockDim.x) lds[b0] = src[b0];
+      lv.da2 = im.dim_a * 0x10001u;
+      lv.dc2 = im.dim_c * 0x10001u;
+      lv.w2 = (im.dim_c + 1u) * 0x10001u;
+      lv.blo2 = im.b_lo * 0x10001u;
+      lv.nb2 = im.nb * 0x10001u;
+      loaded = im.off;
+    }
+    // (1) the replica at step t0 into the copy, in logical order; a group of
+    // eight that passes L takes its sites one by one
+    const uint32_t tm = p.no_stream ? 0u : t0 % L;
+    for (uint32_t i = 8u * threadIdx.x; i < L; i += 8u * blockDim.x) {
+      uint32_t pm = i + tm;
+      pm -= pm >= L ? L : 0u;
+      const uint32_t pp = i >= tm ? i - tm : i + L - tm;
+      if (i + 8u <= L) {
+        uint32_t m[4], z[4], q[4];
+        load8_wrap(mrs, 0u, pm, L, m);
+        load8_wrap(mrs, mab, i, L, z);
+        load8_wrap(mrs, 2u * mab, pp, L, q);
+        bstore4(srs, 2u * i, 0u, m);
+        bstore4(srs, 2u * i, sab, z);
+        bstore4(srs, 2u * i, 2u * sab, q);
+      } else {
+        for (uint32_t x = i; x < L; ++x) {
+          uint32_t a1 = x + tm;
+          a1 -= a1 >= L ? L : 0u;
+          const uint32_t a3 = x >= tm ? x - tm : x + L - tm;
+          bstore2(srs, 2u * x, 0u, bload2(mrs, 2u * a1, 0u));
+          bstore2(srs, 2u * x, sab, bload2(mrs, 2u * x, mab));
+          bstore2(srs, 2u * x, 2u * sab, bload2(mrs, 2u * a3, 2u * mab));
+        }
+      }
+    }
+    __syncthreads();
+    // (2) the steps on the copy: the replica itself, shifted from step t0
+    sv.L = L;
+    sv.lg = L;
+    sv.rid = sl.rid;
+    const uint32_t nch = (L + 511u) / 512u;
+    for (uint32_t s = 0; s < tb.steps; ++s) {
+      sv.t = t0 + s;
+      sv.tm = p.no_stream ? 0u : s % L;
+      const uint32_t k = min(wave, nch);
+      if (threadIdx.x == 0) next_chunk = nwaves;
+      const Win cw = locate(k * 512u, sv);
+      Raw cr;
+      if (k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
+      __syncthreads();  // the counter is reset
+      run_segment<GAL, MODE, true, 0>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+      if (F) {
+        drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
+        F = 0;
+      }
+      __syncthreads();  // step s is written before step s + 1 reads it
+    }
+    // (3) the replica back at step t0 + steps (a group that passes L site by
+    // site)
+    const uint32_t tms = p.no_stream ? 0u : tb.steps % L;
+    const uint32_t tmk = p.no_stream ? 0u : (uint32_t)(((uint64_t)t0 + tb.steps) % L);
+    for (uint32_t i = 8u * threadIdx.x; i < L; i += 8u * blockDim.x) {
+      if (i + 8u <= L) {
+        uint32_t cm = i + tms;
+        cm -= cm >= L ? L : 0u;
+        const uint32_t cp = i >= tms ? i - tms : i + L - tms;
+        uint32_t m[4], z[4], q[4];
+        load8_wrap(srs, 0u, cm, L, m);
+        load8_wrap(srs, sab, i, L, z);
+        load8_wrap(srs, 2u * sab, cp, L, q);
+        uint32_t pm = i + tmk;
+        pm -= pm >= L ? L : 0u;
+        const uint32_t pp = i >= tmk ? i - tmk : i + L - tmk;
+        store8_wrap(mrs, 0u, pm, L, m);
+        store8_wrap(mrs, mab, i, L, z);
+        store8_wrap(mrs, 2u * mab, pp, L, q);
+      } else {
+        for (uint32_t x = i; x < L; ++x) {
+          uint32_t c1 = x + tms;
+          c1 -= c1 >= L ? L : 0u;
+          const uint32_t c3 = x >= tms ? x - tms : x + L - tms;
+          uint32_t a1 = x + tmk;
+          a1 -= a1 >= L ? L : 0u;
+          const uint32_t a3 = x >= tmk ? x - tmk : x + L - tmk;
+          bstore2(mrs, 2u * a1, 0u, bload2(srs, 2u * c1, 0u));
+          bstore2(mrs, 2u * x, mab, bload2(srs, 2u * x, sab));
+          bstore2(mrs, 2u * a3, 2u * mab, bload2(srs, 2u * c3, 2u * sab));
+        }
+      }
+    }
+    if (threadIdx.x == 0) a.tslot[r] = t0 - a.t_off + tb.steps;
+  }
+}
+
 // n_i(x, 0) ~ Poisson(f_i^eq): one Philox call per site (counter (x, 0,
 // replica, 1)), words 0, 1, 2 for i = -1, 0, +1, inverse CDF over the host's
 // quantised thresholds.  t must be 0, so physical = logical order.
@@ -1744,6 +1890,10 @@ hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint3
   if (!e) e = blocked_occupancy_one(k_step_tb<1024, true>, lds, b);
   if (!e) e = blocked_occupancy_one(k_step_tt<1024, false>, lds, b);
   if (!e) e = blocked_occupancy_one(k_step_tt<1024, true>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tr<1024, false, kDrainDeferred>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tr<1024, true, kDrainDeferred>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tr<1024, false, kDrainPatch>, lds, b);
+  if (!e) e = blocked_occupancy_one(k_step_tr<1024, true, kDrainPatch>, lds, b);
   if (e) return e;
   if (b < 1) return hipErrorInvalidConfiguration;
   max_blocks = (uint32_t)b * n_cu;
@@ -1752,7 +1902,11 @@ hipError_t step_blocked_occupancy(const Schedule &sch, uint32_t lds_bytes, uint3
 
 hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLaunch &a,
                                const TbLaunch &tb, uint32_t grid) {
-  if (sch.groups != 1 || sch.threads != 1024 || !a.single || tb.steps == 0 ||
+  if (tb.reps) {
+    if (sch.groups != 1 || sch.threads != 1024 || tb.steps == 0 || !tb.scratch ||
+        tb.bstride < 3ull * tb.stride || 6ull * tb.stride >= (1ull << 31))
+      return hipErrorInvalidValue;
+  } else if (sch.groups != 1 || sch.threads != 1024 || !a.single || tb.steps == 0 ||
       tb.steps > tb.kh || tb.stride < tb.es || tb.bstride < 3ull * tb.stride ||
       tb.es != (tb.T ? tb.T : tb.R) + 2u * tb.kh)
     return hipErrorInvalidValue;
@@ -1777,6 +1931,20 @@ hipError_t launch_step_blocked(const Schedule &sch, hipStream_t s, const StepLau
                                        : reinterpret_cast<const void *>(k_step_tt<1024, false>))
                        : (a.p.galilean ? reinterpret_cast<const void *>(k_step_tb<1024, true>)
                                        : reinterpret_cast<const void *>(k_step_tb<1024, false>));
+  if (tb.reps) {
+    // replicas: an ordinary launch (no grid-wide barrier)
+    if (!tb.items || !tb.item_first || tb.n_logs) return hipErrorInvalidValue;
+    // misses resolved per chunk (patched) or per step (deferred)
+    const bool patch = a.p.drain == kDrainPatch;
+    if (a.p.galilean) {
+      if (patch) k_step_tr<1024, true, kDrainPatch><<<grid, 1024, lds, s>>>(a, tb);
+      else k_step_tr<1024, true, kDrainDeferred><<<grid, 1024, lds, s>>>(a, tb);
+    } else {
+      if (patch) k_step_tr<1024, false, kDrainPatch><<<grid, 1024, lds, s>>>(a, tb);
+      else k_step_tr<1024, false, kDrainDeferred><<<grid, 1024, lds, s>>>(a, tb);
+    }
+    return hipGetLastError();
+  }
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(1024), args, lds, s);
 }
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import synth
-from paper_1706_01094_amd.mclg import FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError
+from paper_1706_01094_amd.mclg import DRAIN_PATCH, FLAG_GALILEAN, FLAG_NO_STREAM, Lattice, MclgError
 from tests.state_digest import digest
 
 pytestmark = pytest.mark.gpu
@@ -124,7 +124,8 @@ def test_blocked_density_wave_windows():
 def test_blocked_refused_where_it_does_not_apply():
     g = Lattice([4096, 4096], 3, rho=5.0, u0=0.0)
     with pytest.raises(MclgError):
-        g.set_blocked(4)  # more than one replica
+        g.set_blocked(4, 1024)  # replicas are copied whole, not in tiles
+    g.set_blocked(4)
     g.close()
     g = Lattice(1 << 17, 3, rho=5.0, u0=0.0)
     with pytest.raises(MclgError):
@@ -250,3 +251,113 @@ def test_tiled_full_size_hbm_resident_windows():
         for x0, f in futs:
             assert np.array_equal(full[:, x0:x0 + W], f.result()), x0
     g.close()
+
+
+# ---- several replicas: each block advances whole replicas ----
+
+REPS = dict(L=[100, 2048, 3000, 777, 5, 4096, 1, 70001, 12345],
+            rid=[10, 11, 12, 13, 14, 99, 3, 7, 8],
+            rho=[5.0, 10.0, 50.0, 80.0, 20.0, 33.0, 4.0, 45.0, 100.0],
+            u0=[0.0, 0.1, -0.2, 0.05, 0.0, 0.15, 0.0, -0.1, 0.2])
+
+
+def pair_reps(seed, K, C=10, lam=(1, 1), n_max=255, flags=0, drain=None):
+    say("replicas", dict(seed=seed, K=K, C=C, lam=lam, n_max=n_max, flags=flags, drain=drain))
+    g = Lattice(REPS["L"], seed, C=C, lam=lam, n_max=n_max, rho=REPS["rho"], u0=REPS["u0"],
+                flags=flags, replica_id=REPS["rid"])
+    if drain is not None:
+        g.set_drain(drain)
+    g.set_blocked(K)
+    o = O.OracleSim(REPS["L"], seed, C=C, lam=lam, n_max=n_max, flags=flags,
+                    replica_id=REPS["rid"])
+    for r in range(len(REPS["L"])):
+        o.init_poisson(r, REPS["rho"][r], REPS["u0"][r])
+    return g, o
+
+
+def same_all(g, o, what):
+    for r in range(len(REPS["L"])):
+        a, b = g.counts(r), o.counts(r)
+        if not np.array_equal(a, b):
+            bad = np.argwhere(a != b)
+            raise AssertionError(f"{what} replica {r}: {len(bad)} counts differ, "
+                                 f"first {bad[:5].tolist()}")
+
+
+@pytest.mark.parametrize("K,drain", [(2, None), (7, None), (32, None), (7, DRAIN_PATCH),
+                                     (32, DRAIN_PATCH)])
+def test_replicas_equal_oracle(K, drain):
+    """Replicas of 1 to 70001 sites (lengths not multiples of 8, shorter than
+    a lane's eight sites), each with its own density, velocity and collision
+    image, blocks holding several of them; misses resolved at the end of each
+    step or per chunk (patched)."""
+    g, o = pair_reps(97, K, drain=drain)
+    t = 0
+    for n in (K, 2 * K + 3, 1, 3 * K):
+        g.step(n)
+        for r in range(len(REPS["L"])):
+            o.step(n, rep=r)
+        t += n
+        same_all(g, o, f"K={K} t={t}")
+    g.close()
+
+
+@pytest.mark.parametrize("C,lam,n_max,flags,drain", [
+    (0, (1, 1), 255, 0, None),
+    (10, (1, 1), 24, 0, None),
+    (10, (1, 1), 255, FLAG_NO_STREAM, None),
+    (10, (3, 4), 255, FLAG_GALILEAN, None),
+    (10, (1, 1), 24, 0, DRAIN_PATCH),
+    (10, (3, 4), 255, FLAG_GALILEAN, DRAIN_PATCH),
+])
+def test_replicas_flags_and_parameters(C, lam, n_max, flags, drain):
+    g, o = pair_reps(99, 8, C=C, lam=lam, n_max=n_max, flags=flags, drain=drain)
+    for n in (8, 11, 16):
+        g.step(n)
+        for r in range(len(REPS["L"])):
+            o.step(n, rep=r)
+        same_all(g, o, f"C={C} n_max={n_max} flags={flags}")
+    g.close()
+
+
+def test_replicas_full_size_batched_sampled():
+    """The 1024-replica batched workload (826 MB: misses resolved per chunk)
+    with 16 steps per launch: 64
+    replicas (the 8 densest, the 4 largest, the 4 smallest and 48 drawn at
+    random) equal the oracle's runs after every launch up to t = 48, and every
+    replica's state digest equals one launch per step's."""
+    from concurrent.futures import ThreadPoolExecutor
+    from tests.test_gpu_scale import WORKERS, _oracle_replica
+    man = synth.replica_manifest()
+    seed = synth.BATCHED["seed"]
+    n = len(man["L"])
+    dense = list(np.argsort(-man["rho"], kind="stable")[:8])
+    big = list(np.argsort(-man["L"].astype(np.int64), kind="stable")[:4])
+    small = list(np.argsort(man["L"].astype(np.int64), kind="stable")[:4])
+    rng = np.random.default_rng(2)
+    pick = sorted(set(int(r) for r in dense + big + small))
+    rest = [r for r in rng.permutation(n) if r not in pick]
+    pick = sorted(pick + [int(r) for r in rest[: 64 - len(pick)]])
+    T, every = 48, 16
+    say("replicas full size", n, "checking", len(pick))
+    with ThreadPoolExecutor(WORKERS) as ex:
+        futs = {r: ex.submit(_oracle_replica, man, seed, r, T, every) for r in pick}
+        g = Lattice(man["L"], seed, rho=man["rho"], u0=man["u0"], replica_id=man["replica_id"])
+        g.set_blocked(every)
+        got = {r: [] for r in pick}
+        for _ in range(T // every):
+            g.step(every)
+            for r in pick:
+                got[r].append(g.counts(r))
+        dg = g.moments(digest=True)
+        g.close()
+        for r in pick:
+            want = futs[r].result()
+            for k in range(T // every):
+                a, b = got[r][k], want[k]
+                assert np.array_equal(a, b), (r, (k + 1) * every)
+    h = Lattice(man["L"], seed, rho=man["rho"], u0=man["u0"], replica_id=man["replica_id"])
+    h.step(T)
+    dh = h.moments(digest=True)
+    h.close()
+    assert [m["digest"] for m in dg] == [m["digest"] for m in dh]

@@ -21,9 +21,10 @@ def test_more_than_one_gpu_is_refused():
 
 
 # sites per launch of each counted workload: L = 2^24, L = 2^27 (one step
-# per launch, and in tiles), and the 1024-replica manifest
+# per launch, and in tiles), and the 1024-replica manifest (one step per
+# launch, and whole replicas per block)
 TRAFFIC_SITES = {"plain": 1 << 24, "probe": 1 << 27, "batched": 137_671_148,
-                 "probe_blocked": 1 << 27}
+                 "probe_blocked": 1 << 27, "batched_blocked": 137_671_148}
 
 
 @pytest.mark.parametrize("which", sorted(TRAFFIC_SITES))

@@ -260,15 +260,17 @@ int mclg_moments_noalloc(mclg_ctx *ctx, const int32_t *twiddle, uint32_t n_modes
  *   dev_out: device, caller-owned, n_logs x n_replicas mclg_moments_t (log j
  *     of replica r at j n_replicas + r); t is the device's step counter (the
  *     steps taken modulo 2^32).
- *   With several steps per launch on whole ranges (mclg_set_blocked, tile
- *     1), at most two modes and not two modes with MCLG_MOMENTS_DIGEST, the
- *     run goes in launches of that many steps (the last one shorter) and
- *     each launch sums the logs that fall in it from the blocks' copies, the
- *     last one as it writes the sites back: the state is not read again, and
- *     one launch covers several logs when `every` is below its steps.
- *     Otherwise the moment kernels run after each interval's steps.  Either way the partial sums live in the
- *     blocked scratch or the workspace, so calls on one context are
- *     stream-ordered and need no clearing.
+ *   With several steps per launch on whole ranges (mclg_set_blocked for
+ *     one lattice, not in tiles), at most two modes and not two modes with
+ *     MCLG_MOMENTS_DIGEST, the run goes in launches of that many steps (the
+ *     last one shorter) and each launch sums the logs that fall in it from
+ *     the blocks' copies, the last one as it writes the sites back: the
+ *     state is not read again, and one launch covers several logs when
+ *     `every` is below its steps.  With the digest or MCLG_FLAG_GALILEAN a
+ *     launch ends at each log.  Otherwise the moment kernels run after each
+ *     interval's steps.  Either way the partial sums live in the blocked
+ *     scratch or the workspace, so calls on one context are stream-ordered
+ *     and need no clearing.
  * MCLG_E_INVAL for every = 0, every x n_logs >= 2^62 and as mclg_moments;
  * D2Q9 contexts: MCLG_E_UNSUPPORTED. */
 int mclg_step_log(mclg_ctx *ctx, uint64_t every, uint64_t n_logs, const int32_t *twiddle,
@@ -324,7 +326,7 @@ int mclg_set_grid_limit(mclg_ctx *ctx, uint32_t max_blocks);
 enum { MCLG_DRAIN_AUTO = 0, MCLG_DRAIN_DEFERRED = 1, MCLG_DRAIN_CHUNK = 2, MCLG_DRAIN_PATCH = 3 };
 int mclg_set_drain(mclg_ctx *ctx, uint32_t policy);
 
-/* Several steps per launch (temporal blocking) for a context of one lattice
+/* Several steps per launch (temporal blocking) for a context of lattices
  * (Sec. "The D1Q3 model": the update of a site at t + 1 reads only its
  * neighbours at t, so a block that holds its sites and `steps` more on each
  * side can advance them `steps` steps alone).  mclg_step then launches
@@ -335,20 +337,25 @@ int mclg_set_drain(mclg_ctx *ctx, uint32_t policy);
  * steps.  The bits are the same as with one step per launch.
  *   tile: 1 = each block copies its whole range (about L / 256 sites); >= 2
  *     = each block goes through its range in tiles, copies of `tile` sites
- *     (a multiple of 8, at least 3 x steps rounded up to 8, at most 2^20)
+ *     (a multiple of 8, more than 2 x steps rounded up to 8, at most 2^20)
  *     whose own tile - 2 x (steps rounded up to 8) sites it writes back
- *     before the next tile, so that the copies stay in the L2 when the
+ *     before the next tile, so that the copies stay in the caches when the
  *     ranges would not; 0 = whole ranges while all blocks' copies fit
  *     128 MiB, else tiles of 65536 sites.
+ *   Several replicas: each block advances whole replicas (the host deals
+ *     them out, longest first), each copied whole with its own image, so
+ *     every replica length works; tile must be 0 or 1, and the scratch
+ *     holds one copy of the largest replica per block.  mclg_set_blocked
+ *     then uploads the blocks' replica lists and synchronises the stream.
  *   mclg_blocked_bytes: the scratch bytes `steps` steps per launch need (the
  *     blocks' copies, and room for the partial sums of mclg_step_log).
  *   mclg_set_blocked: steps in [2, 256] with scratch (device, caller-owned,
  *     at least mclg_blocked_bytes, kept until blocking is switched off or the
  *     context destroyed); steps <= 1 switches it off (scratch unused).
- * MCLG_E_UNSUPPORTED for D2Q9 or more than one replica, L not a multiple of
- * 8, a schedule other than 1024 threads, or a lattice too short for the
- * extra sites of 256 or so blocks; MCLG_E_INVAL for steps > 256, a bad
- * `tile` or too small a scratch.  mclg_set_schedule switches blocking off.
+ * MCLG_E_UNSUPPORTED for D2Q9, a schedule other than 1024 threads, and for
+ * one lattice L not a multiple of 8 or too short for the extra sites of 256
+ * or so blocks; MCLG_E_INVAL for steps > 256, a bad `tile` or too small a
+ * scratch.  mclg_set_schedule switches blocking off.
  * Graph launches (mclg_step_graph) take one step per launch. */
 int mclg_blocked_bytes(mclg_ctx *ctx, uint32_t steps, uint32_t tile, uint64_t *scratch_bytes);
 int mclg_set_blocked(mclg_ctx *ctx, uint32_t steps, uint32_t tile, void *scratch,

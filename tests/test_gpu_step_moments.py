@@ -6,7 +6,7 @@ oracle's counts at the same step (and the state digest), and the state stays
 equal to the oracle's; logs between a launch's steps, at its end, several per
 launch, one per several launches, launches cut at the logs (digest, Galilean
 acceptance) and the fallback to the separate moment kernels (two modes with
-the digest, no blocking, several replicas) are all covered."""
+the digest, no blocking, tiles, whole replicas) are all covered."""
 import ctypes as ct
 import sys
 
@@ -96,8 +96,8 @@ def test_step_log_galilean_cuts_launches_at_logs():
 
 
 def test_step_log_without_blocking_and_several_replicas():
-    """The fallback path: several replicas (no blocking possible), three
-    modes, against numpy's sums of the counts read back after each call."""
+    """The fallback path: several replicas without blocking, three modes,
+    against numpy's sums of the counts read back after each call."""
     import torch
     Ls = [4099, 33000, 7]
     g = Lattice(Ls, 5, rho=[10.0, 40.0, 3.0], u0=[0.0, 0.1, -0.2])
@@ -159,3 +159,33 @@ def test_step_log_refuses_bad_arguments():
     assert f(g.ctx, 4, 2, 0, 0, 0, 0) == M.E_INVAL
     assert f(g.ctx, 1 << 40, 1 << 40, 0, 0, 0, out.data_ptr()) == M.E_INVAL
     g.close()
+
+
+@pytest.mark.parametrize("Ls,tile", [([1 << 20], 1024), ([4099, 33000, 7, 70001], 0)])
+def test_step_log_with_tiles_and_replicas(Ls, tile):
+    """Blocking in tiles (one lattice) or on whole replicas (several) takes
+    the moment kernels after each interval: records equal numpy's sums of
+    the oracle's counts at every log."""
+    import torch
+    K = 8
+    say("step_log blocked", dict(L=Ls, tile=tile))
+    rho, u0 = 25.0, 0.05
+    g = Lattice(Ls, 87, C=10, rho=rho, u0=u0)
+    g.set_blocked(K, tile)
+    o = O.OracleSim(Ls, 87, C=10)
+    for r in range(len(Ls)):
+        o.init_poisson(r, rho, u0)
+    tw = [synth.twiddles(L, 1) for L in Ls]
+    twd = torch.as_tensor(np.concatenate([w.reshape(-1) for w in tw])).to(g.device)
+    g.stream.wait_stream(torch.cuda.current_stream(g.device))
+    n_logs, every = 3, 12
+    out = new_out(g, n_logs)
+    g.step_log(every, n_logs, out, twd, 1)
+    recs = records(g, out, n_logs * len(Ls))
+    for j in range(n_logs):
+        o.step(every)
+        for r in range(len(Ls)):
+            expect(recs[j * len(Ls) + r], o.counts(r), tw[r], 1, False, every * (j + 1),
+                   (Ls, tile, j, r))
+    g.close()
+    o.close()

@@ -1373,16 +1373,17 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
 // blocks' whole copies would stream from memory at every step.  Block b owns
 // the sites [X0, end) = [b R, min(L, b R + R)) and goes through them in
 // tiles of T sites from left to right: tile [a, a + n) is copied with kh
-// extra sites on each side into the copy area (es = n + 2 kh sites, which
-// stay in the L2 while they are stepped), advanced `steps` steps as in
-// k_step_tb, and written back at step t + steps before the next tile.
-// Every site a tile reads is at step t: its own sites and the extra sites
-// on its right that lie in the block's region are not written yet; the
-// extra sites on its left were written back with the previous tile, so
-// that tile kept them (at step t) in a carry area; extra sites in other
-// blocks' regions come from the side areas, where each block put its
-// region's first and last kh sites before the grid-wide barrier (with
-// device-coherent stores and loads: the barrier has no fence).
+// extra sites on each side into the copy area (es = n + 2 kh sites; all
+// blocks' copies together stay in the caches while they are stepped),
+// advanced `steps` steps as in k_step_tb, and written back at step
+// t + steps before the next tile.  Every site a tile reads must be at step
+// t, and a write-back overwrites step-t values kh sites to either side of
+// the written ones (shifted layout), so the tile's first 2 kh sites come
+// from the carry area the previous tile filled, the sites within kh of the
+// region's ends from side areas where every block put its region's first
+// and last kh sites before the grid-wide barrier (with device-coherent
+// stores and loads: the barrier has no fence), and only the rest from the
+// state; see the copy-in below.
 // Per-block scratch (elements): the copy (3 x stride), two carry areas (3 x
 // 2 kh each) and the two side areas (3 x kh each).
 template <int MAXT, bool GAL>

@@ -673,8 +673,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the lattice and replica work of this build "
-              "runs on a single MI355X (sharding across GPUs is described in DESIGN.md).",
+        print("bench.py measures one GPU only: the lattice and replica work runs on a "
+              "single MI355X; sharding a lattice or a batch across GPUs is not implemented.",
               file=sys.stderr)
         raise SystemExit(2)
     import torch

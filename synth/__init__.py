@@ -2,7 +2,8 @@
 
 Holds no arithmetic of the method: only workload shapes, parameter draws and
 initial-condition sampling with numpy's PCG64 generator.  The paper uses no
-dataset; these are the workload recipes ("Inputs").
+dataset; these are the workload recipes, with the sizes, densities and
+velocities of its set-ups.
 """
 from __future__ import annotations
 

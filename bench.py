@@ -8,7 +8,7 @@ other workloads (an HBM-resident lattice, the 1024-replica batch, the
 density wave, the served trace, D2Q9) follow under "extra".
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu]
-    python bench.py --only plain|probe|batched|wave|served|d2q9|moments
+    python bench.py --only plain|probe|batched|wave|served|d2q9|moments|bound
     python bench.py --copy-probe BYTES     (counter calibration: device copies)
 """
 from __future__ import annotations
@@ -234,8 +234,8 @@ def run_probe(args, torch, M):
     blocked = None
     K = args.probe_blocked
     if K > 1:
-        # several steps per launch in tiles whose copies stay in the L2: the
-        # state is read and written once per launch
+        # several steps per launch in tiles (their copies go between the L2s
+        # and the Infinity Cache): the state is read and written once per launch
         lat.set_blocked(K)
         lat.step(K)
         n = max(1, args.probe_steps // K) * K
@@ -586,6 +586,36 @@ def run_d2q9(args, torch, M):
     return out
 
 
+def run_bound(args, torch, M):
+    """What bounds the blocked step: the headline lattice (L = 2^24, `--blocked`
+    steps per launch) at the headline density, at lower densities (fewer
+    misses of the LDS image) and with no collisions at all (C = 0: the
+    kernel only streams the blocks' copies), each timed over `--bound-steps`
+    steps after one warm-up launch."""
+    import synth
+    w = synth.PLAIN_LARGE
+    L, K = w["L"], max(2, args.blocked)
+    out = {"L": L, "steps_per_launch": K, "cases": []}
+    for C, rho, u0 in ((10, w["rho"], w["u0"]), (10, 20.0, 0.0), (10, 5.0, 0.0), (0, w["rho"], w["u0"])):
+        lat = M.Lattice(L, w["seed"], C=C, lam=(1, 1), n_max=255, rho=rho, u0=u0)
+        lat.set_blocked(K)
+        lat.step(K)
+        n = max(1, args.bound_steps // K) * K
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, lat.stream)
+        e0.record(lat.stream)
+        lat.step(n)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        out["cases"].append({"C": C, "rho": rho, "u0": u0, "steps": n, "us_per_step": ms * 1e3,
+                             "site_updates_per_s": L / (ms / 1e3),
+                             "frac": BYTES_PER_SITE_UPDATE * L / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                             "check": lat.check()})
+        lat.close()
+    return out
+
+
 def run_moments(args, torch, M):
     """The moment kernels alone (for kernel traces): exact moments of the
     L = 2^24 lattice (no modes), of the L = 2^22 density wave (one mode), and
@@ -627,7 +657,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the plain headline (skip the other workloads)")
     ap.add_argument("--only", default="",
-                    choices=["", "plain", "probe", "batched", "wave", "served", "d2q9", "moments"],
+                    choices=["", "plain", "probe", "batched", "wave", "served", "d2q9", "moments",
+                             "bound"],
                     help="run one workload and print its result")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--batched-warmup", type=int, default=20)
@@ -652,6 +683,8 @@ def main():
                          "that fall in it; 1: off)")
     ap.add_argument("--serve-window", type=float, default=10.0)
     ap.add_argument("--serve-limit", type=float, default=120.0)
+    ap.add_argument("--bound-steps", type=int, default=1024,
+                    help="steps per case of --only bound")
     ap.add_argument("--d2q9-steps", type=int, default=50)
     ap.add_argument("--d2q9-warmup", type=int, default=5)
     ap.add_argument("--d2q9-only", action="store_true", help="same as --only d2q9")
@@ -683,7 +716,7 @@ def main():
         raise SystemExit("no GPU visible")
 
     legs = {"probe": run_probe, "batched": run_batched, "wave": run_wave,
-            "d2q9": run_d2q9, "moments": run_moments}
+            "d2q9": run_d2q9, "moments": run_moments, "bound": run_bound}
     if args.only in legs:
         print(json.dumps({args.only: legs[args.only](args, torch, M)}), flush=True)
         return

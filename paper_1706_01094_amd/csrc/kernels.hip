@@ -664,7 +664,8 @@ __device__ __forceinline__ uint32_t grab_chunk(uint32_t *ctr, uint32_t lane) {
 }
 
 // The chunks [k0, se) of one segment of a slot (chunk j at x0 + (j - i)
-// 512): the wave's first chunk k (its loads already issued into cr when
+// 512, or with `rev`, for a segment that starts at i = 0, at x0 + (se - 1 -
+// j) 512): the wave's first chunk k (its loads already issued into cr when
 // fast), then chunks claimed one at a time from the block's counter.  One
 // chunk: the next chunk's loads go out first (into the other register set;
 // its bytes are disjoint from this chunk's), then this chunk is decided and
@@ -677,7 +678,8 @@ __device__ __forceinline__ void run_segment(const StepParams &p, const TableDev 
                                             uint4 *over, Rsrc ovr, uint32_t &F, uint32_t lane,
                                             uint32_t nwaves, bool youngest, bool second,
                                             uint32_t &next_chunk, uint32_t i, uint32_t se,
-                                            uint32_t x0, uint32_t k, Win cw, Raw &cr) {
+                                            uint32_t x0, uint32_t k, Win cw, Raw &cr,
+                                            bool rev = false) {
   constexpr bool PATCH = MODE == kDrainPatch;
   // (CPO: the chunk accesses' cache policy when given, else streaming with
   // patched drains)
@@ -696,7 +698,7 @@ __device__ __forceinline__ void run_segment(const StepParams &p, const TableDev 
     const bool has_next = nk < se;
     Win nw = cw;
     if (has_next) {
-      nw = locate(x0 + (nk - i) * 512u, sv);
+      nw = locate(x0 + (rev ? se - 1u - nk : nk - i) * 512u, sv);
       if (nw.fast) issue_raw<CP>(nw, sv, lane, nxt);
     }
 
@@ -1326,14 +1328,19 @@ __global__ void __launch_bounds__(MAXT) k_step_tb(StepLaunch a, TbLaunch tb) {
     sv.t = t0 + s;
     sv.tm = p.no_stream ? 0u : s % es;
     const uint32_t k = min(wave, nch);
+    // odd steps take the chunks from the copy's end: a step starts on the
+    // chunks the step before finished with, which the L2 still holds (the
+    // order of a step's chunks does not change its results)
+    const bool rev = (s & 1u) != 0u;
     if (threadIdx.x == 0) next_chunk = nwaves;
-    const Win cw = locate(k * 512u, sv);
+    const Win cw = locate((rev && k < nch ? nch - 1u - k : k) * 512u, sv);
     Raw cr;
     if (active && k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
     __syncthreads();  // the counter is reset
     if (active) {
       run_segment<GAL, MODE, true>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
-                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr,
+                                   rev);
       if (F) {
         drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
@@ -1554,13 +1561,15 @@ __global__ void __launch_bounds__(MAXT) k_step_tt(StepLaunch a, TbLaunch tb) {
       sv.t = t0 + s;
       sv.tm = p.no_stream ? 0u : s % es;
       const uint32_t k = min(wave, nch);
+      const bool rev = (s & 1u) != 0u;  // alternating chunk order, as in k_step_tb
       if (threadIdx.x == 0) next_chunk = nwaves;
-      const Win cw = locate(k * 512u, sv);
+      const Win cw = locate((rev && k < nch ? nch - 1u - k : k) * 512u, sv);
       Raw cr;
       if (k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
       __syncthreads();  // the counter is reset
       run_segment<GAL, MODE, true>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
-                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr,
+                                   rev);
       if (F) {
         drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;
@@ -1671,13 +1680,15 @@ __global__ void __launch_bounds__(MAXT) k_step_tr(StepLaunch a, TbLaunch tb) {
       sv.t = t0 + s;
       sv.tm = p.no_stream ? 0u : s % L;
       const uint32_t k = min(wave, nch);
+      const bool rev = (s & 1u) != 0u;  // alternating chunk order, as in k_step_tb
       if (threadIdx.x == 0) next_chunk = nwaves;
-      const Win cw = locate(k * 512u, sv);
+      const Win cw = locate((rev && k < nch ? nch - 1u - k : k) * 512u, sv);
       Raw cr;
       if (k < nch && cw.fast) issue_raw<0>(cw, sv, lane, cr);
       __syncthreads();  // the counter is reset
       run_segment<GAL, MODE, true, 0>(p, a.tab, a.err, sv, lv, key, queue, over, ovr, F, lane,
-                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr);
+                                   nwaves, youngest, second, next_chunk, 0u, nch, 0u, k, cw, cr,
+                                   rev);
       if (F) {
         drain_queue<GAL, true>(queue, over, F, lane, sv, p, a.tab, a.err);
         F = 0;

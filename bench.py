@@ -5,7 +5,9 @@ workload (D1Q3, L = 2^24, rho = 50, u0 = 0.1, C = 10, lambda = 1, Poisson
 initial state, seed 2).  Prints one JSON line with site updates per second,
 the HBM roofline of the fused kernel, and the oracle timed on the host; the
 other workloads (an HBM-resident lattice, the 1024-replica batch, the
-density wave, the served trace, D2Q9) follow under "extra".
+density wave, the served trace, D2Q9, and the headline lattice at lower
+densities and without collisions, which shows what bounds its step) follow
+under "extra".
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extra] [--no-cpu]
     python bench.py --only plain|probe|batched|wave|served|d2q9|moments|bound
@@ -760,6 +762,8 @@ def main():
     if not args.no_extra:
         extra = {}
         extra["roofline_probe"] = run_probe(args, torch, M)
+        torch.cuda.empty_cache()
+        extra["bound"] = run_bound(args, torch, M)
         torch.cuda.empty_cache()
         extra["batched"] = run_batched(args, torch, M)
         torch.cuda.empty_cache()
